@@ -1,0 +1,153 @@
+/*
+ * blob_rd: linear solves of the minimally-resolved reactive blob model
+ * (Bhalla, Griffith, Patankar, Donev, arXiv:1306.3159) on one AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Problem (all on a 3-D periodic, cell-centred grid, cell k centred at
+ * (k + 1/2) h, arrays laid out [z][y][x] with x fastest):
+ *   L          the standard 7-point Laplacian (Sec. III.A);
+ *   J          local averaging, (J c)_i = sum_k phi_w(q_i - r_k) c_k, with the
+ *              tensor-product Peskin kernel phi_w, w = 4 or 3 (Sec. III.A,
+ *              eq. tensor_product);
+ *   S          spreading, S = h^-3 J^T (Sec. III.A);
+ *   kappa      per-blob reaction rates (eq. c_t_blob).
+ *
+ * Conventions for every entry point:
+ *   - Grid vectors (f, c) are caller-owned DEVICE pointers to nx*ny*nz
+ *     doubles, contiguous, [z][y][x].
+ *   - Blob vectors (q, kappa, lambda) are caller-owned DEVICE pointers:
+ *     q is [N][3] doubles (x, y, z, physical units, any real value: wrapped
+ *     periodically), kappa and lambda are [N] doubles.
+ *   - The library allocates no device memory: all scratch lives in the
+ *     caller's workspace (blob_rd_workspace_bytes). The handle owns only a
+ *     small host structure.
+ *   - Work is enqueued on the caller's HIP stream (NULL = legacy default
+ *     stream). Solves return once convergence is known: they synchronise the
+ *     stream to read convergence scalars; outputs are complete on return.
+ *   - Return codes: 0 success; BLOB_RD_ENOTCONV (1) iteration limit reached,
+ *     best iterate written and stats filled; negative values are hard
+ *     errors (nothing meaningful written). No exception crosses the ABI;
+ *     blob_rd_last_error() describes the most recent failure on the calling
+ *     thread.
+ */
+#ifndef BLOB_RD_H
+#define BLOB_RD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BLOB_RD_OK 0
+#define BLOB_RD_ENOTCONV 1
+#define BLOB_RD_EINVAL (-1)
+#define BLOB_RD_ENOMEM (-2)   /* workspace too small */
+#define BLOB_RD_EDEVICE (-3)  /* HIP runtime error */
+#define BLOB_RD_ESINGULAR (-4)
+#define BLOB_RD_ENUMERIC (-5) /* NaN/Inf detected or Krylov breakdown */
+
+#define BLOB_RD_FP64 0   /* FP64 V-cycles */
+#define BLOB_RD_MIXED 1  /* FP32 V-cycles under FP64 Krylov, residuals and refinement */
+
+#define BLOB_RD_PRECOND_NONE 0
+#define BLOB_RD_PRECOND_DIAGONAL 1 /* scalar gamma^-1 of eq. Schur_diagonal */
+#define BLOB_RD_PRECOND_LEARNED 2  /* sparse pairwise network preconditioner */
+
+typedef struct blob_rd* blob_rd_t;
+
+typedef struct {
+    int32_t nx, ny, nz;      /* grid cells per axis; each >= 8; coarsening must reach <= 512 cells */
+    double h;                /* grid spacing (> 0) */
+    double D;                /* diffusion coefficient chi (> 0) */
+    int32_t kernel_w;        /* 4 (Peskin four-point) or 3 (three-point) */
+    int64_t n_blobs;         /* N >= 0 */
+    const double* q;         /* device [N][3] positions */
+    const double* kappa;     /* device [N] rates, or NULL (all zero) */
+    int32_t precision;       /* BLOB_RD_FP64 | BLOB_RD_MIXED */
+    int32_t schur_precond;   /* BLOB_RD_PRECOND_* (absorbing solves) */
+    double rtol;             /* target relative residual (unweighted 2-norm), e.g. 1e-8 */
+    int32_t max_iter;        /* outer iteration cap (CG or Schur GMRES), 0 = default */
+    int32_t gmres_restart;   /* 0 = default 30 */
+    int32_t inner_max_iter;  /* cap per inner Poisson solve, 0 = default */
+    void* workspace;         /* device memory owned by the caller */
+    size_t workspace_bytes;
+    void* stream;            /* hipStream_t, NULL = default stream */
+} blob_rd_params;
+
+typedef struct {
+    int32_t outer_iters;       /* CG iterations (reactive/step) or Schur GMRES iterations */
+    int32_t inner_iters_total; /* inner CG iterations summed over Schur matvecs */
+    int32_t vcycles;           /* multigrid V-cycles applied (the paper's cost proxy) */
+    int32_t fallback;          /* 1 if the learned preconditioner was replaced by the plain one */
+    int32_t refinements;       /* outer refinement passes (true FP64 residual checks that restarted) */
+    double rel_resid;          /* true FP64 relative residual of the returned solution */
+    double seconds;            /* wall time of the call */
+    double alg_bytes;          /* algorithmic HBM bytes of the grid kernels launched */
+} blob_rd_stats;
+
+/* Bytes of device workspace needed for these parameters (0 on invalid parameters). */
+size_t blob_rd_workspace_bytes(const blob_rd_params* p);
+
+/* Validate parameters, place blobs on the grid (wrap, kernel weights, tile
+ * binning: one pass of kernels on the stream), build the multigrid hierarchy
+ * and the dense coarsest-grid (pseudo-)inverse. q and kappa are copied into
+ * the workspace, so the caller may free them afterwards. The workspace must
+ * stay valid until blob_rd_destroy. Errors: EINVAL (dims < 8, a level that
+ * cannot coarsen to <= 512 cells, kernel_w not 3/4, h or D not positive,
+ * N < 0), ENOMEM (workspace too small), EDEVICE. */
+int blob_rd_create(const blob_rd_params* p, blob_rd_t* out);
+
+/* Release the host handle (the caller frees the workspace). NULL is accepted. */
+int blob_rd_destroy(blob_rd_t h);
+
+/* Reactive system (eqs. unsteady_system, steady_state):
+ *   (alpha I - D L + S kappa J) c = f,   alpha >= 0.
+ * c: on entry the initial guess, on exit the solution. Multigrid-
+ * preconditioned CG (Sec. III.E, eq. Pinv_Poisson); for alpha = 0 the
+ * constant mode is corrected exactly. ESINGULAR if alpha = 0 and
+ * sum(kappa) = 0. */
+int blob_rd_solve_reactive(blob_rd_t h, double alpha, const double* f, double* c,
+                           blob_rd_stats* stats);
+
+/* Absorbing (diffusion-limited) saddle point (eq. saddle_point with
+ * zeta = 1, xi = 1/dV_f):
+ *   (alpha I - D L) c + S lambda = f,   J c = 0.
+ * Schur-complement GMRES(restart) on J (alpha I - D L)^+ S (eqs. c_exact,
+ * r_schur) with inner multigrid-preconditioned CG solves; for alpha = 0
+ * the periodic null space is handled as in Appendix A (sum(lambda) =
+ * h^3 sum(f), mean-zero fluctuation, mean concentration recovered from the
+ * constraint). c (grid) and lambda (N) are outputs. EINVAL if N = 0. */
+int blob_rd_solve_absorbing(blob_rd_t h, double alpha, const double* f, double* c,
+                            double* lambda, blob_rd_stats* stats);
+
+/* One backward-Euler step (eq. c_np1) of dc/dt = D L c - S kappa J c + f:
+ *   (I/dt - D L + S kappa J) c^{n+1} = c^n/dt + f.
+ * c: c^n on entry, c^{n+1} on exit (warm-started from c^n). */
+int blob_rd_step(blob_rd_t h, double dt, const double* f, double* c, blob_rd_stats* stats);
+
+/* Message for the last failure on the calling thread (never NULL). */
+const char* blob_rd_last_error(blob_rd_t h);
+
+/* ---- Operator-level entry points (same handle, same stream rules) ---- */
+
+/* lambda_out[i] = (J c)_i (Sec. III.A local averaging). */
+int blob_rd_interp(blob_rd_t h, const double* c, double* out);
+
+/* out = S lambda (Sec. III.A spreading, S = h^-3 J^T); overwrites out. */
+int blob_rd_spread(blob_rd_t h, const double* lambda, double* out);
+
+/* y = (alpha I - D L + S kappa J) x (with_blobs = 1) or (alpha I - D L) x (0). */
+int blob_rd_apply(blob_rd_t h, double alpha, int with_blobs, const double* x, double* y);
+
+/* z = one multigrid V(2,2) cycle for alpha I - D L applied to r from a zero
+ * initial guess, in the handle's precision (Sec. III.E, eq. Helmholtz). No
+ * mean projection is applied. */
+int blob_rd_vcycle(blob_rd_t h, double alpha, const double* r, double* z);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLOB_RD_H */

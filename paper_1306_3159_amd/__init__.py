@@ -1,0 +1,13 @@
+"""blob_rd: MI355X (gfx950) linear solves of the reactive blob model of arXiv:1306.3159.
+
+The compute path is the HIP library ``libblob_rd.so`` (C ABI declared in
+``include/blob_rd.h``). This package only marshals arguments: PyTorch
+provides device memory and streams, every step of a solve runs in the
+library's kernels. There is no CPU fallback: if the library is missing the
+import of :mod:`paper_1306_3159_amd.native` fails loudly.
+"""
+from .native import (BlobRD, BlobRDError, NotConverged, Stats, load_library, FP64, MIXED,
+                     PRECOND_NONE, PRECOND_DIAGONAL, PRECOND_LEARNED)
+
+__all__ = ["BlobRD", "BlobRDError", "NotConverged", "Stats", "load_library", "FP64", "MIXED",
+           "PRECOND_NONE", "PRECOND_DIAGONAL", "PRECOND_LEARNED"]

@@ -1,0 +1,106 @@
+// Internal declarations of the blob_rd HIP library (gfx950).
+//
+// Data layout in device memory:
+//  * FP64 grid vectors (Krylov iterates, residuals, right-hand sides) are in
+//    natural order [z][y][x], x fastest, as the public ABI exposes them.
+//  * Multigrid levels are stored red/black split: level l with dims
+//    (nx, ny, nz), nx even, keeps two arrays per field, one per colour
+//    (colour = (x + y + z) mod 2, red = 0), each [z][y][nx/2]. Cell (x, y, z)
+//    of colour c sits at index x/2 of row (y, z) of array c. A Gauss-Seidel
+//    half-sweep then reads the other colour's array and writes its own with
+//    unit stride. The coarsest level (<= 512 cells, possibly odd) is natural.
+//  * Blob data are structure-of-arrays in original blob order plus a
+//    permutation that sorts blobs by the grid tile of their base cell.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace brd {
+
+constexpr int kBlock = 256;
+constexpr int kFinBlock = 1024;
+constexpr int kMaxLevels = 16;
+constexpr int kMaxCoarse = 512;
+constexpr int kStageBlobs = 128;   // blobs staged in LDS per pass of the spread gather
+
+// Device-resident scalars of one CG solve. Every kernel of an iteration reads
+// `done` first and returns if it is set, so the host can enqueue iterations
+// without waiting for convergence.
+struct Scalars {
+    double rz;        // z . r of the current iterate (with the constant shift)
+    double pq;        // p . B p
+    double alpha;     // CG step
+    double beta;      // CG direction update (Polak-Ribiere form)
+    double rr;        // r . r
+    double rsum;      // sum r
+    double qsum;      // sum q
+    double tol2;      // stop when rr <= tol2
+    double shift;     // constant added to the V-cycle output z (null-space handling)
+    double mean_r;    // mean removed from r before the V-cycle (projected problems)
+    double inv_ncell; // 1 / (nx ny nz)
+    double eBe_inv;   // 1 / (e^T B e) for the reactive alpha = 0 constant mode (0 otherwise)
+    double rr0;       // r . r of the initial residual
+    double gg;        // right-hand side g . g
+    int32_t done;     // 1: converged (or failed); kernels become no-ops
+    int32_t iters;    // completed CG iterations
+    int32_t project;  // 1: alpha = 0 problem, work on mean-zero vectors
+    int32_t status;   // 0 ok, 1 breakdown/non-finite
+};
+
+// Device-resident scalars of the Schur GMRES (single work-group kernels).
+struct GmresScalars {
+    double beta;      // initial residual norm of the current cycle
+    double res;       // current residual estimate |g_{k+1}|
+    double hk1;       // last subdiagonal entry
+    int32_t k;        // columns in the current cycle
+    int32_t status;
+};
+
+struct LevelDims {
+    int nx, ny, nz;   // cells
+    int hx;           // nx / 2 (split levels)
+    double h;         // spacing at this level
+};
+
+// ---- helpers -------------------------------------------------------------
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Blocks are dispatched to the 8 XCDs round-robin; this remaps the hardware
+// block id so each XCD works on one contiguous eighth of the index space,
+// keeping neighbouring rows and planes in the same XCD's L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+    unsigned full = nb >> 3, rem = nb & 7u, xcd = b & 7u, local = b >> 3;
+    return xcd * full + (xcd < rem ? xcd : rem) + local;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Deterministic block reduction of K values; thread k < K writes block
+// partial k to part[k * nparts + slot].
+template <int K>
+__device__ __forceinline__ void block_partials(double (&v)[K], double* part, unsigned nparts, unsigned slot) {
+    __shared__ double sh[K][16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh[k][wid] = v[k];
+    __syncthreads();
+    if (threadIdx.x < K) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += sh[threadIdx.x][w];
+        part[(size_t)threadIdx.x * nparts + slot] = s;
+    }
+}
+
+inline unsigned nblocks(size_t n, int bs = kBlock) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace brd

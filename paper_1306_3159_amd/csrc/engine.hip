@@ -1,0 +1,985 @@
+// Host engine and C-ABI of blob_rd.
+//
+// Solvers (arXiv:1306.3159):
+//  * reactive system (alpha I - D L + S kappa J) c = f (eqs. unsteady_system,
+//    steady_state) by CG preconditioned with one multigrid V-cycle for
+//    alpha I - D L (Sec. III.E, eq. Pinv_Poisson). CG scalars stay on the
+//    device; the direction update uses the Polak-Ribiere form so an FP32
+//    V-cycle (slightly nonlinear in rounding) is tolerated. For alpha = 0 the
+//    preconditioner is P MG(P r) + e (e^T r)/(e^T B e), P = I - e e^T/n;
+//  * absorbing saddle point (eq. saddle_point, zeta = 1, xi = 1/dV_f) by
+//    Schur-complement GMRES(m) with modified Gram-Schmidt on
+//    G = J (alpha I - D L)^+ S (eqs. c_exact, r_schur); for alpha = 0 the
+//    periodic null space is handled as in Appendix A: the mean sink strength
+//    is fixed by the total source, GMRES works on mean-zero N-vectors and
+//    the mean concentration follows from J c = 0;
+//  * backward-Euler steps (eq. c_np1).
+// Every solve ends with an FP64 residual of the returned answer and, when
+// that misses the target, iterative refinement on the residual equations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/blob_rd.h"
+#include "launch.hpp"
+
+using namespace brd;
+
+namespace {
+
+thread_local std::string g_last_error = "";
+
+struct Err : std::runtime_error {
+    int code;
+    Err(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                                      \
+    do {                                                                                               \
+        hipError_t e_ = (x);                                                                           \
+        if (e_ != hipSuccess)                                                                          \
+            throw Err(BLOB_RD_EDEVICE, std::string(#x ": ") + hipGetErrorString(e_));                  \
+    } while (0)
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int level_dims(int nx, int ny, int nz, LevelDims* out) {
+    int l = 0;
+    for (;;) {
+        if (l >= kMaxLevels) return -1;
+        out[l].nx = nx;
+        out[l].ny = ny;
+        out[l].nz = nz;
+        out[l].hx = nx / 2;
+        ++l;
+        if ((nx & 1) || (ny & 1) || (nz & 1) || nx <= 4 || ny <= 4 || nz <= 4) break;
+        nx /= 2;
+        ny /= 2;
+        nz /= 2;
+    }
+    return l;
+}
+
+int tile_edge(int n) {
+    if (n % 8 == 0) return 8;
+    for (int d = 7; d >= 3; --d)
+        if (n % d == 0) return d;
+    return -1;
+}
+
+// Workspace plan: byte offsets of every buffer.
+struct Plan {
+    size_t ncell = 0;
+    int nlev = 0;
+    LevelDims lev[kMaxLevels];
+    int m = 0;
+    size_t esz = 8;
+    int N = 0, restart = 30, ntiles = 0;
+    BlobGeom geom{};
+    size_t off_grid[7]{};
+    size_t off_lvl[kMaxLevels][6]{};
+    size_t off_cinv[4]{};
+    size_t off_part = 0, part_cap = 0;
+    size_t off_sc = 0, off_gs = 0, off_dsc = 0;
+    size_t off_q = 0, off_kappa = 0, off_base = 0, off_wts = 0, off_tile = 0, off_counts = 0, off_offsets = 0,
+           off_cursor = 0, off_perm = 0;
+    size_t off_nv[12]{};
+    size_t off_V = 0, off_H = 0, off_cs = 0, off_sn = 0, off_gv = 0, off_yv = 0;
+    size_t total = 0;
+};
+
+int make_plan(const blob_rd_params* p, Plan* P, std::string* why) {
+    if (!p) {
+        *why = "null params";
+        return BLOB_RD_EINVAL;
+    }
+    if (p->nx < 8 || p->ny < 8 || p->nz < 8) {
+        *why = "grid dims must be >= 8";
+        return BLOB_RD_EINVAL;
+    }
+    if (!(p->h > 0.0) || !(p->D > 0.0)) {
+        *why = "h and D must be positive";
+        return BLOB_RD_EINVAL;
+    }
+    if (p->kernel_w != 3 && p->kernel_w != 4) {
+        *why = "kernel_w must be 3 or 4";
+        return BLOB_RD_EINVAL;
+    }
+    if (p->n_blobs < 0 || p->n_blobs > (1 << 26)) {
+        *why = "n_blobs out of range";
+        return BLOB_RD_EINVAL;
+    }
+    if (p->n_blobs > 0 && !p->q) {
+        *why = "q is null";
+        return BLOB_RD_EINVAL;
+    }
+    if (p->precision != BLOB_RD_FP64 && p->precision != BLOB_RD_MIXED) {
+        *why = "precision must be FP64 (0) or MIXED (1)";
+        return BLOB_RD_EINVAL;
+    }
+    const size_t ncell = (size_t)p->nx * p->ny * p->nz;
+    if (ncell > (size_t)1 << 30) {
+        *why = "grid too large";
+        return BLOB_RD_EINVAL;
+    }
+    P->ncell = ncell;
+    P->nlev = level_dims(p->nx, p->ny, p->nz, P->lev);
+    if (P->nlev < 2) {
+        *why = "grid cannot be coarsened";
+        return BLOB_RD_EINVAL;
+    }
+    for (int l = 0; l < P->nlev; ++l) P->lev[l].h = p->h * (double)(1 << l);
+    const LevelDims& C = P->lev[P->nlev - 1];
+    P->m = C.nx * C.ny * C.nz;
+    if (P->m > kMaxCoarse) {
+        *why = "coarsest multigrid level exceeds 512 cells (dims must be 2^k times a small factor)";
+        return BLOB_RD_EINVAL;
+    }
+    const int tx = tile_edge(p->nx), ty = tile_edge(p->ny), tz = tile_edge(p->nz);
+    if (tx < 0 || ty < 0 || tz < 0) {
+        *why = "each grid dim needs a divisor between 3 and 8";
+        return BLOB_RD_EINVAL;
+    }
+    P->geom = BlobGeom{p->nx, p->ny, p->nz, tx, ty, tz, p->nx / tx, p->ny / ty, p->nz / tz, p->h, p->kernel_w};
+    P->ntiles = P->geom.ntx * P->geom.nty * P->geom.ntz;
+    P->esz = p->precision == BLOB_RD_MIXED ? 4 : 8;
+    P->N = (int)p->n_blobs;
+    P->restart = p->gmres_restart > 0 ? p->gmres_restart : 30;
+    if (P->restart > 200) {
+        *why = "gmres_restart must be <= 200";
+        return BLOB_RD_EINVAL;
+    }
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = align_up(o + bytes);
+        return r;
+    };
+    for (int i = 0; i < 7; ++i) P->off_grid[i] = take(ncell * 8);
+    for (int l = 0; l < P->nlev - 1; ++l) {
+        const size_t half = (size_t)P->lev[l].hx * P->lev[l].ny * P->lev[l].nz;
+        for (int k = 0; k < 6; ++k) P->off_lvl[l][k] = take(half * P->esz);
+    }
+    P->off_lvl[P->nlev - 1][0] = take((size_t)P->m * P->esz);  // coarsest u (natural)
+    P->off_lvl[P->nlev - 1][2] = take((size_t)P->m * P->esz);  // coarsest f (natural)
+    for (int k = 0; k < 4; ++k) P->off_cinv[k] = take((size_t)P->m * P->m * 8);
+    P->part_cap = nblocks(ncell) + 64;
+    P->off_part = take(P->part_cap * 3 * 8);
+    P->off_sc = take(sizeof(Scalars));
+    P->off_gs = take(sizeof(GmresScalars));
+    P->off_dsc = take(64 * 8);
+    const size_t N = (size_t)std::max(P->N, 1);
+    P->off_q = take(N * 3 * 8);
+    P->off_kappa = take(N * 8);
+    P->off_base = take(N * 3 * 4);
+    P->off_wts = take(N * 12 * 8);
+    P->off_tile = take(N * 4);
+    P->off_counts = take((size_t)P->ntiles * 4);
+    P->off_offsets = take(((size_t)P->ntiles + 1) * 4);
+    P->off_cursor = take((size_t)P->ntiles * 4);
+    P->off_perm = take(N * 4);
+    for (int k = 0; k < 12; ++k) P->off_nv[k] = take(N * 8);
+    const size_t m = (size_t)P->restart;
+    P->off_V = take((m + 1) * N * 8);
+    P->off_H = take((m + 1) * m * 8);
+    P->off_cs = take(m * 8);
+    P->off_sn = take(m * 8);
+    P->off_gv = take((m + 1) * 8);
+    P->off_yv = take(m * 8);
+    P->total = o + 256;
+    return 0;
+}
+
+// Dense (pseudo-)inverse of the coarsest operator alpha I - D L_H (row-major m x m).
+// For alpha = 0 it returns (A + e e^T/m)^{-1} - e e^T/m, the pseudo-inverse on
+// mean-zero vectors. LU with partial pivoting, then column-wise solves.
+std::vector<double> coarse_inverse(const LevelDims& C, double D, double alpha) {
+    const int nx = C.nx, ny = C.ny, nz = C.nz, m = nx * ny * nz;
+    const double s = D / (C.h * C.h);
+    std::vector<double> A((size_t)m * m, 0.0);
+    auto id = [&](int x, int y, int z) {
+        x = (x + nx) % nx;
+        y = (y + ny) % ny;
+        z = (z + nz) % nz;
+        return (z * ny + y) * nx + x;
+    };
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int r = id(x, y, z);
+                A[(size_t)r * m + r] += alpha + 6.0 * s;
+                const int nb[6] = {id(x - 1, y, z), id(x + 1, y, z), id(x, y - 1, z),
+                                   id(x, y + 1, z), id(x, y, z - 1), id(x, y, z + 1)};
+                for (int k = 0; k < 6; ++k) A[(size_t)r * m + nb[k]] -= s;
+            }
+    const double e = 1.0 / m;
+    if (alpha == 0.0)
+        for (auto& v : A) v += e;
+    std::vector<int> piv(m);
+    for (int k = 0; k < m; ++k) {
+        int pr = k;
+        for (int i = k + 1; i < m; ++i)
+            if (std::fabs(A[(size_t)i * m + k]) > std::fabs(A[(size_t)pr * m + k])) pr = i;
+        piv[k] = pr;
+        if (pr != k)
+            for (int j = 0; j < m; ++j) std::swap(A[(size_t)k * m + j], A[(size_t)pr * m + j]);
+        const double d = A[(size_t)k * m + k];
+        if (d == 0.0) throw Err(BLOB_RD_ESINGULAR, "singular coarsest operator");
+        for (int i = k + 1; i < m; ++i) {
+            const double l = A[(size_t)i * m + k] / d;
+            A[(size_t)i * m + k] = l;
+            for (int j = k + 1; j < m; ++j) A[(size_t)i * m + j] -= l * A[(size_t)k * m + j];
+        }
+    }
+    std::vector<double> inv((size_t)m * m);
+    std::vector<double> col(m);
+    for (int c = 0; c < m; ++c) {
+        std::fill(col.begin(), col.end(), 0.0);
+        col[c] = 1.0;
+        for (int k = 0; k < m; ++k)
+            if (piv[k] != k) std::swap(col[k], col[piv[k]]);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < i; ++j) col[i] -= A[(size_t)i * m + j] * col[j];
+        for (int i = m - 1; i >= 0; --i) {
+            for (int j = i + 1; j < m; ++j) col[i] -= A[(size_t)i * m + j] * col[j];
+            col[i] /= A[(size_t)i * m + i];
+        }
+        for (int r = 0; r < m; ++r) inv[(size_t)r * m + c] = col[r] - (alpha == 0.0 ? e : 0.0);
+    }
+    return inv;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct blob_rd {
+    Plan P;
+    blob_rd_params prm{};
+    hipStream_t st = nullptr;
+    char* ws = nullptr;
+    double sum_kappa = 0.0;
+    bool has_kappa = false;
+    double cinv_alpha[4];
+    int cinv_used = 0;
+    int cinv_next = 0;
+    // host mirrors (pinned)
+    Scalars* hsc = nullptr;
+    GmresScalars* hgs = nullptr;
+    double* hbuf = nullptr;
+    std::string err;
+    // counters for stats of the current call
+    int vcycles = 0;
+    double alg_bytes = 0.0;
+    int inner_iters = 0;
+    int last_iters[4] = {0, 0, 0, 0};  // CG iterations of the previous solve per (blobs, alpha == 0)
+
+    template <typename T>
+    T* at(size_t off) const {
+        return reinterpret_cast<T*>(ws + off);
+    }
+    double* grid(int i) const { return at<double>(P.off_grid[i]); }
+    Scalars* sc() const { return at<Scalars>(P.off_sc); }
+    GmresScalars* gs() const { return at<GmresScalars>(P.off_gs); }
+    double* part() const { return at<double>(P.off_part); }
+    double* dsc() const { return at<double>(P.off_dsc); }
+    double* nv(int k) const { return at<double>(P.off_nv[k]); }
+    double inv_h3() const { return 1.0 / (prm.h * prm.h * prm.h); }
+};
+
+namespace {
+
+enum GridBuf { G_R = 0, G_P = 1, G_Q = 2, G_U = 3, G_G = 4, G_T1 = 5, G_T2 = 6 };
+
+__global__ void k_sc_init(Scalars* sc, int project, double inv_ncell, double eBe_inv, double rtol2, double abs2) {
+    sc->rz = 0.0;
+    sc->pq = 0.0;
+    sc->alpha = 0.0;
+    sc->beta = 0.0;
+    sc->rr = 0.0;
+    sc->rsum = 0.0;
+    sc->qsum = 0.0;
+    sc->tol2 = rtol2;
+    sc->shift = 0.0;
+    sc->mean_r = 0.0;
+    sc->inv_ncell = inv_ncell;
+    sc->eBe_inv = eBe_inv;
+    sc->rr0 = abs2;
+    sc->gg = 0.0;
+    sc->done = 0;
+    sc->iters = 0;
+    sc->project = project;
+    sc->status = 0;
+}
+
+void sync_read(blob_rd* H, void* host, const void* dev, size_t bytes) {
+    HIPCHK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, H->st));
+    HIPCHK(hipStreamSynchronize(H->st));
+}
+
+const double* select_cinv(blob_rd* H, double alpha) {
+    for (int k = 0; k < H->cinv_used; ++k)
+        if (H->cinv_alpha[k] == alpha) return H->at<double>(H->P.off_cinv[k]);
+    const int slot = H->cinv_next;
+    H->cinv_next = (H->cinv_next + 1) % 4;
+    if (H->cinv_used < 4) ++H->cinv_used;
+    H->cinv_alpha[slot] = alpha;
+    std::vector<double> inv = coarse_inverse(H->P.lev[H->P.nlev - 1], H->prm.D, alpha);
+    double* dst = H->at<double>(H->P.off_cinv[slot]);
+    HIPCHK(hipMemcpyAsync(dst, inv.data(), inv.size() * 8, hipMemcpyHostToDevice, H->st));
+    HIPCHK(hipStreamSynchronize(H->st));
+    return dst;
+}
+
+// One V(2,2) cycle for alpha I - D L applied to the FP64 natural vector r
+// (mean_r removed when the scalars say so); the result is left in level 0's
+// u arrays (split layout).
+template <typename T>
+void vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const double* cinv) {
+    const Plan& P = H->P;
+    const int L = P.nlev - 1;
+    hipStream_t st = H->st;
+    auto lv = [&](int l, int k) { return H->at<T>(P.off_lvl[l][k]); };  // 0 u0, 1 u1, 2 f0, 3 f1, 4 r0, 5 r1
+    const double D = H->prm.D;
+    {
+        const LevelDims& d = P.lev[0];
+        const double s = D / (d.h * d.h);
+        launch_enter<T>(st, r, lv(0, 2), lv(0, 3), lv(0, 0), d.nx, d.ny, d.nz, 1.0 / (alpha + 6.0 * s), sc);
+    }
+    for (int l = 0; l < L; ++l) {
+        const LevelDims& d = P.lev[l];
+        const double s = D / (d.h * d.h), diag = alpha + 6.0 * s;
+        launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc);
+        launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc);
+        launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc);
+        launch_resid_split<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), lv(l, 3), lv(l, 4), lv(l, 5), d.hx, d.ny, d.nz, s,
+                              diag, sc);
+        const int cnat = (l + 1 == L);
+        const LevelDims& c = P.lev[l + 1];
+        const double sc_ = D / (c.h * c.h);
+        if (cnat)
+            launch_restrict<T>(st, lv(l, 4), lv(l, 5), d.nx, d.ny, d.nz, lv(L, 2), nullptr, nullptr, 1, 0.0, sc);
+        else
+            launch_restrict<T>(st, lv(l, 4), lv(l, 5), d.nx, d.ny, d.nz, lv(l + 1, 2), lv(l + 1, 3), lv(l + 1, 0), 0,
+                               1.0 / (alpha + 6.0 * sc_), sc);
+        H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * (3 * 1.5 + 3 + 1.125);
+    }
+    launch_coarse<T>(st, lv(L, 2), lv(L, 0), cinv, P.m, sc);
+    for (int l = L - 1; l >= 0; --l) {
+        const LevelDims& d = P.lev[l];
+        const double s = D / (d.h * d.h), diag = alpha + 6.0 * s;
+        const int cnat = (l + 1 == L);
+        launch_prolong<T>(st, lv(l + 1, 0), cnat ? nullptr : lv(l + 1, 1), cnat, lv(l, 0), lv(l, 1), d.nx, d.ny, d.nz,
+                          sc);
+        launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc);
+        launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc);
+        launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc);
+        launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc);
+        H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * (4 * 1.5 + 2.125);
+    }
+    H->alg_bytes += (double)P.ncell * (8 + P.esz * 1.5);
+    H->vcycles += 1;
+}
+
+template <typename T>
+void precond_zdots(blob_rd* H, double alpha, const double* r, const double* q, const double* cinv) {
+    vcycle<T>(H, alpha, r, H->sc(), cinv);
+    const LevelDims& d = H->P.lev[0];
+    unsigned np = 0;
+    launch_zdots<T>(H->st, H->at<T>(H->P.off_lvl[0][0]), H->at<T>(H->P.off_lvl[0][1]), r, q, d.nx, d.ny, d.nz,
+                    H->part(), H->sc(), &np);
+    launch_fin(H->st, FIN_BETA, H->part(), np, H->sc(), nullptr, nullptr, 0, 0.0);
+    H->alg_bytes += (double)H->P.ncell * (H->P.esz + 16);
+}
+
+// q += S kappa J p, with jx = J p and mu = kappa J p kept for the CG dots.
+void blob_term(blob_rd* H, const double* p, double* q, const Scalars* sc) {
+    const Plan& P = H->P;
+    launch_interp(H->st, p, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts), H->at<int>(P.off_perm),
+                  H->nv(0), H->at<double>(P.off_kappa), H->nv(1), sc);
+    launch_spread(H->st, H->nv(1), 0.0, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
+                  H->at<int>(P.off_offsets), H->at<int>(P.off_perm), q, q, H->inv_h3(), 1, sc);
+}
+
+struct PcgResult {
+    int iters = 0;
+    int status = 0;
+    bool converged = false;
+    double rr = 0.0, gg = 0.0;
+};
+
+// CG on (alpha I - D L [+ S kappa J]) x = g. x_zero: start from x = 0 (x is
+// overwritten). Stops at |r|^2 <= max(rtol^2 |g|^2, abs_tol^2).
+template <typename T>
+PcgResult pcg(blob_rd* H, bool with_blobs, double alpha, const double* g, double* x, bool x_zero, double rtol,
+              double abs_tol, int maxit) {
+    const Plan& P = H->P;
+    hipStream_t st = H->st;
+    double* r = H->grid(G_R);
+    double* p = H->grid(G_P);
+    double* q = H->grid(G_Q);
+    const LevelDims& d = P.lev[0];
+    const double s = H->prm.D / (d.h * d.h);
+    const int project = alpha == 0.0 ? 1 : 0;
+    const bool blobs = with_blobs && P.N > 0 && H->has_kappa;
+    const double eBe = alpha * (double)P.ncell + H->sum_kappa * H->inv_h3();
+    const double eBe_inv = (with_blobs && project && eBe > 0.0) ? 1.0 / eBe : 0.0;
+    const double* cinv = select_cinv(H, alpha);
+    hipLaunchKernelGGL(k_sc_init, dim3(1), dim3(1), 0, st, H->sc(), project, 1.0 / (double)P.ncell, eBe_inv,
+                       rtol * rtol, abs_tol * abs_tol);
+    unsigned np = 0;
+    if (x_zero) {
+        launch_fill(st, x, P.ncell, 0.0);
+        launch_residual_from_q(st, g, nullptr, r, P.ncell, H->part(), &np);
+        H->alg_bytes += (double)P.ncell * 24;
+    } else {
+        launch_applyA_plain(st, x, q, alpha, s, d.nx, d.ny, d.nz);
+        if (blobs) blob_term(H, x, q, nullptr);
+        launch_residual_from_q(st, g, q, r, P.ncell, H->part(), &np);
+        H->alg_bytes += (double)P.ncell * 40;
+    }
+    launch_fin(st, FIN_INIT, H->part(), np, H->sc(), nullptr, nullptr, 0, 0.0);
+    precond_zdots<T>(H, alpha, r, q, cinv);
+    int& hist = H->last_iters[(with_blobs ? 2 : 0) + project];
+    int chunk = hist > 0 ? std::min(hist, maxit) : std::min(4, maxit);
+    int done_iters = 0;
+    PcgResult res;
+    for (;;) {
+        for (int k = 0; k < chunk; ++k) {
+            launch_dir<T>(st, H->at<T>(P.off_lvl[0][0]), H->at<T>(P.off_lvl[0][1]), p, d.nx, d.ny, d.nz, H->sc());
+            launch_applyA(st, p, q, alpha, s, d.nx, d.ny, d.nz, H->part(), H->sc(), &np);
+            if (blobs) {
+                blob_term(H, p, q, H->sc());
+                launch_fin(st, FIN_ALPHA, H->part(), np, H->sc(), H->nv(0), H->nv(1), P.N, H->inv_h3());
+            } else {
+                launch_fin(st, FIN_ALPHA, H->part(), np, H->sc(), nullptr, nullptr, 0, 0.0);
+            }
+            launch_update(st, x, r, p, q, P.ncell, H->part(), H->sc(), &np);
+            launch_fin(st, FIN_UPDATE, H->part(), np, H->sc(), nullptr, nullptr, 0, 0.0);
+            precond_zdots<T>(H, alpha, r, q, cinv);
+            H->alg_bytes += (double)P.ncell * (P.esz + 24 + 16 + 48);
+        }
+        sync_read(H, H->hsc, H->sc(), sizeof(Scalars));
+        done_iters = H->hsc->iters;
+        if (H->hsc->done || done_iters >= maxit) break;
+        // predict the remaining iterations from the observed contraction
+        const Scalars& hs = *H->hsc;
+        chunk = 4;
+        if (done_iters > 0 && hs.rr0 > 0.0 && hs.rr > 0.0 && hs.tol2 > 0.0 && hs.rr < hs.rr0) {
+            const double rho = std::pow(hs.rr / hs.rr0, 0.5 / done_iters);
+            const double rem = std::log(std::sqrt(hs.tol2 / hs.rr)) / std::log(rho);
+            if (std::isfinite(rem)) chunk = (int)std::ceil(rem);
+        }
+        chunk = std::max(1, std::min(16, chunk));
+        if (done_iters + chunk > maxit) chunk = maxit - done_iters;
+    }
+    res.iters = H->hsc->iters;
+    hist = res.iters;
+    res.status = H->hsc->status;
+    res.rr = H->hsc->rr;
+    res.gg = H->hsc->gg;
+    res.converged = H->hsc->done && H->hsc->status == 0;
+    return res;
+}
+
+// True FP64 residual t = g - B x; returns |t| and |g|.
+void true_residual(blob_rd* H, bool with_blobs, double alpha, const double* g, const double* x, double* t, double* rn,
+                   double* gn) {
+    const Plan& P = H->P;
+    const LevelDims& d = P.lev[0];
+    const double s = H->prm.D / (d.h * d.h);
+    double* q = H->grid(G_Q);
+    launch_applyA_plain(H->st, x, q, alpha, s, d.nx, d.ny, d.nz);
+    if (with_blobs && P.N > 0 && H->has_kappa) blob_term(H, x, q, nullptr);
+    unsigned np = 0;
+    launch_residual_from_q(H->st, g, q, t, P.ncell, H->part(), &np);
+    launch_reduce_parts(H->st, H->part(), np, 3, H->dsc());
+    sync_read(H, H->hbuf, H->dsc(), 3 * 8);
+    *rn = std::sqrt(H->hbuf[0]);
+    *gn = std::sqrt(H->hbuf[2]);
+    H->alg_bytes += (double)P.ncell * 40;
+}
+
+int default_maxit(blob_rd* H) { return H->prm.max_iter > 0 ? H->prm.max_iter : 1000; }
+int inner_maxit(blob_rd* H) { return H->prm.inner_max_iter > 0 ? H->prm.inner_max_iter : 200; }
+
+template <typename T>
+int reactive_solve(blob_rd* H, double alpha, const double* g, double* c, blob_rd_stats* stt) {
+    const double rtol = H->prm.rtol > 0.0 ? H->prm.rtol : 1e-8;
+    int total = 0, refinements = 0;
+    double rn = 0.0, gn = 1.0;
+    bool ok = false;
+    for (int pass = 0; pass < 4; ++pass) {
+        // CG aims a little below the target so the true residual lands under it.
+        PcgResult pr = pcg<T>(H, true, alpha, g, c, false, 0.5 * rtol, 0.0, default_maxit(H) - total);
+        total += pr.iters;
+        if (pr.status) throw Err(BLOB_RD_ENUMERIC, "non-finite value or breakdown in CG");
+        true_residual(H, true, alpha, g, c, H->grid(G_T1), &rn, &gn);
+        if (gn == 0.0) gn = 1.0;
+        if (rn <= rtol * gn) {
+            ok = true;
+            break;
+        }
+        if (total >= default_maxit(H)) break;
+        ++refinements;
+    }
+    if (stt) {
+        stt->outer_iters = total;
+        stt->rel_resid = rn / gn;
+        stt->refinements = refinements;
+    }
+    return ok ? BLOB_RD_OK : BLOB_RD_ENOTCONV;
+}
+
+// y = [P] J A^+ S [P] x for N-vectors x (device) -> y (device).
+template <typename T>
+void schur_apply(blob_rd* H, double alpha, const double* x, double* y, double inner_rtol) {
+    const Plan& P = H->P;
+    hipStream_t st = H->st;
+    double* xt = H->nv(2);
+    launch_nvec_copy_scale(st, x, xt, P.N, 1.0, 0.0);
+    if (alpha == 0.0) launch_nvec_project(st, xt, P.N);
+    launch_spread(st, xt, 0.0, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
+                  H->at<int>(P.off_offsets), H->at<int>(P.off_perm), nullptr, H->grid(G_G), H->inv_h3(), 0, nullptr);
+    H->alg_bytes += (double)P.ncell * 8;
+    PcgResult pr = pcg<T>(H, false, alpha, H->grid(G_G), H->grid(G_U), true, inner_rtol, 0.0, inner_maxit(H));
+    if (pr.status) throw Err(BLOB_RD_ENUMERIC, "non-finite value or breakdown in inner CG");
+    H->inner_iters += pr.iters;
+    launch_interp(st, H->grid(G_U), P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
+                  H->at<int>(P.off_perm), nullptr, nullptr, y, nullptr);
+    if (alpha == 0.0) launch_nvec_project(st, y, P.N);
+}
+
+struct SaddleInfo {
+    int gmres_iters = 0;
+    double schur_res = 0.0;
+    bool converged = false;
+};
+
+// Solve [A, S; J, 0][c; lam] = [g; phi] (phi may be null = 0) with Schur GMRES.
+template <typename T>
+SaddleInfo saddle_solve(blob_rd* H, double alpha, const double* g, const double* phi, double* c, double* lam,
+                        double atol_schur, double final_rtol_abs, double inner_rtol) {
+    const Plan& P = H->P;
+    hipStream_t st = H->st;
+    const int N = P.N;
+    const double h3 = H->prm.h * H->prm.h * H->prm.h;
+    SaddleInfo info;
+    // total source -> mean sink strength (Appendix A)
+    double lbar = 0.0;
+    if (alpha == 0.0) {
+        unsigned np = 0;
+        launch_norm_partials(st, g, P.ncell, H->part(), &np);
+        launch_reduce_parts(st, H->part(), np, 2, H->dsc());
+        sync_read(H, H->hbuf, H->dsc(), 16);
+        lbar = h3 * H->hbuf[0] / (double)N;
+        H->alg_bytes += (double)P.ncell * 8;
+    }
+    double* gg = H->grid(G_G);
+    double* u = H->grid(G_U);
+    // u0 = A^+ (g - lbar S 1); b = J u0 - phi (projected)
+    double* rhs0 = H->grid(G_T2);
+    launch_spread(st, nullptr, -lbar, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
+                  H->at<int>(P.off_offsets), H->at<int>(P.off_perm), g, rhs0, H->inv_h3(), 0, nullptr);
+    H->alg_bytes += (double)P.ncell * 16;
+    PcgResult pr = pcg<T>(H, false, alpha, rhs0, u, true, inner_rtol, 0.0, inner_maxit(H));
+    if (pr.status) throw Err(BLOB_RD_ENUMERIC, "non-finite value in Poisson solve");
+    H->inner_iters += pr.iters;
+    double* b = H->nv(3);
+    launch_interp(st, u, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts), H->at<int>(P.off_perm), nullptr,
+                  nullptr, b, nullptr);
+    if (phi) launch_axpby(st, b, phi, N, 1.0, -1.0);
+    if (alpha == 0.0) launch_nvec_project(st, b, N);
+    // GMRES(m) with MGS on the (projected) Schur system G lt = b
+    double* lt = H->nv(4);
+    double* w = H->nv(5);
+    launch_nvec_copy_scale(st, nullptr, lt, N, 0.0, 0.0);
+    const int m = P.restart;
+    double* V = H->at<double>(P.off_V);
+    double* Hm = H->at<double>(P.off_H);
+    const int maxit = default_maxit(H);
+    bool first = true;
+    for (;;) {
+        if (!first) schur_apply<T>(H, alpha, lt, w, inner_rtol);
+        launch_gmres_start(st, b, w, first ? 0 : 1, V, H->at<double>(P.off_gv), N, H->gs());
+        first = false;
+        sync_read(H, H->hgs, H->gs(), sizeof(GmresScalars));
+        info.schur_res = H->hgs->res;
+        if (H->hgs->status) throw Err(BLOB_RD_ENUMERIC, "non-finite Schur residual");
+        if (H->hgs->res <= atol_schur) {
+            info.converged = true;
+            break;
+        }
+        if (info.gmres_iters >= maxit) break;
+        int k = 0;
+        for (; k < m && info.gmres_iters < maxit; ++k) {
+            schur_apply<T>(H, alpha, V + (size_t)k * N, V + (size_t)(k + 1) * N, inner_rtol);
+            launch_gmres_arnoldi(st, V, Hm, H->at<double>(P.off_cs), H->at<double>(P.off_sn),
+                                 H->at<double>(P.off_gv), N, k, m, H->gs());
+            ++info.gmres_iters;
+            sync_read(H, H->hgs, H->gs(), sizeof(GmresScalars));
+            if (H->hgs->status) throw Err(BLOB_RD_ENUMERIC, "GMRES breakdown");
+            if (H->hgs->res <= atol_schur || H->hgs->hk1 == 0.0) {
+                ++k;
+                break;
+            }
+        }
+        launch_gmres_update(st, V, Hm, H->at<double>(P.off_gv), H->at<double>(P.off_yv), lt, N, k, m);
+        info.schur_res = H->hgs->res;
+        // The Arnoldi estimate decides; the FP64 saddle residual computed by the
+        // caller checks the answer and triggers refinement if needed.
+        if (H->hgs->res <= atol_schur) {
+            info.converged = true;
+            break;
+        }
+        if (info.gmres_iters >= maxit) break;
+    }
+    if (alpha == 0.0) launch_nvec_project(st, lt, N);
+    // lam = lbar + lt ; c = A^+ (g - S lam) (+ cbar)
+    launch_nvec_copy_scale(st, lt, lam, N, 1.0, lbar);
+    launch_spread(st, lam, 0.0, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
+                  H->at<int>(P.off_offsets), H->at<int>(P.off_perm), g, gg, -H->inv_h3(), 0, nullptr);
+    H->alg_bytes += (double)P.ncell * 16;
+    pr = pcg<T>(H, false, alpha, gg, c, true, 0.0, final_rtol_abs, inner_maxit(H));
+    if (pr.status) throw Err(BLOB_RD_ENUMERIC, "non-finite value in Poisson solve");
+    H->inner_iters += pr.iters;
+    if (alpha == 0.0) {
+        // J c + cbar = phi  ->  cbar = mean(phi - J c)
+        double* jc = H->nv(6);
+        launch_interp(st, c, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts), H->at<int>(P.off_perm),
+                      nullptr, nullptr, jc, nullptr);
+        if (phi) launch_axpby(st, jc, phi, N, 1.0, -1.0);
+        launch_nvec_sums(st, jc, nullptr, N, H->dsc());
+        sync_read(H, H->hbuf, H->dsc(), 24);
+        const double cbar = -H->hbuf[0] / (double)N;
+        launch_fill(st, H->dsc() + 32, 1, cbar);
+        launch_add_shift(st, c, P.ncell, H->dsc() + 32, 1.0);
+        H->alg_bytes += (double)P.ncell * 16;
+    }
+    return info;
+}
+
+// FP64 saddle residual: t = g - A c - S lam (grid), tn = phi - J c (N); returns norms^2.
+void saddle_residual(blob_rd* H, double alpha, const double* g, const double* phi, const double* c, const double* lam,
+                     double* t, double* tn, double* r1sq, double* r2sq, double* gsq) {
+    const Plan& P = H->P;
+    const LevelDims& d = P.lev[0];
+    const double s = H->prm.D / (d.h * d.h);
+    double* q = H->grid(G_Q);
+    launch_applyA_plain(H->st, c, q, alpha, s, d.nx, d.ny, d.nz);
+    launch_spread(H->st, lam, 0.0, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
+                  H->at<int>(P.off_offsets), H->at<int>(P.off_perm), q, q, H->inv_h3(), 1, nullptr);
+    unsigned np = 0;
+    launch_residual_from_q(H->st, g, q, t, P.ncell, H->part(), &np);
+    launch_reduce_parts(H->st, H->part(), np, 3, H->dsc());
+    launch_interp(H->st, c, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts), H->at<int>(P.off_perm),
+                  nullptr, nullptr, tn, nullptr);
+    if (phi)
+        launch_axpby(H->st, tn, phi, P.N, -1.0, 1.0);
+    else
+        launch_nvec_copy_scale(H->st, tn, tn, P.N, -1.0, 0.0);
+    launch_nvec_sums(H->st, tn, nullptr, P.N, H->dsc() + 3);
+    sync_read(H, H->hbuf, H->dsc(), 6 * 8);
+    *r1sq = H->hbuf[0];
+    *gsq = H->hbuf[2];
+    *r2sq = H->hbuf[4];
+    H->alg_bytes += (double)P.ncell * 40;
+}
+
+template <typename T>
+int absorbing_solve(blob_rd* H, double alpha, const double* f, double* c, double* lam, blob_rd_stats* stt) {
+    const Plan& P = H->P;
+    const double rtol = H->prm.rtol > 0.0 ? H->prm.rtol : 1e-8;
+    // |f| sets the scale of the saddle residual
+    unsigned np = 0;
+    launch_norm_partials(H->st, f, P.ncell, H->part(), &np);
+    launch_reduce_parts(H->st, H->part(), np, 2, H->dsc());
+    sync_read(H, H->hbuf, H->dsc(), 16);
+    double fn = std::sqrt(H->hbuf[1]);
+    if (fn == 0.0) fn = 1.0;
+    const double inner_rtol = std::min(1e-2, 0.05 * rtol);
+    SaddleInfo si = saddle_solve<T>(H, alpha, f, nullptr, c, lam, 0.4 * rtol * fn, 0.4 * rtol * fn, inner_rtol);
+    int gm = si.gmres_iters;
+    double r1, r2, gsq;
+    double* t = H->grid(G_T1);
+    double* tn = H->nv(7);
+    saddle_residual(H, alpha, f, nullptr, c, lam, t, tn, &r1, &r2, &gsq);
+    double rel = std::sqrt(r1 + r2) / fn;
+    int refinements = 0;
+    // iterative refinement on the residual equations, in FP64 residuals
+    double* dc = H->grid(G_T2);
+    while (rel > rtol && refinements < 3 && gm < default_maxit(H)) {
+        ++refinements;
+        // correction system [A, S; J, 0][dc; dlam] = [t; tn] with t in G_T1 and tn
+        // in nv(7); saddle_solve only reads them and writes dc (G_T2), dlam (nv(8)).
+        double* dlam = H->nv(8);
+        SaddleInfo s2 = saddle_solve<T>(H, alpha, t, tn, dc, dlam, 0.4 * rtol * fn, 0.4 * rtol * fn, inner_rtol);
+        gm += s2.gmres_iters;
+        launch_axpby(H->st, c, dc, P.ncell, 1.0, 1.0);
+        launch_axpby(H->st, lam, dlam, P.N, 1.0, 1.0);
+        saddle_residual(H, alpha, f, nullptr, c, lam, t, tn, &r1, &r2, &gsq);
+        rel = std::sqrt(r1 + r2) / fn;
+    }
+    if (stt) {
+        stt->outer_iters = gm;
+        stt->rel_resid = rel;
+        stt->refinements = refinements;
+    }
+    return rel <= rtol ? BLOB_RD_OK : BLOB_RD_ENOTCONV;
+}
+
+__global__ void k_step_rhs(const double* f, const double* c, double* g, unsigned n, double inv_dt) {
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) g[i] = f[i] + inv_dt * c[i];
+}
+
+int fail(blob_rd* H, const Err& e) {
+    g_last_error = e.what();
+    if (H) H->err = e.what();
+    return e.code;
+}
+
+template <typename F>
+int guarded(blob_rd* H, blob_rd_stats* stt, F&& fn) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (H) {
+        H->vcycles = 0;
+        H->alg_bytes = 0.0;
+        H->inner_iters = 0;
+    }
+    if (stt) std::memset(stt, 0, sizeof(*stt));
+    int rc;
+    try {
+        rc = fn();
+    } catch (const Err& e) {
+        rc = fail(H, e);
+    } catch (const std::exception& e) {
+        rc = fail(H, Err(BLOB_RD_EDEVICE, e.what()));
+    }
+    if (stt && H) {
+        stt->vcycles = H->vcycles;
+        stt->alg_bytes = H->alg_bytes;
+        stt->inner_iters_total = H->inner_iters;
+        stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return rc;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+size_t blob_rd_workspace_bytes(const blob_rd_params* p) {
+    Plan P;
+    std::string why;
+    if (make_plan(p, &P, &why) != 0) {
+        g_last_error = why;
+        return 0;
+    }
+    return P.total;
+}
+
+int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
+    if (!out) {
+        g_last_error = "null output handle";
+        return BLOB_RD_EINVAL;
+    }
+    *out = nullptr;
+    blob_rd* H = new blob_rd();
+    std::string why;
+    int rc = make_plan(p, &H->P, &why);
+    if (rc != 0) {
+        g_last_error = why;
+        delete H;
+        return rc;
+    }
+    if (!p->workspace || p->workspace_bytes < H->P.total) {
+        g_last_error = "workspace missing or smaller than blob_rd_workspace_bytes()";
+        delete H;
+        return BLOB_RD_ENOMEM;
+    }
+    H->prm = *p;
+    H->st = (hipStream_t)p->stream;
+    // Align the workspace base to 256 bytes.
+    uintptr_t base = (uintptr_t)p->workspace;
+    H->ws = (char*)((base + 255) & ~(uintptr_t)255);
+    try {
+        HIPCHK(hipHostMalloc((void**)&H->hsc, sizeof(Scalars), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&H->hgs, sizeof(GmresScalars), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&H->hbuf, 64 * sizeof(double), hipHostMallocDefault));
+        const Plan& P = H->P;
+        const int N = P.N;
+        hipStream_t st = H->st;
+        HIPCHK(hipMemsetAsync(H->at<int>(P.off_counts), 0, (size_t)P.ntiles * 4, st));
+        HIPCHK(hipMemsetAsync(H->at<int>(P.off_cursor), 0, (size_t)P.ntiles * 4, st));
+        HIPCHK(hipMemsetAsync(H->grid(G_Q), 0, P.ncell * 8, st));
+        HIPCHK(hipMemsetAsync(H->grid(G_P), 0, P.ncell * 8, st));
+        if (N > 0) {
+            // Validate inputs on the host before any kernel derives indices from them.
+            std::vector<double> hq((size_t)N * 3), hk;
+            HIPCHK(hipMemcpyAsync(hq.data(), p->q, (size_t)N * 24, hipMemcpyDeviceToHost, st));
+            if (p->kappa) {
+                hk.resize(N);
+                HIPCHK(hipMemcpyAsync(hk.data(), p->kappa, (size_t)N * 8, hipMemcpyDeviceToHost, st));
+            }
+            HIPCHK(hipStreamSynchronize(st));
+            for (double v : hq)
+                if (!std::isfinite(v) || std::fabs(v) > 1e12) throw Err(BLOB_RD_EINVAL, "q contains non-finite or huge values");
+            for (double v : hk)
+                if (!std::isfinite(v) || v < 0.0) throw Err(BLOB_RD_EINVAL, "kappa must be finite and >= 0");
+            HIPCHK(hipMemcpyAsync(H->at<double>(P.off_q), p->q, (size_t)N * 24, hipMemcpyDeviceToDevice, st));
+            if (p->kappa)
+                HIPCHK(hipMemcpyAsync(H->at<double>(P.off_kappa), p->kappa, (size_t)N * 8, hipMemcpyDeviceToDevice,
+                                      st));
+            else
+                HIPCHK(hipMemsetAsync(H->at<double>(P.off_kappa), 0, (size_t)N * 8, st));
+            launch_blob_setup(st, H->at<double>(P.off_q), N, P.geom, H->at<int>(P.off_base),
+                              H->at<double>(P.off_wts), H->at<int>(P.off_tile), H->at<int>(P.off_counts));
+        }
+        launch_bin_scan(st, H->at<int>(P.off_counts), P.ntiles, H->at<int>(P.off_offsets));
+        if (N > 0) {
+            launch_bin_scatter(st, H->at<int>(P.off_tile), N, H->at<int>(P.off_offsets), H->at<int>(P.off_cursor),
+                               H->at<int>(P.off_perm));
+            launch_bin_sort(st, H->at<int>(P.off_offsets), P.ntiles, H->at<int>(P.off_perm));
+            launch_nvec_sums(st, H->at<double>(P.off_kappa), nullptr, N, H->dsc());
+            sync_read(H, H->hbuf, H->dsc(), 24);
+            H->sum_kappa = H->hbuf[0];
+            H->has_kappa = p->kappa != nullptr;
+            if (!std::isfinite(H->sum_kappa)) throw Err(BLOB_RD_EINVAL, "kappa contains non-finite values");
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        select_cinv(H, 0.0);
+    } catch (const Err& e) {
+        g_last_error = e.what();
+        blob_rd_destroy(H);
+        return e.code;
+    }
+    *out = H;
+    return BLOB_RD_OK;
+}
+
+int blob_rd_destroy(blob_rd_t H) {
+    if (!H) return BLOB_RD_OK;
+    if (H->hsc) (void)hipHostFree(H->hsc);
+    if (H->hgs) (void)hipHostFree(H->hgs);
+    if (H->hbuf) (void)hipHostFree(H->hbuf);
+    delete H;
+    return BLOB_RD_OK;
+}
+
+const char* blob_rd_last_error(blob_rd_t H) {
+    (void)H;
+    return g_last_error.c_str();
+}
+
+int blob_rd_solve_reactive(blob_rd_t H, double alpha, const double* f, double* c, blob_rd_stats* stt) {
+    if (!H || !f || !c) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return g_last_error = "alpha must be >= 0", BLOB_RD_EINVAL;
+    if (alpha == 0.0 && !(H->sum_kappa > 0.0))
+        return g_last_error = "steady reactive system with zero total rate is singular", BLOB_RD_ESINGULAR;
+    return guarded(H, stt, [&]() {
+        int rc = H->P.esz == 4 ? reactive_solve<float>(H, alpha, f, c, stt) : reactive_solve<double>(H, alpha, f, c, stt);
+        HIPCHK(hipGetLastError());
+        return rc;
+    });
+}
+
+int blob_rd_step(blob_rd_t H, double dt, const double* f, double* c, blob_rd_stats* stt) {
+    if (!H || !f || !c) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return g_last_error = "dt must be positive", BLOB_RD_EINVAL;
+    return guarded(H, stt, [&]() {
+        double* g = H->grid(G_G);
+        hipLaunchKernelGGL(k_step_rhs, dim3(nblocks(H->P.ncell)), dim3(kBlock), 0, H->st, f, c, g,
+                           (unsigned)H->P.ncell, 1.0 / dt);
+        H->alg_bytes += (double)H->P.ncell * 24;
+        int rc = H->P.esz == 4 ? reactive_solve<float>(H, 1.0 / dt, g, c, stt)
+                               : reactive_solve<double>(H, 1.0 / dt, g, c, stt);
+        HIPCHK(hipGetLastError());
+        return rc;
+    });
+}
+
+int blob_rd_solve_absorbing(blob_rd_t H, double alpha, const double* f, double* c, double* lambda,
+                            blob_rd_stats* stt) {
+    if (!H || !f || !c || !lambda) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (H->P.N <= 0) return g_last_error = "absorbing solve needs at least one blob", BLOB_RD_EINVAL;
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return g_last_error = "alpha must be >= 0", BLOB_RD_EINVAL;
+    return guarded(H, stt, [&]() {
+        int rc = H->P.esz == 4 ? absorbing_solve<float>(H, alpha, f, c, lambda, stt)
+                               : absorbing_solve<double>(H, alpha, f, c, lambda, stt);
+        HIPCHK(hipGetLastError());
+        return rc;
+    });
+}
+
+int blob_rd_interp(blob_rd_t H, const double* c, double* out) {
+    if (!H || !c || !out) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    return guarded(H, nullptr, [&]() {
+        const Plan& P = H->P;
+        launch_interp(H->st, c, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
+                      H->at<int>(P.off_perm), nullptr, nullptr, out, nullptr);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(H->st));
+        return BLOB_RD_OK;
+    });
+}
+
+int blob_rd_spread(blob_rd_t H, const double* lambda, double* out) {
+    if (!H || !out || (!lambda && H->P.N > 0)) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    return guarded(H, nullptr, [&]() {
+        const Plan& P = H->P;
+        launch_spread(H->st, lambda, 0.0, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
+                      H->at<int>(P.off_offsets), H->at<int>(P.off_perm), nullptr, out, H->inv_h3(), 0, nullptr);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(H->st));
+        return BLOB_RD_OK;
+    });
+}
+
+int blob_rd_apply(blob_rd_t H, double alpha, int with_blobs, const double* x, double* y) {
+    if (!H || !x || !y) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (x == y) return g_last_error = "x and y must not alias", BLOB_RD_EINVAL;
+    return guarded(H, nullptr, [&]() {
+        const Plan& P = H->P;
+        const LevelDims& d = P.lev[0];
+        launch_applyA_plain(H->st, x, y, alpha, H->prm.D / (d.h * d.h), d.nx, d.ny, d.nz);
+        if (with_blobs && P.N > 0 && H->has_kappa) blob_term(H, x, y, nullptr);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(H->st));
+        return BLOB_RD_OK;
+    });
+}
+
+int blob_rd_vcycle(blob_rd_t H, double alpha, const double* r, double* z) {
+    if (!H || !r || !z) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (!(alpha >= 0.0)) return g_last_error = "alpha must be >= 0", BLOB_RD_EINVAL;
+    return guarded(H, nullptr, [&]() {
+        const Plan& P = H->P;
+        const LevelDims& d = P.lev[0];
+        const double* cinv = select_cinv(H, alpha);
+        if (P.esz == 4) {
+            vcycle<float>(H, alpha, r, nullptr, cinv);
+            launch_split_to_nat<float>(H->st, H->at<float>(P.off_lvl[0][0]), H->at<float>(P.off_lvl[0][1]), z, d.nx,
+                                       d.ny, d.nz, 0.0);
+        } else {
+            vcycle<double>(H, alpha, r, nullptr, cinv);
+            launch_split_to_nat<double>(H->st, H->at<double>(P.off_lvl[0][0]), H->at<double>(P.off_lvl[0][1]), z,
+                                        d.nx, d.ny, d.nz, 0.0);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(H->st));
+        return BLOB_RD_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,448 @@
+// Blob kernels: placement and binning, local averaging J, spreading S, and
+// the N-vector kernels of the Schur-complement GMRES.
+//
+// arXiv:1306.3159 Sec. III.A: (J c)_i = sum_k phi_w(q_i - r_k) c_k with the
+// tensor-product kernel of eq. tensor_product, and S = h^-3 J^T. The kernels
+// are Peskin's four-point function and the three-point function of Roma,
+// Peskin and Berger (the paper states their moment conditions, eq.
+// JS_invariance, and cites these forms).
+//
+// Spreading is a gather: one work-group per grid tile collects the blobs
+// binned in its own and neighbouring tiles, stages their weights in LDS and
+// lets each thread sum the contributions to the cells it owns, in a fixed
+// order. No atomics touch floating-point data, so results are bitwise
+// reproducible.
+#include "launch.hpp"
+
+#include <cmath>
+
+namespace brd {
+
+__device__ __forceinline__ double kern4(double r) {
+    const double a = fabs(r);
+    if (a <= 1.0) return (3.0 - 2.0 * a + sqrt(fmax(1.0 + 4.0 * a * (1.0 - a), 0.0))) * 0.125;
+    if (a < 2.0) return (5.0 - 2.0 * a - sqrt(fmax(-7.0 + a * (12.0 - 4.0 * a), 0.0))) * 0.125;
+    return 0.0;
+}
+
+__device__ __forceinline__ double kern3(double r) {
+    const double a = fabs(r);
+    if (a <= 0.5) return (1.0 + sqrt(fmax(1.0 - 3.0 * a * a, 0.0))) * (1.0 / 3.0);
+    if (a < 1.5) {
+        const double b = 1.0 - a;
+        return (5.0 - 3.0 * a - sqrt(fmax(1.0 - 3.0 * b * b, 0.0))) * (1.0 / 6.0);
+    }
+    return 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Placement: wrap q into the box, first support cell k0 (w = 4: floor(s) - 1,
+// w = 3: nearest cell - 1, with s = q/h - 1/2), the w weights per axis
+// (zero-padded to 4) and the tile of the bin cell k0 + 1.
+__global__ void k_blob_setup(const double* __restrict__ q, int N, BlobGeom g, int* __restrict__ base,
+                             double* __restrict__ wts, int* __restrict__ tile_of, int* __restrict__ counts) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const int te[3] = {g.tx, g.ty, g.tz};
+    int tc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double Lb = n[a] * g.h;
+        double qa = q[3 * i + a];
+        qa -= Lb * floor(qa / Lb);
+        if (qa >= Lb) qa -= Lb;
+        const double s = qa / g.h - 0.5;
+        const int k0 = (g.w == 4) ? (int)floor(s) - 1 : (int)floor(s + 0.5) - 1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double d = s - (double)(k0 + j);
+            wts[(3 * i + a) * 4 + j] = (j < g.w) ? (g.w == 4 ? kern4(d) : kern3(d)) : 0.0;
+        }
+        const int kb = ((k0 % n[a]) + n[a]) % n[a];
+        base[3 * i + a] = kb;
+        const int bin = kb + 1 == n[a] ? 0 : kb + 1;
+        tc[a] = bin / te[a];
+    }
+    const int t = (tc[2] * g.nty + tc[1]) * g.ntx + tc[0];
+    tile_of[i] = t;
+    atomicAdd(&counts[t], 1);
+}
+
+void launch_blob_setup(hipStream_t st, const double* q, int N, BlobGeom g, int* base, double* wts, int* tile_of,
+                       int* counts) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_blob_setup, dim3(nblocks(N)), dim3(kBlock), 0, st, q, N, g, base, wts, tile_of, counts);
+}
+
+// Exclusive scan of bin counts, one work-group, contiguous chunk per thread.
+__global__ void __launch_bounds__(kFinBlock) k_bin_scan(const int* __restrict__ counts, int nt, int* offsets) {
+    __shared__ int sh[kFinBlock];
+    const int per = (nt + blockDim.x - 1) / blockDim.x;
+    const int lo = threadIdx.x * per, hi = min(lo + per, nt);
+    int s = 0;
+    for (int i = lo; i < hi; ++i) s += counts[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int t = 0; t < (int)blockDim.x; ++t) {
+            const int v = sh[t];
+            sh[t] = run;
+            run += v;
+        }
+        offsets[nt] = run;
+    }
+    __syncthreads();
+    int run = sh[threadIdx.x];
+    for (int i = lo; i < hi; ++i) {
+        offsets[i] = run;
+        run += counts[i];
+    }
+}
+
+void launch_bin_scan(hipStream_t st, const int* counts, int ntiles, int* offsets) {
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(kFinBlock), 0, st, counts, ntiles, offsets);
+}
+
+__global__ void k_bin_scatter(const int* __restrict__ tile_of, int N, const int* __restrict__ offsets, int* cursor,
+                              int* perm) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int t = tile_of[i];
+    perm[offsets[t] + atomicAdd(&cursor[t], 1)] = i;
+}
+
+void launch_bin_scatter(hipStream_t st, const int* tile_of, int N, const int* offsets, int* cursor, int* perm) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_bin_scatter, dim3(nblocks(N)), dim3(kBlock), 0, st, tile_of, N, offsets, cursor, perm);
+}
+
+// Within each bin, order blobs by index so that every later sum is in a fixed order.
+__global__ void k_bin_sort(const int* __restrict__ offsets, int nt, int* perm) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const int lo = offsets[t], hi = offsets[t + 1];
+    for (int a = lo + 1; a < hi; ++a) {
+        const int v = perm[a];
+        int b = a - 1;
+        while (b >= lo && perm[b] > v) {
+            perm[b + 1] = perm[b];
+            --b;
+        }
+        perm[b + 1] = v;
+    }
+}
+
+void launch_bin_sort(hipStream_t st, const int* offsets, int ntiles, int* perm) {
+    hipLaunchKernelGGL(k_bin_sort, dim3(nblocks(ntiles)), dim3(kBlock), 0, st, offsets, ntiles, perm);
+}
+
+// ---------------------------------------------------------------------------
+// Local averaging: one wave64 per blob, lane l <-> support cell
+// (l & 3, (l >> 2) & 3, l >> 4); a wave reduction sums the 64 products.
+// Blobs are visited in tile order so neighbouring waves share cache lines.
+__global__ void __launch_bounds__(kBlock) k_interp(const double* __restrict__ x, int N, BlobGeom g,
+                                                   const int* __restrict__ base, const double* __restrict__ wts,
+                                                   const int* __restrict__ perm, double* __restrict__ jx,
+                                                   const double* __restrict__ kappa, double* __restrict__ out,
+                                                   const Scalars* sc) {
+    if (sc && sc->done) return;
+    const int wv = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (wv >= N) return;
+    const int i = perm[wv];
+    const int l = threadIdx.x & 63;
+    const int a = l & 3, b = (l >> 2) & 3, c = l >> 4;
+    int cx = base[3 * i] + a, cy = base[3 * i + 1] + b, cz = base[3 * i + 2] + c;
+    cx = cx >= g.nx ? cx - g.nx : cx;
+    cy = cy >= g.ny ? cy - g.ny : cy;
+    cz = cz >= g.nz ? cz - g.nz : cz;
+    const double* w = wts + (size_t)i * 12;
+    const double wgt = w[a] * w[4 + b] * w[8 + c];
+    double v = wgt * x[((size_t)cz * g.ny + cy) * g.nx + cx];
+    v = wave_sum(v);
+    if (l == 0) {
+        if (jx) jx[i] = v;
+        if (out) out[i] = kappa ? kappa[i] * v : v;
+    }
+}
+
+void launch_interp(hipStream_t st, const double* x, int N, BlobGeom g, const int* base, const double* wts,
+                   const int* perm, double* jx, const double* kappa, double* out, const Scalars* sc) {
+    if (N <= 0) return;
+    const int per = kBlock / 64;
+    hipLaunchKernelGGL(k_interp, dim3((N + per - 1) / per), dim3(kBlock), 0, st, x, N, g, base, wts, perm, jx, kappa,
+                       out, sc);
+}
+
+// ---------------------------------------------------------------------------
+// Spreading as a tile gather.
+struct Staged {
+    int bx, by, bz, pad;
+    double w[12];
+    double lam;
+};
+
+__global__ void __launch_bounds__(kBlock) k_spread(const double* __restrict__ lam, double lam_shift, BlobGeom g,
+                                                   const int* __restrict__ base, const double* __restrict__ wts,
+                                                   const int* __restrict__ offsets, const int* __restrict__ perm,
+                                                   const double* base_in, double* out, double scale, int add_only,
+                                                   const Scalars* sc) {
+    if (sc && sc->done) return;
+    __shared__ Staged stg[kStageBlobs];
+    __shared__ int rng_lo[27], rng_len[27], rng_pre[28];
+    __shared__ int nrng;
+    const int t = xcd_block(blockIdx.x, gridDim.x);
+    const int tix = t % g.ntx, tiy = (t / g.ntx) % g.nty, tiz = t / (g.ntx * g.nty);
+    if (threadIdx.x == 0) {
+        int lx[3], ly[3], lz[3], nxl = 0, nyl = 0, nzl = 0;
+        for (int d = -1; d <= 1; ++d) {
+            const int vx = (tix + d + g.ntx) % g.ntx, vy = (tiy + d + g.nty) % g.nty, vz = (tiz + d + g.ntz) % g.ntz;
+            bool dup = false;
+            for (int k = 0; k < nxl; ++k) dup |= lx[k] == vx;
+            if (!dup) lx[nxl++] = vx;
+            dup = false;
+            for (int k = 0; k < nyl; ++k) dup |= ly[k] == vy;
+            if (!dup) ly[nyl++] = vy;
+            dup = false;
+            for (int k = 0; k < nzl; ++k) dup |= lz[k] == vz;
+            if (!dup) lz[nzl++] = vz;
+        }
+        int nr = 0, pre = 0;
+        for (int c = 0; c < nzl; ++c)
+            for (int b = 0; b < nyl; ++b)
+                for (int a = 0; a < nxl; ++a) {
+                    const int nt = (lz[c] * g.nty + ly[b]) * g.ntx + lx[a];
+                    const int lo = offsets[nt], len = offsets[nt + 1] - lo;
+                    if (len > 0) {
+                        rng_lo[nr] = lo;
+                        rng_len[nr] = len;
+                        rng_pre[nr] = pre;
+                        pre += len;
+                        ++nr;
+                    }
+                }
+        rng_pre[nr] = pre;
+        nrng = nr;
+    }
+    __syncthreads();
+    const int nr = nrng;
+    const int K = rng_pre[nr];
+    const int tcells = g.tx * g.ty * g.tz;
+    if (K == 0 && add_only) return;
+
+    double acc[2] = {0.0, 0.0};
+    int cell[2][3];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int lc = threadIdx.x + e * blockDim.x;
+        const int lx = lc % g.tx, ly = (lc / g.tx) % g.ty, lz = lc / (g.tx * g.ty);
+        cell[e][0] = tix * g.tx + lx;
+        cell[e][1] = tiy * g.ty + ly;
+        cell[e][2] = tiz * g.tz + lz;
+    }
+    for (int c0 = 0; c0 < K; c0 += kStageBlobs) {
+        const int cn = min(kStageBlobs, K - c0);
+        __syncthreads();
+        if ((int)threadIdx.x < cn) {
+            const int k = c0 + threadIdx.x;
+            int r = 0;
+            while (rng_pre[r + 1] <= k) ++r;
+            const int i = perm[rng_lo[r] + (k - rng_pre[r])];
+            Staged s;
+            s.bx = base[3 * i];
+            s.by = base[3 * i + 1];
+            s.bz = base[3 * i + 2];
+            s.pad = 0;
+#pragma unroll
+            for (int j = 0; j < 12; ++j) s.w[j] = wts[(size_t)i * 12 + j];
+            s.lam = (lam ? lam[i] : 0.0) + lam_shift;
+            stg[threadIdx.x] = s;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int lc = threadIdx.x + e * blockDim.x;
+            if (lc >= tcells) continue;
+            double a_ = acc[e];
+            for (int j = 0; j < cn; ++j) {
+                int a = cell[e][0] - stg[j].bx;
+                int b = cell[e][1] - stg[j].by;
+                int c = cell[e][2] - stg[j].bz;
+                a += a < 0 ? g.nx : 0;
+                b += b < 0 ? g.ny : 0;
+                c += c < 0 ? g.nz : 0;
+                if (a < 4 && b < 4 && c < 4) a_ += stg[j].w[a] * stg[j].w[4 + b] * stg[j].w[8 + c] * stg[j].lam;
+            }
+            acc[e] = a_;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int lc = threadIdx.x + e * blockDim.x;
+        if (lc >= tcells) continue;
+        const size_t idx = ((size_t)cell[e][2] * g.ny + cell[e][1]) * g.nx + cell[e][0];
+        const double b = base_in ? base_in[idx] : 0.0;
+        out[idx] = b + scale * acc[e];
+    }
+}
+
+void launch_spread(hipStream_t st, const double* lam, double lam_shift, int N, BlobGeom g, const int* base,
+                   const double* wts, const int* offsets, const int* perm, const double* base_in, double* out,
+                   double scale, int add_only, const Scalars* sc) {
+    const unsigned nt = (unsigned)g.ntx * g.nty * g.ntz;
+    hipLaunchKernelGGL(k_spread, dim3(nt), dim3(kBlock), 0, st, lam, lam_shift, g, base, wts, offsets, perm, base_in,
+                       out, scale, add_only, sc);
+}
+
+// ---------------------------------------------------------------------------
+// N-vector kernels: one work-group of kFinBlock threads, fixed reduction order.
+__device__ __forceinline__ double wg_sum(double s) {
+    __shared__ double sh[kFinBlock / 64];
+    s = wave_sum(s);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+    __syncthreads();
+    return t;
+}
+
+__global__ void __launch_bounds__(kFinBlock) k_nvec_project(double* v, int N) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) s += v[i];
+    const double m = wg_sum(s) / (double)N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) v[i] -= m;
+}
+
+void launch_nvec_project(hipStream_t st, double* v, int N) {
+    hipLaunchKernelGGL(k_nvec_project, dim3(1), dim3(kFinBlock), 0, st, v, N);
+}
+
+__global__ void k_nvec_copy_scale(const double* x, double* y, int N, double a, double shift) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) y[i] = (x ? a * x[i] : 0.0) + shift;
+}
+
+void launch_nvec_copy_scale(hipStream_t st, const double* x, double* y, int N, double a, double shift) {
+    hipLaunchKernelGGL(k_nvec_copy_scale, dim3(nblocks(N)), dim3(kBlock), 0, st, x, y, N, a, shift);
+}
+
+__global__ void __launch_bounds__(kFinBlock) k_nvec_sums(const double* a, const double* b, int N, double* out) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        s0 += a[i];
+        s1 += a[i] * a[i];
+        if (b) s2 += a[i] * b[i];
+    }
+    s0 = wg_sum(s0);
+    s1 = wg_sum(s1);
+    s2 = wg_sum(s2);
+    if (threadIdx.x == 0) {
+        out[0] = s0;
+        out[1] = s1;
+        out[2] = s2;
+    }
+}
+
+void launch_nvec_sums(hipStream_t st, const double* a, const double* b, int N, double* out) {
+    hipLaunchKernelGGL(k_nvec_sums, dim3(1), dim3(kFinBlock), 0, st, a, b, N, out);
+}
+
+// GMRES cycle start: r = b - w (or b), beta = |r|, V_0 = r / beta, g = beta e_1.
+__global__ void __launch_bounds__(kFinBlock) k_gmres_start(const double* b, const double* w, int has_w, double* V,
+                                                           double* gvec, int N, GmresScalars* gs) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const double r = has_w ? b[i] - w[i] : b[i];
+        V[i] = r;
+        s += r * r;
+    }
+    const double beta = sqrt(wg_sum(s));
+    const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) V[i] *= inv;
+    if (threadIdx.x == 0) {
+        gvec[0] = beta;
+        gs->beta = beta;
+        gs->res = beta;
+        gs->k = 0;
+        gs->status = (beta == beta) ? 0 : 1;
+    }
+}
+
+void launch_gmres_start(hipStream_t st, const double* b, const double* w, int has_w, double* V, double* g, int N,
+                        GmresScalars* gs) {
+    hipLaunchKernelGGL(k_gmres_start, dim3(1), dim3(kFinBlock), 0, st, b, w, has_w, V, g, N, gs);
+}
+
+// Arnoldi step k with modified Gram-Schmidt: V_{k+1} holds G v_k on entry.
+// H is (m+1) x m row-major; Givens rotations (cs, sn) update g.
+__global__ void __launch_bounds__(kFinBlock) k_gmres_arnoldi(double* V, double* H, double* cs, double* sn,
+                                                             double* gvec, int N, int k, int m, GmresScalars* gs) {
+    double* w = V + (size_t)(k + 1) * N;
+    for (int j = 0; j <= k; ++j) {
+        const double* vj = V + (size_t)j * N;
+        double s = 0.0;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) s += w[i] * vj[i];
+        const double hj = wg_sum(s);
+        for (int i = threadIdx.x; i < N; i += blockDim.x) w[i] -= hj * vj[i];
+        if (threadIdx.x == 0) H[j * m + k] = hj;
+    }
+    double s = 0.0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) s += w[i] * w[i];
+    const double hk1 = sqrt(wg_sum(s));
+    const double inv = hk1 > 0.0 ? 1.0 / hk1 : 0.0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) w[i] *= inv;
+    if (threadIdx.x == 0) {
+        H[(k + 1) * m + k] = hk1;
+        for (int j = 0; j < k; ++j) {
+            const double a = H[j * m + k], b = H[(j + 1) * m + k];
+            H[j * m + k] = cs[j] * a + sn[j] * b;
+            H[(j + 1) * m + k] = -sn[j] * a + cs[j] * b;
+        }
+        const double a = H[k * m + k], b = H[(k + 1) * m + k];
+        const double den = sqrt(a * a + b * b);
+        cs[k] = den == 0.0 ? 1.0 : a / den;
+        sn[k] = den == 0.0 ? 0.0 : b / den;
+        H[k * m + k] = den;
+        H[(k + 1) * m + k] = 0.0;
+        gvec[k + 1] = -sn[k] * gvec[k];
+        gvec[k] = cs[k] * gvec[k];
+        gs->res = fabs(gvec[k + 1]);
+        gs->hk1 = hk1;
+        gs->k = k + 1;
+        if (!(den == den) || !(hk1 == hk1)) gs->status = 1;
+    }
+}
+
+void launch_gmres_arnoldi(hipStream_t st, double* V, double* H, double* cs, double* sn, double* g, int N, int k,
+                          int m, GmresScalars* gs) {
+    hipLaunchKernelGGL(k_gmres_arnoldi, dim3(1), dim3(kFinBlock), 0, st, V, H, cs, sn, g, N, k, m, gs);
+}
+
+// x += V y with H y = g (upper-triangular k x k), y solved by thread 0.
+__global__ void __launch_bounds__(kFinBlock) k_gmres_update(const double* V, const double* H, const double* gvec,
+                                                            double* y, double* x, int N, int k, int m) {
+    if (threadIdx.x == 0) {
+        for (int i = k - 1; i >= 0; --i) {
+            double s = gvec[i];
+            for (int j = i + 1; j < k; ++j) s -= H[i * m + j] * y[j];
+            const double d = H[i * m + i];
+            y[i] = d != 0.0 ? s / d : 0.0;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        double acc = x[i];
+        for (int j = 0; j < k; ++j) acc += y[j] * V[(size_t)j * N + i];
+        x[i] = acc;
+    }
+}
+
+void launch_gmres_update(hipStream_t st, const double* V, const double* H, const double* g, double* y, double* x,
+                         int N, int k, int m) {
+    hipLaunchKernelGGL(k_gmres_update, dim3(1), dim3(kFinBlock), 0, st, V, H, g, y, x, N, k, m);
+}
+
+}  // namespace brd

@@ -1,0 +1,394 @@
+// Natural-layout FP64 grid kernels and the one-work-group finalize kernels.
+//
+// Operators (arXiv:1306.3159 Sec. III.A-III.B): A = alpha I - D L with L the
+// periodic 7-point Laplacian; the CG vector updates of the multigrid-
+// preconditioned Krylov solves of Sec. III.E.
+#include "launch.hpp"
+
+#include <cmath>
+
+namespace brd {
+
+// y = alpha x - s (sum of 6 neighbours - 6 x), s = D / h^2
+__device__ __forceinline__ double stencil_A(const double* __restrict__ x, int X, int Y, int Z, int nx, int ny, int nz,
+                                            double alpha, double s, size_t idx, double* center) {
+    const long long sxy = (long long)nx * ny;
+    const long long i = (long long)idx;
+    const double c = x[i];
+    const double xm = x[i - X + wrapi(X - 1, nx)];
+    const double xp = x[i - X + wrapi(X + 1, nx)];
+    const double ym = x[i + (long long)(wrapi(Y - 1, ny) - Y) * nx];
+    const double yp = x[i + (long long)(wrapi(Y + 1, ny) - Y) * nx];
+    const double zm = x[i + (long long)(wrapi(Z - 1, nz) - Z) * sxy];
+    const double zp = x[i + (long long)(wrapi(Z + 1, nz) - Z) * sxy];
+    *center = c;
+    return alpha * c - s * ((xm + xp) + (ym + yp) + (zm + zp) - 6.0 * c);
+}
+
+__global__ void __launch_bounds__(kBlock) k_applyA(const double* __restrict__ p, double* __restrict__ q,
+                                                   double alpha, double s, int nx, int ny, int nz, unsigned ncell,
+                                                   double* part, const Scalars* sc) {
+    if (sc && sc->done) return;
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const unsigned idx = b * blockDim.x + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (idx < ncell) {
+        const int X = idx % nx;
+        const unsigned t = idx / nx;
+        const int Y = t % ny, Z = t / ny;
+        double c;
+        const double y = stencil_A(p, X, Y, Z, nx, ny, nz, alpha, s, idx, &c);
+        q[idx] = y;
+        v[0] = c * y;
+        v[1] = y;
+    }
+    if (part) block_partials<2>(v, part, gridDim.x, blockIdx.x);
+}
+
+void launch_applyA(hipStream_t st, const double* p, double* q, double alpha, double s, int nx, int ny, int nz,
+                   double* part, const Scalars* sc, unsigned* np) {
+    const unsigned n = (unsigned)nx * ny * nz;
+    const unsigned nb = nblocks(n);
+    hipLaunchKernelGGL(k_applyA, dim3(nb), dim3(kBlock), 0, st, p, q, alpha, s, nx, ny, nz, n, part, sc);
+    if (np) *np = nb;
+}
+
+void launch_applyA_plain(hipStream_t st, const double* x, double* y, double alpha, double s, int nx, int ny,
+                         int nz) {
+    const unsigned n = (unsigned)nx * ny * nz;
+    hipLaunchKernelGGL(k_applyA, dim3(nblocks(n)), dim3(kBlock), 0, st, x, y, alpha, s, nx, ny, nz, n,
+                       (double*)nullptr, (const Scalars*)nullptr);
+}
+
+// r = g - (alpha x - D L x) or, with x == nullptr, r = g - q0 (q0 may be null: r = g).
+__global__ void __launch_bounds__(kBlock) k_residual64(const double* __restrict__ g, const double* __restrict__ x,
+                                                       const double* __restrict__ q0, double* __restrict__ r,
+                                                       double alpha, double s, int nx, int ny, int nz,
+                                                       unsigned ncell, double* part) {
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const unsigned idx = b * blockDim.x + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (idx < ncell) {
+        double ax = 0.0;
+        if (x) {
+            const int X = idx % nx;
+            const unsigned t = idx / nx;
+            double c;
+            ax = stencil_A(x, X, (int)(t % ny), (int)(t / ny), nx, ny, nz, alpha, s, idx, &c);
+        } else if (q0) {
+            ax = q0[idx];
+        }
+        const double gv = g[idx];
+        const double rv = gv - ax;
+        r[idx] = rv;
+        v[0] = rv * rv;
+        v[1] = rv;
+        v[2] = gv * gv;
+    }
+    block_partials<3>(v, part, gridDim.x, blockIdx.x);
+}
+
+void launch_residual64(hipStream_t st, const double* g, const double* x, double* r, double alpha, double s, int nx,
+                       int ny, int nz, double* part, unsigned* np) {
+    const unsigned n = (unsigned)nx * ny * nz;
+    const unsigned nb = nblocks(n);
+    hipLaunchKernelGGL(k_residual64, dim3(nb), dim3(kBlock), 0, st, g, x, (const double*)nullptr, r, alpha, s, nx,
+                       ny, nz, n, part);
+    *np = nb;
+}
+
+void launch_residual_from_q(hipStream_t st, const double* g, const double* q0, double* r, size_t n, double* part,
+                            unsigned* np) {
+    const unsigned nb = nblocks(n);
+    hipLaunchKernelGGL(k_residual64, dim3(nb), dim3(kBlock), 0, st, g, (const double*)nullptr, q0, r, 0.0, 0.0, 1,
+                       1, 1, (unsigned)n, part);
+    *np = nb;
+}
+
+// Split-layout value at natural (X, Y, Z) of level 0.
+template <typename T>
+__device__ __forceinline__ double split_at(const T* __restrict__ z0, const T* __restrict__ z1, int X, int Y, int Z,
+                                           int hx, int ny) {
+    const size_t j = ((size_t)Z * ny + Y) * hx + (X >> 1);
+    return ((X + Y + Z) & 1) ? (double)z1[j] : (double)z0[j];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dir(const T* __restrict__ z0, const T* __restrict__ z1,
+                                                double* __restrict__ p, int nx, int ny, unsigned ncell,
+                                                const Scalars* sc) {
+    if (sc->done) return;
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const unsigned idx = b * blockDim.x + threadIdx.x;
+    if (idx >= ncell) return;
+    const double beta = sc->beta, shift = sc->shift;
+    const int X = idx % nx;
+    const unsigned t = idx / nx;
+    const int Y = t % ny, Z = t / ny;
+    const double zv = split_at(z0, z1, X, Y, Z, nx >> 1, ny) + shift;
+    p[idx] = beta == 0.0 ? zv : zv + beta * p[idx];
+}
+
+template <typename T>
+void launch_dir(hipStream_t st, const T* z0, const T* z1, double* p, int nx, int ny, int nz, const Scalars* sc) {
+    const unsigned n = (unsigned)nx * ny * nz;
+    hipLaunchKernelGGL(k_dir<T>, dim3(nblocks(n)), dim3(kBlock), 0, st, z0, z1, p, nx, ny, n, sc);
+}
+template void launch_dir<float>(hipStream_t, const float*, const float*, double*, int, int, int, const Scalars*);
+template void launch_dir<double>(hipStream_t, const double*, const double*, double*, int, int, int, const Scalars*);
+
+__global__ void __launch_bounds__(kBlock) k_update(double* __restrict__ x, double* __restrict__ r,
+                                                   const double* __restrict__ p, const double* __restrict__ q,
+                                                   unsigned n, double* part, const Scalars* sc) {
+    if (sc->done) return;
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const unsigned idx = b * blockDim.x + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (idx < n) {
+        const double a = sc->alpha;
+        x[idx] += a * p[idx];
+        const double rv = r[idx] - a * q[idx];
+        r[idx] = rv;
+        v[0] = rv * rv;
+        v[1] = rv;
+    }
+    block_partials<2>(v, part, gridDim.x, blockIdx.x);
+}
+
+void launch_update(hipStream_t st, double* x, double* r, const double* p, const double* q, size_t n, double* part,
+                   const Scalars* sc, unsigned* np) {
+    const unsigned nb = nblocks(n);
+    hipLaunchKernelGGL(k_update, dim3(nb), dim3(kBlock), 0, st, x, r, p, q, (unsigned)n, part, sc);
+    *np = nb;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_zdots(const T* __restrict__ z0, const T* __restrict__ z1,
+                                                  const double* __restrict__ r, const double* __restrict__ q, int nx,
+                                                  int ny, unsigned ncell, double* part, const Scalars* sc) {
+    if (sc->done) return;
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const unsigned idx = b * blockDim.x + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (idx < ncell) {
+        const int X = idx % nx;
+        const unsigned t = idx / nx;
+        const double zv = split_at(z0, z1, X, (int)(t % ny), (int)(t / ny), nx >> 1, ny);
+        v[0] = zv;
+        v[1] = zv * r[idx];
+        v[2] = zv * q[idx];
+    }
+    block_partials<3>(v, part, gridDim.x, blockIdx.x);
+}
+
+template <typename T>
+void launch_zdots(hipStream_t st, const T* z0, const T* z1, const double* r, const double* q, int nx, int ny, int nz,
+                  double* part, const Scalars* sc, unsigned* np) {
+    const unsigned n = (unsigned)nx * ny * nz;
+    const unsigned nb = nblocks(n);
+    hipLaunchKernelGGL(k_zdots<T>, dim3(nb), dim3(kBlock), 0, st, z0, z1, r, q, nx, ny, n, part, sc);
+    *np = nb;
+}
+template void launch_zdots<float>(hipStream_t, const float*, const float*, const double*, const double*, int, int,
+                                  int, double*, const Scalars*, unsigned*);
+template void launch_zdots<double>(hipStream_t, const double*, const double*, const double*, const double*, int, int,
+                                   int, double*, const Scalars*, unsigned*);
+
+// out = scale * out + z   (z split -> natural)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_split_to_nat(const T* __restrict__ z0, const T* __restrict__ z1,
+                                                         double* __restrict__ out, int nx, int ny, unsigned ncell,
+                                                         double scale) {
+    const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ncell) return;
+    const int X = idx % nx;
+    const unsigned t = idx / nx;
+    const double zv = split_at(z0, z1, X, (int)(t % ny), (int)(t / ny), nx >> 1, ny);
+    out[idx] = scale == 0.0 ? zv : scale * out[idx] + zv;
+}
+
+template <typename T>
+void launch_split_to_nat(hipStream_t st, const T* z0, const T* z1, double* out, int nx, int ny, int nz,
+                         double scale) {
+    const unsigned n = (unsigned)nx * ny * nz;
+    hipLaunchKernelGGL(k_split_to_nat<T>, dim3(nblocks(n)), dim3(kBlock), 0, st, z0, z1, out, nx, ny, n, scale);
+}
+template void launch_split_to_nat<float>(hipStream_t, const float*, const float*, double*, int, int, int, double);
+template void launch_split_to_nat<double>(hipStream_t, const double*, const double*, double*, int, int, int, double);
+
+__global__ void __launch_bounds__(kBlock) k_norm_partials(const double* __restrict__ v, unsigned n, double* part) {
+    const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+    double a[2] = {0.0, 0.0};
+    if (idx < n) {
+        a[0] = v[idx];
+        a[1] = v[idx] * v[idx];
+    }
+    block_partials<2>(a, part, gridDim.x, blockIdx.x);
+}
+
+void launch_norm_partials(hipStream_t st, const double* v, size_t n, double* part, unsigned* np) {
+    const unsigned nb = nblocks(n);
+    hipLaunchKernelGGL(k_norm_partials, dim3(nb), dim3(kBlock), 0, st, v, (unsigned)n, part);
+    *np = nb;
+}
+
+__global__ void k_fill(double* v, unsigned n, double value) {
+    const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) v[idx] = value;
+}
+void launch_fill(hipStream_t st, double* v, size_t n, double value) {
+    hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(kBlock), 0, st, v, (unsigned)n, value);
+}
+
+__global__ void k_axpby(double* y, const double* x, unsigned n, double a, double b) {
+    const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) y[idx] = (a == 0.0 ? 0.0 : a * y[idx]) + b * x[idx];
+}
+void launch_axpby(hipStream_t st, double* y, const double* x, size_t n, double a, double b) {
+    hipLaunchKernelGGL(k_axpby, dim3(nblocks(n)), dim3(kBlock), 0, st, y, x, (unsigned)n, a, b);
+}
+
+__global__ void k_add_shift(double* v, unsigned n, const double* shift, double sign) {
+    const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) v[idx] += sign * shift[0];
+}
+void launch_add_shift(hipStream_t st, double* v, size_t n, const double* shift_dev, double sign) {
+    hipLaunchKernelGGL(k_add_shift, dim3(nblocks(n)), dim3(kBlock), 0, st, v, (unsigned)n, shift_dev, sign);
+}
+
+// ---------------------------------------------------------------------------
+// Finalize: one work-group of kFinBlock threads reduces block partials in a
+// fixed order and advances the CG scalars.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double fin_sum(const double* __restrict__ p, unsigned n) {
+    __shared__ double sh[kFinBlock / 64];
+    double s = 0.0;
+    for (unsigned i = threadIdx.x; i < n; i += blockDim.x) s += p[i];
+    s = wave_sum(s);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = s;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ bool is_finite_d(double v) { return v == v && v - v == 0.0; }
+
+__global__ void __launch_bounds__(kFinBlock) k_fin(int kind, const double* __restrict__ part, unsigned np,
+                                                   Scalars* sc, const double* __restrict__ na,
+                                                   const double* __restrict__ nb, int nblob, double inv_h3) {
+    if (kind != FIN_INIT && sc->done) return;
+    if (kind == FIN_INIT) {
+        const double rr = fin_sum(part, np);
+        const double rs = fin_sum(part + np, np);
+        const double gg = fin_sum(part + 2 * (size_t)np, np);
+        if (threadIdx.x == 0) {
+            // On entry tol2 holds rtol^2 and rr0 holds an absolute floor^2.
+            const double t2 = fmax(sc->tol2 * gg, sc->rr0);
+            sc->rr = rr;
+            sc->rr0 = rr;
+            sc->rsum = rs;
+            sc->gg = gg;
+            sc->tol2 = t2;
+            sc->iters = 0;
+            sc->beta = 0.0;
+            sc->status = is_finite_d(rr) ? 0 : 1;
+            sc->done = (rr <= t2 || !is_finite_d(rr)) ? 1 : 0;
+            sc->mean_r = sc->project ? rs * sc->inv_ncell : 0.0;
+        }
+    } else if (kind == FIN_ALPHA) {
+        double pq = fin_sum(part, np);
+        double qs = fin_sum(part + np, np);
+        if (na && nb) {
+            // blob term of B: p.(S mu) = h^-3 (J p).mu, sum(S mu) = h^-3 sum(mu)
+            double a = 0.0, c = 0.0;
+            for (int i = threadIdx.x; i < nblob; i += blockDim.x) {
+                a += na[i] * nb[i];
+                c += nb[i];
+            }
+            __shared__ double sh2[2][kFinBlock / 64];
+            a = wave_sum(a);
+            c = wave_sum(c);
+            if ((threadIdx.x & 63) == 0) {
+                sh2[0][threadIdx.x >> 6] = a;
+                sh2[1][threadIdx.x >> 6] = c;
+            }
+            __syncthreads();
+            double ta = 0.0, tc = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+                ta += sh2[0][w];
+                tc += sh2[1][w];
+            }
+            pq += inv_h3 * ta;
+            qs += inv_h3 * tc;
+        }
+        if (threadIdx.x == 0) {
+            sc->pq = pq;
+            sc->qsum = qs;
+            if (!(pq > 0.0) || !is_finite_d(pq) || !is_finite_d(sc->rz)) {
+                sc->status = 1;
+                sc->done = 1;
+                sc->alpha = 0.0;
+            } else {
+                sc->alpha = sc->rz / pq;
+            }
+        }
+    } else if (kind == FIN_UPDATE) {
+        const double rr = fin_sum(part, np);
+        const double rs = fin_sum(part + np, np);
+        if (threadIdx.x == 0) {
+            sc->rr = rr;
+            sc->rsum = rs;
+            sc->iters += 1;
+            sc->mean_r = sc->project ? rs * sc->inv_ncell : 0.0;
+            if (!is_finite_d(rr)) {
+                sc->status = 1;
+                sc->done = 1;
+            } else if (rr <= sc->tol2) {
+                sc->done = 1;
+            }
+        }
+    } else {  // FIN_BETA
+        const double zs = fin_sum(part, np);
+        const double zr = fin_sum(part + np, np);
+        const double zq = fin_sum(part + 2 * (size_t)np, np);
+        if (threadIdx.x == 0) {
+            const double shift = sc->project ? (sc->rsum * sc->eBe_inv - zs * sc->inv_ncell) : 0.0;
+            const double rz_new = zr + shift * sc->rsum;
+            const double zq_full = zq + shift * sc->qsum;
+            sc->shift = shift;
+            if (sc->iters == 0) {
+                sc->beta = 0.0;
+            } else {
+                sc->beta = -sc->alpha * zq_full / sc->rz;
+            }
+            sc->rz = rz_new;
+            if (!is_finite_d(rz_new) || !is_finite_d(sc->beta)) {
+                sc->status = 1;
+                sc->done = 1;
+            }
+        }
+    }
+}
+
+void launch_fin(hipStream_t st, int kind, const double* part, unsigned np, Scalars* sc, const double* na,
+                const double* nb, int nblob, double inv_h3) {
+    hipLaunchKernelGGL(k_fin, dim3(1), dim3(kFinBlock), 0, st, kind, part, np, sc, na, nb, nblob, inv_h3);
+}
+
+__global__ void __launch_bounds__(kFinBlock) k_reduce_parts(const double* __restrict__ part, unsigned np, int k,
+                                                            double* out) {
+    for (int j = 0; j < k; ++j) {
+        const double s = fin_sum(part + (size_t)j * np, np);
+        if (threadIdx.x == 0) out[j] = s;
+    }
+}
+
+void launch_reduce_parts(hipStream_t st, const double* part, unsigned np, int k, double* out) {
+    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(kFinBlock), 0, st, part, np, k, out);
+}
+
+}  // namespace brd

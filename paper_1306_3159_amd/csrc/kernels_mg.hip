@@ -1,0 +1,272 @@
+// Geometric multigrid kernels for alpha I - D L on red/black-split levels.
+//
+// The paper uses a library multigrid whose details it does not give
+// (arXiv:1306.3159 Sec. III.E, eq. Helmholtz). This V-cycle is: V(2,2)
+// red-black Gauss-Seidel (red = (x+y+z) even; pre-smoothing red then black,
+// post-smoothing black then red, so the cycle is symmetric for CG),
+// full-weighting restriction R = P^T/8, cell-centred trilinear
+// prolongation P, rediscretised coarse operators alpha I - D L_{2h} and a
+// dense FP64 (pseudo-)inverse on the coarsest grid.
+//
+// Split layout: cell (x, y, z) of colour c = (x+y+z)&1 lives at index x/2 of
+// row (y, z) of array c. For a cell of colour c at half-index i in row
+// (y, z), x = 2i + s with s = ((y+z)&1) ^ c; its x-neighbours are the other
+// colour at half-indices i-1+s and i+s, and its y/z-neighbours are the other
+// colour at half-index i of the neighbouring rows.
+#include "launch.hpp"
+
+namespace brd {
+
+template <typename T>
+__device__ __forceinline__ T nb_sum(const T* __restrict__ uo, int i, int y, int z, int hx, int ny, int nz, int s) {
+    const size_t row = ((size_t)z * ny + y) * hx;
+    const int il = wrapi(i - 1 + s, hx), ir = wrapi(i + s, hx);
+    const int ym = wrapi(y - 1, ny), yp = wrapi(y + 1, ny), zm = wrapi(z - 1, nz), zp = wrapi(z + 1, nz);
+    const T a = uo[row + il] + uo[row + ir];
+    const T b = uo[((size_t)z * ny + ym) * hx + i] + uo[((size_t)z * ny + yp) * hx + i];
+    const T c = uo[((size_t)zm * ny + y) * hx + i] + uo[((size_t)zp * ny + y) * hx + i];
+    return (a + b) + c;
+}
+
+// ---------------------------------------------------------------------------
+// Fine-level entry: f = r - mean_r (FP64 natural -> T split) and the first red
+// half-sweep from a zero initial guess, u_red = f_red / diag.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_enter(const double* __restrict__ r, T* __restrict__ f0,
+                                                  T* __restrict__ f1, T* __restrict__ u0, int hx, int ny, int nz,
+                                                  double inv_diag, const Scalars* sc) {
+    if (sc && sc->done) return;
+    const unsigned nh = (unsigned)hx * ny * nz;
+    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= nh) return;
+    const int i = idx % hx;
+    const unsigned t = idx / hx;
+    const int y = t % ny, z = t / ny;
+    const double m = sc ? sc->mean_r : 0.0;
+    const int s0 = (y + z) & 1;                       // x offset of the red cell in this row
+    const size_t rowN = ((size_t)z * ny + y) * (2 * hx);
+    const double fr = r[rowN + 2 * i + s0] - m;
+    const double fb = r[rowN + 2 * i + (s0 ^ 1)] - m;
+    f0[idx] = (T)fr;
+    f1[idx] = (T)fb;
+    u0[idx] = (T)((T)fr * (T)inv_diag);
+}
+
+template <typename T>
+void launch_enter(hipStream_t st, const double* r, T* f0, T* f1, T* u0, int nx, int ny, int nz, double inv_diag,
+                  const Scalars* sc) {
+    const unsigned nh = (unsigned)(nx / 2) * ny * nz;
+    hipLaunchKernelGGL(k_enter<T>, dim3(nblocks(nh)), dim3(kBlock), 0, st, r, f0, f1, u0, nx / 2, ny, nz, inv_diag,
+                       sc);
+}
+
+// ---------------------------------------------------------------------------
+// Gauss-Seidel half-sweep on colour `color`: u_c = (f_c + s * sum nbrs) / diag.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gs(T* __restrict__ uc, const T* __restrict__ uo,
+                                               const T* __restrict__ fc, int hx, int ny, int nz, int color, T s,
+                                               T inv_diag, const Scalars* sc) {
+    if (sc && sc->done) return;
+    const unsigned nh = (unsigned)hx * ny * nz;
+    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= nh) return;
+    const int i = idx % hx;
+    const unsigned t = idx / hx;
+    const int y = t % ny, z = t / ny;
+    const int so = ((y + z) & 1) ^ color;
+    const T nb = nb_sum(uo, i, y, z, hx, ny, nz, so);
+    uc[idx] = (fc[idx] + s * nb) * inv_diag;
+}
+
+template <typename T>
+void launch_gs(hipStream_t st, T* uc, const T* uo, const T* fc, int hx, int ny, int nz, int color, double s,
+               double inv_diag, const Scalars* sc) {
+    const unsigned nh = (unsigned)hx * ny * nz;
+    hipLaunchKernelGGL(k_gs<T>, dim3(nblocks(nh)), dim3(kBlock), 0, st, uc, uo, fc, hx, ny, nz, color, (T)s,
+                       (T)inv_diag, sc);
+}
+
+// ---------------------------------------------------------------------------
+// Residual r = f - (diag u - s sum nbrs) for both colours.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_resid(const T* __restrict__ u0, const T* __restrict__ u1,
+                                                  const T* __restrict__ f0, const T* __restrict__ f1,
+                                                  T* __restrict__ r0, T* __restrict__ r1, int hx, int ny, int nz,
+                                                  T s, T diag, const Scalars* sc) {
+    if (sc && sc->done) return;
+    const unsigned nh = (unsigned)hx * ny * nz;
+    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= nh) return;
+    const int i = idx % hx;
+    const unsigned t = idx / hx;
+    const int y = t % ny, z = t / ny;
+    const int s0 = (y + z) & 1;
+    const T nr = nb_sum(u1, i, y, z, hx, ny, nz, s0);        // neighbours of the red cell are black
+    const T nbk = nb_sum(u0, i, y, z, hx, ny, nz, s0 ^ 1);   // and vice versa
+    r0[idx] = f0[idx] - (diag * u0[idx] - s * nr);
+    r1[idx] = f1[idx] - (diag * u1[idx] - s * nbk);
+}
+
+template <typename T>
+void launch_resid_split(hipStream_t st, const T* u0, const T* u1, const T* f0, const T* f1, T* r0, T* r1, int hx,
+                        int ny, int nz, double s, double diag, const Scalars* sc) {
+    const unsigned nh = (unsigned)hx * ny * nz;
+    hipLaunchKernelGGL(k_resid<T>, dim3(nblocks(nh)), dim3(kBlock), 0, st, u0, u1, f0, f1, r0, r1, hx, ny, nz, (T)s,
+                       (T)diag, sc);
+}
+
+// ---------------------------------------------------------------------------
+// Full-weighting restriction, 1-D weights (1, 3, 3, 1)/8 over fine cells
+// 2X-1 .. 2X+2. One thread per coarse cell (natural coarse index). Writes the
+// coarse right-hand side in split layout together with the zero-guess red
+// half-sweep, or in natural layout on the coarsest level.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_restrict(const T* __restrict__ r0, const T* __restrict__ r1, int nx,
+                                                     int ny, int nz, T* __restrict__ cf0, T* __restrict__ cf1,
+                                                     T* __restrict__ cu0, int coarse_natural, T inv_diag_c,
+                                                     const Scalars* sc) {
+    if (sc && sc->done) return;
+    const int cx = nx >> 1, cy = ny >> 1, cz = nz >> 1;
+    const unsigned nc = (unsigned)cx * cy * cz;
+    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= nc) return;
+    const int X = idx % cx;
+    const unsigned t = idx / cx;
+    const int Y = t % cy, Z = t / cy;
+    const int hx = nx >> 1;
+    const T w[4] = {(T)0.125, (T)0.375, (T)0.375, (T)0.125};
+    int xs[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) xs[a] = wrapi(2 * X - 1 + a, nx);
+    T acc = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int z = wrapi(2 * Z - 1 + c, nz);
+        T accb = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int y = wrapi(2 * Y - 1 + b, ny);
+            const size_t row = ((size_t)z * ny + y) * hx;
+            const int pyz = (y + z) & 1;
+            T acca = 0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int x = xs[a];
+                const T v = ((x + pyz) & 1) ? r1[row + (x >> 1)] : r0[row + (x >> 1)];
+                acca += w[a] * v;
+            }
+            accb += w[b] * acca;
+        }
+        acc += w[c] * accb;
+    }
+    if (coarse_natural) {
+        cf0[idx] = acc;
+    } else {
+        const size_t j = ((size_t)Z * cy + Y) * (cx >> 1) + (X >> 1);
+        if ((X + Y + Z) & 1) {
+            cf1[j] = acc;
+        } else {
+            cf0[j] = acc;
+            cu0[j] = acc * inv_diag_c;
+        }
+    }
+}
+
+template <typename T>
+void launch_restrict(hipStream_t st, const T* r0, const T* r1, int nx, int ny, int nz, T* cf0, T* cf1, T* cu0,
+                     int coarse_natural, double inv_diag_c, const Scalars* sc) {
+    const unsigned nc = (unsigned)(nx / 2) * (ny / 2) * (nz / 2);
+    hipLaunchKernelGGL(k_restrict<T>, dim3(nblocks(nc)), dim3(kBlock), 0, st, r0, r1, nx, ny, nz, cf0, cf1, cu0,
+                       coarse_natural, (T)inv_diag_c, sc);
+}
+
+// ---------------------------------------------------------------------------
+// Trilinear prolongation added to the fine split level: fine x = 2I + s takes
+// 3/4 of coarse I and 1/4 of coarse I-1 (s = 0) or I+1 (s = 1) per axis.
+template <typename T>
+__device__ __forceinline__ T coarse_at(const T* __restrict__ c0, const T* __restrict__ c1, int nat, int X, int Y,
+                                       int Z, int cx, int cy) {
+    if (nat) return c0[((size_t)Z * cy + Y) * cx + X];
+    const size_t j = ((size_t)Z * cy + Y) * (cx >> 1) + (X >> 1);
+    return ((X + Y + Z) & 1) ? c1[j] : c0[j];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong(const T* __restrict__ cu0, const T* __restrict__ cu1, int nat,
+                                                    T* __restrict__ u0, T* __restrict__ u1, int nx, int ny, int nz,
+                                                    const Scalars* sc) {
+    if (sc && sc->done) return;
+    const int hx = nx >> 1;
+    const unsigned nh = (unsigned)hx * ny * nz;
+    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= nh) return;
+    const int i = idx % hx;
+    const unsigned t = idx / hx;
+    const int y = t % ny, z = t / ny;
+    const int cx = nx >> 1, cy = ny >> 1, cz = nz >> 1;
+    const int J0 = y >> 1, J1 = wrapi((y & 1) ? J0 + 1 : J0 - 1, cy);
+    const int K0 = z >> 1, K1 = wrapi((z & 1) ? K0 + 1 : K0 - 1, cz);
+    const int s0 = (y + z) & 1;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int x = 2 * i + (s0 ^ c);
+        const int I0 = x >> 1, I1 = wrapi((x & 1) ? I0 + 1 : I0 - 1, cx);
+        const T a00 = (T)0.75 * coarse_at(cu0, cu1, nat, I0, J0, K0, cx, cy) +
+                      (T)0.25 * coarse_at(cu0, cu1, nat, I1, J0, K0, cx, cy);
+        const T a10 = (T)0.75 * coarse_at(cu0, cu1, nat, I0, J1, K0, cx, cy) +
+                      (T)0.25 * coarse_at(cu0, cu1, nat, I1, J1, K0, cx, cy);
+        const T a01 = (T)0.75 * coarse_at(cu0, cu1, nat, I0, J0, K1, cx, cy) +
+                      (T)0.25 * coarse_at(cu0, cu1, nat, I1, J0, K1, cx, cy);
+        const T a11 = (T)0.75 * coarse_at(cu0, cu1, nat, I0, J1, K1, cx, cy) +
+                      (T)0.25 * coarse_at(cu0, cu1, nat, I1, J1, K1, cx, cy);
+        const T v = (T)0.75 * ((T)0.75 * a00 + (T)0.25 * a10) + (T)0.25 * ((T)0.75 * a01 + (T)0.25 * a11);
+        if (c == 0) u0[idx] += v;
+        else u1[idx] += v;
+    }
+}
+
+template <typename T>
+void launch_prolong(hipStream_t st, const T* cu0, const T* cu1, int coarse_natural, T* u0, T* u1, int nx, int ny,
+                    int nz, const Scalars* sc) {
+    const unsigned nh = (unsigned)(nx / 2) * ny * nz;
+    hipLaunchKernelGGL(k_prolong<T>, dim3(nblocks(nh)), dim3(kBlock), 0, st, cu0, cu1, coarse_natural, u0, u1, nx, ny,
+                       nz, sc);
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest grid: u = C f with C the dense FP64 (pseudo-)inverse, m <= 512.
+template <typename T>
+__global__ void __launch_bounds__(kMaxCoarse) k_coarse(const T* __restrict__ f, T* __restrict__ u,
+                                                       const double* __restrict__ cinv, int m, const Scalars* sc) {
+    if (sc && sc->done) return;
+    __shared__ double fs[kMaxCoarse];
+    for (int j = threadIdx.x; j < m; j += blockDim.x) fs[j] = (double)f[j];
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const double* row = cinv + (size_t)i * m;
+        double acc = 0.0;
+        for (int j = 0; j < m; ++j) acc += row[j] * fs[j];
+        u[i] = (T)acc;
+    }
+}
+
+template <typename T>
+void launch_coarse(hipStream_t st, const T* f, T* u, const double* cinv, int m, const Scalars* sc) {
+    hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(kMaxCoarse), 0, st, f, u, cinv, m, sc);
+}
+
+#define BRD_INST(T)                                                                                                \
+    template void launch_enter<T>(hipStream_t, const double*, T*, T*, T*, int, int, int, double, const Scalars*);  \
+    template void launch_gs<T>(hipStream_t, T*, const T*, const T*, int, int, int, int, double, double,            \
+                               const Scalars*);                                                                    \
+    template void launch_resid_split<T>(hipStream_t, const T*, const T*, const T*, const T*, T*, T*, int, int, int, \
+                                        double, double, const Scalars*);                                            \
+    template void launch_restrict<T>(hipStream_t, const T*, const T*, int, int, int, T*, T*, T*, int, double,       \
+                                     const Scalars*);                                                               \
+    template void launch_prolong<T>(hipStream_t, const T*, const T*, int, T*, T*, int, int, int, const Scalars*);  \
+    template void launch_coarse<T>(hipStream_t, const T*, T*, const double*, int, const Scalars*);
+
+BRD_INST(float)
+BRD_INST(double)
+
+}  // namespace brd

@@ -1,0 +1,103 @@
+// Host-side launchers for the blob_rd kernels (all enqueue on `st`).
+#pragma once
+
+#include "brd.hpp"
+
+namespace brd {
+
+// ---- natural-layout FP64 grid kernels ------------------------------------
+// q = alpha p - D L p ; partials (p.q, sum q) into part[0..1][nb]
+void launch_applyA(hipStream_t st, const double* p, double* q, double alpha, double s, int nx, int ny,
+                   int nz, double* part, const Scalars* sc, unsigned* nparts_out);
+// y = alpha x - D L x (no partials, no guard)
+void launch_applyA_plain(hipStream_t st, const double* x, double* y, double alpha, double s, int nx, int ny,
+                         int nz);
+// r = g - alpha x + D L x ; partials (r.r, sum r, g.g)
+void launch_residual64(hipStream_t st, const double* g, const double* x, double* r, double alpha, double s,
+                       int nx, int ny, int nz, double* part, unsigned* nparts_out);
+// r = g - q0 (q0 may be null: r = g); partials (r.r, sum r, g.g)
+void launch_residual_from_q(hipStream_t st, const double* g, const double* q0, double* r, size_t n, double* part,
+                            unsigned* nparts_out);
+// p = z + shift + beta p  (z split, level-0 layout of type T)
+template <typename T>
+void launch_dir(hipStream_t st, const T* z0, const T* z1, double* p, int nx, int ny, int nz,
+                const Scalars* sc);
+// x += alpha p ; r -= alpha q ; partials (r.r, sum r)
+void launch_update(hipStream_t st, double* x, double* r, const double* p, const double* q, size_t n,
+                   double* part, const Scalars* sc, unsigned* nparts_out);
+// partials (sum z, z.r, z.q) with z split of type T
+template <typename T>
+void launch_zdots(hipStream_t st, const T* z0, const T* z1, const double* r, const double* q, int nx, int ny,
+                  int nz, double* part, const Scalars* sc, unsigned* nparts_out);
+// x += shift + z (final correction of a preconditioner application, z split)
+template <typename T>
+void launch_split_to_nat(hipStream_t st, const T* z0, const T* z1, double* out, int nx, int ny, int nz,
+                         double scale_in_place);
+// sums (sum v, v.v) of a natural vector
+void launch_norm_partials(hipStream_t st, const double* v, size_t n, double* part, unsigned* nparts_out);
+void launch_fill(hipStream_t st, double* v, size_t n, double value);
+void launch_axpby(hipStream_t st, double* y, const double* x, size_t n, double a, double b);  // y = a y + b x
+void launch_add_shift(hipStream_t st, double* v, size_t n, const double* shift_dev, double sign);
+
+// ---- finalize kernels (one work-group) ------------------------------------
+enum FinKind { FIN_INIT = 0, FIN_ALPHA = 1, FIN_UPDATE = 2, FIN_BETA = 3 };
+void launch_fin(hipStream_t st, int kind, const double* part, unsigned nparts, Scalars* sc,
+                const double* nvec_a, const double* nvec_b, int nblob, double inv_h3);
+// sum of partial sets into out[0..k-1] (generic)
+void launch_reduce_parts(hipStream_t st, const double* part, unsigned nparts, int k, double* out);
+
+// ---- multigrid (split layout) ---------------------------------------------
+template <typename T>
+void launch_enter(hipStream_t st, const double* r, T* f0, T* f1, T* u0, int nx, int ny, int nz,
+                  double inv_diag, const Scalars* sc);
+template <typename T>
+void launch_gs(hipStream_t st, T* uc, const T* uo, const T* fc, int hx, int ny, int nz, int color, double s,
+               double inv_diag, const Scalars* sc);
+template <typename T>
+void launch_resid_split(hipStream_t st, const T* u0, const T* u1, const T* f0, const T* f1, T* r0, T* r1, int hx,
+                        int ny, int nz, double s, double diag, const Scalars* sc);
+// fine split residual -> coarse f (split, with zero-guess red update) or natural (coarsest)
+template <typename T>
+void launch_restrict(hipStream_t st, const T* r0, const T* r1, int nx, int ny, int nz, T* cf0, T* cf1, T* cu0,
+                     int coarse_natural, double inv_diag_c, const Scalars* sc);
+template <typename T>
+void launch_prolong(hipStream_t st, const T* cu0, const T* cu1, int coarse_natural, T* u0, T* u1, int nx, int ny,
+                    int nz, const Scalars* sc);
+template <typename T>
+void launch_coarse(hipStream_t st, const T* f, T* u, const double* cinv, int m, const Scalars* sc);
+
+// ---- blobs -----------------------------------------------------------------
+struct BlobGeom {
+    int nx, ny, nz;
+    int tx, ty, tz;      // tile edge per axis (divides the grid edge)
+    int ntx, nty, ntz;   // tiles per axis
+    double h;
+    int w;
+};
+// wrap positions, kernel weights, tile ids, bin counts (int atomics on counts only)
+void launch_blob_setup(hipStream_t st, const double* q, int N, BlobGeom g, int* base /*[3N]*/,
+                       double* wts /*[12N]*/, int* tile_of, int* counts);
+void launch_bin_scan(hipStream_t st, const int* counts, int ntiles, int* offsets /*ntiles+1*/);
+void launch_bin_scatter(hipStream_t st, const int* tile_of, int N, const int* offsets, int* cursor, int* perm);
+void launch_bin_sort(hipStream_t st, const int* offsets, int ntiles, int* perm);
+// out[i] = scale_i * (J x)_i, scale = kappa (if non-null) ; jx (optional) gets (J x)_i
+void launch_interp(hipStream_t st, const double* x, int N, BlobGeom g, const int* base, const double* wts,
+                   const int* perm, double* jx, const double* kappa, double* out, const Scalars* sc);
+// out = base_in + scale * sum_i w_i lam_i   over the grid (gather by tiles);
+// add_only: out already holds base_in (aliased) and empty tiles are skipped.
+void launch_spread(hipStream_t st, const double* lam, double lam_shift, int N, BlobGeom g, const int* base,
+                   const double* wts, const int* offsets, const int* perm, const double* base_in, double* out,
+                   double scale, int add_only, const Scalars* sc);
+
+// ---- N-vector kernels (single work-group) ------------------------------------
+void launch_nvec_project(hipStream_t st, double* v, int N);  // v -= mean(v)
+void launch_nvec_copy_scale(hipStream_t st, const double* x, double* y, int N, double a, double shift);
+void launch_gmres_start(hipStream_t st, const double* b, const double* w, int has_w, double* V, double* g, int N,
+                        GmresScalars* gs);
+void launch_gmres_arnoldi(hipStream_t st, double* V, double* H, double* cs, double* sn, double* g, int N, int k,
+                          int m, GmresScalars* gs);
+void launch_gmres_update(hipStream_t st, const double* V, const double* H, const double* g, double* y, double* x,
+                         int N, int k, int m);
+void launch_nvec_sums(hipStream_t st, const double* a, const double* b, int N, double* out /*sum a, a.a, a.b*/);
+
+}  // namespace brd

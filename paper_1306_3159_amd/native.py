@@ -1,0 +1,239 @@
+"""ctypes binding of libblob_rd.so, argument marshalling only.
+
+Names follow the C ABI (include/blob_rd.h): create/destroy, solve_reactive,
+solve_absorbing, step, interp, spread, apply, vcycle.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple, Union
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libblob_rd.so")
+
+FP64 = 0
+MIXED = 1
+PRECOND_NONE = 0
+PRECOND_DIAGONAL = 1
+PRECOND_LEARNED = 2
+
+OK = 0
+ENOTCONV = 1
+_ERRNAMES = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESINGULAR", -5: "ENUMERIC"}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("h", ctypes.c_double), ("D", ctypes.c_double), ("kernel_w", ctypes.c_int32),
+        ("n_blobs", ctypes.c_int64), ("q", ctypes.c_void_p), ("kappa", ctypes.c_void_p),
+        ("precision", ctypes.c_int32), ("schur_precond", ctypes.c_int32),
+        ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
+        ("inner_max_iter", ctypes.c_int32), ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("outer_iters", ctypes.c_int32), ("inner_iters_total", ctypes.c_int32),
+        ("vcycles", ctypes.c_int32), ("fallback", ctypes.c_int32), ("refinements", ctypes.c_int32),
+        ("rel_resid", ctypes.c_double), ("seconds", ctypes.c_double), ("alg_bytes", ctypes.c_double),
+    ]
+
+    def as_dict(self, rc: int = 0) -> dict:
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["rc"] = rc
+        return d
+
+
+class BlobRDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"blob_rd error {_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class NotConverged(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = ctypes.CDLL(path)
+    vp, d, i32 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
+    P = ctypes.POINTER(Params)
+    S = ctypes.POINTER(Stats)
+    L.blob_rd_workspace_bytes.argtypes = [P]
+    L.blob_rd_workspace_bytes.restype = ctypes.c_size_t
+    L.blob_rd_create.argtypes = [P, ctypes.POINTER(vp)]
+    L.blob_rd_create.restype = i32
+    L.blob_rd_destroy.argtypes = [vp]
+    L.blob_rd_destroy.restype = i32
+    L.blob_rd_last_error.argtypes = [vp]
+    L.blob_rd_last_error.restype = ctypes.c_char_p
+    L.blob_rd_solve_reactive.argtypes = [vp, d, vp, vp, S]
+    L.blob_rd_solve_reactive.restype = i32
+    L.blob_rd_solve_absorbing.argtypes = [vp, d, vp, vp, vp, S]
+    L.blob_rd_solve_absorbing.restype = i32
+    L.blob_rd_step.argtypes = [vp, d, vp, vp, S]
+    L.blob_rd_step.restype = i32
+    L.blob_rd_interp.argtypes = [vp, vp, vp]
+    L.blob_rd_interp.restype = i32
+    L.blob_rd_spread.argtypes = [vp, vp, vp]
+    L.blob_rd_spread.restype = i32
+    L.blob_rd_apply.argtypes = [vp, d, i32, vp, vp]
+    L.blob_rd_apply.restype = i32
+    L.blob_rd_vcycle.argtypes = [vp, d, vp, vp]
+    L.blob_rd_vcycle.restype = i32
+    _lib = L
+    return L
+
+
+def _dev_f64(t: torch.Tensor, shape, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class BlobRD:
+    """A blob configuration on a periodic grid (wraps a blob_rd handle).
+
+    Grid tensors are float64 CUDA tensors of shape (nz, ny, nx); q is (N, 3)
+    float64 (x, y, z) and kappa (N,) float64 on the same device.
+    """
+
+    def __init__(self, shape: Union[int, Sequence[int]], q: torch.Tensor, kappa: Optional[torch.Tensor] = None,
+                 h: float = 1.0, D: float = 1.0, kernel_w: int = 4, precision: int = FP64,
+                 schur_precond: int = PRECOND_NONE, rtol: float = 1e-8, max_iter: int = 0,
+                 gmres_restart: int = 0, inner_max_iter: int = 0, stream: Optional[torch.cuda.Stream] = None):
+        L = load_library()
+        if isinstance(shape, int):
+            shape = (shape, shape, shape)
+        self.shape = tuple(int(s) for s in shape)          # (nz, ny, nx)
+        nz, ny, nx = self.shape
+        self.device = q.device
+        N = int(q.shape[0])
+        self.N = N
+        if N > 0:
+            _dev_f64(q, (N, 3), "q")
+        if kappa is not None:
+            _dev_f64(kappa, (N,), "kappa")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(q.device)
+        self._q, self._kappa = q, kappa
+        p = Params(nx, ny, nz, float(h), float(D), int(kernel_w), N, q.data_ptr() if N > 0 else None,
+                   None if kappa is None else kappa.data_ptr(), int(precision), int(schur_precond),
+                   float(rtol), int(max_iter), int(gmres_restart), int(inner_max_iter), None, 0,
+                   ctypes.c_void_p(self.stream.cuda_stream))
+        nbytes = L.blob_rd_workspace_bytes(ctypes.byref(p))
+        if nbytes == 0:
+            raise BlobRDError(-1, L.blob_rd_last_error(None).decode())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=q.device)
+        p.workspace = self.workspace.data_ptr()
+        p.workspace_bytes = nbytes
+        self.params = p
+        h_ = ctypes.c_void_p()
+        with torch.cuda.device(q.device):
+            rc = L.blob_rd_create(ctypes.byref(p), ctypes.byref(h_))
+        if rc != OK:
+            raise BlobRDError(rc, L.blob_rd_last_error(None).decode())
+        self._h = h_
+        self._lib = L
+
+    # -- helpers -------------------------------------------------------------
+    def _check(self, rc: int, st: Optional[Stats] = None, allow_notconv: bool = True) -> dict:
+        if rc < 0:
+            raise BlobRDError(rc, self._lib.blob_rd_last_error(self._h).decode())
+        out = st.as_dict(rc) if st is not None else {"rc": rc}
+        if rc == ENOTCONV and not allow_notconv:
+            raise NotConverged(str(out))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.blob_rd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _grid(self, t, name):
+        return _dev_f64(t, self.shape, name)
+
+    def _new_grid(self):
+        return torch.zeros(self.shape, dtype=torch.float64, device=self.device)
+
+    # -- solves ------------------------------------------------------------------
+    def solve_reactive(self, f: torch.Tensor, c: Optional[torch.Tensor] = None, alpha: float = 0.0
+                       ) -> Tuple[torch.Tensor, dict]:
+        """(alpha I - D L + S kappa J) c = f; c is the initial guess (zeros if None)."""
+        self._grid(f, "f")
+        c = self._new_grid() if c is None else self._grid(c, "c")
+        st = Stats()
+        rc = self._lib.blob_rd_solve_reactive(self._h, float(alpha), _ptr(f), _ptr(c), ctypes.byref(st))
+        return c, self._check(rc, st)
+
+    def solve_absorbing(self, f: torch.Tensor, alpha: float = 0.0, c: Optional[torch.Tensor] = None,
+                        lam: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, torch.Tensor, dict]:
+        """[alpha I - D L, S; J, 0][c; lam] = [f; 0]."""
+        self._grid(f, "f")
+        c = self._new_grid() if c is None else self._grid(c, "c")
+        lam = torch.zeros(self.N, dtype=torch.float64, device=self.device) if lam is None else lam
+        st = Stats()
+        rc = self._lib.blob_rd_solve_absorbing(self._h, float(alpha), _ptr(f), _ptr(c), _ptr(lam), ctypes.byref(st))
+        return c, lam, self._check(rc, st)
+
+    def step(self, f: torch.Tensor, c: torch.Tensor, dt: float) -> dict:
+        """One backward-Euler step; c holds c^n on entry and c^{n+1} on exit."""
+        self._grid(f, "f")
+        self._grid(c, "c")
+        st = Stats()
+        rc = self._lib.blob_rd_step(self._h, float(dt), _ptr(f), _ptr(c), ctypes.byref(st))
+        return self._check(rc, st)
+
+    # -- operators --------------------------------------------------------------
+    def interp(self, c: torch.Tensor) -> torch.Tensor:
+        self._grid(c, "c")
+        out = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        self._check(self._lib.blob_rd_interp(self._h, _ptr(c), _ptr(out)))
+        return out
+
+    def spread(self, lam: torch.Tensor) -> torch.Tensor:
+        out = self._new_grid()
+        self._check(self._lib.blob_rd_spread(self._h, _ptr(lam), _ptr(out)))
+        return out
+
+    def apply(self, x: torch.Tensor, alpha: float = 0.0, with_blobs: bool = True) -> torch.Tensor:
+        self._grid(x, "x")
+        y = self._new_grid()
+        self._check(self._lib.blob_rd_apply(self._h, float(alpha), int(bool(with_blobs)), _ptr(x), _ptr(y)))
+        return y
+
+    def vcycle(self, r: torch.Tensor, alpha: float = 0.0) -> torch.Tensor:
+        self._grid(r, "r")
+        z = self._new_grid()
+        self._check(self._lib.blob_rd_vcycle(self._h, float(alpha), _ptr(r), _ptr(z)))
+        return z

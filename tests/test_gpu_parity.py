@@ -1,0 +1,278 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle.
+
+Tolerances: FP64 paths match the oracle to ~1e-12 relative element by element
+(operators, one V-cycle) and to 1e-10 relative for solves; mixed-precision
+solves (FP32 V-cycles under FP64 CG, refinement) reach the 1e-8 relative
+residual and match the FP64 solution to ~1e-8 (solution error is bounded by
+the condition number times the residual).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import exact as ex
+from oracle import iterative as it
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1306_3159_amd import native
+    native.load_library()
+    return torch.device("cuda:0")
+
+
+def T(a, dev):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def H(t):
+    return t.detach().cpu().numpy()
+
+
+def make(dev, shape, q, kappa=None, **kw):
+    from paper_1306_3159_amd import BlobRD
+    return BlobRD(shape, T(q, dev), None if kappa is None else T(kappa, dev), **kw)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# ------------------------------------------------------------------ operators
+CASES = [((32, 32, 32), 40, 1.0, 4), ((24, 24, 24), 30, 0.7, 4), ((20, 20, 20), 25, 1.0, 4),
+         ((16, 32, 24), 20, 1.0, 4), ((48, 48, 48), 60, 1.0, 3), ((8, 8, 8), 3, 1.0, 4)]
+
+
+@pytest.mark.parametrize("shape,N,h,w", CASES)
+def test_interp_spread_apply_parity(dev, shape, N, h, w):
+    _say("interp/spread/apply", shape, N, h, w)
+    rng = np.random.default_rng(100 + N)
+    nz, ny, nx = shape
+    q = rng.uniform(-2.0, 2.0 + nx * h, size=(N, 3)) * np.array([1.0, ny / nx, nz / nx])
+    kappa = W.log_uniform(rng, 1e-2, 1e2, N)
+    c = rng.standard_normal(shape)
+    lam = rng.standard_normal(N)
+    S = make(dev, shape, q, kappa, h=h, kernel_w=w)
+    qw = q.copy()  # oracle uses the nearest periodic image itself
+    jc = H(S.interp(T(c, dev)))
+    assert np.max(np.abs(jc - ex.interp(c, qw, h, w))) < 1e-13 * max(1, np.abs(jc).max())
+    sl = H(S.spread(T(lam, dev)))
+    ref = ex.spread(lam, qw, shape, h, w)
+    assert np.max(np.abs(sl - ref)) < 1e-13 * np.abs(ref).max()
+    for alpha in (0.0, 0.37):
+        y = H(S.apply(T(c, dev), alpha, True))
+        refy = ex.apply_B(c, qw, kappa, alpha, 1.0, h, w)
+        assert np.max(np.abs(y - refy)) < 1e-12 * np.abs(refy).max()
+    S.close()
+
+
+# ------------------------------------------------------------------ multigrid
+@pytest.mark.parametrize("shape", [(32, 32, 32), (48, 48, 48), (16, 32, 24), (64, 64, 64)])
+@pytest.mark.parametrize("alpha", [0.0, 2.0])
+def test_vcycle_parity_fp64(dev, shape, alpha):
+    _say("vcycle fp64", shape, alpha)
+    rng = np.random.default_rng(7)
+    r = rng.standard_normal(shape)
+    if alpha == 0.0:
+        r -= r.mean()
+    S = make(dev, shape, np.zeros((0, 3)))
+    z = H(S.vcycle(T(r, dev), alpha))
+    zr = it.vcycle(r, alpha)
+    assert np.max(np.abs(z - zr)) < 1e-12 * np.abs(zr).max()
+    S.close()
+
+
+@pytest.mark.parametrize("alpha", [0.0, 2.0])
+def test_vcycle_parity_mixed(dev, alpha):
+    _say("vcycle mixed", alpha)
+    shape = (64, 64, 64)
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal(shape)
+    if alpha == 0.0:
+        r -= r.mean()
+    from paper_1306_3159_amd import MIXED
+    S = make(dev, shape, np.zeros((0, 3)), precision=MIXED)
+    z = H(S.vcycle(T(r, dev), alpha))
+    zr = it.vcycle(r, alpha)
+    assert rel(z, zr) < 2e-6
+    S.close()
+
+
+# ------------------------------------------------------------------ reactive
+@pytest.mark.parametrize("prec", [0, 1])
+def test_single_blob_reactive(dev, prec):
+    """32^3, one blob at a seeded position, kappa = 1, f = 1, steady (alpha = 0)."""
+    inst = W.single_blob()
+    _say("single blob reactive", prec)
+    S = make(dev, inst.n, inst.q, inst.kappa, precision=prec, rtol=inst.rtol if prec == 0 else 1e-8)
+    c, st = S.solve_reactive(T(inst.f, dev))
+    c = H(c)
+    assert st["rc"] == 0, st
+    ce, mu = ex.solve_reactive(inst.f, inst.q, inst.kappa, 0.0)
+    tol = 1e-10 if prec == 0 else 1e-8
+    assert ex.reactive_residual(c, inst.f, inst.q, inst.kappa, 0.0) <= tol
+    assert rel(c, ce) < tol
+    # closed form: mean(c) = V (1/kappa + gamma / D)
+    gam = ex.gamma_single_blob(inst.q[0], (32, 32, 32))
+    assert c.mean() == pytest.approx(32 ** 3 * (1.0 + gam), rel=tol)
+    S.close()
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.5])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_reactive_many_blobs(dev, alpha, prec):
+    _say("reactive many", alpha, prec)
+    rng = np.random.default_rng(31)
+    n = 32
+    q = W.rsa_positions(rng, n, 40, 3.0)
+    kappa = W.log_uniform(rng, 1e-2, 1e2, 40)
+    f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
+    S = make(dev, n, q, kappa, precision=prec, rtol=1e-10 if prec == 0 else 1e-8)
+    c, st = S.solve_reactive(T(f, dev), alpha=alpha)
+    c = H(c)
+    assert st["rc"] == 0, st
+    ce, _ = ex.solve_reactive(f, q, kappa, alpha)
+    tol = 1e-10 if prec == 0 else 1e-8
+    assert ex.reactive_residual(c, f, q, kappa, alpha) <= tol
+    assert rel(c, ce) < 10 * tol
+    S.close()
+
+
+# ------------------------------------------------------------------ absorbing
+@pytest.mark.parametrize("alpha", [0.0, 0.25])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_absorbing_small(dev, alpha, prec):
+    _say("absorbing small", alpha, prec)
+    rng = np.random.default_rng(41)
+    n = 32
+    q = W.rsa_positions(rng, n, 30, 3.0)
+    f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
+    S = make(dev, n, q, precision=prec, rtol=1e-10 if prec == 0 else 1e-8)
+    c, lam, st = S.solve_absorbing(T(f, dev), alpha=alpha)
+    c, lam = H(c), H(lam)
+    assert st["rc"] == 0, st
+    ce, le = ex.solve_absorbing(f, q, alpha)
+    tol = 1e-10 if prec == 0 else 1e-8
+    assert ex.absorbing_residual(c, lam, f, q, alpha) <= tol
+    assert rel(lam, le) < 100 * tol
+    assert rel(c, ce) < 100 * tol
+    if alpha == 0.0:
+        assert lam.sum() == pytest.approx(f.sum(), rel=1e-12)
+    S.close()
+
+
+def test_single_absorbing_blob_radius(dev):
+    """Sec. IV.A: single absorbing blob at a node with s = 1/V: a ~ 1.27 h (four-point)."""
+    n = 64
+    V = float(n ** 3)
+    q = np.array([[32.0, 32.0, 32.0]])
+    _say("radius", n)
+    S = make(dev, n, q, rtol=1e-10)
+    c, lam, st = S.solve_absorbing(T(np.full((n, n, n), 1.0 / V), dev))
+    c = H(c)
+    a = ex.radius_extrapolated(ex.radius_from_mean(c.mean(), 1.0 / V, V), n)
+    assert a == pytest.approx(1.27, rel=0.01)
+    assert H(lam)[0] == pytest.approx(1.0, rel=1e-12)
+    S.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lattice_128_uniform_source(dev, prec):
+    """128^3 grid, 8^3 blobs 16h apart at cell vertices, f = 1: lam_i = 16^3 and c equals
+    the one-cell (16^3) solution tiled 8 times per axis."""
+    inst = W.cubic_lattice()
+    _say("lattice128", prec)
+    S = make(dev, inst.n, inst.q, precision=prec, rtol=1e-8)
+    c, lam, st = S.solve_absorbing(T(inst.f, dev))
+    assert st["rc"] == 0, st
+    c, lam = H(c), H(lam)
+    c1, _ = ex.solve_absorbing(np.ones((16, 16, 16)), np.array([[8.0, 8.0, 8.0]]), 0.0)
+    tiled = np.tile(c1, (8, 8, 8))
+    assert np.max(np.abs(lam - 4096.0)) < 1e-8 * 4096
+    assert rel(c, tiled) < 1e-8
+    assert st["rel_resid"] <= 1e-8
+    S.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_lattice_128_random_source(dev, prec):
+    """Same lattice, random source: the Schur GMRES does real work. Checked through the
+    oracle's FP64 saddle residual at full size and sampled against the oracle solve."""
+    inst = W.cubic_lattice(random_f=True)
+    _say("lattice128 random f", prec)
+    S = make(dev, inst.n, inst.q, precision=prec, rtol=1e-8)
+    c, lam, st = S.solve_absorbing(T(inst.f, dev))
+    assert st["rc"] == 0, st
+    c, lam = H(c), H(lam)
+    r = ex.absorbing_residual(c, lam, inst.f, inst.q, 0.0)
+    assert r <= 1e-8
+    assert lam.sum() == pytest.approx(inst.f.sum(), rel=1e-12)
+    S.close()
+
+
+# ------------------------------------------------------------------ time stepping
+def test_backward_euler_steps(dev):
+    _say("BE steps")
+    rng = np.random.default_rng(51)
+    n = 32
+    q = W.rsa_positions(rng, n, 20, 3.0)
+    kappa = W.log_uniform(rng, 1e-2, 1e2, 20)
+    f = np.ones((n, n, n))
+    S = make(dev, n, q, kappa, rtol=1e-11)
+    c = torch.zeros((n, n, n), dtype=torch.float64, device=dev)
+    ce = np.zeros((n, n, n))
+    G = ex.schur_matrix(q, (n, n, n), 2.0)
+    for k in range(3):
+        st = S.step(T(f, dev), c, 0.5)
+        assert st["rc"] == 0
+        ce = ex.step(ce, f, q, kappa, 0.5, G=G)
+    assert rel(H(c), ce) < 1e-10
+    S.close()
+
+
+# ------------------------------------------------------------------ errors, determinism
+def test_error_codes(dev):
+    _say("errors")
+    from paper_1306_3159_amd import BlobRD, BlobRDError
+    with pytest.raises(BlobRDError) as e:
+        BlobRD((36, 36, 36), T(np.zeros((1, 3)), dev))
+    assert e.value.code == -1
+    S = make(dev, 16, np.array([[3.0, 4.0, 5.0]]))       # kappa missing -> zero rates
+    with pytest.raises(BlobRDError) as e:
+        S.solve_reactive(T(np.ones((16, 16, 16)), dev))
+    assert e.value.code == -4
+    S.close()
+    S = make(dev, 16, np.zeros((0, 3)))
+    with pytest.raises(BlobRDError) as e:
+        S.solve_absorbing(T(np.ones((16, 16, 16)), dev))
+    assert e.value.code == -1
+    S.close()
+
+
+def test_bitwise_deterministic(dev):
+    _say("determinism")
+    rng = np.random.default_rng(61)
+    n = 32
+    q = W.rsa_positions(rng, n, 50, 3.0)
+    f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
+    outs = []
+    for _ in range(2):
+        S = make(dev, n, q, precision=1)
+        c, lam, st = S.solve_absorbing(T(f, dev))
+        outs.append((H(c), H(lam)))
+        S.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
