@@ -146,6 +146,21 @@ int blob_rd_apply(blob_rd_t h, double alpha, int with_blobs, const double* x, do
  * mean projection is applied. */
 int blob_rd_vcycle(blob_rd_t h, double alpha, const double* r, double* z);
 
+/* ---- Measurement ---- */
+
+#define BLOB_RD_KERNEL_GS 0        /* one Gauss-Seidel half-sweep on the finest level */
+#define BLOB_RD_KERNEL_STENCIL 1   /* FP64 operator apply y = alpha x - D L x (+ CG partial dots) */
+#define BLOB_RD_KERNEL_RESTRICT 2  /* finest residual + full-weighting restriction */
+#define BLOB_RD_KERNEL_PROLONG 3   /* trilinear prolongation + correction onto the finest level */
+#define BLOB_RD_KERNEL_VCYCLE 4    /* one whole V-cycle (all levels) */
+
+/* Launch one kernel of the solve path `reps` times back to back on the
+ * handle's stream, bracketed by HIP events, on the handle's own workspace
+ * buffers (their contents are overwritten). avg_ms receives the mean time
+ * per launch and bytes the algorithmic HBM bytes one launch must move
+ * (each input read once, each output written once). */
+int blob_rd_time_kernel(blob_rd_t h, int kernel, int reps, double* avg_ms, double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

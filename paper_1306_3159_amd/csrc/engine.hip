@@ -982,4 +982,109 @@ int blob_rd_vcycle(blob_rd_t H, double alpha, const double* r, double* z) {
     });
 }
 
+int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, double* bytes) {
+    if (!H || !avg_ms || !bytes || reps <= 0) return g_last_error = "bad argument", BLOB_RD_EINVAL;
+    if (kernel < 0 || kernel > 4) return g_last_error = "unknown kernel id", BLOB_RD_EINVAL;
+    return guarded(H, nullptr, [&]() {
+        const Plan& P = H->P;
+        const LevelDims& d = P.lev[0];
+        const double alpha = 0.0, s = H->prm.D / (d.h * d.h), diag = alpha + 6.0 * s;
+        const size_t half = (size_t)d.hx * d.ny * d.nz;
+        const double* cinv = select_cinv(H, alpha);
+        // Defined contents for every buffer the kernels read.
+        for (int k = 0; k < 6; ++k) HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[0][k], 0, half * P.esz, H->st));
+        if (P.nlev > 1) {
+            const int L = P.nlev - 1;
+            for (int l = 1; l < L; ++l) {
+                const size_t hl = (size_t)P.lev[l].hx * P.lev[l].ny * P.lev[l].nz;
+                for (int k = 0; k < 6; ++k) HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[l][k], 0, hl * P.esz, H->st));
+            }
+            HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[L][0], 0, (size_t)P.m * P.esz, H->st));
+            HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[L][2], 0, (size_t)P.m * P.esz, H->st));
+        }
+        HIPCHK(hipMemsetAsync(H->grid(G_P), 0, P.ncell * 8, H->st));
+        HIPCHK(hipMemsetAsync(H->grid(G_R), 0, P.ncell * 8, H->st));
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        auto one = [&]() {
+            const bool f32 = P.esz == 4;
+            const LevelDims& c = P.lev[1];
+            const int cnat = P.nlev == 2;
+            switch (kernel) {
+                case BLOB_RD_KERNEL_GS:
+                    if (f32) launch_gs<float>(H->st, H->at<float>(P.off_lvl[0][1]), H->at<float>(P.off_lvl[0][0]),
+                                              H->at<float>(P.off_lvl[0][3]), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, nullptr);
+                    else launch_gs<double>(H->st, H->at<double>(P.off_lvl[0][1]), H->at<double>(P.off_lvl[0][0]),
+                                           H->at<double>(P.off_lvl[0][3]), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, nullptr);
+                    break;
+                case BLOB_RD_KERNEL_STENCIL:
+                    launch_applyA(H->st, H->grid(G_P), H->grid(G_Q), alpha, s, d.nx, d.ny, d.nz, H->part(), nullptr,
+                                  nullptr);
+                    break;
+                case BLOB_RD_KERNEL_RESTRICT:
+                    if (f32) {
+                        launch_resid_split<float>(H->st, H->at<float>(P.off_lvl[0][0]), H->at<float>(P.off_lvl[0][1]),
+                                                  H->at<float>(P.off_lvl[0][2]), H->at<float>(P.off_lvl[0][3]),
+                                                  H->at<float>(P.off_lvl[0][4]), H->at<float>(P.off_lvl[0][5]), d.hx,
+                                                  d.ny, d.nz, s, diag, nullptr);
+                        launch_restrict<float>(H->st, H->at<float>(P.off_lvl[0][4]), H->at<float>(P.off_lvl[0][5]), d.nx,
+                                               d.ny, d.nz, H->at<float>(P.off_lvl[1][2]),
+                                               cnat ? nullptr : H->at<float>(P.off_lvl[1][3]),
+                                               cnat ? nullptr : H->at<float>(P.off_lvl[1][0]), cnat,
+                                               1.0 / (alpha + 6.0 * H->prm.D / (c.h * c.h)), nullptr);
+                    } else {
+                        launch_resid_split<double>(H->st, H->at<double>(P.off_lvl[0][0]), H->at<double>(P.off_lvl[0][1]),
+                                                   H->at<double>(P.off_lvl[0][2]), H->at<double>(P.off_lvl[0][3]),
+                                                   H->at<double>(P.off_lvl[0][4]), H->at<double>(P.off_lvl[0][5]),
+                                                   d.hx, d.ny, d.nz, s, diag, nullptr);
+                        launch_restrict<double>(H->st, H->at<double>(P.off_lvl[0][4]), H->at<double>(P.off_lvl[0][5]),
+                                                d.nx, d.ny, d.nz, H->at<double>(P.off_lvl[1][2]),
+                                                cnat ? nullptr : H->at<double>(P.off_lvl[1][3]),
+                                                cnat ? nullptr : H->at<double>(P.off_lvl[1][0]), cnat,
+                                                1.0 / (alpha + 6.0 * H->prm.D / (c.h * c.h)), nullptr);
+                    }
+                    break;
+                case BLOB_RD_KERNEL_PROLONG:
+                    if (f32) launch_prolong<float>(H->st, H->at<float>(P.off_lvl[1][0]),
+                                                   cnat ? nullptr : H->at<float>(P.off_lvl[1][1]), cnat,
+                                                   H->at<float>(P.off_lvl[0][0]), H->at<float>(P.off_lvl[0][1]), d.nx,
+                                                   d.ny, d.nz, nullptr);
+                    else launch_prolong<double>(H->st, H->at<double>(P.off_lvl[1][0]),
+                                                cnat ? nullptr : H->at<double>(P.off_lvl[1][1]), cnat,
+                                                H->at<double>(P.off_lvl[0][0]), H->at<double>(P.off_lvl[0][1]), d.nx,
+                                                d.ny, d.nz, nullptr);
+                    break;
+                default:
+                    if (f32) vcycle<float>(H, alpha, H->grid(G_R), nullptr, cinv);
+                    else vcycle<double>(H, alpha, H->grid(G_R), nullptr, cinv);
+            }
+        };
+        one();  // warm
+        HIPCHK(hipEventRecord(e0, H->st));
+        for (int i = 0; i < reps; ++i) one();
+        HIPCHK(hipEventRecord(e1, H->st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *avg_ms = (double)ms / reps;
+        const double n = (double)P.ncell, e = (double)P.esz;
+        switch (kernel) {
+            case BLOB_RD_KERNEL_GS: *bytes = n * 0.5 * e * 3; break;              // other colour, f, own colour
+            case BLOB_RD_KERNEL_STENCIL: *bytes = n * 16; break;                 // read x, write y (FP64)
+            case BLOB_RD_KERNEL_RESTRICT: *bytes = n * e * 4 + n / 8 * e; break; // u, f read; r write+read; coarse f
+            case BLOB_RD_KERNEL_PROLONG: *bytes = n * e * 2 + n / 8 * e; break;  // u read+write, coarse read
+            default: {
+                double b = 0.0;
+                for (int l = 0; l + 1 < P.nlev; ++l) b += n / (double)(1 << (3 * l)) * e * (7 * 1.5 + 4 + 2 + 0.25);
+                *bytes = b + n * 8;
+            }
+        }
+        HIPCHK(hipGetLastError());
+        return BLOB_RD_OK;
+    });
+}
+
 }  // extern "C"

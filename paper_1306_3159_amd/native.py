@@ -96,6 +96,8 @@ def load_library(path: str = LIB_PATH):
     L.blob_rd_apply.restype = i32
     L.blob_rd_vcycle.argtypes = [vp, d, vp, vp]
     L.blob_rd_vcycle.restype = i32
+    L.blob_rd_time_kernel.argtypes = [vp, i32, i32, ctypes.POINTER(d), ctypes.POINTER(d)]
+    L.blob_rd_time_kernel.restype = i32
     _lib = L
     return L
 
@@ -237,3 +239,13 @@ class BlobRD:
         z = self._new_grid()
         self._check(self._lib.blob_rd_vcycle(self._h, float(alpha), _ptr(r), _ptr(z)))
         return z
+
+    # -- measurement ------------------------------------------------------------
+    KERNELS = {"gs": 0, "stencil": 1, "restrict": 2, "prolong": 3, "vcycle": 4}
+
+    def time_kernel(self, kernel: str, reps: int = 50) -> Tuple[float, float]:
+        """Mean ms per launch (HIP events on this handle's stream) and algorithmic bytes per launch."""
+        ms, by = ctypes.c_double(), ctypes.c_double()
+        self._check(self._lib.blob_rd_time_kernel(self._h, self.KERNELS[kernel], int(reps), ctypes.byref(ms),
+                                                  ctypes.byref(by)))
+        return ms.value, by.value
