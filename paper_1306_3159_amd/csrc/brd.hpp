@@ -59,6 +59,17 @@ struct GmresScalars {
     int32_t status;
 };
 
+// Levels handled by the single-work-group coarse tail (index 0 = first tail
+// level, last = coarsest). LDS byte offsets of u, f, r per level.
+struct TailDesc {
+    int nlev;
+    int m;
+    int nx[kMaxLevels], ny[kMaxLevels], nz[kMaxLevels];
+    double s[kMaxLevels], diag[kMaxLevels], inv_diag[kMaxLevels];
+    unsigned off_u[kMaxLevels], off_f[kMaxLevels], off_r[kMaxLevels];
+    unsigned lds_bytes;
+};
+
 struct LevelDims {
     int nx, ny, nz;   // cells
     int hx;           // nx / 2 (split levels)
@@ -102,5 +113,20 @@ __device__ __forceinline__ void block_partials(double (&v)[K], double* part, uns
 }
 
 inline unsigned nblocks(size_t n, int bs = kBlock) { return (unsigned)((n + bs - 1) / bs); }
+
+// Reductions over grid vectors use at most kRedBlocks blocks, each owning one
+// contiguous chunk of the index space, so the finalize reads few partials.
+constexpr unsigned kRedBlocks = 4096;
+inline unsigned red_blocks(size_t n) {
+    const unsigned nb = nblocks(n);
+    return nb < kRedBlocks ? nb : kRedBlocks;
+}
+// chunk [lo, hi) of logical block b of nb over n items (chunks are multiples of blockDim)
+__device__ __forceinline__ void chunk_of(unsigned b, unsigned nb, unsigned n, unsigned* lo, unsigned* hi) {
+    const unsigned per = ((n + nb - 1) / nb + blockDim.x - 1) / blockDim.x * blockDim.x;
+    const unsigned l = b * per;
+    *lo = l < n ? l : n;
+    *hi = l + per < n ? l + per : n;
+}
 
 }  // namespace brd

@@ -22,6 +22,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <stdexcept>
 #include <string>
@@ -83,7 +84,7 @@ struct Plan {
     size_t esz = 8;
     int N = 0, restart = 30, ntiles = 0;
     BlobGeom geom{};
-    size_t off_grid[7]{};
+    size_t off_grid[8]{};
     size_t off_lvl[kMaxLevels][6]{};
     size_t off_cinv[4]{};
     size_t off_part = 0, part_cap = 0;
@@ -162,7 +163,7 @@ int make_plan(const blob_rd_params* p, Plan* P, std::string* why) {
         o = align_up(o + bytes);
         return r;
     };
-    for (int i = 0; i < 7; ++i) P->off_grid[i] = take(ncell * 8);
+    for (int i = 0; i < 8; ++i) P->off_grid[i] = take(ncell * 8);
     for (int l = 0; l < P->nlev - 1; ++l) {
         const size_t half = (size_t)P->lev[l].hx * P->lev[l].ny * P->lev[l].nz;
         for (int k = 0; k < 6; ++k) P->off_lvl[l][k] = take(half * P->esz);
@@ -279,6 +280,19 @@ struct blob_rd {
     double alg_bytes = 0.0;
     int inner_iters = 0;
     int last_iters[4] = {0, 0, 0, 0};  // CG iterations of the previous solve per (blobs, alpha == 0)
+    int tail_level[2] = {1 << 20, 1 << 20};  // first level of the LDS tail for FP32 / FP64 (>= nlev-1: none)
+    // CG iteration pairs captured as HIP graphs, keyed by (precision, blobs, alpha).
+    struct GraphEntry {
+        int esz;
+        bool blobs;
+        double alpha;
+        hipGraphExec_t exec;
+        double bytes_per_iter;
+    };
+    std::vector<GraphEntry> graphs;
+    hipStream_t cap_stream = nullptr;
+    bool use_graphs = true;
+    bool relax = true;  // relaxed inner tolerances in the Schur GMRES
 
     template <typename T>
     T* at(size_t off) const {
@@ -295,7 +309,7 @@ struct blob_rd {
 
 namespace {
 
-enum GridBuf { G_R = 0, G_P = 1, G_Q = 2, G_U = 3, G_G = 4, G_T1 = 5, G_T2 = 6 };
+enum GridBuf { G_R = 0, G_P = 1, G_Q = 2, G_U = 3, G_G = 4, G_T1 = 5, G_T2 = 6, G_P2 = 7 };
 
 __global__ void k_sc_init(Scalars* sc, int project, double inv_ncell, double eBe_inv, double rtol2, double abs2) {
     sc->rz = 0.0;
@@ -328,7 +342,21 @@ const double* select_cinv(blob_rd* H, double alpha) {
         if (H->cinv_alpha[k] == alpha) return H->at<double>(H->P.off_cinv[k]);
     const int slot = H->cinv_next;
     H->cinv_next = (H->cinv_next + 1) % 4;
-    if (H->cinv_used < 4) ++H->cinv_used;
+    if (H->cinv_used < 4) {
+        ++H->cinv_used;
+    } else {
+        // graphs captured for the evicted alpha point at this slot: drop them
+        HIPCHK(hipStreamSynchronize(H->st));
+        const double old = H->cinv_alpha[slot];
+        for (size_t i = 0; i < H->graphs.size();) {
+            if (H->graphs[i].alpha == old) {
+                (void)hipGraphExecDestroy(H->graphs[i].exec);
+                H->graphs.erase(H->graphs.begin() + i);
+            } else {
+                ++i;
+            }
+        }
+    }
     H->cinv_alpha[slot] = alpha;
     std::vector<double> inv = coarse_inverse(H->P.lev[H->P.nlev - 1], H->prm.D, alpha);
     double* dst = H->at<double>(H->P.off_cinv[slot]);
@@ -340,6 +368,53 @@ const double* select_cinv(blob_rd* H, double alpha) {
 // One V(2,2) cycle for alpha I - D L applied to the FP64 natural vector r
 // (mean_r removed when the scalars say so); the result is left in level 0's
 // u arrays (split layout).
+// First level of the single-work-group LDS tail: the coarsest levels whose
+// u, f, r arrays fit the LDS budget together.
+int tail_start(const Plan& P, size_t esz, size_t budget) {
+    const int L = P.nlev - 1;
+    int t = L;  // never used as is: the tail always includes one smoothing level
+    size_t bytes = 2 * (size_t)P.m * esz + 64;
+    for (int l = L - 1; l >= 0; --l) {
+        const size_t c = (size_t)P.lev[l].nx * P.lev[l].ny * P.lev[l].nz;
+        const size_t add = 3 * ((c * esz + 15) & ~(size_t)15);
+        if (bytes + add > budget || c > 16 * 1024) break;
+        bytes += add;
+        t = l;
+    }
+    return t;
+}
+
+template <typename T>
+TailDesc make_tail(const blob_rd* H, int t, double alpha) {
+    const Plan& P = H->P;
+    TailDesc d{};
+    const int L = P.nlev - 1;
+    d.nlev = L - t + 1;
+    d.m = P.m;
+    unsigned o = 0;
+    auto take = [&](size_t n) {
+        unsigned r = o;
+        o += (unsigned)((n * sizeof(T) + 15) & ~(size_t)15);
+        return r;
+    };
+    for (int k = 0; k < d.nlev; ++k) {
+        const LevelDims& ld = P.lev[t + k];
+        d.nx[k] = ld.nx;
+        d.ny[k] = ld.ny;
+        d.nz[k] = ld.nz;
+        const double s = H->prm.D / (ld.h * ld.h);
+        d.s[k] = s;
+        d.diag[k] = alpha + 6.0 * s;
+        d.inv_diag[k] = 1.0 / (alpha + 6.0 * s);
+        const size_t n = (size_t)ld.nx * ld.ny * ld.nz;
+        d.off_u[k] = take(n);
+        d.off_f[k] = take(n);
+        d.off_r[k] = (k + 1 < d.nlev) ? take(n) : 0;
+    }
+    d.lds_bytes = o;
+    return d;
+}
+
 template <typename T>
 void vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const double* cinv) {
     const Plan& P = H->P;
@@ -347,10 +422,42 @@ void vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const 
     hipStream_t st = H->st;
     auto lv = [&](int l, int k) { return H->at<T>(P.off_lvl[l][k]); };  // 0 u0, 1 u1, 2 f0, 3 f1, 4 r0, 5 r1
     const double D = H->prm.D;
+    const int t = H->tail_level[sizeof(T) == 4 ? 0 : 1];
     {
         const LevelDims& d = P.lev[0];
         const double s = D / (d.h * d.h);
         launch_enter<T>(st, r, lv(0, 2), lv(0, 3), lv(0, 0), d.nx, d.ny, d.nz, 1.0 / (alpha + 6.0 * s), sc);
+    }
+    if (t < L) {
+        for (int l = 0; l < t; ++l) {
+            const LevelDims& d = P.lev[l];
+            const double s = D / (d.h * d.h), diag = alpha + 6.0 * s;
+            launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc);
+            launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc);
+            launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc);
+            launch_resid_split<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), lv(l, 3), lv(l, 4), lv(l, 5), d.hx, d.ny, d.nz,
+                                  s, diag, sc);
+            const LevelDims& c = P.lev[l + 1];
+            const double sc_ = D / (c.h * c.h);
+            launch_restrict<T>(st, lv(l, 4), lv(l, 5), d.nx, d.ny, d.nz, lv(l + 1, 2), lv(l + 1, 3), lv(l + 1, 0), 0,
+                               1.0 / (alpha + 6.0 * sc_), sc);
+            H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * (3 * 1.5 + 3 + 1.125);
+        }
+        const TailDesc td = make_tail<T>(H, t, alpha);
+        launch_tail<T>(st, lv(t, 2), lv(t, 3), lv(t, 0), lv(t, 1), td, cinv, sc);
+        for (int l = t - 1; l >= 0; --l) {
+            const LevelDims& d = P.lev[l];
+            const double s = D / (d.h * d.h), diag = alpha + 6.0 * s;
+            launch_prolong<T>(st, lv(l + 1, 0), lv(l + 1, 1), 0, lv(l, 0), lv(l, 1), d.nx, d.ny, d.nz, sc);
+            launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc);
+            launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc);
+            launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc);
+            launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc);
+            H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * (4 * 1.5 + 2.125);
+        }
+        H->alg_bytes += (double)P.ncell * (8 + P.esz * 1.5);
+        H->vcycles += 1;
+        return;
     }
     for (int l = 0; l < L; ++l) {
         const LevelDims& d = P.lev[l];
@@ -422,7 +529,8 @@ PcgResult pcg(blob_rd* H, bool with_blobs, double alpha, const double* g, double
     const Plan& P = H->P;
     hipStream_t st = H->st;
     double* r = H->grid(G_R);
-    double* p = H->grid(G_P);
+    double* pbuf[2] = {H->grid(G_P), H->grid(G_P2)};
+    int parity = 0;
     double* q = H->grid(G_Q);
     const LevelDims& d = P.lev[0];
     const double s = H->prm.D / (d.h * d.h);
@@ -450,20 +558,57 @@ PcgResult pcg(blob_rd* H, bool with_blobs, double alpha, const double* g, double
     int chunk = hist > 0 ? std::min(hist, maxit) : std::min(4, maxit);
     int done_iters = 0;
     PcgResult res;
+    // One CG iteration; all scalars come from device memory, so the sequence
+    // is identical from one iteration to the next apart from the p parity.
+    auto iteration = [&](hipStream_t s_) {
+        hipStream_t keep = H->st;
+        H->st = s_;
+        double* po = pbuf[parity];
+        double* p = pbuf[parity ^ 1];
+        parity ^= 1;
+        launch_dir_apply<T>(s_, H->at<T>(P.off_lvl[0][0]), H->at<T>(P.off_lvl[0][1]), po, p, q, alpha, s, d.nx, d.ny,
+                            d.nz, H->part(), H->sc(), &np);
+        if (blobs) {
+            blob_term(H, p, q, H->sc());
+            launch_fin(s_, FIN_ALPHA, H->part(), np, H->sc(), H->nv(0), H->nv(1), P.N, H->inv_h3());
+        } else {
+            launch_fin(s_, FIN_ALPHA, H->part(), np, H->sc(), nullptr, nullptr, 0, 0.0);
+        }
+        launch_update(s_, x, r, p, q, P.ncell, H->part(), H->sc(), &np);
+        launch_fin(s_, FIN_UPDATE, H->part(), np, H->sc(), nullptr, nullptr, 0, 0.0);
+        precond_zdots<T>(H, alpha, r, q, cinv);
+        H->alg_bytes += (double)P.ncell * (P.esz + 24 + 48);
+        H->st = keep;
+    };
+    blob_rd::GraphEntry* ge = nullptr;
+    if (H->use_graphs && x == H->grid(G_U)) {
+        for (auto& g : H->graphs)
+            if (g.esz == (int)sizeof(T) && g.blobs == blobs && g.alpha == alpha) ge = &g;
+        if (!ge) {
+            if (!H->cap_stream) HIPCHK(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
+            const double b0 = H->alg_bytes;
+            const int v0 = H->vcycles;
+            HIPCHK(hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeThreadLocal));
+            iteration(H->cap_stream);
+            iteration(H->cap_stream);
+            hipGraph_t graph;
+            HIPCHK(hipStreamEndCapture(H->cap_stream, &graph));
+            hipGraphExec_t exec;
+            HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            (void)hipGraphDestroy(graph);
+            H->graphs.push_back({(int)sizeof(T), blobs, alpha, exec, 0.5 * (H->alg_bytes - b0)});
+            ge = &H->graphs.back();
+            H->alg_bytes = b0;
+            H->vcycles = v0;
+        }
+    }
     for (;;) {
-        for (int k = 0; k < chunk; ++k) {
-            launch_dir<T>(st, H->at<T>(P.off_lvl[0][0]), H->at<T>(P.off_lvl[0][1]), p, d.nx, d.ny, d.nz, H->sc());
-            launch_applyA(st, p, q, alpha, s, d.nx, d.ny, d.nz, H->part(), H->sc(), &np);
-            if (blobs) {
-                blob_term(H, p, q, H->sc());
-                launch_fin(st, FIN_ALPHA, H->part(), np, H->sc(), H->nv(0), H->nv(1), P.N, H->inv_h3());
-            } else {
-                launch_fin(st, FIN_ALPHA, H->part(), np, H->sc(), nullptr, nullptr, 0, 0.0);
-            }
-            launch_update(st, x, r, p, q, P.ncell, H->part(), H->sc(), &np);
-            launch_fin(st, FIN_UPDATE, H->part(), np, H->sc(), nullptr, nullptr, 0, 0.0);
-            precond_zdots<T>(H, alpha, r, q, cinv);
-            H->alg_bytes += (double)P.ncell * (P.esz + 24 + 16 + 48);
+        if (ge) {
+            for (int k = 0; k < chunk; k += 2) HIPCHK(hipGraphLaunch(ge->exec, st));
+        } else {
+            // an even number of iterations keeps the p parity aligned with the graphs
+            chunk += chunk & 1;
+            for (int k = 0; k < chunk; ++k) iteration(st);
         }
         sync_read(H, H->hsc, H->sc(), sizeof(Scalars));
         done_iters = H->hsc->iters;
@@ -481,6 +626,10 @@ PcgResult pcg(blob_rd* H, bool with_blobs, double alpha, const double* g, double
     }
     res.iters = H->hsc->iters;
     hist = res.iters;
+    if (ge) {
+        H->alg_bytes += ge->bytes_per_iter * res.iters;
+        H->vcycles += res.iters;
+    }
     res.status = H->hsc->status;
     res.rr = H->hsc->rr;
     res.gg = H->hsc->gg;
@@ -515,12 +664,14 @@ int reactive_solve(blob_rd* H, double alpha, const double* g, double* c, blob_rd
     int total = 0, refinements = 0;
     double rn = 0.0, gn = 1.0;
     bool ok = false;
+    double* x = H->grid(G_U);
+    launch_axpby(H->st, x, c, H->P.ncell, 0.0, 1.0);
     for (int pass = 0; pass < 4; ++pass) {
         // CG aims a little below the target so the true residual lands under it.
-        PcgResult pr = pcg<T>(H, true, alpha, g, c, false, 0.5 * rtol, 0.0, default_maxit(H) - total);
+        PcgResult pr = pcg<T>(H, true, alpha, g, x, false, 0.5 * rtol, 0.0, default_maxit(H) - total);
         total += pr.iters;
         if (pr.status) throw Err(BLOB_RD_ENUMERIC, "non-finite value or breakdown in CG");
-        true_residual(H, true, alpha, g, c, H->grid(G_T1), &rn, &gn);
+        true_residual(H, true, alpha, g, x, H->grid(G_T1), &rn, &gn);
         if (gn == 0.0) gn = 1.0;
         if (rn <= rtol * gn) {
             ok = true;
@@ -529,6 +680,7 @@ int reactive_solve(blob_rd* H, double alpha, const double* g, double* c, blob_rd
         if (total >= default_maxit(H)) break;
         ++refinements;
     }
+    launch_axpby(H->st, c, x, H->P.ncell, 0.0, 1.0);
     if (stt) {
         stt->outer_iters = total;
         stt->rel_resid = rn / gn;
@@ -618,13 +770,20 @@ SaddleInfo saddle_solve(blob_rd* H, double alpha, const double* g, const double*
         }
         if (info.gmres_iters >= maxit) break;
         int k = 0;
+        double res_prev = H->hgs->res;
         for (; k < m && info.gmres_iters < maxit; ++k) {
-            schur_apply<T>(H, alpha, V + (size_t)k * N, V + (size_t)(k + 1) * N, inner_rtol);
+            // Inexact Krylov: the matvec may be less accurate as the residual falls
+            // (Bouras-Fraysse / Simoncini-Szyld relaxation); the FP64 saddle residual
+            // and refinement of the caller guard the final answer.
+            double tau = inner_rtol;
+            if (H->relax && res_prev > 0.0) tau = std::min(1e-2, std::max(inner_rtol, 0.1 * atol_schur / res_prev));
+            schur_apply<T>(H, alpha, V + (size_t)k * N, V + (size_t)(k + 1) * N, tau);
             launch_gmres_arnoldi(st, V, Hm, H->at<double>(P.off_cs), H->at<double>(P.off_sn),
                                  H->at<double>(P.off_gv), N, k, m, H->gs());
             ++info.gmres_iters;
             sync_read(H, H->hgs, H->gs(), sizeof(GmresScalars));
             if (H->hgs->status) throw Err(BLOB_RD_ENUMERIC, "GMRES breakdown");
+            res_prev = H->hgs->res;
             if (H->hgs->res <= atol_schur || H->hgs->hk1 == 0.0) {
                 ++k;
                 break;
@@ -646,9 +805,10 @@ SaddleInfo saddle_solve(blob_rd* H, double alpha, const double* g, const double*
     launch_spread(st, lam, 0.0, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
                   H->at<int>(P.off_offsets), H->at<int>(P.off_perm), g, gg, -H->inv_h3(), 0, nullptr);
     H->alg_bytes += (double)P.ncell * 16;
-    pr = pcg<T>(H, false, alpha, gg, c, true, 0.0, final_rtol_abs, inner_maxit(H));
+    pr = pcg<T>(H, false, alpha, gg, u, true, 0.0, final_rtol_abs, inner_maxit(H));
     if (pr.status) throw Err(BLOB_RD_ENUMERIC, "non-finite value in Poisson solve");
     H->inner_iters += pr.iters;
+    launch_axpby(st, c, u, P.ncell, 0.0, 1.0);
     if (alpha == 0.0) {
         // J c + cbar = phi  ->  cbar = mean(phi - J c)
         double* jc = H->nv(6);
@@ -809,6 +969,8 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
     }
     H->prm = *p;
     H->st = (hipStream_t)p->stream;
+    if (const char* g = std::getenv("BLOB_RD_GRAPHS")) H->use_graphs = std::atoi(g) != 0;
+    if (const char* g = std::getenv("BLOB_RD_RELAX")) H->relax = std::atoi(g) != 0;
     // Align the workspace base to 256 bytes.
     uintptr_t base = (uintptr_t)p->workspace;
     H->ws = (char*)((base + 255) & ~(uintptr_t)255);
@@ -823,6 +985,7 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
         HIPCHK(hipMemsetAsync(H->at<int>(P.off_cursor), 0, (size_t)P.ntiles * 4, st));
         HIPCHK(hipMemsetAsync(H->grid(G_Q), 0, P.ncell * 8, st));
         HIPCHK(hipMemsetAsync(H->grid(G_P), 0, P.ncell * 8, st));
+        HIPCHK(hipMemsetAsync(H->grid(G_P2), 0, P.ncell * 8, st));
         if (N > 0) {
             // Validate inputs on the host before any kernel derives indices from them.
             std::vector<double> hq((size_t)N * 3), hk;
@@ -859,6 +1022,22 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
         select_cinv(H, 0.0);
+        // LDS budget of the coarse tail: the device limit per block, capped at 160 KiB.
+        int dev = 0, lds = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        const size_t budget = std::min<size_t>((size_t)lds, 160 * 1024);
+        H->tail_level[0] = tail_start(P, 4, budget);
+        H->tail_level[1] = tail_start(P, 8, budget);
+        const int Lc = P.nlev - 1;
+        if (H->tail_level[0] < Lc) {
+            const size_t need = make_tail<float>(H, H->tail_level[0], 0.0).lds_bytes;
+            if (need > 48 * 1024) HIPCHK(tail_set_lds<float>(need));
+        }
+        if (H->tail_level[1] < Lc) {
+            const size_t need = make_tail<double>(H, H->tail_level[1], 0.0).lds_bytes;
+            if (need > 48 * 1024) HIPCHK(tail_set_lds<double>(need));
+        }
     } catch (const Err& e) {
         g_last_error = e.what();
         blob_rd_destroy(H);
@@ -870,6 +1049,9 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
 
 int blob_rd_destroy(blob_rd_t H) {
     if (!H) return BLOB_RD_OK;
+    for (auto& g : H->graphs) (void)hipGraphExecDestroy(g.exec);
+    H->graphs.clear();
+    if (H->cap_stream) (void)hipStreamDestroy(H->cap_stream);
     if (H->hsc) (void)hipHostFree(H->hsc);
     if (H->hgs) (void)hipHostFree(H->hgs);
     if (H->hbuf) (void)hipHostFree(H->hbuf);

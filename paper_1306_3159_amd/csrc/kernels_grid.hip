@@ -29,18 +29,18 @@ __global__ void __launch_bounds__(kBlock) k_applyA(const double* __restrict__ p,
                                                    double alpha, double s, int nx, int ny, int nz, unsigned ncell,
                                                    double* part, const Scalars* sc) {
     if (sc && sc->done) return;
-    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-    const unsigned idx = b * blockDim.x + threadIdx.x;
+    unsigned lo, hi;
+    chunk_of(xcd_block(blockIdx.x, gridDim.x), gridDim.x, ncell, &lo, &hi);
     double v[2] = {0.0, 0.0};
-    if (idx < ncell) {
+    for (unsigned idx = lo + threadIdx.x; idx < hi; idx += blockDim.x) {
         const int X = idx % nx;
         const unsigned t = idx / nx;
         const int Y = t % ny, Z = t / ny;
         double c;
         const double y = stencil_A(p, X, Y, Z, nx, ny, nz, alpha, s, idx, &c);
         q[idx] = y;
-        v[0] = c * y;
-        v[1] = y;
+        v[0] += c * y;
+        v[1] += y;
     }
     if (part) block_partials<2>(v, part, gridDim.x, blockIdx.x);
 }
@@ -48,10 +48,64 @@ __global__ void __launch_bounds__(kBlock) k_applyA(const double* __restrict__ p,
 void launch_applyA(hipStream_t st, const double* p, double* q, double alpha, double s, int nx, int ny, int nz,
                    double* part, const Scalars* sc, unsigned* np) {
     const unsigned n = (unsigned)nx * ny * nz;
-    const unsigned nb = nblocks(n);
+    const unsigned nb = part ? red_blocks(n) : nblocks(n);
     hipLaunchKernelGGL(k_applyA, dim3(nb), dim3(kBlock), 0, st, p, q, alpha, s, nx, ny, nz, n, part, sc);
     if (np) *np = nb;
 }
+
+// Fused CG direction update and operator apply:
+// p_new = z + shift + beta p_old at the cell and its 6 neighbours (z split of
+// type T), q = alpha p_new - D L p_new, partials (p_new . q, sum q).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dir_apply(const T* __restrict__ z0, const T* __restrict__ z1,
+                                                      const double* __restrict__ po, double* __restrict__ pn,
+                                                      double* __restrict__ q, double alpha, double s, int nx, int ny,
+                                                      int nz, unsigned ncell, double* part, const Scalars* sc) {
+    if (sc->done) return;
+    const double beta = sc->beta, shift = sc->shift;
+    const int hx = nx >> 1;
+    unsigned lo, hi;
+    chunk_of(xcd_block(blockIdx.x, gridDim.x), gridDim.x, ncell, &lo, &hi);
+    double v[2] = {0.0, 0.0};
+    const long long sxy = (long long)nx * ny;
+    for (unsigned idx = lo + threadIdx.x; idx < hi; idx += blockDim.x) {
+        const int X = idx % nx;
+        const unsigned t = idx / nx;
+        const int Y = t % ny, Z = t / ny;
+        auto pnew = [&](int x, int y, int z, long long i) {
+            const size_t j = ((size_t)z * ny + y) * hx + (x >> 1);
+            const double zv = (((x + y + z) & 1) ? (double)z1[j] : (double)z0[j]) + shift;
+            return beta == 0.0 ? zv : zv + beta * po[i];
+        };
+        const long long i = (long long)idx;
+        const int xm = wrapi(X - 1, nx), xp = wrapi(X + 1, nx), ym = wrapi(Y - 1, ny), yp = wrapi(Y + 1, ny);
+        const int zm = wrapi(Z - 1, nz), zp = wrapi(Z + 1, nz);
+        const double c = pnew(X, Y, Z, i);
+        const double a = pnew(xm, Y, Z, i - X + xm) + pnew(xp, Y, Z, i - X + xp);
+        const double b = pnew(X, ym, Z, i + (long long)(ym - Y) * nx) + pnew(X, yp, Z, i + (long long)(yp - Y) * nx);
+        const double d = pnew(X, Y, zm, i + (long long)(zm - Z) * sxy) + pnew(X, Y, zp, i + (long long)(zp - Z) * sxy);
+        const double y = alpha * c - s * (a + b + d - 6.0 * c);
+        pn[idx] = c;
+        q[idx] = y;
+        v[0] += c * y;
+        v[1] += y;
+    }
+    block_partials<2>(v, part, gridDim.x, blockIdx.x);
+}
+
+template <typename T>
+void launch_dir_apply(hipStream_t st, const T* z0, const T* z1, const double* po, double* pn, double* q, double alpha,
+                      double s, int nx, int ny, int nz, double* part, const Scalars* sc, unsigned* np) {
+    const unsigned n = (unsigned)nx * ny * nz;
+    const unsigned nb = red_blocks(n);
+    hipLaunchKernelGGL(k_dir_apply<T>, dim3(nb), dim3(kBlock), 0, st, z0, z1, po, pn, q, alpha, s, nx, ny, nz, n,
+                       part, sc);
+    *np = nb;
+}
+template void launch_dir_apply<float>(hipStream_t, const float*, const float*, const double*, double*, double*,
+                                      double, double, int, int, int, double*, const Scalars*, unsigned*);
+template void launch_dir_apply<double>(hipStream_t, const double*, const double*, const double*, double*, double*,
+                                       double, double, int, int, int, double*, const Scalars*, unsigned*);
 
 void launch_applyA_plain(hipStream_t st, const double* x, double* y, double alpha, double s, int nx, int ny,
                          int nz) {
@@ -65,10 +119,10 @@ __global__ void __launch_bounds__(kBlock) k_residual64(const double* __restrict_
                                                        const double* __restrict__ q0, double* __restrict__ r,
                                                        double alpha, double s, int nx, int ny, int nz,
                                                        unsigned ncell, double* part) {
-    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-    const unsigned idx = b * blockDim.x + threadIdx.x;
+    unsigned lo, hi;
+    chunk_of(xcd_block(blockIdx.x, gridDim.x), gridDim.x, ncell, &lo, &hi);
     double v[3] = {0.0, 0.0, 0.0};
-    if (idx < ncell) {
+    for (unsigned idx = lo + threadIdx.x; idx < hi; idx += blockDim.x) {
         double ax = 0.0;
         if (x) {
             const int X = idx % nx;
@@ -81,9 +135,9 @@ __global__ void __launch_bounds__(kBlock) k_residual64(const double* __restrict_
         const double gv = g[idx];
         const double rv = gv - ax;
         r[idx] = rv;
-        v[0] = rv * rv;
-        v[1] = rv;
-        v[2] = gv * gv;
+        v[0] += rv * rv;
+        v[1] += rv;
+        v[2] += gv * gv;
     }
     block_partials<3>(v, part, gridDim.x, blockIdx.x);
 }
@@ -91,7 +145,7 @@ __global__ void __launch_bounds__(kBlock) k_residual64(const double* __restrict_
 void launch_residual64(hipStream_t st, const double* g, const double* x, double* r, double alpha, double s, int nx,
                        int ny, int nz, double* part, unsigned* np) {
     const unsigned n = (unsigned)nx * ny * nz;
-    const unsigned nb = nblocks(n);
+    const unsigned nb = red_blocks(n);
     hipLaunchKernelGGL(k_residual64, dim3(nb), dim3(kBlock), 0, st, g, x, (const double*)nullptr, r, alpha, s, nx,
                        ny, nz, n, part);
     *np = nb;
@@ -99,7 +153,7 @@ void launch_residual64(hipStream_t st, const double* g, const double* x, double*
 
 void launch_residual_from_q(hipStream_t st, const double* g, const double* q0, double* r, size_t n, double* part,
                             unsigned* np) {
-    const unsigned nb = nblocks(n);
+    const unsigned nb = red_blocks(n);
     hipLaunchKernelGGL(k_residual64, dim3(nb), dim3(kBlock), 0, st, g, (const double*)nullptr, q0, r, 0.0, 0.0, 1,
                        1, 1, (unsigned)n, part);
     *np = nb;
@@ -141,23 +195,23 @@ __global__ void __launch_bounds__(kBlock) k_update(double* __restrict__ x, doubl
                                                    const double* __restrict__ p, const double* __restrict__ q,
                                                    unsigned n, double* part, const Scalars* sc) {
     if (sc->done) return;
-    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-    const unsigned idx = b * blockDim.x + threadIdx.x;
+    unsigned lo, hi;
+    chunk_of(xcd_block(blockIdx.x, gridDim.x), gridDim.x, n, &lo, &hi);
     double v[2] = {0.0, 0.0};
-    if (idx < n) {
-        const double a = sc->alpha;
+    const double a = sc->alpha;
+    for (unsigned idx = lo + threadIdx.x; idx < hi; idx += blockDim.x) {
         x[idx] += a * p[idx];
         const double rv = r[idx] - a * q[idx];
         r[idx] = rv;
-        v[0] = rv * rv;
-        v[1] = rv;
+        v[0] += rv * rv;
+        v[1] += rv;
     }
     block_partials<2>(v, part, gridDim.x, blockIdx.x);
 }
 
 void launch_update(hipStream_t st, double* x, double* r, const double* p, const double* q, size_t n, double* part,
                    const Scalars* sc, unsigned* np) {
-    const unsigned nb = nblocks(n);
+    const unsigned nb = red_blocks(n);
     hipLaunchKernelGGL(k_update, dim3(nb), dim3(kBlock), 0, st, x, r, p, q, (unsigned)n, part, sc);
     *np = nb;
 }
@@ -167,16 +221,16 @@ __global__ void __launch_bounds__(kBlock) k_zdots(const T* __restrict__ z0, cons
                                                   const double* __restrict__ r, const double* __restrict__ q, int nx,
                                                   int ny, unsigned ncell, double* part, const Scalars* sc) {
     if (sc->done) return;
-    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-    const unsigned idx = b * blockDim.x + threadIdx.x;
+    unsigned lo, hi;
+    chunk_of(xcd_block(blockIdx.x, gridDim.x), gridDim.x, ncell, &lo, &hi);
     double v[3] = {0.0, 0.0, 0.0};
-    if (idx < ncell) {
+    for (unsigned idx = lo + threadIdx.x; idx < hi; idx += blockDim.x) {
         const int X = idx % nx;
         const unsigned t = idx / nx;
         const double zv = split_at(z0, z1, X, (int)(t % ny), (int)(t / ny), nx >> 1, ny);
-        v[0] = zv;
-        v[1] = zv * r[idx];
-        v[2] = zv * q[idx];
+        v[0] += zv;
+        v[1] += zv * r[idx];
+        v[2] += zv * q[idx];
     }
     block_partials<3>(v, part, gridDim.x, blockIdx.x);
 }
@@ -185,7 +239,7 @@ template <typename T>
 void launch_zdots(hipStream_t st, const T* z0, const T* z1, const double* r, const double* q, int nx, int ny, int nz,
                   double* part, const Scalars* sc, unsigned* np) {
     const unsigned n = (unsigned)nx * ny * nz;
-    const unsigned nb = nblocks(n);
+    const unsigned nb = red_blocks(n);
     hipLaunchKernelGGL(k_zdots<T>, dim3(nb), dim3(kBlock), 0, st, z0, z1, r, q, nx, ny, n, part, sc);
     *np = nb;
 }
@@ -217,17 +271,18 @@ template void launch_split_to_nat<float>(hipStream_t, const float*, const float*
 template void launch_split_to_nat<double>(hipStream_t, const double*, const double*, double*, int, int, int, double);
 
 __global__ void __launch_bounds__(kBlock) k_norm_partials(const double* __restrict__ v, unsigned n, double* part) {
-    const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned lo, hi;
+    chunk_of(blockIdx.x, gridDim.x, n, &lo, &hi);
     double a[2] = {0.0, 0.0};
-    if (idx < n) {
-        a[0] = v[idx];
-        a[1] = v[idx] * v[idx];
+    for (unsigned idx = lo + threadIdx.x; idx < hi; idx += blockDim.x) {
+        a[0] += v[idx];
+        a[1] += v[idx] * v[idx];
     }
     block_partials<2>(a, part, gridDim.x, blockIdx.x);
 }
 
 void launch_norm_partials(hipStream_t st, const double* v, size_t n, double* part, unsigned* np) {
-    const unsigned nb = nblocks(n);
+    const unsigned nb = red_blocks(n);
     hipLaunchKernelGGL(k_norm_partials, dim3(nb), dim3(kBlock), 0, st, v, (unsigned)n, part);
     *np = nb;
 }

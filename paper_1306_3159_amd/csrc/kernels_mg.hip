@@ -242,17 +242,239 @@ __global__ void __launch_bounds__(kMaxCoarse) k_coarse(const T* __restrict__ f, 
     __shared__ double fs[kMaxCoarse];
     for (int j = threadIdx.x; j < m; j += blockDim.x) fs[j] = (double)f[j];
     __syncthreads();
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int i = wv; i < m; i += nw) {
         const double* row = cinv + (size_t)i * m;
         double acc = 0.0;
-        for (int j = 0; j < m; ++j) acc += row[j] * fs[j];
-        u[i] = (T)acc;
+        for (int j = lane; j < m; j += 64) acc += row[j] * fs[j];
+        acc = wave_sum(acc);
+        if (lane == 0) u[i] = (T)acc;
     }
 }
 
 template <typename T>
 void launch_coarse(hipStream_t st, const T* f, T* u, const double* cinv, int m, const Scalars* sc) {
     hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(kMaxCoarse), 0, st, f, u, cinv, m, sc);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse tail: the whole V-cycle below level t in one work-group with every
+// level in LDS (natural layout [z][y][x]). It performs exactly the operations
+// of the per-level kernels, in the same order and with the same summation
+// order, so it is interchangeable with them: zero initial guess, R B R B
+// pre-smoothing, residual, full weighting, coarse dense solve, trilinear
+// correction, B R B R post-smoothing.
+constexpr int kTailPer = 16;  // max cells per thread in a tail level (16 * 1024 cells)
+
+// Packed cell coordinates (x | y << 10 | z << 20) of the cells a thread owns
+// in one level, for the full grid and for each colour. Loops over them are
+// unrolled to compile-time indices so the arrays stay in registers.
+struct TailCells {
+    int n_all, n_c0, n_c1;
+    int all[kTailPer], c0[kTailPer / 2], c1[kTailPer / 2];
+};
+
+__device__ __forceinline__ void tail_cells(TailCells& tc, int nx, int ny, int nz) {
+    const int n = nx * ny * nz, hx = nx >> 1, nh = hx * ny * nz;
+    tc.n_all = tc.n_c0 = tc.n_c1 = 0;
+#pragma unroll
+    for (int k = 0; k < kTailPer; ++k) {
+        const int j = threadIdx.x + k * blockDim.x;
+        const int x = j % nx, t = j / nx, y = t % ny, z = t / ny;
+        tc.all[k] = x | (y << 10) | (z << 20);
+        if (j < n) tc.n_all = k + 1;
+    }
+#pragma unroll
+    for (int k = 0; k < kTailPer / 2; ++k) {
+        const int j = threadIdx.x + k * blockDim.x;
+        const int i = j % hx, t = j / hx, y = t % ny, z = t / ny;
+        tc.c0[k] = (2 * i + ((y + z) & 1)) | (y << 10) | (z << 20);
+        tc.c1[k] = (2 * i + (((y + z) & 1) ^ 1)) | (y << 10) | (z << 20);
+        if (j < nh) tc.n_c0 = tc.n_c1 = k + 1;
+    }
+}
+
+#define TAIL_X(p) ((p) & 1023)
+#define TAIL_Y(p) (((p) >> 10) & 1023)
+#define TAIL_Z(p) ((p) >> 20)
+
+template <typename T>
+__device__ __forceinline__ T tail_nb(const T* u, int x, int y, int z, int nx, int ny, int nz) {
+    const int row = (z * ny + y) * nx;
+    const T a = u[row + wrapi(x - 1, nx)] + u[row + wrapi(x + 1, nx)];
+    const T b = u[(z * ny + wrapi(y - 1, ny)) * nx + x] + u[(z * ny + wrapi(y + 1, ny)) * nx + x];
+    const T c = u[(wrapi(z - 1, nz) * ny + y) * nx + x] + u[(wrapi(z + 1, nz) * ny + y) * nx + x];
+    return (a + b) + c;
+}
+
+template <typename T>
+__device__ __forceinline__ void tail_gs(T* u, const T* f, const TailCells& tc, int nx, int ny, int nz, int color, T s,
+                                        T inv_diag) {
+    const int n = color ? tc.n_c1 : tc.n_c0;
+#pragma unroll
+    for (int k = 0; k < kTailPer / 2; ++k) {
+        if (k < n) {
+            const int p = color ? tc.c1[k] : tc.c0[k];
+            const int x = TAIL_X(p), y = TAIL_Y(p), z = TAIL_Z(p);
+            const int j = (z * ny + y) * nx + x;
+            u[j] = (f[j] + s * tail_nb(u, x, y, z, nx, ny, nz)) * inv_diag;
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kFinBlock) k_tail(const T* __restrict__ f0g, const T* __restrict__ f1g,
+                                                    T* __restrict__ u0g, T* __restrict__ u1g, TailDesc d,
+                                                    const double* __restrict__ cinv, const Scalars* sc) {
+    if (sc && sc->done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+#define TAIL_U(l) reinterpret_cast<T*>(smem + d.off_u[l])
+#define TAIL_F(l) reinterpret_cast<T*>(smem + d.off_f[l])
+#define TAIL_R(l) reinterpret_cast<T*>(smem + d.off_r[l])
+    const int L = d.nlev - 1;  // coarsest, natural, m cells
+    TailCells tc;
+    tail_cells(tc, d.nx[0], d.ny[0], d.nz[0]);
+    {
+        const int nx = d.nx[0], ny = d.ny[0], hx = nx >> 1;
+        T* F0 = TAIL_F(0);
+#pragma unroll
+        for (int k = 0; k < kTailPer / 2; ++k) {
+            if (k < tc.n_c0) {
+                const int p0 = tc.c0[k], p1 = tc.c1[k];
+                const int y = TAIL_Y(p0), z = TAIL_Z(p0);
+                const int j = (z * ny + y) * hx + (TAIL_X(p0) >> 1);
+                F0[(z * ny + y) * nx + TAIL_X(p0)] = f0g[j];
+                F0[(z * ny + y) * nx + TAIL_X(p1)] = f1g[j];
+            }
+        }
+    }
+    __syncthreads();
+    for (int l = 0; l < L; ++l) {
+        const int nx = d.nx[l], ny = d.ny[l], nz = d.nz[l];
+        if (l > 0) tail_cells(tc, nx, ny, nz);
+        T* U = TAIL_U(l);
+        T* F = TAIL_F(l);
+        T* R = TAIL_R(l);
+        const T s = (T)d.s[l], idg = (T)d.inv_diag[l], dg = (T)d.diag[l];
+#pragma unroll
+        for (int k = 0; k < kTailPer; ++k)
+            if (k < tc.n_all) {
+                const int p = tc.all[k];
+                U[(TAIL_Z(p) * ny + TAIL_Y(p)) * nx + TAIL_X(p)] = (T)0;
+            }
+        __syncthreads();
+        tail_gs(U, F, tc, nx, ny, nz, 0, s, idg);
+        tail_gs(U, F, tc, nx, ny, nz, 1, s, idg);
+        tail_gs(U, F, tc, nx, ny, nz, 0, s, idg);
+        tail_gs(U, F, tc, nx, ny, nz, 1, s, idg);
+#pragma unroll
+        for (int k = 0; k < kTailPer; ++k)
+            if (k < tc.n_all) {
+                const int p = tc.all[k];
+                const int x = TAIL_X(p), y = TAIL_Y(p), z = TAIL_Z(p);
+                const int j = (z * ny + y) * nx + x;
+                R[j] = F[j] - (dg * U[j] - s * tail_nb(U, x, y, z, nx, ny, nz));
+            }
+        __syncthreads();
+        const int cx = nx >> 1, cy = ny >> 1, nc = cx * cy * (nz >> 1);
+        T* Fc = TAIL_F(l + 1);
+        const T w0 = (T)0.125, w1 = (T)0.375;
+        for (int j = threadIdx.x; j < nc; j += blockDim.x) {
+            const int X = j % cx, t = j / cx, Y = t % cy, Z = t / cy;
+            const int x0 = wrapi(2 * X - 1, nx), x1 = 2 * X, x2 = 2 * X + 1, x3 = wrapi(2 * X + 2, nx);
+            T acc = 0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int z = wrapi(2 * Z - 1 + c, nz);
+                T accb = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const T* rr = R + (z * ny + wrapi(2 * Y - 1 + b, ny)) * nx;
+                    const T acca = ((w0 * rr[x0] + w1 * rr[x1]) + w1 * rr[x2]) + w0 * rr[x3];
+                    accb += (b == 0 || b == 3 ? w0 : w1) * acca;
+                }
+                acc += (c == 0 || c == 3 ? w0 : w1) * accb;
+            }
+            Fc[j] = acc;
+        }
+        __syncthreads();
+    }
+    {
+        // one wave per row of the dense inverse: coalesced loads, wave reduction
+        const T* Fl = TAIL_F(L);
+        T* Ul = TAIL_U(L);
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        for (int i = wv; i < d.m; i += nw) {
+            const double* row = cinv + (size_t)i * d.m;
+            double acc = 0.0;
+            for (int j = lane; j < d.m; j += 64) acc += row[j] * (double)Fl[j];
+            acc = wave_sum(acc);
+            if (lane == 0) Ul[i] = (T)acc;
+        }
+    }
+    __syncthreads();
+    for (int l = L - 1; l >= 0; --l) {
+        const int nx = d.nx[l], ny = d.ny[l], nz = d.nz[l];
+        tail_cells(tc, nx, ny, nz);
+        const int cx = nx >> 1, cy = ny >> 1, cz = nz >> 1;
+        const T* C = TAIL_U(l + 1);
+        T* U = TAIL_U(l);
+        const T* F = TAIL_F(l);
+#pragma unroll
+        for (int k = 0; k < kTailPer; ++k)
+            if (k < tc.n_all) {
+                const int p = tc.all[k];
+                const int x = TAIL_X(p), y = TAIL_Y(p), z = TAIL_Z(p);
+                const int I0 = x >> 1, I1 = wrapi((x & 1) ? I0 + 1 : I0 - 1, cx);
+                const int J0 = y >> 1, J1 = wrapi((y & 1) ? J0 + 1 : J0 - 1, cy);
+                const int K0 = z >> 1, K1 = wrapi((z & 1) ? K0 + 1 : K0 - 1, cz);
+                const T* c00 = C + (K0 * cy + J0) * cx;
+                const T* c10 = C + (K0 * cy + J1) * cx;
+                const T* c01 = C + (K1 * cy + J0) * cx;
+                const T* c11 = C + (K1 * cy + J1) * cx;
+                const T a00 = (T)0.75 * c00[I0] + (T)0.25 * c00[I1];
+                const T a10 = (T)0.75 * c10[I0] + (T)0.25 * c10[I1];
+                const T a01 = (T)0.75 * c01[I0] + (T)0.25 * c01[I1];
+                const T a11 = (T)0.75 * c11[I0] + (T)0.25 * c11[I1];
+                U[(z * ny + y) * nx + x] +=
+                    (T)0.75 * ((T)0.75 * a00 + (T)0.25 * a10) + (T)0.25 * ((T)0.75 * a01 + (T)0.25 * a11);
+            }
+        __syncthreads();
+        const T s = (T)d.s[l], idg = (T)d.inv_diag[l];
+        tail_gs(U, F, tc, nx, ny, nz, 1, s, idg);
+        tail_gs(U, F, tc, nx, ny, nz, 0, s, idg);
+        tail_gs(U, F, tc, nx, ny, nz, 1, s, idg);
+        tail_gs(U, F, tc, nx, ny, nz, 0, s, idg);
+    }
+    {
+        const int nx = d.nx[0], ny = d.ny[0], hx = nx >> 1;
+        const T* U0 = TAIL_U(0);
+#pragma unroll
+        for (int k = 0; k < kTailPer / 2; ++k) {
+            if (k < tc.n_c0) {
+                const int p0 = tc.c0[k], p1 = tc.c1[k];
+                const int y = TAIL_Y(p0), z = TAIL_Z(p0);
+                const int j = (z * ny + y) * hx + (TAIL_X(p0) >> 1);
+                u0g[j] = U0[(z * ny + y) * nx + TAIL_X(p0)];
+                u1g[j] = U0[(z * ny + y) * nx + TAIL_X(p1)];
+            }
+        }
+    }
+#undef TAIL_U
+#undef TAIL_F
+#undef TAIL_R
+}
+
+template <typename T>
+void launch_tail(hipStream_t st, const T* f0, const T* f1, T* u0, T* u1, const TailDesc& d, const double* cinv,
+                 const Scalars* sc) {
+    hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(kFinBlock), d.lds_bytes, st, f0, f1, u0, u1, d, cinv, sc);
+}
+
+template <typename T>
+hipError_t tail_set_lds(size_t bytes) {
+    return hipFuncSetAttribute((const void*)k_tail<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 #define BRD_INST(T)                                                                                                \
@@ -264,7 +486,10 @@ void launch_coarse(hipStream_t st, const T* f, T* u, const double* cinv, int m, 
     template void launch_restrict<T>(hipStream_t, const T*, const T*, int, int, int, T*, T*, T*, int, double,       \
                                      const Scalars*);                                                               \
     template void launch_prolong<T>(hipStream_t, const T*, const T*, int, T*, T*, int, int, int, const Scalars*);  \
-    template void launch_coarse<T>(hipStream_t, const T*, T*, const double*, int, const Scalars*);
+    template void launch_coarse<T>(hipStream_t, const T*, T*, const double*, int, const Scalars*);             \
+    template void launch_tail<T>(hipStream_t, const T*, const T*, T*, T*, const TailDesc&, const double*,         \
+                                 const Scalars*);                                                                   \
+    template hipError_t tail_set_lds<T>(size_t);
 
 BRD_INST(float)
 BRD_INST(double)

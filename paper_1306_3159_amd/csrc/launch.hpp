@@ -22,6 +22,10 @@ void launch_residual_from_q(hipStream_t st, const double* g, const double* q0, d
 template <typename T>
 void launch_dir(hipStream_t st, const T* z0, const T* z1, double* p, int nx, int ny, int nz,
                 const Scalars* sc);
+// p_new = z + shift + beta p_old (on the fly at 7 points), q = A p_new ; partials (p.q, sum q)
+template <typename T>
+void launch_dir_apply(hipStream_t st, const T* z0, const T* z1, const double* po, double* pn, double* q, double alpha,
+                      double s, int nx, int ny, int nz, double* part, const Scalars* sc, unsigned* nparts_out);
 // x += alpha p ; r -= alpha q ; partials (r.r, sum r)
 void launch_update(hipStream_t st, double* x, double* r, const double* p, const double* q, size_t n,
                    double* part, const Scalars* sc, unsigned* nparts_out);
@@ -65,6 +69,12 @@ void launch_prolong(hipStream_t st, const T* cu0, const T* cu1, int coarse_natur
                     int nz, const Scalars* sc);
 template <typename T>
 void launch_coarse(hipStream_t st, const T* f, T* u, const double* cinv, int m, const Scalars* sc);
+
+template <typename T>
+void launch_tail(hipStream_t st, const T* f0, const T* f1, T* u0, T* u1, const TailDesc& d, const double* cinv,
+                 const Scalars* sc);
+template <typename T>
+hipError_t tail_set_lds(size_t bytes);
 
 // ---- blobs -----------------------------------------------------------------
 struct BlobGeom {

@@ -276,3 +276,28 @@ def test_bitwise_deterministic(dev):
         outs.append((H(c), H(lam)))
         S.close()
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_graph_replay_matches_eager(dev, monkeypatch):
+    """CG iterations replayed from captured HIP graphs give bitwise the same answers as
+    eager launches; several solves in a row (graph replays with eager work between)."""
+    _say("graphs vs eager")
+    rng = np.random.default_rng(71)
+    n = 32
+    q = W.rsa_positions(rng, n, 40, 3.0)
+    kappa = W.log_uniform(rng, 1e-2, 1e2, 40)
+    fs = [1.0 + 0.5 * rng.standard_normal((n, n, n)) for _ in range(3)]
+    res = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("BLOB_RD_GRAPHS", mode)
+        S = make(dev, n, q, kappa, precision=1)
+        outs = []
+        for f in fs:
+            c, lam, st = S.solve_absorbing(T(f, dev))
+            cr, st2 = S.solve_reactive(T(f, dev))
+            outs.append((H(c), H(lam), H(cr)))
+        res[mode] = outs
+        S.close()
+    for a, b in zip(res["1"], res["0"]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
