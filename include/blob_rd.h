@@ -146,6 +146,62 @@ int blob_rd_apply(blob_rd_t h, double alpha, int with_blobs, const double* x, do
  * mean projection is applied. */
 int blob_rd_vcycle(blob_rd_t h, double alpha, const double* r, double* z);
 
+/* ---- Learned Schur preconditioner ----
+ *
+ * The paper preconditions the Schur complement M = J A^+ S with the diagonal
+ * M^{-1} ~ chi gamma^{-1} I, gamma ~ (4 pi a)^{-1} (Sec. III.E, eq.
+ * Schur_diagonal). The learned preconditioner keeps that diagonal (a0 =
+ * 1.255 h, the averaged reactive radius of Sec. IV.A) and adds a symmetric
+ * pairwise correction for blob pairs closer than r_c = 12 h:
+ *   W_ij = D h [delta_ij 4 pi a0/h + (g(i,j) + g(j,i))/2],
+ * g a 10 -> 64 -> 64 -> 1 SiLU network of pair features
+ *   [d/r_c (3), |d|/r_c, frac(q_i/h - 1/2) (3), frac(q_j/h - 1/2) (3)]
+ * (d the minimum-image separation), bfloat16 weights with float32
+ * accumulation. GMRES applies z = P W P r as a right preconditioner on
+ * steady (alpha = 0) absorbing solves when schur_precond = LEARNED.
+ * Training minimises (1/S) sum_s |P W y_s - x_s|^2/|x_s|^2 over sample pairs
+ * (x_s, y_s = P M P x_s) from blob_rd_schur_apply, with Adam.
+ *
+ * Parameters are one float32 vector of BLOB_RD_NET_PARAMS values:
+ * [W1 (64 x 10, row = output unit) | b1 (64) | W2 (64 x 64) | b2 (64) | w3 (64) | b3]. */
+#define BLOB_RD_NET_PARAMS 4929
+
+typedef struct blob_rd_net* blob_rd_net_t;
+
+/* Device bytes a network object needs (weights, Adam moments, gradient, per-wave partials). */
+size_t blob_rd_net_workspace_bytes(void);
+/* Network object on caller-owned device memory; parameters start at zero. */
+int blob_rd_net_create(void* workspace, size_t bytes, void* stream, blob_rd_net_t* out);
+int blob_rd_net_destroy(blob_rd_net_t net);
+/* Copy parameters from a device float32 vector; resets the Adam moments, the step count and the gradient. */
+int blob_rd_net_set_params(blob_rd_net_t net, const float* params);
+int blob_rd_net_get_params(blob_rd_net_t net, float* params);  /* device float32 [BLOB_RD_NET_PARAMS] */
+int blob_rd_net_zero_grad(blob_rd_net_t net);
+int blob_rd_net_get_grad(blob_rd_net_t net, float* grad);      /* device float32 [BLOB_RD_NET_PARAMS] */
+/* One Adam step (Kingma and Ba 2015, beta1 0.9, beta2 0.999, eps 1e-8) with the accumulated gradient. */
+int blob_rd_net_adam_step(blob_rd_net_t net, float lr);
+
+/* Build the pair list of the handle's blobs and evaluate W with the current
+ * network into caller-owned device memory `buf`. With buf == NULL only the
+ * required size is returned in *needed (this counts the pairs on the GPU).
+ * The buffer must stay valid while the handle uses the preconditioner.
+ * Non-finite entries mark the preconditioner unusable: solves then run
+ * without it and report stats.fallback = 1. */
+int blob_rd_precond_build(blob_rd_t h, blob_rd_net_t net, void* buf, size_t bytes, size_t* needed);
+/* z = P W P r (N-vectors, device). */
+int blob_rd_precond_apply(blob_rd_t h, const double* r, double* z);
+/* Copy the CSR of W (rows ascending, columns ascending) to device buffers; any may be NULL. */
+int blob_rd_precond_csr(blob_rd_t h, int64_t* nnz, int32_t* rowptr, int32_t* col, double* val);
+/* Loss over S sample pairs (X, Y device [S][N], rows x_s and y_s) and its
+ * gradient, added into the network's gradient (computed with the network
+ * the preconditioner was built from). *loss (host) receives the loss. */
+int blob_rd_precond_loss_grad(blob_rd_t h, blob_rd_net_t net, const double* X, const double* Y, int32_t S,
+                              double* loss);
+/* y = P J (alpha I - D L)^+ S P x (P projects out the mean for alpha = 0;
+ * identity otherwise): one Schur-complement product with an inner
+ * multigrid-CG solve to relative tolerance inner_rtol (eq. r_schur). */
+int blob_rd_schur_apply(blob_rd_t h, double alpha, const double* x, double* y, double inner_rtol);
+
 /* ---- Measurement ---- */
 
 #define BLOB_RD_KERNEL_GS 0        /* one Gauss-Seidel half-sweep on the finest level */

@@ -70,6 +70,26 @@ struct TailDesc {
     unsigned lds_bytes;
 };
 
+// Learned preconditioner network: flat float32 parameter vector
+// [W1 (64 x 10, row = output) | b1 | W2 (64 x 64) | b2 | w3 | b3].
+constexpr int kNetFeat = 10;
+constexpr int kOffW1 = 0, kOffB1 = 640, kOffW2 = 704, kOffB2 = 4800, kOffW3 = 4864, kOffB3 = 4928;
+constexpr int kNetParams = 4929;
+
+struct NetDev {
+    const float* P;     // float32 masters
+    const __bf16* W1b;  // [64][16] bfloat16, columns >= 10 zero
+    const __bf16* W2b;  // [64][64] bfloat16
+    const __bf16* w3b;  // [64] bfloat16
+};
+
+struct PairGeom {
+    double box[3];  // box edge per axis (x, y, z)
+    double h;
+    double rc;      // pair cutoff
+    int ncx, ncy, ncz;  // pair-search cells per axis
+};
+
 struct LevelDims {
     int nx, ny, nz;   // cells
     int hx;           // nx / 2 (split levels)

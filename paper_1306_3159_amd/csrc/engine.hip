@@ -293,6 +293,19 @@ struct blob_rd {
     hipStream_t cap_stream = nullptr;
     bool use_graphs = true;
     bool relax = true;  // relaxed inner tolerances in the Schur GMRES
+    // learned Schur preconditioner (CSR of W in a caller-provided buffer)
+    struct Learned {
+        bool ready = false;
+        bool bad = false;      // non-finite entries: never used
+        long long nnz = 0;
+        int* rowptr = nullptr;
+        int* col = nullptr;
+        int* rowidx = nullptr;
+        double* val = nullptr;
+        float* dg = nullptr;
+        PairGeom pg{};
+    } lrn;
+    int fallback = 0;
 
     template <typename T>
     T* at(size_t off) const {
@@ -689,6 +702,16 @@ int reactive_solve(blob_rd* H, double alpha, const double* g, double* c, blob_rd
     return ok ? BLOB_RD_OK : BLOB_RD_ENOTCONV;
 }
 
+// z = P W P r with the learned CSR (r, z device N-vectors; nv(11) scratch).
+void precond_apply(blob_rd* H, const double* r, double* z) {
+    const int N = H->P.N;
+    double* t = H->nv(11);
+    launch_nvec_copy_scale(H->st, r, t, N, 1.0, 0.0);
+    launch_nvec_project(H->st, t, N);
+    launch_spmv(H->st, H->lrn.rowptr, H->lrn.col, H->lrn.val, t, z, N);
+    launch_nvec_project(H->st, z, N);
+}
+
 // y = [P] J A^+ S [P] x for N-vectors x (device) -> y (device).
 template <typename T>
 void schur_apply(blob_rd* H, double alpha, const double* x, double* y, double inner_rtol) {
@@ -757,6 +780,11 @@ SaddleInfo saddle_solve(blob_rd* H, double alpha, const double* g, const double*
     double* Hm = H->at<double>(P.off_H);
     const int maxit = default_maxit(H);
     bool first = true;
+    bool use_w = false;
+    if (H->prm.schur_precond == BLOB_RD_PRECOND_LEARNED && alpha == 0.0) {
+        if (H->lrn.ready && !H->lrn.bad) use_w = true;
+        else H->fallback = 1;
+    }
     for (;;) {
         if (!first) schur_apply<T>(H, alpha, lt, w, inner_rtol);
         launch_gmres_start(st, b, w, first ? 0 : 1, V, H->at<double>(P.off_gv), N, H->gs());
@@ -771,13 +799,19 @@ SaddleInfo saddle_solve(blob_rd* H, double alpha, const double* g, const double*
         if (info.gmres_iters >= maxit) break;
         int k = 0;
         double res_prev = H->hgs->res;
+        const double res_cycle0 = res_prev;
         for (; k < m && info.gmres_iters < maxit; ++k) {
             // Inexact Krylov: the matvec may be less accurate as the residual falls
             // (Bouras-Fraysse / Simoncini-Szyld relaxation); the FP64 saddle residual
             // and refinement of the caller guard the final answer.
             double tau = inner_rtol;
             if (H->relax && res_prev > 0.0) tau = std::min(1e-2, std::max(inner_rtol, 0.1 * atol_schur / res_prev));
-            schur_apply<T>(H, alpha, V + (size_t)k * N, V + (size_t)(k + 1) * N, tau);
+            if (use_w) {
+                precond_apply(H, V + (size_t)k * N, H->nv(9));
+                schur_apply<T>(H, alpha, H->nv(9), V + (size_t)(k + 1) * N, tau);
+            } else {
+                schur_apply<T>(H, alpha, V + (size_t)k * N, V + (size_t)(k + 1) * N, tau);
+            }
             launch_gmres_arnoldi(st, V, Hm, H->at<double>(P.off_cs), H->at<double>(P.off_sn),
                                  H->at<double>(P.off_gv), N, k, m, H->gs());
             ++info.gmres_iters;
@@ -789,7 +823,20 @@ SaddleInfo saddle_solve(blob_rd* H, double alpha, const double* g, const double*
                 break;
             }
         }
-        launch_gmres_update(st, V, Hm, H->at<double>(P.off_gv), H->at<double>(P.off_yv), lt, N, k, m);
+        if (use_w) {
+            // right preconditioning: lt += P W P (V y)
+            launch_nvec_copy_scale(st, nullptr, H->nv(10), N, 0.0, 0.0);
+            launch_gmres_update(st, V, Hm, H->at<double>(P.off_gv), H->at<double>(P.off_yv), H->nv(10), N, k, m);
+            precond_apply(H, H->nv(10), H->nv(9));
+            launch_axpby(st, lt, H->nv(9), N, 1.0, 1.0);
+            // watchdog: a full cycle that did not cut the residual 10x drops the learned part
+            if (k == m && H->hgs->res > 0.1 * res_cycle0) {
+                use_w = false;
+                H->fallback = 1;
+            }
+        } else {
+            launch_gmres_update(st, V, Hm, H->at<double>(P.off_gv), H->at<double>(P.off_yv), lt, N, k, m);
+        }
         info.schur_res = H->hgs->res;
         // The Arnoldi estimate decides; the FP64 saddle residual computed by the
         // caller checks the answer and triggers refinement if needed.
@@ -912,6 +959,7 @@ int guarded(blob_rd* H, blob_rd_stats* stt, F&& fn) {
         H->vcycles = 0;
         H->alg_bytes = 0.0;
         H->inner_iters = 0;
+        H->fallback = 0;
     }
     if (stt) std::memset(stt, 0, sizeof(*stt));
     int rc;
@@ -923,6 +971,7 @@ int guarded(blob_rd* H, blob_rd_stats* stt, F&& fn) {
         rc = fail(H, Err(BLOB_RD_EDEVICE, e.what()));
     }
     if (stt && H) {
+        stt->fallback = H->fallback;
         stt->vcycles = H->vcycles;
         stt->alg_bytes = H->alg_bytes;
         stt->inner_iters_total = H->inner_iters;
@@ -1158,6 +1207,316 @@ int blob_rd_vcycle(blob_rd_t H, double alpha, const double* r, double* z) {
             launch_split_to_nat<double>(H->st, H->at<double>(P.off_lvl[0][0]), H->at<double>(P.off_lvl[0][1]), z,
                                         d.nx, d.ny, d.nz, 0.0);
         }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(H->st));
+        return BLOB_RD_OK;
+    });
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Learned preconditioner: network object and configuration hooks.
+// ===========================================================================
+struct blob_rd_net {
+    hipStream_t st = nullptr;
+    char* ws = nullptr;
+    float* P = nullptr;
+    float* m = nullptr;
+    float* v = nullptr;
+    float* grad = nullptr;
+    __bf16* W1b = nullptr;
+    __bf16* W2b = nullptr;
+    __bf16* w3b = nullptr;
+    float* wpart = nullptr;
+    int max_waves = 1024;
+    int t = 0;
+    NetDev dev() const { return NetDev{P, W1b, W2b, w3b}; }
+};
+
+namespace {
+constexpr int kNetMaxWaves = 1024;
+size_t net_bytes() {
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        size_t r = o;
+        o = align_up(o + b);
+        return r;
+    };
+    take(4 * (size_t)kNetParams * 4);
+    take(64 * 16 * 2);
+    take(64 * 64 * 2);
+    take(64 * 2);
+    take((size_t)kNetMaxWaves * kNetParams * 4);
+    return o + 256;
+}
+
+PairGeom pair_geom(const blob_rd* H) {
+    PairGeom pg{};
+    const int n[3] = {H->prm.nx, H->prm.ny, H->prm.nz};
+    pg.h = H->prm.h;
+    pg.rc = 12.0 * H->prm.h;
+    int nc[3];
+    for (int a = 0; a < 3; ++a) {
+        pg.box[a] = n[a] * H->prm.h;
+        nc[a] = (int)std::floor(pg.box[a] / pg.rc);
+        if (nc[a] < 3) nc[a] = 1;
+    }
+    pg.ncx = nc[0];
+    pg.ncy = nc[1];
+    pg.ncz = nc[2];
+    return pg;
+}
+
+// Bin blobs into pair-search cells and count pairs per row; int scratch in G_T1.
+// Returns nnz; rowptr (N+1) left in the scratch at the returned pointer.
+long long pair_count(blob_rd* H, const PairGeom& pg, int** rowptr_out, int** cell_of, int** offsets, int** perm) {
+    const Plan& P = H->P;
+    const int N = P.N;
+    const int nc = pg.ncx * pg.ncy * pg.ncz;
+    if (4 * (size_t)N + 3 * (size_t)nc + 2 > 2 * P.ncell) throw Err(BLOB_RD_EINVAL, "too many blobs for the pair scratch");
+    int* s = reinterpret_cast<int*>(H->grid(G_T1));
+    int* cell = s;
+    int* counts = cell + N;
+    int* offs = counts + nc;
+    int* cursor = offs + nc + 1;
+    int* prm = cursor + nc;
+    int* cnt = prm + N;
+    int* rowptr = cnt + N;
+    HIPCHK(hipMemsetAsync(counts, 0, (size_t)nc * 4, H->st));
+    HIPCHK(hipMemsetAsync(cursor, 0, (size_t)nc * 4, H->st));
+    const double* q = H->at<double>(P.off_q);
+    launch_pair_cells(H->st, q, N, pg, cell, counts);
+    launch_bin_scan(H->st, counts, nc, offs);
+    launch_bin_scatter(H->st, cell, N, offs, cursor, prm);
+    launch_bin_sort(H->st, offs, nc, prm);
+    launch_pair_count(H->st, q, N, pg, cell, offs, prm, cnt);
+    launch_bin_scan(H->st, cnt, N, rowptr);
+    int nnz = 0;
+    HIPCHK(hipMemcpyAsync(H->hbuf, rowptr + N, sizeof(int), hipMemcpyDeviceToHost, H->st));
+    HIPCHK(hipStreamSynchronize(H->st));
+    std::memcpy(&nnz, H->hbuf, sizeof(int));
+    *rowptr_out = rowptr;
+    *cell_of = cell;
+    *offsets = offs;
+    *perm = prm;
+    return nnz;
+}
+
+size_t learned_bytes(int N, long long nnz) {
+    return align_up((size_t)(N + 1) * 4) + 2 * align_up((size_t)nnz * 4) + align_up((size_t)nnz * 8) +
+           align_up((size_t)nnz * 4) + 256;
+}
+}  // namespace
+
+extern "C" {
+
+size_t blob_rd_net_workspace_bytes(void) { return net_bytes(); }
+
+int blob_rd_net_create(void* workspace, size_t bytes, void* stream, blob_rd_net_t* out) {
+    if (!out || !workspace) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (bytes < net_bytes()) return g_last_error = "net workspace too small", BLOB_RD_ENOMEM;
+    blob_rd_net* N = new blob_rd_net();
+    N->st = (hipStream_t)stream;
+    N->ws = (char*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        size_t r = o;
+        o = align_up(o + b);
+        return N->ws + r;
+    };
+    char* base = take(4 * (size_t)kNetParams * 4);
+    N->P = (float*)base;
+    N->m = N->P + kNetParams;
+    N->v = N->m + kNetParams;
+    N->grad = N->v + kNetParams;
+    N->W1b = (__bf16*)take(64 * 16 * 2);
+    N->W2b = (__bf16*)take(64 * 64 * 2);
+    N->w3b = (__bf16*)take(64 * 2);
+    N->wpart = (float*)take((size_t)kNetMaxWaves * kNetParams * 4);
+    N->max_waves = kNetMaxWaves;
+    if (hipMemsetAsync(N->P, 0, 4 * (size_t)kNetParams * 4, N->st) != hipSuccess) {
+        delete N;
+        return g_last_error = "hipMemsetAsync failed", BLOB_RD_EDEVICE;
+    }
+    launch_net_pack(N->st, N->P, N->W1b, N->W2b, N->w3b);
+    *out = N;
+    return BLOB_RD_OK;
+}
+
+int blob_rd_net_destroy(blob_rd_net_t N) {
+    delete N;
+    return BLOB_RD_OK;
+}
+
+int blob_rd_net_set_params(blob_rd_net_t N, const float* params) {
+    if (!N || !params) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    try {
+        HIPCHK(hipMemcpyAsync(N->P, params, (size_t)kNetParams * 4, hipMemcpyDeviceToDevice, N->st));
+        HIPCHK(hipMemsetAsync(N->m, 0, 3 * (size_t)kNetParams * 4, N->st));  // m, v, grad
+        N->t = 0;
+        launch_net_pack(N->st, N->P, N->W1b, N->W2b, N->w3b);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(N->st));
+    } catch (const Err& e) {
+        return fail(nullptr, e);
+    }
+    return BLOB_RD_OK;
+}
+
+int blob_rd_net_get_params(blob_rd_net_t N, float* params) {
+    if (!N || !params) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (hipMemcpyAsync(params, N->P, (size_t)kNetParams * 4, hipMemcpyDeviceToDevice, N->st) != hipSuccess ||
+        hipStreamSynchronize(N->st) != hipSuccess)
+        return g_last_error = "copy failed", BLOB_RD_EDEVICE;
+    return BLOB_RD_OK;
+}
+
+int blob_rd_net_zero_grad(blob_rd_net_t N) {
+    if (!N) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    return hipMemsetAsync(N->grad, 0, (size_t)kNetParams * 4, N->st) == hipSuccess ? BLOB_RD_OK : BLOB_RD_EDEVICE;
+}
+
+int blob_rd_net_get_grad(blob_rd_net_t N, float* grad) {
+    if (!N || !grad) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (hipMemcpyAsync(grad, N->grad, (size_t)kNetParams * 4, hipMemcpyDeviceToDevice, N->st) != hipSuccess ||
+        hipStreamSynchronize(N->st) != hipSuccess)
+        return g_last_error = "copy failed", BLOB_RD_EDEVICE;
+    return BLOB_RD_OK;
+}
+
+int blob_rd_net_adam_step(blob_rd_net_t N, float lr) {
+    if (!N || !(lr > 0.f)) return g_last_error = "bad argument", BLOB_RD_EINVAL;
+    N->t += 1;
+    launch_adam(N->st, N->P, N->m, N->v, N->grad, lr, 0.9f, 0.999f, 1e-8f, N->t);
+    launch_net_pack(N->st, N->P, N->W1b, N->W2b, N->w3b);
+    return hipGetLastError() == hipSuccess ? BLOB_RD_OK : BLOB_RD_EDEVICE;
+}
+
+int blob_rd_precond_build(blob_rd_t H, blob_rd_net_t Nt, void* buf, size_t bytes, size_t* needed) {
+    if (!H || !Nt) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (H->P.N <= 0) return g_last_error = "no blobs", BLOB_RD_EINVAL;
+    return guarded(H, nullptr, [&]() {
+        const int N = H->P.N;
+        const PairGeom pg = pair_geom(H);
+        int *rowptr_s, *cell, *offs, *prm;
+        const long long nnz = pair_count(H, pg, &rowptr_s, &cell, &offs, &prm);
+        const size_t need = learned_bytes(N, nnz);
+        if (needed) *needed = need;
+        if (!buf) return BLOB_RD_OK;
+        if (bytes < need) throw Err(BLOB_RD_ENOMEM, "precond buffer smaller than the size reported");
+        char* b = (char*)(((uintptr_t)buf + 255) & ~(uintptr_t)255);
+        if (b + need - 256 > (char*)buf + bytes) throw Err(BLOB_RD_ENOMEM, "precond buffer misaligned/too small");
+        auto& L = H->lrn;
+        L.rowptr = (int*)b;
+        b += align_up((size_t)(N + 1) * 4);
+        L.col = (int*)b;
+        b += align_up((size_t)nnz * 4);
+        L.rowidx = (int*)b;
+        b += align_up((size_t)nnz * 4);
+        L.val = (double*)b;
+        b += align_up((size_t)nnz * 8);
+        L.dg = (float*)b;
+        L.nnz = nnz;
+        L.pg = pg;
+        const double* q = H->at<double>(H->P.off_q);
+        HIPCHK(hipMemcpyAsync(L.rowptr, rowptr_s, (size_t)(N + 1) * 4, hipMemcpyDeviceToDevice, H->st));
+        launch_pair_fill(H->st, q, N, pg, cell, offs, prm, L.rowptr, L.col, L.rowidx);
+        launch_rowidx(H->st, L.rowptr, N, L.rowidx);
+        // the network's stream ordering: make sure its weights are current
+        HIPCHK(hipStreamSynchronize(Nt->st));
+        launch_net_assemble(H->st, q, pg, Nt->dev(), L.col, L.rowidx, nnz, H->prm.D * H->prm.h,
+                            4.0 * M_PI * 1.255, L.val);
+        int* bad = reinterpret_cast<int*>(H->dsc() + 40);
+        launch_count_bad(H->st, L.val, nnz, bad);
+        HIPCHK(hipMemcpyAsync(H->hbuf, bad, sizeof(int), hipMemcpyDeviceToHost, H->st));
+        HIPCHK(hipStreamSynchronize(H->st));
+        int nbad = 0;
+        std::memcpy(&nbad, H->hbuf, sizeof(int));
+        L.bad = nbad != 0;
+        L.ready = true;
+        HIPCHK(hipGetLastError());
+        return BLOB_RD_OK;
+    });
+}
+
+int blob_rd_precond_apply(blob_rd_t H, const double* r, double* z) {
+    if (!H || !r || !z) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (!H->lrn.ready) return g_last_error = "learned preconditioner not built", BLOB_RD_EINVAL;
+    return guarded(H, nullptr, [&]() {
+        precond_apply(H, r, z);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(H->st));
+        return BLOB_RD_OK;
+    });
+}
+
+int blob_rd_precond_csr(blob_rd_t H, int64_t* nnz, int32_t* rowptr, int32_t* col, double* val) {
+    if (!H || !nnz) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (!H->lrn.ready) return g_last_error = "learned preconditioner not built", BLOB_RD_EINVAL;
+    *nnz = H->lrn.nnz;
+    try {
+        const int N = H->P.N;
+        if (rowptr) HIPCHK(hipMemcpyAsync(rowptr, H->lrn.rowptr, (size_t)(N + 1) * 4, hipMemcpyDeviceToDevice, H->st));
+        if (col) HIPCHK(hipMemcpyAsync(col, H->lrn.col, (size_t)H->lrn.nnz * 4, hipMemcpyDeviceToDevice, H->st));
+        if (val) HIPCHK(hipMemcpyAsync(val, H->lrn.val, (size_t)H->lrn.nnz * 8, hipMemcpyDeviceToDevice, H->st));
+        HIPCHK(hipStreamSynchronize(H->st));
+    } catch (const Err& e) {
+        return fail(H, e);
+    }
+    return BLOB_RD_OK;
+}
+
+int blob_rd_precond_loss_grad(blob_rd_t H, blob_rd_net_t Nt, const double* X, const double* Y, int32_t S,
+                              double* loss) {
+    if (!H || !Nt || !X || !Y || S <= 0 || S > 64) return g_last_error = "bad argument", BLOB_RD_EINVAL;
+    if (!H->lrn.ready) return g_last_error = "learned preconditioner not built", BLOB_RD_EINVAL;
+    return guarded(H, nullptr, [&]() {
+        const int N = H->P.N;
+        auto& L = H->lrn;
+        hipStream_t st = H->st;
+        if ((size_t)2 * S * N + 64 > H->P.ncell) throw Err(BLOB_RD_EINVAL, "too many samples for this grid");
+        double* RP = H->grid(G_T2);
+        double* YP = RP + (size_t)S * N;
+        double* coef = YP + (size_t)S * N;
+        double lsum = 0.0;
+        std::vector<double> cf(S);
+        for (int s = 0; s < S; ++s) {
+            double* yp = YP + (size_t)s * N;
+            double* rp = RP + (size_t)s * N;
+            launch_nvec_copy_scale(st, Y + (size_t)s * N, yp, N, 1.0, 0.0);
+            launch_nvec_project(st, yp, N);
+            launch_spmv(st, L.rowptr, L.col, L.val, yp, rp, N);
+            launch_nvec_project(st, rp, N);
+            launch_axpby(st, rp, X + (size_t)s * N, N, 1.0, -1.0);   // res = P W P y - x
+            launch_nvec_sums(st, rp, nullptr, N, H->dsc());
+            launch_nvec_sums(st, X + (size_t)s * N, nullptr, N, H->dsc() + 3);
+            sync_read(H, H->hbuf, H->dsc(), 6 * 8);
+            const double rr = H->hbuf[1], xx = H->hbuf[4];
+            if (!(xx > 0.0)) throw Err(BLOB_RD_EINVAL, "zero sample x");
+            lsum += rr / xx / S;
+            cf[s] = 2.0 / (S * xx);
+            launch_nvec_project(st, rp, N);
+        }
+        HIPCHK(hipMemcpyAsync(coef, cf.data(), (size_t)S * 8, hipMemcpyHostToDevice, st));
+        launch_entry_grad(st, L.rowidx, L.col, L.nnz, RP, YP, coef, S, N, 0.5 * H->prm.D * H->prm.h, L.dg);
+        HIPCHK(hipStreamSynchronize(Nt->st));
+        const int nw = launch_net_backward(st, H->at<double>(H->P.off_q), L.pg, Nt->dev(), L.col, L.rowidx, L.nnz,
+                                           L.dg, Nt->wpart, Nt->max_waves);
+        launch_grad_reduce(st, Nt->wpart, nw, Nt->grad);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        if (loss) *loss = lsum;
+        return BLOB_RD_OK;
+    });
+}
+
+int blob_rd_schur_apply(blob_rd_t H, double alpha, const double* x, double* y, double inner_rtol) {
+    if (!H || !x || !y || H->P.N <= 0) return g_last_error = "bad argument", BLOB_RD_EINVAL;
+    if (!(alpha >= 0.0) || !(inner_rtol > 0.0)) return g_last_error = "bad alpha or tolerance", BLOB_RD_EINVAL;
+    return guarded(H, nullptr, [&]() {
+        if (H->P.esz == 4) schur_apply<float>(H, alpha, x, y, inner_rtol);
+        else schur_apply<double>(H, alpha, x, y, inner_rtol);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(H->st));
         return BLOB_RD_OK;

@@ -110,4 +110,25 @@ void launch_gmres_update(hipStream_t st, const double* V, const double* H, const
                          int N, int k, int m);
 void launch_nvec_sums(hipStream_t st, const double* a, const double* b, int N, double* out /*sum a, a.a, a.b*/);
 
+// ---- learned preconditioner -------------------------------------------------
+void launch_pair_cells(hipStream_t st, const double* q, int N, PairGeom pg, int* cell_of, int* counts);
+void launch_pair_count(hipStream_t st, const double* q, int N, PairGeom pg, const int* cell_of, const int* offsets,
+                       const int* perm, int* cnt);
+void launch_pair_fill(hipStream_t st, const double* q, int N, PairGeom pg, const int* cell_of, const int* offsets,
+                      const int* perm, const int* rowptr, int* col, int* rowidx);
+void launch_rowidx(hipStream_t st, const int* rowptr, int N, int* rowidx);
+void launch_net_assemble(hipStream_t st, const double* q, PairGeom pg, NetDev net, const int* col, const int* rowidx,
+                         long long nnz, double Dh, double diag, double* val);
+void launch_spmv(hipStream_t st, const int* rowptr, const int* col, const double* val, const double* x, double* y,
+                 int N);
+void launch_count_bad(hipStream_t st, const double* v, long long n, int* out);
+void launch_entry_grad(hipStream_t st, const int* rowidx, const int* col, long long nnz, const double* RP,
+                       const double* YP, const double* coef, int S, int N, double half_Dh, float* dg);
+int launch_net_backward(hipStream_t st, const double* q, PairGeom pg, NetDev net, const int* col, const int* rowidx,
+                        long long nnz, const float* dg, float* wpart, int max_waves);
+void launch_grad_reduce(hipStream_t st, const float* wpart, int nwaves, float* grad);
+void launch_adam(hipStream_t st, float* P, float* m, float* v, const float* grad, float lr, float b1, float b2,
+                 float eps, int t);
+void launch_net_pack(hipStream_t st, const float* P, __bf16* W1b, __bf16* W2b, __bf16* w3b);
+
 }  // namespace brd

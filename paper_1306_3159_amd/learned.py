@@ -1,0 +1,90 @@
+"""Training driver of the learned Schur preconditioner (loop control only).
+
+Samples come from the method itself: for a blob configuration and seeded
+mean-zero random vectors x_s, the library computes y_s = P M P x_s with
+M = J (-D L)^+ S (one multigrid-CG Poisson solve per sample,
+blob_rd_schur_apply). Training then minimises
+(1/S) sum_s |P W y_s - x_s|^2 / |x_s|^2 over the configurations with the
+library's forward/backward kernels and Adam; W is rebuilt from the current
+network for every configuration visited.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import Callable, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from .native import BlobRD, Net, MIXED, PRECOND_LEARNED, PRECOND_NONE, NET_PARAMS
+
+
+@dataclasses.dataclass
+class Sample:
+    shape: tuple
+    q: np.ndarray          # (N, 3) positions
+    X: torch.Tensor        # (S, N) device, mean-zero rows
+    Y: torch.Tensor        # (S, N) device, Y_s = P M P X_s
+
+
+def harvest(shape, q: np.ndarray, n_samples: int, seed: int, device, inner_rtol: float = 1e-8,
+            precision: int = MIXED) -> Sample:
+    """Schur products of seeded random vectors for one configuration."""
+    rng = np.random.default_rng(seed)
+    N = q.shape[0]
+    X = rng.standard_normal((n_samples, N))
+    X -= X.mean(axis=1, keepdims=True)
+    Xd = torch.tensor(X, device=device)
+    S = BlobRD(shape, torch.tensor(q, device=device), precision=precision)
+    Y = torch.stack([S.schur_apply(Xd[s], 0.0, inner_rtol) for s in range(n_samples)])
+    S.close()
+    return Sample(tuple(shape) if not isinstance(shape, int) else (shape,) * 3, q, Xd, Y)
+
+
+def loss_and_grad(net: Net, samples: Sequence[Sample], device) -> float:
+    """Accumulate the gradient over configurations into the network; returns the mean loss."""
+    total = 0.0
+    for smp in samples:
+        S = BlobRD(smp.shape, torch.tensor(smp.q, device=device))
+        S.precond_build(net)
+        total += S.precond_loss_grad(net, smp.X, smp.Y)
+        S.close()
+    return total / max(1, len(samples))
+
+
+def train(net: Net, samples: List[Sample], epochs: int, lr: float, batch: int, device, seed: int = 0,
+          log: Optional[Callable[[str], None]] = None) -> List[float]:
+    """Adam over mini-batches of configurations; returns the mean loss per epoch."""
+    rng = np.random.default_rng(seed)
+    hist = []
+    for ep in range(epochs):
+        order = rng.permutation(len(samples))
+        losses = []
+        t0 = time.time()
+        for b0 in range(0, len(order), batch):
+            net.zero_grad()
+            sub = [samples[i] for i in order[b0:b0 + batch]]
+            losses.append(loss_and_grad(net, sub, device))
+            net.adam_step(lr)
+        hist.append(float(np.mean(losses)))
+        if log:
+            log(f"epoch {ep}: loss {hist[-1]:.5f} ({time.time() - t0:.1f}s)")
+    return hist
+
+
+def gmres_iterations(shape, q: np.ndarray, f: torch.Tensor, net: Optional[Net], device, rtol: float = 1e-8,
+                     precision: int = MIXED):
+    """Schur GMRES iterations and wall time of one absorbing solve, with or without W."""
+    S = BlobRD(shape, torch.tensor(q, device=device), precision=precision, rtol=rtol,
+               schur_precond=PRECOND_LEARNED if net is not None else PRECOND_NONE)
+    if net is not None:
+        S.precond_build(net)
+    c, lam, st = S.solve_absorbing(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c, lam, st = S.solve_absorbing(f)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    S.close()
+    return st, dt, c, lam

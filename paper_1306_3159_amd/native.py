@@ -98,6 +98,24 @@ def load_library(path: str = LIB_PATH):
     L.blob_rd_vcycle.restype = i32
     L.blob_rd_time_kernel.argtypes = [vp, i32, i32, ctypes.POINTER(d), ctypes.POINTER(d)]
     L.blob_rd_time_kernel.restype = i32
+    L.blob_rd_net_workspace_bytes.argtypes = []
+    L.blob_rd_net_workspace_bytes.restype = ctypes.c_size_t
+    L.blob_rd_net_create.argtypes = [vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.blob_rd_net_destroy.argtypes = [vp]
+    L.blob_rd_net_set_params.argtypes = [vp, vp]
+    L.blob_rd_net_get_params.argtypes = [vp, vp]
+    L.blob_rd_net_zero_grad.argtypes = [vp]
+    L.blob_rd_net_get_grad.argtypes = [vp, vp]
+    L.blob_rd_net_adam_step.argtypes = [vp, ctypes.c_float]
+    L.blob_rd_precond_build.argtypes = [vp, vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+    L.blob_rd_precond_apply.argtypes = [vp, vp, vp]
+    L.blob_rd_precond_csr.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), vp, vp, vp]
+    L.blob_rd_precond_loss_grad.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.POINTER(d)]
+    L.blob_rd_schur_apply.argtypes = [vp, d, vp, vp, d]
+    for name in ("blob_rd_net_create", "blob_rd_net_destroy", "blob_rd_net_set_params", "blob_rd_net_get_params",
+                 "blob_rd_net_zero_grad", "blob_rd_net_get_grad", "blob_rd_net_adam_step", "blob_rd_precond_build",
+                 "blob_rd_precond_apply", "blob_rd_precond_csr", "blob_rd_precond_loss_grad", "blob_rd_schur_apply"):
+        getattr(L, name).restype = i32
     _lib = L
     return L
 
@@ -116,6 +134,63 @@ def _dev_f64(t: torch.Tensor, shape, name: str) -> torch.Tensor:
 
 def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+NET_PARAMS = 4929
+
+
+class Net:
+    """The learned preconditioner's network (weights, Adam state, gradient) on the GPU."""
+
+    def __init__(self, device=None, stream: Optional[torch.cuda.Stream] = None):
+        L = load_library()
+        self._lib = L
+        self.device = torch.device("cuda:0") if device is None else device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = L.blob_rd_net_workspace_bytes()
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        rc = L.blob_rd_net_create(ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != OK:
+            raise BlobRDError(rc, L.blob_rd_last_error(None).decode())
+        self._h = h
+
+    def _chk(self, rc):
+        if rc != OK:
+            raise BlobRDError(rc, self._lib.blob_rd_last_error(None).decode())
+
+    def set_params(self, p: torch.Tensor):
+        p = p.to(device=self.device, dtype=torch.float32).contiguous()
+        assert p.numel() == NET_PARAMS
+        self._chk(self._lib.blob_rd_net_set_params(self._h, _ptr(p)))
+
+    def get_params(self) -> torch.Tensor:
+        out = torch.empty(NET_PARAMS, dtype=torch.float32, device=self.device)
+        self._chk(self._lib.blob_rd_net_get_params(self._h, _ptr(out)))
+        return out
+
+    def zero_grad(self):
+        self._chk(self._lib.blob_rd_net_zero_grad(self._h))
+
+    def get_grad(self) -> torch.Tensor:
+        out = torch.empty(NET_PARAMS, dtype=torch.float32, device=self.device)
+        self._chk(self._lib.blob_rd_net_get_grad(self._h, _ptr(out)))
+        return out
+
+    def adam_step(self, lr: float):
+        self._chk(self._lib.blob_rd_net_adam_step(self._h, ctypes.c_float(lr)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.blob_rd_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class BlobRD:
@@ -249,3 +324,43 @@ class BlobRD:
         self._check(self._lib.blob_rd_time_kernel(self._h, self.KERNELS[kernel], int(reps), ctypes.byref(ms),
                                                   ctypes.byref(by)))
         return ms.value, by.value
+
+    # -- learned preconditioner -------------------------------------------------
+    def precond_build(self, net: "Net") -> int:
+        """Pair list + W from the network; returns nnz. The buffer is kept by this object."""
+        need = ctypes.c_size_t()
+        self._check(self._lib.blob_rd_precond_build(self._h, net._h, None, 0, ctypes.byref(need)))
+        self._pbuf = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=self.device)
+        self._check(self._lib.blob_rd_precond_build(self._h, net._h, ctypes.c_void_p(self._pbuf.data_ptr()),
+                                                    self._pbuf.numel(), ctypes.byref(need)))
+        nnz = ctypes.c_int64()
+        self._check(self._lib.blob_rd_precond_csr(self._h, ctypes.byref(nnz), None, None, None))
+        return int(nnz.value)
+
+    def precond_csr(self):
+        nnz = ctypes.c_int64()
+        self._check(self._lib.blob_rd_precond_csr(self._h, ctypes.byref(nnz), None, None, None))
+        ptr = torch.empty(self.N + 1, dtype=torch.int32, device=self.device)
+        col = torch.empty(int(nnz.value), dtype=torch.int32, device=self.device)
+        val = torch.empty(int(nnz.value), dtype=torch.float64, device=self.device)
+        self._check(self._lib.blob_rd_precond_csr(self._h, ctypes.byref(nnz), _ptr(ptr), _ptr(col), _ptr(val)))
+        return ptr, col, val
+
+    def precond_apply(self, r: torch.Tensor) -> torch.Tensor:
+        z = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        self._check(self._lib.blob_rd_precond_apply(self._h, _ptr(r), _ptr(z)))
+        return z
+
+    def precond_loss_grad(self, net: "Net", X: torch.Tensor, Y: torch.Tensor) -> float:
+        X = X.contiguous()
+        Y = Y.contiguous()
+        S = int(X.shape[0])
+        loss = ctypes.c_double()
+        self._check(self._lib.blob_rd_precond_loss_grad(self._h, net._h, _ptr(X), _ptr(Y), S, ctypes.byref(loss)))
+        return loss.value
+
+    def schur_apply(self, x: torch.Tensor, alpha: float = 0.0, inner_rtol: float = 1e-10) -> torch.Tensor:
+        y = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        self._check(self._lib.blob_rd_schur_apply(self._h, float(alpha), _ptr(x.contiguous()), _ptr(y),
+                                                  float(inner_rtol)))
+        return y

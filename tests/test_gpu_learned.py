@@ -1,0 +1,221 @@
+"""GPU parity of the learned Schur preconditioner against oracle/learned.py."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import exact as ex
+from oracle import learned as LN
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1306_3159_amd import native
+    native.load_library()
+    return torch.device("cuda:0")
+
+
+def T(a, dev, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=dev)
+
+
+def rand_params(seed):
+    rng = np.random.default_rng(seed)
+    p = LN.init_params(seed)
+    p["b1"] = (0.1 * rng.standard_normal(64)).astype(np.float32)
+    p["b2"] = (0.1 * rng.standard_normal(64)).astype(np.float32)
+    p["w3"] = (0.3 * rng.standard_normal(64)).astype(np.float32)
+    p["b3"] = np.array([0.2], np.float32)
+    return p
+
+
+def net_with(dev, p):
+    from paper_1306_3159_amd import Net
+    net = Net(dev)
+    net.set_params(T(LN.flatten(p), dev, torch.float32))
+    return net
+
+
+@pytest.mark.parametrize("n,N", [(32, 40), (48, 120), (64, 300)])
+def test_pair_list_and_assembly(dev, n, N):
+    """CSR pattern identical to the oracle's (integers: bitwise); values within the bf16
+    activation rounding of the MFMA path (oracle: float64 on the same bf16 weights)."""
+    _say("pairs", n, N)
+    from paper_1306_3159_amd import BlobRD
+    rng = np.random.default_rng(n + N)
+    q = W.rsa_positions(rng, n, N, 3.0) + rng.integers(-1, 2, (N, 3)) * n   # some unwrapped images
+    p = rand_params(3)
+    net = net_with(dev, p)
+    S = BlobRD(n, T(q, dev))
+    nnz = S.precond_build(net)
+    ptr, col, val = (t.cpu().numpy() for t in S.precond_csr())
+    optr, ocol, oval, _ = LN.assemble(LN.rounded(p), q, (n, n, n))
+    assert nnz == ocol.size
+    assert np.array_equal(ptr, optr) and np.array_equal(col, ocol)
+    diag = (np.repeat(np.arange(N), np.diff(optr)) == ocol) * 4 * math.pi * LN.A0
+    learned_o, learned_g = oval - diag, val - diag
+    assert np.linalg.norm(learned_g - learned_o) <= 2e-2 * np.linalg.norm(learned_o)
+    # symmetric
+    Wd = np.zeros((N, N))
+    for i in range(N):
+        Wd[i, col[ptr[i]:ptr[i + 1]]] = val[ptr[i]:ptr[i + 1]]
+    assert np.array_equal(Wd, Wd.T)
+    # apply = P W P r
+    r = rng.standard_normal(N)
+    z = S.precond_apply(T(r, dev)).cpu().numpy()
+    assert np.allclose(z, LN.project(LN.spmv(ptr, col, val, LN.project(r))), rtol=1e-12, atol=1e-12)
+    S.close()
+    net.close()
+
+
+def test_untrained_net_is_diagonal(dev):
+    _say("untrained")
+    from paper_1306_3159_amd import BlobRD
+    rng = np.random.default_rng(5)
+    q = W.rsa_positions(rng, 32, 50, 3.0)
+    net = net_with(dev, LN.init_params(0))
+    S = BlobRD(32, T(q, dev), D=1.5)
+    S.precond_build(net)
+    ptr, col, val = (t.cpu().numpy() for t in S.precond_csr())
+    row = np.repeat(np.arange(50), np.diff(ptr))
+    assert np.allclose(val[row == col], 1.5 * 4 * math.pi * LN.A0, rtol=1e-15, atol=0)
+    assert np.all(val[row != col] == 0.0)
+    S.close()
+
+
+def test_gradient_matches_oracle(dev):
+    """GPU forward/backward (bf16 MFMA, fp32 accumulation) vs the oracle's float64 gradient
+    on the same bf16-rounded weights: relative error per tensor <= 1e-2... 3e-2."""
+    _say("grad")
+    from paper_1306_3159_amd import BlobRD
+    rng = np.random.default_rng(11)
+    n, N, Sm = 48, 150, 4
+    q = W.rsa_positions(rng, n, N, 3.0)
+    p = rand_params(12)
+    X = rng.standard_normal((Sm, N))
+    X -= X.mean(1, keepdims=True)
+    Y = 0.05 * rng.standard_normal((Sm, N))
+    loss_o, g_o = LN.loss_and_grad(p, q, (n, n, n), X, Y)
+    net = net_with(dev, p)
+    net.zero_grad()
+    S = BlobRD(n, T(q, dev))
+    S.precond_build(net)
+    loss_g = S.precond_loss_grad(net, T(X, dev), T(Y, dev))
+    g = LN.unflatten(net.get_grad().cpu().numpy())
+    assert loss_g == pytest.approx(loss_o, rel=1e-2)
+    for k in LN.PARAM_ORDER:
+        a, b = np.asarray(g[k], np.float64), np.asarray(g_o[k], np.float64)
+        assert np.linalg.norm(a - b) <= 3e-2 * np.linalg.norm(b) + 1e-12, (k, np.linalg.norm(a - b) / np.linalg.norm(b))
+    S.close()
+    net.close()
+
+
+def test_adam_step_matches_oracle(dev):
+    _say("adam")
+    from paper_1306_3159_amd import BlobRD
+    rng = np.random.default_rng(13)
+    q = W.rsa_positions(rng, 32, 60, 3.0)
+    p = rand_params(14)
+    X = rng.standard_normal((2, 60))
+    X -= X.mean(1, keepdims=True)
+    Y = 0.05 * rng.standard_normal((2, 60))
+    net = net_with(dev, p)
+    S = BlobRD(32, T(q, dev))
+    for step in range(2):
+        net.zero_grad()
+        S.precond_build(net)
+        S.precond_loss_grad(net, T(X, dev), T(Y, dev))
+        gpu_grad = LN.unflatten(net.get_grad().cpu().numpy())
+        before = LN.unflatten(net.get_params().cpu().numpy())
+        net.adam_step(1e-3)
+        after = LN.unflatten(net.get_params().cpu().numpy())
+        if step == 0:
+            st = {}
+        ref = LN.adam_step(before, gpu_grad, st, 1e-3)
+        for k in LN.PARAM_ORDER:
+            assert np.allclose(after[k], ref[k], rtol=1e-5, atol=1e-6), k
+    S.close()
+    net.close()
+
+
+def test_schur_apply_matches_exact(dev):
+    """y = P J (-L)^+ S P x against the FFT/dense oracle Schur matrix."""
+    _say("schur apply")
+    from paper_1306_3159_amd import BlobRD
+    rng = np.random.default_rng(15)
+    n, N = 32, 25
+    q = W.rsa_positions(rng, n, N, 3.0)
+    G = ex.schur_matrix(q, (n, n, n), 0.0)
+    P = np.eye(N) - 1.0 / N
+    x = rng.standard_normal(N)
+    S = BlobRD(n, T(q, dev))
+    y = S.schur_apply(T(x, dev), 0.0, 1e-12).cpu().numpy()
+    ref = P @ G @ P @ x
+    assert np.linalg.norm(y - ref) <= 1e-9 * np.linalg.norm(ref)
+    S.close()
+
+
+def test_learned_solve_and_fallback(dev):
+    """Absorbing solve with the learned preconditioner reaches 1e-8 and matches the exact
+    answer; NaN weights trigger the fallback to the plain Schur GMRES."""
+    _say("learned solve")
+    from paper_1306_3159_amd import BlobRD, PRECOND_LEARNED, MIXED
+    rng = np.random.default_rng(17)
+    n, N = 32, 40
+    q = W.rsa_positions(rng, n, N, 3.0)
+    f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
+    ce, le = ex.solve_absorbing(f, q, 0.0)
+    p = rand_params(18)
+    p["w3"] *= 0.1
+    for bad in (False, True):
+        if bad:
+            p["w3"][3] = np.nan
+        net = net_with(dev, p)
+        S = BlobRD(n, T(q, dev), precision=MIXED, schur_precond=PRECOND_LEARNED, rtol=1e-8)
+        S.precond_build(net)
+        c, lam, st = S.solve_absorbing(T(f, dev))
+        assert st["rc"] == 0 and st["fallback"] == int(bad), st
+        assert ex.absorbing_residual(c.cpu().numpy(), lam.cpu().numpy(), f, q, 0.0) <= 1e-8
+        assert np.linalg.norm(lam.cpu().numpy() - le) <= 1e-6 * np.linalg.norm(le)
+        S.close()
+        net.close()
+
+
+def test_training_reduces_gmres_iterations(dev):
+    """A short training run on the method's own Schur products lowers the GMRES
+    iteration count on held-out configurations of the same density."""
+    _say("training gain")
+    from paper_1306_3159_amd import Net, learned as LD
+    n, N = 64, 156        # density of 10^4 blobs in 256^3
+    train = [LD.harvest(n, W.rsa_positions(np.random.default_rng(500 + i), n, N, 3.0), 6, 900 + i, dev)
+             for i in range(12)]
+    net = Net(dev)
+    net.set_params(T(LN.flatten(LN.init_params(1)), dev, torch.float32))
+    hist = LD.train(net, train, epochs=25, lr=3e-3, batch=4, device=dev)
+    assert hist[-1] < 0.8 * hist[0], hist
+    its_none, its_learn = [], []
+    for k in range(3):
+        rng = np.random.default_rng(700 + k)
+        q = W.rsa_positions(rng, n, N, 3.0)
+        f = T(1.0 + 0.5 * rng.standard_normal((n, n, n)), dev)
+        st0, _, _, _ = LD.gmres_iterations(n, q, f, None, dev)
+        st1, _, _, _ = LD.gmres_iterations(n, q, f, net, dev)
+        assert st0["rc"] == 0 and st1["rc"] == 0 and st1["fallback"] == 0
+        its_none.append(st0["outer_iters"])
+        its_learn.append(st1["outer_iters"])
+    print("iterations none", its_none, "learned", its_learn, flush=True)
+    assert sum(its_learn) < sum(its_none)
+    net.close()
