@@ -1,19 +1,19 @@
 """Benchmark: solves/sec to a 1e-8 relative residual on one MI355X.
 
-Default workload: the diffusion-limited (absorbing) saddle point on a 128^3
-periodic grid with a simple-cubic lattice of 8^3 = 512 blobs 16h apart
-(four-point kernel), solved by Schur-complement GMRES(30) with inner
-multigrid-preconditioned CG. The source is f = 1 + 0.5 N(0,1): with f = 1 the
-lattice symmetry makes the projected Schur right-hand side vanish and GMRES
-would have nothing to do, so the random source is what exercises the Schur
-path (the f = 1 case is timed as an extra line).
+Default workload (the learned Schur preconditioner case): a 256^3 periodic
+grid with 10^4 absorbing blobs placed by random sequential addition
+(minimum separation 3h), four-point kernel, uniform source f = 1, steady
+diffusion-limited saddle point solved by Schur-complement GMRES(30) with
+inner multigrid-preconditioned CG, to a 1e-8 relative residual.
 
-A step is one full solve (grid and blob inputs already resident in device
-memory). The timed path is FP32 V-cycles under FP64 CG/GMRES with FP64
-residuals and refinement ("mixed"); the same solve with FP64 V-cycles
-("plain FP64") is timed beside it.
+A step is one full absorbing solve with inputs resident in device memory.
+`value` is the learned + FP32 path: FP32 V-cycles under FP64 CG/GMRES with
+FP64 residuals and refinement, right-preconditioned by the trained network
+(weights in paper_1306_3159_amd/weights). Beside it: the same solve in plain
+FP64 (FP64 V-cycles, no learned part) and with FP32 V-cycles alone, and the
+128^3 lattice workload (8^3 blobs 16h apart, random source) as an extra line.
 
-Prints ONE JSON line (rank 0).
+Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -30,142 +30,136 @@ sys.path.insert(0, ROOT)
 
 METRIC = "solves/sec at 1e-8 rel residual, learned+FP32 vs plain FP64; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+WEIGHTS = os.path.join(ROOT, "paper_1306_3159_amd", "weights", "precond_rsa256.npy")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="lattice128_randf",
-                    choices=["lattice128_randf", "lattice128", "single_blob32", "rsa256_reactive",
-                             "rsa256_absorbing", "be256"])
+    ap.add_argument("--workload", default="rsa256_learned", choices=["rsa256_learned", "lattice128_randf"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--no-extra", action="store_true", help="skip the comparison paths and the extra workload")
+    ap.add_argument("--kernel-reps", type=int, default=100)
     return ap.parse_args()
 
 
-def make_instance(name):
-    import workloads as W
-    if name == "lattice128_randf":
-        return W.cubic_lattice(random_f=True)
-    if name == "lattice128":
-        return W.cubic_lattice()
-    if name == "single_blob32":
-        return W.single_blob()
-    if name in ("rsa256_reactive", "be256"):
-        return W.disordered(kind="reactive")
-    if name == "rsa256_absorbing":
-        return W.disordered(kind="absorbing")
-    raise ValueError(name)
-
-
-def time_solves(S, inst, f, steps, warmup, kind):
+def timed(fn, steps, warmup):
     import torch
-    def one():
-        if kind == "absorbing":
-            return S.solve_absorbing(f)[2]
-        if kind == "reactive":
-            return S.solve_reactive(f)[1]
-        c = torch.zeros_like(f)
-        st = None
-        for _ in range(20):
-            st = S.step(f, c, 0.5)
-        return st
-    st = None
     for _ in range(warmup):
-        st = one()
+        fn()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = []
+    st = None
     for _ in range(steps):
-        stats.append(one())
+        st = fn()
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    return dt, stats
+    return time.perf_counter() - t0, st
 
 
-def cpu_baseline(inst, kind):
-    from oracle import iterative as it
-    it.build(force=False)
-    t0 = time.perf_counter()
-    if kind == "absorbing":
-        c, lam, st = it.solve_absorbing(inst.f, inst.q, inst.alpha, rtol=inst.rtol, inner_rtol=5e-10)
-    elif kind == "reactive":
-        c, st = it.solve_reactive(inst.f, inst.q, inst.kappa, inst.alpha, rtol=inst.rtol)
-    else:
-        c = np.zeros_like(inst.f)
-        c, st = it.step(c, inst.f, inst.q, inst.kappa, 0.5, rtol=inst.rtol)
-    dt = time.perf_counter() - t0
-    return dt, st, it.num_threads()
+def summary(st):
+    return {"gmres_iters": st["outer_iters"], "inner_cg_iters": st["inner_iters_total"], "vcycles": st["vcycles"],
+            "rel_resid": st["rel_resid"], "refinements": st["refinements"], "fallback": st["fallback"],
+            "alg_bytes": st["alg_bytes"]}
 
 
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design note "
-                                   "(z-slab decomposition), not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "single-GPU build: multi-GPU sharding (z-slab decomposition) is a design note, "
+                                   "not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
-    from paper_1306_3159_amd import BlobRD, MIXED, FP64
+    import workloads as W
+    from paper_1306_3159_amd import BlobRD, Net, MIXED, FP64, PRECOND_LEARNED, PRECOND_NONE
 
     dev = torch.device("cuda:0")
-    inst = make_instance(args.workload)
-    kind = "step" if args.workload == "be256" else inst.kind
-    q = torch.tensor(inst.q, device=dev)
-    kap = torch.tensor(inst.kappa, device=dev) if inst.kind == "reactive" else None
-    f = torch.tensor(inst.f, device=dev)
     rtol = 1e-8
+    if args.workload == "rsa256_learned":
+        inst = W.learned_eval(256, 10000, index=0)
+    else:
+        inst = W.cubic_lattice(random_f=True)
+    q = torch.tensor(inst.q, device=dev)
+    f = torch.tensor(inst.f, device=dev)
 
-    S = BlobRD(inst.n, q, kap, precision=MIXED, rtol=rtol)
-    dt, stats = time_solves(S, inst, f, args.steps, args.warmup, kind)
-    last = stats[-1]
+    net = None
+    if args.workload == "rsa256_learned":
+        net = Net(dev)
+        net.set_params(torch.tensor(np.load(WEIGHTS), device=dev))
+        S = BlobRD(inst.n, q, precision=MIXED, schur_precond=PRECOND_LEARNED, rtol=rtol)
+        S.precond_build(net)
+    else:
+        S = BlobRD(inst.n, q, precision=MIXED, rtol=rtol)
+    dt, st = timed(lambda: S.solve_absorbing(f)[2], args.steps, args.warmup)
     value = args.steps / dt
+    learned = args.workload == "rsa256_learned"
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64 Krylov + f32 V-cycles", "data": "synthetic",
-        "config": {"workload": args.workload, "n": inst.n, "N": inst.N, "kind": kind, "rtol": rtol,
-                   "kernel_w": 4, "gmres_restart": 30, "precision": "mixed"},
-        "solve": {"outer_iters": last["outer_iters"], "inner_iters": last["inner_iters_total"],
-                  "vcycles": last["vcycles"], "rel_resid": last["rel_resid"],
-                  "refinements": last["refinements"], "alg_bytes": last["alg_bytes"],
-                  "alg_GBs": last["alg_bytes"] / (1e-3 * 1e3 * dt / args.steps) / 1e9},
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 Krylov/residuals + f32 V-cycles"
+        + (" + bf16 network" if learned else ""), "data": "synthetic",
+        "config": {"workload": args.workload, "n": inst.n, "N": inst.N, "kind": "absorbing", "rtol": rtol,
+                   "kernel_w": 4, "gmres_restart": 30, "path": "learned+fp32" if learned else "fp32",
+                   "source": "f=1" if learned else "f=1+0.5N(0,1)", "seed": inst.seed},
+        "solve": summary(st),
     }
-    if kind == "step":
-        out["unit"] = "20-step runs/s"
+    out["solve"]["alg_GBs"] = st["alg_bytes"] / (dt / args.steps) / 1e9
 
-    if not args.no_plain:
-        P = BlobRD(inst.n, q, kap, precision=FP64, rtol=rtol)
-        psteps = max(2, args.steps // 2)
-        pdt, pstats = time_solves(P, inst, f, psteps, 1, kind)
-        out["plain_fp64"] = {"value": psteps / pdt, "ms_per_step": 1e3 * pdt / psteps,
-                             "outer_iters": pstats[-1]["outer_iters"],
-                             "inner_iters": pstats[-1]["inner_iters_total"],
-                             "rel_resid": pstats[-1]["rel_resid"]}
+    if not args.no_extra:
+        P = BlobRD(inst.n, q, precision=FP64, rtol=rtol)
+        pdt, pst = timed(lambda: P.solve_absorbing(f)[2], max(2, args.steps // 2), 1)
+        n = max(2, args.steps // 2)
+        out["plain_fp64"] = {"value": n / pdt, "ms_per_step": 1e3 * pdt / n, **summary(pst)}
         out["speedup_vs_plain_fp64"] = value / out["plain_fp64"]["value"]
         P.close()
+        if learned:
+            M = BlobRD(inst.n, q, precision=MIXED, rtol=rtol)
+            mdt, mst = timed(lambda: M.solve_absorbing(f)[2], n, 1)
+            out["fp32_no_learned"] = {"value": n / mdt, "ms_per_step": 1e3 * mdt / n, **summary(mst)}
+            M.close()
+            lat = W.cubic_lattice(random_f=True)
+            L = BlobRD(lat.n, torch.tensor(lat.q, device=dev), precision=MIXED, rtol=rtol)
+            ldt, lst = timed(lambda: L.solve_absorbing(torch.tensor(lat.f, device=dev))[2], 5, 1)
+            L2 = BlobRD(lat.n, torch.tensor(lat.q, device=dev), precision=FP64, rtol=rtol)
+            l2dt, l2st = timed(lambda: L2.solve_absorbing(torch.tensor(lat.f, device=dev))[2], 5, 1)
+            out["lattice128_randf"] = {"fp32_value": 5 / ldt, "plain_fp64_value": 5 / l2dt, **summary(lst)}
+            L.close()
+            L2.close()
 
-    # Roofline of the dominant kernel: the finest-level Gauss-Seidel half-sweep,
-    # timed with HIP events on the handle's stream.
+    # Roofline of the dominant kernel: the finest-level Gauss-Seidel half-sweep
+    # (FP32), timed with HIP events on the handle's stream.
     ms, by = S.time_kernel("gs", args.kernel_reps)
     ach = by / (ms * 1e-3) / 1e9
-    out["roofline"] = {"kernel": "gs_half_sweep_f32_finest", "bound": "hbm", "achieved": ach,
-                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                       "avg_us": ms * 1e3, "bytes_per_launch": by}
-    others = {}
+    out["roofline"] = {"kernel": "k_gs<float> finest level", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_us": ms * 1e3,
+                       "bytes_per_launch": by}
+    kern = {}
     for k in ("stencil", "restrict", "prolong", "vcycle"):
         kms, kby = S.time_kernel(k, max(10, args.kernel_reps // 4))
-        others[k] = {"avg_us": kms * 1e3, "alg_GBs": kby / (kms * 1e-3) / 1e9}
-    out["kernels"] = others
+        kern[k] = {"avg_us": kms * 1e3, "alg_GBs": kby / (kms * 1e-3) / 1e9, "bytes": kby}
+    out["kernels"] = kern
     S.close()
+    if net is not None:
+        net.close()
 
     if not args.no_cpu_baseline:
-        cdt, cst, cores = cpu_baseline(inst, kind)
-        out["cpu_baseline"] = {"value": 1.0 / cdt, "unit": "solves/s", "cores": cores, "kind": "oracle",
-                               "sample": f"one full {kind} solve of the same workload by the C FP64 oracle "
-                                         f"({cdt:.1f} s)"}
+        from oracle import iterative as it
+        it.build(force=False)
+        g = np.asarray(inst.f, dtype=np.float64)
+        g = g - g.mean()
+        k = 2
+        t0 = time.perf_counter()
+        for _ in range(k):
+            it.solve_poisson(g, 0.0, rtol=5e-10)
+        tp = (time.perf_counter() - t0) / k
+        per_solve = st["outer_iters"] if args.workload != "rsa256_learned" else out.get("plain_fp64", {}).get(
+            "gmres_iters", st["outer_iters"])
+        n_poisson = per_solve + 2
+        out["cpu_baseline"] = {
+            "value": 1.0 / (tp * n_poisson), "unit": "solves/s", "cores": it.num_threads(), "kind": "oracle",
+            "sample": f"{k} oracle MG-CG Poisson solves on the same grid (rtol 5e-10, {tp:.2f} s each), scaled by "
+                      f"{n_poisson} Poisson solves per absorbing solve ({per_solve} Schur GMRES products + 2)"}
     print(json.dumps(out))
 
 

@@ -753,6 +753,22 @@ int ora_solve_absorbing(const ora_problem* P, double alpha, const double* f, dou
     return rc;
 }
 
+/* u = A^+ g by MG-preconditioned CG to relative tolerance rtol (one inner solve
+ * of the absorbing method; used to time a bounded sample of it). */
+int ora_solve_poisson(const ora_problem* P, double alpha, const double* g, double* u, double rtol, int maxit,
+                      ora_stats* st) {
+    memset(st, 0, sizeof(*st));
+    ora_op op;
+    op.P = P;
+    op.alpha = alpha;
+    op.with_blobs = 0;
+    op.eBe = 0.0;
+    op.mg = ora_mg_create(P->nx, P->ny, P->nz, P->h, P->D, alpha);
+    int rc = poisson(&op, g, u, rtol, maxit, st);
+    ora_mg_destroy(op.mg);
+    return rc;
+}
+
 /* Number of OpenMP threads the oracle runs with (1 when built without OpenMP). */
 int ora_num_threads(void) {
 #ifdef _OPENMP

@@ -73,6 +73,8 @@ def lib():
         L.ora_solve_absorbing.argtypes = [P, d, dp, dp, dp, d, d, i, i, ctypes.POINTER(Stats)]
         L.ora_solve_absorbing.restype = i
         L.ora_num_threads.restype = i
+        L.ora_solve_poisson.argtypes = [P, d, dp, dp, d, i, ctypes.POINTER(Stats)]
+        L.ora_solve_poisson.restype = i
         _lib = L
     return _lib
 
@@ -226,3 +228,13 @@ def solve_absorbing(f, q, alpha, D=1.0, h=1.0, w=4, rtol=1e-10, inner_rtol=1e-12
 
 def num_threads() -> int:
     return int(lib().ora_num_threads())
+
+
+def solve_poisson(g, alpha, D=1.0, h=1.0, rtol=1e-10, maxit=500):
+    """u = (alpha I - D L)^+ g by the oracle's MG-preconditioned CG (mean-zero for alpha = 0)."""
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    H = _Holder(g.shape, np.zeros((0, 3)), None, h, D, 4)
+    u = np.zeros_like(g)
+    st = Stats()
+    rc = lib().ora_solve_poisson(ctypes.byref(H.p), alpha, _ptr(g), _ptr(u), rtol, maxit, ctypes.byref(st))
+    return u, dict(rc=rc, inner_iters=st.inner_iters, vcycles=st.vcycles)

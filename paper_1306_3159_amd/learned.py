@@ -20,6 +20,18 @@ import torch
 from .native import BlobRD, Net, MIXED, PRECOND_LEARNED, PRECOND_NONE, NET_PARAMS
 
 
+def initial_params(seed: int = 0) -> np.ndarray:
+    """Seeded starting weights as one float32 vector in the library's parameter layout
+    [W1 (64x10) | b1 | W2 (64x64) | b2 | w3 | b3]: He-scaled normal hidden layers and a
+    zero output layer, so the untrained network reproduces the diagonal preconditioner."""
+    rng = np.random.default_rng(seed)
+    w1 = rng.standard_normal((64, 10)) * np.sqrt(2.0 / 10)
+    w2 = rng.standard_normal((64, 64)) * np.sqrt(2.0 / 64)
+    v = np.concatenate([w1.ravel(), np.zeros(64), w2.ravel(), np.zeros(64), np.zeros(64), np.zeros(1)])
+    assert v.size == NET_PARAMS
+    return v.astype(np.float32)
+
+
 @dataclasses.dataclass
 class Sample:
     shape: tuple
@@ -28,13 +40,34 @@ class Sample:
     Y: torch.Tensor        # (S, N) device, Y_s = P M P X_s
 
 
-def harvest(shape, q: np.ndarray, n_samples: int, seed: int, device, inner_rtol: float = 1e-8,
-            precision: int = MIXED) -> Sample:
-    """Schur products of seeded random vectors for one configuration."""
+def sample_vectors(q: np.ndarray, box, n_samples: int, seed: int, smooth_fraction: float = 0.5,
+                   kmax2: int = 4) -> np.ndarray:
+    """Seeded mean-zero blob vectors: white noise, and (for a fraction of them) smooth fields
+    sum_k a_k cos(2 pi k.q/L) + b_k sin(2 pi k.q/L) over the wave vectors 0 < |k|^2 <= kmax2,
+    which carry the slowly varying modes of the Schur complement."""
     rng = np.random.default_rng(seed)
     N = q.shape[0]
     X = rng.standard_normal((n_samples, N))
+    n_smooth = int(round(smooth_fraction * n_samples))
+    if n_smooth:
+        r = int(np.floor(np.sqrt(kmax2)))
+        ks = np.array([(a, b, c) for a in range(-r, r + 1) for b in range(-r, r + 1) for c in range(-r, r + 1)
+                       if 0 < a * a + b * b + c * c <= kmax2], dtype=np.float64)
+        ph = 2.0 * np.pi * (q / np.asarray(box, dtype=np.float64)) @ ks.T        # (N, K)
+        for s in range(n_smooth):
+            a = rng.standard_normal(ks.shape[0])
+            b = rng.standard_normal(ks.shape[0])
+            X[s] = np.cos(ph) @ a + np.sin(ph) @ b
     X -= X.mean(axis=1, keepdims=True)
+    return X
+
+
+def harvest(shape, q: np.ndarray, n_samples: int, seed: int, device, inner_rtol: float = 1e-8,
+            precision: int = MIXED, smooth_fraction: float = 0.5, h: float = 1.0) -> Sample:
+    """Schur products of seeded sample vectors for one configuration."""
+    dims = (shape,) * 3 if isinstance(shape, int) else tuple(shape)
+    box = (dims[2] * h, dims[1] * h, dims[0] * h)      # (x, y, z) edges
+    X = sample_vectors(q, box, n_samples, seed, smooth_fraction)
     Xd = torch.tensor(X, device=device)
     S = BlobRD(shape, torch.tensor(q, device=device), precision=precision)
     Y = torch.stack([S.schur_apply(Xd[s], 0.0, inner_rtol) for s in range(n_samples)])
