@@ -78,9 +78,77 @@ __global__ void __launch_bounds__(kBlock) k_gs(T* __restrict__ uc, const T* __re
     uc[idx] = (fc[idx] + s * nb) * inv_diag;
 }
 
+// Vector form: each thread updates VW = 16 / sizeof(T) consecutive cells of a
+// split row with 16-byte loads and stores (same arithmetic and summation
+// order as k_gs, so results are bitwise identical). Needs hx % VW == 0.
+template <typename T>
+struct VecOf;
+template <>
+struct VecOf<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static constexpr int W = 4;
+};
+template <>
+struct VecOf<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+    static constexpr int W = 2;
+};
+
+// x-neighbours of the VW cells starting at i0 (x offset so): left = other[i-1+so], right = other[i+so]
+template <typename T>
+__device__ __forceinline__ void row_neighbours(const T* __restrict__ orow, int i0, int hx, int so,
+                                               typename VecOf<T>::type& left, typename VecOf<T>::type& right) {
+    typedef typename VecOf<T>::type V;
+    constexpr int VW = VecOf<T>::W;
+    const V o = *reinterpret_cast<const V*>(orow + i0);
+    const T edge = so ? orow[i0 + VW == hx ? 0 : i0 + VW] : orow[i0 == 0 ? hx - 1 : i0 - 1];
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+        left[k] = so ? o[k] : (k ? o[k - 1] : edge);
+        right[k] = so ? (k + 1 < VW ? o[k + 1] : edge) : o[k];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gs_vec(T* __restrict__ uc, const T* __restrict__ uo,
+                                                   const T* __restrict__ fc, int hx, int ny, int nz, int color, T s,
+                                                   T inv_diag, const Scalars* sc) {
+    typedef typename VecOf<T>::type V;
+    constexpr int VW = VecOf<T>::W;
+    if (sc && sc->done) return;
+    const int hv = hx / VW;
+    const unsigned nv = (unsigned)hv * ny * nz;
+    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= nv) return;
+    const int iv = idx % hv;
+    const unsigned t = idx / hv;
+    const int y = t % ny, z = t / ny;
+    const int i0 = iv * VW;
+    const int so = ((y + z) & 1) ^ color;
+    const size_t row = ((size_t)z * ny + y) * hx;
+    V left, right;
+    row_neighbours<T>(uo + row, i0, hx, so, left, right);
+    const V ym = *reinterpret_cast<const V*>(uo + ((size_t)z * ny + wrapi(y - 1, ny)) * hx + i0);
+    const V yp = *reinterpret_cast<const V*>(uo + ((size_t)z * ny + wrapi(y + 1, ny)) * hx + i0);
+    const V zm = *reinterpret_cast<const V*>(uo + ((size_t)wrapi(z - 1, nz) * ny + y) * hx + i0);
+    const V zp = *reinterpret_cast<const V*>(uo + ((size_t)wrapi(z + 1, nz) * ny + y) * hx + i0);
+    const V f = *reinterpret_cast<const V*>(fc + row + i0);
+    V out;
+#pragma unroll
+    for (int k = 0; k < VW; ++k) out[k] = (f[k] + s * (((left[k] + right[k]) + (ym[k] + yp[k])) + (zm[k] + zp[k]))) * inv_diag;
+    *reinterpret_cast<V*>(uc + row + i0) = out;
+}
+
 template <typename T>
 void launch_gs(hipStream_t st, T* uc, const T* uo, const T* fc, int hx, int ny, int nz, int color, double s,
                double inv_diag, const Scalars* sc) {
+    constexpr int VW = VecOf<T>::W;
+    if (hx % VW == 0 && hx >= VW) {
+        const unsigned nv = (unsigned)(hx / VW) * ny * nz;
+        hipLaunchKernelGGL(k_gs_vec<T>, dim3(nblocks(nv)), dim3(kBlock), 0, st, uc, uo, fc, hx, ny, nz, color, (T)s,
+                           (T)inv_diag, sc);
+        return;
+    }
     const unsigned nh = (unsigned)hx * ny * nz;
     hipLaunchKernelGGL(k_gs<T>, dim3(nblocks(nh)), dim3(kBlock), 0, st, uc, uo, fc, hx, ny, nz, color, (T)s,
                        (T)inv_diag, sc);
@@ -108,8 +176,55 @@ __global__ void __launch_bounds__(kBlock) k_resid(const T* __restrict__ u0, cons
 }
 
 template <typename T>
+__global__ void __launch_bounds__(kBlock) k_resid_vec(const T* __restrict__ u0, const T* __restrict__ u1,
+                                                      const T* __restrict__ f0, const T* __restrict__ f1,
+                                                      T* __restrict__ r0, T* __restrict__ r1, int hx, int ny, int nz,
+                                                      T s, T diag, const Scalars* sc) {
+    typedef typename VecOf<T>::type V;
+    constexpr int VW = VecOf<T>::W;
+    if (sc && sc->done) return;
+    const int hv = hx / VW;
+    const unsigned nv = (unsigned)hv * ny * nz;
+    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= nv) return;
+    const int iv = idx % hv;
+    const unsigned t = idx / hv;
+    const int y = t % ny, z = t / ny;
+    const int i0 = iv * VW;
+    const int s0 = (y + z) & 1;
+    const size_t row = ((size_t)z * ny + y) * hx;
+    const size_t rym = ((size_t)z * ny + wrapi(y - 1, ny)) * hx + i0, ryp = ((size_t)z * ny + wrapi(y + 1, ny)) * hx + i0;
+    const size_t rzm = ((size_t)wrapi(z - 1, nz) * ny + y) * hx + i0, rzp = ((size_t)wrapi(z + 1, nz) * ny + y) * hx + i0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const T* uo = c ? u0 : u1;    // neighbours are of the other colour
+        const T* uc = c ? u1 : u0;
+        const T* fc = c ? f1 : f0;
+        T* rc = c ? r1 : r0;
+        V left, right;
+        row_neighbours<T>(uo + row, i0, hx, s0 ^ c, left, right);
+        const V ym = *reinterpret_cast<const V*>(uo + rym), yp = *reinterpret_cast<const V*>(uo + ryp);
+        const V zm = *reinterpret_cast<const V*>(uo + rzm), zp = *reinterpret_cast<const V*>(uo + rzp);
+        const V u = *reinterpret_cast<const V*>(uc + row + i0);
+        const V f = *reinterpret_cast<const V*>(fc + row + i0);
+        V out;
+#pragma unroll
+        for (int k = 0; k < VW; ++k)
+            out[k] = f[k] - (diag * u[k] - s * (((left[k] + right[k]) + (ym[k] + yp[k])) + (zm[k] + zp[k])));
+        *reinterpret_cast<V*>(rc + row + i0) = out;
+    }
+}
+
+template <typename T>
 void launch_resid_split(hipStream_t st, const T* u0, const T* u1, const T* f0, const T* f1, T* r0, T* r1, int hx,
                         int ny, int nz, double s, double diag, const Scalars* sc) {
+    constexpr int VW = VecOf<T>::W;
+    if (hx % VW == 0 && hx >= VW) {
+        const unsigned nv = (unsigned)(hx / VW) * ny * nz;
+        hipLaunchKernelGGL(k_resid_vec<T>, dim3(nblocks(nv)), dim3(kBlock), 0, st, u0, u1, f0, f1, r0, r1, hx, ny,
+                           nz, (T)s, (T)diag, sc);
+        return;
+    }
     const unsigned nh = (unsigned)hx * ny * nz;
     hipLaunchKernelGGL(k_resid<T>, dim3(nblocks(nh)), dim3(kBlock), 0, st, u0, u1, f0, f1, r0, r1, hx, ny, nz, (T)s,
                        (T)diag, sc);
