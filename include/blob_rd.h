@@ -202,6 +202,19 @@ int blob_rd_precond_loss_grad(blob_rd_t h, blob_rd_net_t net, const double* X, c
  * multigrid-CG solve to relative tolerance inner_rtol (eq. r_schur). */
 int blob_rd_schur_apply(blob_rd_t h, double alpha, const double* x, double* y, double inner_rtol);
 
+/* ---- Batches of independent suspensions ----
+ *
+ * Solve n independent instances (each its own handle, created with its own
+ * stream) concurrently: `threads` host workers take instances largest-first
+ * and drive their solves, so the kernels and graph replays of different
+ * instances overlap on the GPU. kind[i] = 0 reactive (c[i] initial guess in,
+ * solution out; lambda[i] ignored), 1 absorbing (c[i], lambda[i] out). The
+ * results are bitwise those of solving each instance alone. Returns the
+ * first hard error, else BLOB_RD_ENOTCONV if any instance missed its
+ * tolerance, else 0; stats (may be NULL) receives one entry per instance. */
+int blob_rd_solve_batch(blob_rd_t* h, int32_t n, const int32_t* kind, double alpha, const double* const* f,
+                        double* const* c, double* const* lambda, int32_t threads, blob_rd_stats* stats);
+
 /* ---- Measurement ---- */
 
 #define BLOB_RD_KERNEL_GS 0        /* one Gauss-Seidel half-sweep on the finest level */
@@ -209,10 +222,13 @@ int blob_rd_schur_apply(blob_rd_t h, double alpha, const double* x, double* y, d
 #define BLOB_RD_KERNEL_RESTRICT 2  /* finest residual + full-weighting restriction */
 #define BLOB_RD_KERNEL_PROLONG 3   /* trilinear prolongation + correction onto the finest level */
 #define BLOB_RD_KERNEL_VCYCLE 4    /* one whole V-cycle (all levels) */
+#define BLOB_RD_KERNEL_COLD 256    /* OR-ed flag: evict the last-level cache before each timed launch */
 
 /* Launch one kernel of the solve path `reps` times back to back on the
  * handle's stream, bracketed by HIP events, on the handle's own workspace
- * buffers (their contents are overwritten). avg_ms receives the mean time
+ * buffers (their contents are overwritten). With BLOB_RD_KERNEL_COLD each
+ * launch is timed alone after streaming >= 512 MB through the cache (HBM
+ * rather than Infinity Cache bandwidth; needs a grid of >= 128^3 cells). avg_ms receives the mean time
  * per launch and bytes the algorithmic HBM bytes one launch must move
  * (each input read once, each output written once). */
 int blob_rd_time_kernel(blob_rd_t h, int kernel, int reps, double* avg_ms, double* bytes);

@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -694,6 +696,7 @@ int reactive_solve(blob_rd* H, double alpha, const double* g, double* c, blob_rd
         ++refinements;
     }
     launch_axpby(H->st, c, x, H->P.ncell, 0.0, 1.0);
+    HIPCHK(hipStreamSynchronize(H->st));  // outputs are complete on return
     if (stt) {
         stt->outer_iters = total;
         stt->rel_resid = rn / gn;
@@ -1523,8 +1526,53 @@ int blob_rd_schur_apply(blob_rd_t H, double alpha, const double* x, double* y, d
     });
 }
 
+int blob_rd_solve_batch(blob_rd_t* hs, int32_t n, const int32_t* kind, double alpha, const double* const* f,
+                        double* const* c, double* const* lambda, int32_t threads, blob_rd_stats* stats) {
+    if (!hs || !kind || !f || !c || n < 0 || threads <= 0) return g_last_error = "bad argument", BLOB_RD_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (!hs[i] || !f[i] || !c[i] || (kind[i] == 1 && (!lambda || !lambda[i])) || (kind[i] != 0 && kind[i] != 1))
+            return g_last_error = "bad instance " + std::to_string(i), BLOB_RD_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return g_last_error = "a handle appears twice in the batch", BLOB_RD_EINVAL;
+    }
+    // largest grids first for load balance
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hs[a]->P.ncell > hs[b]->P.ncell; });
+    std::vector<int> rcs(n, 0);
+    std::vector<std::string> errs(n);
+    std::atomic<int> next(0);
+    auto worker = [&]() {
+        for (;;) {
+            const int k = next.fetch_add(1);
+            if (k >= n) return;
+            const int i = order[k];
+            blob_rd_stats* si = stats ? &stats[i] : nullptr;
+            rcs[i] = kind[i] == 0 ? blob_rd_solve_reactive(hs[i], alpha, f[i], c[i], si)
+                                  : blob_rd_solve_absorbing(hs[i], alpha, f[i], c[i], lambda[i], si);
+            if (rcs[i] < 0) errs[i] = g_last_error;
+        }
+    };
+    const int nt = std::max(1, std::min<int>(threads, n));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto& t : pool) t.join();
+    int rc = BLOB_RD_OK;
+    for (int i = 0; i < n; ++i)
+        if (rcs[i] < 0) {
+            g_last_error = "instance " + std::to_string(i) + ": " + errs[i];
+            return rcs[i];
+        }
+    for (int i = 0; i < n; ++i)
+        if (rcs[i] == BLOB_RD_ENOTCONV) rc = BLOB_RD_ENOTCONV;
+    return rc;
+}
+
 int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, double* bytes) {
     if (!H || !avg_ms || !bytes || reps <= 0) return g_last_error = "bad argument", BLOB_RD_EINVAL;
+    const bool cold = (kernel & BLOB_RD_KERNEL_COLD) != 0;
+    kernel &= ~BLOB_RD_KERNEL_COLD;
     if (kernel < 0 || kernel > 4) return g_last_error = "unknown kernel id", BLOB_RD_EINVAL;
     return guarded(H, nullptr, [&]() {
         const Plan& P = H->P;
@@ -1602,12 +1650,29 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
             }
         };
         one();  // warm
-        HIPCHK(hipEventRecord(e0, H->st));
-        for (int i = 0; i < reps; ++i) one();
-        HIPCHK(hipEventRecord(e1, H->st));
-        HIPCHK(hipEventSynchronize(e1));
         float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (cold) {
+            // Evict the 256 MB Infinity Cache before every timed launch by streaming
+            // through >= 512 MB of the workspace's FP64 scratch vectors.
+            double* flush = H->grid(G_T1);
+            const size_t fl = std::min<size_t>(3 * P.ncell, (size_t)96 << 20);  // doubles (G_T1, G_T2, G_P2 are adjacent)
+            for (int i = 0; i < reps; ++i) {
+                launch_axpby(H->st, flush, flush + fl / 2, fl / 2, 0.5, 0.5);
+                HIPCHK(hipEventRecord(e0, H->st));
+                one();
+                HIPCHK(hipEventRecord(e1, H->st));
+                HIPCHK(hipEventSynchronize(e1));
+                float t = 0.f;
+                HIPCHK(hipEventElapsedTime(&t, e0, e1));
+                ms += t;
+            }
+        } else {
+            HIPCHK(hipEventRecord(e0, H->st));
+            for (int i = 0; i < reps; ++i) one();
+            HIPCHK(hipEventRecord(e1, H->st));
+            HIPCHK(hipEventSynchronize(e1));
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         *avg_ms = (double)ms / reps;

@@ -112,6 +112,9 @@ def load_library(path: str = LIB_PATH):
     L.blob_rd_precond_csr.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), vp, vp, vp]
     L.blob_rd_precond_loss_grad.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.POINTER(d)]
     L.blob_rd_schur_apply.argtypes = [vp, d, vp, vp, d]
+    L.blob_rd_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), d,
+                                      ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int32, S]
+    L.blob_rd_solve_batch.restype = i32
     for name in ("blob_rd_net_create", "blob_rd_net_destroy", "blob_rd_net_set_params", "blob_rd_net_get_params",
                  "blob_rd_net_zero_grad", "blob_rd_net_get_grad", "blob_rd_net_adam_step", "blob_rd_precond_build",
                  "blob_rd_precond_apply", "blob_rd_precond_csr", "blob_rd_precond_loss_grad", "blob_rd_schur_apply"):
@@ -318,11 +321,12 @@ class BlobRD:
     # -- measurement ------------------------------------------------------------
     KERNELS = {"gs": 0, "stencil": 1, "restrict": 2, "prolong": 3, "vcycle": 4}
 
-    def time_kernel(self, kernel: str, reps: int = 50) -> Tuple[float, float]:
-        """Mean ms per launch (HIP events on this handle's stream) and algorithmic bytes per launch."""
+    def time_kernel(self, kernel: str, reps: int = 50, cold: bool = False) -> Tuple[float, float]:
+        """Mean ms per launch (HIP events on this handle's stream) and algorithmic bytes per launch.
+        cold=True evicts the last-level cache before each launch."""
         ms, by = ctypes.c_double(), ctypes.c_double()
-        self._check(self._lib.blob_rd_time_kernel(self._h, self.KERNELS[kernel], int(reps), ctypes.byref(ms),
-                                                  ctypes.byref(by)))
+        kid = self.KERNELS[kernel] | (256 if cold else 0)
+        self._check(self._lib.blob_rd_time_kernel(self._h, kid, int(reps), ctypes.byref(ms), ctypes.byref(by)))
         return ms.value, by.value
 
     # -- learned preconditioner -------------------------------------------------
@@ -364,3 +368,21 @@ class BlobRD:
         self._check(self._lib.blob_rd_schur_apply(self._h, float(alpha), _ptr(x.contiguous()), _ptr(y),
                                                   float(inner_rtol)))
         return y
+
+
+def solve_batch(solvers: Sequence["BlobRD"], kinds: Sequence[int], fs, cs, lams, alpha: float = 0.0,
+                threads: int = 8):
+    """Solve independent instances concurrently (each solver should own its own stream).
+    kinds: 0 reactive, 1 absorbing. Returns (rc, list of stats dicts)."""
+    L = load_library()
+    n = len(solvers)
+    H = (ctypes.c_void_p * n)(*[s._h for s in solvers])
+    K = (ctypes.c_int32 * n)(*[int(k) for k in kinds])
+    F = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+    C = (ctypes.c_void_p * n)(*[c.data_ptr() for c in cs])
+    Lm = (ctypes.c_void_p * n)(*[(l.data_ptr() if l is not None else None) for l in lams])
+    st = (Stats * n)()
+    rc = L.blob_rd_solve_batch(H, n, K, float(alpha), F, C, Lm, int(threads), st)
+    if rc < 0:
+        raise BlobRDError(rc, L.blob_rd_last_error(None).decode())
+    return rc, [st[i].as_dict(rc) for i in range(n)]

@@ -301,3 +301,103 @@ def test_graph_replay_matches_eager(dev, monkeypatch):
     for a, b in zip(res["1"], res["0"]):
         for x, y in zip(a, b):
             assert np.array_equal(x, y)
+
+
+def test_batch_matches_solo(dev):
+    """Uneven instances (grids 32/48/64, reactive and absorbing) solved concurrently on
+    their own streams give bitwise the results of solving each alone."""
+    _say("batch")
+    from paper_1306_3159_amd import BlobRD, solve_batch
+    specs = [(32, 60, 0), (48, 200, 1), (64, 300, 0), (32, 20, 1), (48, 90, 0), (64, 150, 1)]
+    inst = []
+    for k, (n, N, kind) in enumerate(specs):
+        rng = np.random.default_rng(800 + k)
+        q = W.rsa_positions(rng, n, N, 3.0)
+        kap = W.log_uniform(rng, 1e-2, 1e2, N)
+        inst.append((n, q, kap, kind))
+
+    def handles():
+        out = []
+        for n, q, kap, kind in inst:
+            out.append(make(dev, n, q, kap, precision=1, stream=torch.cuda.Stream(dev)))
+        return out
+
+    solo = []
+    for S, (n, q, kap, kind) in zip(handles(), inst):
+        f = T(np.ones((n, n, n)), dev)
+        torch.cuda.synchronize()
+        if kind == 0:
+            c, st = S.solve_reactive(f)
+            solo.append((H(c), None))
+        else:
+            c, lam, st = S.solve_absorbing(f)
+            solo.append((H(c), H(lam)))
+        assert st["rc"] == 0
+        S.close()
+    Hs = handles()
+    fs = [T(np.ones((n, n, n)), dev) for n, _, _, _ in inst]
+    cs = [torch.zeros((n, n, n), dtype=torch.float64, device=dev) for n, _, _, _ in inst]
+    ls = [torch.zeros(q.shape[0], dtype=torch.float64, device=dev) if kind else None for _, q, _, kind in inst]
+    torch.cuda.synchronize()
+    rc, stats = solve_batch(Hs, [k for *_, k in inst], fs, cs, ls, threads=4)
+    assert rc == 0, stats
+    for (c0, l0), c, l in zip(solo, cs, ls):
+        assert np.array_equal(H(c), c0)
+        if l0 is not None:
+            assert np.array_equal(H(l), l0)
+    for S in Hs:
+        S.close()
+
+
+@pytest.fixture(scope="module")
+def rsa256():
+    return W.disordered(kind="reactive")
+
+
+def test_rsa256_reactive_full_size(dev, rsa256):
+    """256^3, 2e4 RSA blobs, kappa log-uniform in [1e-2, 1e2], f = 1: steady reactive solve
+    (FP32 V-cycles, FP64 CG) checked by the oracle's FP64 residual at full size."""
+    inst = rsa256
+    _say("rsa256 reactive")
+    S = make(dev, inst.n, inst.q, inst.kappa, precision=1, rtol=1e-8)
+    c, st = S.solve_reactive(T(inst.f, dev))
+    assert st["rc"] == 0, st
+    print("rsa256 reactive", st, flush=True)
+    assert ex.reactive_residual(H(c), inst.f, inst.q, inst.kappa, 0.0) <= 1e-8
+    S.close()
+
+
+def test_rsa256_absorbing_full_size(dev, rsa256):
+    inst = rsa256
+    _say("rsa256 absorbing")
+    S = make(dev, inst.n, inst.q, precision=1, rtol=1e-8)
+    c, lam, st = S.solve_absorbing(T(inst.f, dev))
+    assert st["rc"] == 0, st
+    print("rsa256 absorbing", st, flush=True)
+    c, lam = H(c), H(lam)
+    assert ex.absorbing_residual(c, lam, inst.f, inst.q, 0.0) <= 1e-8
+    assert lam.sum() == pytest.approx(inst.f.sum(), rel=1e-12)
+    S.close()
+
+
+def test_rsa256_backward_euler(dev, rsa256):
+    """Backward-Euler steps dt = 0.5 from c = 0: every step meets 1e-8 (oracle residual on
+    the first two steps) and the total reactant grows monotonically toward steady state."""
+    inst = rsa256
+    _say("rsa256 BE")
+    S = make(dev, inst.n, inst.q, inst.kappa, precision=1, rtol=1e-8)
+    c = torch.zeros((inst.n,) * 3, dtype=torch.float64, device=dev)
+    f = T(inst.f, dev)
+    prev = None
+    totals = []
+    for k in range(20):
+        if k < 2:
+            prev = H(c)
+        st = S.step(f, c, 0.5)
+        assert st["rc"] == 0 and st["rel_resid"] <= 1e-8, (k, st)
+        if k < 2:
+            g = inst.f + prev / 0.5
+            assert ex.reactive_residual(H(c), g, inst.q, inst.kappa, 2.0) <= 1e-8
+        totals.append(float(c.sum()))
+    assert all(b > a for a, b in zip(totals, totals[1:]))
+    S.close()
