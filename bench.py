@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rsa256_learned", choices=["rsa256_learned", "lattice128_randf", "batch64"])
     ap.add_argument("--threads", type=int, default=8, help="host workers of the batch executor")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="also run one device copy of this many MiB (calibrates memory counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the comparison paths and the extra workload")
     ap.add_argument("--kernel-reps", type=int, default=100)
@@ -212,6 +214,13 @@ def main():
             "value": 1.0 / (tp * n_poisson), "unit": "solves/s", "cores": it.num_threads(), "kind": "oracle",
             "sample": f"{k} oracle MG-CG Poisson solves on the same grid (rtol 5e-10, {tp:.2f} s each), scaled by "
                       f"{n_poisson} Poisson solves per absorbing solve ({per_solve} Schur GMRES products + 2)"}
+    if args.copy_probe:
+        src = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * src.numel() * 8
     print(json.dumps(out))
 
 
