@@ -514,8 +514,8 @@ void precond_zdots(blob_rd* H, double alpha, const double* r, const double* q, c
     vcycle<T>(H, alpha, r, H->sc(), cinv);
     const LevelDims& d = H->P.lev[0];
     unsigned np = 0;
-    launch_zdots<T>(H->st, H->at<T>(H->P.off_lvl[0][0]), H->at<T>(H->P.off_lvl[0][1]), r, q, d.nx, d.ny, d.nz,
-                    H->part(), H->sc(), &np);
+    launch_zdots2<T>(H->st, H->at<T>(H->P.off_lvl[0][0]), H->at<T>(H->P.off_lvl[0][1]), r, q, d.nx, d.ny, d.nz,
+                     H->part(), H->sc(), &np);
     launch_fin(H->st, FIN_BETA, H->part(), np, H->sc(), nullptr, nullptr, 0, 0.0);
     H->alg_bytes += (double)H->P.ncell * (H->P.esz + 16);
 }
@@ -578,21 +578,20 @@ PcgResult pcg(blob_rd* H, bool with_blobs, double alpha, const double* g, double
     auto iteration = [&](hipStream_t s_) {
         hipStream_t keep = H->st;
         H->st = s_;
-        double* po = pbuf[parity];
-        double* p = pbuf[parity ^ 1];
-        parity ^= 1;
-        launch_dir_apply<T>(s_, H->at<T>(P.off_lvl[0][0]), H->at<T>(P.off_lvl[0][1]), po, p, q, alpha, s, d.nx, d.ny,
-                            d.nz, H->part(), H->sc(), &np);
+        double* p = pbuf[0];
+        (void)parity;
+        launch_dir2<T>(s_, H->at<T>(P.off_lvl[0][0]), H->at<T>(P.off_lvl[0][1]), p, d.nx, d.ny, d.nz, H->sc());
+        launch_applyA2(s_, p, q, alpha, s, d.nx, d.ny, d.nz, H->part(), H->sc(), &np);
         if (blobs) {
             blob_term(H, p, q, H->sc());
             launch_fin(s_, FIN_ALPHA, H->part(), np, H->sc(), H->nv(0), H->nv(1), P.N, H->inv_h3());
         } else {
             launch_fin(s_, FIN_ALPHA, H->part(), np, H->sc(), nullptr, nullptr, 0, 0.0);
         }
-        launch_update(s_, x, r, p, q, P.ncell, H->part(), H->sc(), &np);
+        launch_update2(s_, x, r, p, q, P.ncell, H->part(), H->sc(), &np);
         launch_fin(s_, FIN_UPDATE, H->part(), np, H->sc(), nullptr, nullptr, 0, 0.0);
         precond_zdots<T>(H, alpha, r, q, cinv);
-        H->alg_bytes += (double)P.ncell * (P.esz + 24 + 48);
+        H->alg_bytes += (double)P.ncell * (P.esz / 2.0 + 16 + 16 + 48);
         H->st = keep;
     };
     blob_rd::GraphEntry* ge = nullptr;
@@ -1607,10 +1606,12 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
                     else launch_gs<double>(H->st, H->at<double>(P.off_lvl[0][1]), H->at<double>(P.off_lvl[0][0]),
                                            H->at<double>(P.off_lvl[0][3]), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, nullptr);
                     break;
-                case BLOB_RD_KERNEL_STENCIL:
-                    launch_applyA(H->st, H->grid(G_P), H->grid(G_Q), alpha, s, d.nx, d.ny, d.nz, H->part(), nullptr,
-                                  nullptr);
+                case BLOB_RD_KERNEL_STENCIL: {
+                    unsigned npp = 0;
+                    launch_applyA2(H->st, H->grid(G_P), H->grid(G_Q), alpha, s, d.nx, d.ny, d.nz, H->part(), nullptr,
+                                   &npp);
                     break;
+                }
                 case BLOB_RD_KERNEL_RESTRICT:
                     if (f32) {
                         launch_resid_split<float>(H->st, H->at<float>(P.off_lvl[0][0]), H->at<float>(P.off_lvl[0][1]),
@@ -1681,7 +1682,7 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
             case BLOB_RD_KERNEL_GS: *bytes = n * 0.5 * e * 3; break;              // other colour, f, own colour
             case BLOB_RD_KERNEL_STENCIL: *bytes = n * 16; break;                 // read x, write y (FP64)
             case BLOB_RD_KERNEL_RESTRICT: *bytes = n * e * 4 + n / 8 * e; break; // u, f read; r write+read; coarse f
-            case BLOB_RD_KERNEL_PROLONG: *bytes = n * e * 2 + n / 8 * e; break;  // u read+write, coarse read
+            case BLOB_RD_KERNEL_PROLONG: *bytes = n * e + n / 8 * e; break;  // red u read+write, coarse read
             default: {
                 double b = 0.0;
                 for (int l = 0; l + 1 < P.nlev; ++l) b += n / (double)(1 << (3 * l)) * e * (7 * 1.5 + 4 + 2 + 0.25);

@@ -53,6 +53,156 @@ void launch_applyA(hipStream_t st, const double* p, double* q, double alpha, dou
     if (np) *np = nb;
 }
 
+typedef double double2_t __attribute__((ext_vector_type(2)));
+
+// Two cells per thread (x even, x + 1) with 16-byte loads: q = alpha p - D L p,
+// partials (p.q, sum q). Same arithmetic and summation order as stencil_A.
+__global__ void __launch_bounds__(kBlock) k_applyA2(const double* __restrict__ p, double* __restrict__ q,
+                                                    double alpha, double s, int nx, int ny, int nz, unsigned npair,
+                                                    double* part, const Scalars* sc) {
+    if (sc && sc->done) return;
+    unsigned lo, hi;
+    chunk_of(xcd_block(blockIdx.x, gridDim.x), gridDim.x, npair, &lo, &hi);
+    double v[2] = {0.0, 0.0};
+    const int hx = nx >> 1;
+    const long long sxy = (long long)nx * ny;
+    for (unsigned k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+        const int X = 2 * (int)(k % hx);
+        const unsigned t = k / hx;
+        const int Y = t % ny, Z = t / ny;
+        const long long i = ((long long)Z * ny + Y) * nx + X;
+        const double2_t c = *reinterpret_cast<const double2_t*>(p + i);
+        const double xl = p[i - X + (X == 0 ? nx - 1 : X - 1)];
+        const double xr = p[i - X + (X + 2 == nx ? 0 : X + 2)];
+        const double2_t ym = *reinterpret_cast<const double2_t*>(p + i + (long long)(wrapi(Y - 1, ny) - Y) * nx);
+        const double2_t yp = *reinterpret_cast<const double2_t*>(p + i + (long long)(wrapi(Y + 1, ny) - Y) * nx);
+        const double2_t zm = *reinterpret_cast<const double2_t*>(p + i + (long long)(wrapi(Z - 1, nz) - Z) * sxy);
+        const double2_t zp = *reinterpret_cast<const double2_t*>(p + i + (long long)(wrapi(Z + 1, nz) - Z) * sxy);
+        double2_t y;
+        y[0] = alpha * c[0] - s * ((xl + c[1]) + (ym[0] + yp[0]) + (zm[0] + zp[0]) - 6.0 * c[0]);
+        y[1] = alpha * c[1] - s * ((c[0] + xr) + (ym[1] + yp[1]) + (zm[1] + zp[1]) - 6.0 * c[1]);
+        *reinterpret_cast<double2_t*>(q + i) = y;
+        v[0] += c[0] * y[0] + c[1] * y[1];
+        v[1] += y[0] + y[1];
+    }
+    if (part) block_partials<2>(v, part, gridDim.x, blockIdx.x);
+}
+
+void launch_applyA2(hipStream_t st, const double* p, double* q, double alpha, double s, int nx, int ny, int nz,
+                    double* part, const Scalars* sc, unsigned* np) {
+    const unsigned npair = (unsigned)(nx / 2) * ny * nz;
+    const unsigned nb = red_blocks(npair);
+    hipLaunchKernelGGL(k_applyA2, dim3(nb), dim3(kBlock), 0, st, p, q, alpha, s, nx, ny, nz, npair, part, sc);
+    *np = nb;
+}
+
+// p = z + shift + beta p, two cells per thread (z from the split level-0 arrays)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dir2(const T* __restrict__ z0, const T* __restrict__ z1,
+                                                 double* __restrict__ p, int nx, int ny, unsigned npair,
+                                                 const Scalars* sc) {
+    if (sc->done) return;
+    const unsigned k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (k >= npair) return;
+    const double beta = sc->beta, shift = sc->shift;
+    const int hx = nx >> 1;
+    const unsigned t = k / hx;
+    const int Y = t % ny, Z = t / ny;
+    const int par = (Y + Z) & 1;  // colour of the even cell
+    const double za = (double)(par ? z1[k] : z0[k]) + shift;
+    const double zb = (double)(par ? z0[k] : z1[k]) + shift;
+    double2_t* pp = reinterpret_cast<double2_t*>(p) + k;
+    double2_t v;
+    if (beta == 0.0) {
+        v[0] = za;
+        v[1] = zb;
+    } else {
+        const double2_t o = *pp;
+        v[0] = za + beta * o[0];
+        v[1] = zb + beta * o[1];
+    }
+    *pp = v;
+}
+
+template <typename T>
+void launch_dir2(hipStream_t st, const T* z0, const T* z1, double* p, int nx, int ny, int nz, const Scalars* sc) {
+    const unsigned npair = (unsigned)(nx / 2) * ny * nz;
+    hipLaunchKernelGGL(k_dir2<T>, dim3(nblocks(npair)), dim3(kBlock), 0, st, z0, z1, p, nx, ny, npair, sc);
+}
+template void launch_dir2<float>(hipStream_t, const float*, const float*, double*, int, int, int, const Scalars*);
+template void launch_dir2<double>(hipStream_t, const double*, const double*, double*, int, int, int, const Scalars*);
+
+// x += alpha p ; r -= alpha q ; partials (r.r, sum r), two cells per thread
+__global__ void __launch_bounds__(kBlock) k_update2(double* __restrict__ x, double* __restrict__ r,
+                                                    const double* __restrict__ p, const double* __restrict__ q,
+                                                    unsigned npair, double* part, const Scalars* sc) {
+    if (sc->done) return;
+    unsigned lo, hi;
+    chunk_of(xcd_block(blockIdx.x, gridDim.x), gridDim.x, npair, &lo, &hi);
+    double v[2] = {0.0, 0.0};
+    const double a = sc->alpha;
+    for (unsigned k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+        double2_t xv = reinterpret_cast<double2_t*>(x)[k];
+        double2_t rv = reinterpret_cast<double2_t*>(r)[k];
+        const double2_t pv = reinterpret_cast<const double2_t*>(p)[k];
+        const double2_t qv = reinterpret_cast<const double2_t*>(q)[k];
+        xv[0] += a * pv[0];
+        xv[1] += a * pv[1];
+        rv[0] -= a * qv[0];
+        rv[1] -= a * qv[1];
+        reinterpret_cast<double2_t*>(x)[k] = xv;
+        reinterpret_cast<double2_t*>(r)[k] = rv;
+        v[0] += rv[0] * rv[0] + rv[1] * rv[1];
+        v[1] += rv[0] + rv[1];
+    }
+    block_partials<2>(v, part, gridDim.x, blockIdx.x);
+}
+
+void launch_update2(hipStream_t st, double* x, double* r, const double* p, const double* q, size_t n, double* part,
+                    const Scalars* sc, unsigned* np) {
+    const unsigned npair = (unsigned)(n / 2);
+    const unsigned nb = red_blocks(npair);
+    hipLaunchKernelGGL(k_update2, dim3(nb), dim3(kBlock), 0, st, x, r, p, q, npair, part, sc);
+    *np = nb;
+}
+
+// partials (sum z, z.r, z.q), two cells per thread
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_zdots2(const T* __restrict__ z0, const T* __restrict__ z1,
+                                                   const double* __restrict__ r, const double* __restrict__ q,
+                                                   int nx, int ny, unsigned npair, double* part, const Scalars* sc) {
+    if (sc->done) return;
+    unsigned lo, hi;
+    chunk_of(xcd_block(blockIdx.x, gridDim.x), gridDim.x, npair, &lo, &hi);
+    double v[3] = {0.0, 0.0, 0.0};
+    const int hx = nx >> 1;
+    for (unsigned k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+        const unsigned t = k / hx;
+        const int par = ((int)(t % ny) + (int)(t / ny)) & 1;
+        const double za = (double)(par ? z1[k] : z0[k]);
+        const double zb = (double)(par ? z0[k] : z1[k]);
+        const double2_t rv = reinterpret_cast<const double2_t*>(r)[k];
+        const double2_t qv = reinterpret_cast<const double2_t*>(q)[k];
+        v[0] += za + zb;
+        v[1] += za * rv[0] + zb * rv[1];
+        v[2] += za * qv[0] + zb * qv[1];
+    }
+    block_partials<3>(v, part, gridDim.x, blockIdx.x);
+}
+
+template <typename T>
+void launch_zdots2(hipStream_t st, const T* z0, const T* z1, const double* r, const double* q, int nx, int ny, int nz,
+                   double* part, const Scalars* sc, unsigned* np) {
+    const unsigned npair = (unsigned)(nx / 2) * ny * nz;
+    const unsigned nb = red_blocks(npair);
+    hipLaunchKernelGGL(k_zdots2<T>, dim3(nb), dim3(kBlock), 0, st, z0, z1, r, q, nx, ny, npair, part, sc);
+    *np = nb;
+}
+template void launch_zdots2<float>(hipStream_t, const float*, const float*, const double*, const double*, int, int,
+                                   int, double*, const Scalars*, unsigned*);
+template void launch_zdots2<double>(hipStream_t, const double*, const double*, const double*, const double*, int,
+                                    int, int, double*, const Scalars*, unsigned*);
+
 // Fused CG direction update and operator apply:
 // p_new = z + shift + beta p_old at the cell and its 6 neighbours (z split of
 // type T), q = alpha p_new - D L p_new, partials (p_new . q, sum q).

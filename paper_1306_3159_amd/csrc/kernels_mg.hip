@@ -340,9 +340,57 @@ __global__ void __launch_bounds__(kBlock) k_prolong(const T* __restrict__ cu0, c
     }
 }
 
+// Red-only trilinear correction, VW red cells per thread. The V-cycle's
+// post-smoothing starts with a black half-sweep, which overwrites every black
+// value without reading it, so correcting black cells would be a dead store;
+// the result equals a correction of both colours followed by that sweep.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong_red(const T* __restrict__ cu0, const T* __restrict__ cu1,
+                                                        T* __restrict__ u0, int nx, int ny, int nz,
+                                                        const Scalars* sc) {
+    typedef typename VecOf<T>::type V;
+    constexpr int VW = VecOf<T>::W;
+    if (sc && sc->done) return;
+    const int hx = nx >> 1, hv = hx / VW;
+    const unsigned nv = (unsigned)hv * ny * nz;
+    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= nv) return;
+    const int iv = idx % hv;
+    const unsigned t = idx / hv;
+    const int y = t % ny, z = t / ny;
+    const int i0 = iv * VW;
+    const int cx = nx >> 1, cy = ny >> 1, cz = nz >> 1;
+    const int J0 = y >> 1, J1 = wrapi((y & 1) ? J0 + 1 : J0 - 1, cy);
+    const int K0 = z >> 1, K1 = wrapi((z & 1) ? K0 + 1 : K0 - 1, cz);
+    const int s0 = (y + z) & 1;  // red cell x = 2 i + s0, coarse I0 = i, I1 = i +/- 1
+    const size_t row = ((size_t)z * ny + y) * hx;
+    V u = *reinterpret_cast<const V*>(u0 + row + i0);
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+        const int I0 = i0 + k, I1 = wrapi(s0 ? I0 + 1 : I0 - 1, cx);
+        const T a00 = (T)0.75 * coarse_at(cu0, cu1, 0, I0, J0, K0, cx, cy) +
+                      (T)0.25 * coarse_at(cu0, cu1, 0, I1, J0, K0, cx, cy);
+        const T a10 = (T)0.75 * coarse_at(cu0, cu1, 0, I0, J1, K0, cx, cy) +
+                      (T)0.25 * coarse_at(cu0, cu1, 0, I1, J1, K0, cx, cy);
+        const T a01 = (T)0.75 * coarse_at(cu0, cu1, 0, I0, J0, K1, cx, cy) +
+                      (T)0.25 * coarse_at(cu0, cu1, 0, I1, J0, K1, cx, cy);
+        const T a11 = (T)0.75 * coarse_at(cu0, cu1, 0, I0, J1, K1, cx, cy) +
+                      (T)0.25 * coarse_at(cu0, cu1, 0, I1, J1, K1, cx, cy);
+        u[k] += (T)0.75 * ((T)0.75 * a00 + (T)0.25 * a10) + (T)0.25 * ((T)0.75 * a01 + (T)0.25 * a11);
+    }
+    *reinterpret_cast<V*>(u0 + row + i0) = u;
+}
+
 template <typename T>
 void launch_prolong(hipStream_t st, const T* cu0, const T* cu1, int coarse_natural, T* u0, T* u1, int nx, int ny,
                     int nz, const Scalars* sc) {
+    constexpr int VW = VecOf<T>::W;
+    const int hx = nx / 2;
+    if (!coarse_natural && hx % VW == 0 && hx >= VW) {
+        const unsigned nv = (unsigned)(hx / VW) * ny * nz;
+        hipLaunchKernelGGL(k_prolong_red<T>, dim3(nblocks(nv)), dim3(kBlock), 0, st, cu0, cu1, u0, nx, ny, nz, sc);
+        return;
+    }
     const unsigned nh = (unsigned)(nx / 2) * ny * nz;
     hipLaunchKernelGGL(k_prolong<T>, dim3(nblocks(nh)), dim3(kBlock), 0, st, cu0, cu1, coarse_natural, u0, u1, nx, ny,
                        nz, sc);
@@ -389,23 +437,44 @@ struct TailCells {
     int all[kTailPer], c0[kTailPer / 2], c1[kTailPer / 2];
 };
 
+// j -> (a, b, c) for dims (na, nb): shifts and masks when both are powers of two.
+__device__ __forceinline__ void tail_decode(int j, int na, int nb, int& a, int& b, int& c) {
+    if (((na & (na - 1)) | (nb & (nb - 1))) == 0) {
+        const int la = __ffs(na) - 1, lb = __ffs(nb) - 1;
+        a = j & (na - 1);
+        b = (j >> la) & (nb - 1);
+        c = j >> (la + lb);
+    } else {
+        a = j % na;
+        const int t = j / na;
+        b = t % nb;
+        c = t / nb;
+    }
+}
+
 __device__ __forceinline__ void tail_cells(TailCells& tc, int nx, int ny, int nz) {
     const int n = nx * ny * nz, hx = nx >> 1, nh = hx * ny * nz;
     tc.n_all = tc.n_c0 = tc.n_c1 = 0;
 #pragma unroll
     for (int k = 0; k < kTailPer; ++k) {
         const int j = threadIdx.x + k * blockDim.x;
-        const int x = j % nx, t = j / nx, y = t % ny, z = t / ny;
-        tc.all[k] = x | (y << 10) | (z << 20);
-        if (j < n) tc.n_all = k + 1;
+        if (j < n) {
+            int x, y, z;
+            tail_decode(j, nx, ny, x, y, z);
+            tc.all[k] = x | (y << 10) | (z << 20);
+            tc.n_all = k + 1;
+        }
     }
 #pragma unroll
     for (int k = 0; k < kTailPer / 2; ++k) {
         const int j = threadIdx.x + k * blockDim.x;
-        const int i = j % hx, t = j / hx, y = t % ny, z = t / ny;
-        tc.c0[k] = (2 * i + ((y + z) & 1)) | (y << 10) | (z << 20);
-        tc.c1[k] = (2 * i + (((y + z) & 1) ^ 1)) | (y << 10) | (z << 20);
-        if (j < nh) tc.n_c0 = tc.n_c1 = k + 1;
+        if (j < nh) {
+            int i, y, z;
+            tail_decode(j, hx, ny, i, y, z);
+            tc.c0[k] = (2 * i + ((y + z) & 1)) | (y << 10) | (z << 20);
+            tc.c1[k] = (2 * i + (((y + z) & 1) ^ 1)) | (y << 10) | (z << 20);
+            tc.n_c0 = tc.n_c1 = k + 1;
+        }
     }
 }
 

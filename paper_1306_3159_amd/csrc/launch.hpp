@@ -26,6 +26,17 @@ void launch_dir(hipStream_t st, const T* z0, const T* z1, double* p, int nx, int
 template <typename T>
 void launch_dir_apply(hipStream_t st, const T* z0, const T* z1, const double* po, double* pn, double* q, double alpha,
                       double s, int nx, int ny, int nz, double* part, const Scalars* sc, unsigned* nparts_out);
+// Two-cells-per-thread forms (nx even): stencil with partials, direction update,
+// CG update, z dots.
+void launch_applyA2(hipStream_t st, const double* p, double* q, double alpha, double s, int nx, int ny, int nz,
+                    double* part, const Scalars* sc, unsigned* nparts_out);
+template <typename T>
+void launch_dir2(hipStream_t st, const T* z0, const T* z1, double* p, int nx, int ny, int nz, const Scalars* sc);
+void launch_update2(hipStream_t st, double* x, double* r, const double* p, const double* q, size_t n, double* part,
+                    const Scalars* sc, unsigned* nparts_out);
+template <typename T>
+void launch_zdots2(hipStream_t st, const T* z0, const T* z1, const double* r, const double* q, int nx, int ny, int nz,
+                   double* part, const Scalars* sc, unsigned* nparts_out);
 // x += alpha p ; r -= alpha q ; partials (r.r, sum r)
 void launch_update(hipStream_t st, double* x, double* r, const double* p, const double* q, size_t n,
                    double* part, const Scalars* sc, unsigned* nparts_out);
