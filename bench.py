@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the comparison paths and the extra workload")
     ap.add_argument("--kernel-reps", type=int, default=100)
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="time candidate work-group sizes of the multigrid kernels before the timed solves")
     return ap.parse_args()
 
 
@@ -140,6 +142,10 @@ def main():
         S.precond_build(net)
     else:
         S = BlobRD(inst.n, q, precision=MIXED, rtol=rtol)
+    tuning = None
+    if args.autotune:
+        S.autotune(reps=10)
+        tuning = S.get_tuning().tolist()
     dt, st = timed(lambda: S.solve_absorbing(f)[2], args.steps, args.warmup)
     value = args.steps / dt
     learned = args.workload == "rsa256_learned"
@@ -152,11 +158,14 @@ def main():
                    "kernel_w": 4, "gmres_restart": 30, "path": "learned+fp32" if learned else "fp32",
                    "source": "f=1" if learned else "f=1+0.5N(0,1)", "seed": inst.seed},
         "solve": summary(st),
+        "tuning": tuning,
     }
     out["solve"]["alg_GBs"] = st["alg_bytes"] / (dt / args.steps) / 1e9
 
     if not args.no_extra:
         P = BlobRD(inst.n, q, precision=FP64, rtol=rtol)
+        if args.autotune:
+            P.autotune(reps=10)
         pdt, pst = timed(lambda: P.solve_absorbing(f)[2], max(2, args.steps // 2), 1)
         n = max(2, args.steps // 2)
         out["plain_fp64"] = {"value": n / pdt, "ms_per_step": 1e3 * pdt / n, **summary(pst)}
@@ -164,6 +173,8 @@ def main():
         P.close()
         if learned:
             M = BlobRD(inst.n, q, precision=MIXED, rtol=rtol)
+            if args.autotune:
+                M.autotune(reps=10)
             mdt, mst = timed(lambda: M.solve_absorbing(f)[2], n, 1)
             out["fp32_no_learned"] = {"value": n / mdt, "ms_per_step": 1e3 * mdt / n, **summary(mst)}
             M.close()

@@ -233,6 +233,41 @@ int blob_rd_solve_batch(blob_rd_t* h, int32_t n, const int32_t* kind, double alp
  * (each input read once, each output written once). */
 int blob_rd_time_kernel(blob_rd_t h, int kernel, int reps, double* avg_ms, double* bytes);
 
+/* ---- Launch-shape autotuning ----
+ *
+ * The multigrid kernels launched per level (Gauss-Seidel half-sweep,
+ * residual, restriction, prolongation; the single-work-group coarse tail is
+ * not tuned) take their work-group size from a per-handle table,
+ * BLOB_RD_TUNE_KINDS entries per level, level-major, finest level first.
+ * Every entry is one of 64, 128, 256, 512; the default is 256. The choice
+ * changes timing only: each kernel updates every cell independently of how
+ * cells are grouped, so solves are bitwise identical for any table. */
+#define BLOB_RD_TUNE_KINDS 4
+
+/* Number of levels with per-level launches for this handle's precision
+ * (the table then has 4 * that many entries). */
+int blob_rd_tune_levels(blob_rd_t h);
+
+/* Copy the table out (n_entries >= 4 * levels) or replace it (every entry
+ * validated, else BLOB_RD_EINVAL and nothing changes). Replacing it drops
+ * the handle's captured graphs, which are captured again on next use. */
+int blob_rd_get_tuning(blob_rd_t h, int32_t* table, int32_t n_entries);
+int blob_rd_set_tuning(blob_rd_t h, const int32_t* table, int32_t n_entries);
+
+/* Time every candidate work-group size of every tuned kernel on every
+ * level (reps back-to-back launches each, HIP events on the handle's
+ * stream, on the handle's workspace, whose contents are overwritten) and
+ * keep the fastest; the default size stays unless another is at least 3%
+ * faster. cache_path (NULL: the environment variable BLOB_RD_TUNE_CACHE,
+ * if set; NULL and unset: no cache) names a JSON object file mapping
+ * "<gfx arch>|<f32|f64>|<nx>x<ny>x<nz>|<gs|resid|restrict|prolong>" to a
+ * work-group size, keyed by the level's own dimensions so that handles of
+ * different sizes share entries. Levels whose four entries are all found
+ * there are not timed; the newly timed ones are merged into the file
+ * (written to a temporary file, then renamed). *timed (may be NULL)
+ * receives the number of levels timed. Synchronises the handle's stream. */
+int blob_rd_autotune(blob_rd_t h, int32_t reps, const char* cache_path, int32_t* timed);
+
 #ifdef __cplusplus
 }
 #endif

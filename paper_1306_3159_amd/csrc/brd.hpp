@@ -21,6 +21,7 @@
 namespace brd {
 
 constexpr int kBlock = 256;
+constexpr int kMaxTuneBlock = 512;  // largest work-group the autotuner may pick
 constexpr int kFinBlock = 1024;
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarse = 512;

@@ -17,6 +17,7 @@
 // Every solve ends with an FP64 residual of the returned answer and, when
 // that misses the target, iterative refinement on the residual equations.
 #include <hip/hip_runtime.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <atomic>
@@ -26,6 +27,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -283,6 +285,9 @@ struct blob_rd {
     int inner_iters = 0;
     int last_iters[4] = {0, 0, 0, 0};  // CG iterations of the previous solve per (blobs, alpha == 0)
     int tail_level[2] = {1 << 20, 1 << 20};  // first level of the LDS tail for FP32 / FP64 (>= nlev-1: none)
+    // Work-group size per (level, multigrid kernel): Gauss-Seidel, residual, restriction,
+    // prolongation. kBlock until blob_rd_autotune picks others.
+    int bs[kMaxLevels][4];
     // CG iteration pairs captured as HIP graphs, keyed by (precision, blobs, alpha).
     struct GraphEntry {
         int esz;
@@ -447,15 +452,16 @@ void vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const 
         for (int l = 0; l < t; ++l) {
             const LevelDims& d = P.lev[l];
             const double s = D / (d.h * d.h), diag = alpha + 6.0 * s;
-            launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc);
-            launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc);
-            launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc);
+            const int* b = H->bs[l];
+            launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
+            launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
+            launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
             launch_resid_split<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), lv(l, 3), lv(l, 4), lv(l, 5), d.hx, d.ny, d.nz,
-                                  s, diag, sc);
+                                  s, diag, sc, b[1]);
             const LevelDims& c = P.lev[l + 1];
             const double sc_ = D / (c.h * c.h);
             launch_restrict<T>(st, lv(l, 4), lv(l, 5), d.nx, d.ny, d.nz, lv(l + 1, 2), lv(l + 1, 3), lv(l + 1, 0), 0,
-                               1.0 / (alpha + 6.0 * sc_), sc);
+                               1.0 / (alpha + 6.0 * sc_), sc, b[2]);
             H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * (3 * 1.5 + 3 + 1.125);
         }
         const TailDesc td = make_tail<T>(H, t, alpha);
@@ -463,11 +469,12 @@ void vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const 
         for (int l = t - 1; l >= 0; --l) {
             const LevelDims& d = P.lev[l];
             const double s = D / (d.h * d.h), diag = alpha + 6.0 * s;
-            launch_prolong<T>(st, lv(l + 1, 0), lv(l + 1, 1), 0, lv(l, 0), lv(l, 1), d.nx, d.ny, d.nz, sc);
-            launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc);
-            launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc);
-            launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc);
-            launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc);
+            const int* b = H->bs[l];
+            launch_prolong<T>(st, lv(l + 1, 0), lv(l + 1, 1), 0, lv(l, 0), lv(l, 1), d.nx, d.ny, d.nz, sc, b[3]);
+            launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
+            launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
+            launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
+            launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
             H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * (4 * 1.5 + 2.125);
         }
         H->alg_bytes += (double)P.ncell * (8 + P.esz * 1.5);
@@ -477,19 +484,20 @@ void vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const 
     for (int l = 0; l < L; ++l) {
         const LevelDims& d = P.lev[l];
         const double s = D / (d.h * d.h), diag = alpha + 6.0 * s;
-        launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc);
-        launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc);
-        launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc);
+        const int* b = H->bs[l];
+        launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
+        launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
+        launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
         launch_resid_split<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), lv(l, 3), lv(l, 4), lv(l, 5), d.hx, d.ny, d.nz, s,
-                              diag, sc);
+                              diag, sc, b[1]);
         const int cnat = (l + 1 == L);
         const LevelDims& c = P.lev[l + 1];
         const double sc_ = D / (c.h * c.h);
         if (cnat)
-            launch_restrict<T>(st, lv(l, 4), lv(l, 5), d.nx, d.ny, d.nz, lv(L, 2), nullptr, nullptr, 1, 0.0, sc);
+            launch_restrict<T>(st, lv(l, 4), lv(l, 5), d.nx, d.ny, d.nz, lv(L, 2), nullptr, nullptr, 1, 0.0, sc, b[2]);
         else
             launch_restrict<T>(st, lv(l, 4), lv(l, 5), d.nx, d.ny, d.nz, lv(l + 1, 2), lv(l + 1, 3), lv(l + 1, 0), 0,
-                               1.0 / (alpha + 6.0 * sc_), sc);
+                               1.0 / (alpha + 6.0 * sc_), sc, b[2]);
         H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * (3 * 1.5 + 3 + 1.125);
     }
     launch_coarse<T>(st, lv(L, 2), lv(L, 0), cinv, P.m, sc);
@@ -497,12 +505,13 @@ void vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const 
         const LevelDims& d = P.lev[l];
         const double s = D / (d.h * d.h), diag = alpha + 6.0 * s;
         const int cnat = (l + 1 == L);
+        const int* b = H->bs[l];
         launch_prolong<T>(st, lv(l + 1, 0), cnat ? nullptr : lv(l + 1, 1), cnat, lv(l, 0), lv(l, 1), d.nx, d.ny, d.nz,
-                          sc);
-        launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc);
-        launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc);
-        launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc);
-        launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc);
+                          sc, b[3]);
+        launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
+        launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
+        launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
+        launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
         H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * (4 * 1.5 + 2.125);
     }
     H->alg_bytes += (double)P.ncell * (8 + P.esz * 1.5);
@@ -1021,6 +1030,8 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
     H->prm = *p;
     H->st = (hipStream_t)p->stream;
     if (const char* g = std::getenv("BLOB_RD_GRAPHS")) H->use_graphs = std::atoi(g) != 0;
+    for (auto& row : H->bs)
+        for (int& v : row) v = kBlock;
     if (const char* g = std::getenv("BLOB_RD_RELAX")) H->relax = std::atoi(g) != 0;
     // Align the workspace base to 256 bytes.
     uintptr_t base = (uintptr_t)p->workspace;
@@ -1311,6 +1322,116 @@ size_t learned_bytes(int N, long long nnz) {
 }
 }  // namespace
 
+namespace {
+
+// Defined (zero) contents for every multigrid level buffer, before kernels are
+// timed on them outside a solve.
+void zero_levels(blob_rd* H) {
+    const Plan& P = H->P;
+    const int L = P.nlev - 1;
+    for (int l = 0; l < std::max(L, 1); ++l) {
+        const size_t hl = (size_t)P.lev[l].hx * P.lev[l].ny * P.lev[l].nz;
+        const int nb = (L == 0) ? 4 : 6;
+        for (int k = 0; k < nb; ++k) HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[l][k], 0, hl * P.esz, H->st));
+    }
+    if (L > 0) {
+        HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[L][0], 0, (size_t)P.m * P.esz, H->st));
+        HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[L][2], 0, (size_t)P.m * P.esz, H->st));
+    }
+}
+
+// Levels launched one kernel at a time (above the LDS tail or the dense coarse solve).
+int tuned_levels(const blob_rd* H) {
+    const int L = H->P.nlev - 1;
+    const int t = H->tail_level[H->P.esz == 4 ? 0 : 1];
+    return std::max(0, std::min(t, L));
+}
+
+const char* const kTuneKind[BLOB_RD_TUNE_KINDS] = {"gs", "resid", "restrict", "prolong"};
+const int kTuneCand[4] = {64, 128, 256, 512};
+
+// One launch of tuned kernel `kind` on level l with work-group size bs.
+template <typename T>
+void tune_launch(blob_rd* H, int l, int kind, int bs) {
+    const Plan& P = H->P;
+    const int L = P.nlev - 1;
+    const bool tail = H->tail_level[sizeof(T) == 4 ? 0 : 1] < L;
+    const int cnat = (!tail && l + 1 == L);
+    auto lv = [&](int ll, int k) { return H->at<T>(P.off_lvl[ll][k]); };
+    const LevelDims& d = P.lev[l];
+    const double s = H->prm.D / (d.h * d.h), diag = 6.0 * s;
+    switch (kind) {
+        case 0: launch_gs<T>(H->st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, nullptr, bs); break;
+        case 1:
+            launch_resid_split<T>(H->st, lv(l, 0), lv(l, 1), lv(l, 2), lv(l, 3), lv(l, 4), lv(l, 5), d.hx, d.ny, d.nz,
+                                  s, diag, nullptr, bs);
+            break;
+        case 2: {
+            const LevelDims& c = P.lev[l + 1];
+            launch_restrict<T>(H->st, lv(l, 4), lv(l, 5), d.nx, d.ny, d.nz, lv(l + 1, 2), cnat ? nullptr : lv(l + 1, 3),
+                               cnat ? nullptr : lv(l + 1, 0), cnat, 1.0 / (6.0 * H->prm.D / (c.h * c.h)), nullptr, bs);
+            break;
+        }
+        default:
+            launch_prolong<T>(H->st, lv(l + 1, 0), cnat ? nullptr : lv(l + 1, 1), cnat, lv(l, 0), lv(l, 1), d.nx, d.ny,
+                              d.nz, nullptr, bs);
+    }
+}
+
+std::string tune_key(const std::string& arch, int esz, const LevelDims& d, int kind) {
+    return arch + "|" + (esz == 4 ? "f32" : "f64") + "|" + std::to_string(d.nx) + "x" + std::to_string(d.ny) + "x" +
+           std::to_string(d.nz) + "|" + kTuneKind[kind];
+}
+
+// The cache file is one flat JSON object of "key": integer pairs, as written below.
+std::map<std::string, int> tune_cache_read(const char* path) {
+    std::map<std::string, int> m;
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return m;
+    std::string txt;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, fp)) > 0) txt.append(buf, got);
+    std::fclose(fp);
+    size_t i = 0;
+    while ((i = txt.find('"', i)) != std::string::npos) {
+        const size_t j = txt.find('"', i + 1);
+        if (j == std::string::npos) break;
+        const std::string key = txt.substr(i + 1, j - i - 1);
+        size_t k = txt.find(':', j);
+        if (k == std::string::npos) break;
+        m[key] = std::atoi(txt.c_str() + k + 1);
+        i = txt.find_first_of(",}", k);
+        if (i == std::string::npos) break;
+    }
+    return m;
+}
+
+bool tune_cache_write(const char* path, const std::map<std::string, int>& m) {
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long long)getpid());
+    FILE* fp = std::fopen(tmp.c_str(), "wb");
+    if (!fp) return false;
+    std::fputs("{\n", fp);
+    size_t i = 0;
+    for (const auto& kv : m) std::fprintf(fp, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < m.size() ? "," : "");
+    std::fputs("}\n", fp);
+    const bool ok = std::fclose(fp) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+bool valid_block(int v) {
+    for (int c : kTuneCand)
+        if (v == c) return true;
+    return false;
+}
+
+void drop_graphs(blob_rd* H) {
+    for (auto& g : H->graphs) (void)hipGraphExecDestroy(g.exec);
+    H->graphs.clear();
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t blob_rd_net_workspace_bytes(void) { return net_bytes(); }
@@ -1577,19 +1698,8 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
         const Plan& P = H->P;
         const LevelDims& d = P.lev[0];
         const double alpha = 0.0, s = H->prm.D / (d.h * d.h), diag = alpha + 6.0 * s;
-        const size_t half = (size_t)d.hx * d.ny * d.nz;
         const double* cinv = select_cinv(H, alpha);
-        // Defined contents for every buffer the kernels read.
-        for (int k = 0; k < 6; ++k) HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[0][k], 0, half * P.esz, H->st));
-        if (P.nlev > 1) {
-            const int L = P.nlev - 1;
-            for (int l = 1; l < L; ++l) {
-                const size_t hl = (size_t)P.lev[l].hx * P.lev[l].ny * P.lev[l].nz;
-                for (int k = 0; k < 6; ++k) HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[l][k], 0, hl * P.esz, H->st));
-            }
-            HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[L][0], 0, (size_t)P.m * P.esz, H->st));
-            HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[L][2], 0, (size_t)P.m * P.esz, H->st));
-        }
+        zero_levels(H);
         HIPCHK(hipMemsetAsync(H->grid(G_P), 0, P.ncell * 8, H->st));
         HIPCHK(hipMemsetAsync(H->grid(G_R), 0, P.ncell * 8, H->st));
         hipEvent_t e0, e1;
@@ -1690,6 +1800,104 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
             }
         }
         HIPCHK(hipGetLastError());
+        return BLOB_RD_OK;
+    });
+}
+
+int blob_rd_tune_levels(blob_rd_t H) {
+    if (!H) return g_last_error = "null handle", BLOB_RD_EINVAL;
+    return tuned_levels(H);
+}
+
+int blob_rd_get_tuning(blob_rd_t H, int32_t* table, int32_t n_entries) {
+    if (!H || !table) return g_last_error = "bad argument", BLOB_RD_EINVAL;
+    const int nl = tuned_levels(H);
+    if (n_entries < nl * BLOB_RD_TUNE_KINDS) return g_last_error = "table too small", BLOB_RD_EINVAL;
+    for (int l = 0; l < nl; ++l)
+        for (int k = 0; k < BLOB_RD_TUNE_KINDS; ++k) table[l * BLOB_RD_TUNE_KINDS + k] = H->bs[l][k];
+    return BLOB_RD_OK;
+}
+
+int blob_rd_set_tuning(blob_rd_t H, const int32_t* table, int32_t n_entries) {
+    if (!H || !table) return g_last_error = "bad argument", BLOB_RD_EINVAL;
+    const int nl = tuned_levels(H);
+    if (n_entries < nl * BLOB_RD_TUNE_KINDS) return g_last_error = "table too small", BLOB_RD_EINVAL;
+    for (int i = 0; i < nl * BLOB_RD_TUNE_KINDS; ++i)
+        if (!valid_block(table[i]))
+            return g_last_error = "work-group size " + std::to_string(table[i]) + " is not 64, 128, 256 or 512",
+                   BLOB_RD_EINVAL;
+    for (int l = 0; l < nl; ++l)
+        for (int k = 0; k < BLOB_RD_TUNE_KINDS; ++k) H->bs[l][k] = table[l * BLOB_RD_TUNE_KINDS + k];
+    drop_graphs(H);
+    return BLOB_RD_OK;
+}
+
+int blob_rd_autotune(blob_rd_t H, int32_t reps, const char* cache_path, int32_t* timed) {
+    if (!H || reps <= 0) return g_last_error = "bad argument", BLOB_RD_EINVAL;
+    if (!cache_path) cache_path = std::getenv("BLOB_RD_TUNE_CACHE");
+    return guarded(H, nullptr, [&]() {
+        const Plan& P = H->P;
+        const int nl = tuned_levels(H);
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        hipDeviceProp_t prop;
+        HIPCHK(hipGetDeviceProperties(&prop, dev));
+        std::string arch = prop.gcnArchName;
+        arch = arch.substr(0, arch.find(':'));
+        std::map<std::string, int> cache;
+        if (cache_path) cache = tune_cache_read(cache_path);
+        int ntimed = 0;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        for (int l = 0; l < nl; ++l) {
+            int found[BLOB_RD_TUNE_KINDS];
+            bool all = true;
+            for (int k = 0; k < BLOB_RD_TUNE_KINDS; ++k) {
+                auto it = cache.find(tune_key(arch, P.esz, P.lev[l], k));
+                found[k] = (it != cache.end() && valid_block(it->second)) ? it->second : 0;
+                all = all && found[k];
+            }
+            if (all) {
+                for (int k = 0; k < BLOB_RD_TUNE_KINDS; ++k) H->bs[l][k] = found[k];
+                continue;
+            }
+            if (!e0) {
+                HIPCHK(hipEventCreate(&e0));
+                HIPCHK(hipEventCreate(&e1));
+                zero_levels(H);
+            }
+            for (int k = 0; k < BLOB_RD_TUNE_KINDS; ++k) {
+                float best = 0.f, def = 0.f;
+                int pick = kBlock;
+                for (int c : kTuneCand) {
+                    auto one = [&]() {
+                        if (P.esz == 4) tune_launch<float>(H, l, k, c);
+                        else tune_launch<double>(H, l, k, c);
+                    };
+                    one();
+                    HIPCHK(hipEventRecord(e0, H->st));
+                    for (int r = 0; r < reps; ++r) one();
+                    HIPCHK(hipEventRecord(e1, H->st));
+                    HIPCHK(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                    if (c == kBlock) def = ms;
+                    if (best == 0.f || ms < best) best = ms, pick = c;
+                }
+                if (best > 0.97f * def) pick = kBlock;
+                H->bs[l][k] = pick;
+                cache[tune_key(arch, P.esz, P.lev[l], k)] = pick;
+            }
+            ++ntimed;
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        HIPCHK(hipGetLastError());
+        drop_graphs(H);
+        if (timed) *timed = ntimed;
+        if (cache_path && ntimed > 0 && !tune_cache_write(cache_path, cache)) {
+            g_last_error = std::string("cannot write tuning cache ") + cache_path;
+            return BLOB_RD_EINVAL;
+        }
         return BLOB_RD_OK;
     });
 }

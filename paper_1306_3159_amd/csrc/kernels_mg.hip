@@ -63,7 +63,7 @@ void launch_enter(hipStream_t st, const double* r, T* f0, T* f1, T* u0, int nx, 
 // ---------------------------------------------------------------------------
 // Gauss-Seidel half-sweep on colour `color`: u_c = (f_c + s * sum nbrs) / diag.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_gs(T* __restrict__ uc, const T* __restrict__ uo,
+__global__ void __launch_bounds__(kMaxTuneBlock) k_gs(T* __restrict__ uc, const T* __restrict__ uo,
                                                const T* __restrict__ fc, int hx, int ny, int nz, int color, T s,
                                                T inv_diag, const Scalars* sc) {
     if (sc && sc->done) return;
@@ -110,7 +110,7 @@ __device__ __forceinline__ void row_neighbours(const T* __restrict__ orow, int i
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_gs_vec(T* __restrict__ uc, const T* __restrict__ uo,
+__global__ void __launch_bounds__(kMaxTuneBlock) k_gs_vec(T* __restrict__ uc, const T* __restrict__ uo,
                                                    const T* __restrict__ fc, int hx, int ny, int nz, int color, T s,
                                                    T inv_diag, const Scalars* sc) {
     typedef typename VecOf<T>::type V;
@@ -141,23 +141,23 @@ __global__ void __launch_bounds__(kBlock) k_gs_vec(T* __restrict__ uc, const T* 
 
 template <typename T>
 void launch_gs(hipStream_t st, T* uc, const T* uo, const T* fc, int hx, int ny, int nz, int color, double s,
-               double inv_diag, const Scalars* sc) {
+               double inv_diag, const Scalars* sc, int bs) {
     constexpr int VW = VecOf<T>::W;
     if (hx % VW == 0 && hx >= VW) {
         const unsigned nv = (unsigned)(hx / VW) * ny * nz;
-        hipLaunchKernelGGL(k_gs_vec<T>, dim3(nblocks(nv)), dim3(kBlock), 0, st, uc, uo, fc, hx, ny, nz, color, (T)s,
+        hipLaunchKernelGGL(k_gs_vec<T>, dim3(nblocks(nv, bs)), dim3(bs), 0, st, uc, uo, fc, hx, ny, nz, color, (T)s,
                            (T)inv_diag, sc);
         return;
     }
     const unsigned nh = (unsigned)hx * ny * nz;
-    hipLaunchKernelGGL(k_gs<T>, dim3(nblocks(nh)), dim3(kBlock), 0, st, uc, uo, fc, hx, ny, nz, color, (T)s,
+    hipLaunchKernelGGL(k_gs<T>, dim3(nblocks(nh, bs)), dim3(bs), 0, st, uc, uo, fc, hx, ny, nz, color, (T)s,
                        (T)inv_diag, sc);
 }
 
 // ---------------------------------------------------------------------------
 // Residual r = f - (diag u - s sum nbrs) for both colours.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_resid(const T* __restrict__ u0, const T* __restrict__ u1,
+__global__ void __launch_bounds__(kMaxTuneBlock) k_resid(const T* __restrict__ u0, const T* __restrict__ u1,
                                                   const T* __restrict__ f0, const T* __restrict__ f1,
                                                   T* __restrict__ r0, T* __restrict__ r1, int hx, int ny, int nz,
                                                   T s, T diag, const Scalars* sc) {
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(kBlock) k_resid(const T* __restrict__ u0, cons
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_resid_vec(const T* __restrict__ u0, const T* __restrict__ u1,
+__global__ void __launch_bounds__(kMaxTuneBlock) k_resid_vec(const T* __restrict__ u0, const T* __restrict__ u1,
                                                       const T* __restrict__ f0, const T* __restrict__ f1,
                                                       T* __restrict__ r0, T* __restrict__ r1, int hx, int ny, int nz,
                                                       T s, T diag, const Scalars* sc) {
@@ -217,16 +217,16 @@ __global__ void __launch_bounds__(kBlock) k_resid_vec(const T* __restrict__ u0, 
 
 template <typename T>
 void launch_resid_split(hipStream_t st, const T* u0, const T* u1, const T* f0, const T* f1, T* r0, T* r1, int hx,
-                        int ny, int nz, double s, double diag, const Scalars* sc) {
+                        int ny, int nz, double s, double diag, const Scalars* sc, int bs) {
     constexpr int VW = VecOf<T>::W;
     if (hx % VW == 0 && hx >= VW) {
         const unsigned nv = (unsigned)(hx / VW) * ny * nz;
-        hipLaunchKernelGGL(k_resid_vec<T>, dim3(nblocks(nv)), dim3(kBlock), 0, st, u0, u1, f0, f1, r0, r1, hx, ny,
+        hipLaunchKernelGGL(k_resid_vec<T>, dim3(nblocks(nv, bs)), dim3(bs), 0, st, u0, u1, f0, f1, r0, r1, hx, ny,
                            nz, (T)s, (T)diag, sc);
         return;
     }
     const unsigned nh = (unsigned)hx * ny * nz;
-    hipLaunchKernelGGL(k_resid<T>, dim3(nblocks(nh)), dim3(kBlock), 0, st, u0, u1, f0, f1, r0, r1, hx, ny, nz, (T)s,
+    hipLaunchKernelGGL(k_resid<T>, dim3(nblocks(nh, bs)), dim3(bs), 0, st, u0, u1, f0, f1, r0, r1, hx, ny, nz, (T)s,
                        (T)diag, sc);
 }
 
@@ -236,7 +236,7 @@ void launch_resid_split(hipStream_t st, const T* u0, const T* u1, const T* f0, c
 // coarse right-hand side in split layout together with the zero-guess red
 // half-sweep, or in natural layout on the coarsest level.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_restrict(const T* __restrict__ r0, const T* __restrict__ r1, int nx,
+__global__ void __launch_bounds__(kMaxTuneBlock) k_restrict(const T* __restrict__ r0, const T* __restrict__ r1, int nx,
                                                      int ny, int nz, T* __restrict__ cf0, T* __restrict__ cf1,
                                                      T* __restrict__ cu0, int coarse_natural, T inv_diag_c,
                                                      const Scalars* sc) {
@@ -289,9 +289,9 @@ __global__ void __launch_bounds__(kBlock) k_restrict(const T* __restrict__ r0, c
 
 template <typename T>
 void launch_restrict(hipStream_t st, const T* r0, const T* r1, int nx, int ny, int nz, T* cf0, T* cf1, T* cu0,
-                     int coarse_natural, double inv_diag_c, const Scalars* sc) {
+                     int coarse_natural, double inv_diag_c, const Scalars* sc, int bs) {
     const unsigned nc = (unsigned)(nx / 2) * (ny / 2) * (nz / 2);
-    hipLaunchKernelGGL(k_restrict<T>, dim3(nblocks(nc)), dim3(kBlock), 0, st, r0, r1, nx, ny, nz, cf0, cf1, cu0,
+    hipLaunchKernelGGL(k_restrict<T>, dim3(nblocks(nc, bs)), dim3(bs), 0, st, r0, r1, nx, ny, nz, cf0, cf1, cu0,
                        coarse_natural, (T)inv_diag_c, sc);
 }
 
@@ -307,7 +307,7 @@ __device__ __forceinline__ T coarse_at(const T* __restrict__ c0, const T* __rest
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_prolong(const T* __restrict__ cu0, const T* __restrict__ cu1, int nat,
+__global__ void __launch_bounds__(kMaxTuneBlock) k_prolong(const T* __restrict__ cu0, const T* __restrict__ cu1, int nat,
                                                     T* __restrict__ u0, T* __restrict__ u1, int nx, int ny, int nz,
                                                     const Scalars* sc) {
     if (sc && sc->done) return;
@@ -345,7 +345,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong(const T* __restrict__ cu0, c
 // value without reading it, so correcting black cells would be a dead store;
 // the result equals a correction of both colours followed by that sweep.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_prolong_red(const T* __restrict__ cu0, const T* __restrict__ cu1,
+__global__ void __launch_bounds__(kMaxTuneBlock) k_prolong_red(const T* __restrict__ cu0, const T* __restrict__ cu1,
                                                         T* __restrict__ u0, int nx, int ny, int nz,
                                                         const Scalars* sc) {
     typedef typename VecOf<T>::type V;
@@ -383,16 +383,16 @@ __global__ void __launch_bounds__(kBlock) k_prolong_red(const T* __restrict__ cu
 
 template <typename T>
 void launch_prolong(hipStream_t st, const T* cu0, const T* cu1, int coarse_natural, T* u0, T* u1, int nx, int ny,
-                    int nz, const Scalars* sc) {
+                    int nz, const Scalars* sc, int bs) {
     constexpr int VW = VecOf<T>::W;
     const int hx = nx / 2;
     if (!coarse_natural && hx % VW == 0 && hx >= VW) {
         const unsigned nv = (unsigned)(hx / VW) * ny * nz;
-        hipLaunchKernelGGL(k_prolong_red<T>, dim3(nblocks(nv)), dim3(kBlock), 0, st, cu0, cu1, u0, nx, ny, nz, sc);
+        hipLaunchKernelGGL(k_prolong_red<T>, dim3(nblocks(nv, bs)), dim3(bs), 0, st, cu0, cu1, u0, nx, ny, nz, sc);
         return;
     }
     const unsigned nh = (unsigned)(nx / 2) * ny * nz;
-    hipLaunchKernelGGL(k_prolong<T>, dim3(nblocks(nh)), dim3(kBlock), 0, st, cu0, cu1, coarse_natural, u0, u1, nx, ny,
+    hipLaunchKernelGGL(k_prolong<T>, dim3(nblocks(nh, bs)), dim3(bs), 0, st, cu0, cu1, coarse_natural, u0, u1, nx, ny,
                        nz, sc);
 }
 
@@ -427,23 +427,17 @@ void launch_coarse(hipStream_t st, const T* f, T* u, const double* cinv, int m, 
 // order, so it is interchangeable with them: zero initial guess, R B R B
 // pre-smoothing, residual, full weighting, coarse dense solve, trilinear
 // correction, B R B R post-smoothing.
-constexpr int kTailPer = 16;  // max cells per thread in a tail level (16 * 1024 cells)
+// Thread-strided loops over each level's cells; cell coordinates are decoded
+// on the fly (shifts and masks for power-of-two dimensions), so no per-thread
+// cell tables are kept live across the barriers.
+__device__ __forceinline__ bool tail_pow2(int a) { return (a & (a - 1)) == 0; }
 
-// Packed cell coordinates (x | y << 10 | z << 20) of the cells a thread owns
-// in one level, for the full grid and for each colour. Loops over them are
-// unrolled to compile-time indices so the arrays stay in registers.
-struct TailCells {
-    int n_all, n_c0, n_c1;
-    int all[kTailPer], c0[kTailPer / 2], c1[kTailPer / 2];
-};
-
-// j -> (a, b, c) for dims (na, nb): shifts and masks when both are powers of two.
-__device__ __forceinline__ void tail_decode(int j, int na, int nb, int& a, int& b, int& c) {
-    if (((na & (na - 1)) | (nb & (nb - 1))) == 0) {
-        const int la = __ffs(na) - 1, lb = __ffs(nb) - 1;
+// j -> (a, b, c) for row-major dims (na, nb, *).
+__device__ __forceinline__ void tail_decode(int j, int na, int nb, bool p2, int la, int lab, int& a, int& b, int& c) {
+    if (p2) {
         a = j & (na - 1);
         b = (j >> la) & (nb - 1);
-        c = j >> (la + lb);
+        c = j >> lab;
     } else {
         a = j % na;
         const int t = j / na;
@@ -452,35 +446,19 @@ __device__ __forceinline__ void tail_decode(int j, int na, int nb, int& a, int& 
     }
 }
 
-__device__ __forceinline__ void tail_cells(TailCells& tc, int nx, int ny, int nz) {
-    const int n = nx * ny * nz, hx = nx >> 1, nh = hx * ny * nz;
-    tc.n_all = tc.n_c0 = tc.n_c1 = 0;
-#pragma unroll
-    for (int k = 0; k < kTailPer; ++k) {
-        const int j = threadIdx.x + k * blockDim.x;
-        if (j < n) {
-            int x, y, z;
-            tail_decode(j, nx, ny, x, y, z);
-            tc.all[k] = x | (y << 10) | (z << 20);
-            tc.n_all = k + 1;
-        }
+// Decoder of one (na, nb) plane shape: uniform across the work-group.
+struct TailDec {
+    int na, nb, la, lab;
+    bool p2;
+    __device__ __forceinline__ TailDec(int a, int b) : na(a), nb(b) {
+        p2 = tail_pow2(a) && tail_pow2(b);
+        la = __ffs(a) - 1;
+        lab = la + __ffs(b) - 1;
     }
-#pragma unroll
-    for (int k = 0; k < kTailPer / 2; ++k) {
-        const int j = threadIdx.x + k * blockDim.x;
-        if (j < nh) {
-            int i, y, z;
-            tail_decode(j, hx, ny, i, y, z);
-            tc.c0[k] = (2 * i + ((y + z) & 1)) | (y << 10) | (z << 20);
-            tc.c1[k] = (2 * i + (((y + z) & 1) ^ 1)) | (y << 10) | (z << 20);
-            tc.n_c0 = tc.n_c1 = k + 1;
-        }
+    __device__ __forceinline__ void operator()(int j, int& x, int& y, int& z) const {
+        tail_decode(j, na, nb, p2, la, lab, x, y, z);
     }
-}
-
-#define TAIL_X(p) ((p) & 1023)
-#define TAIL_Y(p) (((p) >> 10) & 1023)
-#define TAIL_Z(p) ((p) >> 20)
+};
 
 template <typename T>
 __device__ __forceinline__ T tail_nb(const T* u, int x, int y, int z, int nx, int ny, int nz) {
@@ -491,22 +469,27 @@ __device__ __forceinline__ T tail_nb(const T* u, int x, int y, int z, int nx, in
     return (a + b) + c;
 }
 
+// One half-sweep of colour `color` (red: x + y + z even) in LDS.
 template <typename T>
-__device__ __forceinline__ void tail_gs(T* u, const T* f, const TailCells& tc, int nx, int ny, int nz, int color, T s,
-                                        T inv_diag) {
-    const int n = color ? tc.n_c1 : tc.n_c0;
-#pragma unroll
-    for (int k = 0; k < kTailPer / 2; ++k) {
-        if (k < n) {
-            const int p = color ? tc.c1[k] : tc.c0[k];
-            const int x = TAIL_X(p), y = TAIL_Y(p), z = TAIL_Z(p);
-            const int j = (z * ny + y) * nx + x;
-            u[j] = (f[j] + s * tail_nb(u, x, y, z, nx, ny, nz)) * inv_diag;
-        }
+__device__ __forceinline__ void tail_gs(T* u, const T* f, int nx, int ny, int nz, int color, T s, T inv_diag) {
+    const int hx = nx >> 1, nh = hx * ny * nz;
+    const TailDec dec(hx, ny);
+    for (int j = threadIdx.x; j < nh; j += blockDim.x) {
+        int i, y, z;
+        dec(j, i, y, z);
+        const int x = 2 * i + ((y + z + color) & 1);
+        const int k = (z * ny + y) * nx + x;
+        u[k] = (f[k] + s * tail_nb(u, x, y, z, nx, ny, nz)) * inv_diag;
     }
     __syncthreads();
 }
 
+// Coarse tail: the whole V-cycle below level t in one work-group with every
+// level in LDS (natural layout [z][y][x]). It performs exactly the operations
+// of the per-level kernels, in the same order and with the same summation
+// order, so it is interchangeable with them: zero initial guess, R B R B
+// pre-smoothing, residual, full weighting, coarse dense solve, trilinear
+// correction, B R B R post-smoothing.
 template <typename T>
 __global__ void __launch_bounds__(kFinBlock) k_tail(const T* __restrict__ f0g, const T* __restrict__ f1g,
                                                     T* __restrict__ u0g, T* __restrict__ u1g, TailDesc d,
@@ -517,55 +500,48 @@ __global__ void __launch_bounds__(kFinBlock) k_tail(const T* __restrict__ f0g, c
 #define TAIL_F(l) reinterpret_cast<T*>(smem + d.off_f[l])
 #define TAIL_R(l) reinterpret_cast<T*>(smem + d.off_r[l])
     const int L = d.nlev - 1;  // coarsest, natural, m cells
-    TailCells tc;
-    tail_cells(tc, d.nx[0], d.ny[0], d.nz[0]);
     {
-        const int nx = d.nx[0], ny = d.ny[0], hx = nx >> 1;
+        // split (red, black) global arrays -> natural LDS level 0
+        const int nx = d.nx[0], ny = d.ny[0], hx = nx >> 1, nh = hx * ny * d.nz[0];
+        const TailDec dec(hx, ny);
         T* F0 = TAIL_F(0);
-#pragma unroll
-        for (int k = 0; k < kTailPer / 2; ++k) {
-            if (k < tc.n_c0) {
-                const int p0 = tc.c0[k], p1 = tc.c1[k];
-                const int y = TAIL_Y(p0), z = TAIL_Z(p0);
-                const int j = (z * ny + y) * hx + (TAIL_X(p0) >> 1);
-                F0[(z * ny + y) * nx + TAIL_X(p0)] = f0g[j];
-                F0[(z * ny + y) * nx + TAIL_X(p1)] = f1g[j];
-            }
+        for (int j = threadIdx.x; j < nh; j += blockDim.x) {
+            int i, y, z;
+            dec(j, i, y, z);
+            const int row = (z * ny + y) * nx, par = (y + z) & 1;
+            F0[row + 2 * i + par] = f0g[j];
+            F0[row + 2 * i + (par ^ 1)] = f1g[j];
         }
     }
     __syncthreads();
     for (int l = 0; l < L; ++l) {
-        const int nx = d.nx[l], ny = d.ny[l], nz = d.nz[l];
-        if (l > 0) tail_cells(tc, nx, ny, nz);
+        const int nx = d.nx[l], ny = d.ny[l], nz = d.nz[l], n = nx * ny * nz;
         T* U = TAIL_U(l);
         T* F = TAIL_F(l);
         T* R = TAIL_R(l);
         const T s = (T)d.s[l], idg = (T)d.inv_diag[l], dg = (T)d.diag[l];
-#pragma unroll
-        for (int k = 0; k < kTailPer; ++k)
-            if (k < tc.n_all) {
-                const int p = tc.all[k];
-                U[(TAIL_Z(p) * ny + TAIL_Y(p)) * nx + TAIL_X(p)] = (T)0;
-            }
+        for (int j = threadIdx.x; j < n; j += blockDim.x) U[j] = (T)0;
         __syncthreads();
-        tail_gs(U, F, tc, nx, ny, nz, 0, s, idg);
-        tail_gs(U, F, tc, nx, ny, nz, 1, s, idg);
-        tail_gs(U, F, tc, nx, ny, nz, 0, s, idg);
-        tail_gs(U, F, tc, nx, ny, nz, 1, s, idg);
-#pragma unroll
-        for (int k = 0; k < kTailPer; ++k)
-            if (k < tc.n_all) {
-                const int p = tc.all[k];
-                const int x = TAIL_X(p), y = TAIL_Y(p), z = TAIL_Z(p);
-                const int j = (z * ny + y) * nx + x;
+        tail_gs(U, F, nx, ny, nz, 0, s, idg);
+        tail_gs(U, F, nx, ny, nz, 1, s, idg);
+        tail_gs(U, F, nx, ny, nz, 0, s, idg);
+        tail_gs(U, F, nx, ny, nz, 1, s, idg);
+        {
+            const TailDec dec(nx, ny);
+            for (int j = threadIdx.x; j < n; j += blockDim.x) {
+                int x, y, z;
+                dec(j, x, y, z);
                 R[j] = F[j] - (dg * U[j] - s * tail_nb(U, x, y, z, nx, ny, nz));
             }
+        }
         __syncthreads();
         const int cx = nx >> 1, cy = ny >> 1, nc = cx * cy * (nz >> 1);
         T* Fc = TAIL_F(l + 1);
         const T w0 = (T)0.125, w1 = (T)0.375;
+        const TailDec cdec(cx, cy);
         for (int j = threadIdx.x; j < nc; j += blockDim.x) {
-            const int X = j % cx, t = j / cx, Y = t % cy, Z = t / cy;
+            int X, Y, Z;
+            cdec(j, X, Y, Z);
             const int x0 = wrapi(2 * X - 1, nx), x1 = 2 * X, x2 = 2 * X + 1, x3 = wrapi(2 * X + 2, nx);
             T acc = 0;
 #pragma unroll
@@ -599,50 +575,45 @@ __global__ void __launch_bounds__(kFinBlock) k_tail(const T* __restrict__ f0g, c
     }
     __syncthreads();
     for (int l = L - 1; l >= 0; --l) {
-        const int nx = d.nx[l], ny = d.ny[l], nz = d.nz[l];
-        tail_cells(tc, nx, ny, nz);
+        const int nx = d.nx[l], ny = d.ny[l], nz = d.nz[l], n = nx * ny * nz;
         const int cx = nx >> 1, cy = ny >> 1, cz = nz >> 1;
         const T* C = TAIL_U(l + 1);
         T* U = TAIL_U(l);
         const T* F = TAIL_F(l);
-#pragma unroll
-        for (int k = 0; k < kTailPer; ++k)
-            if (k < tc.n_all) {
-                const int p = tc.all[k];
-                const int x = TAIL_X(p), y = TAIL_Y(p), z = TAIL_Z(p);
-                const int I0 = x >> 1, I1 = wrapi((x & 1) ? I0 + 1 : I0 - 1, cx);
-                const int J0 = y >> 1, J1 = wrapi((y & 1) ? J0 + 1 : J0 - 1, cy);
-                const int K0 = z >> 1, K1 = wrapi((z & 1) ? K0 + 1 : K0 - 1, cz);
-                const T* c00 = C + (K0 * cy + J0) * cx;
-                const T* c10 = C + (K0 * cy + J1) * cx;
-                const T* c01 = C + (K1 * cy + J0) * cx;
-                const T* c11 = C + (K1 * cy + J1) * cx;
-                const T a00 = (T)0.75 * c00[I0] + (T)0.25 * c00[I1];
-                const T a10 = (T)0.75 * c10[I0] + (T)0.25 * c10[I1];
-                const T a01 = (T)0.75 * c01[I0] + (T)0.25 * c01[I1];
-                const T a11 = (T)0.75 * c11[I0] + (T)0.25 * c11[I1];
-                U[(z * ny + y) * nx + x] +=
-                    (T)0.75 * ((T)0.75 * a00 + (T)0.25 * a10) + (T)0.25 * ((T)0.75 * a01 + (T)0.25 * a11);
-            }
+        const TailDec dec(nx, ny);
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            int x, y, z;
+            dec(j, x, y, z);
+            const int I0 = x >> 1, I1 = wrapi((x & 1) ? I0 + 1 : I0 - 1, cx);
+            const int J0 = y >> 1, J1 = wrapi((y & 1) ? J0 + 1 : J0 - 1, cy);
+            const int K0 = z >> 1, K1 = wrapi((z & 1) ? K0 + 1 : K0 - 1, cz);
+            const T* c00 = C + (K0 * cy + J0) * cx;
+            const T* c10 = C + (K0 * cy + J1) * cx;
+            const T* c01 = C + (K1 * cy + J0) * cx;
+            const T* c11 = C + (K1 * cy + J1) * cx;
+            const T a00 = (T)0.75 * c00[I0] + (T)0.25 * c00[I1];
+            const T a10 = (T)0.75 * c10[I0] + (T)0.25 * c10[I1];
+            const T a01 = (T)0.75 * c01[I0] + (T)0.25 * c01[I1];
+            const T a11 = (T)0.75 * c11[I0] + (T)0.25 * c11[I1];
+            U[j] += (T)0.75 * ((T)0.75 * a00 + (T)0.25 * a10) + (T)0.25 * ((T)0.75 * a01 + (T)0.25 * a11);
+        }
         __syncthreads();
         const T s = (T)d.s[l], idg = (T)d.inv_diag[l];
-        tail_gs(U, F, tc, nx, ny, nz, 1, s, idg);
-        tail_gs(U, F, tc, nx, ny, nz, 0, s, idg);
-        tail_gs(U, F, tc, nx, ny, nz, 1, s, idg);
-        tail_gs(U, F, tc, nx, ny, nz, 0, s, idg);
+        tail_gs(U, F, nx, ny, nz, 1, s, idg);
+        tail_gs(U, F, nx, ny, nz, 0, s, idg);
+        tail_gs(U, F, nx, ny, nz, 1, s, idg);
+        tail_gs(U, F, nx, ny, nz, 0, s, idg);
     }
     {
-        const int nx = d.nx[0], ny = d.ny[0], hx = nx >> 1;
+        const int nx = d.nx[0], ny = d.ny[0], hx = nx >> 1, nh = hx * ny * d.nz[0];
+        const TailDec dec(hx, ny);
         const T* U0 = TAIL_U(0);
-#pragma unroll
-        for (int k = 0; k < kTailPer / 2; ++k) {
-            if (k < tc.n_c0) {
-                const int p0 = tc.c0[k], p1 = tc.c1[k];
-                const int y = TAIL_Y(p0), z = TAIL_Z(p0);
-                const int j = (z * ny + y) * hx + (TAIL_X(p0) >> 1);
-                u0g[j] = U0[(z * ny + y) * nx + TAIL_X(p0)];
-                u1g[j] = U0[(z * ny + y) * nx + TAIL_X(p1)];
-            }
+        for (int j = threadIdx.x; j < nh; j += blockDim.x) {
+            int i, y, z;
+            dec(j, i, y, z);
+            const int row = (z * ny + y) * nx, par = (y + z) & 1;
+            u0g[j] = U0[row + 2 * i + par];
+            u1g[j] = U0[row + 2 * i + (par ^ 1)];
         }
     }
 #undef TAIL_U
@@ -664,12 +635,13 @@ hipError_t tail_set_lds(size_t bytes) {
 #define BRD_INST(T)                                                                                                \
     template void launch_enter<T>(hipStream_t, const double*, T*, T*, T*, int, int, int, double, const Scalars*);  \
     template void launch_gs<T>(hipStream_t, T*, const T*, const T*, int, int, int, int, double, double,            \
-                               const Scalars*);                                                                    \
+                               const Scalars*, int);                                                               \
     template void launch_resid_split<T>(hipStream_t, const T*, const T*, const T*, const T*, T*, T*, int, int, int, \
-                                        double, double, const Scalars*);                                            \
+                                        double, double, const Scalars*, int);                                       \
     template void launch_restrict<T>(hipStream_t, const T*, const T*, int, int, int, T*, T*, T*, int, double,       \
-                                     const Scalars*);                                                               \
-    template void launch_prolong<T>(hipStream_t, const T*, const T*, int, T*, T*, int, int, int, const Scalars*);  \
+                                     const Scalars*, int);                                                          \
+    template void launch_prolong<T>(hipStream_t, const T*, const T*, int, T*, T*, int, int, int, const Scalars*,    \
+                                    int);                                                                           \
     template void launch_coarse<T>(hipStream_t, const T*, T*, const double*, int, const Scalars*);             \
     template void launch_tail<T>(hipStream_t, const T*, const T*, T*, T*, const TailDesc&, const double*,         \
                                  const Scalars*);                                                                   \

@@ -9,6 +9,7 @@ import ctypes
 import os
 from typing import Optional, Sequence, Tuple, Union
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -98,6 +99,14 @@ def load_library(path: str = LIB_PATH):
     L.blob_rd_vcycle.restype = i32
     L.blob_rd_time_kernel.argtypes = [vp, i32, i32, ctypes.POINTER(d), ctypes.POINTER(d)]
     L.blob_rd_time_kernel.restype = i32
+    L.blob_rd_tune_levels.argtypes = [vp]
+    L.blob_rd_tune_levels.restype = i32
+    L.blob_rd_get_tuning.argtypes = [vp, vp, i32]
+    L.blob_rd_get_tuning.restype = i32
+    L.blob_rd_set_tuning.argtypes = [vp, vp, i32]
+    L.blob_rd_set_tuning.restype = i32
+    L.blob_rd_autotune.argtypes = [vp, i32, ctypes.c_char_p, ctypes.POINTER(i32)]
+    L.blob_rd_autotune.restype = i32
     L.blob_rd_net_workspace_bytes.argtypes = []
     L.blob_rd_net_workspace_bytes.restype = ctypes.c_size_t
     L.blob_rd_net_create.argtypes = [vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
@@ -328,6 +337,29 @@ class BlobRD:
         kid = self.KERNELS[kernel] | (256 if cold else 0)
         self._check(self._lib.blob_rd_time_kernel(self._h, kid, int(reps), ctypes.byref(ms), ctypes.byref(by)))
         return ms.value, by.value
+
+    # -- launch-shape tuning -----------------------------------------------------
+    TUNE_KINDS = ("gs", "resid", "restrict", "prolong")
+
+    def get_tuning(self) -> np.ndarray:
+        """Work-group size per (level, kernel) as a (levels, 4) int32 array."""
+        nl = self._lib.blob_rd_tune_levels(self._h)
+        self._check(min(nl, 0))
+        t = np.zeros(max(nl, 1) * 4, dtype=np.int32)
+        self._check(self._lib.blob_rd_get_tuning(self._h, t.ctypes.data_as(ctypes.c_void_p), t.size))
+        return t[:nl * 4].reshape(nl, 4)
+
+    def set_tuning(self, table) -> None:
+        t = np.ascontiguousarray(table, dtype=np.int32).ravel()
+        self._check(self._lib.blob_rd_set_tuning(self._h, t.ctypes.data_as(ctypes.c_void_p), t.size))
+
+    def autotune(self, reps: int = 20, cache: Optional[str] = None) -> int:
+        """Time candidate work-group sizes and keep the fastest; returns the number of levels timed
+        (levels found in the JSON cache file are not timed)."""
+        n = ctypes.c_int32()
+        self._check(self._lib.blob_rd_autotune(self._h, int(reps), None if cache is None else cache.encode(),
+                                               ctypes.byref(n)))
+        return n.value
 
     # -- learned preconditioner -------------------------------------------------
     def precond_build(self, net: "Net") -> int:
