@@ -89,7 +89,7 @@ struct Plan {
     int N = 0, restart = 30, ntiles = 0;
     BlobGeom geom{};
     size_t off_grid[8]{};
-    size_t off_lvl[kMaxLevels][6]{};
+    size_t off_lvl[kMaxLevels][5]{};
     size_t off_cinv[4]{};
     size_t off_part = 0, part_cap = 0;
     size_t off_sc = 0, off_gs = 0, off_dsc = 0;
@@ -170,7 +170,8 @@ int make_plan(const blob_rd_params* p, Plan* P, std::string* why) {
     for (int i = 0; i < 8; ++i) P->off_grid[i] = take(ncell * 8);
     for (int l = 0; l < P->nlev - 1; ++l) {
         const size_t half = (size_t)P->lev[l].hx * P->lev[l].ny * P->lev[l].nz;
-        for (int k = 0; k < 6; ++k) P->off_lvl[l][k] = take(half * P->esz);
+        // u0, u1, f0, f1 and the red residual r0 (the black residual is never stored)
+        for (int k = 0; k < 5; ++k) P->off_lvl[l][k] = take(half * P->esz);
     }
     P->off_lvl[P->nlev - 1][0] = take((size_t)P->m * P->esz);  // coarsest u (natural)
     P->off_lvl[P->nlev - 1][2] = take((size_t)P->m * P->esz);  // coarsest f (natural)
@@ -435,12 +436,20 @@ TailDesc make_tail(const blob_rd* H, int t, double alpha) {
     return d;
 }
 
+// Algorithmic bytes per fine cell of a level, in units of the level's element
+// size (each input read once, each output written once): three half-sweeps,
+// the red residual, its restriction and the coarse f and u on the way down;
+// the red-cell correction (the black cells are overwritten by the next black
+// half-sweep, which does not read them) and four half-sweeps on the way up.
+constexpr double kPreRestrictBytes = 3 * 1.5 + 2.0 + 0.5 + 0.1875;
+constexpr double kProlongPostBytes = 1.125 + 4 * 1.5;
+
 template <typename T>
 void vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const double* cinv) {
     const Plan& P = H->P;
     const int L = P.nlev - 1;
     hipStream_t st = H->st;
-    auto lv = [&](int l, int k) { return H->at<T>(P.off_lvl[l][k]); };  // 0 u0, 1 u1, 2 f0, 3 f1, 4 r0, 5 r1
+    auto lv = [&](int l, int k) { return H->at<T>(P.off_lvl[l][k]); };  // 0 u0, 1 u1, 2 f0, 3 f1, 4 r0 (red)
     const double D = H->prm.D;
     const int t = H->tail_level[sizeof(T) == 4 ? 0 : 1];
     {
@@ -456,13 +465,12 @@ void vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const 
             launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
             launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
             launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
-            launch_resid_split<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), lv(l, 3), lv(l, 4), lv(l, 5), d.hx, d.ny, d.nz,
-                                  s, diag, sc, b[1]);
+            launch_resid_red<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), lv(l, 4), d.hx, d.ny, d.nz, s, diag, sc, b[1]);
             const LevelDims& c = P.lev[l + 1];
             const double sc_ = D / (c.h * c.h);
-            launch_restrict<T>(st, lv(l, 4), lv(l, 5), d.nx, d.ny, d.nz, lv(l + 1, 2), lv(l + 1, 3), lv(l + 1, 0), 0,
+            launch_restrict<T>(st, lv(l, 4), d.nx, d.ny, d.nz, lv(l + 1, 2), lv(l + 1, 3), lv(l + 1, 0), 0,
                                1.0 / (alpha + 6.0 * sc_), sc, b[2]);
-            H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * (3 * 1.5 + 3 + 1.125);
+            H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * kPreRestrictBytes;
         }
         const TailDesc td = make_tail<T>(H, t, alpha);
         launch_tail<T>(st, lv(t, 2), lv(t, 3), lv(t, 0), lv(t, 1), td, cinv, sc);
@@ -475,7 +483,7 @@ void vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const 
             launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
             launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
             launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
-            H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * (4 * 1.5 + 2.125);
+            H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * kProlongPostBytes;
         }
         H->alg_bytes += (double)P.ncell * (8 + P.esz * 1.5);
         H->vcycles += 1;
@@ -488,17 +496,16 @@ void vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const 
         launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
         launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
         launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
-        launch_resid_split<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), lv(l, 3), lv(l, 4), lv(l, 5), d.hx, d.ny, d.nz, s,
-                              diag, sc, b[1]);
+        launch_resid_red<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), lv(l, 4), d.hx, d.ny, d.nz, s, diag, sc, b[1]);
         const int cnat = (l + 1 == L);
         const LevelDims& c = P.lev[l + 1];
         const double sc_ = D / (c.h * c.h);
         if (cnat)
-            launch_restrict<T>(st, lv(l, 4), lv(l, 5), d.nx, d.ny, d.nz, lv(L, 2), nullptr, nullptr, 1, 0.0, sc, b[2]);
+            launch_restrict<T>(st, lv(l, 4), d.nx, d.ny, d.nz, lv(L, 2), nullptr, nullptr, 1, 0.0, sc, b[2]);
         else
-            launch_restrict<T>(st, lv(l, 4), lv(l, 5), d.nx, d.ny, d.nz, lv(l + 1, 2), lv(l + 1, 3), lv(l + 1, 0), 0,
+            launch_restrict<T>(st, lv(l, 4), d.nx, d.ny, d.nz, lv(l + 1, 2), lv(l + 1, 3), lv(l + 1, 0), 0,
                                1.0 / (alpha + 6.0 * sc_), sc, b[2]);
-        H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * (3 * 1.5 + 3 + 1.125);
+        H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * kPreRestrictBytes;
     }
     launch_coarse<T>(st, lv(L, 2), lv(L, 0), cinv, P.m, sc);
     for (int l = L - 1; l >= 0; --l) {
@@ -512,7 +519,7 @@ void vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const 
         launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
         launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
         launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
-        H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * (4 * 1.5 + 2.125);
+        H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * kProlongPostBytes;
     }
     H->alg_bytes += (double)P.ncell * (8 + P.esz * 1.5);
     H->vcycles += 1;
@@ -1329,15 +1336,12 @@ namespace {
 void zero_levels(blob_rd* H) {
     const Plan& P = H->P;
     const int L = P.nlev - 1;
-    for (int l = 0; l < std::max(L, 1); ++l) {
+    for (int l = 0; l < L; ++l) {
         const size_t hl = (size_t)P.lev[l].hx * P.lev[l].ny * P.lev[l].nz;
-        const int nb = (L == 0) ? 4 : 6;
-        for (int k = 0; k < nb; ++k) HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[l][k], 0, hl * P.esz, H->st));
+        for (int k = 0; k < 5; ++k) HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[l][k], 0, hl * P.esz, H->st));
     }
-    if (L > 0) {
-        HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[L][0], 0, (size_t)P.m * P.esz, H->st));
-        HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[L][2], 0, (size_t)P.m * P.esz, H->st));
-    }
+    HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[L][0], 0, (size_t)P.m * P.esz, H->st));
+    HIPCHK(hipMemsetAsync(H->ws + P.off_lvl[L][2], 0, (size_t)P.m * P.esz, H->st));
 }
 
 // Levels launched one kernel at a time (above the LDS tail or the dense coarse solve).
@@ -1363,12 +1367,11 @@ void tune_launch(blob_rd* H, int l, int kind, int bs) {
     switch (kind) {
         case 0: launch_gs<T>(H->st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, nullptr, bs); break;
         case 1:
-            launch_resid_split<T>(H->st, lv(l, 0), lv(l, 1), lv(l, 2), lv(l, 3), lv(l, 4), lv(l, 5), d.hx, d.ny, d.nz,
-                                  s, diag, nullptr, bs);
+            launch_resid_red<T>(H->st, lv(l, 0), lv(l, 1), lv(l, 2), lv(l, 4), d.hx, d.ny, d.nz, s, diag, nullptr, bs);
             break;
         case 2: {
             const LevelDims& c = P.lev[l + 1];
-            launch_restrict<T>(H->st, lv(l, 4), lv(l, 5), d.nx, d.ny, d.nz, lv(l + 1, 2), cnat ? nullptr : lv(l + 1, 3),
+            launch_restrict<T>(H->st, lv(l, 4), d.nx, d.ny, d.nz, lv(l + 1, 2), cnat ? nullptr : lv(l + 1, 3),
                                cnat ? nullptr : lv(l + 1, 0), cnat, 1.0 / (6.0 * H->prm.D / (c.h * c.h)), nullptr, bs);
             break;
         }
@@ -1724,21 +1727,19 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
                 }
                 case BLOB_RD_KERNEL_RESTRICT:
                     if (f32) {
-                        launch_resid_split<float>(H->st, H->at<float>(P.off_lvl[0][0]), H->at<float>(P.off_lvl[0][1]),
-                                                  H->at<float>(P.off_lvl[0][2]), H->at<float>(P.off_lvl[0][3]),
-                                                  H->at<float>(P.off_lvl[0][4]), H->at<float>(P.off_lvl[0][5]), d.hx,
-                                                  d.ny, d.nz, s, diag, nullptr);
-                        launch_restrict<float>(H->st, H->at<float>(P.off_lvl[0][4]), H->at<float>(P.off_lvl[0][5]), d.nx,
+                        launch_resid_red<float>(H->st, H->at<float>(P.off_lvl[0][0]), H->at<float>(P.off_lvl[0][1]),
+                                                H->at<float>(P.off_lvl[0][2]), H->at<float>(P.off_lvl[0][4]), d.hx,
+                                                d.ny, d.nz, s, diag, nullptr);
+                        launch_restrict<float>(H->st, H->at<float>(P.off_lvl[0][4]), d.nx,
                                                d.ny, d.nz, H->at<float>(P.off_lvl[1][2]),
                                                cnat ? nullptr : H->at<float>(P.off_lvl[1][3]),
                                                cnat ? nullptr : H->at<float>(P.off_lvl[1][0]), cnat,
                                                1.0 / (alpha + 6.0 * H->prm.D / (c.h * c.h)), nullptr);
                     } else {
-                        launch_resid_split<double>(H->st, H->at<double>(P.off_lvl[0][0]), H->at<double>(P.off_lvl[0][1]),
-                                                   H->at<double>(P.off_lvl[0][2]), H->at<double>(P.off_lvl[0][3]),
-                                                   H->at<double>(P.off_lvl[0][4]), H->at<double>(P.off_lvl[0][5]),
-                                                   d.hx, d.ny, d.nz, s, diag, nullptr);
-                        launch_restrict<double>(H->st, H->at<double>(P.off_lvl[0][4]), H->at<double>(P.off_lvl[0][5]),
+                        launch_resid_red<double>(H->st, H->at<double>(P.off_lvl[0][0]), H->at<double>(P.off_lvl[0][1]),
+                                                 H->at<double>(P.off_lvl[0][2]), H->at<double>(P.off_lvl[0][4]), d.hx,
+                                                 d.ny, d.nz, s, diag, nullptr);
+                        launch_restrict<double>(H->st, H->at<double>(P.off_lvl[0][4]),
                                                 d.nx, d.ny, d.nz, H->at<double>(P.off_lvl[1][2]),
                                                 cnat ? nullptr : H->at<double>(P.off_lvl[1][3]),
                                                 cnat ? nullptr : H->at<double>(P.off_lvl[1][0]), cnat,
@@ -1791,12 +1792,13 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
         switch (kernel) {
             case BLOB_RD_KERNEL_GS: *bytes = n * 0.5 * e * 3; break;              // other colour, f, own colour
             case BLOB_RD_KERNEL_STENCIL: *bytes = n * 16; break;                 // read x, write y (FP64)
-            case BLOB_RD_KERNEL_RESTRICT: *bytes = n * e * 4 + n / 8 * e; break; // u, f read; r write+read; coarse f
+            case BLOB_RD_KERNEL_RESTRICT: *bytes = n * e * 2.5 + n / 8 * e * 1.5; break;  // red u, black u, red f; red r write+read; coarse f, u
             case BLOB_RD_KERNEL_PROLONG: *bytes = n * e + n / 8 * e; break;  // red u read+write, coarse read
             default: {
                 double b = 0.0;
-                for (int l = 0; l + 1 < P.nlev; ++l) b += n / (double)(1 << (3 * l)) * e * (7 * 1.5 + 4 + 2 + 0.25);
-                *bytes = b + n * 8;
+                for (int l = 0; l + 1 < P.nlev; ++l)
+                    b += n / (double)(1 << (3 * l)) * e * (kPreRestrictBytes + kProlongPostBytes);
+                *bytes = b + n * (8 + 1.5 * e);  // + entry: FP64 residual in, f and the first red sweep out
             }
         }
         HIPCHK(hipGetLastError());

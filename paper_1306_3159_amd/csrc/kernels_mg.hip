@@ -155,12 +155,14 @@ void launch_gs(hipStream_t st, T* uc, const T* uo, const T* fc, int hx, int ny, 
 }
 
 // ---------------------------------------------------------------------------
-// Residual r = f - (diag u - s sum nbrs) for both colours.
+// Residual after pre-smoothing. The pre-smoothing sweeps end with a black
+// half-sweep, after which the black residual f - (diag u - s sum nbrs) is zero
+// in exact arithmetic: only the red residual is formed (split array r0), and
+// the restriction takes the black cells as zero.
 template <typename T>
 __global__ void __launch_bounds__(kMaxTuneBlock) k_resid(const T* __restrict__ u0, const T* __restrict__ u1,
-                                                  const T* __restrict__ f0, const T* __restrict__ f1,
-                                                  T* __restrict__ r0, T* __restrict__ r1, int hx, int ny, int nz,
-                                                  T s, T diag, const Scalars* sc) {
+                                                  const T* __restrict__ f0, T* __restrict__ r0, int hx, int ny,
+                                                  int nz, T s, T diag, const Scalars* sc) {
     if (sc && sc->done) return;
     const unsigned nh = (unsigned)hx * ny * nz;
     const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -168,18 +170,14 @@ __global__ void __launch_bounds__(kMaxTuneBlock) k_resid(const T* __restrict__ u
     const int i = idx % hx;
     const unsigned t = idx / hx;
     const int y = t % ny, z = t / ny;
-    const int s0 = (y + z) & 1;
-    const T nr = nb_sum(u1, i, y, z, hx, ny, nz, s0);        // neighbours of the red cell are black
-    const T nbk = nb_sum(u0, i, y, z, hx, ny, nz, s0 ^ 1);   // and vice versa
+    const T nr = nb_sum(u1, i, y, z, hx, ny, nz, (y + z) & 1);  // neighbours of a red cell are black
     r0[idx] = f0[idx] - (diag * u0[idx] - s * nr);
-    r1[idx] = f1[idx] - (diag * u1[idx] - s * nbk);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kMaxTuneBlock) k_resid_vec(const T* __restrict__ u0, const T* __restrict__ u1,
-                                                      const T* __restrict__ f0, const T* __restrict__ f1,
-                                                      T* __restrict__ r0, T* __restrict__ r1, int hx, int ny, int nz,
-                                                      T s, T diag, const Scalars* sc) {
+                                                      const T* __restrict__ f0, T* __restrict__ r0, int hx, int ny,
+                                                      int nz, T s, T diag, const Scalars* sc) {
     typedef typename VecOf<T>::type V;
     constexpr int VW = VecOf<T>::W;
     if (sc && sc->done) return;
@@ -191,55 +189,56 @@ __global__ void __launch_bounds__(kMaxTuneBlock) k_resid_vec(const T* __restrict
     const unsigned t = idx / hv;
     const int y = t % ny, z = t / ny;
     const int i0 = iv * VW;
-    const int s0 = (y + z) & 1;
     const size_t row = ((size_t)z * ny + y) * hx;
-    const size_t rym = ((size_t)z * ny + wrapi(y - 1, ny)) * hx + i0, ryp = ((size_t)z * ny + wrapi(y + 1, ny)) * hx + i0;
-    const size_t rzm = ((size_t)wrapi(z - 1, nz) * ny + y) * hx + i0, rzp = ((size_t)wrapi(z + 1, nz) * ny + y) * hx + i0;
+    V left, right;
+    row_neighbours<T>(u1 + row, i0, hx, (y + z) & 1, left, right);
+    const V ym = *reinterpret_cast<const V*>(u1 + ((size_t)z * ny + wrapi(y - 1, ny)) * hx + i0);
+    const V yp = *reinterpret_cast<const V*>(u1 + ((size_t)z * ny + wrapi(y + 1, ny)) * hx + i0);
+    const V zm = *reinterpret_cast<const V*>(u1 + ((size_t)wrapi(z - 1, nz) * ny + y) * hx + i0);
+    const V zp = *reinterpret_cast<const V*>(u1 + ((size_t)wrapi(z + 1, nz) * ny + y) * hx + i0);
+    const V u = *reinterpret_cast<const V*>(u0 + row + i0);
+    const V f = *reinterpret_cast<const V*>(f0 + row + i0);
+    V out;
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const T* uo = c ? u0 : u1;    // neighbours are of the other colour
-        const T* uc = c ? u1 : u0;
-        const T* fc = c ? f1 : f0;
-        T* rc = c ? r1 : r0;
-        V left, right;
-        row_neighbours<T>(uo + row, i0, hx, s0 ^ c, left, right);
-        const V ym = *reinterpret_cast<const V*>(uo + rym), yp = *reinterpret_cast<const V*>(uo + ryp);
-        const V zm = *reinterpret_cast<const V*>(uo + rzm), zp = *reinterpret_cast<const V*>(uo + rzp);
-        const V u = *reinterpret_cast<const V*>(uc + row + i0);
-        const V f = *reinterpret_cast<const V*>(fc + row + i0);
-        V out;
-#pragma unroll
-        for (int k = 0; k < VW; ++k)
-            out[k] = f[k] - (diag * u[k] - s * (((left[k] + right[k]) + (ym[k] + yp[k])) + (zm[k] + zp[k])));
-        *reinterpret_cast<V*>(rc + row + i0) = out;
-    }
+    for (int k = 0; k < VW; ++k)
+        out[k] = f[k] - (diag * u[k] - s * (((left[k] + right[k]) + (ym[k] + yp[k])) + (zm[k] + zp[k])));
+    *reinterpret_cast<V*>(r0 + row + i0) = out;
 }
 
 template <typename T>
-void launch_resid_split(hipStream_t st, const T* u0, const T* u1, const T* f0, const T* f1, T* r0, T* r1, int hx,
-                        int ny, int nz, double s, double diag, const Scalars* sc, int bs) {
+void launch_resid_red(hipStream_t st, const T* u0, const T* u1, const T* f0, T* r0, int hx, int ny, int nz, double s,
+                      double diag, const Scalars* sc, int bs) {
     constexpr int VW = VecOf<T>::W;
     if (hx % VW == 0 && hx >= VW) {
         const unsigned nv = (unsigned)(hx / VW) * ny * nz;
-        hipLaunchKernelGGL(k_resid_vec<T>, dim3(nblocks(nv, bs)), dim3(bs), 0, st, u0, u1, f0, f1, r0, r1, hx, ny,
-                           nz, (T)s, (T)diag, sc);
+        hipLaunchKernelGGL(k_resid_vec<T>, dim3(nblocks(nv, bs)), dim3(bs), 0, st, u0, u1, f0, r0, hx, ny, nz, (T)s,
+                           (T)diag, sc);
         return;
     }
     const unsigned nh = (unsigned)hx * ny * nz;
-    hipLaunchKernelGGL(k_resid<T>, dim3(nblocks(nh, bs)), dim3(bs), 0, st, u0, u1, f0, f1, r0, r1, hx, ny, nz, (T)s,
-                       (T)diag, sc);
+    hipLaunchKernelGGL(k_resid<T>, dim3(nblocks(nh, bs)), dim3(bs), 0, st, u0, u1, f0, r0, hx, ny, nz, (T)s, (T)diag,
+                       sc);
 }
 
 // ---------------------------------------------------------------------------
 // Full-weighting restriction, 1-D weights (1, 3, 3, 1)/8 over fine cells
-// 2X-1 .. 2X+2. One thread per coarse cell (natural coarse index). Writes the
-// coarse right-hand side in split layout together with the zero-guess red
+// 2X-1 .. 2X+2, of the red residual r0 (black cells zero). Writes the coarse
+// right-hand side in split layout together with the zero-guess red
 // half-sweep, or in natural layout on the coarsest level.
+//
+// In a fine row of parity p = (y + z) & 1 the red cells are x = 2i + p, so
+// of the four fine cells of coarse X the red ones are 2X-1 (weight 1/8) and
+// 2X+1 (3/8) when p = 1, 2X (3/8) and 2X+2 (1/8) when p = 0.
 template <typename T>
-__global__ void __launch_bounds__(kMaxTuneBlock) k_restrict(const T* __restrict__ r0, const T* __restrict__ r1, int nx,
-                                                     int ny, int nz, T* __restrict__ cf0, T* __restrict__ cf1,
-                                                     T* __restrict__ cu0, int coarse_natural, T inv_diag_c,
-                                                     const Scalars* sc) {
+__device__ __forceinline__ T restrict_row(T w0, T w1, int p, T a, T b, T c) {
+    // p = 1: (a, b) = r0[X-1], r0[X]; p = 0: (b, c) = r0[X], r0[X+1]
+    return p ? w0 * a + w1 * b : w1 * b + w0 * c;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMaxTuneBlock) k_restrict(const T* __restrict__ r0, int nx, int ny, int nz,
+                                                     T* __restrict__ cf0, T* __restrict__ cf1, T* __restrict__ cu0,
+                                                     int coarse_natural, T inv_diag_c, const Scalars* sc) {
     if (sc && sc->done) return;
     const int cx = nx >> 1, cy = ny >> 1, cz = nz >> 1;
     const unsigned nc = (unsigned)cx * cy * cz;
@@ -249,10 +248,8 @@ __global__ void __launch_bounds__(kMaxTuneBlock) k_restrict(const T* __restrict_
     const unsigned t = idx / cx;
     const int Y = t % cy, Z = t / cy;
     const int hx = nx >> 1;
-    const T w[4] = {(T)0.125, (T)0.375, (T)0.375, (T)0.125};
-    int xs[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) xs[a] = wrapi(2 * X - 1 + a, nx);
+    const T w0 = (T)0.125, w1 = (T)0.375;
+    const int xl = X == 0 ? hx - 1 : X - 1, xr = X + 1 == hx ? 0 : X + 1;
     T acc = 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -261,18 +258,11 @@ __global__ void __launch_bounds__(kMaxTuneBlock) k_restrict(const T* __restrict_
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int y = wrapi(2 * Y - 1 + b, ny);
-            const size_t row = ((size_t)z * ny + y) * hx;
-            const int pyz = (y + z) & 1;
-            T acca = 0;
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const int x = xs[a];
-                const T v = ((x + pyz) & 1) ? r1[row + (x >> 1)] : r0[row + (x >> 1)];
-                acca += w[a] * v;
-            }
-            accb += w[b] * acca;
+            const T* row = r0 + ((size_t)z * ny + y) * hx;
+            const int p = (y + z) & 1;
+            accb += (b == 0 || b == 3 ? w0 : w1) * restrict_row(w0, w1, p, p ? row[xl] : (T)0, row[X], p ? (T)0 : row[xr]);
         }
-        acc += w[c] * accb;
+        acc += (c == 0 || c == 3 ? w0 : w1) * accb;
     }
     if (coarse_natural) {
         cf0[idx] = acc;
@@ -287,11 +277,74 @@ __global__ void __launch_bounds__(kMaxTuneBlock) k_restrict(const T* __restrict_
     }
 }
 
+// Four consecutive coarse cells per thread: one 4-wide load of r0 per fine
+// row plus its two edge values; same arithmetic as k_restrict. Needs cx % 4 == 0.
 template <typename T>
-void launch_restrict(hipStream_t st, const T* r0, const T* r1, int nx, int ny, int nz, T* cf0, T* cf1, T* cu0,
-                     int coarse_natural, double inv_diag_c, const Scalars* sc, int bs) {
-    const unsigned nc = (unsigned)(nx / 2) * (ny / 2) * (nz / 2);
-    hipLaunchKernelGGL(k_restrict<T>, dim3(nblocks(nc, bs)), dim3(bs), 0, st, r0, r1, nx, ny, nz, cf0, cf1, cu0,
+__global__ void __launch_bounds__(kMaxTuneBlock) k_restrict4(const T* __restrict__ r0, int nx, int ny, int nz,
+                                                      T* __restrict__ cf0, T* __restrict__ cf1, T* __restrict__ cu0,
+                                                      int coarse_natural, T inv_diag_c, const Scalars* sc) {
+    typedef T V4 __attribute__((ext_vector_type(4)));
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    if (sc && sc->done) return;
+    const int cx = nx >> 1, cy = ny >> 1, cz = nz >> 1, cv = cx >> 2;
+    const unsigned n4 = (unsigned)cv * cy * cz;
+    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= n4) return;
+    const int v = idx % cv;
+    const unsigned t = idx / cv;
+    const int Y = t % cy, Z = t / cy;
+    const int hx = nx >> 1, X0 = 4 * v;
+    const T w0 = (T)0.125, w1 = (T)0.375;
+    const int xl = X0 == 0 ? hx - 1 : X0 - 1, xr = X0 + 4 == hx ? 0 : X0 + 4;
+    T acc[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int z = wrapi(2 * Z - 1 + c, nz);
+        T accb[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int y = wrapi(2 * Y - 1 + b, ny);
+            const T* row = r0 + ((size_t)z * ny + y) * hx;
+            const int p = (y + z) & 1;
+            const V4 m = *reinterpret_cast<const V4*>(row + X0);
+            const T e = p ? row[xl] : row[xr];
+            const T wb = (b == 0 || b == 3) ? w0 : w1;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const T a = p ? (k ? m[k - 1] : e) : (T)0;
+                const T cc = p ? (T)0 : (k < 3 ? m[k + 1] : e);
+                accb[k] += wb * restrict_row(w0, w1, p, a, m[k], cc);
+            }
+        }
+        const T wc = (c == 0 || c == 3) ? w0 : w1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += wc * accb[k];
+    }
+    if (coarse_natural) {
+        *reinterpret_cast<V4*>(cf0 + ((size_t)Z * cy + Y) * cx + X0) = V4{acc[0], acc[1], acc[2], acc[3]};
+    } else {
+        const int pc = (Y + Z) & 1;  // coarse X0 is red when pc == 0
+        const size_t j = ((size_t)Z * cy + Y) * (cx >> 1) + (X0 >> 1);
+        const V2 red = pc ? V2{acc[1], acc[3]} : V2{acc[0], acc[2]};
+        const V2 blk = pc ? V2{acc[0], acc[2]} : V2{acc[1], acc[3]};
+        *reinterpret_cast<V2*>(cf0 + j) = red;
+        *reinterpret_cast<V2*>(cf1 + j) = blk;
+        *reinterpret_cast<V2*>(cu0 + j) = red * inv_diag_c;
+    }
+}
+
+template <typename T>
+void launch_restrict(hipStream_t st, const T* r0, int nx, int ny, int nz, T* cf0, T* cf1, T* cu0, int coarse_natural,
+                     double inv_diag_c, const Scalars* sc, int bs) {
+    const int cx = nx / 2;
+    if (cx % 4 == 0) {
+        const unsigned n4 = (unsigned)(cx / 4) * (ny / 2) * (nz / 2);
+        hipLaunchKernelGGL(k_restrict4<T>, dim3(nblocks(n4, bs)), dim3(bs), 0, st, r0, nx, ny, nz, cf0, cf1, cu0,
+                           coarse_natural, (T)inv_diag_c, sc);
+        return;
+    }
+    const unsigned nc = (unsigned)cx * (ny / 2) * (nz / 2);
+    hipLaunchKernelGGL(k_restrict<T>, dim3(nblocks(nc, bs)), dim3(bs), 0, st, r0, nx, ny, nz, cf0, cf1, cu0,
                        coarse_natural, (T)inv_diag_c, sc);
 }
 
@@ -531,7 +584,7 @@ __global__ void __launch_bounds__(kFinBlock) k_tail(const T* __restrict__ f0g, c
             for (int j = threadIdx.x; j < n; j += blockDim.x) {
                 int x, y, z;
                 dec(j, x, y, z);
-                R[j] = F[j] - (dg * U[j] - s * tail_nb(U, x, y, z, nx, ny, nz));
+                R[j] = ((x + y + z) & 1) ? (T)0 : F[j] - (dg * U[j] - s * tail_nb(U, x, y, z, nx, ny, nz));
             }
         }
         __syncthreads();
@@ -636,10 +689,10 @@ hipError_t tail_set_lds(size_t bytes) {
     template void launch_enter<T>(hipStream_t, const double*, T*, T*, T*, int, int, int, double, const Scalars*);  \
     template void launch_gs<T>(hipStream_t, T*, const T*, const T*, int, int, int, int, double, double,            \
                                const Scalars*, int);                                                               \
-    template void launch_resid_split<T>(hipStream_t, const T*, const T*, const T*, const T*, T*, T*, int, int, int, \
-                                        double, double, const Scalars*, int);                                       \
-    template void launch_restrict<T>(hipStream_t, const T*, const T*, int, int, int, T*, T*, T*, int, double,       \
-                                     const Scalars*, int);                                                          \
+    template void launch_resid_red<T>(hipStream_t, const T*, const T*, const T*, T*, int, int, int, double, double, \
+                                      const Scalars*, int);                                                         \
+    template void launch_restrict<T>(hipStream_t, const T*, int, int, int, T*, T*, T*, int, double, const Scalars*, \
+                                     int);                                                                          \
     template void launch_prolong<T>(hipStream_t, const T*, const T*, int, T*, T*, int, int, int, const Scalars*,    \
                                     int);                                                                           \
     template void launch_coarse<T>(hipStream_t, const T*, T*, const double*, int, const Scalars*);             \

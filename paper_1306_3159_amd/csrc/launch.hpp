@@ -68,13 +68,14 @@ void launch_enter(hipStream_t st, const double* r, T* f0, T* f1, T* u0, int nx, 
 template <typename T>
 void launch_gs(hipStream_t st, T* uc, const T* uo, const T* fc, int hx, int ny, int nz, int color, double s,
                double inv_diag, const Scalars* sc, int bs = kBlock);
+// red residual after pre-smoothing (the black one is zero after the closing black half-sweep)
 template <typename T>
-void launch_resid_split(hipStream_t st, const T* u0, const T* u1, const T* f0, const T* f1, T* r0, T* r1, int hx,
-                        int ny, int nz, double s, double diag, const Scalars* sc, int bs = kBlock);
-// fine split residual -> coarse f (split, with zero-guess red update) or natural (coarsest)
+void launch_resid_red(hipStream_t st, const T* u0, const T* u1, const T* f0, T* r0, int hx, int ny, int nz, double s,
+                      double diag, const Scalars* sc, int bs = kBlock);
+// fine red residual -> coarse f (split, with zero-guess red update) or natural (coarsest)
 template <typename T>
-void launch_restrict(hipStream_t st, const T* r0, const T* r1, int nx, int ny, int nz, T* cf0, T* cf1, T* cu0,
-                     int coarse_natural, double inv_diag_c, const Scalars* sc, int bs = kBlock);
+void launch_restrict(hipStream_t st, const T* r0, int nx, int ny, int nz, T* cf0, T* cf1, T* cu0, int coarse_natural,
+                     double inv_diag_c, const Scalars* sc, int bs = kBlock);
 template <typename T>
 void launch_prolong(hipStream_t st, const T* cu0, const T* cu1, int coarse_natural, T* u0, T* u1, int nx, int ny,
                     int nz, const Scalars* sc, int bs = kBlock);
