@@ -41,6 +41,7 @@ struct Scalars {
     double tol2;      // stop when rr <= tol2
     double shift;     // constant added to the V-cycle output z (null-space handling)
     double mean_r;    // mean removed from r before the V-cycle (projected problems)
+    double mean_next; // mean of the next r predicted from sum r and sum q (fused update + V-cycle entry)
     double inv_ncell; // 1 / (nx ny nz)
     double eBe_inv;   // 1 / (e^T B e) for the reactive alpha = 0 constant mode (0 otherwise)
     double rr0;       // r . r of the initial residual

@@ -343,6 +343,7 @@ __global__ void k_sc_init(Scalars* sc, int project, double inv_ncell, double eBe
     sc->tol2 = rtol2;
     sc->shift = 0.0;
     sc->mean_r = 0.0;
+    sc->mean_next = 0.0;
     sc->inv_ncell = inv_ncell;
     sc->eBe_inv = eBe_inv;
     sc->rr0 = abs2;
@@ -444,18 +445,36 @@ TailDesc make_tail(const blob_rd* H, int t, double alpha) {
 constexpr double kPreRestrictBytes = 3 * 1.5 + 2.0 + 0.5 + 0.1875;
 constexpr double kProlongPostBytes = 1.125 + 4 * 1.5;
 
+// entered: level 0's f and first red sweep were already written (fused CG
+// update). dot_q (with a non-null sc): fuse the CG dots (sum z, z.r, z.q) into
+// the closing red half-sweep of level 0 when that level has its own launches;
+// returns the number of partials written to H->part(), 0 when not fused.
 template <typename T>
-void vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const double* cinv) {
+unsigned vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const double* cinv,
+                bool entered = false, const double* dot_q = nullptr) {
     const Plan& P = H->P;
     const int L = P.nlev - 1;
     hipStream_t st = H->st;
     auto lv = [&](int l, int k) { return H->at<T>(P.off_lvl[l][k]); };  // 0 u0, 1 u1, 2 f0, 3 f1, 4 r0 (red)
     const double D = H->prm.D;
     const int t = H->tail_level[sizeof(T) == 4 ? 0 : 1];
-    {
+    unsigned ndots = 0;
+    // closing red half-sweep of level l (with the CG dots on level 0 when asked;
+    // that launch keeps the default work-group size, so its partial sums, and
+    // with them every result, do not depend on the tuning table)
+    auto last_red = [&](int l, double s, double diag, const int* b) {
+        const LevelDims& d = P.lev[l];
+        if (l == 0 && dot_q && sc)
+            ndots = launch_gs_dots<T>(st, lv(0, 0), lv(0, 1), lv(0, 2), d.hx, d.ny, d.nz, s, 1.0 / diag, r, dot_q,
+                                      H->part(), sc, kBlock);
+        if (!(l == 0 && ndots))
+            launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
+    };
+    if (!entered) {
         const LevelDims& d = P.lev[0];
         const double s = D / (d.h * d.h);
         launch_enter<T>(st, r, lv(0, 2), lv(0, 3), lv(0, 0), d.nx, d.ny, d.nz, 1.0 / (alpha + 6.0 * s), sc);
+        H->alg_bytes += (double)P.ncell * (8 + P.esz * 1.5);
     }
     if (t < L) {
         for (int l = 0; l < t; ++l) {
@@ -482,12 +501,11 @@ void vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const 
             launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
             launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
             launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
-            launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
+            last_red(l, s, diag, b);
             H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * kProlongPostBytes;
         }
-        H->alg_bytes += (double)P.ncell * (8 + P.esz * 1.5);
         H->vcycles += 1;
-        return;
+        return ndots;
     }
     for (int l = 0; l < L; ++l) {
         const LevelDims& d = P.lev[l];
@@ -518,22 +536,26 @@ void vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const 
         launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
         launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
         launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
-        launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
+        last_red(l, s, diag, b);
         H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * kProlongPostBytes;
     }
-    H->alg_bytes += (double)P.ncell * (8 + P.esz * 1.5);
     H->vcycles += 1;
+    return ndots;
 }
 
 template <typename T>
-void precond_zdots(blob_rd* H, double alpha, const double* r, const double* q, const double* cinv) {
-    vcycle<T>(H, alpha, r, H->sc(), cinv);
-    const LevelDims& d = H->P.lev[0];
-    unsigned np = 0;
-    launch_zdots2<T>(H->st, H->at<T>(H->P.off_lvl[0][0]), H->at<T>(H->P.off_lvl[0][1]), r, q, d.nx, d.ny, d.nz,
-                     H->part(), H->sc(), &np);
+void precond_zdots(blob_rd* H, double alpha, const double* r, const double* q, const double* cinv,
+                   bool entered = false) {
+    unsigned np = vcycle<T>(H, alpha, r, H->sc(), cinv, entered, q);
+    if (np) {
+        H->alg_bytes += (double)H->P.ncell * 16;  // r, q read by the fused sweep
+    } else {
+        const LevelDims& d = H->P.lev[0];
+        launch_zdots2<T>(H->st, H->at<T>(H->P.off_lvl[0][0]), H->at<T>(H->P.off_lvl[0][1]), r, q, d.nx, d.ny, d.nz,
+                         H->part(), H->sc(), &np);
+        H->alg_bytes += (double)H->P.ncell * (H->P.esz + 16);
+    }
     launch_fin(H->st, FIN_BETA, H->part(), np, H->sc(), nullptr, nullptr, 0, 0.0);
-    H->alg_bytes += (double)H->P.ncell * (H->P.esz + 16);
 }
 
 // q += S kappa J p, with jx = J p and mu = kappa J p kept for the CG dots.
@@ -604,10 +626,13 @@ PcgResult pcg(blob_rd* H, bool with_blobs, double alpha, const double* g, double
         } else {
             launch_fin(s_, FIN_ALPHA, H->part(), np, H->sc(), nullptr, nullptr, 0, 0.0);
         }
-        launch_update2(s_, x, r, p, q, P.ncell, H->part(), H->sc(), &np);
+        launch_update2_enter<T>(s_, x, r, p, q, H->at<T>(P.off_lvl[0][2]), H->at<T>(P.off_lvl[0][3]),
+                                H->at<T>(P.off_lvl[0][0]), d.nx, d.ny, d.nz, 1.0 / (alpha + 6.0 * s), H->part(),
+                                H->sc(), &np);
         launch_fin(s_, FIN_UPDATE, H->part(), np, H->sc(), nullptr, nullptr, 0, 0.0);
-        precond_zdots<T>(H, alpha, r, q, cinv);
-        H->alg_bytes += (double)P.ncell * (P.esz / 2.0 + 16 + 16 + 48);
+        precond_zdots<T>(H, alpha, r, q, cinv, true);
+        // direction (z, p r/w), stencil (p, q), update (x, r r/w, p, q) with the V-cycle entry (f, red u)
+        H->alg_bytes += (double)P.ncell * (P.esz + 16 + 16 + 48 + 1.5 * P.esz);
         H->st = keep;
     };
     blob_rd::GraphEntry* ge = nullptr;

@@ -132,15 +132,22 @@ void launch_dir2(hipStream_t st, const T* z0, const T* z1, double* p, int nx, in
 template void launch_dir2<float>(hipStream_t, const float*, const float*, double*, int, int, int, const Scalars*);
 template void launch_dir2<double>(hipStream_t, const double*, const double*, double*, int, int, int, const Scalars*);
 
-// x += alpha p ; r -= alpha q ; partials (r.r, sum r), two cells per thread
-__global__ void __launch_bounds__(kBlock) k_update2(double* __restrict__ x, double* __restrict__ r,
-                                                    const double* __restrict__ p, const double* __restrict__ q,
-                                                    unsigned npair, double* part, const Scalars* sc) {
+// x += alpha p ; r -= alpha q with partials (r.r, sum r), and the V-cycle
+// entry for the new r in the same pass: f = r - mean (the mean predicted from
+// sum r and sum q) into the split level-0 arrays, and the first red
+// half-sweep from a zero guess, u_red = f_red / diag (as k_enter computes it).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_update2_enter(double* __restrict__ x, double* __restrict__ r,
+                                                          const double* __restrict__ p, const double* __restrict__ q,
+                                                          T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ u0,
+                                                          int nx, int ny, unsigned npair, double inv_diag,
+                                                          double* part, const Scalars* sc) {
     if (sc->done) return;
     unsigned lo, hi;
     chunk_of(xcd_block(blockIdx.x, gridDim.x), gridDim.x, npair, &lo, &hi);
     double v[2] = {0.0, 0.0};
-    const double a = sc->alpha;
+    const double a = sc->alpha, m = sc->mean_next;
+    const int hx = nx >> 1;
     for (unsigned k = lo + threadIdx.x; k < hi; k += blockDim.x) {
         double2_t xv = reinterpret_cast<double2_t*>(x)[k];
         double2_t rv = reinterpret_cast<double2_t*>(r)[k];
@@ -154,17 +161,31 @@ __global__ void __launch_bounds__(kBlock) k_update2(double* __restrict__ x, doub
         reinterpret_cast<double2_t*>(r)[k] = rv;
         v[0] += rv[0] * rv[0] + rv[1] * rv[1];
         v[1] += rv[0] + rv[1];
+        const unsigned t = k / hx;
+        const int par = ((int)(t % ny) + (int)(t / ny)) & 1;  // colour of the even cell
+        const double fa = rv[0] - m, fb = rv[1] - m;
+        const double fr = par ? fb : fa, fk = par ? fa : fb;
+        f0[k] = (T)fr;
+        f1[k] = (T)fk;
+        u0[k] = (T)((T)fr * (T)inv_diag);
     }
     block_partials<2>(v, part, gridDim.x, blockIdx.x);
 }
 
-void launch_update2(hipStream_t st, double* x, double* r, const double* p, const double* q, size_t n, double* part,
-                    const Scalars* sc, unsigned* np) {
-    const unsigned npair = (unsigned)(n / 2);
+template <typename T>
+void launch_update2_enter(hipStream_t st, double* x, double* r, const double* p, const double* q, T* f0, T* f1, T* u0,
+                          int nx, int ny, int nz, double inv_diag, double* part, const Scalars* sc, unsigned* np) {
+    const unsigned npair = (unsigned)(nx / 2) * ny * nz;
     const unsigned nb = red_blocks(npair);
-    hipLaunchKernelGGL(k_update2, dim3(nb), dim3(kBlock), 0, st, x, r, p, q, npair, part, sc);
+    hipLaunchKernelGGL(k_update2_enter<T>, dim3(nb), dim3(kBlock), 0, st, x, r, p, q, f0, f1, u0, nx, ny, npair,
+                       inv_diag, part, sc);
     *np = nb;
 }
+template void launch_update2_enter<float>(hipStream_t, double*, double*, const double*, const double*, float*, float*,
+                                          float*, int, int, int, double, double*, const Scalars*, unsigned*);
+template void launch_update2_enter<double>(hipStream_t, double*, double*, const double*, const double*, double*,
+                                           double*, double*, int, int, int, double, double*, const Scalars*,
+                                           unsigned*);
 
 // partials (sum z, z.r, z.q), two cells per thread
 template <typename T>
@@ -203,60 +224,6 @@ template void launch_zdots2<float>(hipStream_t, const float*, const float*, cons
 template void launch_zdots2<double>(hipStream_t, const double*, const double*, const double*, const double*, int,
                                     int, int, double*, const Scalars*, unsigned*);
 
-// Fused CG direction update and operator apply:
-// p_new = z + shift + beta p_old at the cell and its 6 neighbours (z split of
-// type T), q = alpha p_new - D L p_new, partials (p_new . q, sum q).
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_dir_apply(const T* __restrict__ z0, const T* __restrict__ z1,
-                                                      const double* __restrict__ po, double* __restrict__ pn,
-                                                      double* __restrict__ q, double alpha, double s, int nx, int ny,
-                                                      int nz, unsigned ncell, double* part, const Scalars* sc) {
-    if (sc->done) return;
-    const double beta = sc->beta, shift = sc->shift;
-    const int hx = nx >> 1;
-    unsigned lo, hi;
-    chunk_of(xcd_block(blockIdx.x, gridDim.x), gridDim.x, ncell, &lo, &hi);
-    double v[2] = {0.0, 0.0};
-    const long long sxy = (long long)nx * ny;
-    for (unsigned idx = lo + threadIdx.x; idx < hi; idx += blockDim.x) {
-        const int X = idx % nx;
-        const unsigned t = idx / nx;
-        const int Y = t % ny, Z = t / ny;
-        auto pnew = [&](int x, int y, int z, long long i) {
-            const size_t j = ((size_t)z * ny + y) * hx + (x >> 1);
-            const double zv = (((x + y + z) & 1) ? (double)z1[j] : (double)z0[j]) + shift;
-            return beta == 0.0 ? zv : zv + beta * po[i];
-        };
-        const long long i = (long long)idx;
-        const int xm = wrapi(X - 1, nx), xp = wrapi(X + 1, nx), ym = wrapi(Y - 1, ny), yp = wrapi(Y + 1, ny);
-        const int zm = wrapi(Z - 1, nz), zp = wrapi(Z + 1, nz);
-        const double c = pnew(X, Y, Z, i);
-        const double a = pnew(xm, Y, Z, i - X + xm) + pnew(xp, Y, Z, i - X + xp);
-        const double b = pnew(X, ym, Z, i + (long long)(ym - Y) * nx) + pnew(X, yp, Z, i + (long long)(yp - Y) * nx);
-        const double d = pnew(X, Y, zm, i + (long long)(zm - Z) * sxy) + pnew(X, Y, zp, i + (long long)(zp - Z) * sxy);
-        const double y = alpha * c - s * (a + b + d - 6.0 * c);
-        pn[idx] = c;
-        q[idx] = y;
-        v[0] += c * y;
-        v[1] += y;
-    }
-    block_partials<2>(v, part, gridDim.x, blockIdx.x);
-}
-
-template <typename T>
-void launch_dir_apply(hipStream_t st, const T* z0, const T* z1, const double* po, double* pn, double* q, double alpha,
-                      double s, int nx, int ny, int nz, double* part, const Scalars* sc, unsigned* np) {
-    const unsigned n = (unsigned)nx * ny * nz;
-    const unsigned nb = red_blocks(n);
-    hipLaunchKernelGGL(k_dir_apply<T>, dim3(nb), dim3(kBlock), 0, st, z0, z1, po, pn, q, alpha, s, nx, ny, nz, n,
-                       part, sc);
-    *np = nb;
-}
-template void launch_dir_apply<float>(hipStream_t, const float*, const float*, const double*, double*, double*,
-                                      double, double, int, int, int, double*, const Scalars*, unsigned*);
-template void launch_dir_apply<double>(hipStream_t, const double*, const double*, const double*, double*, double*,
-                                       double, double, int, int, int, double*, const Scalars*, unsigned*);
-
 void launch_applyA_plain(hipStream_t st, const double* x, double* y, double alpha, double s, int nx, int ny,
                          int nz) {
     const unsigned n = (unsigned)nx * ny * nz;
@@ -292,15 +259,6 @@ __global__ void __launch_bounds__(kBlock) k_residual64(const double* __restrict_
     block_partials<3>(v, part, gridDim.x, blockIdx.x);
 }
 
-void launch_residual64(hipStream_t st, const double* g, const double* x, double* r, double alpha, double s, int nx,
-                       int ny, int nz, double* part, unsigned* np) {
-    const unsigned n = (unsigned)nx * ny * nz;
-    const unsigned nb = red_blocks(n);
-    hipLaunchKernelGGL(k_residual64, dim3(nb), dim3(kBlock), 0, st, g, x, (const double*)nullptr, r, alpha, s, nx,
-                       ny, nz, n, part);
-    *np = nb;
-}
-
 void launch_residual_from_q(hipStream_t st, const double* g, const double* q0, double* r, size_t n, double* part,
                             unsigned* np) {
     const unsigned nb = red_blocks(n);
@@ -316,87 +274,6 @@ __device__ __forceinline__ double split_at(const T* __restrict__ z0, const T* __
     const size_t j = ((size_t)Z * ny + Y) * hx + (X >> 1);
     return ((X + Y + Z) & 1) ? (double)z1[j] : (double)z0[j];
 }
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_dir(const T* __restrict__ z0, const T* __restrict__ z1,
-                                                double* __restrict__ p, int nx, int ny, unsigned ncell,
-                                                const Scalars* sc) {
-    if (sc->done) return;
-    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-    const unsigned idx = b * blockDim.x + threadIdx.x;
-    if (idx >= ncell) return;
-    const double beta = sc->beta, shift = sc->shift;
-    const int X = idx % nx;
-    const unsigned t = idx / nx;
-    const int Y = t % ny, Z = t / ny;
-    const double zv = split_at(z0, z1, X, Y, Z, nx >> 1, ny) + shift;
-    p[idx] = beta == 0.0 ? zv : zv + beta * p[idx];
-}
-
-template <typename T>
-void launch_dir(hipStream_t st, const T* z0, const T* z1, double* p, int nx, int ny, int nz, const Scalars* sc) {
-    const unsigned n = (unsigned)nx * ny * nz;
-    hipLaunchKernelGGL(k_dir<T>, dim3(nblocks(n)), dim3(kBlock), 0, st, z0, z1, p, nx, ny, n, sc);
-}
-template void launch_dir<float>(hipStream_t, const float*, const float*, double*, int, int, int, const Scalars*);
-template void launch_dir<double>(hipStream_t, const double*, const double*, double*, int, int, int, const Scalars*);
-
-__global__ void __launch_bounds__(kBlock) k_update(double* __restrict__ x, double* __restrict__ r,
-                                                   const double* __restrict__ p, const double* __restrict__ q,
-                                                   unsigned n, double* part, const Scalars* sc) {
-    if (sc->done) return;
-    unsigned lo, hi;
-    chunk_of(xcd_block(blockIdx.x, gridDim.x), gridDim.x, n, &lo, &hi);
-    double v[2] = {0.0, 0.0};
-    const double a = sc->alpha;
-    for (unsigned idx = lo + threadIdx.x; idx < hi; idx += blockDim.x) {
-        x[idx] += a * p[idx];
-        const double rv = r[idx] - a * q[idx];
-        r[idx] = rv;
-        v[0] += rv * rv;
-        v[1] += rv;
-    }
-    block_partials<2>(v, part, gridDim.x, blockIdx.x);
-}
-
-void launch_update(hipStream_t st, double* x, double* r, const double* p, const double* q, size_t n, double* part,
-                   const Scalars* sc, unsigned* np) {
-    const unsigned nb = red_blocks(n);
-    hipLaunchKernelGGL(k_update, dim3(nb), dim3(kBlock), 0, st, x, r, p, q, (unsigned)n, part, sc);
-    *np = nb;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_zdots(const T* __restrict__ z0, const T* __restrict__ z1,
-                                                  const double* __restrict__ r, const double* __restrict__ q, int nx,
-                                                  int ny, unsigned ncell, double* part, const Scalars* sc) {
-    if (sc->done) return;
-    unsigned lo, hi;
-    chunk_of(xcd_block(blockIdx.x, gridDim.x), gridDim.x, ncell, &lo, &hi);
-    double v[3] = {0.0, 0.0, 0.0};
-    for (unsigned idx = lo + threadIdx.x; idx < hi; idx += blockDim.x) {
-        const int X = idx % nx;
-        const unsigned t = idx / nx;
-        const double zv = split_at(z0, z1, X, (int)(t % ny), (int)(t / ny), nx >> 1, ny);
-        v[0] += zv;
-        v[1] += zv * r[idx];
-        v[2] += zv * q[idx];
-    }
-    block_partials<3>(v, part, gridDim.x, blockIdx.x);
-}
-
-template <typename T>
-void launch_zdots(hipStream_t st, const T* z0, const T* z1, const double* r, const double* q, int nx, int ny, int nz,
-                  double* part, const Scalars* sc, unsigned* np) {
-    const unsigned n = (unsigned)nx * ny * nz;
-    const unsigned nb = red_blocks(n);
-    hipLaunchKernelGGL(k_zdots<T>, dim3(nb), dim3(kBlock), 0, st, z0, z1, r, q, nx, ny, n, part, sc);
-    *np = nb;
-}
-template void launch_zdots<float>(hipStream_t, const float*, const float*, const double*, const double*, int, int,
-                                  int, double*, const Scalars*, unsigned*);
-template void launch_zdots<double>(hipStream_t, const double*, const double*, const double*, const double*, int, int,
-                                   int, double*, const Scalars*, unsigned*);
 
 // out = scale * out + z   (z split -> natural)
 template <typename T>
@@ -533,12 +410,15 @@ __global__ void __launch_bounds__(kFinBlock) k_fin(int kind, const double* __res
         if (threadIdx.x == 0) {
             sc->pq = pq;
             sc->qsum = qs;
+            sc->mean_next = 0.0;
             if (!(pq > 0.0) || !is_finite_d(pq) || !is_finite_d(sc->rz)) {
                 sc->status = 1;
                 sc->done = 1;
                 sc->alpha = 0.0;
             } else {
                 sc->alpha = sc->rz / pq;
+                // sum(r - alpha q) = sum r - alpha sum q: the mean the fused update removes
+                if (sc->project) sc->mean_next = (sc->rsum - sc->alpha * qs) * sc->inv_ncell;
             }
         }
     } else if (kind == FIN_UPDATE) {

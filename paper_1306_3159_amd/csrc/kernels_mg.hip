@@ -139,6 +139,73 @@ __global__ void __launch_bounds__(kMaxTuneBlock) k_gs_vec(T* __restrict__ uc, co
     *reinterpret_cast<V*>(uc + row + i0) = out;
 }
 
+// The closing red half-sweep on the finest level fused with the CG dots of
+// its result z: block partials (sum z, z.r, z.q) over both colours, r and q
+// natural FP64 (split index i of a row is the natural cell pair 2i, 2i + 1).
+// The black z at the thread's split indices are the x-neighbour vector the
+// sweep loads anyway. Needs hx % VW == 0 and a non-null sc.
+template <typename T>
+__global__ void __launch_bounds__(kMaxTuneBlock) k_gs_vec_dots(T* __restrict__ uc, const T* __restrict__ uo,
+                                                        const T* __restrict__ fc, int hx, int ny, int nz, T s,
+                                                        T inv_diag, const double* __restrict__ r,
+                                                        const double* __restrict__ q, double* part,
+                                                        const Scalars* sc) {
+    typedef typename VecOf<T>::type V;
+    typedef typename VecOf<double>::type D2;
+    constexpr int VW = VecOf<T>::W;
+    if (sc->done) return;
+    const int hv = hx / VW;
+    const unsigned nv = (unsigned)hv * ny * nz;
+    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (idx < nv) {
+        const int iv = idx % hv;
+        const unsigned t = idx / hv;
+        const int y = t % ny, z = t / ny;
+        const int i0 = iv * VW;
+        const int par = (y + z) & 1;  // red cells sit at x = 2i + par; the even cell's colour is par
+        const size_t row = ((size_t)z * ny + y) * hx;
+        V left, right;
+        row_neighbours<T>(uo + row, i0, hx, par, left, right);
+        const V blk = *reinterpret_cast<const V*>(uo + row + i0);
+        const V ym = *reinterpret_cast<const V*>(uo + ((size_t)z * ny + wrapi(y - 1, ny)) * hx + i0);
+        const V yp = *reinterpret_cast<const V*>(uo + ((size_t)z * ny + wrapi(y + 1, ny)) * hx + i0);
+        const V zm = *reinterpret_cast<const V*>(uo + ((size_t)wrapi(z - 1, nz) * ny + y) * hx + i0);
+        const V zp = *reinterpret_cast<const V*>(uo + ((size_t)wrapi(z + 1, nz) * ny + y) * hx + i0);
+        const V f = *reinterpret_cast<const V*>(fc + row + i0);
+        V out;
+#pragma unroll
+        for (int k = 0; k < VW; ++k)
+            out[k] = (f[k] + s * (((left[k] + right[k]) + (ym[k] + yp[k])) + (zm[k] + zp[k]))) * inv_diag;
+        *reinterpret_cast<V*>(uc + row + i0) = out;
+#pragma unroll
+        for (int k = 0; k < VW; ++k) {
+            const double zr = (double)out[k], zb = (double)blk[k];
+            const double za = par ? zb : zr, zc = par ? zr : zb;  // even, odd cell
+            const D2 rv = reinterpret_cast<const D2*>(r)[row + i0 + k];
+            const D2 qv = reinterpret_cast<const D2*>(q)[row + i0 + k];
+            acc[0] += za + zc;
+            acc[1] += za * rv[0] + zc * rv[1];
+            acc[2] += za * qv[0] + zc * qv[1];
+        }
+    }
+    block_partials<3>(acc, part, gridDim.x, blockIdx.x);
+}
+
+// Returns the number of partial slots, or 0 when the level is not vectorizable
+// (nothing launched: the caller sweeps with launch_gs and forms the dots apart).
+template <typename T>
+unsigned launch_gs_dots(hipStream_t st, T* uc, const T* uo, const T* fc, int hx, int ny, int nz, double s,
+                        double inv_diag, const double* r, const double* q, double* part, const Scalars* sc, int bs) {
+    constexpr int VW = VecOf<T>::W;
+    if (hx % VW != 0 || hx < VW) return 0;
+    const unsigned nv = (unsigned)(hx / VW) * ny * nz;
+    const unsigned nb = nblocks(nv, bs);
+    hipLaunchKernelGGL(k_gs_vec_dots<T>, dim3(nb), dim3(bs), 0, st, uc, uo, fc, hx, ny, nz, (T)s, (T)inv_diag, r, q,
+                       part, sc);
+    return nb;
+}
+
 template <typename T>
 void launch_gs(hipStream_t st, T* uc, const T* uo, const T* fc, int hx, int ny, int nz, int color, double s,
                double inv_diag, const Scalars* sc, int bs) {
@@ -695,6 +762,8 @@ hipError_t tail_set_lds(size_t bytes) {
                                      int);                                                                          \
     template void launch_prolong<T>(hipStream_t, const T*, const T*, int, T*, T*, int, int, int, const Scalars*,    \
                                     int);                                                                           \
+    template unsigned launch_gs_dots<T>(hipStream_t, T*, const T*, const T*, int, int, int, double, double,         \
+                                        const double*, const double*, double*, const Scalars*, int);                \
     template void launch_coarse<T>(hipStream_t, const T*, T*, const double*, int, const Scalars*);             \
     template void launch_tail<T>(hipStream_t, const T*, const T*, T*, T*, const TailDesc&, const double*,         \
                                  const Scalars*);                                                                   \

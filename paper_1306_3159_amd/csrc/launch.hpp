@@ -12,38 +12,26 @@ void launch_applyA(hipStream_t st, const double* p, double* q, double alpha, dou
 // y = alpha x - D L x (no partials, no guard)
 void launch_applyA_plain(hipStream_t st, const double* x, double* y, double alpha, double s, int nx, int ny,
                          int nz);
-// r = g - alpha x + D L x ; partials (r.r, sum r, g.g)
-void launch_residual64(hipStream_t st, const double* g, const double* x, double* r, double alpha, double s,
-                       int nx, int ny, int nz, double* part, unsigned* nparts_out);
 // r = g - q0 (q0 may be null: r = g); partials (r.r, sum r, g.g)
 void launch_residual_from_q(hipStream_t st, const double* g, const double* q0, double* r, size_t n, double* part,
                             unsigned* nparts_out);
-// p = z + shift + beta p  (z split, level-0 layout of type T)
-template <typename T>
-void launch_dir(hipStream_t st, const T* z0, const T* z1, double* p, int nx, int ny, int nz,
-                const Scalars* sc);
-// p_new = z + shift + beta p_old (on the fly at 7 points), q = A p_new ; partials (p.q, sum q)
-template <typename T>
-void launch_dir_apply(hipStream_t st, const T* z0, const T* z1, const double* po, double* pn, double* q, double alpha,
-                      double s, int nx, int ny, int nz, double* part, const Scalars* sc, unsigned* nparts_out);
 // Two-cells-per-thread forms (nx even): stencil with partials, direction update,
 // CG update, z dots.
 void launch_applyA2(hipStream_t st, const double* p, double* q, double alpha, double s, int nx, int ny, int nz,
                     double* part, const Scalars* sc, unsigned* nparts_out);
+// p = z + shift + beta p (z split, level-0 layout of type T)
 template <typename T>
 void launch_dir2(hipStream_t st, const T* z0, const T* z1, double* p, int nx, int ny, int nz, const Scalars* sc);
-void launch_update2(hipStream_t st, double* x, double* r, const double* p, const double* q, size_t n, double* part,
-                    const Scalars* sc, unsigned* nparts_out);
+// x += alpha p ; r -= alpha q with partials (r.r, sum r), and the V-cycle entry of
+// the new r (f split, first red sweep u0)
+template <typename T>
+void launch_update2_enter(hipStream_t st, double* x, double* r, const double* p, const double* q, T* f0, T* f1, T* u0,
+                          int nx, int ny, int nz, double inv_diag, double* part, const Scalars* sc,
+                          unsigned* nparts_out);
+// partials (sum z, z.r, z.q) with z split of type T
 template <typename T>
 void launch_zdots2(hipStream_t st, const T* z0, const T* z1, const double* r, const double* q, int nx, int ny, int nz,
                    double* part, const Scalars* sc, unsigned* nparts_out);
-// x += alpha p ; r -= alpha q ; partials (r.r, sum r)
-void launch_update(hipStream_t st, double* x, double* r, const double* p, const double* q, size_t n,
-                   double* part, const Scalars* sc, unsigned* nparts_out);
-// partials (sum z, z.r, z.q) with z split of type T
-template <typename T>
-void launch_zdots(hipStream_t st, const T* z0, const T* z1, const double* r, const double* q, int nx, int ny,
-                  int nz, double* part, const Scalars* sc, unsigned* nparts_out);
 // x += shift + z (final correction of a preconditioner application, z split)
 template <typename T>
 void launch_split_to_nat(hipStream_t st, const T* z0, const T* z1, double* out, int nx, int ny, int nz,
@@ -68,6 +56,12 @@ void launch_enter(hipStream_t st, const double* r, T* f0, T* f1, T* u0, int nx, 
 template <typename T>
 void launch_gs(hipStream_t st, T* uc, const T* uo, const T* fc, int hx, int ny, int nz, int color, double s,
                double inv_diag, const Scalars* sc, int bs = kBlock);
+// closing red half-sweep of the finest level + partials (sum z, z.r, z.q); returns
+// the partial count, 0 if not applicable (nothing launched)
+template <typename T>
+unsigned launch_gs_dots(hipStream_t st, T* uc, const T* uo, const T* fc, int hx, int ny, int nz, double s,
+                        double inv_diag, const double* r, const double* q, double* part, const Scalars* sc,
+                        int bs = kBlock);
 // red residual after pre-smoothing (the black one is zero after the closing black half-sweep)
 template <typename T>
 void launch_resid_red(hipStream_t st, const T* u0, const T* u1, const T* f0, T* r0, int hx, int ny, int nz, double s,
