@@ -226,11 +226,15 @@ int blob_rd_solve_batch(blob_rd_t* h, int32_t n, const int32_t* kind, double alp
 
 /* Launch one kernel of the solve path `reps` times back to back on the
  * handle's stream, bracketed by HIP events, on the handle's own workspace
- * buffers (their contents are overwritten). With BLOB_RD_KERNEL_COLD each
- * launch is timed alone after streaming >= 512 MB through the cache (HBM
- * rather than Infinity Cache bandwidth; needs a grid of >= 128^3 cells). avg_ms receives the mean time
- * per launch and bytes the algorithmic HBM bytes one launch must move
- * (each input read once, each output written once). */
+ * buffers (their contents are overwritten). BLOB_RD_KERNEL_COLD asks for HBM
+ * rather than last-level-cache bandwidth: the Gauss-Seidel and stencil
+ * kernels then run back to back over independent buffer sets carved from the
+ * handle's eight FP64 grid vectors (64 bytes per cell in all, more than the
+ * 256 MB Infinity Cache from 160^3 cells), so each launch finds its data
+ * evicted; the other kernels are each timed alone after >= 512 MB have been
+ * streamed through the cache. avg_ms receives the mean time per launch and
+ * bytes the algorithmic HBM bytes one launch must move (each input read once,
+ * each output written once). */
 int blob_rd_time_kernel(blob_rd_t h, int kernel, int reps, double* avg_ms, double* bytes);
 
 /* ---- Launch-shape autotuning ----
