@@ -88,11 +88,13 @@ def summary(st):
 
 
 def bench_batch(args, dev, rtol):
-    """64 uneven suspensions (grids 32..128, up to 2000 blobs, reactive/absorbing 50/50) solved
-    concurrently, each handle on its own stream; a step is the whole batch."""
+    """64 uneven suspensions (grids 32..128, up to 2000 blobs, reactive/absorbing 50/50); a step
+    is the whole batch. value: the lock-step executor (every instance's CG iterations in shared
+    batched launches, one captured graph replayed in rounds); beside it the per-instance-stream
+    executor and one-by-one solves."""
     import torch
     import workloads as W
-    from paper_1306_3159_amd import BlobRD, MIXED, solve_batch
+    from paper_1306_3159_amd import BlobRD, MIXED, solve_batch, solve_batched
     insts = W.batch_instances()
     Hs = [BlobRD(i.n, torch.tensor(i.q, device=dev), torch.tensor(i.kappa, device=dev), precision=MIXED, rtol=rtol,
                  stream=torch.cuda.Stream(dev)) for i in insts]
@@ -100,14 +102,23 @@ def bench_batch(args, dev, rtol):
     kinds = [1 if i.kind == "absorbing" else 0 for i in insts]
     cs = [torch.zeros_like(f) for f in fs]
     ls = [torch.zeros(i.N, dtype=torch.float64, device=dev) if k else None for i, k in zip(insts, kinds)]
+    bstream = torch.cuda.Stream(dev)
 
-    def step():
+    def step_lockstep():
+        for c in cs:
+            c.zero_()
+        torch.cuda.synchronize()
+        return solve_batched(Hs, kinds, fs, cs, ls, stream=bstream)
+
+    def step_streams():
         for c in cs:
             c.zero_()
         torch.cuda.synchronize()
         return solve_batch(Hs, kinds, fs, cs, ls, threads=args.threads)
 
-    dt, (rc, stats) = timed(step, args.steps, args.warmup)
+    dt, (rc, stats) = timed(step_lockstep, args.steps, args.warmup)
+    sdt, (src, sstats) = timed(step_streams, max(2, args.steps // 2), 1)
+    ns = max(2, args.steps // 2)
     t1 = time.perf_counter()
     for H, k, f, c, l in zip(Hs, kinds, fs, cs, ls):
         c.zero_()
@@ -123,8 +134,9 @@ def bench_batch(args, dev, rtol):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64 Krylov/residuals + f32 V-cycles", "data": "synthetic",
            "config": {"workload": "batch64", "instances": len(insts), "total_cells": cells,
-                      "total_blobs": sum(i.N for i in insts), "rtol": rtol, "threads": args.threads},
+                      "total_blobs": sum(i.N for i in insts), "rtol": rtol, "executor": "lock-step batched launches"},
            "rc": rc, "max_rel_resid": max(s["rel_resid"] for s in stats),
+           "streams_executor": {"instances_per_s": len(insts) * ns / sdt, "threads": args.threads, "rc": src},
            "serial_instances_per_s": len(insts) / serial}
     for H in Hs:
         H.close()

@@ -6,8 +6,8 @@ provides device memory and streams, every step of a solve runs in the
 library's kernels. There is no CPU fallback: if the library is missing the
 import of :mod:`paper_1306_3159_amd.native` fails loudly.
 """
-from .native import (BlobRD, Net, NET_PARAMS, solve_batch, BlobRDError, NotConverged, Stats, load_library, FP64, MIXED,
-                     PRECOND_NONE, PRECOND_DIAGONAL, PRECOND_LEARNED)
+from .native import (BlobRD, Net, NET_PARAMS, solve_batch, solve_batched, BlobRDError, NotConverged, Stats,
+                     load_library, FP64, MIXED, PRECOND_NONE, PRECOND_DIAGONAL, PRECOND_LEARNED)
 
-__all__ = ["BlobRD", "Net", "NET_PARAMS", "solve_batch", "BlobRDError", "NotConverged", "Stats", "load_library", "FP64", "MIXED",
-           "PRECOND_NONE", "PRECOND_DIAGONAL", "PRECOND_LEARNED"]
+__all__ = ["BlobRD", "Net", "NET_PARAMS", "solve_batch", "solve_batched", "BlobRDError", "NotConverged", "Stats",
+           "load_library", "FP64", "MIXED", "PRECOND_NONE", "PRECOND_DIAGONAL", "PRECOND_LEARNED"]

@@ -92,6 +92,54 @@ struct PairGeom {
     int ncx, ncy, ncz;  // pair-search cells per axis
 };
 
+struct BlobGeom {
+    int nx, ny, nz;
+    int tx, ty, tz;      // tile edge per axis (divides the grid edge)
+    int ntx, nty, ntz;   // tiles per axis
+    double h;
+    int w;
+};
+
+// Logical block of a launch: partial-sum slot b of nb. Solo kernels pass
+// (blockIdx.x, gridDim.x); batched kernels pass an instance's local slot, so
+// every instance's partition of work and of partial sums is the solo one.
+struct Blk {
+    unsigned b, nb;
+};
+
+// One instance's slice of a batched launch: global blocks [block0, block0 + nb)
+// (block0 a multiple of 8, so a slot keeps the XCD of its solo launch).
+struct BatchEntry {
+    unsigned block0, nb;
+    int inst;
+    int pad;
+};
+
+// Everything a batched CG iteration reads about one instance (device memory).
+struct InstDev {
+    Scalars* sc;
+    double* part;
+    double *x, *r, *p, *q;               // CG vectors of the current solve
+    double alpha;                         // operator alpha I - D L (+ S kappa J)
+    int nx, ny, nz, nlev, t;              // level 0 dims, levels, first tail level
+    int np_apply, np_update, np_dots;     // partial slots of the three reductions
+    void* lv[kMaxLevels][5];              // split level arrays u0, u1, f0, f1, r0
+    int lnx[kMaxLevels], lny[kMaxLevels], lnz[kMaxLevels];
+    double ls[kMaxLevels], ldiag[kMaxLevels];  // D / h_l^2 and alpha + 6 s_l
+    int blobs, N;                         // blob term in the operator (reactive)
+    BlobGeom geom;
+    const int* base;
+    const double* wts;
+    const int* offsets;
+    const int* perm;
+    const double* kappa;
+    double* jx;
+    double* mu;
+    double inv_h3;
+    const double* cinv;                   // coarsest (pseudo-)inverse for alpha
+    TailDesc tail;
+};
+
 struct LevelDims {
     int nx, ny, nz;   // cells
     int hx;           // nx / 2 (split levels)
@@ -143,6 +191,32 @@ inline unsigned red_blocks(size_t n) {
     const unsigned nb = nblocks(n);
     return nb < kRedBlocks ? nb : kRedBlocks;
 }
+// Entry of a batched launch that owns global block g (entries sorted by block0).
+__device__ __forceinline__ int batch_entry(const BatchEntry* e, int n, unsigned g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (e[mid].block0 <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// The instance and local block of this batched block, or null when the block
+// is padding, the instance is not gated in, or its solve is done (uniform per
+// block, so callers may return before barriers).
+__device__ __forceinline__ const InstDev* batch_slot(const InstDev* inst, const int* gate, const BatchEntry* ent,
+                                                     int nent, Blk& blk) {
+    const BatchEntry e = ent[batch_entry(ent, nent, blockIdx.x)];
+    const unsigned b = blockIdx.x - e.block0;
+    if (b >= e.nb || !gate[e.inst]) return nullptr;
+    const InstDev* I = inst + e.inst;
+    if (I->sc->done) return nullptr;
+    blk.b = b;
+    blk.nb = e.nb;
+    return I;
+}
+
 // chunk [lo, hi) of logical block b of nb over n items (chunks are multiples of blockDim)
 __device__ __forceinline__ void chunk_of(unsigned b, unsigned nb, unsigned n, unsigned* lo, unsigned* hi) {
     const unsigned per = ((n + nb - 1) / nb + blockDim.x - 1) / blockDim.x * blockDim.x;

@@ -22,6 +22,8 @@
 #include <algorithm>
 #include <atomic>
 #include <thread>
+#include <mutex>
+#include <condition_variable>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -265,6 +267,8 @@ std::vector<double> coarse_inverse(const LevelDims& C, double D, double alpha) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+struct BatchServer;
+
 struct blob_rd {
     Plan P;
     blob_rd_params prm{};
@@ -314,6 +318,9 @@ struct blob_rd {
         PairGeom pg{};
     } lrn;
     int fallback = 0;
+    // lock-step batch executor this handle currently belongs to (null: solo)
+    BatchServer* batch = nullptr;
+    int batch_slot = -1;
 
     template <typename T>
     T* at(size_t off) const {
@@ -567,6 +574,20 @@ void blob_term(blob_rd* H, const double* p, double* q, const Scalars* sc) {
                   H->at<int>(P.off_offsets), H->at<int>(P.off_perm), q, q, H->inv_h3(), 1, sc);
 }
 
+// Batch executor hooks (defined with the executor below).
+void batch_run_cg(blob_rd* H, double* x, int maxit, bool blobs, double alpha);
+
+// Algorithmic bytes of one CG iteration inside the CG loop (update with the
+// V-cycle entry, V-cycle with the fused dots).
+double iteration_bytes(const blob_rd* H) {
+    const Plan& P = H->P;
+    const int L = P.nlev - 1;
+    const int t = std::min(H->tail_level[P.esz == 4 ? 0 : 1], L);
+    double b = (double)P.ncell * (P.esz + 16 + 16 + 48 + 1.5 * P.esz) + (double)P.ncell * 16;
+    for (int l = 0; l < t; ++l) b += (double)P.ncell / (1 << (3 * l)) * P.esz * (kPreRestrictBytes + kProlongPostBytes);
+    return b;
+}
+
 struct PcgResult {
     int iters = 0;
     int status = 0;
@@ -635,6 +656,22 @@ PcgResult pcg(blob_rd* H, bool with_blobs, double alpha, const double* g, double
         H->alg_bytes += (double)P.ncell * (P.esz + 16 + 16 + 48 + 1.5 * P.esz);
         H->st = keep;
     };
+    if (H->batch) {
+        // The lock-step batch executor runs this solve's iterations in its
+        // batched launches, together with the other instances' solves.
+        HIPCHK(hipStreamSynchronize(st));
+        batch_run_cg(H, x, maxit, blobs, alpha);
+        sync_read(H, H->hsc, H->sc(), sizeof(Scalars));
+        res.iters = H->hsc->iters;
+        hist = res.iters;
+        H->alg_bytes += iteration_bytes(H) * res.iters;
+        H->vcycles += res.iters;
+        res.status = H->hsc->status;
+        res.rr = H->hsc->rr;
+        res.gg = H->hsc->gg;
+        res.converged = H->hsc->done && H->hsc->status == 0;
+        return res;
+    }
     blob_rd::GraphEntry* ge = nullptr;
     if (H->use_graphs && x == H->grid(G_U)) {
         for (auto& g : H->graphs)
@@ -1460,6 +1497,355 @@ void drop_graphs(blob_rd* H) {
 
 }  // namespace
 
+namespace {
+
+// ===========================================================================
+// Lock-step batch executor: the CG iterations of many independent solves run
+// as one sequence of batched launches (each launch covers one step, e.g. one
+// Gauss-Seidel half-sweep of one level, for every instance through a flat
+// block table), captured once as a HIP graph and replayed in rounds. Each
+// instance's solver logic (GMRES, set-up, final solves) runs on its own host
+// thread and stream; whenever it needs CG iterations it hands them to the
+// executor and waits. An instance takes part in a round only when it is gated
+// in, and its kernels become no-ops once its done flag is set.
+// ===========================================================================
+constexpr int kBatchRoundIters = 2;  // CG iterations per graph replay
+
+}  // namespace
+
+struct BatchTable {
+    int off = 0, n = 0;
+    unsigned blocks = 0;
+};
+
+struct BatchServer {
+    int n = 0, esz = 4;
+    double alpha = 0.0;
+    std::vector<blob_rd*> hs;
+    hipStream_t st = nullptr;
+    InstDev* d_inst = nullptr;
+    int* d_gate = nullptr;
+    int* d_status = nullptr;
+    BatchEntry* d_ent = nullptr;
+    InstDev* h_inst = nullptr;   // pinned mirrors
+    int* h_gate = nullptr;
+    int* h_status = nullptr;
+    BatchTable t_dir, t_apply, t_update, t_dots, t_interp, t_spread;
+    std::vector<BatchTable> t_lv, t_rs;  // per level: sweep/residual/correction, restriction
+    int Lmax = 0;
+    unsigned tail_lds = 0;
+    hipGraphExec_t exec = nullptr;
+    int rounds = 0;
+    // coordination
+    struct Slot {
+        bool waiting = false;   // asked for CG iterations
+        bool gated = false;     // taking part in rounds
+        bool released = false;  // its CG run has ended
+        bool dirty = false;     // descriptor changed since the last upload
+        bool finished = false;  // its whole solve returned
+        int maxit = 0;
+        std::condition_variable cv;
+    };
+    std::vector<Slot> slots;
+    std::mutex m;
+    std::condition_variable cv;
+    std::string fault;  // set when a round fails; waiting instances then fail too
+};
+
+namespace {
+
+size_t batch_align(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t batch_bytes(int n) {
+    return batch_align((size_t)n * sizeof(InstDev)) + 2 * batch_align((size_t)n * 2 * sizeof(int)) +
+           batch_align((size_t)n * (6 + 2 * kMaxLevels) * sizeof(BatchEntry));
+}
+
+// Why instance H cannot run its CG iterations in batched launches (empty: it can).
+std::string batch_unfit(const blob_rd* H, int esz) {
+    const Plan& P = H->P;
+    const int L = P.nlev - 1;
+    const int t = H->tail_level[P.esz == 4 ? 0 : 1];
+    const int VW = 16 / P.esz;
+    if (P.esz != esz) return "mixed precisions";
+    if (t >= L || t < 1) return "no coarse tail below a per-level finest level";
+    for (int l = 0; l < t; ++l) {
+        const LevelDims& d = P.lev[l];
+        if (d.hx % VW != 0 || (d.nx / 2) % 4 != 0) return "level " + std::to_string(l) + " not vectorizable";
+    }
+    return "";
+}
+
+__global__ void k_batch_status(const InstDev* inst, int n, int* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[2 * i] = inst[i].sc->done;
+    out[2 * i + 1] = inst[i].sc->iters;
+}
+
+template <typename T>
+void batch_round(BatchServer& B, hipStream_t s) {
+    const InstDev* I = B.d_inst;
+    const int* G = B.d_gate;
+    auto E = [&](const BatchTable& t) { return B.d_ent + t.off; };
+    for (int it = 0; it < kBatchRoundIters; ++it) {
+        launchb_cg<T>(s, BCG_DIR, I, G, E(B.t_dir), B.t_dir.n, B.t_dir.blocks, B.n);
+        launchb_cg<T>(s, BCG_APPLY, I, G, E(B.t_apply), B.t_apply.n, B.t_apply.blocks, B.n);
+        if (B.t_interp.n) {
+            launchb_blob(s, 0, I, G, E(B.t_interp), B.t_interp.n, B.t_interp.blocks);
+            launchb_blob(s, 1, I, G, E(B.t_spread), B.t_spread.n, B.t_spread.blocks);
+        }
+        launchb_cg<T>(s, BCG_FIN_ALPHA, I, G, nullptr, 0, 0, B.n);
+        launchb_cg<T>(s, BCG_UPDATE, I, G, E(B.t_update), B.t_update.n, B.t_update.blocks, B.n);
+        launchb_cg<T>(s, BCG_FIN_UPDATE, I, G, nullptr, 0, 0, B.n);
+        for (int l = 0; l < B.Lmax; ++l) {
+            const BatchTable& a = B.t_lv[l];
+            const BatchTable& r = B.t_rs[l];
+            launchb_mg<T>(s, BMG_GS, I, G, E(a), a.n, a.blocks, l, 1, 0);
+            launchb_mg<T>(s, BMG_GS, I, G, E(a), a.n, a.blocks, l, 0, 0);
+            launchb_mg<T>(s, BMG_GS, I, G, E(a), a.n, a.blocks, l, 1, 0);
+            launchb_mg<T>(s, BMG_RESID, I, G, E(a), a.n, a.blocks, l, 0, 0);
+            launchb_mg<T>(s, BMG_RESTRICT, I, G, E(r), r.n, r.blocks, l, 0, 0);
+        }
+        launchb_mg<T>(s, BMG_TAIL, I, G, nullptr, B.n, B.n, 0, 0, B.tail_lds);
+        for (int l = B.Lmax - 1; l >= 0; --l) {
+            const BatchTable& a = B.t_lv[l];
+            launchb_mg<T>(s, BMG_PROLONG, I, G, E(a), a.n, a.blocks, l, 0, 0);
+            launchb_mg<T>(s, BMG_GS, I, G, E(a), a.n, a.blocks, l, 1, 0);
+            launchb_mg<T>(s, BMG_GS, I, G, E(a), a.n, a.blocks, l, 0, 0);
+            launchb_mg<T>(s, BMG_GS, I, G, E(a), a.n, a.blocks, l, 1, 0);
+            if (l == 0)
+                launchb_mg<T>(s, BMG_GS_DOTS, I, G, E(B.t_dots), B.t_dots.n, B.t_dots.blocks, 0, 0, 0);
+            else
+                launchb_mg<T>(s, BMG_GS, I, G, E(a), a.n, a.blocks, l, 0, 0);
+        }
+        launchb_cg<T>(s, BCG_FIN_BETA, I, G, nullptr, 0, 0, B.n);
+    }
+    hipLaunchKernelGGL(k_batch_status, dim3((B.n + 63) / 64), dim3(64), 0, s, I, B.n, B.d_status);
+}
+
+// Descriptor of instance H for CG iterations with operator alpha (x set per CG run).
+void batch_describe(BatchServer& B, int i, blob_rd* H, bool blobs) {
+    const Plan& P = H->P;
+    InstDev& D = B.h_inst[i];
+    std::memset(&D, 0, sizeof(InstDev));
+    const int L = P.nlev - 1;
+    const int t = H->tail_level[P.esz == 4 ? 0 : 1];
+    D.sc = H->sc();
+    D.part = H->part();
+    D.x = H->grid(G_U);
+    D.r = H->grid(G_R);
+    D.p = H->grid(G_P);
+    D.q = H->grid(G_Q);
+    D.alpha = B.alpha;
+    D.nx = P.lev[0].nx;
+    D.ny = P.lev[0].ny;
+    D.nz = P.lev[0].nz;
+    D.nlev = P.nlev;
+    D.t = t;
+    for (int l = 0; l <= L; ++l) {
+        for (int k = 0; k < 5; ++k) D.lv[l][k] = H->ws + P.off_lvl[l][k];
+        D.lnx[l] = P.lev[l].nx;
+        D.lny[l] = P.lev[l].ny;
+        D.lnz[l] = P.lev[l].nz;
+        D.ls[l] = H->prm.D / (P.lev[l].h * P.lev[l].h);
+        D.ldiag[l] = B.alpha + 6.0 * D.ls[l];
+    }
+    const unsigned npair = (unsigned)(D.nx / 2) * D.ny * D.nz;
+    D.np_apply = D.np_update = (int)red_blocks(npair);
+    D.np_dots = (int)nblocks((size_t)(P.lev[0].hx / (16 / P.esz)) * D.ny * D.nz);
+    D.blobs = blobs ? 1 : 0;
+    D.N = P.N;
+    D.geom = P.geom;
+    D.base = H->at<int>(P.off_base);
+    D.wts = H->at<double>(P.off_wts);
+    D.offsets = H->at<int>(P.off_offsets);
+    D.perm = H->at<int>(P.off_perm);
+    D.kappa = H->at<double>(P.off_kappa);
+    D.jx = H->nv(0);
+    D.mu = H->nv(1);
+    D.inv_h3 = H->inv_h3();
+    D.cinv = select_cinv(H, B.alpha);
+    D.tail = P.esz == 4 ? make_tail<float>(H, t, B.alpha) : make_tail<double>(H, t, B.alpha);
+}
+
+void batch_setup(BatchServer& B, char* ws, size_t ws_bytes, const int32_t* kind) {
+    const int n = B.n;
+    char* o = ws;
+    B.d_inst = reinterpret_cast<InstDev*>(o);
+    o += batch_align((size_t)n * sizeof(InstDev));
+    B.d_gate = reinterpret_cast<int*>(o);
+    o += batch_align((size_t)n * 2 * sizeof(int));
+    B.d_status = reinterpret_cast<int*>(o);
+    o += batch_align((size_t)n * 2 * sizeof(int));
+    B.d_ent = reinterpret_cast<BatchEntry*>(o);
+    (void)ws_bytes;
+    HIPCHK(hipHostMalloc((void**)&B.h_inst, (size_t)n * sizeof(InstDev), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&B.h_gate, (size_t)n * 2 * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&B.h_status, (size_t)n * 2 * sizeof(int), hipHostMallocDefault));
+    B.Lmax = 0;
+    for (int i = 0; i < n; ++i) {
+        blob_rd* H = B.hs[i];
+        const bool blobs = kind[i] == 0 && H->P.N > 0 && H->has_kappa;
+        batch_describe(B, i, H, blobs);
+        HIPCHK(hipStreamSynchronize(H->st));  // coarse inverse uploads
+        B.Lmax = std::max(B.Lmax, B.h_inst[i].t);
+        B.tail_lds = std::max(B.tail_lds, B.h_inst[i].tail.lds_bytes);
+        B.h_gate[i] = 0;
+    }
+    std::vector<BatchEntry> ents;
+    auto table = [&](auto nb_of) {
+        BatchTable t;
+        t.off = (int)ents.size();
+        unsigned g = 0;
+        for (int i = 0; i < n; ++i) {
+            const unsigned nb = nb_of(i);
+            if (!nb) continue;
+            ents.push_back(BatchEntry{g, nb, i, 0});
+            g += (nb + 7u) & ~7u;
+            ++t.n;
+        }
+        t.blocks = g;
+        return t;
+    };
+    const int VW = 16 / B.esz;
+    auto npair = [&](int i) { const InstDev& D = B.h_inst[i]; return (size_t)(D.nx / 2) * D.ny * D.nz; };
+    auto nv = [&](int i, int l) {
+        const InstDev& D = B.h_inst[i];
+        return (size_t)(D.lnx[l] / 2 / VW) * D.lny[l] * D.lnz[l];
+    };
+    B.t_dir = table([&](int i) { return nblocks(npair(i)); });
+    B.t_apply = table([&](int i) { return red_blocks(npair(i)); });
+    B.t_update = table([&](int i) { return red_blocks(npair(i)); });
+    B.t_dots = table([&](int i) { return nblocks(nv(i, 0)); });
+    B.t_interp = table([&](int i) {
+        const InstDev& D = B.h_inst[i];
+        return D.blobs ? (unsigned)((D.N + kBlock / 64 - 1) / (kBlock / 64)) : 0u;
+    });
+    B.t_spread = table([&](int i) {
+        const InstDev& D = B.h_inst[i];
+        return D.blobs ? (unsigned)(D.geom.ntx * D.geom.nty * D.geom.ntz) : 0u;
+    });
+    B.t_lv.assign(B.Lmax, BatchTable{});
+    B.t_rs.assign(B.Lmax, BatchTable{});
+    for (int l = 0; l < B.Lmax; ++l) {
+        B.t_lv[l] = table([&](int i) { return l < B.h_inst[i].t ? nblocks(nv(i, l)) : 0u; });
+        B.t_rs[l] = table([&](int i) {
+            const InstDev& D = B.h_inst[i];
+            return l < D.t ? nblocks((size_t)(D.lnx[l] / 2 / 4) * (D.lny[l] / 2) * (D.lnz[l] / 2)) : 0u;
+        });
+    }
+    if (ents.size() > (size_t)n * (6 + 2 * kMaxLevels)) throw Err(BLOB_RD_EDEVICE, "batch table overflow");
+    HIPCHK(hipMemcpyAsync(B.d_ent, ents.data(), ents.size() * sizeof(BatchEntry), hipMemcpyHostToDevice, B.st));
+    HIPCHK(hipMemcpyAsync(B.d_inst, B.h_inst, (size_t)n * sizeof(InstDev), hipMemcpyHostToDevice, B.st));
+    HIPCHK(hipMemcpyAsync(B.d_gate, B.h_gate, (size_t)n * sizeof(int), hipMemcpyHostToDevice, B.st));
+    HIPCHK(hipStreamSynchronize(B.st));
+    if (B.esz == 4) HIPCHK(tail_set_lds_batched<float>(std::max<unsigned>(B.tail_lds, 1)));
+    else HIPCHK(tail_set_lds_batched<double>(std::max<unsigned>(B.tail_lds, 1)));
+    hipStream_t cap;
+    HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    if (B.esz == 4) batch_round<float>(B, cap);
+    else batch_round<double>(B, cap);
+    hipGraph_t graph;
+    HIPCHK(hipStreamEndCapture(cap, &graph));
+    HIPCHK(hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+}
+
+void batch_teardown(BatchServer& B) {
+    if (B.exec) (void)hipGraphExecDestroy(B.exec);
+    if (B.h_inst) (void)hipHostFree(B.h_inst);
+    if (B.h_gate) (void)hipHostFree(B.h_gate);
+    if (B.h_status) (void)hipHostFree(B.h_status);
+    B.exec = nullptr;
+    B.h_inst = nullptr;
+    B.h_gate = B.h_status = nullptr;
+}
+
+// Instance side: hand this CG run (x, at most maxit iterations) to the executor
+// and wait until it has converged, failed or used its iterations.
+void batch_run_cg(blob_rd* H, double* x, int maxit, bool blobs, double alpha) {
+    BatchServer& B = *H->batch;
+    const int i = H->batch_slot;
+    std::unique_lock<std::mutex> lk(B.m);
+    if (!B.fault.empty()) throw Err(BLOB_RD_EDEVICE, "batch executor: " + B.fault);
+    // the batched launches were laid out for one operator per instance
+    if (alpha != B.alpha || (blobs ? 1 : 0) != B.h_inst[i].blobs)
+        throw Err(BLOB_RD_EINVAL, "batch executor: CG operator differs from the one the batch was laid out for");
+    BatchServer::Slot& S = B.slots[i];
+    if (B.h_inst[i].x != x) {
+        B.h_inst[i].x = x;
+        S.dirty = true;
+    }
+    S.maxit = maxit;
+    S.released = false;
+    S.waiting = true;
+    B.cv.notify_all();
+    S.cv.wait(lk, [&] { return S.released || !B.fault.empty(); });
+    if (!B.fault.empty() && !S.released) throw Err(BLOB_RD_EDEVICE, "batch executor: " + B.fault);
+}
+
+// Executor side: rounds of the captured graph for the gated instances until
+// every instance's solve has returned.
+void batch_serve(BatchServer& B) {
+    for (;;) {
+        std::vector<int> upload;
+        {
+            std::unique_lock<std::mutex> lk(B.m);
+            B.cv.wait(lk, [&] {
+                bool any = false, all_done = true;
+                for (auto& S : B.slots) {
+                    any = any || S.waiting || S.gated;
+                    all_done = all_done && S.finished;
+                }
+                return any || all_done;
+            });
+            bool any = false;
+            for (int i = 0; i < B.n; ++i) {
+                BatchServer::Slot& S = B.slots[i];
+                if (S.waiting) {
+                    S.waiting = false;
+                    S.gated = true;
+                    B.h_gate[i] = 1;
+                    if (S.dirty) upload.push_back(i);
+                    S.dirty = false;
+                }
+                any = any || S.gated;
+            }
+            if (!any) return;  // every solve has returned
+        }
+        try {
+            for (int i : upload)
+                HIPCHK(hipMemcpyAsync(B.d_inst + i, B.h_inst + i, sizeof(InstDev), hipMemcpyHostToDevice, B.st));
+            HIPCHK(hipMemcpyAsync(B.d_gate, B.h_gate, (size_t)B.n * sizeof(int), hipMemcpyHostToDevice, B.st));
+            HIPCHK(hipGraphLaunch(B.exec, B.st));
+            HIPCHK(hipMemcpyAsync(B.h_status, B.d_status, (size_t)B.n * 2 * sizeof(int), hipMemcpyDeviceToHost, B.st));
+            HIPCHK(hipStreamSynchronize(B.st));
+        } catch (const Err& e) {
+            std::lock_guard<std::mutex> lk(B.m);
+            B.fault = e.what();
+            for (auto& S : B.slots) S.cv.notify_all();
+            return;
+        }
+        ++B.rounds;
+        std::lock_guard<std::mutex> lk(B.m);
+        for (int i = 0; i < B.n; ++i) {
+            BatchServer::Slot& S = B.slots[i];
+            if (!S.gated) continue;
+            if (B.h_status[2 * i] || B.h_status[2 * i + 1] >= S.maxit) {
+                S.gated = false;
+                B.h_gate[i] = 0;
+                S.released = true;
+                S.cv.notify_all();
+            }
+        }
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t blob_rd_net_workspace_bytes(void) { return net_bytes(); }
@@ -1963,6 +2349,76 @@ int blob_rd_autotune(blob_rd_t H, int32_t reps, const char* cache_path, int32_t*
         }
         return BLOB_RD_OK;
     });
+}
+
+size_t blob_rd_batch_workspace_bytes(int32_t n) { return n > 0 ? batch_bytes(n) + 256 : 0; }
+
+int blob_rd_solve_batched(blob_rd_t* hs, int32_t n, const int32_t* kind, double alpha, const double* const* f,
+                          double* const* c, double* const* lambda, void* workspace, size_t workspace_bytes,
+                          void* stream, blob_rd_stats* stats) {
+    if (!hs || !kind || !f || !c || n <= 0) return g_last_error = "bad argument", BLOB_RD_EINVAL;
+    if (!workspace || workspace_bytes < blob_rd_batch_workspace_bytes(n))
+        return g_last_error = "batch workspace missing or smaller than blob_rd_batch_workspace_bytes()",
+               BLOB_RD_ENOMEM;
+    for (int i = 0; i < n; ++i) {
+        if (!hs[i] || !f[i] || !c[i] || (kind[i] == 1 && (!lambda || !lambda[i])) || (kind[i] != 0 && kind[i] != 1))
+            return g_last_error = "bad instance " + std::to_string(i), BLOB_RD_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return g_last_error = "a handle appears twice in the batch", BLOB_RD_EINVAL;
+        if (hs[i]->batch) return g_last_error = "instance " + std::to_string(i) + " is in another batch", BLOB_RD_EINVAL;
+        const std::string why = batch_unfit(hs[i], hs[0]->P.esz);
+        if (!why.empty())
+            return g_last_error = "instance " + std::to_string(i) + " cannot join batched launches: " + why,
+                   BLOB_RD_EINVAL;
+    }
+    BatchServer B;
+    B.n = n;
+    B.esz = (int)hs[0]->P.esz;
+    B.alpha = alpha;
+    B.hs.assign(hs, hs + n);
+    B.st = (hipStream_t)stream;
+    B.slots = std::vector<BatchServer::Slot>(n);
+    uintptr_t base = ((uintptr_t)workspace + 255) & ~(uintptr_t)255;
+    try {
+        batch_setup(B, reinterpret_cast<char*>(base), workspace_bytes - (base - (uintptr_t)workspace), kind);
+    } catch (const Err& e) {
+        batch_teardown(B);
+        g_last_error = e.what();
+        return e.code;
+    }
+    for (int i = 0; i < n; ++i) {
+        hs[i]->batch = &B;
+        hs[i]->batch_slot = i;
+    }
+    std::vector<int> rcs(n, 0);
+    std::vector<std::string> errs(n);
+    std::vector<std::thread> th;
+    th.reserve(n);
+    for (int i = 0; i < n; ++i)
+        th.emplace_back([&, i]() {
+            blob_rd_stats* si = stats ? &stats[i] : nullptr;
+            rcs[i] = kind[i] == 0 ? blob_rd_solve_reactive(hs[i], alpha, f[i], c[i], si)
+                                  : blob_rd_solve_absorbing(hs[i], alpha, f[i], c[i], lambda[i], si);
+            if (rcs[i] < 0) errs[i] = g_last_error;
+            std::lock_guard<std::mutex> lk(B.m);
+            B.slots[i].finished = true;
+            B.cv.notify_all();
+        });
+    batch_serve(B);
+    for (auto& t : th) t.join();
+    for (int i = 0; i < n; ++i) {
+        hs[i]->batch = nullptr;
+        hs[i]->batch_slot = -1;
+    }
+    batch_teardown(B);
+    for (int i = 0; i < n; ++i)
+        if (rcs[i] < 0) {
+            g_last_error = "instance " + std::to_string(i) + ": " + errs[i];
+            return rcs[i];
+        }
+    for (int i = 0; i < n; ++i)
+        if (rcs[i] == BLOB_RD_ENOTCONV) return BLOB_RD_ENOTCONV;
+    return BLOB_RD_OK;
 }
 
 }  // extern "C"

@@ -142,13 +142,11 @@ void launch_bin_sort(hipStream_t st, const int* offsets, int ntiles, int* perm) 
 // Local averaging: one wave64 per blob, lane l <-> support cell
 // (l & 3, (l >> 2) & 3, l >> 4); a wave reduction sums the 64 products.
 // Blobs are visited in tile order so neighbouring waves share cache lines.
-__global__ void __launch_bounds__(kBlock) k_interp(const double* __restrict__ x, int N, BlobGeom g,
-                                                   const int* __restrict__ base, const double* __restrict__ wts,
-                                                   const int* __restrict__ perm, double* __restrict__ jx,
-                                                   const double* __restrict__ kappa, double* __restrict__ out,
-                                                   const Scalars* sc) {
-    if (sc && sc->done) return;
-    const int wv = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+__device__ __forceinline__ void interp_body(const double* __restrict__ x, int N, const BlobGeom& g,
+                                            const int* __restrict__ base, const double* __restrict__ wts,
+                                            const int* __restrict__ perm, double* __restrict__ jx,
+                                            const double* __restrict__ kappa, double* __restrict__ out, Blk blk) {
+    const int wv = blk.b * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (wv >= N) return;
     const int i = perm[wv];
     const int l = threadIdx.x & 63;
@@ -167,6 +165,15 @@ __global__ void __launch_bounds__(kBlock) k_interp(const double* __restrict__ x,
     }
 }
 
+__global__ void __launch_bounds__(kBlock) k_interp(const double* __restrict__ x, int N, BlobGeom g,
+                                                   const int* __restrict__ base, const double* __restrict__ wts,
+                                                   const int* __restrict__ perm, double* __restrict__ jx,
+                                                   const double* __restrict__ kappa, double* __restrict__ out,
+                                                   const Scalars* sc) {
+    if (sc && sc->done) return;
+    interp_body(x, N, g, base, wts, perm, jx, kappa, out, Blk{blockIdx.x, gridDim.x});
+}
+
 void launch_interp(hipStream_t st, const double* x, int N, BlobGeom g, const int* base, const double* wts,
                    const int* perm, double* jx, const double* kappa, double* out, const Scalars* sc) {
     if (N <= 0) return;
@@ -183,16 +190,14 @@ struct Staged {
     double lam;
 };
 
-__global__ void __launch_bounds__(kBlock) k_spread(const double* __restrict__ lam, double lam_shift, BlobGeom g,
-                                                   const int* __restrict__ base, const double* __restrict__ wts,
-                                                   const int* __restrict__ offsets, const int* __restrict__ perm,
-                                                   const double* base_in, double* out, double scale, int add_only,
-                                                   const Scalars* sc) {
-    if (sc && sc->done) return;
+__device__ __forceinline__ void spread_body(const double* __restrict__ lam, double lam_shift, const BlobGeom& g,
+                                            const int* __restrict__ base, const double* __restrict__ wts,
+                                            const int* __restrict__ offsets, const int* __restrict__ perm,
+                                            const double* base_in, double* out, double scale, int add_only, Blk blk) {
     __shared__ Staged stg[kStageBlobs];
     __shared__ int rng_lo[27], rng_len[27], rng_pre[28];
     __shared__ int nrng;
-    const int t = xcd_block(blockIdx.x, gridDim.x);
+    const int t = xcd_block(blk.b, blk.nb);
     const int tix = t % g.ntx, tiy = (t / g.ntx) % g.nty, tiz = t / (g.ntx * g.nty);
     if (threadIdx.x == 0) {
         int lx[3], ly[3], lz[3], nxl = 0, nyl = 0, nzl = 0;
@@ -285,6 +290,39 @@ __global__ void __launch_bounds__(kBlock) k_spread(const double* __restrict__ la
         const double b = base_in ? base_in[idx] : 0.0;
         out[idx] = b + scale * acc[e];
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_spread(const double* __restrict__ lam, double lam_shift, BlobGeom g,
+                                                   const int* __restrict__ base, const double* __restrict__ wts,
+                                                   const int* __restrict__ offsets, const int* __restrict__ perm,
+                                                   const double* base_in, double* out, double scale, int add_only,
+                                                   const Scalars* sc) {
+    if (sc && sc->done) return;
+    spread_body(lam, lam_shift, g, base, wts, offsets, perm, base_in, out, scale, add_only, Blk{blockIdx.x, gridDim.x});
+}
+
+// Batched blob term of B = alpha I - D L + S kappa J inside a CG iteration:
+// jx = J p, mu = kappa jx (interp), then q += h^-3 S mu (spread, touched tiles only).
+__global__ void __launch_bounds__(kBlock) kb_interp(const InstDev* inst, const int* gate, const BatchEntry* ent,
+                                                    int nent) {
+    Blk blk;
+    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
+    if (!I || !I->blobs) return;
+    interp_body(I->p, I->N, I->geom, I->base, I->wts, I->perm, I->jx, I->kappa, I->mu, blk);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_spread(const InstDev* inst, const int* gate, const BatchEntry* ent,
+                                                    int nent) {
+    Blk blk;
+    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
+    if (!I || !I->blobs) return;
+    spread_body(I->mu, 0.0, I->geom, I->base, I->wts, I->offsets, I->perm, I->q, I->q, I->inv_h3, 1, blk);
+}
+
+void launchb_blob(hipStream_t st, int spread, const InstDev* inst, const int* gate, const BatchEntry* ent, int nent,
+                  unsigned nblocks_total) {
+    if (spread) hipLaunchKernelGGL(kb_spread, dim3(nblocks_total), dim3(kBlock), 0, st, inst, gate, ent, nent);
+    else hipLaunchKernelGGL(kb_interp, dim3(nblocks_total), dim3(kBlock), 0, st, inst, gate, ent, nent);
 }
 
 void launch_spread(hipStream_t st, const double* lam, double lam_shift, int N, BlobGeom g, const int* base,

@@ -57,12 +57,10 @@ typedef double double2_t __attribute__((ext_vector_type(2)));
 
 // Two cells per thread (x even, x + 1) with 16-byte loads: q = alpha p - D L p,
 // partials (p.q, sum q). Same arithmetic and summation order as stencil_A.
-__global__ void __launch_bounds__(kBlock) k_applyA2(const double* __restrict__ p, double* __restrict__ q,
-                                                    double alpha, double s, int nx, int ny, int nz, unsigned npair,
-                                                    double* part, const Scalars* sc) {
-    if (sc && sc->done) return;
+__device__ __forceinline__ void applyA2_body(const double* __restrict__ p, double* __restrict__ q, double alpha,
+                                             double s, int nx, int ny, int nz, unsigned npair, double* part, Blk blk) {
     unsigned lo, hi;
-    chunk_of(xcd_block(blockIdx.x, gridDim.x), gridDim.x, npair, &lo, &hi);
+    chunk_of(xcd_block(blk.b, blk.nb), blk.nb, npair, &lo, &hi);
     double v[2] = {0.0, 0.0};
     const int hx = nx >> 1;
     const long long sxy = (long long)nx * ny;
@@ -85,7 +83,23 @@ __global__ void __launch_bounds__(kBlock) k_applyA2(const double* __restrict__ p
         v[0] += c[0] * y[0] + c[1] * y[1];
         v[1] += y[0] + y[1];
     }
-    if (part) block_partials<2>(v, part, gridDim.x, blockIdx.x);
+    if (part) block_partials<2>(v, part, blk.nb, blk.b);
+}
+
+__global__ void __launch_bounds__(kBlock) k_applyA2(const double* __restrict__ p, double* __restrict__ q,
+                                                    double alpha, double s, int nx, int ny, int nz, unsigned npair,
+                                                    double* part, const Scalars* sc) {
+    if (sc && sc->done) return;
+    applyA2_body(p, q, alpha, s, nx, ny, nz, npair, part, Blk{blockIdx.x, gridDim.x});
+}
+
+__global__ void __launch_bounds__(kBlock) kb_applyA2(const InstDev* inst, const int* gate, const BatchEntry* ent,
+                                                     int nent) {
+    Blk blk;
+    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
+    if (!I) return;
+    applyA2_body(I->p, I->q, I->alpha, I->ls[0], I->nx, I->ny, I->nz, (unsigned)(I->nx / 2) * I->ny * I->nz,
+                 I->part, blk);
 }
 
 void launch_applyA2(hipStream_t st, const double* p, double* q, double alpha, double s, int nx, int ny, int nz,
@@ -98,13 +112,10 @@ void launch_applyA2(hipStream_t st, const double* p, double* q, double alpha, do
 
 // p = z + shift + beta p, two cells per thread (z from the split level-0 arrays)
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_dir2(const T* __restrict__ z0, const T* __restrict__ z1,
-                                                 double* __restrict__ p, int nx, int ny, unsigned npair,
-                                                 const Scalars* sc) {
-    if (sc->done) return;
-    const unsigned k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void dir2_body(const T* __restrict__ z0, const T* __restrict__ z1, double* __restrict__ p,
+                                          int nx, int ny, unsigned npair, double beta, double shift, Blk blk) {
+    const unsigned k = xcd_block(blk.b, blk.nb) * blockDim.x + threadIdx.x;
     if (k >= npair) return;
-    const double beta = sc->beta, shift = sc->shift;
     const int hx = nx >> 1;
     const unsigned t = k / hx;
     const int Y = t % ny, Z = t / ny;
@@ -125,6 +136,24 @@ __global__ void __launch_bounds__(kBlock) k_dir2(const T* __restrict__ z0, const
 }
 
 template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dir2(const T* __restrict__ z0, const T* __restrict__ z1,
+                                                 double* __restrict__ p, int nx, int ny, unsigned npair,
+                                                 const Scalars* sc) {
+    if (sc->done) return;
+    dir2_body<T>(z0, z1, p, nx, ny, npair, sc->beta, sc->shift, Blk{blockIdx.x, gridDim.x});
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_dir2(const InstDev* inst, const int* gate, const BatchEntry* ent,
+                                                  int nent) {
+    Blk blk;
+    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
+    if (!I) return;
+    dir2_body<T>(static_cast<const T*>(I->lv[0][0]), static_cast<const T*>(I->lv[0][1]), I->p, I->nx, I->ny,
+                 (unsigned)(I->nx / 2) * I->ny * I->nz, I->sc->beta, I->sc->shift, blk);
+}
+
+template <typename T>
 void launch_dir2(hipStream_t st, const T* z0, const T* z1, double* p, int nx, int ny, int nz, const Scalars* sc) {
     const unsigned npair = (unsigned)(nx / 2) * ny * nz;
     hipLaunchKernelGGL(k_dir2<T>, dim3(nblocks(npair)), dim3(kBlock), 0, st, z0, z1, p, nx, ny, npair, sc);
@@ -137,16 +166,14 @@ template void launch_dir2<double>(hipStream_t, const double*, const double*, dou
 // sum r and sum q) into the split level-0 arrays, and the first red
 // half-sweep from a zero guess, u_red = f_red / diag (as k_enter computes it).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_update2_enter(double* __restrict__ x, double* __restrict__ r,
-                                                          const double* __restrict__ p, const double* __restrict__ q,
-                                                          T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ u0,
-                                                          int nx, int ny, unsigned npair, double inv_diag,
-                                                          double* part, const Scalars* sc) {
-    if (sc->done) return;
+__device__ __forceinline__ void update2_enter_body(double* __restrict__ x, double* __restrict__ r,
+                                                   const double* __restrict__ p, const double* __restrict__ q,
+                                                   T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ u0, int nx,
+                                                   int ny, unsigned npair, double inv_diag, double a, double m,
+                                                   double* part, Blk blk) {
     unsigned lo, hi;
-    chunk_of(xcd_block(blockIdx.x, gridDim.x), gridDim.x, npair, &lo, &hi);
+    chunk_of(xcd_block(blk.b, blk.nb), blk.nb, npair, &lo, &hi);
     double v[2] = {0.0, 0.0};
-    const double a = sc->alpha, m = sc->mean_next;
     const int hx = nx >> 1;
     for (unsigned k = lo + threadIdx.x; k < hi; k += blockDim.x) {
         double2_t xv = reinterpret_cast<double2_t*>(x)[k];
@@ -169,7 +196,29 @@ __global__ void __launch_bounds__(kBlock) k_update2_enter(double* __restrict__ x
         f1[k] = (T)fk;
         u0[k] = (T)((T)fr * (T)inv_diag);
     }
-    block_partials<2>(v, part, gridDim.x, blockIdx.x);
+    block_partials<2>(v, part, blk.nb, blk.b);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_update2_enter(double* __restrict__ x, double* __restrict__ r,
+                                                          const double* __restrict__ p, const double* __restrict__ q,
+                                                          T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ u0,
+                                                          int nx, int ny, unsigned npair, double inv_diag,
+                                                          double* part, const Scalars* sc) {
+    if (sc->done) return;
+    update2_enter_body<T>(x, r, p, q, f0, f1, u0, nx, ny, npair, inv_diag, sc->alpha, sc->mean_next, part,
+                          Blk{blockIdx.x, gridDim.x});
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_update2_enter(const InstDev* inst, const int* gate,
+                                                           const BatchEntry* ent, int nent) {
+    Blk blk;
+    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
+    if (!I) return;
+    update2_enter_body<T>(I->x, I->r, I->p, I->q, static_cast<T*>(I->lv[0][2]), static_cast<T*>(I->lv[0][3]),
+                          static_cast<T*>(I->lv[0][0]), I->nx, I->ny, (unsigned)(I->nx / 2) * I->ny * I->nz,
+                          1.0 / I->ldiag[0], I->sc->alpha, I->sc->mean_next, I->part, blk);
 }
 
 template <typename T>
@@ -359,10 +408,9 @@ __device__ __forceinline__ double fin_sum(const double* __restrict__ p, unsigned
 
 __device__ __forceinline__ bool is_finite_d(double v) { return v == v && v - v == 0.0; }
 
-__global__ void __launch_bounds__(kFinBlock) k_fin(int kind, const double* __restrict__ part, unsigned np,
-                                                   Scalars* sc, const double* __restrict__ na,
-                                                   const double* __restrict__ nb, int nblob, double inv_h3) {
-    if (kind != FIN_INIT && sc->done) return;
+__device__ __forceinline__ void fin_body(int kind, const double* __restrict__ part, unsigned np, Scalars* sc,
+                                         const double* __restrict__ na, const double* __restrict__ nb, int nblob,
+                                         double inv_h3) {
     if (kind == FIN_INIT) {
         const double rr = fin_sum(part, np);
         const double rs = fin_sum(part + np, np);
@@ -459,10 +507,46 @@ __global__ void __launch_bounds__(kFinBlock) k_fin(int kind, const double* __res
     }
 }
 
+__global__ void __launch_bounds__(kFinBlock) k_fin(int kind, const double* __restrict__ part, unsigned np,
+                                                   Scalars* sc, const double* __restrict__ na,
+                                                   const double* __restrict__ nb, int nblob, double inv_h3) {
+    if (kind != FIN_INIT && sc->done) return;
+    fin_body(kind, part, np, sc, na, nb, nblob, inv_h3);
+}
+
 void launch_fin(hipStream_t st, int kind, const double* part, unsigned np, Scalars* sc, const double* na,
                 const double* nb, int nblob, double inv_h3) {
     hipLaunchKernelGGL(k_fin, dim3(1), dim3(kFinBlock), 0, st, kind, part, np, sc, na, nb, nblob, inv_h3);
 }
+
+// One work-group per instance: FIN_ALPHA (with the blob sums of blob
+// instances), FIN_UPDATE or FIN_BETA of every gated, unfinished instance.
+__global__ void __launch_bounds__(kFinBlock) kb_fin(int kind, const InstDev* inst, const int* gate, int ninst) {
+    const int i = blockIdx.x;
+    if (i >= ninst || !gate[i]) return;
+    const InstDev* I = inst + i;
+    if (I->sc->done) return;
+    const unsigned np = kind == FIN_ALPHA ? I->np_apply : kind == FIN_UPDATE ? I->np_update : I->np_dots;
+    const bool blob = kind == FIN_ALPHA && I->blobs;
+    fin_body(kind, I->part, np, I->sc, blob ? I->jx : nullptr, blob ? I->mu : nullptr, blob ? I->N : 0, I->inv_h3);
+}
+
+template <typename T>
+void launchb_cg(hipStream_t st, int what, const InstDev* inst, const int* gate, const BatchEntry* ent, int nent,
+                unsigned nblocks_total, int ninst) {
+    const dim3 g(nblocks_total), b(kBlock);
+    switch (what) {
+        case BCG_DIR: hipLaunchKernelGGL(kb_dir2<T>, g, b, 0, st, inst, gate, ent, nent); break;
+        case BCG_APPLY: hipLaunchKernelGGL(kb_applyA2, g, b, 0, st, inst, gate, ent, nent); break;
+        case BCG_UPDATE: hipLaunchKernelGGL(kb_update2_enter<T>, g, b, 0, st, inst, gate, ent, nent); break;
+        default:
+            hipLaunchKernelGGL(kb_fin, dim3(ninst), dim3(kFinBlock), 0, st,
+                               what == BCG_FIN_ALPHA ? FIN_ALPHA : what == BCG_FIN_UPDATE ? FIN_UPDATE : FIN_BETA,
+                               inst, gate, ninst);
+    }
+}
+template void launchb_cg<float>(hipStream_t, int, const InstDev*, const int*, const BatchEntry*, int, unsigned, int);
+template void launchb_cg<double>(hipStream_t, int, const InstDev*, const int*, const BatchEntry*, int, unsigned, int);
 
 __global__ void __launch_bounds__(kFinBlock) k_reduce_parts(const double* __restrict__ part, unsigned np, int k,
                                                             double* out) {

@@ -110,15 +110,12 @@ __device__ __forceinline__ void row_neighbours(const T* __restrict__ orow, int i
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kMaxTuneBlock) k_gs_vec(T* __restrict__ uc, const T* __restrict__ uo,
-                                                   const T* __restrict__ fc, int hx, int ny, int nz, int color, T s,
-                                                   T inv_diag, const Scalars* sc) {
+__device__ __forceinline__ void gs_vec_body(T* __restrict__ uc, const T* __restrict__ uo, const T* __restrict__ fc, int hx, int ny, int nz, int color, T s, T inv_diag, Blk blk) {
     typedef typename VecOf<T>::type V;
     constexpr int VW = VecOf<T>::W;
-    if (sc && sc->done) return;
     const int hv = hx / VW;
     const unsigned nv = (unsigned)hv * ny * nz;
-    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const unsigned idx = xcd_block(blk.b, blk.nb) * blockDim.x + threadIdx.x;
     if (idx >= nv) return;
     const int iv = idx % hv;
     const unsigned t = idx / hv;
@@ -139,24 +136,27 @@ __global__ void __launch_bounds__(kMaxTuneBlock) k_gs_vec(T* __restrict__ uc, co
     *reinterpret_cast<V*>(uc + row + i0) = out;
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kMaxTuneBlock) k_gs_vec(T* __restrict__ uc, const T* __restrict__ uo,
+                                                   const T* __restrict__ fc, int hx, int ny, int nz, int color, T s,
+                                                   T inv_diag, const Scalars* sc) {
+    if (sc && sc->done) return;
+    gs_vec_body<T>(uc, uo, fc, hx, ny, nz, color, s, inv_diag, Blk{blockIdx.x, gridDim.x});
+}
+
 // The closing red half-sweep on the finest level fused with the CG dots of
 // its result z: block partials (sum z, z.r, z.q) over both colours, r and q
 // natural FP64 (split index i of a row is the natural cell pair 2i, 2i + 1).
 // The black z at the thread's split indices are the x-neighbour vector the
 // sweep loads anyway. Needs hx % VW == 0 and a non-null sc.
 template <typename T>
-__global__ void __launch_bounds__(kMaxTuneBlock) k_gs_vec_dots(T* __restrict__ uc, const T* __restrict__ uo,
-                                                        const T* __restrict__ fc, int hx, int ny, int nz, T s,
-                                                        T inv_diag, const double* __restrict__ r,
-                                                        const double* __restrict__ q, double* part,
-                                                        const Scalars* sc) {
+__device__ __forceinline__ void gs_vec_dots_body(T* __restrict__ uc, const T* __restrict__ uo, const T* __restrict__ fc, int hx, int ny, int nz, T s, T inv_diag, const double* __restrict__ r, const double* __restrict__ q, double* part, Blk blk) {
     typedef typename VecOf<T>::type V;
     typedef typename VecOf<double>::type D2;
     constexpr int VW = VecOf<T>::W;
-    if (sc->done) return;
     const int hv = hx / VW;
     const unsigned nv = (unsigned)hv * ny * nz;
-    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const unsigned idx = xcd_block(blk.b, blk.nb) * blockDim.x + threadIdx.x;
     double acc[3] = {0.0, 0.0, 0.0};
     if (idx < nv) {
         const int iv = idx % hv;
@@ -189,7 +189,17 @@ __global__ void __launch_bounds__(kMaxTuneBlock) k_gs_vec_dots(T* __restrict__ u
             acc[2] += za * qv[0] + zc * qv[1];
         }
     }
-    block_partials<3>(acc, part, gridDim.x, blockIdx.x);
+    block_partials<3>(acc, part, blk.nb, blk.b);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMaxTuneBlock) k_gs_vec_dots(T* __restrict__ uc, const T* __restrict__ uo,
+                                                        const T* __restrict__ fc, int hx, int ny, int nz, T s,
+                                                        T inv_diag, const double* __restrict__ r,
+                                                        const double* __restrict__ q, double* part,
+                                                        const Scalars* sc) {
+    if (sc->done) return;
+    gs_vec_dots_body<T>(uc, uo, fc, hx, ny, nz, s, inv_diag, r, q, part, Blk{blockIdx.x, gridDim.x});
 }
 
 // Returns the number of partial slots, or 0 when the level is not vectorizable
@@ -242,15 +252,12 @@ __global__ void __launch_bounds__(kMaxTuneBlock) k_resid(const T* __restrict__ u
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kMaxTuneBlock) k_resid_vec(const T* __restrict__ u0, const T* __restrict__ u1,
-                                                      const T* __restrict__ f0, T* __restrict__ r0, int hx, int ny,
-                                                      int nz, T s, T diag, const Scalars* sc) {
+__device__ __forceinline__ void resid_vec_body(const T* __restrict__ u0, const T* __restrict__ u1, const T* __restrict__ f0, T* __restrict__ r0, int hx, int ny, int nz, T s, T diag, Blk blk) {
     typedef typename VecOf<T>::type V;
     constexpr int VW = VecOf<T>::W;
-    if (sc && sc->done) return;
     const int hv = hx / VW;
     const unsigned nv = (unsigned)hv * ny * nz;
-    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const unsigned idx = xcd_block(blk.b, blk.nb) * blockDim.x + threadIdx.x;
     if (idx >= nv) return;
     const int iv = idx % hv;
     const unsigned t = idx / hv;
@@ -270,6 +277,14 @@ __global__ void __launch_bounds__(kMaxTuneBlock) k_resid_vec(const T* __restrict
     for (int k = 0; k < VW; ++k)
         out[k] = f[k] - (diag * u[k] - s * (((left[k] + right[k]) + (ym[k] + yp[k])) + (zm[k] + zp[k])));
     *reinterpret_cast<V*>(r0 + row + i0) = out;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMaxTuneBlock) k_resid_vec(const T* __restrict__ u0, const T* __restrict__ u1,
+                                                      const T* __restrict__ f0, T* __restrict__ r0, int hx, int ny,
+                                                      int nz, T s, T diag, const Scalars* sc) {
+    if (sc && sc->done) return;
+    resid_vec_body<T>(u0, u1, f0, r0, hx, ny, nz, s, diag, Blk{blockIdx.x, gridDim.x});
 }
 
 template <typename T>
@@ -347,15 +362,12 @@ __global__ void __launch_bounds__(kMaxTuneBlock) k_restrict(const T* __restrict_
 // Four consecutive coarse cells per thread: one 4-wide load of r0 per fine
 // row plus its two edge values; same arithmetic as k_restrict. Needs cx % 4 == 0.
 template <typename T>
-__global__ void __launch_bounds__(kMaxTuneBlock) k_restrict4(const T* __restrict__ r0, int nx, int ny, int nz,
-                                                      T* __restrict__ cf0, T* __restrict__ cf1, T* __restrict__ cu0,
-                                                      int coarse_natural, T inv_diag_c, const Scalars* sc) {
+__device__ __forceinline__ void restrict4_body(const T* __restrict__ r0, int nx, int ny, int nz, T* __restrict__ cf0, T* __restrict__ cf1, T* __restrict__ cu0, int coarse_natural, T inv_diag_c, Blk blk) {
     typedef T V4 __attribute__((ext_vector_type(4)));
     typedef T V2 __attribute__((ext_vector_type(2)));
-    if (sc && sc->done) return;
     const int cx = nx >> 1, cy = ny >> 1, cz = nz >> 1, cv = cx >> 2;
     const unsigned n4 = (unsigned)cv * cy * cz;
-    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const unsigned idx = xcd_block(blk.b, blk.nb) * blockDim.x + threadIdx.x;
     if (idx >= n4) return;
     const int v = idx % cv;
     const unsigned t = idx / cv;
@@ -398,6 +410,14 @@ __global__ void __launch_bounds__(kMaxTuneBlock) k_restrict4(const T* __restrict
         *reinterpret_cast<V2*>(cf1 + j) = blk;
         *reinterpret_cast<V2*>(cu0 + j) = red * inv_diag_c;
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMaxTuneBlock) k_restrict4(const T* __restrict__ r0, int nx, int ny, int nz,
+                                                      T* __restrict__ cf0, T* __restrict__ cf1, T* __restrict__ cu0,
+                                                      int coarse_natural, T inv_diag_c, const Scalars* sc) {
+    if (sc && sc->done) return;
+    restrict4_body<T>(r0, nx, ny, nz, cf0, cf1, cu0, coarse_natural, inv_diag_c, Blk{blockIdx.x, gridDim.x});
 }
 
 template <typename T>
@@ -465,15 +485,12 @@ __global__ void __launch_bounds__(kMaxTuneBlock) k_prolong(const T* __restrict__
 // value without reading it, so correcting black cells would be a dead store;
 // the result equals a correction of both colours followed by that sweep.
 template <typename T>
-__global__ void __launch_bounds__(kMaxTuneBlock) k_prolong_red(const T* __restrict__ cu0, const T* __restrict__ cu1,
-                                                        T* __restrict__ u0, int nx, int ny, int nz,
-                                                        const Scalars* sc) {
+__device__ __forceinline__ void prolong_red_body(const T* __restrict__ cu0, const T* __restrict__ cu1, T* __restrict__ u0, int nx, int ny, int nz, Blk blk) {
     typedef typename VecOf<T>::type V;
     constexpr int VW = VecOf<T>::W;
-    if (sc && sc->done) return;
     const int hx = nx >> 1, hv = hx / VW;
     const unsigned nv = (unsigned)hv * ny * nz;
-    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const unsigned idx = xcd_block(blk.b, blk.nb) * blockDim.x + threadIdx.x;
     if (idx >= nv) return;
     const int iv = idx % hv;
     const unsigned t = idx / hv;
@@ -499,6 +516,14 @@ __global__ void __launch_bounds__(kMaxTuneBlock) k_prolong_red(const T* __restri
         u[k] += (T)0.75 * ((T)0.75 * a00 + (T)0.25 * a10) + (T)0.25 * ((T)0.75 * a01 + (T)0.25 * a11);
     }
     *reinterpret_cast<V*>(u0 + row + i0) = u;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMaxTuneBlock) k_prolong_red(const T* __restrict__ cu0, const T* __restrict__ cu1,
+                                                        T* __restrict__ u0, int nx, int ny, int nz,
+                                                        const Scalars* sc) {
+    if (sc && sc->done) return;
+    prolong_red_body<T>(cu0, cu1, u0, nx, ny, nz, Blk{blockIdx.x, gridDim.x});
 }
 
 template <typename T>
@@ -611,10 +636,8 @@ __device__ __forceinline__ void tail_gs(T* u, const T* f, int nx, int ny, int nz
 // pre-smoothing, residual, full weighting, coarse dense solve, trilinear
 // correction, B R B R post-smoothing.
 template <typename T>
-__global__ void __launch_bounds__(kFinBlock) k_tail(const T* __restrict__ f0g, const T* __restrict__ f1g,
-                                                    T* __restrict__ u0g, T* __restrict__ u1g, TailDesc d,
-                                                    const double* __restrict__ cinv, const Scalars* sc) {
-    if (sc && sc->done) return;
+__device__ __forceinline__ void tail_body(const T* __restrict__ f0g, const T* __restrict__ f1g, T* __restrict__ u0g,
+                                          T* __restrict__ u1g, const TailDesc& d, const double* __restrict__ cinv) {
     extern __shared__ __align__(16) unsigned char smem[];
 #define TAIL_U(l) reinterpret_cast<T*>(smem + d.off_u[l])
 #define TAIL_F(l) reinterpret_cast<T*>(smem + d.off_f[l])
@@ -742,6 +765,14 @@ __global__ void __launch_bounds__(kFinBlock) k_tail(const T* __restrict__ f0g, c
 }
 
 template <typename T>
+__global__ void __launch_bounds__(kFinBlock) k_tail(const T* __restrict__ f0g, const T* __restrict__ f1g,
+                                                    T* __restrict__ u0g, T* __restrict__ u1g, TailDesc d,
+                                                    const double* __restrict__ cinv, const Scalars* sc) {
+    if (sc && sc->done) return;
+    tail_body<T>(f0g, f1g, u0g, u1g, d, cinv);
+}
+
+template <typename T>
 void launch_tail(hipStream_t st, const T* f0, const T* f1, T* u0, T* u1, const TailDesc& d, const double* cinv,
                  const Scalars* sc) {
     hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(kFinBlock), d.lds_bytes, st, f0, f1, u0, u1, d, cinv, sc);
@@ -750,6 +781,94 @@ void launch_tail(hipStream_t st, const T* f0, const T* f1, T* u0, T* u1, const T
 template <typename T>
 hipError_t tail_set_lds(size_t bytes) {
     return hipFuncSetAttribute((const void*)k_tail<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms: one launch covers one level of every instance in the table
+// (the same bodies as the solo kernels, so results are bitwise the same).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_gs(const InstDev* inst, const int* gate, const BatchEntry* ent, int nent,
+                                                int l, int color) {
+    Blk blk;
+    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
+    if (!I) return;
+    T* const* a = reinterpret_cast<T* const*>(I->lv[l]);
+    const int c = color;
+    gs_vec_body<T>(a[c ? 1 : 0], a[c ? 0 : 1], a[c ? 3 : 2], I->lnx[l] >> 1, I->lny[l], I->lnz[l], c, (T)I->ls[l],
+                   (T)(1.0 / I->ldiag[l]), blk);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_gs_dots(const InstDev* inst, const int* gate, const BatchEntry* ent,
+                                                     int nent) {
+    Blk blk;
+    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
+    if (!I) return;
+    T* const* a = reinterpret_cast<T* const*>(I->lv[0]);
+    gs_vec_dots_body<T>(a[0], a[1], a[2], I->lnx[0] >> 1, I->lny[0], I->lnz[0], (T)I->ls[0], (T)(1.0 / I->ldiag[0]),
+                        I->r, I->q, I->part, blk);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_resid(const InstDev* inst, const int* gate, const BatchEntry* ent,
+                                                   int nent, int l) {
+    Blk blk;
+    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
+    if (!I) return;
+    T* const* a = reinterpret_cast<T* const*>(I->lv[l]);
+    resid_vec_body<T>(a[0], a[1], a[2], a[4], I->lnx[l] >> 1, I->lny[l], I->lnz[l], (T)I->ls[l], (T)I->ldiag[l], blk);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_restrict(const InstDev* inst, const int* gate, const BatchEntry* ent,
+                                                      int nent, int l) {
+    Blk blk;
+    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
+    if (!I) return;
+    T* const* a = reinterpret_cast<T* const*>(I->lv[l]);
+    T* const* c = reinterpret_cast<T* const*>(I->lv[l + 1]);
+    restrict4_body<T>(a[4], I->lnx[l], I->lny[l], I->lnz[l], c[2], c[3], c[0], 0, (T)(1.0 / I->ldiag[l + 1]), blk);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) kb_prolong(const InstDev* inst, const int* gate, const BatchEntry* ent,
+                                                     int nent, int l) {
+    Blk blk;
+    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
+    if (!I) return;
+    T* const* a = reinterpret_cast<T* const*>(I->lv[l]);
+    T* const* c = reinterpret_cast<T* const*>(I->lv[l + 1]);
+    prolong_red_body<T>(c[0], c[1], a[0], I->lnx[l], I->lny[l], I->lnz[l], blk);
+}
+
+// One work-group per instance: the coarse tail from the instance's level t.
+template <typename T>
+__global__ void __launch_bounds__(kFinBlock) kb_tail(const InstDev* inst, const int* gate, int ninst) {
+    const int i = blockIdx.x;
+    if (i >= ninst || !gate[i]) return;
+    const InstDev* I = inst + i;
+    if (I->sc->done) return;
+    T* const* a = reinterpret_cast<T* const*>(I->lv[I->t]);
+    tail_body<T>(a[2], a[3], a[0], a[1], I->tail, I->cinv);
+}
+
+template <typename T>
+void launchb_mg(hipStream_t st, int what, const InstDev* inst, const int* gate, const BatchEntry* ent, int nent,
+                unsigned nblocks_total, int l, int color, unsigned lds) {
+    const dim3 g(nblocks_total), b(kBlock);
+    switch (what) {
+        case BMG_GS: hipLaunchKernelGGL(kb_gs<T>, g, b, 0, st, inst, gate, ent, nent, l, color); break;
+        case BMG_GS_DOTS: hipLaunchKernelGGL(kb_gs_dots<T>, g, b, 0, st, inst, gate, ent, nent); break;
+        case BMG_RESID: hipLaunchKernelGGL(kb_resid<T>, g, b, 0, st, inst, gate, ent, nent, l); break;
+        case BMG_RESTRICT: hipLaunchKernelGGL(kb_restrict<T>, g, b, 0, st, inst, gate, ent, nent, l); break;
+        case BMG_PROLONG: hipLaunchKernelGGL(kb_prolong<T>, g, b, 0, st, inst, gate, ent, nent, l); break;
+        default: hipLaunchKernelGGL(kb_tail<T>, dim3(nent), dim3(kFinBlock), lds, st, inst, gate, nent);
+    }
+}
+
+template <typename T>
+hipError_t tail_set_lds_batched(size_t bytes) {
+    return hipFuncSetAttribute((const void*)kb_tail<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 #define BRD_INST(T)                                                                                                \
@@ -767,7 +886,10 @@ hipError_t tail_set_lds(size_t bytes) {
     template void launch_coarse<T>(hipStream_t, const T*, T*, const double*, int, const Scalars*);             \
     template void launch_tail<T>(hipStream_t, const T*, const T*, T*, T*, const TailDesc&, const double*,         \
                                  const Scalars*);                                                                   \
-    template hipError_t tail_set_lds<T>(size_t);
+    template hipError_t tail_set_lds<T>(size_t);                                                                   \
+    template void launchb_mg<T>(hipStream_t, int, const InstDev*, const int*, const BatchEntry*, int, unsigned, int, \
+                                int, unsigned);                                                                    \
+    template hipError_t tail_set_lds_batched<T>(size_t);
 
 BRD_INST(float)
 BRD_INST(double)

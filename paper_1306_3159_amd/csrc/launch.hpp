@@ -82,14 +82,24 @@ void launch_tail(hipStream_t st, const T* f0, const T* f1, T* u0, T* u1, const T
 template <typename T>
 hipError_t tail_set_lds(size_t bytes);
 
+// ---- batched launches (one launch per step for every instance of a batch) ----
+enum { BCG_DIR = 0, BCG_APPLY, BCG_UPDATE, BCG_FIN_ALPHA, BCG_FIN_UPDATE, BCG_FIN_BETA };
+enum { BMG_GS = 0, BMG_GS_DOTS, BMG_RESID, BMG_RESTRICT, BMG_PROLONG, BMG_TAIL };
+// CG steps; the fin kinds take one work-group per instance (ninst)
+template <typename T>
+void launchb_cg(hipStream_t st, int what, const InstDev* inst, const int* gate, const BatchEntry* ent, int nent,
+                unsigned nblocks_total, int ninst);
+// V-cycle steps on level l; BMG_TAIL takes one work-group per instance (nent = ninst) with lds bytes
+template <typename T>
+void launchb_mg(hipStream_t st, int what, const InstDev* inst, const int* gate, const BatchEntry* ent, int nent,
+                unsigned nblocks_total, int l, int color, unsigned lds);
+template <typename T>
+hipError_t tail_set_lds_batched(size_t bytes);
+// blob term: interp (spread = 0) or spread (1)
+void launchb_blob(hipStream_t st, int spread, const InstDev* inst, const int* gate, const BatchEntry* ent, int nent,
+                  unsigned nblocks_total);
+
 // ---- blobs -----------------------------------------------------------------
-struct BlobGeom {
-    int nx, ny, nz;
-    int tx, ty, tz;      // tile edge per axis (divides the grid edge)
-    int ntx, nty, ntz;   // tiles per axis
-    double h;
-    int w;
-};
 // wrap positions, kernel weights, tile ids, bin counts (int atomics on counts only)
 void launch_blob_setup(hipStream_t st, const double* q, int N, BlobGeom g, int* base /*[3N]*/,
                        double* wts /*[12N]*/, int* tile_of, int* counts);

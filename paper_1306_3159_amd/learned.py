@@ -87,11 +87,15 @@ def loss_and_grad(net: Net, samples: Sequence[Sample], device) -> float:
 
 
 def train(net: Net, samples: List[Sample], epochs: int, lr: float, batch: int, device, seed: int = 0,
-          log: Optional[Callable[[str], None]] = None) -> List[float]:
-    """Adam over mini-batches of configurations; returns the mean loss per epoch."""
+          log: Optional[Callable[[str], None]] = None, lr_final: Optional[float] = None) -> List[float]:
+    """Adam over mini-batches of configurations; returns the mean loss per epoch. With lr_final
+    the step size follows a cosine from lr down to lr_final over the epochs."""
     rng = np.random.default_rng(seed)
     hist = []
+    base = lr
     for ep in range(epochs):
+        if lr_final is not None and epochs > 1:
+            lr = lr_final + 0.5 * (base - lr_final) * (1.0 + np.cos(np.pi * ep / (epochs - 1)))
         order = rng.permutation(len(samples))
         losses = []
         t0 = time.time()

@@ -124,6 +124,12 @@ def load_library(path: str = LIB_PATH):
     L.blob_rd_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), d,
                                       ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int32, S]
     L.blob_rd_solve_batch.restype = i32
+    L.blob_rd_batch_workspace_bytes.argtypes = [ctypes.c_int32]
+    L.blob_rd_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.blob_rd_solve_batched.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), d,
+                                        ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
+                                        ctypes.c_size_t, vp, S]
+    L.blob_rd_solve_batched.restype = i32
     for name in ("blob_rd_net_create", "blob_rd_net_destroy", "blob_rd_net_set_params", "blob_rd_net_get_params",
                  "blob_rd_net_zero_grad", "blob_rd_net_get_grad", "blob_rd_net_adam_step", "blob_rd_precond_build",
                  "blob_rd_precond_apply", "blob_rd_precond_csr", "blob_rd_precond_loss_grad", "blob_rd_schur_apply"):
@@ -415,6 +421,30 @@ def solve_batch(solvers: Sequence["BlobRD"], kinds: Sequence[int], fs, cs, lams,
     Lm = (ctypes.c_void_p * n)(*[(l.data_ptr() if l is not None else None) for l in lams])
     st = (Stats * n)()
     rc = L.blob_rd_solve_batch(H, n, K, float(alpha), F, C, Lm, int(threads), st)
+    if rc < 0:
+        raise BlobRDError(rc, L.blob_rd_last_error(None).decode())
+    return rc, [st[i].as_dict(rc) for i in range(n)]
+
+
+def solve_batched(solvers: Sequence["BlobRD"], kinds: Sequence[int], fs, cs, lams, alpha: float = 0.0,
+                  stream: Optional[torch.cuda.Stream] = None):
+    """Lock-step batched solve: the CG iterations of all instances run in shared batched launches
+    (one captured graph replayed in rounds). kinds: 0 reactive, 1 absorbing. Returns (rc, stats)."""
+    L = load_library()
+    n = len(solvers)
+    dev = solvers[0].device
+    H = (ctypes.c_void_p * n)(*[s._h for s in solvers])
+    K = (ctypes.c_int32 * n)(*[int(k) for k in kinds])
+    F = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+    C = (ctypes.c_void_p * n)(*[c.data_ptr() for c in cs])
+    Lm = (ctypes.c_void_p * n)(*[(l.data_ptr() if l is not None else None) for l in lams])
+    st = (Stats * n)()
+    nbytes = int(L.blob_rd_batch_workspace_bytes(n))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    strm = stream if stream is not None else torch.cuda.current_stream(dev)
+    torch.cuda.synchronize(dev)
+    rc = L.blob_rd_solve_batched(H, n, K, float(alpha), F, C, Lm, ctypes.c_void_p(ws.data_ptr()), nbytes,
+                                 ctypes.c_void_p(strm.cuda_stream), st)
     if rc < 0:
         raise BlobRDError(rc, L.blob_rd_last_error(None).decode())
     return rc, [st[i].as_dict(rc) for i in range(n)]

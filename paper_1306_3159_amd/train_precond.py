@@ -33,6 +33,13 @@ def log(msg):
     print(msg, flush=True)
 
 
+def _positions(arg):
+    """Blob positions of training configuration i (seeded; runs in a worker process)."""
+    import workloads as W
+    i, n, blobs = arg
+    return W.training_config(i, n, blobs).q
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--configs", type=int, default=500)
@@ -46,6 +53,9 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--eval", default="256:10000:2", help="comma list of n:blobs:count held-out sets")
+    ap.add_argument("--lr-final", type=float, default=None,
+                    help="cosine-decay the learning rate to this value over the epochs (default: constant)")
+    ap.add_argument("--workers", type=int, default=1, help="host processes generating the configurations")
     args = ap.parse_args(argv)
 
     import torch
@@ -56,21 +66,30 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     t0 = time.time()
     samples = []
-    for i in range(args.configs):
-        inst = W.training_config(i, args.n, args.blobs)
-        samples.append(LD.harvest(args.n, inst.q, args.samples, 1306_700_000 + i, dev,
-                                  smooth_fraction=args.smooth))
+    pool = None
+    if args.workers > 1:
+        import multiprocessing as mp
+        pool = mp.get_context("fork").Pool(args.workers)
+        positions = pool.imap(_positions, [(i, args.n, args.blobs) for i in range(args.configs)], chunksize=4)
+    else:
+        positions = (_positions((i, args.n, args.blobs)) for i in range(args.configs))
+    for i, q in enumerate(positions):
+        samples.append(LD.harvest(args.n, q, args.samples, 1306_700_000 + i, dev, smooth_fraction=args.smooth))
         if (i + 1) % 50 == 0:
             log(f"harvested {i + 1}/{args.configs} configurations ({time.time() - t0:.1f}s)")
+    if pool is not None:
+        pool.close()
     net = Net(dev)
     net.set_params(torch.tensor(LD.initial_params(args.seed), device=dev))
-    hist = LD.train(net, samples, args.epochs, args.lr, args.batch, dev, seed=args.seed, log=log)
+    hist = LD.train(net, samples, args.epochs, args.lr, args.batch, dev, seed=args.seed, log=log,
+                    lr_final=args.lr_final)
     params = net.get_params().cpu().numpy()
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, params)
     log(f"saved {args.out}")
     report = {"configs": args.configs, "n": args.n, "blobs": args.blobs, "samples": args.samples,
-              "epochs": args.epochs, "lr": args.lr, "batch": args.batch, "loss": hist,
+              "epochs": args.epochs, "lr": args.lr, "lr_final": args.lr_final, "batch": args.batch,
+              "smooth": args.smooth, "seed": args.seed, "loss": hist,
               "train_seconds": time.time() - t0, "eval": []}
     for spec in args.eval.split(","):
         if not spec:

@@ -1,0 +1,107 @@
+"""Lock-step batched launches: the CG iterations of uneven instances run in shared batched
+kernels (one captured graph replayed in rounds) and give bitwise the solo results."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1306_3159_amd import native
+    native.load_library()
+    return torch.device("cuda:0")
+
+
+def _instances(specs, seed0):
+    out = []
+    for k, (n, N, kind) in enumerate(specs):
+        rng = np.random.default_rng(seed0 + k)
+        q = W.rsa_positions(rng, n, N, 3.0)
+        kap = W.log_uniform(rng, 1e-2, 1e2, N)
+        f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
+        out.append((n, q, kap, kind, f))
+    return out
+
+
+def _handles(dev, inst, prec):
+    from paper_1306_3159_amd import BlobRD
+    return [BlobRD(n, torch.tensor(q, device=dev), torch.tensor(kap, device=dev), precision=prec,
+                   stream=torch.cuda.Stream(dev)) for n, q, kap, kind, f in inst]
+
+
+def _solo(dev, inst, prec):
+    res = []
+    for S, (n, q, kap, kind, f) in zip(_handles(dev, inst, prec), inst):
+        ft = torch.tensor(f, device=dev)
+        torch.cuda.synchronize()
+        if kind == 0:
+            c, st = S.solve_reactive(ft)
+            res.append((c.cpu().numpy(), None, st))
+        else:
+            c, lam, st = S.solve_absorbing(ft)
+            res.append((c.cpu().numpy(), lam.cpu().numpy(), st))
+        assert st["rc"] == 0
+        S.close()
+    return res
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_batched_matches_solo(dev, prec):
+    _say("batched vs solo, prec", prec)
+    from paper_1306_3159_amd import solve_batched
+    specs = [(32, 60, 0), (48, 200, 1), (64, 300, 0), (32, 20, 1), (96, 400, 1), (64, 150, 1), (48, 90, 0),
+             (128, 500, 0)]
+    inst = _instances(specs, 4100)
+    solo = _solo(dev, inst, prec)
+    Hs = _handles(dev, inst, prec)
+    for rep in range(2):  # a second batched call on the same handles (fresh tables and graph)
+        fs = [torch.tensor(f, device=dev) for *_, f in inst]
+        cs = [torch.zeros_like(f) for f in fs]
+        ls = [torch.zeros(q.shape[0], dtype=torch.float64, device=dev) if kind else None
+              for _, q, _, kind, _ in inst]
+        rc, stats = solve_batched(Hs, [kind for _, _, _, kind, _ in inst], fs, cs, ls)
+        assert rc == 0, stats
+        for (c0, l0, st0), c, l, st in zip(solo, cs, ls, stats):
+            assert np.array_equal(c.cpu().numpy(), c0)
+            if l0 is not None:
+                assert np.array_equal(l.cpu().numpy(), l0)
+            assert st["outer_iters"] == st0["outer_iters"]
+    # the handles still solve alone afterwards
+    n, q, kap, kind, f = inst[0]
+    c, st = Hs[0].solve_reactive(torch.tensor(f, device=dev))
+    assert np.array_equal(c.cpu().numpy(), solo[0][0])
+    for S in Hs:
+        S.close()
+
+
+def test_batched_rejects_unfit(dev):
+    _say("batched validation")
+    from paper_1306_3159_amd import BlobRD, solve_batched
+    from paper_1306_3159_amd.native import BlobRDError
+    rng = np.random.default_rng(4200)
+    shapes = [(32, 32, 20), (32, 32, 32)]  # [z, y, x]: x = 20 leaves 10-cell split rows (not 4-wide)
+    Hs, fs = [], []
+    for sh in shapes:
+        q = np.column_stack([rng.uniform(0, sh[2], 10), rng.uniform(0, sh[1], 10), rng.uniform(0, sh[0], 10)])
+        Hs.append(BlobRD(sh, torch.tensor(q, device=dev), torch.ones(10, dtype=torch.float64, device=dev),
+                         precision=1))
+        fs.append(torch.ones(sh, dtype=torch.float64, device=dev))
+    cs = [torch.zeros_like(f) for f in fs]
+    with pytest.raises(BlobRDError, match="instance 0"):
+        solve_batched(Hs, [0, 0], fs, cs, [None, None])
+    for S in Hs:
+        S.close()
