@@ -87,6 +87,11 @@ def summary(st):
             "alg_bytes": st["alg_bytes"]}
 
 
+# Grids up to 64^3 are launch-latency-bound and share the lock-step batched
+# launches; larger ones are bandwidth-bound and run on their own streams.
+LOCKSTEP_MAX_CELLS = 64 ** 3
+
+
 def bench_batch(args, dev, rtol):
     """64 uneven suspensions (grids 32..128, up to 2000 blobs, reactive/absorbing 50/50); a step
     is the whole batch. value: the lock-step executor (every instance's CG iterations in shared
@@ -108,7 +113,8 @@ def bench_batch(args, dev, rtol):
         for c in cs:
             c.zero_()
         torch.cuda.synchronize()
-        return solve_batched(Hs, kinds, fs, cs, ls, stream=bstream)
+        return solve_batched(Hs, kinds, fs, cs, ls, stream=bstream, lockstep_max_cells=LOCKSTEP_MAX_CELLS,
+                             threads=args.threads)
 
     def step_streams():
         for c in cs:
@@ -134,7 +140,10 @@ def bench_batch(args, dev, rtol):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64 Krylov/residuals + f32 V-cycles", "data": "synthetic",
            "config": {"workload": "batch64", "instances": len(insts), "total_cells": cells,
-                      "total_blobs": sum(i.N for i in insts), "rtol": rtol, "executor": "lock-step batched launches"},
+                      "total_blobs": sum(i.N for i in insts), "rtol": rtol,
+                      "executor": "lock-step batched launches for grids <= 64^3, own streams for larger grids",
+                      "lockstep_instances": sum(1 for i in insts if i.n ** 3 <= LOCKSTEP_MAX_CELLS),
+                      "stream_threads": args.threads},
            "rc": rc, "max_rel_resid": max(s["rel_resid"] for s in stats),
            "streams_executor": {"instances_per_s": len(insts) * ns / sdt, "threads": args.threads, "rc": src},
            "serial_instances_per_s": len(insts) / serial}

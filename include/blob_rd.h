@@ -215,25 +215,26 @@ int blob_rd_schur_apply(blob_rd_t h, double alpha, const double* x, double* y, d
 int blob_rd_solve_batch(blob_rd_t* h, int32_t n, const int32_t* kind, double alpha, const double* const* f,
                         double* const* c, double* const* lambda, int32_t threads, blob_rd_stats* stats);
 
-/* Lock-step batched form of the same: the CG iterations of all instances run
- * as one sequence of batched launches (one launch per step, e.g. one
- * Gauss-Seidel half-sweep of one level, covering every instance through a
- * flat table of work-group slices), captured once as a HIP graph and
- * replayed in rounds of two iterations on `stream`; an instance takes part
- * in a round while it is in a CG run and drops out when its done flag is set
- * (a run may use one iteration past its limit). Each instance's own solver
- * logic (Schur GMRES, set-up, final solves) runs on a host thread per
- * instance and its handle's stream. The results are bitwise those of solving
- * each instance alone. Requirements: one V-cycle precision for all handles,
- * and each grid's finest levels launched per level and vectorizable (grid
- * edges divisible by 16 for FP32, 8 for FP64) above a coarse tail; otherwise
- * BLOB_RD_EINVAL names the instance (blob_rd_solve_batch serves any batch).
- * workspace: caller-owned device memory of blob_rd_batch_workspace_bytes(n)
- * bytes (descriptor and block tables). */
+/* Lock-step batched form of the same. The CG iterations of the member
+ * instances run as one sequence of batched launches (one launch per step,
+ * e.g. one Gauss-Seidel half-sweep of one level, over a work list of every
+ * member's work-group slices; a fixed grid strides over the list), captured
+ * once as a HIP graph and replayed in rounds of two iterations on `stream`.
+ * A member takes part in a round while it is in a CG run and drops out when
+ * its done flag is set (a run may use one iteration past its limit). Each
+ * instance's own solver logic (Schur GMRES, set-up, final solves) runs on a
+ * host thread per instance and its handle's stream. Members: grids of at
+ * most lockstep_max_cells cells (<= 0: no limit) whose finest levels are
+ * launched per level and vectorizable (x edge divisible by 16 for FP32, 8 for
+ * FP64) above a coarse tail, in the first member's precision; the other
+ * instances run their whole solves on their own streams meanwhile, at most
+ * `threads` at a time (0: all). The results are bitwise those of solving
+ * each instance alone. workspace: caller-owned device memory of
+ * blob_rd_batch_workspace_bytes(n) bytes (descriptors and work lists). */
 size_t blob_rd_batch_workspace_bytes(int32_t n);
 int blob_rd_solve_batched(blob_rd_t* h, int32_t n, const int32_t* kind, double alpha, const double* const* f,
-                          double* const* c, double* const* lambda, void* workspace, size_t workspace_bytes,
-                          void* stream, blob_rd_stats* stats);
+                          double* const* c, double* const* lambda, int64_t lockstep_max_cells, int32_t threads,
+                          void* workspace, size_t workspace_bytes, void* stream, blob_rd_stats* stats);
 
 /* ---- Measurement ---- */
 

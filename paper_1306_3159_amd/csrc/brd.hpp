@@ -202,13 +202,25 @@ __device__ __forceinline__ int batch_entry(const BatchEntry* e, int n, unsigned 
     return lo;
 }
 
-// The instance and local block of this batched block, or null when the block
-// is padding, the instance is not gated in, or its solve is done (uniform per
-// block, so callers may return before barriers).
+// A batched launch's work list, rebuilt for the instances taking part in each
+// round: `total` virtual blocks over `n` entries (the BatchEntry array follows
+// the header). Launches have a fixed grid that strides over the virtual blocks.
+struct BatchTab {
+    unsigned total;
+    int n;
+    int pad0, pad1;
+};
+__device__ __forceinline__ const BatchEntry* tab_entries(const BatchTab* t) {
+    return reinterpret_cast<const BatchEntry*>(t + 1);
+}
+
+// The instance and local block of virtual block g, or null when g is padding,
+// the instance is not gated in, or its solve is done (uniform per block, so
+// callers may skip barriers together).
 __device__ __forceinline__ const InstDev* batch_slot(const InstDev* inst, const int* gate, const BatchEntry* ent,
-                                                     int nent, Blk& blk) {
-    const BatchEntry e = ent[batch_entry(ent, nent, blockIdx.x)];
-    const unsigned b = blockIdx.x - e.block0;
+                                                     int nent, unsigned g, Blk& blk) {
+    const BatchEntry e = ent[batch_entry(ent, nent, g)];
+    const unsigned b = g - e.block0;
     if (b >= e.nb || !gate[e.inst]) return nullptr;
     const InstDev* I = inst + e.inst;
     if (I->sc->done) return nullptr;

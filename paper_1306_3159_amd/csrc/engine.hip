@@ -1513,9 +1513,12 @@ constexpr int kBatchRoundIters = 2;  // CG iterations per graph replay
 
 }  // namespace
 
+// One batched launch's work list: per-instance block counts, and where its
+// per-round compacted table lives in the workspace.
 struct BatchTable {
-    int off = 0, n = 0;
-    unsigned blocks = 0;
+    std::vector<unsigned> nb;  // work-group slices per instance (0: not in this launch)
+    size_t off = 0;            // byte offset of the BatchTab header in the table region
+    unsigned grid = 0;         // fixed grid of the launch
 };
 
 struct BatchServer {
@@ -1526,16 +1529,21 @@ struct BatchServer {
     InstDev* d_inst = nullptr;
     int* d_gate = nullptr;
     int* d_status = nullptr;
-    BatchEntry* d_ent = nullptr;
+    char* d_tabs = nullptr;      // work lists (BatchTab + entries) of every launch
     InstDev* h_inst = nullptr;   // pinned mirrors
     int* h_gate = nullptr;
     int* h_status = nullptr;
-    BatchTable t_dir, t_apply, t_update, t_dots, t_interp, t_spread;
-    std::vector<BatchTable> t_lv, t_rs;  // per level: sweep/residual/correction, restriction
+    char* h_tabs = nullptr;
+    size_t tabs_bytes = 0;
+    // work lists: CG direction, stencil, update, closing sweep + dots, interp, spread,
+    // then per level sweep/residual/correction and restriction
+    std::vector<BatchTable> tabs;
     int Lmax = 0;
     unsigned tail_lds = 0;
     hipGraphExec_t exec = nullptr;
     int rounds = 0;
+    long long gated_rounds = 0;  // sum over rounds of gated instances
+    double busy_s = 0.0, idle_s = 0.0;
     // coordination
     struct Slot {
         bool waiting = false;   // asked for CG iterations
@@ -1556,9 +1564,14 @@ namespace {
 
 size_t batch_align(size_t b) { return (b + 255) & ~(size_t)255; }
 
+enum { TAB_DIR = 0, TAB_APPLY, TAB_UPDATE, TAB_DOTS, TAB_INTERP, TAB_SPREAD, TAB_LEVELS };
+constexpr unsigned kPersistBlocks = 2048;  // grid of a batched launch (8 work-groups per CU)
+
+size_t batch_tab_bytes(int n) { return batch_align(sizeof(BatchTab) + (size_t)n * sizeof(BatchEntry)); }
+
 size_t batch_bytes(int n) {
     return batch_align((size_t)n * sizeof(InstDev)) + 2 * batch_align((size_t)n * 2 * sizeof(int)) +
-           batch_align((size_t)n * (6 + 2 * kMaxLevels) * sizeof(BatchEntry));
+           (TAB_LEVELS + 2 * kMaxLevels) * batch_tab_bytes(n);
 }
 
 // Why instance H cannot run its CG iterations in batched launches (empty: it can).
@@ -1587,41 +1600,58 @@ template <typename T>
 void batch_round(BatchServer& B, hipStream_t s) {
     const InstDev* I = B.d_inst;
     const int* G = B.d_gate;
-    auto E = [&](const BatchTable& t) { return B.d_ent + t.off; };
+    auto T_ = [&](int k) { return reinterpret_cast<const BatchTab*>(B.d_tabs + B.tabs[k].off); };
+    auto grid = [&](int k) { return B.tabs[k].grid; };
+    const int LV = TAB_LEVELS, RS = TAB_LEVELS + B.Lmax;
     for (int it = 0; it < kBatchRoundIters; ++it) {
-        launchb_cg<T>(s, BCG_DIR, I, G, E(B.t_dir), B.t_dir.n, B.t_dir.blocks, B.n);
-        launchb_cg<T>(s, BCG_APPLY, I, G, E(B.t_apply), B.t_apply.n, B.t_apply.blocks, B.n);
-        if (B.t_interp.n) {
-            launchb_blob(s, 0, I, G, E(B.t_interp), B.t_interp.n, B.t_interp.blocks);
-            launchb_blob(s, 1, I, G, E(B.t_spread), B.t_spread.n, B.t_spread.blocks);
+        launchb_cg<T>(s, BCG_DIR, I, G, T_(TAB_DIR), grid(TAB_DIR), B.n);
+        launchb_cg<T>(s, BCG_APPLY, I, G, T_(TAB_APPLY), grid(TAB_APPLY), B.n);
+        if (grid(TAB_INTERP)) {
+            launchb_blob(s, 0, I, G, T_(TAB_INTERP), grid(TAB_INTERP));
+            launchb_blob(s, 1, I, G, T_(TAB_SPREAD), grid(TAB_SPREAD));
         }
-        launchb_cg<T>(s, BCG_FIN_ALPHA, I, G, nullptr, 0, 0, B.n);
-        launchb_cg<T>(s, BCG_UPDATE, I, G, E(B.t_update), B.t_update.n, B.t_update.blocks, B.n);
-        launchb_cg<T>(s, BCG_FIN_UPDATE, I, G, nullptr, 0, 0, B.n);
+        launchb_cg<T>(s, BCG_FIN_ALPHA, I, G, nullptr, 0, B.n);
+        launchb_cg<T>(s, BCG_UPDATE, I, G, T_(TAB_UPDATE), grid(TAB_UPDATE), B.n);
+        launchb_cg<T>(s, BCG_FIN_UPDATE, I, G, nullptr, 0, B.n);
         for (int l = 0; l < B.Lmax; ++l) {
-            const BatchTable& a = B.t_lv[l];
-            const BatchTable& r = B.t_rs[l];
-            launchb_mg<T>(s, BMG_GS, I, G, E(a), a.n, a.blocks, l, 1, 0);
-            launchb_mg<T>(s, BMG_GS, I, G, E(a), a.n, a.blocks, l, 0, 0);
-            launchb_mg<T>(s, BMG_GS, I, G, E(a), a.n, a.blocks, l, 1, 0);
-            launchb_mg<T>(s, BMG_RESID, I, G, E(a), a.n, a.blocks, l, 0, 0);
-            launchb_mg<T>(s, BMG_RESTRICT, I, G, E(r), r.n, r.blocks, l, 0, 0);
+            launchb_mg<T>(s, BMG_GS, I, G, T_(LV + l), grid(LV + l), l, 1, 0);
+            launchb_mg<T>(s, BMG_GS, I, G, T_(LV + l), grid(LV + l), l, 0, 0);
+            launchb_mg<T>(s, BMG_GS, I, G, T_(LV + l), grid(LV + l), l, 1, 0);
+            launchb_mg<T>(s, BMG_RESID, I, G, T_(LV + l), grid(LV + l), l, 0, 0);
+            launchb_mg<T>(s, BMG_RESTRICT, I, G, T_(RS + l), grid(RS + l), l, 0, 0);
         }
-        launchb_mg<T>(s, BMG_TAIL, I, G, nullptr, B.n, B.n, 0, 0, B.tail_lds);
+        launchb_mg<T>(s, BMG_TAIL, I, G, nullptr, B.n, 0, 0, B.tail_lds);
         for (int l = B.Lmax - 1; l >= 0; --l) {
-            const BatchTable& a = B.t_lv[l];
-            launchb_mg<T>(s, BMG_PROLONG, I, G, E(a), a.n, a.blocks, l, 0, 0);
-            launchb_mg<T>(s, BMG_GS, I, G, E(a), a.n, a.blocks, l, 1, 0);
-            launchb_mg<T>(s, BMG_GS, I, G, E(a), a.n, a.blocks, l, 0, 0);
-            launchb_mg<T>(s, BMG_GS, I, G, E(a), a.n, a.blocks, l, 1, 0);
+            launchb_mg<T>(s, BMG_PROLONG, I, G, T_(LV + l), grid(LV + l), l, 0, 0);
+            launchb_mg<T>(s, BMG_GS, I, G, T_(LV + l), grid(LV + l), l, 1, 0);
+            launchb_mg<T>(s, BMG_GS, I, G, T_(LV + l), grid(LV + l), l, 0, 0);
+            launchb_mg<T>(s, BMG_GS, I, G, T_(LV + l), grid(LV + l), l, 1, 0);
             if (l == 0)
-                launchb_mg<T>(s, BMG_GS_DOTS, I, G, E(B.t_dots), B.t_dots.n, B.t_dots.blocks, 0, 0, 0);
+                launchb_mg<T>(s, BMG_GS_DOTS, I, G, T_(TAB_DOTS), grid(TAB_DOTS), 0, 0, 0);
             else
-                launchb_mg<T>(s, BMG_GS, I, G, E(a), a.n, a.blocks, l, 0, 0);
+                launchb_mg<T>(s, BMG_GS, I, G, T_(LV + l), grid(LV + l), l, 0, 0);
         }
-        launchb_cg<T>(s, BCG_FIN_BETA, I, G, nullptr, 0, 0, B.n);
+        launchb_cg<T>(s, BCG_FIN_BETA, I, G, nullptr, 0, B.n);
     }
     hipLaunchKernelGGL(k_batch_status, dim3((B.n + 63) / 64), dim3(64), 0, s, I, B.n, B.d_status);
+}
+
+// Work lists of the round: the gated instances' slices, each starting at a
+// multiple of 8 virtual blocks (a slot keeps the XCD of its solo launch).
+void batch_fill_tabs(BatchServer& B) {
+    for (const BatchTable& t : B.tabs) {
+        BatchTab* h = reinterpret_cast<BatchTab*>(B.h_tabs + t.off);
+        BatchEntry* e = reinterpret_cast<BatchEntry*>(h + 1);
+        unsigned g = 0;
+        int k = 0;
+        for (int i = 0; i < B.n; ++i) {
+            if (!B.h_gate[i] || !t.nb[i]) continue;
+            e[k++] = BatchEntry{g, t.nb[i], i, 0};
+            g += (t.nb[i] + 7u) & ~7u;
+        }
+        h->total = g;
+        h->n = k;
+    }
 }
 
 // Descriptor of instance H for CG iterations with operator alpha (x set per CG run).
@@ -1678,7 +1708,7 @@ void batch_setup(BatchServer& B, char* ws, size_t ws_bytes, const int32_t* kind)
     o += batch_align((size_t)n * 2 * sizeof(int));
     B.d_status = reinterpret_cast<int*>(o);
     o += batch_align((size_t)n * 2 * sizeof(int));
-    B.d_ent = reinterpret_cast<BatchEntry*>(o);
+    B.d_tabs = o;
     (void)ws_bytes;
     HIPCHK(hipHostMalloc((void**)&B.h_inst, (size_t)n * sizeof(InstDev), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&B.h_gate, (size_t)n * 2 * sizeof(int), hipHostMallocDefault));
@@ -1693,50 +1723,42 @@ void batch_setup(BatchServer& B, char* ws, size_t ws_bytes, const int32_t* kind)
         B.tail_lds = std::max(B.tail_lds, B.h_inst[i].tail.lds_bytes);
         B.h_gate[i] = 0;
     }
-    std::vector<BatchEntry> ents;
-    auto table = [&](auto nb_of) {
-        BatchTable t;
-        t.off = (int)ents.size();
-        unsigned g = 0;
-        for (int i = 0; i < n; ++i) {
-            const unsigned nb = nb_of(i);
-            if (!nb) continue;
-            ents.push_back(BatchEntry{g, nb, i, 0});
-            g += (nb + 7u) & ~7u;
-            ++t.n;
-        }
-        t.blocks = g;
-        return t;
-    };
     const int VW = 16 / B.esz;
     auto npair = [&](int i) { const InstDev& D = B.h_inst[i]; return (size_t)(D.nx / 2) * D.ny * D.nz; };
     auto nv = [&](int i, int l) {
         const InstDev& D = B.h_inst[i];
         return (size_t)(D.lnx[l] / 2 / VW) * D.lny[l] * D.lnz[l];
     };
-    B.t_dir = table([&](int i) { return nblocks(npair(i)); });
-    B.t_apply = table([&](int i) { return red_blocks(npair(i)); });
-    B.t_update = table([&](int i) { return red_blocks(npair(i)); });
-    B.t_dots = table([&](int i) { return nblocks(nv(i, 0)); });
-    B.t_interp = table([&](int i) {
+    B.tabs.assign(TAB_LEVELS + 2 * B.Lmax, BatchTable{});
+    for (auto& t : B.tabs) t.nb.assign(n, 0u);
+    for (int i = 0; i < n; ++i) {
         const InstDev& D = B.h_inst[i];
-        return D.blobs ? (unsigned)((D.N + kBlock / 64 - 1) / (kBlock / 64)) : 0u;
-    });
-    B.t_spread = table([&](int i) {
-        const InstDev& D = B.h_inst[i];
-        return D.blobs ? (unsigned)(D.geom.ntx * D.geom.nty * D.geom.ntz) : 0u;
-    });
-    B.t_lv.assign(B.Lmax, BatchTable{});
-    B.t_rs.assign(B.Lmax, BatchTable{});
-    for (int l = 0; l < B.Lmax; ++l) {
-        B.t_lv[l] = table([&](int i) { return l < B.h_inst[i].t ? nblocks(nv(i, l)) : 0u; });
-        B.t_rs[l] = table([&](int i) {
-            const InstDev& D = B.h_inst[i];
-            return l < D.t ? nblocks((size_t)(D.lnx[l] / 2 / 4) * (D.lny[l] / 2) * (D.lnz[l] / 2)) : 0u;
-        });
+        B.tabs[TAB_DIR].nb[i] = nblocks(npair(i));
+        B.tabs[TAB_APPLY].nb[i] = red_blocks(npair(i));
+        B.tabs[TAB_UPDATE].nb[i] = red_blocks(npair(i));
+        B.tabs[TAB_DOTS].nb[i] = nblocks(nv(i, 0));
+        if (D.blobs) {
+            B.tabs[TAB_INTERP].nb[i] = (unsigned)((D.N + kBlock / 64 - 1) / (kBlock / 64));
+            B.tabs[TAB_SPREAD].nb[i] = (unsigned)(D.geom.ntx * D.geom.nty * D.geom.ntz);
+        }
+        for (int l = 0; l < D.t; ++l) {
+            B.tabs[TAB_LEVELS + l].nb[i] = nblocks(nv(i, l));
+            B.tabs[TAB_LEVELS + B.Lmax + l].nb[i] =
+                nblocks((size_t)(D.lnx[l] / 2 / 4) * (D.lny[l] / 2) * (D.lnz[l] / 2));
+        }
     }
-    if (ents.size() > (size_t)n * (6 + 2 * kMaxLevels)) throw Err(BLOB_RD_EDEVICE, "batch table overflow");
-    HIPCHK(hipMemcpyAsync(B.d_ent, ents.data(), ents.size() * sizeof(BatchEntry), hipMemcpyHostToDevice, B.st));
+    const size_t tb = batch_tab_bytes(n);
+    for (size_t k = 0; k < B.tabs.size(); ++k) {
+        BatchTable& t = B.tabs[k];
+        t.off = k * tb;
+        unsigned all = 0;
+        for (unsigned v : t.nb) all += (v + 7u) & ~7u;
+        t.grid = std::min(all, kPersistBlocks);
+    }
+    B.tabs_bytes = B.tabs.size() * tb;
+    HIPCHK(hipHostMalloc((void**)&B.h_tabs, B.tabs_bytes, hipHostMallocDefault));
+    std::memset(B.h_tabs, 0, B.tabs_bytes);
+    HIPCHK(hipMemcpyAsync(B.d_tabs, B.h_tabs, B.tabs_bytes, hipMemcpyHostToDevice, B.st));
     HIPCHK(hipMemcpyAsync(B.d_inst, B.h_inst, (size_t)n * sizeof(InstDev), hipMemcpyHostToDevice, B.st));
     HIPCHK(hipMemcpyAsync(B.d_gate, B.h_gate, (size_t)n * sizeof(int), hipMemcpyHostToDevice, B.st));
     HIPCHK(hipStreamSynchronize(B.st));
@@ -1759,9 +1781,11 @@ void batch_teardown(BatchServer& B) {
     if (B.h_inst) (void)hipHostFree(B.h_inst);
     if (B.h_gate) (void)hipHostFree(B.h_gate);
     if (B.h_status) (void)hipHostFree(B.h_status);
+    if (B.h_tabs) (void)hipHostFree(B.h_tabs);
     B.exec = nullptr;
     B.h_inst = nullptr;
     B.h_gate = B.h_status = nullptr;
+    B.h_tabs = nullptr;
 }
 
 // Instance side: hand this CG run (x, at most maxit iterations) to the executor
@@ -1790,8 +1814,10 @@ void batch_run_cg(blob_rd* H, double* x, int maxit, bool blobs, double alpha) {
 // Executor side: rounds of the captured graph for the gated instances until
 // every instance's solve has returned.
 void batch_serve(BatchServer& B) {
+    using clk = std::chrono::steady_clock;
     for (;;) {
         std::vector<int> upload;
+        const auto w0 = clk::now();
         {
             std::unique_lock<std::mutex> lk(B.m);
             B.cv.wait(lk, [&] {
@@ -1815,11 +1841,16 @@ void batch_serve(BatchServer& B) {
                 any = any || S.gated;
             }
             if (!any) return;  // every solve has returned
+            batch_fill_tabs(B);
         }
+        const auto w1 = clk::now();
+        B.idle_s += std::chrono::duration<double>(w1 - w0).count();
+        for (int i = 0; i < B.n; ++i) B.gated_rounds += B.h_gate[i];
         try {
             for (int i : upload)
                 HIPCHK(hipMemcpyAsync(B.d_inst + i, B.h_inst + i, sizeof(InstDev), hipMemcpyHostToDevice, B.st));
             HIPCHK(hipMemcpyAsync(B.d_gate, B.h_gate, (size_t)B.n * sizeof(int), hipMemcpyHostToDevice, B.st));
+            HIPCHK(hipMemcpyAsync(B.d_tabs, B.h_tabs, B.tabs_bytes, hipMemcpyHostToDevice, B.st));
             HIPCHK(hipGraphLaunch(B.exec, B.st));
             HIPCHK(hipMemcpyAsync(B.h_status, B.d_status, (size_t)B.n * 2 * sizeof(int), hipMemcpyDeviceToHost, B.st));
             HIPCHK(hipStreamSynchronize(B.st));
@@ -1830,6 +1861,7 @@ void batch_serve(BatchServer& B) {
             return;
         }
         ++B.rounds;
+        B.busy_s += std::chrono::duration<double>(clk::now() - w1).count();
         std::lock_guard<std::mutex> lk(B.m);
         for (int i = 0; i < B.n; ++i) {
             BatchServer::Slot& S = B.slots[i];
@@ -2354,9 +2386,9 @@ int blob_rd_autotune(blob_rd_t H, int32_t reps, const char* cache_path, int32_t*
 size_t blob_rd_batch_workspace_bytes(int32_t n) { return n > 0 ? batch_bytes(n) + 256 : 0; }
 
 int blob_rd_solve_batched(blob_rd_t* hs, int32_t n, const int32_t* kind, double alpha, const double* const* f,
-                          double* const* c, double* const* lambda, void* workspace, size_t workspace_bytes,
-                          void* stream, blob_rd_stats* stats) {
-    if (!hs || !kind || !f || !c || n <= 0) return g_last_error = "bad argument", BLOB_RD_EINVAL;
+                          double* const* c, double* const* lambda, int64_t lockstep_max_cells, int32_t threads,
+                          void* workspace, size_t workspace_bytes, void* stream, blob_rd_stats* stats) {
+    if (!hs || !kind || !f || !c || n <= 0 || threads < 0) return g_last_error = "bad argument", BLOB_RD_EINVAL;
     if (!workspace || workspace_bytes < blob_rd_batch_workspace_bytes(n))
         return g_last_error = "batch workspace missing or smaller than blob_rd_batch_workspace_bytes()",
                BLOB_RD_ENOMEM;
@@ -2366,49 +2398,85 @@ int blob_rd_solve_batched(blob_rd_t* hs, int32_t n, const int32_t* kind, double 
         for (int j = 0; j < i; ++j)
             if (hs[j] == hs[i]) return g_last_error = "a handle appears twice in the batch", BLOB_RD_EINVAL;
         if (hs[i]->batch) return g_last_error = "instance " + std::to_string(i) + " is in another batch", BLOB_RD_EINVAL;
-        const std::string why = batch_unfit(hs[i], hs[0]->P.esz);
-        if (!why.empty())
-            return g_last_error = "instance " + std::to_string(i) + " cannot join batched launches: " + why,
-                   BLOB_RD_EINVAL;
+    }
+    // Members of the lock-step launches: grids up to lockstep_max_cells whose
+    // levels fit the batched kernels, in the first member's precision. The
+    // others run their CG iterations on their own streams meanwhile.
+    std::vector<int> member, mkind;
+    int esz = 0;
+    for (int i = 0; i < n; ++i) {
+        const blob_rd* H = hs[i];
+        if (lockstep_max_cells > 0 && (int64_t)H->P.ncell > lockstep_max_cells) continue;
+        if (!batch_unfit(H, esz ? esz : (int)H->P.esz).empty()) continue;
+        esz = (int)H->P.esz;
+        member.push_back(i);
+        mkind.push_back(kind[i]);
     }
     BatchServer B;
-    B.n = n;
-    B.esz = (int)hs[0]->P.esz;
+    B.n = (int)member.size();
+    B.esz = esz ? esz : 4;
     B.alpha = alpha;
-    B.hs.assign(hs, hs + n);
+    for (int i : member) B.hs.push_back(hs[i]);
     B.st = (hipStream_t)stream;
-    B.slots = std::vector<BatchServer::Slot>(n);
-    uintptr_t base = ((uintptr_t)workspace + 255) & ~(uintptr_t)255;
-    try {
-        batch_setup(B, reinterpret_cast<char*>(base), workspace_bytes - (base - (uintptr_t)workspace), kind);
-    } catch (const Err& e) {
-        batch_teardown(B);
-        g_last_error = e.what();
-        return e.code;
+    B.slots = std::vector<BatchServer::Slot>(B.n);
+    if (B.n) {
+        uintptr_t base = ((uintptr_t)workspace + 255) & ~(uintptr_t)255;
+        try {
+            batch_setup(B, reinterpret_cast<char*>(base), workspace_bytes - (base - (uintptr_t)workspace),
+                        mkind.data());
+        } catch (const Err& e) {
+            batch_teardown(B);
+            g_last_error = e.what();
+            return e.code;
+        }
+        for (int k = 0; k < B.n; ++k) {
+            hs[member[k]]->batch = &B;
+            hs[member[k]]->batch_slot = k;
+        }
     }
-    for (int i = 0; i < n; ++i) {
-        hs[i]->batch = &B;
-        hs[i]->batch_slot = i;
-    }
-    std::vector<int> rcs(n, 0);
+    std::vector<int> rcs(n, 0), slot_of(n, -1);
+    for (int k = 0; k < B.n; ++k) slot_of[member[k]] = k;
     std::vector<std::string> errs(n);
+    // the instances outside the lock-step launches share `threads` concurrent solves
+    std::mutex qm;
+    std::condition_variable qcv;
+    int running = 0;
+    const int cap = threads > 0 ? threads : n;
     std::vector<std::thread> th;
     th.reserve(n);
     for (int i = 0; i < n; ++i)
         th.emplace_back([&, i]() {
+            const bool outside = slot_of[i] < 0;
+            if (outside) {
+                std::unique_lock<std::mutex> lk(qm);
+                qcv.wait(lk, [&] { return running < cap; });
+                ++running;
+            }
             blob_rd_stats* si = stats ? &stats[i] : nullptr;
             rcs[i] = kind[i] == 0 ? blob_rd_solve_reactive(hs[i], alpha, f[i], c[i], si)
                                   : blob_rd_solve_absorbing(hs[i], alpha, f[i], c[i], lambda[i], si);
             if (rcs[i] < 0) errs[i] = g_last_error;
-            std::lock_guard<std::mutex> lk(B.m);
-            B.slots[i].finished = true;
-            B.cv.notify_all();
+            if (outside) {
+                std::lock_guard<std::mutex> lk(qm);
+                --running;
+                qcv.notify_all();
+            } else {
+                std::lock_guard<std::mutex> lk(B.m);
+                B.slots[slot_of[i]].finished = true;
+                B.cv.notify_all();
+            }
         });
-    batch_serve(B);
+    const auto t0 = std::chrono::steady_clock::now();
+    if (B.n) batch_serve(B);
     for (auto& t : th) t.join();
-    for (int i = 0; i < n; ++i) {
-        hs[i]->batch = nullptr;
-        hs[i]->batch_slot = -1;
+    if (std::getenv("BLOB_RD_LOG"))
+        std::fprintf(stderr, "[blob_rd] batched solve: %d instances (%d in lock-step launches), %.1f ms, %d rounds "
+                     "(%.1f ms running, %.1f ms waiting for instances), %.1f instances per round\n", n, B.n,
+                     1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(), B.rounds,
+                     1e3 * B.busy_s, 1e3 * B.idle_s, B.rounds ? (double)B.gated_rounds / B.rounds : 0.0);
+    for (int k = 0; k < B.n; ++k) {
+        hs[member[k]]->batch = nullptr;
+        hs[member[k]]->batch_slot = -1;
     }
     batch_teardown(B);
     for (int i = 0; i < n; ++i)

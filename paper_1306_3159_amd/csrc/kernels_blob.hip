@@ -303,26 +303,31 @@ __global__ void __launch_bounds__(kBlock) k_spread(const double* __restrict__ la
 
 // Batched blob term of B = alpha I - D L + S kappa J inside a CG iteration:
 // jx = J p, mu = kappa jx (interp), then q += h^-3 S mu (spread, touched tiles only).
-__global__ void __launch_bounds__(kBlock) kb_interp(const InstDev* inst, const int* gate, const BatchEntry* ent,
-                                                    int nent) {
-    Blk blk;
-    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
-    if (!I || !I->blobs) return;
-    interp_body(I->p, I->N, I->geom, I->base, I->wts, I->perm, I->jx, I->kappa, I->mu, blk);
+__global__ void __launch_bounds__(kBlock) kb_interp(const InstDev* inst, const int* gate, const BatchTab* tab) {
+    const BatchEntry* ent = tab_entries(tab);
+    for (unsigned g = blockIdx.x; g < tab->total; g += gridDim.x) {
+        Blk blk;
+        const InstDev* I = batch_slot(inst, gate, ent, tab->n, g, blk);
+        if (!I || !I->blobs) continue;
+        interp_body(I->p, I->N, I->geom, I->base, I->wts, I->perm, I->jx, I->kappa, I->mu, blk);
+    }
 }
 
-__global__ void __launch_bounds__(kBlock) kb_spread(const InstDev* inst, const int* gate, const BatchEntry* ent,
-                                                    int nent) {
-    Blk blk;
-    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
-    if (!I || !I->blobs) return;
-    spread_body(I->mu, 0.0, I->geom, I->base, I->wts, I->offsets, I->perm, I->q, I->q, I->inv_h3, 1, blk);
+__global__ void __launch_bounds__(kBlock) kb_spread(const InstDev* inst, const int* gate, const BatchTab* tab) {
+    const BatchEntry* ent = tab_entries(tab);
+    for (unsigned g = blockIdx.x; g < tab->total; g += gridDim.x) {
+        Blk blk;
+        const InstDev* I = batch_slot(inst, gate, ent, tab->n, g, blk);
+        if (!I || !I->blobs) continue;
+        spread_body(I->mu, 0.0, I->geom, I->base, I->wts, I->offsets, I->perm, I->q, I->q, I->inv_h3, 1, blk);
+        __syncthreads();  // staging arrays are reused by the next virtual block
+    }
 }
 
-void launchb_blob(hipStream_t st, int spread, const InstDev* inst, const int* gate, const BatchEntry* ent, int nent,
-                  unsigned nblocks_total) {
-    if (spread) hipLaunchKernelGGL(kb_spread, dim3(nblocks_total), dim3(kBlock), 0, st, inst, gate, ent, nent);
-    else hipLaunchKernelGGL(kb_interp, dim3(nblocks_total), dim3(kBlock), 0, st, inst, gate, ent, nent);
+void launchb_blob(hipStream_t st, int spread, const InstDev* inst, const int* gate, const BatchTab* tab,
+                  unsigned grid) {
+    if (spread) hipLaunchKernelGGL(kb_spread, dim3(grid), dim3(kBlock), 0, st, inst, gate, tab);
+    else hipLaunchKernelGGL(kb_interp, dim3(grid), dim3(kBlock), 0, st, inst, gate, tab);
 }
 
 void launch_spread(hipStream_t st, const double* lam, double lam_shift, int N, BlobGeom g, const int* base,

@@ -93,13 +93,16 @@ __global__ void __launch_bounds__(kBlock) k_applyA2(const double* __restrict__ p
     applyA2_body(p, q, alpha, s, nx, ny, nz, npair, part, Blk{blockIdx.x, gridDim.x});
 }
 
-__global__ void __launch_bounds__(kBlock) kb_applyA2(const InstDev* inst, const int* gate, const BatchEntry* ent,
-                                                     int nent) {
-    Blk blk;
-    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
-    if (!I) return;
-    applyA2_body(I->p, I->q, I->alpha, I->ls[0], I->nx, I->ny, I->nz, (unsigned)(I->nx / 2) * I->ny * I->nz,
-                 I->part, blk);
+__global__ void __launch_bounds__(kBlock) kb_applyA2(const InstDev* inst, const int* gate, const BatchTab* tab) {
+    const BatchEntry* ent = tab_entries(tab);
+    for (unsigned g = blockIdx.x; g < tab->total; g += gridDim.x) {
+        Blk blk;
+        const InstDev* I = batch_slot(inst, gate, ent, tab->n, g, blk);
+        if (!I) continue;
+        applyA2_body(I->p, I->q, I->alpha, I->ls[0], I->nx, I->ny, I->nz, (unsigned)(I->nx / 2) * I->ny * I->nz,
+                     I->part, blk);
+        __syncthreads();  // partial-sum scratch is reused by the next virtual block
+    }
 }
 
 void launch_applyA2(hipStream_t st, const double* p, double* q, double alpha, double s, int nx, int ny, int nz,
@@ -144,13 +147,15 @@ __global__ void __launch_bounds__(kBlock) k_dir2(const T* __restrict__ z0, const
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) kb_dir2(const InstDev* inst, const int* gate, const BatchEntry* ent,
-                                                  int nent) {
-    Blk blk;
-    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
-    if (!I) return;
-    dir2_body<T>(static_cast<const T*>(I->lv[0][0]), static_cast<const T*>(I->lv[0][1]), I->p, I->nx, I->ny,
-                 (unsigned)(I->nx / 2) * I->ny * I->nz, I->sc->beta, I->sc->shift, blk);
+__global__ void __launch_bounds__(kBlock) kb_dir2(const InstDev* inst, const int* gate, const BatchTab* tab) {
+    const BatchEntry* ent = tab_entries(tab);
+    for (unsigned g = blockIdx.x; g < tab->total; g += gridDim.x) {
+        Blk blk;
+        const InstDev* I = batch_slot(inst, gate, ent, tab->n, g, blk);
+        if (!I) continue;
+        dir2_body<T>(static_cast<const T*>(I->lv[0][0]), static_cast<const T*>(I->lv[0][1]), I->p, I->nx, I->ny,
+                     (unsigned)(I->nx / 2) * I->ny * I->nz, I->sc->beta, I->sc->shift, blk);
+    }
 }
 
 template <typename T>
@@ -211,14 +216,17 @@ __global__ void __launch_bounds__(kBlock) k_update2_enter(double* __restrict__ x
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) kb_update2_enter(const InstDev* inst, const int* gate,
-                                                           const BatchEntry* ent, int nent) {
-    Blk blk;
-    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
-    if (!I) return;
-    update2_enter_body<T>(I->x, I->r, I->p, I->q, static_cast<T*>(I->lv[0][2]), static_cast<T*>(I->lv[0][3]),
-                          static_cast<T*>(I->lv[0][0]), I->nx, I->ny, (unsigned)(I->nx / 2) * I->ny * I->nz,
-                          1.0 / I->ldiag[0], I->sc->alpha, I->sc->mean_next, I->part, blk);
+__global__ void __launch_bounds__(kBlock) kb_update2_enter(const InstDev* inst, const int* gate, const BatchTab* tab) {
+    const BatchEntry* ent = tab_entries(tab);
+    for (unsigned g = blockIdx.x; g < tab->total; g += gridDim.x) {
+        Blk blk;
+        const InstDev* I = batch_slot(inst, gate, ent, tab->n, g, blk);
+        if (!I) continue;
+        update2_enter_body<T>(I->x, I->r, I->p, I->q, static_cast<T*>(I->lv[0][2]), static_cast<T*>(I->lv[0][3]),
+                              static_cast<T*>(I->lv[0][0]), I->nx, I->ny, (unsigned)(I->nx / 2) * I->ny * I->nz,
+                              1.0 / I->ldiag[0], I->sc->alpha, I->sc->mean_next, I->part, blk);
+        __syncthreads();  // partial-sum scratch is reused by the next virtual block
+    }
 }
 
 template <typename T>
@@ -532,21 +540,21 @@ __global__ void __launch_bounds__(kFinBlock) kb_fin(int kind, const InstDev* ins
 }
 
 template <typename T>
-void launchb_cg(hipStream_t st, int what, const InstDev* inst, const int* gate, const BatchEntry* ent, int nent,
-                unsigned nblocks_total, int ninst) {
-    const dim3 g(nblocks_total), b(kBlock);
+void launchb_cg(hipStream_t st, int what, const InstDev* inst, const int* gate, const BatchTab* tab, unsigned grid,
+                int ninst) {
+    const dim3 g(grid), b(kBlock);
     switch (what) {
-        case BCG_DIR: hipLaunchKernelGGL(kb_dir2<T>, g, b, 0, st, inst, gate, ent, nent); break;
-        case BCG_APPLY: hipLaunchKernelGGL(kb_applyA2, g, b, 0, st, inst, gate, ent, nent); break;
-        case BCG_UPDATE: hipLaunchKernelGGL(kb_update2_enter<T>, g, b, 0, st, inst, gate, ent, nent); break;
+        case BCG_DIR: hipLaunchKernelGGL(kb_dir2<T>, g, b, 0, st, inst, gate, tab); break;
+        case BCG_APPLY: hipLaunchKernelGGL(kb_applyA2, g, b, 0, st, inst, gate, tab); break;
+        case BCG_UPDATE: hipLaunchKernelGGL(kb_update2_enter<T>, g, b, 0, st, inst, gate, tab); break;
         default:
             hipLaunchKernelGGL(kb_fin, dim3(ninst), dim3(kFinBlock), 0, st,
                                what == BCG_FIN_ALPHA ? FIN_ALPHA : what == BCG_FIN_UPDATE ? FIN_UPDATE : FIN_BETA,
                                inst, gate, ninst);
     }
 }
-template void launchb_cg<float>(hipStream_t, int, const InstDev*, const int*, const BatchEntry*, int, unsigned, int);
-template void launchb_cg<double>(hipStream_t, int, const InstDev*, const int*, const BatchEntry*, int, unsigned, int);
+template void launchb_cg<float>(hipStream_t, int, const InstDev*, const int*, const BatchTab*, unsigned, int);
+template void launchb_cg<double>(hipStream_t, int, const InstDev*, const int*, const BatchTab*, unsigned, int);
 
 __global__ void __launch_bounds__(kFinBlock) k_reduce_parts(const double* __restrict__ part, unsigned np, int k,
                                                             double* out) {

@@ -787,58 +787,71 @@ hipError_t tail_set_lds(size_t bytes) {
 // Batched forms: one launch covers one level of every instance in the table
 // (the same bodies as the solo kernels, so results are bitwise the same).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) kb_gs(const InstDev* inst, const int* gate, const BatchEntry* ent, int nent,
-                                                int l, int color) {
-    Blk blk;
-    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
-    if (!I) return;
-    T* const* a = reinterpret_cast<T* const*>(I->lv[l]);
-    const int c = color;
-    gs_vec_body<T>(a[c ? 1 : 0], a[c ? 0 : 1], a[c ? 3 : 2], I->lnx[l] >> 1, I->lny[l], I->lnz[l], c, (T)I->ls[l],
-                   (T)(1.0 / I->ldiag[l]), blk);
+__global__ void __launch_bounds__(kBlock) kb_gs(const InstDev* inst, const int* gate, const BatchTab* tab, int l, int color) {
+    const BatchEntry* ent = tab_entries(tab);
+    for (unsigned g = blockIdx.x; g < tab->total; g += gridDim.x) {
+        Blk blk;
+        const InstDev* I = batch_slot(inst, gate, ent, tab->n, g, blk);
+        if (!I) continue;
+        T* const* a = reinterpret_cast<T* const*>(I->lv[l]);
+        const int c = color;
+        gs_vec_body<T>(a[c ? 1 : 0], a[c ? 0 : 1], a[c ? 3 : 2], I->lnx[l] >> 1, I->lny[l], I->lnz[l], c,
+                       (T)I->ls[l], (T)(1.0 / I->ldiag[l]), blk);
+    }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) kb_gs_dots(const InstDev* inst, const int* gate, const BatchEntry* ent,
-                                                     int nent) {
-    Blk blk;
-    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
-    if (!I) return;
-    T* const* a = reinterpret_cast<T* const*>(I->lv[0]);
-    gs_vec_dots_body<T>(a[0], a[1], a[2], I->lnx[0] >> 1, I->lny[0], I->lnz[0], (T)I->ls[0], (T)(1.0 / I->ldiag[0]),
-                        I->r, I->q, I->part, blk);
+__global__ void __launch_bounds__(kBlock) kb_gs_dots(const InstDev* inst, const int* gate, const BatchTab* tab) {
+    const BatchEntry* ent = tab_entries(tab);
+    for (unsigned g = blockIdx.x; g < tab->total; g += gridDim.x) {
+        Blk blk;
+        const InstDev* I = batch_slot(inst, gate, ent, tab->n, g, blk);
+        if (!I) continue;
+        T* const* a = reinterpret_cast<T* const*>(I->lv[0]);
+        gs_vec_dots_body<T>(a[0], a[1], a[2], I->lnx[0] >> 1, I->lny[0], I->lnz[0], (T)I->ls[0],
+                            (T)(1.0 / I->ldiag[0]), I->r, I->q, I->part, blk);
+        __syncthreads();  // partial-sum scratch is reused by the next virtual block
+    }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) kb_resid(const InstDev* inst, const int* gate, const BatchEntry* ent,
-                                                   int nent, int l) {
-    Blk blk;
-    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
-    if (!I) return;
-    T* const* a = reinterpret_cast<T* const*>(I->lv[l]);
-    resid_vec_body<T>(a[0], a[1], a[2], a[4], I->lnx[l] >> 1, I->lny[l], I->lnz[l], (T)I->ls[l], (T)I->ldiag[l], blk);
+__global__ void __launch_bounds__(kBlock) kb_resid(const InstDev* inst, const int* gate, const BatchTab* tab, int l) {
+    const BatchEntry* ent = tab_entries(tab);
+    for (unsigned g = blockIdx.x; g < tab->total; g += gridDim.x) {
+        Blk blk;
+        const InstDev* I = batch_slot(inst, gate, ent, tab->n, g, blk);
+        if (!I) continue;
+        T* const* a = reinterpret_cast<T* const*>(I->lv[l]);
+        resid_vec_body<T>(a[0], a[1], a[2], a[4], I->lnx[l] >> 1, I->lny[l], I->lnz[l], (T)I->ls[l],
+                          (T)I->ldiag[l], blk);
+    }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) kb_restrict(const InstDev* inst, const int* gate, const BatchEntry* ent,
-                                                      int nent, int l) {
-    Blk blk;
-    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
-    if (!I) return;
-    T* const* a = reinterpret_cast<T* const*>(I->lv[l]);
-    T* const* c = reinterpret_cast<T* const*>(I->lv[l + 1]);
-    restrict4_body<T>(a[4], I->lnx[l], I->lny[l], I->lnz[l], c[2], c[3], c[0], 0, (T)(1.0 / I->ldiag[l + 1]), blk);
+__global__ void __launch_bounds__(kBlock) kb_restrict(const InstDev* inst, const int* gate, const BatchTab* tab, int l) {
+    const BatchEntry* ent = tab_entries(tab);
+    for (unsigned g = blockIdx.x; g < tab->total; g += gridDim.x) {
+        Blk blk;
+        const InstDev* I = batch_slot(inst, gate, ent, tab->n, g, blk);
+        if (!I) continue;
+        T* const* a = reinterpret_cast<T* const*>(I->lv[l]);
+        T* const* c = reinterpret_cast<T* const*>(I->lv[l + 1]);
+        restrict4_body<T>(a[4], I->lnx[l], I->lny[l], I->lnz[l], c[2], c[3], c[0], 0, (T)(1.0 / I->ldiag[l + 1]),
+                          blk);
+    }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) kb_prolong(const InstDev* inst, const int* gate, const BatchEntry* ent,
-                                                     int nent, int l) {
-    Blk blk;
-    const InstDev* I = batch_slot(inst, gate, ent, nent, blk);
-    if (!I) return;
-    T* const* a = reinterpret_cast<T* const*>(I->lv[l]);
-    T* const* c = reinterpret_cast<T* const*>(I->lv[l + 1]);
-    prolong_red_body<T>(c[0], c[1], a[0], I->lnx[l], I->lny[l], I->lnz[l], blk);
+__global__ void __launch_bounds__(kBlock) kb_prolong(const InstDev* inst, const int* gate, const BatchTab* tab, int l) {
+    const BatchEntry* ent = tab_entries(tab);
+    for (unsigned g = blockIdx.x; g < tab->total; g += gridDim.x) {
+        Blk blk;
+        const InstDev* I = batch_slot(inst, gate, ent, tab->n, g, blk);
+        if (!I) continue;
+        T* const* a = reinterpret_cast<T* const*>(I->lv[l]);
+        T* const* c = reinterpret_cast<T* const*>(I->lv[l + 1]);
+        prolong_red_body<T>(c[0], c[1], a[0], I->lnx[l], I->lny[l], I->lnz[l], blk);
+    }
 }
 
 // One work-group per instance: the coarse tail from the instance's level t.
@@ -853,16 +866,16 @@ __global__ void __launch_bounds__(kFinBlock) kb_tail(const InstDev* inst, const 
 }
 
 template <typename T>
-void launchb_mg(hipStream_t st, int what, const InstDev* inst, const int* gate, const BatchEntry* ent, int nent,
-                unsigned nblocks_total, int l, int color, unsigned lds) {
-    const dim3 g(nblocks_total), b(kBlock);
+void launchb_mg(hipStream_t st, int what, const InstDev* inst, const int* gate, const BatchTab* tab, unsigned grid,
+                int l, int color, unsigned lds) {
+    const dim3 g(grid), b(kBlock);
     switch (what) {
-        case BMG_GS: hipLaunchKernelGGL(kb_gs<T>, g, b, 0, st, inst, gate, ent, nent, l, color); break;
-        case BMG_GS_DOTS: hipLaunchKernelGGL(kb_gs_dots<T>, g, b, 0, st, inst, gate, ent, nent); break;
-        case BMG_RESID: hipLaunchKernelGGL(kb_resid<T>, g, b, 0, st, inst, gate, ent, nent, l); break;
-        case BMG_RESTRICT: hipLaunchKernelGGL(kb_restrict<T>, g, b, 0, st, inst, gate, ent, nent, l); break;
-        case BMG_PROLONG: hipLaunchKernelGGL(kb_prolong<T>, g, b, 0, st, inst, gate, ent, nent, l); break;
-        default: hipLaunchKernelGGL(kb_tail<T>, dim3(nent), dim3(kFinBlock), lds, st, inst, gate, nent);
+        case BMG_GS: hipLaunchKernelGGL(kb_gs<T>, g, b, 0, st, inst, gate, tab, l, color); break;
+        case BMG_GS_DOTS: hipLaunchKernelGGL(kb_gs_dots<T>, g, b, 0, st, inst, gate, tab); break;
+        case BMG_RESID: hipLaunchKernelGGL(kb_resid<T>, g, b, 0, st, inst, gate, tab, l); break;
+        case BMG_RESTRICT: hipLaunchKernelGGL(kb_restrict<T>, g, b, 0, st, inst, gate, tab, l); break;
+        case BMG_PROLONG: hipLaunchKernelGGL(kb_prolong<T>, g, b, 0, st, inst, gate, tab, l); break;
+        default: hipLaunchKernelGGL(kb_tail<T>, dim3(grid), dim3(kFinBlock), lds, st, inst, gate, (int)grid);
     }
 }
 
@@ -887,8 +900,8 @@ hipError_t tail_set_lds_batched(size_t bytes) {
     template void launch_tail<T>(hipStream_t, const T*, const T*, T*, T*, const TailDesc&, const double*,         \
                                  const Scalars*);                                                                   \
     template hipError_t tail_set_lds<T>(size_t);                                                                   \
-    template void launchb_mg<T>(hipStream_t, int, const InstDev*, const int*, const BatchEntry*, int, unsigned, int, \
-                                int, unsigned);                                                                    \
+    template void launchb_mg<T>(hipStream_t, int, const InstDev*, const int*, const BatchTab*, unsigned, int, int,   \
+                                unsigned);                                                                         \
     template hipError_t tail_set_lds_batched<T>(size_t);
 
 BRD_INST(float)

@@ -85,19 +85,20 @@ hipError_t tail_set_lds(size_t bytes);
 // ---- batched launches (one launch per step for every instance of a batch) ----
 enum { BCG_DIR = 0, BCG_APPLY, BCG_UPDATE, BCG_FIN_ALPHA, BCG_FIN_UPDATE, BCG_FIN_BETA };
 enum { BMG_GS = 0, BMG_GS_DOTS, BMG_RESID, BMG_RESTRICT, BMG_PROLONG, BMG_TAIL };
-// CG steps; the fin kinds take one work-group per instance (ninst)
+// CG steps over the work list `tab` with a fixed grid of `grid` work-groups;
+// the fin kinds take one work-group per instance (ninst)
 template <typename T>
-void launchb_cg(hipStream_t st, int what, const InstDev* inst, const int* gate, const BatchEntry* ent, int nent,
-                unsigned nblocks_total, int ninst);
-// V-cycle steps on level l; BMG_TAIL takes one work-group per instance (nent = ninst) with lds bytes
+void launchb_cg(hipStream_t st, int what, const InstDev* inst, const int* gate, const BatchTab* tab, unsigned grid,
+                int ninst);
+// V-cycle steps on level l; BMG_TAIL takes one work-group per instance (grid = ninst) with lds bytes
 template <typename T>
-void launchb_mg(hipStream_t st, int what, const InstDev* inst, const int* gate, const BatchEntry* ent, int nent,
-                unsigned nblocks_total, int l, int color, unsigned lds);
+void launchb_mg(hipStream_t st, int what, const InstDev* inst, const int* gate, const BatchTab* tab, unsigned grid,
+                int l, int color, unsigned lds);
 template <typename T>
 hipError_t tail_set_lds_batched(size_t bytes);
 // blob term: interp (spread = 0) or spread (1)
-void launchb_blob(hipStream_t st, int spread, const InstDev* inst, const int* gate, const BatchEntry* ent, int nent,
-                  unsigned nblocks_total);
+void launchb_blob(hipStream_t st, int spread, const InstDev* inst, const int* gate, const BatchTab* tab,
+                  unsigned grid);
 
 // ---- blobs -----------------------------------------------------------------
 // wrap positions, kernel weights, tile ids, bin counts (int atomics on counts only)

@@ -127,8 +127,8 @@ def load_library(path: str = LIB_PATH):
     L.blob_rd_batch_workspace_bytes.argtypes = [ctypes.c_int32]
     L.blob_rd_batch_workspace_bytes.restype = ctypes.c_size_t
     L.blob_rd_solve_batched.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), d,
-                                        ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
-                                        ctypes.c_size_t, vp, S]
+                                        ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int64,
+                                        ctypes.c_int32, vp, ctypes.c_size_t, vp, S]
     L.blob_rd_solve_batched.restype = i32
     for name in ("blob_rd_net_create", "blob_rd_net_destroy", "blob_rd_net_set_params", "blob_rd_net_get_params",
                  "blob_rd_net_zero_grad", "blob_rd_net_get_grad", "blob_rd_net_adam_step", "blob_rd_precond_build",
@@ -427,9 +427,11 @@ def solve_batch(solvers: Sequence["BlobRD"], kinds: Sequence[int], fs, cs, lams,
 
 
 def solve_batched(solvers: Sequence["BlobRD"], kinds: Sequence[int], fs, cs, lams, alpha: float = 0.0,
-                  stream: Optional[torch.cuda.Stream] = None):
-    """Lock-step batched solve: the CG iterations of all instances run in shared batched launches
-    (one captured graph replayed in rounds). kinds: 0 reactive, 1 absorbing. Returns (rc, stats)."""
+                  stream: Optional[torch.cuda.Stream] = None, lockstep_max_cells: int = 0, threads: int = 0):
+    """Lock-step batched solve: the CG iterations of the member instances (grids of at most
+    lockstep_max_cells cells, 0 = all that fit) run in shared batched launches (one captured graph
+    replayed in rounds); the others run on their own streams meanwhile, at most `threads` at a time
+    (0 = all). kinds: 0 reactive, 1 absorbing. Returns (rc, stats)."""
     L = load_library()
     n = len(solvers)
     dev = solvers[0].device
@@ -443,8 +445,8 @@ def solve_batched(solvers: Sequence["BlobRD"], kinds: Sequence[int], fs, cs, lam
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     strm = stream if stream is not None else torch.cuda.current_stream(dev)
     torch.cuda.synchronize(dev)
-    rc = L.blob_rd_solve_batched(H, n, K, float(alpha), F, C, Lm, ctypes.c_void_p(ws.data_ptr()), nbytes,
-                                 ctypes.c_void_p(strm.cuda_stream), st)
+    rc = L.blob_rd_solve_batched(H, n, K, float(alpha), F, C, Lm, int(lockstep_max_cells), int(threads),
+                                 ctypes.c_void_p(ws.data_ptr()), nbytes, ctypes.c_void_p(strm.cuda_stream), st)
     if rc < 0:
         raise BlobRDError(rc, L.blob_rd_last_error(None).decode())
     return rc, [st[i].as_dict(rc) for i in range(n)]

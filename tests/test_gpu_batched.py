@@ -59,9 +59,11 @@ def _solo(dev, inst, prec):
     return res
 
 
-@pytest.mark.parametrize("prec", [1, 0])
-def test_batched_matches_solo(dev, prec):
-    _say("batched vs solo, prec", prec)
+@pytest.mark.parametrize("prec,max_cells", [(1, 0), (0, 0), (1, 300000)])
+def test_batched_matches_solo(dev, prec, max_cells):
+    """All instances in the lock-step launches (max_cells 0), or only grids up to 64^3 with the
+    larger ones on their own streams meanwhile: bitwise the solo results either way."""
+    _say("batched vs solo, prec", prec, "max_cells", max_cells)
     from paper_1306_3159_amd import solve_batched
     specs = [(32, 60, 0), (48, 200, 1), (64, 300, 0), (32, 20, 1), (96, 400, 1), (64, 150, 1), (48, 90, 0),
              (128, 500, 0)]
@@ -73,7 +75,8 @@ def test_batched_matches_solo(dev, prec):
         cs = [torch.zeros_like(f) for f in fs]
         ls = [torch.zeros(q.shape[0], dtype=torch.float64, device=dev) if kind else None
               for _, q, _, kind, _ in inst]
-        rc, stats = solve_batched(Hs, [kind for _, _, _, kind, _ in inst], fs, cs, ls)
+        rc, stats = solve_batched(Hs, [kind for _, _, _, kind, _ in inst], fs, cs, ls, lockstep_max_cells=max_cells,
+                                  threads=3 if rep else 0)
         assert rc == 0, stats
         for (c0, l0, st0), c, l, st in zip(solo, cs, ls, stats):
             assert np.array_equal(c.cpu().numpy(), c0)
@@ -88,20 +91,29 @@ def test_batched_matches_solo(dev, prec):
         S.close()
 
 
-def test_batched_rejects_unfit(dev):
-    _say("batched validation")
+def test_batched_serves_unfit_instances_on_streams(dev):
+    """A grid whose split rows are not 4-wide (x = 20) cannot join the batched kernels; it is solved
+    on its own stream while the others use the lock-step launches, with the same results."""
+    _say("batched with an unfit instance")
     from paper_1306_3159_amd import BlobRD, solve_batched
-    from paper_1306_3159_amd.native import BlobRDError
     rng = np.random.default_rng(4200)
-    shapes = [(32, 32, 20), (32, 32, 32)]  # [z, y, x]: x = 20 leaves 10-cell split rows (not 4-wide)
-    Hs, fs = [], []
+    shapes = [(32, 32, 20), (32, 32, 32), (48, 48, 48)]  # [z, y, x]
+    Hs, fs, ref = [], [], []
     for sh in shapes:
-        q = np.column_stack([rng.uniform(0, sh[2], 10), rng.uniform(0, sh[1], 10), rng.uniform(0, sh[0], 10)])
-        Hs.append(BlobRD(sh, torch.tensor(q, device=dev), torch.ones(10, dtype=torch.float64, device=dev),
-                         precision=1))
-        fs.append(torch.ones(sh, dtype=torch.float64, device=dev))
+        q = np.column_stack([rng.uniform(0, sh[2], 12), rng.uniform(0, sh[1], 12), rng.uniform(0, sh[0], 12)])
+        kap = rng.uniform(0.5, 2.0, 12)
+        f = 1.0 + 0.5 * rng.standard_normal(sh)
+        S = BlobRD(sh, torch.tensor(q, device=dev), torch.tensor(kap, device=dev), precision=1,
+                   stream=torch.cuda.Stream(dev))
+        c, st = S.solve_reactive(torch.tensor(f, device=dev))
+        assert st["rc"] == 0
+        ref.append(c.cpu().numpy())
+        Hs.append(S)
+        fs.append(torch.tensor(f, device=dev))
     cs = [torch.zeros_like(f) for f in fs]
-    with pytest.raises(BlobRDError, match="instance 0"):
-        solve_batched(Hs, [0, 0], fs, cs, [None, None])
+    rc, stats = solve_batched(Hs, [0, 0, 0], fs, cs, [None, None, None])
+    assert rc == 0
+    for c, r in zip(cs, ref):
+        assert np.array_equal(c.cpu().numpy(), r)
     for S in Hs:
         S.close()
