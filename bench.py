@@ -108,6 +108,11 @@ def bench_batch(args, dev, rtol):
     cs = [torch.zeros_like(f) for f in fs]
     ls = [torch.zeros(i.N, dtype=torch.float64, device=dev) if k else None for i, k in zip(insts, kinds)]
     bstream = torch.cuda.Stream(dev)
+    tuned = 0
+    if args.autotune:
+        import tempfile
+        cache = os.path.join(tempfile.mkdtemp(), "tune.json")  # one timing per distinct level shape
+        tuned = sum(H.autotune(reps=5, cache=cache) for H in Hs)
 
     def step_lockstep():
         for c in cs:
@@ -143,7 +148,7 @@ def bench_batch(args, dev, rtol):
                       "total_blobs": sum(i.N for i in insts), "rtol": rtol,
                       "executor": "lock-step batched launches for grids <= 64^3, own streams for larger grids",
                       "lockstep_instances": sum(1 for i in insts if i.n ** 3 <= LOCKSTEP_MAX_CELLS),
-                      "stream_threads": args.threads},
+                      "stream_threads": args.threads, "autotuned_levels": tuned},
            "rc": rc, "max_rel_resid": max(s["rel_resid"] for s in stats),
            "streams_executor": {"instances_per_s": len(insts) * ns / sdt, "threads": args.threads, "rc": src},
            "serial_instances_per_s": len(insts) / serial}
