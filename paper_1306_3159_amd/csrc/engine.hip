@@ -305,6 +305,7 @@ struct blob_rd {
     hipStream_t cap_stream = nullptr;
     bool use_graphs = true;
     bool relax = true;  // relaxed inner tolerances in the Schur GMRES
+    bool blocked = true;  // temporally blocked launches on the coarser per-level levels
     // learned Schur preconditioner (CSR of W in a caller-provided buffer)
     struct Learned {
         bool ready = false;
@@ -451,6 +452,10 @@ TailDesc make_tail(const blob_rd* H, int t, double alpha) {
 // half-sweep, which does not read them) and four half-sweeps on the way up.
 constexpr double kPreRestrictBytes = 3 * 1.5 + 2.0 + 0.5 + 0.1875;
 constexpr double kProlongPostBytes = 1.125 + 4 * 1.5;
+// temporally blocked levels: red u and f in, pre-smoothed red and coarse f, u out;
+// coarse u, pre-smoothed red and f in, both colours out
+constexpr double kBlockedDownBytes = 0.5 + 1.0 + 0.5 + 0.1875;
+constexpr double kBlockedUpBytes = 0.125 + 0.5 + 1.0 + 1.0;
 
 // entered: level 0's f and first red sweep were already written (fused CG
 // update). dot_q (with a non-null sc): fuse the CG dots (sum z, z.r, z.q) into
@@ -483,10 +488,25 @@ unsigned vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, co
         launch_enter<T>(st, r, lv(0, 2), lv(0, 3), lv(0, 0), d.nx, d.ny, d.nz, 1.0 / (alpha + 6.0 * s), sc);
         H->alg_bytes += (double)P.ncell * (8 + P.esz * 1.5);
     }
+    // levels below the finest whose pre- and post-smoothing run temporally blocked:
+    // those of at most 64^3 cells, where a launch costs more than the level's bytes
+    // (on larger levels the recomputed halos cost more than the launches they save)
+    auto blocked = [&](int l) {
+        const LevelDims& d = P.lev[l];
+        return H->blocked && l >= 1 && d.nx % 8 == 0 && d.ny % 8 == 0 && d.nz % 8 == 0 &&
+               (size_t)d.nx * d.ny * d.nz <= (size_t)64 * 64 * 64;
+    };
     if (t < L) {
         for (int l = 0; l < t; ++l) {
             const LevelDims& d = P.lev[l];
             const double s = D / (d.h * d.h), diag = alpha + 6.0 * s;
+            if (blocked(l)) {
+                const LevelDims& c = P.lev[l + 1];
+                launch_down<T>(st, lv(l, 0), lv(l, 2), lv(l, 3), lv(l, 4), d.nx, d.ny, d.nz, s, diag, lv(l + 1, 2),
+                               lv(l + 1, 3), lv(l + 1, 0), 1.0 / (alpha + 6.0 * (D / (c.h * c.h))), sc);
+                H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * kBlockedDownBytes;
+                continue;
+            }
             const int* b = H->bs[l];
             launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
             launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
@@ -503,6 +523,12 @@ unsigned vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, co
         for (int l = t - 1; l >= 0; --l) {
             const LevelDims& d = P.lev[l];
             const double s = D / (d.h * d.h), diag = alpha + 6.0 * s;
+            if (blocked(l)) {
+                launch_up<T>(st, lv(l + 1, 0), lv(l + 1, 1), lv(l, 4), lv(l, 2), lv(l, 3), lv(l, 0), lv(l, 1), d.nx,
+                             d.ny, d.nz, s, diag, sc);
+                H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * kBlockedUpBytes;
+                continue;
+            }
             const int* b = H->bs[l];
             launch_prolong<T>(st, lv(l + 1, 0), lv(l + 1, 1), 0, lv(l, 0), lv(l, 1), d.nx, d.ny, d.nz, sc, b[3]);
             launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
@@ -1102,6 +1128,7 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
     for (auto& row : H->bs)
         for (int& v : row) v = kBlock;
     if (const char* g = std::getenv("BLOB_RD_RELAX")) H->relax = std::atoi(g) != 0;
+    if (const char* g = std::getenv("BLOB_RD_BLOCKED")) H->blocked = std::atoi(g) != 0;
     // Align the workspace base to 256 bytes.
     uintptr_t base = (uintptr_t)p->workspace;
     H->ws = (char*)((base + 255) & ~(uintptr_t)255);
@@ -1168,6 +1195,10 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
         if (H->tail_level[1] < Lc) {
             const size_t need = make_tail<double>(H, H->tail_level[1], 0.0).lds_bytes;
             if (need > 48 * 1024) HIPCHK(tail_set_lds<double>(need));
+        }
+        if (H->blocked) {
+            HIPCHK(blocked_set_lds<float>());
+            HIPCHK(blocked_set_lds<double>());
         }
     } catch (const Err& e) {
         g_last_error = e.what();

@@ -542,6 +542,221 @@ void launch_prolong(hipStream_t st, const T* cu0, const T* cu1, int coarse_natur
 }
 
 // ---------------------------------------------------------------------------
+// Temporally blocked forms for the small per-level levels, where a launch costs
+// more than its bytes: one launch does the whole pre-smoothing, residual and
+// restriction of a tile, one the whole correction and post-smoothing. A tile is
+// 4 x 4 x 4 coarse cells (8^3 fine cells); it is computed in LDS from a halo that
+// shrinks by one cell per half-sweep, so neighbouring tiles recompute their
+// shared halo instead of synchronising. The arithmetic per cell is that of the
+// per-step kernels, in the same order, so the results are bitwise identical.
+constexpr int kTile = 8;             // fine tile edge
+constexpr int kDownW = kTile + 10;   // pre-smoothing window: 5-cell halo
+constexpr int kUpW = kTile + 8;      // post-smoothing window: 4-cell halo
+constexpr int kUpCW = kTile / 2 + 6; // coarse window of the correction
+constexpr int kResW = kTile + 2;     // residual window: 1-cell halo
+
+inline size_t down_lds_bytes(size_t esz) { return esz * (2 * kDownW * kDownW * kDownW + kResW * kResW * kResW); }
+inline size_t up_lds_bytes(size_t esz) { return esz * (2 * kUpW * kUpW * kUpW + kUpCW * kUpCW * kUpCW); }
+
+// One half-sweep of the cells of colour `col` in the window cube [lo, hi)^3 of a
+// W^3 LDS window; a cell's colour is (a + b + c + par) & 1 in window coordinates.
+template <typename T, int W>
+__device__ __forceinline__ void win_sweep(T* U, const T* F, int lo, int hi, int col, int par, T s, T inv_diag) {
+    const int w = hi - lo, half = w >> 1, count = half * w * w;
+    for (int j = threadIdx.x; j < count; j += blockDim.x) {
+        const int i = j % half, t = j / half;
+        const int b = lo + t % w, c = lo + t / w;
+        const int a = lo + 2 * i + ((col + b + c + par - lo) & 1);
+        const int k = (c * W + b) * W + a;
+        U[k] = (F[k] + s * (((U[k - 1] + U[k + 1]) + (U[k - W] + U[k + W])) + (U[k - W * W] + U[k + W * W]))) *
+               inv_diag;
+    }
+    __syncthreads();
+}
+
+// Pre-smoothing (black, red, black from the zero-guess red u0), red residual and
+// restriction of the tile; writes the pre-smoothed red to `ured` (a separate
+// array: neighbouring tiles still read u0 in their halos) and the coarse f and
+// zero-guess red u of level l + 1 (split).
+template <typename T>
+__global__ void __launch_bounds__(kFinBlock) k_down(const T* __restrict__ u0, const T* __restrict__ f0,
+                                                 const T* __restrict__ f1, T* __restrict__ ured, int nx, int ny, int nz,
+                                                 T s, T inv_diag, T diag, T* __restrict__ cf0, T* __restrict__ cf1,
+                                                 T* __restrict__ cu0, T inv_diag_c, const Scalars* sc) {
+    if (sc && sc->done) return;
+    constexpr int W = kDownW;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* U = reinterpret_cast<T*>(smem);
+    T* F = U + W * W * W;
+    T* R = F + W * W * W;
+    const int hx = nx >> 1, cx = nx >> 1, cy = ny >> 1, cz = nz >> 1;
+    const int tx = cx / 4, ty = cy / 4;
+    const unsigned tile = xcd_block(blockIdx.x, gridDim.x);
+    const int X0 = 4 * (int)(tile % tx), Y0 = 4 * (int)((tile / tx) % ty), Z0 = 4 * (int)(tile / (tx * ty));
+    const int ox = 2 * X0 - 5, oy = 2 * Y0 - 5, oz = 2 * Z0 - 5;  // window origin (fine)
+    for (int j = threadIdx.x; j < W * W * W; j += blockDim.x) {
+        const int a = j % W, b = (j / W) % W, c = j / (W * W);
+        const int x = wrapi(ox + a, nx), y = wrapi(oy + b, ny), z = wrapi(oz + c, nz);
+        const size_t k = ((size_t)z * ny + y) * hx + (x >> 1);
+        const int col = (x + y + z) & 1;
+        F[j] = col ? f1[k] : f0[k];
+        U[j] = col ? (T)0 : u0[k];
+    }
+    __syncthreads();
+    // window colour parity: the origin offsets are odd on all three axes
+    win_sweep<T, W>(U, F, 1, W - 1, 1, 1, s, inv_diag);
+    win_sweep<T, W>(U, F, 2, W - 2, 0, 1, s, inv_diag);
+    win_sweep<T, W>(U, F, 3, W - 3, 1, 1, s, inv_diag);
+    constexpr int RW = kResW;
+    for (int j = threadIdx.x; j < RW * RW * RW; j += blockDim.x) {
+        const int a = 4 + j % RW, b = 4 + (j / RW) % RW, c = 4 + j / (RW * RW);
+        const int k = (c * W + b) * W + a;
+        R[j] = ((a + b + c + 1) & 1)
+                   ? (T)0
+                   : F[k] - (diag * U[k] -
+                             s * (((U[k - 1] + U[k + 1]) + (U[k - W] + U[k + W])) + (U[k - W * W] + U[k + W * W])));
+    }
+    __syncthreads();
+    // pre-smoothed red of the tile interior
+    for (int j = threadIdx.x; j < kTile * kTile * kTile / 2; j += blockDim.x) {
+        const int i = j % (kTile / 2), t = j / (kTile / 2);
+        const int b = 5 + t % kTile, c = 5 + t / kTile;
+        const int a = 5 + 2 * i + ((b + c) & 1);  // red: (a + b + c + 1) even
+        const int x = ox + a, y = oy + b, z = oz + c;  // interior cells need no wrap
+        ured[((size_t)z * ny + y) * hx + (x >> 1)] = U[(c * W + b) * W + a];
+    }
+    // restriction of the tile's 64 coarse cells (black residual zero): the four
+    // z-planes of each coarse cell in parallel, then their weighted sum in order
+    T* P = U;  // the sweep window is free now
+    for (int j = threadIdx.x; j < 256; j += blockDim.x) {
+        const int cell = j & 63, c = j >> 6;
+        const int Xl = cell & 3, Yl = (cell >> 2) & 3, Zl = cell >> 4;
+        const T w0 = (T)0.125, w1 = (T)0.375;
+        T accb = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const T* row = R + ((2 * Zl + c) * RW + (2 * Yl + b)) * RW;  // fine y = 2Yl - 1 + b, +1 window shift
+            const int p = (b + c) & 1;  // parity of the fine row: red cells at x = 2X - 1, 2X + 1 when 1
+            const T ra = row[2 * Xl], rb = row[2 * Xl + 1], rc = row[2 * Xl + 2], rd = row[2 * Xl + 3];
+            accb += (b == 0 || b == 3 ? w0 : w1) * restrict_row(w0, w1, p, p ? ra : (T)0, p ? rc : rb, p ? (T)0 : rd);
+        }
+        P[j] = accb;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int cell = threadIdx.x;
+        const int Xl = cell & 3, Yl = (cell >> 2) & 3, Zl = cell >> 4;
+        const T w0 = (T)0.125, w1 = (T)0.375;
+        T acc = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc += (c == 0 || c == 3 ? w0 : w1) * P[c * 64 + cell];
+        const int X = X0 + Xl, Y = Y0 + Yl, Z = Z0 + Zl;
+        const size_t j = ((size_t)Z * cy + Y) * (cx >> 1) + (X >> 1);
+        if ((X + Y + Z) & 1) {
+            cf1[j] = acc;
+        } else {
+            cf0[j] = acc;
+            cu0[j] = acc * inv_diag_c;
+        }
+    }
+    (void)cz;
+}
+
+// Correction of the red cells from the coarse level (split), then
+// post-smoothing (black, red, black, red); writes the tile's final u0 and u1.
+template <typename T>
+__global__ void __launch_bounds__(kFinBlock) k_up(const T* __restrict__ cu0, const T* __restrict__ cu1,
+                                               const T* __restrict__ ured, const T* __restrict__ f0,
+                                               const T* __restrict__ f1, T* __restrict__ u0, T* __restrict__ u1,
+                                               int nx, int ny, int nz, T s, T inv_diag, const Scalars* sc) {
+    if (sc && sc->done) return;
+    constexpr int W = kUpW, CW = kUpCW;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* U = reinterpret_cast<T*>(smem);
+    T* F = U + W * W * W;
+    T* C = F + W * W * W;
+    const int hx = nx >> 1, cx = nx >> 1, cy = ny >> 1, cz = nz >> 1;
+    const int tx = cx / 4, ty = cy / 4;
+    const unsigned tile = xcd_block(blockIdx.x, gridDim.x);
+    const int X0 = 4 * (int)(tile % tx), Y0 = 4 * (int)((tile / tx) % ty), Z0 = 4 * (int)(tile / (tx * ty));
+    const int ox = 2 * X0 - 4, oy = 2 * Y0 - 4, oz = 2 * Z0 - 4;  // window origin (fine)
+    const int cox = X0 - 3, coy = Y0 - 3, coz = Z0 - 3;          // coarse window origin
+    for (int j = threadIdx.x; j < CW * CW * CW; j += blockDim.x) {
+        const int a = j % CW, b = (j / CW) % CW, c = j / (CW * CW);
+        C[j] = coarse_at(cu0, cu1, 0, wrapi(cox + a, cx), wrapi(coy + b, cy), wrapi(coz + c, cz), cx, cy);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < W * W * W; j += blockDim.x) {
+        const int a = j % W, b = (j / W) % W, c = j / (W * W);
+        const int xu = ox + a, yu = oy + b, zu = oz + c;  // unwrapped fine coordinates
+        const int x = wrapi(xu, nx), y = wrapi(yu, ny), z = wrapi(zu, nz);
+        const size_t k = ((size_t)z * ny + y) * hx + (x >> 1);
+        const int col = (x + y + z) & 1;
+        F[j] = col ? f1[k] : f0[k];
+        if (col) {
+            U[j] = (T)0;
+        } else {
+            // trilinear weights 3/4 (own coarse cell) and 1/4 (the neighbour on the cell's side)
+            const int I0 = (xu >> 1) - cox, I1 = (xu & 1) ? I0 + 1 : I0 - 1;
+            const int J0 = (yu >> 1) - coy, J1 = (yu & 1) ? J0 + 1 : J0 - 1;
+            const int K0 = (zu >> 1) - coz, K1 = (zu & 1) ? K0 + 1 : K0 - 1;
+            const T* c00 = C + (K0 * CW + J0) * CW;
+            const T* c10 = C + (K0 * CW + J1) * CW;
+            const T* c01 = C + (K1 * CW + J0) * CW;
+            const T* c11 = C + (K1 * CW + J1) * CW;
+            const T a00 = (T)0.75 * c00[I0] + (T)0.25 * c00[I1];
+            const T a10 = (T)0.75 * c10[I0] + (T)0.25 * c10[I1];
+            const T a01 = (T)0.75 * c01[I0] + (T)0.25 * c01[I1];
+            const T a11 = (T)0.75 * c11[I0] + (T)0.25 * c11[I1];
+            T u = ured[k];
+            u += (T)0.75 * ((T)0.75 * a00 + (T)0.25 * a10) + (T)0.25 * ((T)0.75 * a01 + (T)0.25 * a11);
+            U[j] = u;
+        }
+    }
+    __syncthreads();
+    // window colour parity: the origin offsets are even
+    win_sweep<T, W>(U, F, 1, W - 1, 1, 0, s, inv_diag);
+    win_sweep<T, W>(U, F, 2, W - 2, 0, 0, s, inv_diag);
+    win_sweep<T, W>(U, F, 3, W - 3, 1, 0, s, inv_diag);
+    win_sweep<T, W>(U, F, 4, W - 4, 0, 0, s, inv_diag);
+    for (int j = threadIdx.x; j < kTile * kTile * kTile; j += blockDim.x) {
+        const int a = 4 + j % kTile, b = 4 + (j / kTile) % kTile, c = 4 + j / (kTile * kTile);
+        const int x = ox + a, y = oy + b, z = oz + c;
+        const size_t k = ((size_t)z * ny + y) * hx + (x >> 1);
+        const T v = U[(c * W + b) * W + a];
+        if ((x + y + z) & 1) u1[k] = v;
+        else u0[k] = v;
+    }
+}
+
+template <typename T>
+void launch_down(hipStream_t st, const T* u0, const T* f0, const T* f1, T* ured, int nx, int ny, int nz, double s,
+                 double diag, T* cf0, T* cf1, T* cu0, double inv_diag_c, const Scalars* sc) {
+    const unsigned nt = (unsigned)(nx / 8) * (ny / 8) * (nz / 8);
+    const unsigned bs = nt <= 512 ? kFinBlock : kBlock;  // few tiles: more threads per tile
+    hipLaunchKernelGGL(k_down<T>, dim3(nt), dim3(bs), down_lds_bytes(sizeof(T)), st, u0, f0, f1, ured, nx, ny, nz,
+                       (T)s, (T)(1.0 / diag), (T)diag, cf0, cf1, cu0, (T)inv_diag_c, sc);
+}
+
+template <typename T>
+void launch_up(hipStream_t st, const T* cu0, const T* cu1, const T* ured, const T* f0, const T* f1, T* u0, T* u1,
+               int nx, int ny, int nz, double s, double diag, const Scalars* sc) {
+    const unsigned nt = (unsigned)(nx / 8) * (ny / 8) * (nz / 8);
+    const unsigned bs = nt <= 512 ? kFinBlock : kBlock;  // few tiles: more threads per tile
+    hipLaunchKernelGGL(k_up<T>, dim3(nt), dim3(bs), up_lds_bytes(sizeof(T)), st, cu0, cu1, ured, f0, f1, u0, u1,
+                       nx, ny, nz, (T)s, (T)(1.0 / diag), sc);
+}
+
+template <typename T>
+hipError_t blocked_set_lds() {
+    hipError_t e = hipFuncSetAttribute((const void*)k_down<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)down_lds_bytes(sizeof(T)));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_up<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)up_lds_bytes(sizeof(T)));
+}
+
+// ---------------------------------------------------------------------------
 // Coarsest grid: u = C f with C the dense FP64 (pseudo-)inverse, m <= 512.
 template <typename T>
 __global__ void __launch_bounds__(kMaxCoarse) k_coarse(const T* __restrict__ f, T* __restrict__ u,
@@ -900,6 +1115,11 @@ hipError_t tail_set_lds_batched(size_t bytes) {
     template void launch_tail<T>(hipStream_t, const T*, const T*, T*, T*, const TailDesc&, const double*,         \
                                  const Scalars*);                                                                   \
     template hipError_t tail_set_lds<T>(size_t);                                                                   \
+    template void launch_down<T>(hipStream_t, const T*, const T*, const T*, T*, int, int, int, double, double, T*, T*, \
+                                 T*, double, const Scalars*);                                                      \
+    template void launch_up<T>(hipStream_t, const T*, const T*, const T*, const T*, const T*, T*, T*, int, int, int,  \
+                               double, double, const Scalars*);                                                    \
+    template hipError_t blocked_set_lds<T>();                                                                      \
     template void launchb_mg<T>(hipStream_t, int, const InstDev*, const int*, const BatchTab*, unsigned, int, int,   \
                                 unsigned);                                                                         \
     template hipError_t tail_set_lds_batched<T>(size_t);

@@ -81,6 +81,16 @@ void launch_tail(hipStream_t st, const T* f0, const T* f1, T* u0, T* u1, const T
                  const Scalars* sc);
 template <typename T>
 hipError_t tail_set_lds(size_t bytes);
+// temporally blocked level (nx, ny, nz divisible by 8): pre-smoothing + red residual +
+// restriction (pre-smoothed red to ured); red correction + post-smoothing from ured
+template <typename T>
+void launch_down(hipStream_t st, const T* u0, const T* f0, const T* f1, T* ured, int nx, int ny, int nz, double s,
+                 double diag, T* cf0, T* cf1, T* cu0, double inv_diag_c, const Scalars* sc);
+template <typename T>
+void launch_up(hipStream_t st, const T* cu0, const T* cu1, const T* ured, const T* f0, const T* f1, T* u0, T* u1,
+               int nx, int ny, int nz, double s, double diag, const Scalars* sc);
+template <typename T>
+hipError_t blocked_set_lds();
 
 // ---- batched launches (one launch per step for every instance of a batch) ----
 enum { BCG_DIR = 0, BCG_APPLY, BCG_UPDATE, BCG_FIN_ALPHA, BCG_FIN_UPDATE, BCG_FIN_BETA };

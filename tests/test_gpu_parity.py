@@ -401,3 +401,27 @@ def test_rsa256_backward_euler(dev, rsa256):
         totals.append(float(c.sum()))
     assert all(b > a for a, b in zip(totals, totals[1:]))
     S.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_blocked_levels_bitwise(dev, monkeypatch, prec):
+    """The temporally blocked launches of the coarser per-level levels (pre-smoothing, residual and
+    restriction in one launch; correction and post-smoothing in another) give bitwise the results of
+    the per-step launches: one V-cycle and a whole absorbing solve."""
+    _say("blocked levels, prec", prec)
+    rng = np.random.default_rng(91)
+    n = 128
+    q = W.rsa_positions(rng, n, 300, 3.0)
+    f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
+    r = rng.standard_normal((n, n, n))
+    out = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("BLOB_RD_BLOCKED", mode)
+        S = make(dev, n, q, precision=prec)
+        z = H(S.vcycle(T(r, dev), 0.0))
+        c, lam, st = S.solve_absorbing(T(f, dev))
+        assert st["rc"] == 0
+        out[mode] = (z, H(c), H(lam))
+        S.close()
+    for a, b in zip(out["1"], out["0"]):
+        assert np.array_equal(a, b)
