@@ -911,7 +911,7 @@ SaddleInfo saddle_solve(blob_rd* H, double alpha, const double* g, const double*
             // (Bouras-Fraysse / Simoncini-Szyld relaxation); the FP64 saddle residual
             // and refinement of the caller guard the final answer.
             double tau = inner_rtol;
-            if (H->relax && res_prev > 0.0) tau = std::min(1e-2, std::max(inner_rtol, 0.1 * atol_schur / res_prev));
+            if (H->relax && res_prev > 0.0) tau = std::min(1e-1, std::max(inner_rtol, atol_schur / res_prev));
             if (use_w) {
                 precond_apply(H, V + (size_t)k * N, H->nv(9));
                 schur_apply<T>(H, alpha, H->nv(9), V + (size_t)(k + 1) * N, tau);
