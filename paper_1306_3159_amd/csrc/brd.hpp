@@ -50,6 +50,7 @@ struct Scalars {
     int32_t iters;    // completed CG iterations
     int32_t project;  // 1: alpha = 0 problem, work on mean-zero vectors
     int32_t status;   // 0 ok, 1 breakdown/non-finite
+    int32_t xzero;    // 1: x starts at zero and the first update writes it (no prior fill)
 };
 
 // Device-resident scalars of the Schur GMRES (single work-group kernels).

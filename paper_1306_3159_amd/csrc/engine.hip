@@ -340,7 +340,9 @@ namespace {
 
 enum GridBuf { G_R = 0, G_P = 1, G_Q = 2, G_U = 3, G_G = 4, G_T1 = 5, G_T2 = 6, G_P2 = 7 };
 
-__global__ void k_sc_init(Scalars* sc, int project, double inv_ncell, double eBe_inv, double rtol2, double abs2) {
+__global__ void k_sc_init(Scalars* sc, int project, double inv_ncell, double eBe_inv, double rtol2, double abs2,
+                          int xzero) {
+    sc->xzero = xzero;
     sc->rz = 0.0;
     sc->pq = 0.0;
     sc->alpha = 0.0;
@@ -640,12 +642,17 @@ PcgResult pcg(blob_rd* H, bool with_blobs, double alpha, const double* g, double
     const double eBe_inv = (with_blobs && project && eBe > 0.0) ? 1.0 / eBe : 0.0;
     const double* cinv = select_cinv(H, alpha);
     hipLaunchKernelGGL(k_sc_init, dim3(1), dim3(1), 0, st, H->sc(), project, 1.0 / (double)P.ncell, eBe_inv,
-                       rtol * rtol, abs_tol * abs_tol);
+                       rtol * rtol, abs_tol * abs_tol, x_zero ? 1 : 0);
     unsigned np = 0;
     if (x_zero) {
-        launch_fill(st, x, P.ncell, 0.0);
-        launch_residual_from_q(st, g, nullptr, r, P.ncell, H->part(), &np);
-        H->alg_bytes += (double)P.ncell * 24;
+        // x = 0 is written by the first update (or below when no iteration runs)
+        if (g == r) {
+            launch_self_partials(st, g, P.ncell, H->part(), &np);
+            H->alg_bytes += (double)P.ncell * 8;
+        } else {
+            launch_residual_from_q(st, g, nullptr, r, P.ncell, H->part(), &np);
+            H->alg_bytes += (double)P.ncell * 16;
+        }
     } else {
         launch_applyA_plain(st, x, q, alpha, s, d.nx, d.ny, d.nz);
         if (blobs) blob_term(H, x, q, nullptr);
@@ -696,6 +703,7 @@ PcgResult pcg(blob_rd* H, bool with_blobs, double alpha, const double* g, double
         res.rr = H->hsc->rr;
         res.gg = H->hsc->gg;
         res.converged = H->hsc->done && H->hsc->status == 0;
+        if (x_zero && res.iters == 0) launch_fill(st, x, P.ncell, 0.0);
         return res;
     }
     blob_rd::GraphEntry* ge = nullptr;
@@ -752,6 +760,7 @@ PcgResult pcg(blob_rd* H, bool with_blobs, double alpha, const double* g, double
     res.rr = H->hsc->rr;
     res.gg = H->hsc->gg;
     res.converged = H->hsc->done && H->hsc->status == 0;
+    if (x_zero && res.iters == 0) launch_fill(st, x, P.ncell, 0.0);
     return res;
 }
 
@@ -826,10 +835,11 @@ void schur_apply(blob_rd* H, double alpha, const double* x, double* y, double in
     double* xt = H->nv(2);
     launch_nvec_copy_scale(st, x, xt, P.N, 1.0, 0.0);
     if (alpha == 0.0) launch_nvec_project(st, xt, P.N);
+    // S x straight into the CG residual (zero start: r = g)
     launch_spread(st, xt, 0.0, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
-                  H->at<int>(P.off_offsets), H->at<int>(P.off_perm), nullptr, H->grid(G_G), H->inv_h3(), 0, nullptr);
+                  H->at<int>(P.off_offsets), H->at<int>(P.off_perm), nullptr, H->grid(G_R), H->inv_h3(), 0, nullptr);
     H->alg_bytes += (double)P.ncell * 8;
-    PcgResult pr = pcg<T>(H, false, alpha, H->grid(G_G), H->grid(G_U), true, inner_rtol, 0.0, inner_maxit(H));
+    PcgResult pr = pcg<T>(H, false, alpha, H->grid(G_R), H->grid(G_U), true, inner_rtol, 0.0, inner_maxit(H));
     if (pr.status) throw Err(BLOB_RD_ENUMERIC, "non-finite value or breakdown in inner CG");
     H->inner_iters += pr.iters;
     launch_interp(st, H->grid(G_U), P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),

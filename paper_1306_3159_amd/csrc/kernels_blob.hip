@@ -199,34 +199,40 @@ __device__ __forceinline__ void spread_body(const double* __restrict__ lam, doub
     __shared__ int nrng;
     const int t = xcd_block(blk.b, blk.nb);
     const int tix = t % g.ntx, tiy = (t / g.ntx) % g.nty, tiz = t / (g.ntx * g.nty);
-    if (threadIdx.x == 0) {
-        int lx[3], ly[3], lz[3], nxl = 0, nyl = 0, nzl = 0;
-        for (int d = -1; d <= 1; ++d) {
-            const int vx = (tix + d + g.ntx) % g.ntx, vy = (tiy + d + g.nty) % g.nty, vz = (tiz + d + g.ntz) % g.ntz;
-            bool dup = false;
-            for (int k = 0; k < nxl; ++k) dup |= lx[k] == vx;
-            if (!dup) lx[nxl++] = vx;
-            dup = false;
-            for (int k = 0; k < nyl; ++k) dup |= ly[k] == vy;
-            if (!dup) ly[nyl++] = vy;
-            dup = false;
-            for (int k = 0; k < nzl; ++k) dup |= lz[k] == vz;
-            if (!dup) lz[nzl++] = vz;
+    // Blob ranges of the 27 neighbouring tiles (z-major, then y, then x; a tile
+    // reached twice on small periodic grids is taken at its first offset per
+    // axis): one thread per neighbour fetches its range, thread 0 packs them.
+    __shared__ int nb_lo[27], nb_len[27];
+    if (threadIdx.x < 27) {
+        const int d = threadIdx.x;
+        const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+        const int vx = (tix + dx + g.ntx) % g.ntx, vy = (tiy + dy + g.nty) % g.nty, vz = (tiz + dz + g.ntz) % g.ntz;
+        bool first = true;
+        for (int e = -1; e < dx; ++e) first &= (tix + e + g.ntx) % g.ntx != vx;
+        for (int e = -1; e < dy; ++e) first &= (tiy + e + g.nty) % g.nty != vy;
+        for (int e = -1; e < dz; ++e) first &= (tiz + e + g.ntz) % g.ntz != vz;
+        int lo = 0, len = 0;
+        if (first) {
+            const int nt = (vz * g.nty + vy) * g.ntx + vx;
+            lo = offsets[nt];
+            len = offsets[nt + 1] - lo;
         }
+        nb_lo[d] = lo;
+        nb_len[d] = len;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
         int nr = 0, pre = 0;
-        for (int c = 0; c < nzl; ++c)
-            for (int b = 0; b < nyl; ++b)
-                for (int a = 0; a < nxl; ++a) {
-                    const int nt = (lz[c] * g.nty + ly[b]) * g.ntx + lx[a];
-                    const int lo = offsets[nt], len = offsets[nt + 1] - lo;
-                    if (len > 0) {
-                        rng_lo[nr] = lo;
-                        rng_len[nr] = len;
-                        rng_pre[nr] = pre;
-                        pre += len;
-                        ++nr;
-                    }
-                }
+        for (int d = 0; d < 27; ++d) {
+            const int len = nb_len[d];
+            if (len > 0) {
+                rng_lo[nr] = nb_lo[d];
+                rng_len[nr] = len;
+                rng_pre[nr] = pre;
+                pre += len;
+                ++nr;
+            }
+        }
         rng_pre[nr] = pre;
         nrng = nr;
     }
@@ -421,22 +427,65 @@ void launch_gmres_start(hipStream_t st, const double* b, const double* w, int ha
 
 // Arnoldi step k with modified Gram-Schmidt: V_{k+1} holds G v_k on entry.
 // H is (m+1) x m row-major; Givens rotations (cs, sn) update g.
+// Elements of an N-vector a work-group thread keeps in registers during the
+// modified Gram-Schmidt sweep (N <= kArnoldiRegs * kFinBlock).
+constexpr int kArnoldiRegs = 12;
+
 __global__ void __launch_bounds__(kFinBlock) k_gmres_arnoldi(double* V, double* H, double* cs, double* sn,
                                                              double* gvec, int N, int k, int m, GmresScalars* gs) {
     double* w = V + (size_t)(k + 1) * N;
-    for (int j = 0; j <= k; ++j) {
-        const double* vj = V + (size_t)j * N;
+    double hk1;
+    if (N <= kArnoldiRegs * (int)blockDim.x) {
+        // w stays in registers (the same sums, in the same order, as the
+        // streaming form below)
+        double wr[kArnoldiRegs];
+#pragma unroll
+        for (int c = 0; c < kArnoldiRegs; ++c) {
+            const int i = threadIdx.x + c * blockDim.x;
+            wr[c] = i < N ? w[i] : 0.0;
+        }
+        for (int j = 0; j <= k; ++j) {
+            const double* vj = V + (size_t)j * N;
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < kArnoldiRegs; ++c) {
+                const int i = threadIdx.x + c * blockDim.x;
+                if (i < N) s += wr[c] * vj[i];
+            }
+            const double hj = wg_sum(s);
+#pragma unroll
+            for (int c = 0; c < kArnoldiRegs; ++c) {
+                const int i = threadIdx.x + c * blockDim.x;
+                if (i < N) wr[c] -= hj * vj[i];  // v_j again from cache
+            }
+            if (threadIdx.x == 0) H[j * m + k] = hj;
+        }
         double s = 0.0;
-        for (int i = threadIdx.x; i < N; i += blockDim.x) s += w[i] * vj[i];
-        const double hj = wg_sum(s);
-        for (int i = threadIdx.x; i < N; i += blockDim.x) w[i] -= hj * vj[i];
-        if (threadIdx.x == 0) H[j * m + k] = hj;
+#pragma unroll
+        for (int c = 0; c < kArnoldiRegs; ++c)
+            if (threadIdx.x + c * blockDim.x < N) s += wr[c] * wr[c];
+        hk1 = sqrt(wg_sum(s));
+        const double inv = hk1 > 0.0 ? 1.0 / hk1 : 0.0;
+#pragma unroll
+        for (int c = 0; c < kArnoldiRegs; ++c) {
+            const int i = threadIdx.x + c * blockDim.x;
+            if (i < N) w[i] = wr[c] * inv;
+        }
+    } else {
+        for (int j = 0; j <= k; ++j) {
+            const double* vj = V + (size_t)j * N;
+            double s = 0.0;
+            for (int i = threadIdx.x; i < N; i += blockDim.x) s += w[i] * vj[i];
+            const double hj = wg_sum(s);
+            for (int i = threadIdx.x; i < N; i += blockDim.x) w[i] -= hj * vj[i];
+            if (threadIdx.x == 0) H[j * m + k] = hj;
+        }
+        double s = 0.0;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) s += w[i] * w[i];
+        hk1 = sqrt(wg_sum(s));
+        const double inv = hk1 > 0.0 ? 1.0 / hk1 : 0.0;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) w[i] *= inv;
     }
-    double s = 0.0;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) s += w[i] * w[i];
-    const double hk1 = sqrt(wg_sum(s));
-    const double inv = hk1 > 0.0 ? 1.0 / hk1 : 0.0;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) w[i] *= inv;
     if (threadIdx.x == 0) {
         H[(k + 1) * m + k] = hk1;
         for (int j = 0; j < k; ++j) {

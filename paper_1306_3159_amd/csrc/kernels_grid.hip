@@ -175,13 +175,14 @@ __device__ __forceinline__ void update2_enter_body(double* __restrict__ x, doubl
                                                    const double* __restrict__ p, const double* __restrict__ q,
                                                    T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ u0, int nx,
                                                    int ny, unsigned npair, double inv_diag, double a, double m,
-                                                   double* part, Blk blk) {
+                                                   bool fresh, double* part, Blk blk) {
     unsigned lo, hi;
     chunk_of(xcd_block(blk.b, blk.nb), blk.nb, npair, &lo, &hi);
     double v[2] = {0.0, 0.0};
     const int hx = nx >> 1;
     for (unsigned k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-        double2_t xv = reinterpret_cast<double2_t*>(x)[k];
+        // fresh: x starts at zero and is not read (the first step of a zero-start run)
+        double2_t xv = fresh ? double2_t{0.0, 0.0} : reinterpret_cast<double2_t*>(x)[k];
         double2_t rv = reinterpret_cast<double2_t*>(r)[k];
         const double2_t pv = reinterpret_cast<const double2_t*>(p)[k];
         const double2_t qv = reinterpret_cast<const double2_t*>(q)[k];
@@ -211,8 +212,8 @@ __global__ void __launch_bounds__(kBlock) k_update2_enter(double* __restrict__ x
                                                           int nx, int ny, unsigned npair, double inv_diag,
                                                           double* part, const Scalars* sc) {
     if (sc->done) return;
-    update2_enter_body<T>(x, r, p, q, f0, f1, u0, nx, ny, npair, inv_diag, sc->alpha, sc->mean_next, part,
-                          Blk{blockIdx.x, gridDim.x});
+    update2_enter_body<T>(x, r, p, q, f0, f1, u0, nx, ny, npair, inv_diag, sc->alpha, sc->mean_next,
+                          sc->xzero && sc->iters == 0, part, Blk{blockIdx.x, gridDim.x});
 }
 
 template <typename T>
@@ -224,7 +225,8 @@ __global__ void __launch_bounds__(kBlock) kb_update2_enter(const InstDev* inst, 
         if (!I) continue;
         update2_enter_body<T>(I->x, I->r, I->p, I->q, static_cast<T*>(I->lv[0][2]), static_cast<T*>(I->lv[0][3]),
                               static_cast<T*>(I->lv[0][0]), I->nx, I->ny, (unsigned)(I->nx / 2) * I->ny * I->nz,
-                              1.0 / I->ldiag[0], I->sc->alpha, I->sc->mean_next, I->part, blk);
+                              1.0 / I->ldiag[0], I->sc->alpha, I->sc->mean_next,
+                              I->sc->xzero && I->sc->iters == 0, I->part, blk);
         __syncthreads();  // partial-sum scratch is reused by the next virtual block
     }
 }
@@ -314,6 +316,28 @@ __global__ void __launch_bounds__(kBlock) k_residual64(const double* __restrict_
         v[2] += gv * gv;
     }
     block_partials<3>(v, part, gridDim.x, blockIdx.x);
+}
+
+// The partials of launch_residual_from_q(g, null, r) when r already holds g:
+// (g.g, sum g, g.g), same chunks and order.
+__global__ void __launch_bounds__(kBlock) k_self_partials(const double* __restrict__ g, unsigned n, double* part) {
+    unsigned lo, hi;
+    chunk_of(xcd_block(blockIdx.x, gridDim.x), gridDim.x, n, &lo, &hi);
+    double v[3] = {0.0, 0.0, 0.0};
+    for (unsigned idx = lo + threadIdx.x; idx < hi; idx += blockDim.x) {
+        const double gv = g[idx];
+        const double rv = gv - 0.0;
+        v[0] += rv * rv;
+        v[1] += rv;
+        v[2] += gv * gv;
+    }
+    block_partials<3>(v, part, gridDim.x, blockIdx.x);
+}
+
+void launch_self_partials(hipStream_t st, const double* g, size_t n, double* part, unsigned* np) {
+    const unsigned nb = red_blocks(n);
+    hipLaunchKernelGGL(k_self_partials, dim3(nb), dim3(kBlock), 0, st, g, (unsigned)n, part);
+    *np = nb;
 }
 
 void launch_residual_from_q(hipStream_t st, const double* g, const double* q0, double* r, size_t n, double* part,

@@ -12,6 +12,8 @@ void launch_applyA(hipStream_t st, const double* p, double* q, double alpha, dou
 // y = alpha x - D L x (no partials, no guard)
 void launch_applyA_plain(hipStream_t st, const double* x, double* y, double alpha, double s, int nx, int ny,
                          int nz);
+// partials (g.g, sum g, g.g) of a residual that already holds g
+void launch_self_partials(hipStream_t st, const double* g, size_t n, double* part, unsigned* nparts_out);
 // r = g - q0 (q0 may be null: r = g); partials (r.r, sum r, g.g)
 void launch_residual_from_q(hipStream_t st, const double* g, const double* q0, double* r, size_t n, double* part,
                             unsigned* nparts_out);
