@@ -127,6 +127,21 @@ int blob_rd_solve_absorbing(blob_rd_t h, double alpha, const double* f, double* 
  * c: c^n on entry, c^{n+1} on exit (warm-started from c^n). */
 int blob_rd_step(blob_rd_t h, double dt, const double* f, double* c, blob_rd_stats* stats);
 
+/* One backward-Euler step of a diffusion-limited (absorbing) suspension:
+ * eq. c_np1 without the reaction term, with the blob sinks fixed by the
+ * constraint of eq. saddle_point at finite dt (Sec. III.C, A = I/dt - D L
+ * invertible, no null space):
+ *   (I/dt - D L) c^{n+1} + S lambda = c^n/dt + f,   J c^{n+1} = 0.
+ * Solved like blob_rd_solve_absorbing with alpha = 1/dt (Schur GMRES on
+ * J A^{-1} S, eqs. c_exact and r_schur). c: c^n on entry, c^{n+1} on exit.
+ * lambda: N sink strengths, written on exit; with warm != 0 its entry values
+ * (say the previous step's multipliers) are GMRES's initial guess, with
+ * warm = 0 they are ignored and GMRES starts from zero. stats->rel_resid is
+ * measured against g = c^n/dt + f. Errors: EINVAL (null pointer, dt not
+ * positive and finite, N = 0), ENOTCONV, ENUMERIC, EDEVICE. */
+int blob_rd_step_absorbing(blob_rd_t h, double dt, const double* f, double* c, double* lambda, int warm,
+                           blob_rd_stats* stats);
+
 /* Message for the last failure on the calling thread (never NULL). */
 const char* blob_rd_last_error(blob_rd_t h);
 

@@ -298,6 +298,14 @@ def step(c_old, f, q, kappa, dt, D=1.0, h=1.0, w=4, G=None):
     return solve_reactive(f + c_old / dt, q, kappa, 1.0 / dt, D, h, w, G)[0]
 
 
+def step_absorbing(c_old, f, q, dt, D=1.0, h=1.0, w=4, G=None):
+    """One backward-Euler step of a diffusion-limited suspension (eq. c_np1 without the
+    reaction term; the sinks are the multipliers of eq. saddle_point with A = I/dt - D L,
+    the finite-dt case of Sec. III.C, so A is invertible):
+    [A, S; J, 0][c^{n+1}; lam] = [c^n/dt + f; 0]. Returns (c^{n+1}, lam)."""
+    return solve_absorbing(f + c_old / dt, q, 1.0 / dt, D, h, w, G=G)
+
+
 # ---------------------------------------------------------------------------
 # Residuals (the paper does not define one; unweighted 2-norms).
 # ---------------------------------------------------------------------------

@@ -226,6 +226,13 @@ def solve_absorbing(f, q, alpha, D=1.0, h=1.0, w=4, rtol=1e-10, inner_rtol=1e-12
                         rel_resid=st.rel_resid)
 
 
+def step_absorbing(c, f, q, dt, D=1.0, h=1.0, w=4, rtol=1e-10, inner_rtol=1e-12, restart=30, maxit=1000):
+    """Backward-Euler step of an absorbing suspension: the saddle solve with alpha = 1/dt and
+    right-hand side c^n/dt + f (eqs. c_np1, saddle_point). Returns (c^{n+1}, lam, stats)."""
+    g = np.asarray(f, dtype=np.float64) + np.asarray(c, dtype=np.float64) / dt
+    return solve_absorbing(g, q, 1.0 / dt, D, h, w, rtol, inner_rtol, restart, maxit)
+
+
 def num_threads() -> int:
     return int(lib().ora_num_threads())
 

@@ -90,7 +90,7 @@ struct Plan {
     size_t esz = 8;
     int N = 0, restart = 30, ntiles = 0;
     BlobGeom geom{};
-    size_t off_grid[8]{};
+    size_t off_grid[9]{};
     size_t off_lvl[kMaxLevels][5]{};
     size_t off_cinv[4]{};
     size_t off_part = 0, part_cap = 0;
@@ -169,7 +169,7 @@ int make_plan(const blob_rd_params* p, Plan* P, std::string* why) {
         o = align_up(o + bytes);
         return r;
     };
-    for (int i = 0; i < 8; ++i) P->off_grid[i] = take(ncell * 8);
+    for (int i = 0; i < 9; ++i) P->off_grid[i] = take(ncell * 8);
     for (int l = 0; l < P->nlev - 1; ++l) {
         const size_t half = (size_t)P->lev[l].hx * P->lev[l].ny * P->lev[l].nz;
         // u0, u1, f0, f1 and the red residual r0 (the black residual is never stored)
@@ -338,7 +338,8 @@ struct blob_rd {
 
 namespace {
 
-enum GridBuf { G_R = 0, G_P = 1, G_Q = 2, G_U = 3, G_G = 4, G_T1 = 5, G_T2 = 6, G_P2 = 7 };
+// G_S holds the right-hand side of an absorbing time step for the whole solve
+enum GridBuf { G_R = 0, G_P = 1, G_Q = 2, G_U = 3, G_G = 4, G_T1 = 5, G_T2 = 6, G_P2 = 7, G_S = 8 };
 
 __global__ void k_sc_init(Scalars* sc, int project, double inv_ncell, double eBe_inv, double rtol2, double abs2,
                           int xzero) {
@@ -856,7 +857,7 @@ struct SaddleInfo {
 // Solve [A, S; J, 0][c; lam] = [g; phi] (phi may be null = 0) with Schur GMRES.
 template <typename T>
 SaddleInfo saddle_solve(blob_rd* H, double alpha, const double* g, const double* phi, double* c, double* lam,
-                        double atol_schur, double final_rtol_abs, double inner_rtol) {
+                        double atol_schur, double final_rtol_abs, double inner_rtol, const double* lam0 = nullptr) {
     const Plan& P = H->P;
     hipStream_t st = H->st;
     const int N = P.N;
@@ -890,12 +891,18 @@ SaddleInfo saddle_solve(blob_rd* H, double alpha, const double* g, const double*
     // GMRES(m) with MGS on the (projected) Schur system G lt = b
     double* lt = H->nv(4);
     double* w = H->nv(5);
-    launch_nvec_copy_scale(st, nullptr, lt, N, 0.0, 0.0);
+    // initial multiplier: zero, or lam0 - lbar (a previous time step's multipliers)
+    if (lam0) {
+        launch_nvec_copy_scale(st, lam0, lt, N, 1.0, -lbar);
+        if (alpha == 0.0) launch_nvec_project(st, lt, N);
+    } else {
+        launch_nvec_copy_scale(st, nullptr, lt, N, 0.0, 0.0);
+    }
     const int m = P.restart;
     double* V = H->at<double>(P.off_V);
     double* Hm = H->at<double>(P.off_H);
     const int maxit = default_maxit(H);
-    bool first = true;
+    bool first = lam0 == nullptr;
     bool use_w = false;
     if (H->prm.schur_precond == BLOB_RD_PRECOND_LEARNED && alpha == 0.0) {
         if (H->lrn.ready && !H->lrn.bad) use_w = true;
@@ -1016,7 +1023,8 @@ void saddle_residual(blob_rd* H, double alpha, const double* g, const double* ph
 }
 
 template <typename T>
-int absorbing_solve(blob_rd* H, double alpha, const double* f, double* c, double* lam, blob_rd_stats* stt) {
+int absorbing_solve(blob_rd* H, double alpha, const double* f, double* c, double* lam, blob_rd_stats* stt,
+                    const double* lam0 = nullptr) {
     const Plan& P = H->P;
     const double rtol = H->prm.rtol > 0.0 ? H->prm.rtol : 1e-8;
     // |f| sets the scale of the saddle residual
@@ -1027,7 +1035,7 @@ int absorbing_solve(blob_rd* H, double alpha, const double* f, double* c, double
     double fn = std::sqrt(H->hbuf[1]);
     if (fn == 0.0) fn = 1.0;
     const double inner_rtol = std::min(1e-2, 0.05 * rtol);
-    SaddleInfo si = saddle_solve<T>(H, alpha, f, nullptr, c, lam, 0.4 * rtol * fn, 0.4 * rtol * fn, inner_rtol);
+    SaddleInfo si = saddle_solve<T>(H, alpha, f, nullptr, c, lam, 0.4 * rtol * fn, 0.4 * rtol * fn, inner_rtol, lam0);
     int gm = si.gmres_iters;
     double r1, r2, gsq;
     double* t = H->grid(G_T1);
@@ -1258,6 +1266,26 @@ int blob_rd_step(blob_rd_t H, double dt, const double* f, double* c, blob_rd_sta
         H->alg_bytes += (double)H->P.ncell * 24;
         int rc = H->P.esz == 4 ? reactive_solve<float>(H, 1.0 / dt, g, c, stt)
                                : reactive_solve<double>(H, 1.0 / dt, g, c, stt);
+        HIPCHK(hipGetLastError());
+        return rc;
+    });
+}
+
+int blob_rd_step_absorbing(blob_rd_t H, double dt, const double* f, double* c, double* lambda, int warm,
+                           blob_rd_stats* stt) {
+    if (!H || !f || !c || !lambda) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (H->P.N <= 0) return g_last_error = "absorbing step needs at least one blob", BLOB_RD_EINVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return g_last_error = "dt must be positive", BLOB_RD_EINVAL;
+    return guarded(H, stt, [&]() {
+        // g = c^n/dt + f in its own buffer: c is overwritten by c^{n+1}, and the
+        // saddle residual and refinement read g after that
+        double* g = H->grid(G_S);
+        hipLaunchKernelGGL(k_step_rhs, dim3(nblocks(H->P.ncell)), dim3(kBlock), 0, H->st, f, c, g,
+                           (unsigned)H->P.ncell, 1.0 / dt);
+        H->alg_bytes += (double)H->P.ncell * 24;
+        const double* lam0 = warm ? lambda : nullptr;
+        int rc = H->P.esz == 4 ? absorbing_solve<float>(H, 1.0 / dt, g, c, lambda, stt, lam0)
+                               : absorbing_solve<double>(H, 1.0 / dt, g, c, lambda, stt, lam0);
         HIPCHK(hipGetLastError());
         return rc;
     });

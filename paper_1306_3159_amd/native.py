@@ -89,6 +89,8 @@ def load_library(path: str = LIB_PATH):
     L.blob_rd_solve_absorbing.restype = i32
     L.blob_rd_step.argtypes = [vp, d, vp, vp, S]
     L.blob_rd_step.restype = i32
+    L.blob_rd_step_absorbing.argtypes = [vp, d, vp, vp, vp, i32, S]
+    L.blob_rd_step_absorbing.restype = i32
     L.blob_rd_interp.argtypes = [vp, vp, vp]
     L.blob_rd_interp.restype = i32
     L.blob_rd_spread.argtypes = [vp, vp, vp]
@@ -278,6 +280,9 @@ class BlobRD:
     def _grid(self, t, name):
         return _dev_f64(t, self.shape, name)
 
+    def _nvec(self, t, name):
+        return _dev_f64(t, (self.N,), name)
+
     def _new_grid(self):
         return torch.zeros(self.shape, dtype=torch.float64, device=self.device)
 
@@ -296,7 +301,7 @@ class BlobRD:
         """[alpha I - D L, S; J, 0][c; lam] = [f; 0]."""
         self._grid(f, "f")
         c = self._new_grid() if c is None else self._grid(c, "c")
-        lam = torch.zeros(self.N, dtype=torch.float64, device=self.device) if lam is None else lam
+        lam = torch.zeros(self.N, dtype=torch.float64, device=self.device) if lam is None else self._nvec(lam, "lam")
         st = Stats()
         rc = self._lib.blob_rd_solve_absorbing(self._h, float(alpha), _ptr(f), _ptr(c), _ptr(lam), ctypes.byref(st))
         return c, lam, self._check(rc, st)
@@ -307,6 +312,18 @@ class BlobRD:
         self._grid(c, "c")
         st = Stats()
         rc = self._lib.blob_rd_step(self._h, float(dt), _ptr(f), _ptr(c), ctypes.byref(st))
+        return self._check(rc, st)
+
+    def step_absorbing(self, f: torch.Tensor, c: torch.Tensor, lam: torch.Tensor, dt: float, warm: bool = True
+                       ) -> dict:
+        """One backward-Euler step of an absorbing suspension; c holds c^n on entry and c^{n+1}
+        on exit, lam the sink strengths (with warm, its entry values start GMRES)."""
+        self._grid(f, "f")
+        self._grid(c, "c")
+        self._nvec(lam, "lam")
+        st = Stats()
+        rc = self._lib.blob_rd_step_absorbing(self._h, float(dt), _ptr(f), _ptr(c), _ptr(lam), int(bool(warm)),
+                                              ctypes.byref(st))
         return self._check(rc, st)
 
     # -- operators --------------------------------------------------------------

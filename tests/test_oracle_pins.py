@@ -488,6 +488,72 @@ def test_iterative_step_matches_exact():
     assert np.linalg.norm(c - ce) / np.linalg.norm(ce) < 1e-10
 
 
+def test_absorbing_step_matches_dense():
+    """eq. c_np1 with the sinks of eq. saddle_point at finite dt: the block system
+    [I/dt - D L, S; J, 0][c1; lam] = [c0/dt + f; 0] assembled densely and solved by LAPACK."""
+    rng = np.random.default_rng(23)
+    n, h, D, dt = 8, 0.9, 1.3, 0.4
+    shape = (n, n, n)
+    q = W.rsa_positions(rng, n * h, 3, 2.5 * h)
+    f = 1.0 + 0.5 * rng.standard_normal(shape)
+    c0 = rng.standard_normal(shape)
+    Jd = ex.dense_J(q, shape, h)
+    A = np.eye(n ** 3) / dt - D * ex.dense_laplacian(shape, h)
+    M = np.block([[A, Jd.T / h ** 3], [Jd, np.zeros((3, 3))]])
+    ref = np.linalg.solve(M, np.concatenate([(c0 / dt + f).ravel(), np.zeros(3)]))
+    c1, lam = ex.step_absorbing(c0, f, q, dt, D, h)
+    assert np.max(np.abs(c1.ravel() - ref[:-3])) < 1e-10 * np.max(np.abs(ref[:-3]))
+    assert np.max(np.abs(lam - ref[-3:])) < 1e-10 * np.max(np.abs(ref[-3:]))
+
+
+def test_absorbing_step_mass_balance_and_constraint():
+    """Summing the first equation over the periodic grid (L sums to zero, h^3 S sums to the
+    multipliers): h^3 sum(c1 - c0)/dt = h^3 sum(f) - sum(lam); and J c1 = 0."""
+    rng = np.random.default_rng(24)
+    n, h, dt = 16, 0.8, 0.3
+    q = W.rsa_positions(rng, n * h, 7, 2.5 * h)
+    f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
+    c0 = 2.0 + rng.standard_normal((n, n, n))
+    c1, lam = ex.step_absorbing(c0, f, q, dt, h=h)
+    lhs = h ** 3 * np.sum(c1 - c0) / dt
+    assert lhs == pytest.approx(h ** 3 * f.sum() - lam.sum(), rel=1e-11, abs=1e-11 * h ** 3 * np.abs(f).sum())
+    assert np.max(np.abs(ex.interp(c1, q, h))) < 1e-11 * np.max(np.abs(c1))
+
+
+def test_absorbing_steps_reach_steady_state():
+    """Backward-Euler steps with a constant source converge to the steady saddle solution, which
+    the oracle reaches by another route (A singular, Appendix A's bordered system): every
+    non-steady mode is damped by 1/(1 + dt mu) per step."""
+    rng = np.random.default_rng(25)
+    n, dt = 16, 1e4
+    shape = (n, n, n)
+    q = W.rsa_positions(rng, n, 4, 3.0)
+    f = 1.0 + 0.5 * rng.standard_normal(shape)
+    cs, ls = ex.solve_absorbing(f, q, 0.0)
+    G = ex.schur_matrix(q, shape, 1.0 / dt)
+    c = np.zeros(shape)
+    for _ in range(8):
+        c, lam = ex.step_absorbing(c, f, q, dt, G=G)
+    assert np.linalg.norm(c - cs) / np.linalg.norm(cs) < 1e-9
+    assert np.linalg.norm(lam - ls) / np.linalg.norm(ls) < 1e-9
+
+
+def test_iterative_step_absorbing_matches_exact():
+    """The C oracle's absorbing step (GMRES on the Schur complement, MG-CG inner solves)."""
+    rng = np.random.default_rng(26)
+    n = 16
+    q = W.rsa_positions(rng, n, 6, 3.0)
+    f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
+    c = np.zeros((n, n, n))
+    ce = np.zeros((n, n, n))
+    for _ in range(2):
+        c, lam, st = it.step_absorbing(c, f, q, 0.5, rtol=1e-11)
+        assert st["rc"] == 0
+        ce, le = ex.step_absorbing(ce, f, q, 0.5)
+    assert np.linalg.norm(c - ce) / np.linalg.norm(ce) < 1e-9
+    assert np.linalg.norm(lam - le) / np.linalg.norm(le) < 1e-9
+
+
 def test_schur_matrix_far_field():
     """Sec. III.C: M_ij ~ 1/(4 pi D r) for h << r << L (monopole form); loose, periodic box."""
     n = 64
