@@ -161,6 +161,77 @@ int blob_rd_apply(blob_rd_t h, double alpha, int with_blobs, const double* x, do
  * mean projection is applied. */
 int blob_rd_vcycle(blob_rd_t h, double alpha, const double* r, double* z);
 
+/* ---- The paper's own saddle-point solver ----
+ *
+ * Sec. III.E (diffusion-limited case) and the appendix on preconditioning the
+ * saddle-point solver: a Krylov method on the whole block system
+ *   [alpha I - D L, S; J, 0] [c; lambda] = [f; 0]
+ * (eq. saddle_point with zeta = 1), preconditioned by an approximate solve of
+ * the same system through the Schur complement M = J A^{-1} S (eqs. c_exact,
+ * r_schur). One preconditioner application on [vg; vf]:
+ *   1. c* = n multigrid cycles on A c = vg - lbar S 1 (zero initial guess);
+ *   2. lam~ from J c* - vf: the diagonal variant scales it by D/gamma
+ *      (eq. Schur_diagonal, gamma = 1/(4 pi a0)); the approximate-Schur
+ *      variant runs m GMRES iterations (modified Gram-Schmidt, zero guess) on
+ *      (J A1^{-1} S) lam~ = J c* - vf, A1^{-1} one multigrid cycle (eq.
+ *      approx_Schur); the learned variant runs the same iterations on
+ *      (J A1^{-1} S P W P) y = J c* - vf and takes lam~ = P W P y, W the
+ *      learned sparse approximation of the inverse Schur complement (below);
+ *   3. c = c* + n cycles of the stationary iteration on A c = vg - lbar S 1 -
+ *      S lam~, started at c*;
+ *   4.-5. for alpha = 0 only (A singular on the periodic grid): lbar =
+ *      h^3 sum(vg) / N, the blob mean projected out of J c* - vf, of every
+ *      inner product and of lam~, c shifted by the blob mean of vf - J c, and
+ *      lambda = lam~ + lbar; for alpha > 0 lbar = 0 and these steps are skipped.
+ * The multigrid cycles are the handle's V(2,2) cycles in its precision. The
+ * outer solver is flexible GMRES (right preconditioned, the preconditioned
+ * directions kept, restarted, modified Gram-Schmidt) on the concatenated
+ * [grid; blob] vectors with unweighted 2-norms, from a zero initial guess; it
+ * stops when the true FP64 residual |b - K x| recomputed at a restart is
+ * <= rtol |b|. */
+#define BLOB_RD_SADDLE_DIAGONAL 0     /* lam~ = (D/gamma)(J c* - vf) */
+#define BLOB_RD_SADDLE_APPROX_SCHUR 1 /* m inner GMRES iterations, one cycle per product */
+#define BLOB_RD_SADDLE_LEARNED 2      /* approximate-Schur variant whose inner GMRES is right-
+                                         preconditioned by the handle's learned W (alpha = 0; otherwise,
+                                         or without a built W, the plain variant, stats->fallback = 1) */
+
+typedef struct {
+    int32_t precond; /* BLOB_RD_SADDLE_* */
+    int32_t m;       /* inner GMRES iterations of the approximate-Schur variant; 0 = 5; <= gmres_restart */
+    int32_t n;       /* multigrid cycles per approximate Poisson solve; 0 = 1; <= 64 */
+    int32_t restart; /* FGMRES restart length; 0 = 30; <= 1024 */
+    int32_t maxit;   /* total FGMRES iterations; 0 = 1000 */
+    double rtol;     /* relative residual target; 0 = the handle's rtol */
+    double diag;     /* D/gamma of the diagonal variant; 0 = 4 pi a0 D with a0 = 1.255 h (Sec. IV.A) */
+} blob_rd_saddle_opts;
+
+/* Device bytes of the caller's FGMRES workspace for this handle and restart
+ * length (0 = 30): 2 restart + 1 long vectors of ncell + N doubles, the
+ * Hessenberg matrix and rotations. 0 if h is NULL or restart > 1024. */
+size_t blob_rd_fgmres_workspace_bytes(blob_rd_t h, int restart);
+
+/* Solve the absorbing saddle point with the solver above (opts NULL = the
+ * approximate-Schur variant with m = 5, n = 1, restart 30). c (grid) and
+ * lambda (N) are outputs. workspace: device memory, 256-byte aligned, at least
+ * blob_rd_fgmres_workspace_bytes(h, restart) bytes, caller-owned; its contents
+ * are overwritten. Grid scratch comes from the handle's workspace. stats:
+ * outer_iters = FGMRES iterations, inner_iters_total = inner GMRES iterations,
+ * vcycles = multigrid cycles (the paper's cost measure), refinements = restarts,
+ * rel_resid = the true FP64 relative residual. Errors: EINVAL (null pointer,
+ * N = 0, alpha < 0, bad options, misaligned workspace), ENOMEM (workspace too
+ * small), ENOTCONV (maxit reached), ENUMERIC, EDEVICE. */
+int blob_rd_solve_absorbing_fgmres(blob_rd_t h, double alpha, const blob_rd_saddle_opts* opts, const double* f,
+                                   double* c, double* lambda, void* workspace, size_t workspace_bytes,
+                                   blob_rd_stats* stats);
+
+/* One application of the preconditioner above: [zg; zl] ~ K^{-1} [vg; vf]
+ * (grid vectors of ncell doubles, blob vectors of N doubles, device pointers;
+ * vg, vf are not modified and must not alias zg, zl). Synchronises the
+ * handle's stream. Errors: EINVAL (null pointer, N = 0, alpha < 0, bad
+ * options), EDEVICE. */
+int blob_rd_saddle_precond(blob_rd_t h, double alpha, const blob_rd_saddle_opts* opts, const double* vg,
+                           const double* vf, double* zg, double* zl);
+
 /* ---- Learned Schur preconditioner ----
  *
  * The paper preconditions the Schur complement M = J A^+ S with the diagonal

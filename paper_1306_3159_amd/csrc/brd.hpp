@@ -62,6 +62,9 @@ struct GmresScalars {
     int32_t status;
 };
 
+// Longest restart of the flexible GMRES on the block saddle system.
+constexpr int kFgMaxRestart = 1024;
+
 // Levels handled by the single-work-group coarse tail (index 0 = first tail
 // level, last = coarsest). LDS byte offsets of u, f, r per level.
 struct TailDesc {

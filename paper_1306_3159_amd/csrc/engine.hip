@@ -2559,3 +2559,318 @@ int blob_rd_solve_batched(blob_rd_t* hs, int32_t n, const int32_t* kind, double 
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// The paper's own solver for the absorbing saddle point (Sec. III.E,
+// diffusion-limited case; appendix on preconditioning the saddle-point
+// solver): flexible GMRES on the whole block system [A, S; J, 0] with the
+// diagonal or the approximate-Schur-complement preconditioner.
+// ===========================================================================
+namespace {
+
+struct FgOpts {
+    int kind = BLOB_RD_SADDLE_APPROX_SCHUR;
+    int m = 5, n = 1, restart = 30, maxit = 1000;
+    double rtol = 1e-8, diag = 0.0;
+};
+
+// averaged reactive radius of a four-point blob in units of h (Sec. IV.A)
+constexpr double kA0OverH = 1.255;
+
+FgOpts fg_opts(const blob_rd* H, const blob_rd_saddle_opts* o) {
+    FgOpts r;
+    r.rtol = H->prm.rtol > 0.0 ? H->prm.rtol : 1e-8;
+    if (o) {
+        r.kind = o->precond;
+        if (o->m > 0) r.m = o->m;
+        if (o->n > 0) r.n = o->n;
+        if (o->restart > 0) r.restart = o->restart;
+        if (o->maxit > 0) r.maxit = o->maxit;
+        if (o->rtol > 0.0) r.rtol = o->rtol;
+        r.diag = o->diag;
+        if (o->m < 0 || o->n < 0 || o->restart < 0 || o->maxit < 0 || !(o->rtol >= 0.0) || !(o->diag >= 0.0) ||
+            !std::isfinite(o->diag) || !std::isfinite(o->rtol))
+            throw Err(BLOB_RD_EINVAL, "saddle solver options must be non-negative and finite");
+    }
+    if (r.kind != BLOB_RD_SADDLE_DIAGONAL && r.kind != BLOB_RD_SADDLE_APPROX_SCHUR &&
+        r.kind != BLOB_RD_SADDLE_LEARNED)
+        throw Err(BLOB_RD_EINVAL, "unknown saddle preconditioner");
+    if (r.m > H->P.restart)
+        throw Err(BLOB_RD_EINVAL, "inner Krylov iterations exceed the handle's GMRES restart length");
+    if (r.n > 64) throw Err(BLOB_RD_EINVAL, "at most 64 multigrid cycles per approximate solve");
+    if (r.restart > kFgMaxRestart) throw Err(BLOB_RD_EINVAL, "FGMRES restart length above 1024");
+    if (r.diag == 0.0) r.diag = 4.0 * M_PI * kA0OverH * H->prm.h * H->prm.D;
+    return r;
+}
+
+// doubles between consecutive long vectors (grid part, blob part, padding)
+size_t fg_stride(const Plan& P) { return (P.ncell + (size_t)P.N + 31) & ~(size_t)31; }
+
+size_t fg_bytes(const Plan& P, int restart) {
+    const size_t ld = (size_t)restart + 1;
+    return (2 * (size_t)restart + 1) * fg_stride(P) * 8 + (ld * restart + 4 * ld + 8) * 8 + 256;
+}
+
+// n multigrid cycles for A x = rhs as a stationary iteration: from a zero guess
+// the first cycle is x = V rhs, every further cycle (all of them when x holds a
+// guess) adds V (rhs - A x).
+template <typename T>
+void fg_cycles(blob_rd* H, double alpha, const double* rhs, double* x, bool from_zero, int n, const double* cinv) {
+    const Plan& P = H->P;
+    const LevelDims& d = P.lev[0];
+    const double s = H->prm.D / (d.h * d.h);
+    T* z0 = H->at<T>(P.off_lvl[0][0]);
+    T* z1 = H->at<T>(P.off_lvl[0][1]);
+    double* q = H->grid(G_Q);
+    for (int k = 0; k < n; ++k) {
+        if (k == 0 && from_zero) {
+            vcycle<T>(H, alpha, rhs, nullptr, cinv);
+            launch_split_to_nat<T>(H->st, z0, z1, x, d.nx, d.ny, d.nz, 0.0);
+            H->alg_bytes += (double)P.ncell * (P.esz + 8);
+        } else {
+            launch_applyA_plain(H->st, x, q, alpha, s, d.nx, d.ny, d.nz);
+            launch_axpby(H->st, q, rhs, P.ncell, -1.0, 1.0);
+            vcycle<T>(H, alpha, q, nullptr, cinv);
+            launch_split_to_nat<T>(H->st, z0, z1, x, d.nx, d.ny, d.nz, 1.0);
+            H->alg_bytes += (double)P.ncell * (16 + 24 + P.esz + 16);
+        }
+    }
+}
+
+void fg_spread(blob_rd* H, const double* lam, const double* base_in, double* out, double scale, int add_only) {
+    const Plan& P = H->P;
+    launch_spread(H->st, lam, 0.0, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
+                  H->at<int>(P.off_offsets), H->at<int>(P.off_perm), base_in, out, scale, add_only, nullptr);
+    H->alg_bytes += (double)P.ncell * (base_in && !add_only ? 16 : 8);
+}
+
+void fg_interp(blob_rd* H, const double* c, double* out) {
+    const Plan& P = H->P;
+    launch_interp(H->st, c, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts), H->at<int>(P.off_perm),
+                  nullptr, nullptr, out, nullptr);
+}
+
+// [yg; yl] = [A, S; J, 0] [xg; xl]
+void fg_apply_K(blob_rd* H, double alpha, const double* xg, const double* xl, double* yg, double* yl) {
+    const Plan& P = H->P;
+    const LevelDims& d = P.lev[0];
+    launch_applyA_plain(H->st, xg, yg, alpha, H->prm.D / (d.h * d.h), d.nx, d.ny, d.nz);
+    H->alg_bytes += (double)P.ncell * 16;
+    fg_spread(H, xl, yg, yg, H->inv_h3(), 1);
+    fg_interp(H, xg, yl);
+}
+
+// One application of the preconditioner to [vg; vf] -> [zg; zl] (steps 1-5 of
+// the appendix). For A = -D L (alpha = 0): the mean multiplier from the total
+// source, the blob-space mean projected out of h~, of each inner product and of
+// lam~ (a constant offset of an approximate concentration only shifts J c by a
+// constant, which that projection removes), and the mean concentration from the
+// constraint. Grid scratch: G_T1 (source minus the mean sink), G_T2, G_Q, G_U.
+template <typename T>
+void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, const double* vf, double* zg,
+                double* zl) {
+    const Plan& P = H->P;
+    hipStream_t st = H->st;
+    const int N = P.N;
+    const double h3 = H->prm.h * H->prm.h * H->prm.h;
+    const double* cinv = select_cinv(H, alpha);
+    const bool sing = alpha == 0.0;
+    double* ds = H->dsc() + 48;  // [0] sum of vg, [8..10] sums of vf - J c
+    // 1. source with the mean sink removed, and the concentration estimate c*
+    const double* g_t = vg;
+    if (sing) {
+        unsigned np = 0;
+        launch_norm_partials(st, vg, P.ncell, H->part(), &np);
+        launch_reduce_parts(st, H->part(), np, 1, ds);
+        H->alg_bytes += (double)P.ncell * 8;
+        double* ml = H->nv(3);
+        launch_nvec_copy_scale(st, nullptr, ml, N, 0.0, 0.0);
+        launch_add_shift(st, ml, N, ds, -h3 / N);  // -lbar on every blob
+        fg_spread(H, ml, vg, H->grid(G_T1), H->inv_h3(), 0);
+        g_t = H->grid(G_T1);
+    }
+    fg_cycles<T>(H, alpha, g_t, zg, true, o.n, cinv);
+    // 2. Schur-complement system for the (fluctuating) multipliers, right side J c* - vf
+    double* hv = H->nv(4);
+    fg_interp(H, zg, hv);
+    launch_axpby(st, hv, vf, N, 1.0, -1.0);
+    if (sing) launch_nvec_project(st, hv, N);
+    // the learned W approximates the inverse of J (-D L)^+ S on mean-zero multipliers:
+    // it right-preconditions the inner GMRES (plain inner GMRES without it)
+    bool learned = false;
+    if (o.kind == BLOB_RD_SADDLE_LEARNED) {
+        learned = sing && H->lrn.ready && !H->lrn.bad;
+        if (!learned) H->fallback = 1;
+    }
+    if (o.kind == BLOB_RD_SADDLE_DIAGONAL) {
+        launch_nvec_copy_scale(st, hv, zl, N, o.diag, 0.0);
+    } else {
+        // m GMRES iterations on (J A1^{-1} S [W]) y = h~ with one cycle per product, lam~ = [W] y
+        double* V = H->at<double>(P.off_V);
+        double* Hm = H->at<double>(P.off_H);
+        double* gv = H->at<double>(P.off_gv);
+        launch_gmres_start(st, hv, nullptr, 0, V, gv, N, H->gs());
+        const LevelDims& d = P.lev[0];
+        T* z0 = H->at<T>(P.off_lvl[0][0]);
+        T* z1 = H->at<T>(P.off_lvl[0][1]);
+        for (int k = 0; k < o.m; ++k) {
+            const double* vk = V + (size_t)k * N;
+            if (learned) {
+                precond_apply(H, vk, H->nv(9));
+                vk = H->nv(9);
+            }
+            fg_spread(H, vk, nullptr, H->grid(G_T2), H->inv_h3(), 0);
+            vcycle<T>(H, alpha, H->grid(G_T2), nullptr, cinv);
+            launch_split_to_nat<T>(st, z0, z1, H->grid(G_U), d.nx, d.ny, d.nz, 0.0);
+            H->alg_bytes += (double)P.ncell * (P.esz + 8);
+            fg_interp(H, H->grid(G_U), V + (size_t)(k + 1) * N);
+            if (sing) launch_nvec_project(st, V + (size_t)(k + 1) * N, N);
+            launch_gmres_arnoldi(st, V, Hm, H->at<double>(P.off_cs), H->at<double>(P.off_sn), gv, N, k, o.m,
+                                 H->gs());
+        }
+        double* y = learned ? H->nv(10) : zl;
+        launch_nvec_copy_scale(st, nullptr, y, N, 0.0, 0.0);
+        launch_gmres_update(st, V, Hm, gv, H->at<double>(P.off_yv), y, N, o.m, o.m);
+        if (learned) precond_apply(H, y, zl);
+        H->inner_iters += o.m;
+    }
+    if (sing) launch_nvec_project(st, zl, N);
+    // 3. corrected concentration from g~ - S lam~, started at c*
+    fg_spread(H, zl, g_t, H->grid(G_T2), -H->inv_h3(), 0);
+    fg_cycles<T>(H, alpha, H->grid(G_T2), zg, false, o.n, cinv);
+    if (sing) {
+        // 4. mean concentration: mean over blobs of vf - J c ; 5. lam = lam~ + lbar
+        double* jv = H->nv(6);
+        fg_interp(H, zg, jv);
+        launch_axpby(st, jv, vf, N, -1.0, 1.0);
+        launch_nvec_sums(st, jv, nullptr, N, ds + 8);
+        launch_add_shift(st, zg, P.ncell, ds + 8, 1.0 / N);
+        launch_add_shift(st, zl, N, ds, h3 / N);
+        H->alg_bytes += (double)P.ncell * 16;
+    }
+}
+
+// Flexible GMRES (right preconditioned, restarted, modified Gram-Schmidt) on
+// [A, S; J, 0][c; lam] = [f; 0] from a zero guess. Every cycle starts from the
+// true FP64 residual b - K x, which also decides convergence at the end.
+template <typename T>
+int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double* c, double* lam, char* ws,
+             blob_rd_stats* stt) {
+    const Plan& P = H->P;
+    hipStream_t st = H->st;
+    const size_t ncell = P.ncell, n = ncell + (size_t)P.N, stride = fg_stride(P);
+    const int m = o.restart, ld = m + 1;
+    double* V = reinterpret_cast<double*>(ws);
+    double* Z = V + (size_t)(m + 1) * stride;
+    double* Hd = Z + (size_t)m * stride;
+    double* cs = Hd + (size_t)ld * m;
+    double* sn = cs + ld;
+    double* gv = sn + ld;
+    double* yv = gv + ld;
+    double* sd = yv + ld;  // [0] beta, [2..3] Givens outputs
+    launch_fill(st, c, ncell, 0.0);
+    launch_fill(st, lam, P.N, 0.0);
+    int its = 0, cycles = 0;
+    double bnorm = -1.0, rel = 0.0;
+    bool sub = false;
+    for (;;) {
+        if (sub) fg_apply_K(H, alpha, c, lam, V, V + ncell);
+        unsigned np = 0;
+        launch_fg_resid(st, V, f, ncell, n, sub ? 1 : 0, H->part(), &np);
+        launch_fg_fin(st, H->part(), np, sd, 1);
+        H->alg_bytes += (double)n * (sub ? 24 : 16);
+        sync_read(H, H->hbuf, sd, 8);
+        const double beta = H->hbuf[0];
+        if (!std::isfinite(beta)) throw Err(BLOB_RD_ENUMERIC, "non-finite FGMRES residual");
+        if (bnorm < 0.0) bnorm = beta > 0.0 ? beta : 1.0;
+        rel = beta / bnorm;
+        if (rel <= o.rtol || its >= o.maxit) break;
+        ++cycles;
+        launch_fg_scale(st, V, sd, n);
+        launch_fg_gstart(st, gv, ld, sd);
+        H->alg_bytes += (double)n * 16;
+        int k = 0;
+        for (int j = 0; j < m && its < o.maxit; ++j) {
+            double* vj = V + (size_t)j * stride;
+            double* zj = Z + (size_t)j * stride;
+            double* w = V + (size_t)(j + 1) * stride;
+            fg_precond<T>(H, alpha, o, vj, vj + ncell, zj, zj + ncell);
+            fg_apply_K(H, alpha, zj, zj + ncell, w, w + ncell);
+            double* col = Hd + (size_t)j * ld;
+            for (int i = 0; i <= j + 1; ++i) {
+                const double* vprev = i > 0 ? V + (size_t)(i - 1) * stride : nullptr;
+                const double* vnext = i <= j ? V + (size_t)i * stride : nullptr;
+                launch_fg_mgs(st, w, vprev, i > 0 ? col + (i - 1) : nullptr, vnext, n, H->part(), &np);
+                launch_fg_fin(st, H->part(), np, col + i, i == j + 1);
+                H->alg_bytes += (double)n * 8 * ((vprev ? 3 : 1) + (vnext ? 1 : 0));
+            }
+            launch_fg_scale(st, w, col + j + 1, n);
+            H->alg_bytes += (double)n * 16;
+            launch_fg_givens(st, Hd, ld, cs, sn, gv, j, sd + 2);
+            sync_read(H, H->hbuf, sd + 2, 16);
+            ++its;
+            k = j + 1;
+            const double res = H->hbuf[0], sub_diag = H->hbuf[1];
+            if (!std::isfinite(res) || !std::isfinite(sub_diag)) throw Err(BLOB_RD_ENUMERIC, "FGMRES breakdown");
+            if (res <= o.rtol * bnorm || sub_diag == 0.0) break;
+        }
+        launch_fg_backsolve(st, Hd, ld, gv, yv, k);
+        launch_fg_update(st, c, Z, stride, 0, ncell, k, yv);
+        launch_fg_update(st, lam, Z, stride, ncell, P.N, k, yv);
+        H->alg_bytes += (double)n * 8 * (k + 2);
+        sub = true;
+    }
+    if (stt) {
+        stt->outer_iters = its;
+        stt->rel_resid = rel;
+        stt->refinements = cycles > 0 ? cycles - 1 : 0;
+    }
+    return rel <= o.rtol ? BLOB_RD_OK : BLOB_RD_ENOTCONV;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t blob_rd_fgmres_workspace_bytes(blob_rd_t H, int restart) {
+    if (!H) return 0;
+    if (restart <= 0) restart = 30;
+    if (restart > kFgMaxRestart) return 0;
+    return fg_bytes(H->P, restart);
+}
+
+int blob_rd_solve_absorbing_fgmres(blob_rd_t H, double alpha, const blob_rd_saddle_opts* opts, const double* f,
+                                   double* c, double* lambda, void* workspace, size_t workspace_bytes,
+                                   blob_rd_stats* stt) {
+    if (!H || !f || !c || !lambda || !workspace) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (H->P.N <= 0) return g_last_error = "absorbing solve needs at least one blob", BLOB_RD_EINVAL;
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return g_last_error = "alpha must be >= 0", BLOB_RD_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return g_last_error = "workspace not 256-byte aligned",
+                                                              BLOB_RD_EINVAL;
+    return guarded(H, stt, [&]() {
+        const FgOpts o = fg_opts(H, opts);
+        if (workspace_bytes < fg_bytes(H->P, o.restart)) throw Err(BLOB_RD_ENOMEM, "FGMRES workspace too small");
+        char* ws = static_cast<char*>(workspace);
+        int rc = H->P.esz == 4 ? fg_solve<float>(H, alpha, o, f, c, lambda, ws, stt)
+                               : fg_solve<double>(H, alpha, o, f, c, lambda, ws, stt);
+        HIPCHK(hipGetLastError());
+        return rc;
+    });
+}
+
+int blob_rd_saddle_precond(blob_rd_t H, double alpha, const blob_rd_saddle_opts* opts, const double* vg,
+                           const double* vf, double* zg, double* zl) {
+    if (!H || !vg || !vf || !zg || !zl) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (H->P.N <= 0) return g_last_error = "the saddle preconditioner needs at least one blob", BLOB_RD_EINVAL;
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return g_last_error = "alpha must be >= 0", BLOB_RD_EINVAL;
+    return guarded(H, nullptr, [&]() {
+        const FgOpts o = fg_opts(H, opts);
+        if (H->P.esz == 4) fg_precond<float>(H, alpha, o, vg, vf, zg, zl);
+        else fg_precond<double>(H, alpha, o, vg, vf, zg, zl);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(H->st));
+        return BLOB_RD_OK;
+    });
+}
+
+}  // extern "C"

@@ -592,4 +592,176 @@ void launch_reduce_parts(hipStream_t st, const double* part, unsigned np, int k,
     hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(kFinBlock), 0, st, part, np, k, out);
 }
 
+// ---------------------------------------------------------------------------
+// Long vectors of the flexible GMRES on the block saddle system: a grid part of
+// ncell values followed by N blob values, n = ncell + N doubles, each vector
+// 16-byte aligned. Two values per thread (16-byte loads), one scalar tail.
+// ---------------------------------------------------------------------------
+
+// One modified Gram-Schmidt pass: w -= (*hprev) vprev when vprev is set, then
+// partials of w.vnext (of w.w when vnext is null) into part[block].
+__global__ void __launch_bounds__(kBlock) k_fg_mgs(double* __restrict__ w, const double* __restrict__ vprev,
+                                                   const double* __restrict__ hprev, const double* __restrict__ vnext,
+                                                   unsigned n, double* part) {
+    const unsigned n2 = n >> 1;
+    unsigned lo, hi;
+    chunk_of(blockIdx.x, gridDim.x, n2, &lo, &hi);
+    const double hp = vprev ? *hprev : 0.0;
+    double a[1] = {0.0};
+    double2* w2 = reinterpret_cast<double2*>(w);
+    for (unsigned p = lo + threadIdx.x; p < hi; p += blockDim.x) {
+        double2 x = w2[p];
+        if (vprev) {
+            const double2 v = reinterpret_cast<const double2*>(vprev)[p];
+            x.x -= hp * v.x;
+            x.y -= hp * v.y;
+            w2[p] = x;
+        }
+        if (vnext) {
+            const double2 v = reinterpret_cast<const double2*>(vnext)[p];
+            a[0] += x.x * v.x + x.y * v.y;
+        } else {
+            a[0] += x.x * x.x + x.y * x.y;
+        }
+    }
+    if ((n & 1u) && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        double x = w[n - 1];
+        if (vprev) {
+            x -= hp * vprev[n - 1];
+            w[n - 1] = x;
+        }
+        a[0] += x * (vnext ? vnext[n - 1] : x);
+    }
+    block_partials<1>(a, part, gridDim.x, blockIdx.x);
+}
+
+void launch_fg_mgs(hipStream_t st, double* w, const double* vprev, const double* hprev, const double* vnext,
+                   size_t n, double* part, unsigned* np) {
+    const unsigned nb = red_blocks(n / 2 + 1);
+    hipLaunchKernelGGL(k_fg_mgs, dim3(nb), dim3(kBlock), 0, st, w, vprev, hprev, vnext, (unsigned)n, part);
+    *np = nb;
+}
+
+// out = sum of the partials (its square root with take_sqrt)
+__global__ void __launch_bounds__(kFinBlock) k_fg_fin(const double* __restrict__ part, unsigned np, double* out,
+                                                      int take_sqrt) {
+    const double s = fin_sum(part, np);
+    if (threadIdx.x == 0) *out = take_sqrt ? sqrt(s) : s;
+}
+
+void launch_fg_fin(hipStream_t st, const double* part, unsigned np, double* out, int take_sqrt) {
+    hipLaunchKernelGGL(k_fg_fin, dim3(1), dim3(kFinBlock), 0, st, part, np, out, take_sqrt);
+}
+
+// w /= *h (w = 0 when *h is 0: an exact breakdown)
+__global__ void __launch_bounds__(kBlock) k_fg_scale(double* __restrict__ w, const double* __restrict__ h,
+                                                     unsigned n) {
+    const double hv = *h;
+    const double inv = hv > 0.0 ? 1.0 / hv : 0.0;
+    const unsigned p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (2 * p + 1 < n) {
+        double2 x = reinterpret_cast<double2*>(w)[p];
+        x.x *= inv;
+        x.y *= inv;
+        reinterpret_cast<double2*>(w)[p] = x;
+    } else if (2 * p < n) {
+        w[2 * p] *= inv;
+    }
+}
+
+void launch_fg_scale(hipStream_t st, double* w, const double* h, size_t n) {
+    hipLaunchKernelGGL(k_fg_scale, dim3(nblocks((n + 1) / 2)), dim3(kBlock), 0, st, w, h, (unsigned)n);
+}
+
+// r = b - r (sub) or r = b, with b = [bg; 0]; partials of r.r
+__global__ void __launch_bounds__(kBlock) k_fg_resid(double* __restrict__ r, const double* __restrict__ bg,
+                                                     unsigned ncell, unsigned n, int sub, double* part) {
+    unsigned lo, hi;
+    chunk_of(blockIdx.x, gridDim.x, n, &lo, &hi);
+    double a[1] = {0.0};
+    for (unsigned i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const double b = i < ncell ? bg[i] : 0.0;
+        const double v = sub ? b - r[i] : b;
+        r[i] = v;
+        a[0] += v * v;
+    }
+    block_partials<1>(a, part, gridDim.x, blockIdx.x);
+}
+
+void launch_fg_resid(hipStream_t st, double* r, const double* bg, size_t ncell, size_t n, int sub, double* part,
+                     unsigned* np) {
+    const unsigned nb = red_blocks(n);
+    hipLaunchKernelGGL(k_fg_resid, dim3(nb), dim3(kBlock), 0, st, r, bg, (unsigned)ncell, (unsigned)n, sub, part);
+    *np = nb;
+}
+
+// x[i] += sum_j y_j Z_j[off + i] for i < n (Z_j = Z + j * stride, y on the device)
+__global__ void __launch_bounds__(kBlock) k_fg_update(double* __restrict__ x, const double* __restrict__ Z,
+                                                      size_t stride, size_t off, unsigned n, int k,
+                                                      const double* __restrict__ y) {
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = x[i];
+    for (int j = 0; j < k; ++j) acc += y[j] * Z[(size_t)j * stride + off + i];
+    x[i] = acc;
+}
+
+void launch_fg_update(hipStream_t st, double* x, const double* Z, size_t stride, size_t off, size_t n, int k,
+                      const double* y) {
+    if (n == 0 || k == 0) return;
+    hipLaunchKernelGGL(k_fg_update, dim3(nblocks(n)), dim3(kBlock), 0, st, x, Z, stride, off, (unsigned)n, k, y);
+}
+
+// Column j of the Hessenberg matrix (column-major, leading dimension ld) is
+// complete: apply the previous Givens rotations, form rotation j, advance the
+// right-hand side g; out[0] = |g[j+1]| (the residual estimate), out[1] = the
+// subdiagonal entry before rotation.
+__global__ void k_fg_givens(double* Hd, int ld, double* cs, double* sn, double* g, int j, double* out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double* col = Hd + (size_t)j * ld;
+    for (int i = 0; i < j; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * b;
+        col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double den = sqrt(a * a + b * b);
+    cs[j] = den == 0.0 ? 1.0 : a / den;
+    sn[j] = den == 0.0 ? 0.0 : b / den;
+    out[1] = b;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    out[0] = fabs(g[j + 1]);
+}
+
+void launch_fg_givens(hipStream_t st, double* Hd, int ld, double* cs, double* sn, double* g, int j, double* out) {
+    hipLaunchKernelGGL(k_fg_givens, dim3(1), dim3(64), 0, st, Hd, ld, cs, sn, g, j, out);
+}
+
+// g[0] = *beta, g[1..] = 0
+__global__ void k_fg_gstart(double* g, int len, const double* beta) {
+    for (int i = threadIdx.x; i < len; i += blockDim.x) g[i] = i == 0 ? *beta : 0.0;
+}
+
+void launch_fg_gstart(hipStream_t st, double* g, int len, const double* beta) {
+    hipLaunchKernelGGL(k_fg_gstart, dim3(1), dim3(256), 0, st, g, len, beta);
+}
+
+// y = R^{-1} g for the leading k x k upper triangle R of the rotated Hessenberg matrix
+__global__ void k_fg_backsolve(const double* Hd, int ld, const double* g, double* y, int k) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = k - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int j = i + 1; j < k; ++j) s -= Hd[(size_t)j * ld + i] * y[j];
+        const double d = Hd[(size_t)i * ld + i];
+        y[i] = d != 0.0 ? s / d : 0.0;
+    }
+}
+
+void launch_fg_backsolve(hipStream_t st, const double* Hd, int ld, const double* g, double* y, int k) {
+    hipLaunchKernelGGL(k_fg_backsolve, dim3(1), dim3(64), 0, st, Hd, ld, g, y, k);
+}
+
 }  // namespace brd

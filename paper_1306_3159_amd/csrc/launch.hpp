@@ -44,6 +44,26 @@ void launch_fill(hipStream_t st, double* v, size_t n, double value);
 void launch_axpby(hipStream_t st, double* y, const double* x, size_t n, double a, double b);  // y = a y + b x
 void launch_add_shift(hipStream_t st, double* v, size_t n, const double* shift_dev, double sign);
 
+// ---- long [grid; blobs] vectors of the flexible GMRES on the saddle system ----
+// w -= (*hprev) vprev (if vprev), partials of w.vnext (w.w if vnext is null)
+void launch_fg_mgs(hipStream_t st, double* w, const double* vprev, const double* hprev, const double* vnext,
+                   size_t n, double* part, unsigned* np);
+// *out = sum of partials (sqrt of it with take_sqrt)
+void launch_fg_fin(hipStream_t st, const double* part, unsigned np, double* out, int take_sqrt);
+// w /= *h (0 if *h == 0)
+void launch_fg_scale(hipStream_t st, double* w, const double* h, size_t n);
+// r = [bg; 0] - r (sub) or [bg; 0]; partials of r.r
+void launch_fg_resid(hipStream_t st, double* r, const double* bg, size_t ncell, size_t n, int sub, double* part,
+                     unsigned* np);
+// x[0..n) += sum_j y_j Z_j[off ..) (y on the device)
+void launch_fg_update(hipStream_t st, double* x, const double* Z, size_t stride, size_t off, size_t n, int k,
+                      const double* y);
+// Hessenberg column j (column-major, leading dimension ld): rotations, residual
+// estimate out[0] = |g[j+1]|, out[1] = subdiagonal before rotation
+void launch_fg_givens(hipStream_t st, double* Hd, int ld, double* cs, double* sn, double* g, int j, double* out);
+void launch_fg_gstart(hipStream_t st, double* g, int len, const double* beta);
+void launch_fg_backsolve(hipStream_t st, const double* Hd, int ld, const double* g, double* y, int k);
+
 // ---- finalize kernels (one work-group) ------------------------------------
 enum FinKind { FIN_INIT = 0, FIN_ALPHA = 1, FIN_UPDATE = 2, FIN_BETA = 3 };
 void launch_fin(hipStream_t st, int kind, const double* part, unsigned nparts, Scalars* sc,

@@ -51,6 +51,21 @@ class Stats(ctypes.Structure):
         return d
 
 
+class SaddleOpts(ctypes.Structure):
+    _fields_ = [("precond", ctypes.c_int32), ("m", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32), ("rtol", ctypes.c_double),
+                ("diag", ctypes.c_double)]
+
+
+SADDLE_PRECONDS = {"diagonal": 0, "schur": 1, "learned": 2}
+
+
+def _saddle_opts(precond="schur", m=0, n=0, restart=0, maxit=0, rtol=0.0, diag=0.0) -> SaddleOpts:
+    if precond not in SADDLE_PRECONDS:
+        raise ValueError(f"precond must be one of {sorted(SADDLE_PRECONDS)}")
+    return SaddleOpts(SADDLE_PRECONDS[precond], int(m), int(n), int(restart), int(maxit), float(rtol), float(diag))
+
+
 class BlobRDError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"blob_rd error {_ERRNAMES.get(code, code)}: {msg}")
@@ -91,6 +106,12 @@ def load_library(path: str = LIB_PATH):
     L.blob_rd_step.restype = i32
     L.blob_rd_step_absorbing.argtypes = [vp, d, vp, vp, vp, i32, S]
     L.blob_rd_step_absorbing.restype = i32
+    L.blob_rd_fgmres_workspace_bytes.argtypes = [vp, i32]
+    L.blob_rd_fgmres_workspace_bytes.restype = ctypes.c_size_t
+    L.blob_rd_solve_absorbing_fgmres.argtypes = [vp, d, ctypes.POINTER(SaddleOpts), vp, vp, vp, vp, ctypes.c_size_t, S]
+    L.blob_rd_solve_absorbing_fgmres.restype = i32
+    L.blob_rd_saddle_precond.argtypes = [vp, d, ctypes.POINTER(SaddleOpts), vp, vp, vp, vp]
+    L.blob_rd_saddle_precond.restype = i32
     L.blob_rd_interp.argtypes = [vp, vp, vp]
     L.blob_rd_interp.restype = i32
     L.blob_rd_spread.argtypes = [vp, vp, vp]
@@ -325,6 +346,38 @@ class BlobRD:
         rc = self._lib.blob_rd_step_absorbing(self._h, float(dt), _ptr(f), _ptr(c), _ptr(lam), int(bool(warm)),
                                               ctypes.byref(st))
         return self._check(rc, st)
+
+    def solve_absorbing_fgmres(self, f: torch.Tensor, alpha: float = 0.0, precond: str = "schur", m: int = 0,
+                               n: int = 0, restart: int = 0, maxit: int = 0, rtol: float = 0.0, diag: float = 0.0
+                               ) -> Tuple[torch.Tensor, torch.Tensor, dict]:
+        """The paper's own saddle solver: flexible GMRES on [alpha I - D L, S; J, 0][c; lam] = [f; 0]
+        with the diagonal or approximate-Schur preconditioner (m inner iterations, n cycles)."""
+        self._grid(f, "f")
+        o = _saddle_opts(precond, m, n, restart, maxit, rtol, diag)
+        nbytes = int(self._lib.blob_rd_fgmres_workspace_bytes(self._h, o.restart))
+        if nbytes == 0:
+            raise ValueError("FGMRES restart length out of range")
+        if getattr(self, "_fg_ws", None) is None or self._fg_ws.numel() < nbytes:
+            self._fg_ws = None
+            self._fg_ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        c = self._new_grid()
+        lam = torch.zeros(self.N, dtype=torch.float64, device=self.device)
+        st = Stats()
+        rc = self._lib.blob_rd_solve_absorbing_fgmres(self._h, float(alpha), ctypes.byref(o), _ptr(f), _ptr(c),
+                                                      _ptr(lam), _ptr(self._fg_ws), nbytes, ctypes.byref(st))
+        return c, lam, self._check(rc, st)
+
+    def saddle_precond(self, vg: torch.Tensor, vf: torch.Tensor, alpha: float = 0.0, precond: str = "schur",
+                       m: int = 0, n: int = 0, diag: float = 0.0) -> Tuple[torch.Tensor, torch.Tensor]:
+        """One application of the paper's saddle-point preconditioner to [vg; vf]."""
+        self._grid(vg, "vg")
+        self._nvec(vf, "vf")
+        o = _saddle_opts(precond, m, n, 0, 0, 0.0, diag)
+        zg = self._new_grid()
+        zl = torch.zeros(self.N, dtype=torch.float64, device=self.device)
+        self._check(self._lib.blob_rd_saddle_precond(self._h, float(alpha), ctypes.byref(o), _ptr(vg), _ptr(vf),
+                                                     _ptr(zg), _ptr(zl)))
+        return zg, zl
 
     # -- operators --------------------------------------------------------------
     def interp(self, c: torch.Tensor) -> torch.Tensor:

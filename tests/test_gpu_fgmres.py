@@ -1,0 +1,163 @@
+"""GPU parity of the paper's own saddle-point solver (flexible GMRES on the block system with
+the diagonal and approximate-Schur preconditioners) against the oracle, through the C ABI.
+
+One preconditioner application is compared element by element with the oracle's steps run on
+the oracle's own V(2,2) cycles (FP64 handle: the cycles agree to ~1e-12, so 1e-9 covers the
+m = 5 inner GMRES iterations; mixed handle: FP32 cycles, 1e-4). Whole solves are compared with
+the dense exact saddle solution and with the oracle solver's iteration counts.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import exact as ex
+from oracle import iterative as it
+from oracle import saddle_fgmres as fg
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1306_3159_amd import native
+    native.load_library()
+    return torch.device("cuda:0")
+
+
+def T(a, dev):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def H(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def make(dev, n, q, **kw):
+    from paper_1306_3159_amd import BlobRD
+    return BlobRD(n, T(q, dev), **kw)
+
+
+def lattice(n, spacing, rng, jitter=0.0):
+    pts = np.arange(spacing / 2.0, n, spacing)
+    q = np.stack(np.meshgrid(pts, pts, pts, indexing="ij"), -1).reshape(-1, 3)
+    return q + rng.uniform(-jitter, jitter, q.shape)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind", ["diagonal", "schur"])
+@pytest.mark.parametrize("alpha", [0.0, 1.0 / 32 ** 2])
+def test_precond_parity(dev, alpha, kind, prec):
+    _say("saddle precond", alpha, kind, prec)
+    rng = np.random.default_rng(71)
+    n, N = 32, 30
+    q = W.rsa_positions(rng, n, N, 3.0)
+    vg = rng.standard_normal((n, n, n))
+    vf = rng.standard_normal(N)
+    S = make(dev, n, q, precision=prec)
+    zg, zl = S.saddle_precond(T(vg, dev), T(vf, dev), alpha=alpha, precond=kind, m=5, n=1)
+    ops = fg.SaddleOps(q, (n, n, n), alpha)
+    inv = fg.cycles_inverse(ops, lambda r: it.vcycle(r, alpha), 1)
+    cg, cl = fg.precondition(ops, vg, vf, kind, inv, inv, m=5)
+    tol = 1e-9 if prec == 0 else 1e-4
+    assert rel(H(zg), cg) < tol
+    assert rel(H(zl), cl) < tol
+    # two cycles per approximate solve
+    zg2, zl2 = S.saddle_precond(T(vg, dev), T(vf, dev), alpha=alpha, precond=kind, m=5, n=2)
+    inv2 = fg.cycles_inverse(ops, lambda r: it.vcycle(r, alpha), 2)
+    cg2, cl2 = fg.precondition(ops, vg, vf, kind, inv2, inv, m=5)
+    assert rel(H(zg2), cg2) < tol
+    assert rel(H(zl2), cl2) < tol
+    S.close()
+
+
+@pytest.mark.parametrize("kind", ["diagonal", "schur"])
+@pytest.mark.parametrize("alpha", [0.0, 1.0 / 32 ** 2])
+def test_fgmres_solve_matches_oracle(dev, alpha, kind):
+    """FP64 handle: the exact saddle solution to the tolerance, and the oracle solver's iteration
+    count (same arithmetic up to rounding order). Mixed handle: the same solution at 1e-8."""
+    _say("fgmres solve", alpha, kind)
+    rng = np.random.default_rng(72)
+    n, N = 32, 30
+    q = W.rsa_positions(rng, n, N, 3.0)
+    f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
+    ce, le = ex.solve_absorbing(f, q, alpha)
+    _, _, info = fg.solve(f, q, alpha, kind=kind, rtol=1e-10, cycle=lambda r: it.vcycle(r, alpha))
+    for prec, tol in ((0, 1e-10), (1, 1e-8)):
+        S = make(dev, n, q, precision=prec, rtol=tol)
+        c, lam, st = S.solve_absorbing_fgmres(T(f, dev), alpha=alpha, precond=kind)
+        assert st["rc"] == 0, st
+        c, lam = H(c), H(lam)
+        assert st["rel_resid"] <= tol
+        assert ex.absorbing_residual(c, lam, f, q, alpha) <= 1.01 * tol
+        assert rel(c, ce) < 100 * tol and rel(lam, le) < 100 * tol
+        print("prec", prec, kind, "alpha", alpha, "FGMRES", st["outer_iters"], "oracle", info["iters"],
+              "cycles", st["vcycles"], flush=True)
+        if prec == 0:
+            assert abs(st["outer_iters"] - info["iters"]) <= 1
+        S.close()
+
+
+def test_fgmres_fixed_blob_count_lattice(dev):
+    """The paper's fixed-N test (64 = 4^3 blobs on a lattice, A = L^-2 I - L) at L = 64 with both
+    preconditioners: converges, and the oracle's FP64 residual agrees at full size."""
+    _say("fgmres lattice 64")
+    rng = np.random.default_rng(73)
+    n = 64
+    q = lattice(n, 16.0, rng)
+    f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
+    alpha = 1.0 / n ** 2
+    S = make(dev, n, q, precision=1, rtol=1e-8)
+    for kind in ("diagonal", "schur"):
+        c, lam, st = S.solve_absorbing_fgmres(T(f, dev), alpha=alpha, precond=kind, restart=200 if kind == "diagonal"
+                                              else 30)
+        assert st["rc"] == 0, st
+        print(kind, st, flush=True)
+        assert ex.absorbing_residual(H(c), H(lam), f, q, alpha) <= 1e-8
+    S.close()
+
+
+def test_fgmres_errors_and_limits(dev):
+    _say("fgmres errors")
+    from paper_1306_3159_amd import BlobRDError
+    rng = np.random.default_rng(74)
+    n = 16
+    q = W.rsa_positions(rng, n, 5, 3.0)
+    f = T(1.0 + 0.5 * rng.standard_normal((n, n, n)), dev)
+    S = make(dev, n, q, rtol=1e-10)
+    c, lam, st = S.solve_absorbing_fgmres(f, precond="diagonal", maxit=2)
+    assert st["rc"] == 1 and st["outer_iters"] == 2  # not converged, reported
+    with pytest.raises(BlobRDError):
+        S.solve_absorbing_fgmres(f, m=31)  # above the handle's GMRES restart length
+    with pytest.raises(BlobRDError):
+        S.solve_absorbing_fgmres(f, alpha=-1.0)
+    with pytest.raises(BlobRDError):
+        S.saddle_precond(f, torch.zeros(5, dtype=torch.float64, device=dev), n=65)
+    with pytest.raises(ValueError):
+        S.solve_absorbing_fgmres(f, restart=2000)
+    lib = S._lib
+    ws = torch.empty(1024, dtype=torch.uint8, device=dev)
+    from paper_1306_3159_amd.native import Stats, _saddle_opts, _ptr
+    import ctypes
+    o = _saddle_opts()
+    cc = torch.zeros_like(f)
+    ll = torch.zeros(5, dtype=torch.float64, device=dev)
+    rc = lib.blob_rd_solve_absorbing_fgmres(S._h, 0.0, ctypes.byref(o), _ptr(f), _ptr(cc), _ptr(ll), _ptr(ws), 1024,
+                                            ctypes.byref(Stats()))
+    assert rc == -2  # workspace too small
+    S.close()
