@@ -110,12 +110,14 @@ def gmres_fixed(op: Callable[[np.ndarray], np.ndarray], b: np.ndarray, m: int) -
 
 
 def precondition(ops: SaddleOps, vg, vf, kind: str, ainv_n, ainv_1=None, m: int = 5,
-                 diag: Optional[float] = None):
+                 diag: Optional[float] = None, w_apply: Optional[Callable] = None):
     """One application of the paper's saddle-point preconditioner to [vg; vf] (appendix on
     preconditioning the saddle-point solver, steps 1-5; Sec. III.E for the two variants).
 
     kind 'diagonal': multipliers lam~ = diag * h~ with diag = D/gamma = 4 pi a0 D by default.
     kind 'schur': m GMRES iterations on (J A1^{-1} S) lam~ = h~, A1^{-1} one cycle (ainv_1).
+    kind 'learned': the same iterations right-preconditioned by an approximate inverse Schur
+    complement w_apply (the learned P W P): (J A1^{-1} S W) y = h~, lam~ = W y.
     For the singular case (alpha = 0) the blob-space mean is projected out of h~, of every
     product of the inner Krylov operator and of lam~ (a mean offset of an approximate
     concentration only shifts J c by a constant, which that projection removes).
@@ -133,6 +135,9 @@ def precondition(ops: SaddleOps, vg, vf, kind: str, ainv_n, ainv_1=None, m: int 
         lam_t = (4.0 * math.pi * A0_OVER_H * ops.h * ops.D if diag is None else diag) * h_t
     elif kind == "schur":
         lam_t = gmres_fixed(lambda v: proj(ops.J(ainv_1(ops.S(v)))), h_t, m)
+    elif kind == "learned":
+        y = gmres_fixed(lambda v: proj(ops.J(ainv_1(ops.S(w_apply(v))))), h_t, m)
+        lam_t = w_apply(y)
     else:
         raise ValueError(kind)
     lam_t = proj(lam_t)
@@ -204,7 +209,7 @@ def fgmres(apply_K, apply_P, bg, bf, restart=30, rtol=1e-8, maxit=1000):
 
 
 def solve(f, q, alpha, kind="schur", m=5, n=1, restart=30, rtol=1e-8, maxit=1000, D=1.0, h=1.0, w=4,
-          cycle: Optional[Callable] = None, phi=None, diag=None):
+          cycle: Optional[Callable] = None, phi=None, diag=None, w_apply=None):
     """[A, S; J, 0][c; lam] = [f; phi] by flexible GMRES with the paper's preconditioner.
     cycle: one multigrid cycle r -> V r for A (default: the exact inverse, i.e. n and the
     inner products become exact solves). Returns (c, lam, info)."""
@@ -213,6 +218,6 @@ def solve(f, q, alpha, kind="schur", m=5, n=1, restart=30, rtol=1e-8, maxit=1000
     ainv_n = cycles_inverse(ops, cyc, n)
     ainv_1 = cycles_inverse(ops, cyc, 1)
     phi = np.zeros(ops.N) if phi is None else np.asarray(phi, float)
-    c, lam, info = fgmres(ops.K, lambda vg, vf: precondition(ops, vg, vf, kind, ainv_n, ainv_1, m, diag),
+    c, lam, info = fgmres(ops.K, lambda vg, vf: precondition(ops, vg, vf, kind, ainv_n, ainv_1, m, diag, w_apply),
                           np.asarray(f, float), phi, restart, rtol, maxit)
     return c, lam, info

@@ -25,7 +25,7 @@ constexpr int kMaxTuneBlock = 512;  // largest work-group the autotuner may pick
 constexpr int kFinBlock = 1024;
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarse = 512;
-constexpr int kStageBlobs = 128;   // blobs staged in LDS per pass of the spread gather
+constexpr int kStageBlobs = 128;   // candidate blobs staged in LDS per pass of the spread planner
 
 // Device-resident scalars of one CG solve. Every kernel of an iteration reads
 // `done` first and returns if it is set, so the host can enqueue iterations
@@ -140,6 +140,11 @@ struct InstDev {
     double* jx;
     double* mu;
     double inv_h3;
+    int ntouched;                         // spread contribution lists (touched cells, entries)
+    const int* tcell;
+    const int* tptr;
+    const int* tblob;
+    const double* tw;
     const double* cinv;                   // coarsest (pseudo-)inverse for alpha
     TailDesc tail;
 };
@@ -152,6 +157,15 @@ struct LevelDims {
 
 // ---- helpers -------------------------------------------------------------
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Value of cell (X, Y, Z) of a red/black split level (colour (X + Y + Z) mod 2,
+// index X/2 of row (Y, Z) of its colour array, hx = nx/2) as a double.
+template <typename T>
+__device__ __forceinline__ double split_at(const T* __restrict__ z0, const T* __restrict__ z1, int X, int Y, int Z,
+                                           int hx, int ny) {
+    const size_t j = ((size_t)Z * ny + Y) * hx + (X >> 1);
+    return ((X + Y + Z) & 1) ? (double)z1[j] : (double)z0[j];
+}
 
 // Blocks are dispatched to the 8 XCDs round-robin; this remaps the hardware
 // block id so each XCD works on one contiguous eighth of the index space,

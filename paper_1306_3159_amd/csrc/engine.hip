@@ -97,6 +97,8 @@ struct Plan {
     size_t off_sc = 0, off_gs = 0, off_dsc = 0;
     size_t off_q = 0, off_kappa = 0, off_base = 0, off_wts = 0, off_tile = 0, off_counts = 0, off_offsets = 0,
            off_cursor = 0, off_perm = 0;
+    // spread contribution lists: per-tile counts and offsets, touched cells, entries
+    size_t off_sp_cnt = 0, off_sp_off = 0, off_tcell = 0, off_tptr = 0, off_tblob = 0, off_tw = 0;
     size_t off_nv[12]{};
     size_t off_V = 0, off_H = 0, off_cs = 0, off_sn = 0, off_gv = 0, off_yv = 0;
     size_t total = 0;
@@ -193,6 +195,12 @@ int make_plan(const blob_rd_params* p, Plan* P, std::string* why) {
     P->off_offsets = take(((size_t)P->ntiles + 1) * 4);
     P->off_cursor = take((size_t)P->ntiles * 4);
     P->off_perm = take(N * 4);
+    P->off_sp_cnt = take((size_t)P->ntiles * 2 * 4);
+    P->off_sp_off = take(((size_t)P->ntiles + 1) * 2 * 4);
+    P->off_tcell = take(N * 64 * 4);
+    P->off_tptr = take((N * 64 + 1) * 4);
+    P->off_tblob = take(N * 64 * 4);
+    P->off_tw = take(N * 64 * 8);
     for (int k = 0; k < 12; ++k) P->off_nv[k] = take(N * 8);
     const size_t m = (size_t)P->restart;
     P->off_V = take((m + 1) * N * 8);
@@ -319,6 +327,7 @@ struct blob_rd {
         PairGeom pg{};
     } lrn;
     int fallback = 0;
+    int ntouched = 0;  // cells with a nonzero spread weight (length of the contribution lists)
     // lock-step batch executor this handle currently belongs to (null: solo)
     BatchServer* batch = nullptr;
     int batch_slot = -1;
@@ -594,13 +603,26 @@ void precond_zdots(blob_rd* H, double alpha, const double* r, const double* q, c
     launch_fin(H->st, FIN_BETA, H->part(), np, H->sc(), nullptr, nullptr, 0, 0.0);
 }
 
+// out = base_in + scale * S (lam + lam_shift) from the contribution lists: a
+// dense pass (copy of base_in, or zeros without it; none when out aliases
+// base_in) and one thread per touched cell. lam may be null (lam_shift only).
+void spread_to(blob_rd* H, const double* lam, double lam_shift, const double* base_in, double* out, double scale,
+               const Scalars* sc) {
+    const Plan& P = H->P;
+    if (base_in != out) {
+        if (base_in) launch_nvec_copy_scale(H->st, base_in, out, (int)P.ncell, 1.0, 0.0);
+        else launch_fill(H->st, out, P.ncell, 0.0);
+    }
+    launch_spread_sparse(H->st, lam, lam_shift, H->ntouched, H->at<int>(P.off_tcell), H->at<int>(P.off_tptr),
+                         H->at<int>(P.off_tblob), H->at<double>(P.off_tw), base_in, out, scale, sc);
+}
+
 // q += S kappa J p, with jx = J p and mu = kappa J p kept for the CG dots.
 void blob_term(blob_rd* H, const double* p, double* q, const Scalars* sc) {
     const Plan& P = H->P;
     launch_interp(H->st, p, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts), H->at<int>(P.off_perm),
                   H->nv(0), H->at<double>(P.off_kappa), H->nv(1), sc);
-    launch_spread(H->st, H->nv(1), 0.0, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
-                  H->at<int>(P.off_offsets), H->at<int>(P.off_perm), q, q, H->inv_h3(), 1, sc);
+    spread_to(H, H->nv(1), 0.0, q, q, H->inv_h3(), sc);
 }
 
 // Batch executor hooks (defined with the executor below).
@@ -837,8 +859,7 @@ void schur_apply(blob_rd* H, double alpha, const double* x, double* y, double in
     launch_nvec_copy_scale(st, x, xt, P.N, 1.0, 0.0);
     if (alpha == 0.0) launch_nvec_project(st, xt, P.N);
     // S x straight into the CG residual (zero start: r = g)
-    launch_spread(st, xt, 0.0, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
-                  H->at<int>(P.off_offsets), H->at<int>(P.off_perm), nullptr, H->grid(G_R), H->inv_h3(), 0, nullptr);
+    spread_to(H, xt, 0.0, nullptr, H->grid(G_R), H->inv_h3(), nullptr);
     H->alg_bytes += (double)P.ncell * 8;
     PcgResult pr = pcg<T>(H, false, alpha, H->grid(G_R), H->grid(G_U), true, inner_rtol, 0.0, inner_maxit(H));
     if (pr.status) throw Err(BLOB_RD_ENUMERIC, "non-finite value or breakdown in inner CG");
@@ -877,8 +898,7 @@ SaddleInfo saddle_solve(blob_rd* H, double alpha, const double* g, const double*
     double* u = H->grid(G_U);
     // u0 = A^+ (g - lbar S 1); b = J u0 - phi (projected)
     double* rhs0 = H->grid(G_T2);
-    launch_spread(st, nullptr, -lbar, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
-                  H->at<int>(P.off_offsets), H->at<int>(P.off_perm), g, rhs0, H->inv_h3(), 0, nullptr);
+    spread_to(H, nullptr, -lbar, g, rhs0, H->inv_h3(), nullptr);
     H->alg_bytes += (double)P.ncell * 16;
     PcgResult pr = pcg<T>(H, false, alpha, rhs0, u, true, inner_rtol, 0.0, inner_maxit(H));
     if (pr.status) throw Err(BLOB_RD_ENUMERIC, "non-finite value in Poisson solve");
@@ -972,8 +992,7 @@ SaddleInfo saddle_solve(blob_rd* H, double alpha, const double* g, const double*
     if (alpha == 0.0) launch_nvec_project(st, lt, N);
     // lam = lbar + lt ; c = A^+ (g - S lam) (+ cbar)
     launch_nvec_copy_scale(st, lt, lam, N, 1.0, lbar);
-    launch_spread(st, lam, 0.0, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
-                  H->at<int>(P.off_offsets), H->at<int>(P.off_perm), g, gg, -H->inv_h3(), 0, nullptr);
+    spread_to(H, lam, 0.0, g, gg, -H->inv_h3(), nullptr);
     H->alg_bytes += (double)P.ncell * 16;
     pr = pcg<T>(H, false, alpha, gg, u, true, 0.0, final_rtol_abs, inner_maxit(H));
     if (pr.status) throw Err(BLOB_RD_ENUMERIC, "non-finite value in Poisson solve");
@@ -1003,8 +1022,7 @@ void saddle_residual(blob_rd* H, double alpha, const double* g, const double* ph
     const double s = H->prm.D / (d.h * d.h);
     double* q = H->grid(G_Q);
     launch_applyA_plain(H->st, c, q, alpha, s, d.nx, d.ny, d.nz);
-    launch_spread(H->st, lam, 0.0, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
-                  H->at<int>(P.off_offsets), H->at<int>(P.off_perm), q, q, H->inv_h3(), 1, nullptr);
+    spread_to(H, lam, 0.0, q, q, H->inv_h3(), nullptr);
     unsigned np = 0;
     launch_residual_from_q(H->st, g, q, t, P.ncell, H->part(), &np);
     launch_reduce_parts(H->st, H->part(), np, 3, H->dsc());
@@ -1189,6 +1207,26 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
             launch_bin_scatter(st, H->at<int>(P.off_tile), N, H->at<int>(P.off_offsets), H->at<int>(P.off_cursor),
                                H->at<int>(P.off_perm));
             launch_bin_sort(st, H->at<int>(P.off_offsets), P.ntiles, H->at<int>(P.off_perm));
+            // contribution lists of the spread: count per tile, scan, fill
+            int* cnt = H->at<int>(P.off_sp_cnt);
+            int* offE = H->at<int>(P.off_sp_off);
+            int* offC = offE + P.ntiles + 1;
+            launch_spread_plan(st, 0, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
+                               H->at<int>(P.off_offsets), H->at<int>(P.off_perm), cnt, nullptr, nullptr, nullptr,
+                               nullptr, nullptr, nullptr);
+            launch_bin_scan(st, cnt, P.ntiles, offE);
+            launch_bin_scan(st, cnt + P.ntiles, P.ntiles, offC);
+            launch_spread_plan(st, 1, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
+                               H->at<int>(P.off_offsets), H->at<int>(P.off_perm), nullptr, offE, offC,
+                               H->at<int>(P.off_tcell), H->at<int>(P.off_tptr), H->at<int>(P.off_tblob),
+                               H->at<double>(P.off_tw));
+            int nt[2] = {0, 0};
+            HIPCHK(hipMemcpyAsync(&nt[0], offE + P.ntiles, 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(&nt[1], offC + P.ntiles, 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (nt[0] < 0 || nt[0] > 64 * N || nt[1] < 0 || nt[1] > nt[0])
+                throw Err(BLOB_RD_EDEVICE, "spread contribution lists out of range");
+            H->ntouched = nt[1];
             launch_nvec_sums(st, H->at<double>(P.off_kappa), nullptr, N, H->dsc());
             sync_read(H, H->hbuf, H->dsc(), 24);
             H->sum_kappa = H->hbuf[0];
@@ -1320,8 +1358,7 @@ int blob_rd_spread(blob_rd_t H, const double* lambda, double* out) {
     if (!H || !out || (!lambda && H->P.N > 0)) return g_last_error = "null argument", BLOB_RD_EINVAL;
     return guarded(H, nullptr, [&]() {
         const Plan& P = H->P;
-        launch_spread(H->st, lambda, 0.0, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
-                      H->at<int>(P.off_offsets), H->at<int>(P.off_perm), nullptr, out, H->inv_h3(), 0, nullptr);
+        spread_to(H, lambda, 0.0, nullptr, out, H->inv_h3(), nullptr);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(H->st));
         return BLOB_RD_OK;
@@ -1764,6 +1801,11 @@ void batch_describe(BatchServer& B, int i, blob_rd* H, bool blobs) {
     D.jx = H->nv(0);
     D.mu = H->nv(1);
     D.inv_h3 = H->inv_h3();
+    D.ntouched = H->ntouched;
+    D.tcell = H->at<int>(P.off_tcell);
+    D.tptr = H->at<int>(P.off_tptr);
+    D.tblob = H->at<int>(P.off_tblob);
+    D.tw = H->at<double>(P.off_tw);
     D.cinv = select_cinv(H, B.alpha);
     D.tail = P.esz == 4 ? make_tail<float>(H, t, B.alpha) : make_tail<double>(H, t, B.alpha);
 }
@@ -1808,7 +1850,7 @@ void batch_setup(BatchServer& B, char* ws, size_t ws_bytes, const int32_t* kind)
         B.tabs[TAB_DOTS].nb[i] = nblocks(nv(i, 0));
         if (D.blobs) {
             B.tabs[TAB_INTERP].nb[i] = (unsigned)((D.N + kBlock / 64 - 1) / (kBlock / 64));
-            B.tabs[TAB_SPREAD].nb[i] = (unsigned)(D.geom.ntx * D.geom.nty * D.geom.ntz);
+            B.tabs[TAB_SPREAD].nb[i] = nblocks((size_t)D.ntouched);
         }
         for (int l = 0; l < D.t; ++l) {
             B.tabs[TAB_LEVELS + l].nb[i] = nblocks(nv(i, l));
@@ -2639,8 +2681,7 @@ void fg_cycles(blob_rd* H, double alpha, const double* rhs, double* x, bool from
 
 void fg_spread(blob_rd* H, const double* lam, const double* base_in, double* out, double scale, int add_only) {
     const Plan& P = H->P;
-    launch_spread(H->st, lam, 0.0, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
-                  H->at<int>(P.off_offsets), H->at<int>(P.off_perm), base_in, out, scale, add_only, nullptr);
+    spread_to(H, lam, 0.0, base_in, out, scale, nullptr);
     H->alg_bytes += (double)P.ncell * (base_in && !add_only ? 16 : 8);
 }
 
@@ -2710,9 +2751,8 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
         double* Hm = H->at<double>(P.off_H);
         double* gv = H->at<double>(P.off_gv);
         launch_gmres_start(st, hv, nullptr, 0, V, gv, N, H->gs());
-        const LevelDims& d = P.lev[0];
-        T* z0 = H->at<T>(P.off_lvl[0][0]);
-        T* z1 = H->at<T>(P.off_lvl[0][1]);
+        const T* z0 = H->at<T>(P.off_lvl[0][0]);
+        const T* z1 = H->at<T>(P.off_lvl[0][1]);
         for (int k = 0; k < o.m; ++k) {
             const double* vk = V + (size_t)k * N;
             if (learned) {
@@ -2721,12 +2761,10 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
             }
             fg_spread(H, vk, nullptr, H->grid(G_T2), H->inv_h3(), 0);
             vcycle<T>(H, alpha, H->grid(G_T2), nullptr, cinv);
-            launch_split_to_nat<T>(st, z0, z1, H->grid(G_U), d.nx, d.ny, d.nz, 0.0);
-            H->alg_bytes += (double)P.ncell * (P.esz + 8);
-            fg_interp(H, H->grid(G_U), V + (size_t)(k + 1) * N);
-            if (sing) launch_nvec_project(st, V + (size_t)(k + 1) * N, N);
+            launch_interp_split<T>(st, z0, z1, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
+                                   H->at<int>(P.off_perm), V + (size_t)(k + 1) * N);
             launch_gmres_arnoldi(st, V, Hm, H->at<double>(P.off_cs), H->at<double>(P.off_sn), gv, N, k, o.m,
-                                 H->gs());
+                                 H->gs(), sing ? 1 : 0);
         }
         double* y = learned ? H->nv(10) : zl;
         launch_nvec_copy_scale(st, nullptr, y, N, 0.0, 0.0);

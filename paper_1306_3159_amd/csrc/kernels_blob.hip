@@ -182,27 +182,116 @@ void launch_interp(hipStream_t st, const double* x, int N, BlobGeom g, const int
                        out, sc);
 }
 
-// ---------------------------------------------------------------------------
-// Spreading as a tile gather.
-struct Staged {
-    int bx, by, bz, pad;
-    double w[12];
-    double lam;
-};
+// out_i = (J z)_i for z in a red/black split level-0 layout (u0, u1 of type T):
+// the same weights and summation order as interp_body on the natural copy of z.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_interp_split(const T* __restrict__ z0, const T* __restrict__ z1, int N,
+                                                         BlobGeom g, const int* __restrict__ base,
+                                                         const double* __restrict__ wts, const int* __restrict__ perm,
+                                                         double* __restrict__ out) {
+    const int wv = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (wv >= N) return;
+    const int i = perm[wv];
+    const int l = threadIdx.x & 63;
+    const int a = l & 3, b = (l >> 2) & 3, c = l >> 4;
+    int cx = base[3 * i] + a, cy = base[3 * i + 1] + b, cz = base[3 * i + 2] + c;
+    cx = cx >= g.nx ? cx - g.nx : cx;
+    cy = cy >= g.ny ? cy - g.ny : cy;
+    cz = cz >= g.nz ? cz - g.nz : cz;
+    const double* w = wts + (size_t)i * 12;
+    const double wgt = w[a] * w[4 + b] * w[8 + c];
+    double v = wgt * split_at(z0, z1, cx, cy, cz, g.nx >> 1, g.ny);
+    v = wave_sum(v);
+    if (l == 0) out[i] = v;
+}
 
-__device__ __forceinline__ void spread_body(const double* __restrict__ lam, double lam_shift, const BlobGeom& g,
-                                            const int* __restrict__ base, const double* __restrict__ wts,
-                                            const int* __restrict__ offsets, const int* __restrict__ perm,
-                                            const double* base_in, double* out, double scale, int add_only, Blk blk) {
-    __shared__ Staged stg[kStageBlobs];
-    __shared__ int rng_lo[27], rng_len[27], rng_pre[28];
+template <typename T>
+void launch_interp_split(hipStream_t st, const T* z0, const T* z1, int N, BlobGeom g, const int* base,
+                         const double* wts, const int* perm, double* out) {
+    if (N <= 0) return;
+    const int per = kBlock / 64;
+    hipLaunchKernelGGL(k_interp_split<T>, dim3((N + per - 1) / per), dim3(kBlock), 0, st, z0, z1, N, g, base, wts,
+                       perm, out);
+}
+template void launch_interp_split<float>(hipStream_t, const float*, const float*, int, BlobGeom, const int*,
+                                         const double*, const int*, double*);
+template void launch_interp_split<double>(hipStream_t, const double*, const double*, int, BlobGeom, const int*,
+                                          const double*, const int*, double*);
+
+// Batched blob term of B = alpha I - D L + S kappa J inside a CG iteration:
+// jx = J p, mu = kappa jx (interp), then q += h^-3 S mu (spread, touched cells only).
+__global__ void __launch_bounds__(kBlock) kb_interp(const InstDev* inst, const int* gate, const BatchTab* tab) {
+    const BatchEntry* ent = tab_entries(tab);
+    for (unsigned g = blockIdx.x; g < tab->total; g += gridDim.x) {
+        Blk blk;
+        const InstDev* I = batch_slot(inst, gate, ent, tab->n, g, blk);
+        if (!I || !I->blobs) continue;
+        interp_body(I->p, I->N, I->geom, I->base, I->wts, I->perm, I->jx, I->kappa, I->mu, blk);
+    }
+}
+
+// out[c] = base(c) + scale * sum_e tw[e] (lam[tblob[e]] + lam_shift) for touched cell k
+__device__ __forceinline__ void spread_sparse_cell(int k, const double* __restrict__ lam, double lam_shift,
+                                                   const int* __restrict__ tcell, const int* __restrict__ tptr,
+                                                   const int* __restrict__ tblob, const double* __restrict__ tw,
+                                                   const double* base_in, double* out, double scale) {
+    double acc = 0.0;
+    for (int e = tptr[k]; e < tptr[k + 1]; ++e) acc += tw[e] * ((lam ? lam[tblob[e]] : 0.0) + lam_shift);
+    const int c = tcell[k];
+    const double b = base_in ? base_in[c] : 0.0;
+    out[c] = b + scale * acc;
+}
+
+// q += S mu on the touched cells of every gated instance
+__global__ void __launch_bounds__(kBlock) kb_spread(const InstDev* inst, const int* gate, const BatchTab* tab) {
+    const BatchEntry* ent = tab_entries(tab);
+    for (unsigned g = blockIdx.x; g < tab->total; g += gridDim.x) {
+        Blk blk;
+        const InstDev* I = batch_slot(inst, gate, ent, tab->n, g, blk);
+        if (!I || !I->blobs) continue;
+        const int k = (int)(blk.b * blockDim.x + threadIdx.x);
+        if (k < I->ntouched)
+            spread_sparse_cell(k, I->mu, 0.0, I->tcell, I->tptr, I->tblob, I->tw, I->q, I->q, I->inv_h3);
+    }
+}
+
+void launchb_blob(hipStream_t st, int spread, const InstDev* inst, const int* gate, const BatchTab* tab,
+                  unsigned grid) {
+    if (spread) hipLaunchKernelGGL(kb_spread, dim3(grid), dim3(kBlock), 0, st, inst, gate, tab);
+    else hipLaunchKernelGGL(kb_interp, dim3(grid), dim3(kBlock), 0, st, inst, gate, tab);
+}
+
+
+// ---------------------------------------------------------------------------
+// Spreading from contribution lists. The blob placement is fixed for a handle,
+// so the weights one tile gather would find for each cell can be listed once:
+// per touched cell, the (blob, weight) pairs with a nonzero weight, in the
+// gather's candidate order (neighbour tiles z-major, each tile's blobs in bin
+// order) and with the gather's product order ((wx wy) wz) lam. A spread is
+// then a dense pass (zero or copy of the base) plus one thread per touched
+// cell, and the sums are bitwise those of the gather.
+//
+// k_spread_plan, one work-group per tile: mode 0 counts the tile's entries and
+// touched cells into cnt[t] and cnt[ntiles + t]; mode 1 writes them at the
+// scanned offsets offE[t], offC[t] (tcell: cell index, tptr: first entry).
+__global__ void __launch_bounds__(kBlock) k_spread_plan(int mode, BlobGeom g, const int* __restrict__ base,
+                                                        const double* __restrict__ wts,
+                                                        const int* __restrict__ offsets, const int* __restrict__ perm,
+                                                        int* __restrict__ cnt, const int* __restrict__ offE,
+                                                        const int* __restrict__ offC, int* __restrict__ tcell,
+                                                        int* __restrict__ tptr, int* __restrict__ tblob,
+                                                        double* __restrict__ tw) {
+    struct Cand {
+        int bx, by, bz, i;
+        double w[12];
+    };
+    __shared__ Cand stg[kStageBlobs];
+    __shared__ int rng_lo[27], rng_pre[28], nb_lo[27], nb_len[27];
     __shared__ int nrng;
-    const int t = xcd_block(blk.b, blk.nb);
+    __shared__ int ncount[2 * kBlock], nstart[2 * kBlock + 1], crank[2 * kBlock + 1];
+    const int ntiles = g.ntx * g.nty * g.ntz;
+    const int t = blockIdx.x;
     const int tix = t % g.ntx, tiy = (t / g.ntx) % g.nty, tiz = t / (g.ntx * g.nty);
-    // Blob ranges of the 27 neighbouring tiles (z-major, then y, then x; a tile
-    // reached twice on small periodic grids is taken at its first offset per
-    // axis): one thread per neighbour fetches its range, thread 0 packs them.
-    __shared__ int nb_lo[27], nb_len[27];
     if (threadIdx.x < 27) {
         const int d = threadIdx.x;
         const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
@@ -223,27 +312,21 @@ __device__ __forceinline__ void spread_body(const double* __restrict__ lam, doub
     __syncthreads();
     if (threadIdx.x == 0) {
         int nr = 0, pre = 0;
-        for (int d = 0; d < 27; ++d) {
-            const int len = nb_len[d];
-            if (len > 0) {
+        for (int d = 0; d < 27; ++d)
+            if (nb_len[d] > 0) {
                 rng_lo[nr] = nb_lo[d];
-                rng_len[nr] = len;
                 rng_pre[nr] = pre;
-                pre += len;
+                pre += nb_len[d];
                 ++nr;
             }
-        }
         rng_pre[nr] = pre;
         nrng = nr;
     }
     __syncthreads();
-    const int nr = nrng;
-    const int K = rng_pre[nr];
+    const int K = rng_pre[nrng];
     const int tcells = g.tx * g.ty * g.tz;
-    if (K == 0 && add_only) return;
-
-    double acc[2] = {0.0, 0.0};
     int cell[2][3];
+    int n[2] = {0, 0};
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
         const int lc = threadIdx.x + e * blockDim.x;
@@ -252,96 +335,121 @@ __device__ __forceinline__ void spread_body(const double* __restrict__ lam, doub
         cell[e][1] = tiy * g.ty + ly;
         cell[e][2] = tiz * g.tz + lz;
     }
-    for (int c0 = 0; c0 < K; c0 += kStageBlobs) {
-        const int cn = min(kStageBlobs, K - c0);
-        __syncthreads();
-        if ((int)threadIdx.x < cn) {
-            const int k = c0 + threadIdx.x;
-            int r = 0;
-            while (rng_pre[r + 1] <= k) ++r;
-            const int i = perm[rng_lo[r] + (k - rng_pre[r])];
-            Staged s;
-            s.bx = base[3 * i];
-            s.by = base[3 * i + 1];
-            s.bz = base[3 * i + 2];
-            s.pad = 0;
+    // pass 0 counts per cell; pass 1 (mode 1) writes at the per-cell starts
+    for (int pass = 0; pass <= mode; ++pass) {
+        int cur[2] = {0, 0};
+        if (pass == 1) {
 #pragma unroll
-            for (int j = 0; j < 12; ++j) s.w[j] = wts[(size_t)i * 12 + j];
-            s.lam = (lam ? lam[i] : 0.0) + lam_shift;
-            stg[threadIdx.x] = s;
+            for (int e = 0; e < 2; ++e) cur[e] = offE[t] + nstart[threadIdx.x + e * blockDim.x];
         }
-        __syncthreads();
+        for (int c0 = 0; c0 < K; c0 += kStageBlobs) {
+            const int cn = min(kStageBlobs, K - c0);
+            __syncthreads();
+            if ((int)threadIdx.x < cn) {
+                const int k = c0 + threadIdx.x;
+                int r = 0;
+                while (rng_pre[r + 1] <= k) ++r;
+                const int i = perm[rng_lo[r] + (k - rng_pre[r])];
+                Cand c;
+                c.bx = base[3 * i];
+                c.by = base[3 * i + 1];
+                c.bz = base[3 * i + 2];
+                c.i = i;
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int lc = threadIdx.x + e * blockDim.x;
-            if (lc >= tcells) continue;
-            double a_ = acc[e];
-            for (int j = 0; j < cn; ++j) {
-                int a = cell[e][0] - stg[j].bx;
-                int b = cell[e][1] - stg[j].by;
-                int c = cell[e][2] - stg[j].bz;
-                a += a < 0 ? g.nx : 0;
-                b += b < 0 ? g.ny : 0;
-                c += c < 0 ? g.nz : 0;
-                if (a < 4 && b < 4 && c < 4) a_ += stg[j].w[a] * stg[j].w[4 + b] * stg[j].w[8 + c] * stg[j].lam;
+                for (int j = 0; j < 12; ++j) c.w[j] = wts[(size_t)i * 12 + j];
+                stg[threadIdx.x] = c;
             }
-            acc[e] = a_;
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int lc = threadIdx.x + e * blockDim.x;
+                if (lc >= tcells) continue;
+                for (int j = 0; j < cn; ++j) {
+                    int a = cell[e][0] - stg[j].bx;
+                    int b = cell[e][1] - stg[j].by;
+                    int c = cell[e][2] - stg[j].bz;
+                    a += a < 0 ? g.nx : 0;
+                    b += b < 0 ? g.ny : 0;
+                    c += c < 0 ? g.nz : 0;
+                    if (a < 4 && b < 4 && c < 4) {
+                        const double wv = stg[j].w[a] * stg[j].w[4 + b] * stg[j].w[8 + c];
+                        if (wv != 0.0) {
+                            if (pass == 1) {
+                                tblob[cur[e]] = stg[j].i;
+                                tw[cur[e]] = wv;
+                                ++cur[e];
+                            } else {
+                                ++n[e];
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        if (pass == 0) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) ncount[threadIdx.x + e * blockDim.x] = n[e];
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int se = 0, sc = 0;
+                for (int lc = 0; lc < tcells; ++lc) {
+                    nstart[lc] = se;
+                    crank[lc] = sc;
+                    se += ncount[lc];
+                    sc += ncount[lc] > 0 ? 1 : 0;
+                }
+                nstart[tcells] = se;
+                crank[tcells] = sc;
+                if (mode == 0) {
+                    cnt[t] = se;
+                    cnt[ntiles + t] = sc;
+                }
+            }
+            __syncthreads();
+            if (mode == 1) {
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int lc = threadIdx.x + e * blockDim.x;
+                    if (lc < tcells && ncount[lc] > 0) {
+                        const int slot = offC[t] + crank[lc];
+                        tcell[slot] = (cell[e][2] * g.ny + cell[e][1]) * g.nx + cell[e][0];
+                        tptr[slot] = offE[t] + nstart[lc];
+                    }
+                }
+                if (t == ntiles - 1 && threadIdx.x == 0) tptr[offC[ntiles]] = offE[ntiles];
+            }
         }
     }
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const int lc = threadIdx.x + e * blockDim.x;
-        if (lc >= tcells) continue;
-        const size_t idx = ((size_t)cell[e][2] * g.ny + cell[e][1]) * g.nx + cell[e][0];
-        const double b = base_in ? base_in[idx] : 0.0;
-        out[idx] = b + scale * acc[e];
-    }
 }
 
-__global__ void __launch_bounds__(kBlock) k_spread(const double* __restrict__ lam, double lam_shift, BlobGeom g,
-                                                   const int* __restrict__ base, const double* __restrict__ wts,
-                                                   const int* __restrict__ offsets, const int* __restrict__ perm,
-                                                   const double* base_in, double* out, double scale, int add_only,
-                                                   const Scalars* sc) {
-    if (sc && sc->done) return;
-    spread_body(lam, lam_shift, g, base, wts, offsets, perm, base_in, out, scale, add_only, Blk{blockIdx.x, gridDim.x});
-}
-
-// Batched blob term of B = alpha I - D L + S kappa J inside a CG iteration:
-// jx = J p, mu = kappa jx (interp), then q += h^-3 S mu (spread, touched tiles only).
-__global__ void __launch_bounds__(kBlock) kb_interp(const InstDev* inst, const int* gate, const BatchTab* tab) {
-    const BatchEntry* ent = tab_entries(tab);
-    for (unsigned g = blockIdx.x; g < tab->total; g += gridDim.x) {
-        Blk blk;
-        const InstDev* I = batch_slot(inst, gate, ent, tab->n, g, blk);
-        if (!I || !I->blobs) continue;
-        interp_body(I->p, I->N, I->geom, I->base, I->wts, I->perm, I->jx, I->kappa, I->mu, blk);
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) kb_spread(const InstDev* inst, const int* gate, const BatchTab* tab) {
-    const BatchEntry* ent = tab_entries(tab);
-    for (unsigned g = blockIdx.x; g < tab->total; g += gridDim.x) {
-        Blk blk;
-        const InstDev* I = batch_slot(inst, gate, ent, tab->n, g, blk);
-        if (!I || !I->blobs) continue;
-        spread_body(I->mu, 0.0, I->geom, I->base, I->wts, I->offsets, I->perm, I->q, I->q, I->inv_h3, 1, blk);
-        __syncthreads();  // staging arrays are reused by the next virtual block
-    }
-}
-
-void launchb_blob(hipStream_t st, int spread, const InstDev* inst, const int* gate, const BatchTab* tab,
-                  unsigned grid) {
-    if (spread) hipLaunchKernelGGL(kb_spread, dim3(grid), dim3(kBlock), 0, st, inst, gate, tab);
-    else hipLaunchKernelGGL(kb_interp, dim3(grid), dim3(kBlock), 0, st, inst, gate, tab);
-}
-
-void launch_spread(hipStream_t st, const double* lam, double lam_shift, int N, BlobGeom g, const int* base,
-                   const double* wts, const int* offsets, const int* perm, const double* base_in, double* out,
-                   double scale, int add_only, const Scalars* sc) {
+void launch_spread_plan(hipStream_t st, int mode, BlobGeom g, const int* base, const double* wts, const int* offsets,
+                        const int* perm, int* cnt, const int* offE, const int* offC, int* tcell, int* tptr,
+                        int* tblob, double* tw) {
     const unsigned nt = (unsigned)g.ntx * g.nty * g.ntz;
-    hipLaunchKernelGGL(k_spread, dim3(nt), dim3(kBlock), 0, st, lam, lam_shift, g, base, wts, offsets, perm, base_in,
-                       out, scale, add_only, sc);
+    hipLaunchKernelGGL(k_spread_plan, dim3(nt), dim3(kBlock), 0, st, mode, g, base, wts, offsets, perm, cnt, offE, offC,
+                       tcell, tptr, tblob, tw);
+}
+
+// out[c] = base(c) + scale * sum_e tw[e] (lam[tblob[e]] + lam_shift) over the
+// touched cells c (base(c) = base_in[c], 0 without base_in); other cells are
+// not touched (the caller's dense pass set them, or base_in aliases out).
+__global__ void __launch_bounds__(kBlock) k_spread_sparse(const double* __restrict__ lam, double lam_shift,
+                                                          int ntouched, const int* __restrict__ tcell,
+                                                          const int* __restrict__ tptr, const int* __restrict__ tblob,
+                                                          const double* __restrict__ tw, const double* base_in,
+                                                          double* out, double scale, const Scalars* sc) {
+    if (sc && sc->done) return;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ntouched) return;
+    spread_sparse_cell(k, lam, lam_shift, tcell, tptr, tblob, tw, base_in, out, scale);
+}
+
+void launch_spread_sparse(hipStream_t st, const double* lam, double lam_shift, int ntouched, const int* tcell,
+                          const int* tptr, const int* tblob, const double* tw, const double* base_in, double* out,
+                          double scale, const Scalars* sc) {
+    if (ntouched <= 0) return;
+    hipLaunchKernelGGL(k_spread_sparse, dim3(nblocks(ntouched)), dim3(kBlock), 0, st, lam, lam_shift, ntouched, tcell,
+                       tptr, tblob, tw, base_in, out, scale, sc);
 }
 
 // ---------------------------------------------------------------------------
@@ -425,14 +533,16 @@ void launch_gmres_start(hipStream_t st, const double* b, const double* w, int ha
     hipLaunchKernelGGL(k_gmres_start, dim3(1), dim3(kFinBlock), 0, st, b, w, has_w, V, g, N, gs);
 }
 
-// Arnoldi step k with modified Gram-Schmidt: V_{k+1} holds G v_k on entry.
+// Arnoldi step k with modified Gram-Schmidt: V_{k+1} holds G v_k on entry
+// (with project, its mean is removed first, as k_nvec_project does).
 // H is (m+1) x m row-major; Givens rotations (cs, sn) update g.
 // Elements of an N-vector a work-group thread keeps in registers during the
 // modified Gram-Schmidt sweep (N <= kArnoldiRegs * kFinBlock).
 constexpr int kArnoldiRegs = 12;
 
 __global__ void __launch_bounds__(kFinBlock) k_gmres_arnoldi(double* V, double* H, double* cs, double* sn,
-                                                             double* gvec, int N, int k, int m, GmresScalars* gs) {
+                                                             double* gvec, int N, int k, int m, GmresScalars* gs,
+                                                             int project) {
     double* w = V + (size_t)(k + 1) * N;
     double hk1;
     if (N <= kArnoldiRegs * (int)blockDim.x) {
@@ -443,6 +553,15 @@ __global__ void __launch_bounds__(kFinBlock) k_gmres_arnoldi(double* V, double* 
         for (int c = 0; c < kArnoldiRegs; ++c) {
             const int i = threadIdx.x + c * blockDim.x;
             wr[c] = i < N ? w[i] : 0.0;
+        }
+        if (project) {
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < kArnoldiRegs; ++c) s += wr[c];
+            const double mean = wg_sum(s) / (double)N;
+#pragma unroll
+            for (int c = 0; c < kArnoldiRegs; ++c)
+                if (threadIdx.x + c * blockDim.x < N) wr[c] -= mean;
         }
         for (int j = 0; j <= k; ++j) {
             const double* vj = V + (size_t)j * N;
@@ -472,6 +591,12 @@ __global__ void __launch_bounds__(kFinBlock) k_gmres_arnoldi(double* V, double* 
             if (i < N) w[i] = wr[c] * inv;
         }
     } else {
+        if (project) {
+            double s = 0.0;
+            for (int i = threadIdx.x; i < N; i += blockDim.x) s += w[i];
+            const double mean = wg_sum(s) / (double)N;
+            for (int i = threadIdx.x; i < N; i += blockDim.x) w[i] -= mean;
+        }
         for (int j = 0; j <= k; ++j) {
             const double* vj = V + (size_t)j * N;
             double s = 0.0;
@@ -509,8 +634,8 @@ __global__ void __launch_bounds__(kFinBlock) k_gmres_arnoldi(double* V, double* 
 }
 
 void launch_gmres_arnoldi(hipStream_t st, double* V, double* H, double* cs, double* sn, double* g, int N, int k,
-                          int m, GmresScalars* gs) {
-    hipLaunchKernelGGL(k_gmres_arnoldi, dim3(1), dim3(kFinBlock), 0, st, V, H, cs, sn, g, N, k, m, gs);
+                          int m, GmresScalars* gs, int project) {
+    hipLaunchKernelGGL(k_gmres_arnoldi, dim3(1), dim3(kFinBlock), 0, st, V, H, cs, sn, g, N, k, m, gs, project);
 }
 
 // x += V y with H y = g (upper-triangular k x k), y solved by thread 0.

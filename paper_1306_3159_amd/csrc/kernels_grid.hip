@@ -286,6 +286,12 @@ template void launch_zdots2<double>(hipStream_t, const double*, const double*, c
 void launch_applyA_plain(hipStream_t st, const double* x, double* y, double alpha, double s, int nx, int ny,
                          int nz) {
     const unsigned n = (unsigned)nx * ny * nz;
+    if (nx % 2 == 0) {  // two cells per thread, the same arithmetic
+        const unsigned npair = n / 2;
+        hipLaunchKernelGGL(k_applyA2, dim3(nblocks(npair)), dim3(kBlock), 0, st, x, y, alpha, s, nx, ny, nz, npair,
+                           (double*)nullptr, (const Scalars*)nullptr);
+        return;
+    }
     hipLaunchKernelGGL(k_applyA, dim3(nblocks(n)), dim3(kBlock), 0, st, x, y, alpha, s, nx, ny, nz, n,
                        (double*)nullptr, (const Scalars*)nullptr);
 }
@@ -349,12 +355,6 @@ void launch_residual_from_q(hipStream_t st, const double* g, const double* q0, d
 }
 
 // Split-layout value at natural (X, Y, Z) of level 0.
-template <typename T>
-__device__ __forceinline__ double split_at(const T* __restrict__ z0, const T* __restrict__ z1, int X, int Y, int Z,
-                                           int hx, int ny) {
-    const size_t j = ((size_t)Z * ny + Y) * hx + (X >> 1);
-    return ((X + Y + Z) & 1) ? (double)z1[j] : (double)z0[j];
-}
 
 // out = scale * out + z   (z split -> natural)
 template <typename T>

@@ -142,19 +142,29 @@ void launch_bin_sort(hipStream_t st, const int* offsets, int ntiles, int* perm);
 // out[i] = scale_i * (J x)_i, scale = kappa (if non-null) ; jx (optional) gets (J x)_i
 void launch_interp(hipStream_t st, const double* x, int N, BlobGeom g, const int* base, const double* wts,
                    const int* perm, double* jx, const double* kappa, double* out, const Scalars* sc);
-// out = base_in + scale * sum_i w_i lam_i   over the grid (gather by tiles);
-// add_only: out already holds base_in (aliased) and empty tiles are skipped.
-void launch_spread(hipStream_t st, const double* lam, double lam_shift, int N, BlobGeom g, const int* base,
-                   const double* wts, const int* offsets, const int* perm, const double* base_in, double* out,
-                   double scale, int add_only, const Scalars* sc);
+// out_i = (J z)_i for z held in a red/black split level-0 layout (z0, z1 of type T)
+template <typename T>
+void launch_interp_split(hipStream_t st, const T* z0, const T* z1, int N, BlobGeom g, const int* base,
+                         const double* wts, const int* perm, double* out);
+
+// contribution lists of the spread (mode 0: per-tile counts into cnt[0..2 ntiles);
+// mode 1: lists at the scanned offsets offE, offC)
+void launch_spread_plan(hipStream_t st, int mode, BlobGeom g, const int* base, const double* wts, const int* offsets,
+                        const int* perm, int* cnt, const int* offE, const int* offC, int* tcell, int* tptr,
+                        int* tblob, double* tw);
+// out[c] = base(c) + scale * sum (lam + lam_shift) w over the touched cells only
+void launch_spread_sparse(hipStream_t st, const double* lam, double lam_shift, int ntouched, const int* tcell,
+                          const int* tptr, const int* tblob, const double* tw, const double* base_in, double* out,
+                          double scale, const Scalars* sc);
 
 // ---- N-vector kernels (single work-group) ------------------------------------
 void launch_nvec_project(hipStream_t st, double* v, int N);  // v -= mean(v)
 void launch_nvec_copy_scale(hipStream_t st, const double* x, double* y, int N, double a, double shift);
 void launch_gmres_start(hipStream_t st, const double* b, const double* w, int has_w, double* V, double* g, int N,
                         GmresScalars* gs);
+// Arnoldi step k (V_{k+1} holds the product; project: remove its mean first)
 void launch_gmres_arnoldi(hipStream_t st, double* V, double* H, double* cs, double* sn, double* g, int N, int k,
-                          int m, GmresScalars* gs);
+                          int m, GmresScalars* gs, int project = 0);
 void launch_gmres_update(hipStream_t st, const double* V, const double* H, const double* g, double* y, double* x,
                          int N, int k, int m);
 void launch_nvec_sums(hipStream_t st, const double* a, const double* b, int N, double* out /*sum a, a.a, a.b*/);

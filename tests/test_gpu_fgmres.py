@@ -161,3 +161,73 @@ def test_fgmres_errors_and_limits(dev):
                                             ctypes.byref(Stats()))
     assert rc == -2  # workspace too small
     S.close()
+
+
+def _net(dev, p):
+    from paper_1306_3159_amd import Net
+    from oracle import learned as LN
+    net = Net(dev)
+    net.set_params(torch.as_tensor(LN.flatten(p), dtype=torch.float32, device=dev))
+    return net
+
+
+@pytest.mark.parametrize("trained", [False, True])
+def test_precond_parity_learned(dev, trained):
+    """Learned variant (inner GMRES right-preconditioned by P W P). Untrained network: W is
+    exactly the diagonal of eq. Schur_diagonal on both sides, so the FP64 handle matches the
+    oracle to 1e-9. Random weights: W itself differs by the BF16 activation rounding of the
+    network (about 1 %), which bounds the agreement."""
+    _say("saddle precond learned", trained)
+    from oracle import learned as LN
+    from paper_1306_3159_amd import PRECOND_LEARNED
+    rng = np.random.default_rng(75)
+    n, N = 32, 30
+    q = W.rsa_positions(rng, n, N, 3.0)
+    vg = rng.standard_normal((n, n, n))
+    vf = rng.standard_normal(N)
+    p = LN.init_params(5)
+    if trained:
+        p["b1"] = (0.1 * rng.standard_normal(64)).astype(np.float32)
+        p["w3"] = (0.05 * rng.standard_normal(64)).astype(np.float32)
+    net = _net(dev, p)
+    S = make(dev, n, q, precision=0, schur_precond=PRECOND_LEARNED)
+    S.precond_build(net)
+    zg, zl = S.saddle_precond(T(vg, dev), T(vf, dev), alpha=0.0, precond="learned", m=4)
+    ptr, col, val, _ = LN.assemble(LN.rounded(p), q, n)
+    ops = fg.SaddleOps(q, (n, n, n), 0.0)
+    inv = fg.cycles_inverse(ops, lambda r: it.vcycle(r, 0.0), 1)
+    cg, cl = fg.precondition(ops, vg, vf, "learned", inv, inv, m=4, w_apply=lambda v: LN.apply(ptr, col, val, v))
+    tol = 5e-2 if trained else 1e-9
+    assert rel(H(zg), cg) < tol and rel(H(zl), cl) < tol
+    S.close()
+    net.close()
+
+
+def test_fgmres_learned_solve_and_fallback(dev):
+    """Learned block preconditioner: the solve reaches the tolerance and the exact answer; for
+    alpha > 0 (the network approximates the steady Schur complement) and on a handle without a
+    built W it falls back to the plain approximate-Schur variant and says so."""
+    _say("fgmres learned solve")
+    from oracle import learned as LN
+    from paper_1306_3159_amd import PRECOND_LEARNED
+    rng = np.random.default_rng(76)
+    n, N = 32, 30
+    q = W.rsa_positions(rng, n, N, 3.0)
+    f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
+    p = LN.init_params(6)
+    p["w3"] = (0.05 * rng.standard_normal(64)).astype(np.float32)
+    net = _net(dev, p)
+    S = make(dev, n, q, precision=1, schur_precond=PRECOND_LEARNED, rtol=1e-8)
+    S.precond_build(net)
+    for alpha in (0.0, 1.0 / n ** 2):
+        ce, le = ex.solve_absorbing(f, q, alpha)
+        c, lam, st = S.solve_absorbing_fgmres(T(f, dev), alpha=alpha, precond="learned")
+        assert st["rc"] == 0 and st["fallback"] == (1 if alpha > 0 else 0), st
+        assert ex.absorbing_residual(H(c), H(lam), f, q, alpha) <= 1e-8
+        assert rel(H(lam), le) < 1e-6
+    S.close()
+    S2 = make(dev, n, q, precision=1, rtol=1e-8)
+    c, lam, st = S2.solve_absorbing_fgmres(T(f, dev), precond="learned")
+    assert st["rc"] == 0 and st["fallback"] == 1
+    S2.close()
+    net.close()

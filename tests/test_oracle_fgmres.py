@@ -72,6 +72,26 @@ def test_precond_schur_exact_with_enough_inner_iterations(alpha):
     assert _residual(ops, c2, lam2, vg, vf) > 1e-6  # truncated inner solve is approximate
 
 
+@pytest.mark.parametrize("alpha", [0.0, 0.3])
+def test_precond_learned_exact_with_exact_schur_inverse(alpha):
+    """Learned variant: when W is the exact inverse of the (projected) Schur complement, one
+    inner iteration solves eq. approx_Schur (the preconditioned operator is the identity on
+    the multiplier space) and, with exact inner solves, the preconditioner is exact."""
+    rng, ops, vg, vf = _setup(12, 5, alpha, 38)
+    G = ex.schur_matrix(ops.q, ops.shape, alpha)
+    if alpha == 0.0:
+        P = np.eye(5) - 1.0 / 5
+        Winv = np.linalg.pinv(P @ G @ P)
+    else:
+        Winv = np.linalg.inv(G)
+    inv = fg.cycles_inverse(ops, ops.exact_inverse(), 1)
+    c, lam = fg.precondition(ops, vg, vf, "learned", inv, inv, m=1, w_apply=lambda v: Winv @ v)
+    assert _residual(ops, c, lam, vg, vf) < 1e-10
+    # a poor W needs more inner iterations
+    c, lam = fg.precondition(ops, vg, vf, "learned", inv, inv, m=1, w_apply=lambda v: 3.0 * v - v.mean())
+    assert _residual(ops, c, lam, vg, vf) > 1e-6
+
+
 def test_gmres_fixed_is_minimal_residual():
     """gmres_fixed: the minimiser over the Krylov space, by brute force (QR of the explicit
     Krylov matrix and least squares)."""
