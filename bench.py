@@ -3,15 +3,18 @@
 Default workload (the learned Schur preconditioner case): a 256^3 periodic
 grid with 10^4 absorbing blobs placed by random sequential addition
 (minimum separation 3h), four-point kernel, uniform source f = 1, steady
-diffusion-limited saddle point solved by Schur-complement GMRES(30) with
-inner multigrid-preconditioned CG, to a 1e-8 relative residual.
+diffusion-limited saddle point, to a 1e-8 relative residual.
 
 A step is one full absorbing solve with inputs resident in device memory.
-`value` is the learned + FP32 path: FP32 V-cycles under FP64 CG/GMRES with
-FP64 residuals and refinement, right-preconditioned by the trained network
-(weights in paper_1306_3159_amd/weights). Beside it: the same solve in plain
-FP64 (FP64 V-cycles, no learned part) and with FP32 V-cycles alone, and the
-128^3 lattice workload (8^3 blobs 16h apart, random source) as an extra line.
+`value` is the fastest learned + FP32 solver: flexible GMRES(30) on the
+whole block system with the paper's approximate-Schur preconditioner (m = 5
+inner GMRES iterations, one FP32 V-cycle per product, n = 1), the inner
+GMRES right-preconditioned by the trained network (weights in
+paper_1306_3159_amd/weights); FP64 Krylov vectors and true FP64 residuals.
+Beside it: Schur-complement GMRES(30) with inner multigrid-preconditioned CG
+(learned + FP32, FP32 alone, and plain FP64: FP64 V-cycles, no learned part,
+the comparison baseline), the block solver without the network in FP32 and
+FP64, and the 128^3 lattice workload (8^3 blobs 16h apart, random source).
 
 Prints ONE JSON line.
 """
@@ -81,10 +84,13 @@ def timed(fn, steps, warmup):
     return time.perf_counter() - t0, st
 
 
-def summary(st):
-    return {"gmres_iters": st["outer_iters"], "inner_cg_iters": st["inner_iters_total"], "vcycles": st["vcycles"],
-            "rel_resid": st["rel_resid"], "refinements": st["refinements"], "fallback": st["fallback"],
-            "alg_bytes": st["alg_bytes"]}
+def summary(st, block=False):
+    """Iteration counts of a solve: Schur GMRES with inner CG, or (block) flexible GMRES on the
+    block system with inner GMRES iterations of the approximate-Schur preconditioner."""
+    it = {"fgmres_iters": st["outer_iters"], "inner_gmres_iters": st["inner_iters_total"]} if block else \
+        {"gmres_iters": st["outer_iters"], "inner_cg_iters": st["inner_iters_total"]}
+    return {**it, "vcycles": st["vcycles"], "rel_resid": st["rel_resid"], "refinements": st["refinements"],
+            "fallback": st["fallback"], "alg_bytes": st["alg_bytes"]}
 
 
 # Grids up to 64^3 are launch-latency-bound and share the lock-step batched
@@ -190,44 +196,63 @@ def main():
     if args.autotune:
         S.autotune(reps=10)
         tuning = S.get_tuning().tolist()
-    dt, st = timed(lambda: S.solve_absorbing(f)[2], args.steps, args.warmup)
-    value = args.steps / dt
     learned = args.workload == "rsa256_learned"
+    if learned:
+        # block FGMRES, approximate-Schur preconditioner with the learned inner preconditioning
+        dt, st = timed(lambda: S.solve_absorbing_fgmres(f, precond="learned", m=5, n=1, restart=30)[2], args.steps,
+                       args.warmup)
+    else:
+        dt, st = timed(lambda: S.solve_absorbing(f)[2], args.steps, args.warmup)
+    value = args.steps / dt
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64 Krylov/residuals + f32 V-cycles"
         + (" + bf16 network" if learned else ""), "data": "synthetic",
         "config": {"workload": args.workload, "n": inst.n, "N": inst.N, "kind": "absorbing", "rtol": rtol,
-                   "kernel_w": 4, "gmres_restart": 30, "path": "learned+fp32" if learned else "fp32",
+                   "kernel_w": 4, "restart": 30,
+                   "path": "block FGMRES + approximate Schur (m=5, n=1) with learned inner preconditioning + fp32"
+                   if learned else "Schur GMRES + inner MG-CG + fp32",
                    "source": "f=1" if learned else "f=1+0.5N(0,1)", "seed": inst.seed},
-        "solve": summary(st),
+        "solve": summary(st, block=learned),
         "tuning": tuning,
     }
     out["solve"]["alg_GBs"] = st["alg_bytes"] / (dt / args.steps) / 1e9
 
     if not args.no_extra:
+        n = max(2, args.steps // 2)
         P = BlobRD(inst.n, q, precision=FP64, rtol=rtol)
         if args.autotune:
             P.autotune(reps=10)
-        pdt, pst = timed(lambda: P.solve_absorbing(f)[2], max(2, args.steps // 2), 1)
-        n = max(2, args.steps // 2)
-        out["plain_fp64"] = {"value": n / pdt, "ms_per_step": 1e3 * pdt / n, **summary(pst)}
+        pdt, pst = timed(lambda: P.solve_absorbing(f)[2], n, 1)
+        out["plain_fp64"] = {"solver": "Schur GMRES + inner MG-CG, FP64 V-cycles, no learned part",
+                             "value": n / pdt, "ms_per_step": 1e3 * pdt / n, **summary(pst)}
         out["speedup_vs_plain_fp64"] = value / out["plain_fp64"]["value"]
+        if learned:
+            bdt, bst = timed(lambda: P.solve_absorbing_fgmres(f, precond="schur")[2], n, 1)
+            out["block_fgmres_fp64"] = {"value": n / bdt, "ms_per_step": 1e3 * bdt / n, **summary(bst, True)}
         P.close()
         if learned:
+            sdt, sst = timed(lambda: S.solve_absorbing(f)[2], n, 1)
+            out["schur_gmres_learned_fp32"] = {"value": n / sdt, "ms_per_step": 1e3 * sdt / n, **summary(sst)}
             M = BlobRD(inst.n, q, precision=MIXED, rtol=rtol)
             if args.autotune:
                 M.autotune(reps=10)
             mdt, mst = timed(lambda: M.solve_absorbing(f)[2], n, 1)
-            out["fp32_no_learned"] = {"value": n / mdt, "ms_per_step": 1e3 * mdt / n, **summary(mst)}
+            out["schur_gmres_fp32"] = {"value": n / mdt, "ms_per_step": 1e3 * mdt / n, **summary(mst)}
+            cdt, cst = timed(lambda: M.solve_absorbing_fgmres(f, precond="schur")[2], n, 1)
+            out["block_fgmres_fp32"] = {"value": n / cdt, "ms_per_step": 1e3 * cdt / n, **summary(cst, True)}
             M.close()
             lat = W.cubic_lattice(random_f=True)
+            lf = torch.tensor(lat.f, device=dev)
             L = BlobRD(lat.n, torch.tensor(lat.q, device=dev), precision=MIXED, rtol=rtol)
-            ldt, lst = timed(lambda: L.solve_absorbing(torch.tensor(lat.f, device=dev))[2], 5, 1)
+            ldt, lst = timed(lambda: L.solve_absorbing(lf)[2], 5, 1)
+            lbdt, lbst = timed(lambda: L.solve_absorbing_fgmres(lf, precond="schur")[2], 5, 1)
             L2 = BlobRD(lat.n, torch.tensor(lat.q, device=dev), precision=FP64, rtol=rtol)
-            l2dt, l2st = timed(lambda: L2.solve_absorbing(torch.tensor(lat.f, device=dev))[2], 5, 1)
-            out["lattice128_randf"] = {"fp32_value": 5 / ldt, "plain_fp64_value": 5 / l2dt, **summary(lst)}
+            l2dt, l2st = timed(lambda: L2.solve_absorbing(lf)[2], 5, 1)
+            out["lattice128_randf"] = {"fp32_value": 5 / ldt, "plain_fp64_value": 5 / l2dt,
+                                       "block_fgmres_fp32_value": 5 / lbdt, **summary(lst),
+                                       "block_fgmres": summary(lbst, True)}
             L.close()
             L2.close()
 
