@@ -2751,16 +2751,31 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
         double* Hm = H->at<double>(P.off_H);
         double* gv = H->at<double>(P.off_gv);
         launch_gmres_start(st, hv, nullptr, 0, V, gv, N, H->gs());
-        const T* z0 = H->at<T>(P.off_lvl[0][0]);
-        const T* z1 = H->at<T>(P.off_lvl[0][1]);
+        T* z0 = H->at<T>(P.off_lvl[0][0]);
+        T* z1 = H->at<T>(P.off_lvl[0][1]);
+        T* f0 = H->at<T>(P.off_lvl[0][2]);
+        T* f1 = H->at<T>(P.off_lvl[0][3]);
+        const LevelDims& d = P.lev[0];
+        const size_t nh = P.ncell / 2;
+        const double inv_diag = 1.0 / (alpha + 6.0 * H->prm.D / (d.h * d.h));
         for (int k = 0; k < o.m; ++k) {
             const double* vk = V + (size_t)k * N;
             if (learned) {
                 precond_apply(H, vk, H->nv(9));
                 vk = H->nv(9);
             }
-            fg_spread(H, vk, nullptr, H->grid(G_T2), H->inv_h3(), 0);
-            vcycle<T>(H, alpha, H->grid(G_T2), nullptr, cinv);
+            // S v enters the V-cycle from the contribution lists: level-0 f is zero
+            // outside the touched cells after the first product of the loop
+            launch_zero<T>(st, z0, nh);
+            if (k == 0) {
+                launch_zero<T>(st, f0, nh);
+                launch_zero<T>(st, f1, nh);
+            }
+            launch_spread_enter<T>(st, vk, H->ntouched, H->at<int>(P.off_tcell), H->at<int>(P.off_tptr),
+                                   H->at<int>(P.off_tblob), H->at<double>(P.off_tw), H->inv_h3(), f0, f1, z0, d.nx,
+                                   d.ny, inv_diag);
+            H->alg_bytes += (double)nh * P.esz * (k == 0 ? 3 : 1);
+            vcycle<T>(H, alpha, nullptr, nullptr, cinv, true);
             launch_interp_split<T>(st, z0, z1, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
                                    H->at<int>(P.off_perm), V + (size_t)(k + 1) * N);
             launch_gmres_arnoldi(st, V, Hm, H->at<double>(P.off_cs), H->at<double>(P.off_sn), gv, N, k, o.m,

@@ -452,6 +452,63 @@ void launch_spread_sparse(hipStream_t st, const double* lam, double lam_shift, i
                        tptr, tblob, tw, base_in, out, scale, sc);
 }
 
+// V-cycle entry straight from the contribution lists: the right-hand side
+// r = h^-3 scale S lam is nonzero only on touched cells, so its split level-0
+// copy f and the first red half-sweep from zero (u_red = f_red / diag) are
+// written there only; the caller has zeroed u0 (and f0, f1 unless they hold
+// zeros outside the touched cells from a previous entry of the same lists).
+// Bitwise the spread into a zeroed grid followed by k_enter.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_spread_enter(const double* __restrict__ lam, int ntouched,
+                                                         const int* __restrict__ tcell, const int* __restrict__ tptr,
+                                                         const int* __restrict__ tblob, const double* __restrict__ tw,
+                                                         double scale, T* __restrict__ f0, T* __restrict__ f1,
+                                                         T* __restrict__ u0, int nx, int ny, double inv_diag) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ntouched) return;
+    double acc = 0.0;
+    for (int e = tptr[k]; e < tptr[k + 1]; ++e) acc += tw[e] * (lam[tblob[e]] + 0.0);
+    const double r = 0.0 + scale * acc;
+    const int c = tcell[k];
+    const int X = c % nx;
+    const int t = c / nx;
+    const int Y = t % ny, Z = t / ny;
+    const size_t j = ((size_t)Z * ny + Y) * (nx >> 1) + (X >> 1);
+    if ((X + Y + Z) & 1) {
+        f1[j] = (T)r;
+    } else {
+        f0[j] = (T)r;
+        u0[j] = (T)((T)r * (T)inv_diag);
+    }
+}
+
+template <typename T>
+void launch_spread_enter(hipStream_t st, const double* lam, int ntouched, const int* tcell, const int* tptr,
+                         const int* tblob, const double* tw, double scale, T* f0, T* f1, T* u0, int nx, int ny,
+                         double inv_diag) {
+    if (ntouched <= 0) return;
+    hipLaunchKernelGGL(k_spread_enter<T>, dim3(nblocks(ntouched)), dim3(kBlock), 0, st, lam, ntouched, tcell, tptr,
+                       tblob, tw, scale, f0, f1, u0, nx, ny, inv_diag);
+}
+template void launch_spread_enter<float>(hipStream_t, const double*, int, const int*, const int*, const int*,
+                                         const double*, double, float*, float*, float*, int, int, double);
+template void launch_spread_enter<double>(hipStream_t, const double*, int, const int*, const int*, const int*,
+                                          const double*, double, double*, double*, double*, int, int, double);
+
+template <typename T>
+__global__ void k_zero(T* __restrict__ p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (T)0;
+}
+
+template <typename T>
+void launch_zero(hipStream_t st, T* p, size_t n) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_zero<T>, dim3(nblocks(n)), dim3(kBlock), 0, st, p, n);
+}
+template void launch_zero<float>(hipStream_t, float*, size_t);
+template void launch_zero<double>(hipStream_t, double*, size_t);
+
 // ---------------------------------------------------------------------------
 // N-vector kernels: one work-group of kFinBlock threads, fixed reduction order.
 __device__ __forceinline__ double wg_sum(double s) {

@@ -157,6 +157,16 @@ void launch_spread_sparse(hipStream_t st, const double* lam, double lam_shift, i
                           const int* tptr, const int* tblob, const double* tw, const double* base_in, double* out,
                           double scale, const Scalars* sc);
 
+// V-cycle entry of r = scale S lam from the contribution lists (split f at the
+// touched cells, u_red = f_red / diag there); u0, and f0/f1 outside the touched
+// cells, must already be zero
+template <typename T>
+void launch_spread_enter(hipStream_t st, const double* lam, int ntouched, const int* tcell, const int* tptr,
+                         const int* tblob, const double* tw, double scale, T* f0, T* f1, T* u0, int nx, int ny,
+                         double inv_diag);
+template <typename T>
+void launch_zero(hipStream_t st, T* p, size_t n);
+
 // ---- N-vector kernels (single work-group) ------------------------------------
 void launch_nvec_project(hipStream_t st, double* v, int N);  // v -= mean(v)
 void launch_nvec_copy_scale(hipStream_t st, const double* x, double* y, int N, double a, double shift);
