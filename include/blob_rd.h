@@ -287,6 +287,11 @@ int blob_rd_precond_loss_grad(blob_rd_t h, blob_rd_net_t net, const double* X, c
  * identity otherwise): one Schur-complement product with an inner
  * multigrid-CG solve to relative tolerance inner_rtol (eq. r_schur). */
 int blob_rd_schur_apply(blob_rd_t h, double alpha, const double* x, double* y, double inner_rtol);
+/* y = P J A_n^{-1} S P x with A_n^{-1} n multigrid cycles from a zero guess in
+ * the handle's precision (1 <= cycles <= 64): the Schur operator of eq.
+ * approx_Schur that the inner GMRES of the paper's approximate-Schur
+ * preconditioner applies (the learned W can be trained against it). */
+int blob_rd_schur_apply_cycles(blob_rd_t h, double alpha, const double* x, double* y, int cycles);
 
 /* ---- Batches of independent suspensions ----
  *

@@ -2911,6 +2911,27 @@ int blob_rd_solve_absorbing_fgmres(blob_rd_t H, double alpha, const blob_rd_sadd
     });
 }
 
+int blob_rd_schur_apply_cycles(blob_rd_t H, double alpha, const double* x, double* y, int cycles) {
+    if (!H || !x || !y || H->P.N <= 0) return g_last_error = "bad argument", BLOB_RD_EINVAL;
+    if (!(alpha >= 0.0) || !std::isfinite(alpha) || cycles < 1 || cycles > 64)
+        return g_last_error = "bad alpha or cycle count", BLOB_RD_EINVAL;
+    return guarded(H, nullptr, [&]() {
+        const Plan& P = H->P;
+        double* xt = H->nv(2);
+        launch_nvec_copy_scale(H->st, x, xt, P.N, 1.0, 0.0);
+        if (alpha == 0.0) launch_nvec_project(H->st, xt, P.N);
+        spread_to(H, xt, 0.0, nullptr, H->grid(G_T2), H->inv_h3(), nullptr);
+        const double* cinv = select_cinv(H, alpha);
+        if (P.esz == 4) fg_cycles<float>(H, alpha, H->grid(G_T2), H->grid(G_U), true, cycles, cinv);
+        else fg_cycles<double>(H, alpha, H->grid(G_T2), H->grid(G_U), true, cycles, cinv);
+        fg_interp(H, H->grid(G_U), y);
+        if (alpha == 0.0) launch_nvec_project(H->st, y, P.N);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(H->st));
+        return BLOB_RD_OK;
+    });
+}
+
 int blob_rd_saddle_precond(blob_rd_t H, double alpha, const blob_rd_saddle_opts* opts, const double* vg,
                            const double* vf, double* zg, double* zl) {
     if (!H || !vg || !vf || !zg || !zl) return g_last_error = "null argument", BLOB_RD_EINVAL;

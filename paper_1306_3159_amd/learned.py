@@ -63,14 +63,19 @@ def sample_vectors(q: np.ndarray, box, n_samples: int, seed: int, smooth_fractio
 
 
 def harvest(shape, q: np.ndarray, n_samples: int, seed: int, device, inner_rtol: float = 1e-8,
-            precision: int = MIXED, smooth_fraction: float = 0.5, h: float = 1.0) -> Sample:
-    """Schur products of seeded sample vectors for one configuration."""
+            precision: int = MIXED, smooth_fraction: float = 0.5, h: float = 1.0, cycles: int = 0) -> Sample:
+    """Schur products of seeded sample vectors for one configuration: with inner solves to
+    inner_rtol (cycles = 0), or the approximate-Schur operator with `cycles` multigrid cycles
+    per product (the operator the block preconditioner's inner GMRES applies)."""
     dims = (shape,) * 3 if isinstance(shape, int) else tuple(shape)
     box = (dims[2] * h, dims[1] * h, dims[0] * h)      # (x, y, z) edges
     X = sample_vectors(q, box, n_samples, seed, smooth_fraction)
     Xd = torch.tensor(X, device=device)
     S = BlobRD(shape, torch.tensor(q, device=device), precision=precision)
-    Y = torch.stack([S.schur_apply(Xd[s], 0.0, inner_rtol) for s in range(n_samples)])
+    if cycles > 0:
+        Y = torch.stack([S.schur_apply_cycles(Xd[s].contiguous(), 0.0, cycles) for s in range(n_samples)])
+    else:
+        Y = torch.stack([S.schur_apply(Xd[s], 0.0, inner_rtol) for s in range(n_samples)])
     S.close()
     return Sample(tuple(shape) if not isinstance(shape, int) else (shape,) * 3, q, Xd, Y)
 
@@ -108,6 +113,25 @@ def train(net: Net, samples: List[Sample], epochs: int, lr: float, batch: int, d
         if log:
             log(f"epoch {ep}: loss {hist[-1]:.5f} ({time.time() - t0:.1f}s)")
     return hist
+
+
+def block_iterations(shape, q: np.ndarray, f: torch.Tensor, net: Optional[Net], device, rtol: float = 1e-8,
+                     precision: int = MIXED, m: int = 5):
+    """Block FGMRES iterations and wall time of one absorbing solve with the approximate-Schur
+    preconditioner, its inner GMRES preconditioned by W (net) or not."""
+    S = BlobRD(shape, torch.tensor(q, device=device), precision=precision, rtol=rtol,
+               schur_precond=PRECOND_LEARNED if net is not None else PRECOND_NONE)
+    if net is not None:
+        S.precond_build(net)
+    kind = "learned" if net is not None else "schur"
+    S.solve_absorbing_fgmres(f, precond=kind, m=m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c, lam, st = S.solve_absorbing_fgmres(f, precond=kind, m=m)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    S.close()
+    return st, dt, c, lam
 
 
 def gmres_iterations(shape, q: np.ndarray, f: torch.Tensor, net: Optional[Net], device, rtol: float = 1e-8,

@@ -144,6 +144,8 @@ def load_library(path: str = LIB_PATH):
     L.blob_rd_precond_csr.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), vp, vp, vp]
     L.blob_rd_precond_loss_grad.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.POINTER(d)]
     L.blob_rd_schur_apply.argtypes = [vp, d, vp, vp, d]
+    L.blob_rd_schur_apply_cycles.argtypes = [vp, d, vp, vp, i32]
+    L.blob_rd_schur_apply_cycles.restype = i32
     L.blob_rd_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), d,
                                       ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int32, S]
     L.blob_rd_solve_batch.restype = i32
@@ -475,6 +477,13 @@ class BlobRD:
         y = torch.empty(self.N, dtype=torch.float64, device=self.device)
         self._check(self._lib.blob_rd_schur_apply(self._h, float(alpha), _ptr(x.contiguous()), _ptr(y),
                                                   float(inner_rtol)))
+        return y
+
+    def schur_apply_cycles(self, x: torch.Tensor, alpha: float = 0.0, cycles: int = 1) -> torch.Tensor:
+        """y = P J A_n^{-1} S P x with n multigrid cycles (the approximate-Schur operator)."""
+        self._nvec(x, "x")
+        y = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        self._check(self._lib.blob_rd_schur_apply_cycles(self._h, float(alpha), _ptr(x), _ptr(y), int(cycles)))
         return y
 
 

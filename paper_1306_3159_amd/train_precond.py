@@ -56,6 +56,9 @@ def main(argv=None):
     ap.add_argument("--lr-final", type=float, default=None,
                     help="cosine-decay the learning rate to this value over the epochs (default: constant)")
     ap.add_argument("--workers", type=int, default=1, help="host processes generating the configurations")
+    ap.add_argument("--cycles", type=int, default=0,
+                    help="train against the approximate-Schur operator with this many multigrid cycles per product "
+                         "(the block preconditioner's inner operator); 0: Schur products with inner solves")
     args = ap.parse_args(argv)
 
     import torch
@@ -74,7 +77,8 @@ def main(argv=None):
     else:
         positions = (_positions((i, args.n, args.blobs)) for i in range(args.configs))
     for i, q in enumerate(positions):
-        samples.append(LD.harvest(args.n, q, args.samples, 1306_700_000 + i, dev, smooth_fraction=args.smooth))
+        samples.append(LD.harvest(args.n, q, args.samples, 1306_700_000 + i, dev, smooth_fraction=args.smooth,
+                                  cycles=args.cycles))
         if (i + 1) % 50 == 0:
             log(f"harvested {i + 1}/{args.configs} configurations ({time.time() - t0:.1f}s)")
     if pool is not None:
@@ -89,7 +93,7 @@ def main(argv=None):
     log(f"saved {args.out}")
     report = {"configs": args.configs, "n": args.n, "blobs": args.blobs, "samples": args.samples,
               "epochs": args.epochs, "lr": args.lr, "lr_final": args.lr_final, "batch": args.batch,
-              "smooth": args.smooth, "seed": args.seed, "loss": hist,
+              "smooth": args.smooth, "seed": args.seed, "cycles": args.cycles, "loss": hist,
               "train_seconds": time.time() - t0, "eval": []}
     for spec in args.eval.split(","):
         if not spec:
@@ -99,9 +103,12 @@ def main(argv=None):
             inst = W.learned_eval(n, N, index=100 + k) if n == 256 else W.training_config(900_000 + k, n, N)
             f = torch.ones((n, n, n), dtype=torch.float64, device=dev)
             row = {"n": n, "N": N, "seed": inst.seed}
-            for name, netx, prec in (("plain_fp64", None, FP64), ("mixed", None, MIXED),
-                                     ("learned_mixed", net, MIXED)):
-                st, dt, c, lam = LD.gmres_iterations(n, inst.q, f, netx, dev, precision=prec)
+            runs = (("plain_fp64", None, FP64, LD.gmres_iterations), ("mixed", None, MIXED, LD.gmres_iterations),
+                    ("learned_mixed", net, MIXED, LD.gmres_iterations),
+                    ("block_mixed", None, MIXED, LD.block_iterations),
+                    ("block_learned_mixed", net, MIXED, LD.block_iterations))
+            for name, netx, prec, fn in runs:
+                st, dt, c, lam = fn(n, inst.q, f, netx, dev, precision=prec)
                 row[name] = {"gmres_iters": st["outer_iters"], "inner_iters": st["inner_iters_total"],
                              "seconds": dt, "rel_resid": st["rel_resid"], "rc": st["rc"],
                              "fallback": st["fallback"]}

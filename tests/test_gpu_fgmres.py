@@ -231,3 +231,24 @@ def test_fgmres_learned_solve_and_fallback(dev):
     assert st["rc"] == 0 and st["fallback"] == 1
     S2.close()
     net.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_schur_apply_cycles_parity(dev, prec):
+    """The approximate-Schur operator P J A_n^{-1} S P (n multigrid cycles) against the oracle's
+    steps on its own cycles."""
+    _say("schur apply cycles", prec)
+    rng = np.random.default_rng(77)
+    n, N = 32, 30
+    q = W.rsa_positions(rng, n, N, 3.0)
+    x = rng.standard_normal(N)
+    S = make(dev, n, q, precision=prec)
+    ops = fg.SaddleOps(q, (n, n, n), 0.0)
+    xp = x - x.mean()
+    for cyc in (1, 2):
+        y = H(S.schur_apply_cycles(T(x, dev), 0.0, cyc))
+        inv = fg.cycles_inverse(ops, lambda r: it.vcycle(r, 0.0), cyc)
+        ref = ops.J(inv(ops.S(xp)))
+        ref -= ref.mean()
+        assert rel(y, ref) < (1e-10 if prec == 0 else 1e-5)
+    S.close()
