@@ -104,6 +104,23 @@ struct BlobGeom {
     int w;
 };
 
+// Contribution lists of the spread: n touched cells, cell[k] its grid index,
+// entries ptr[k] .. ptr[k+1] of (blob[e], weight w[e]).
+struct SpreadLists {
+    int n;
+    const int* cell;
+    const int* ptr;
+    const int* blob;
+    const double* w;
+};
+// Multipliers a spread takes: lam[b] + c2 lam2[b] + shift (lam, lam2 may be null).
+struct SpreadMult {
+    const double* lam;
+    const double* lam2;
+    double c2;
+    double shift;
+};
+
 // Logical block of a launch: partial-sum slot b of nb. Solo kernels pass
 // (blockIdx.x, gridDim.x); batched kernels pass an instance's local slot, so
 // every instance's partition of work and of partial sums is the solo one.
@@ -198,6 +215,20 @@ __device__ __forceinline__ void block_partials(double (&v)[K], double* part, uns
         for (int w = 0; w < nw; ++w) s += sh[threadIdx.x][w];
         part[(size_t)threadIdx.x * nparts + slot] = s;
     }
+}
+
+// Sum over one work-group (wave sums, then the waves in order); every thread
+// gets the total.
+__device__ __forceinline__ double wg_sum(double s) {
+    __shared__ double sh[kFinBlock / 64];
+    s = wave_sum(s);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+    __syncthreads();
+    return t;
 }
 
 inline unsigned nblocks(size_t n, int bs = kBlock) { return (unsigned)((n + bs - 1) / bs); }

@@ -613,8 +613,10 @@ void spread_to(blob_rd* H, const double* lam, double lam_shift, const double* ba
         if (base_in) launch_nvec_copy_scale(H->st, base_in, out, (int)P.ncell, 1.0, 0.0);
         else launch_fill(H->st, out, P.ncell, 0.0);
     }
-    launch_spread_sparse(H->st, lam, lam_shift, H->ntouched, H->at<int>(P.off_tcell), H->at<int>(P.off_tptr),
-                         H->at<int>(P.off_tblob), H->at<double>(P.off_tw), base_in, out, scale, sc);
+    launch_spread_sparse(H->st,
+                         SpreadLists{H->ntouched, H->at<int>(P.off_tcell), H->at<int>(P.off_tptr),
+                                     H->at<int>(P.off_tblob), H->at<double>(P.off_tw)},
+                         SpreadMult{lam, nullptr, 0.0, lam_shift}, base_in, out, scale, sc);
 }
 
 // q += S kappa J p, with jx = J p and mu = kappa J p kept for the CG dots.
@@ -842,12 +844,9 @@ int reactive_solve(blob_rd* H, double alpha, const double* g, double* c, blob_rd
 
 // z = P W P r with the learned CSR (r, z device N-vectors; nv(11) scratch).
 void precond_apply(blob_rd* H, const double* r, double* z) {
-    const int N = H->P.N;
-    double* t = H->nv(11);
-    launch_nvec_copy_scale(H->st, r, t, N, 1.0, 0.0);
-    launch_nvec_project(H->st, t, N);
-    launch_spmv(H->st, H->lrn.rowptr, H->lrn.col, H->lrn.val, t, z, N);
-    launch_nvec_project(H->st, z, N);
+    // z = P W P r: the input's mean removed inside the SpMV, the output's after it
+    launch_spmv_centered(H->st, H->lrn.rowptr, H->lrn.col, H->lrn.val, r, z, H->P.N);
+    launch_nvec_project(H->st, z, H->P.N);
 }
 
 // y = [P] J A^+ S [P] x for N-vectors x (device) -> y (device).
@@ -2653,28 +2652,53 @@ size_t fg_bytes(const Plan& P, int restart) {
     return (2 * (size_t)restart + 1) * fg_stride(P) * 8 + (ld * restart + 4 * ld + 8) * 8 + 256;
 }
 
-// n multigrid cycles for A x = rhs as a stationary iteration: from a zero guess
-// the first cycle is x = V rhs, every further cycle (all of them when x holds a
-// guess) adds V (rhs - A x).
-template <typename T>
-void fg_cycles(blob_rd* H, double alpha, const double* rhs, double* x, bool from_zero, int n, const double* cinv) {
+SpreadLists spread_lists(const blob_rd* H) {
+    const Plan& P = H->P;
+    return SpreadLists{H->ntouched, H->at<int>(P.off_tcell), H->at<int>(P.off_tptr), H->at<int>(P.off_tblob),
+                       H->at<double>(P.off_tw)};
+}
+
+// q = base - A x + scale S m: the dense residual of base, then the spread term
+// added at the touched cells only (M null: no spread term).
+void fg_resid(blob_rd* H, double alpha, const double* base, const SpreadMult* M, double scale, const double* x,
+              double* q) {
     const Plan& P = H->P;
     const LevelDims& d = P.lev[0];
-    const double s = H->prm.D / (d.h * d.h);
+    launch_applyA_plain(H->st, x, q, alpha, H->prm.D / (d.h * d.h), d.nx, d.ny, d.nz);
+    launch_axpby(H->st, q, base, P.ncell, -1.0, 1.0);
+    if (M) launch_spread_sparse(H->st, spread_lists(H), *M, q, q, scale, nullptr);
+    H->alg_bytes += (double)P.ncell * (16 + 24);
+}
+
+// n multigrid cycles for A x = r, r = base + scale S m (M null: r = base), as a
+// stationary iteration: from a zero guess the first cycle is x = V r (base
+// enters the V-cycle densely and the spread term at the touched cells, so r is
+// never formed), every further cycle (all of them when x holds a guess) adds
+// V (r - A x).
+template <typename T>
+void fg_cycles(blob_rd* H, double alpha, const double* base, const SpreadMult* M, double scale, double* x,
+               bool from_zero, int n, const double* cinv) {
+    const Plan& P = H->P;
+    const LevelDims& d = P.lev[0];
+    const double inv_diag = 1.0 / (alpha + 6.0 * H->prm.D / (d.h * d.h));
     T* z0 = H->at<T>(P.off_lvl[0][0]);
     T* z1 = H->at<T>(P.off_lvl[0][1]);
+    T* f0 = H->at<T>(P.off_lvl[0][2]);
+    T* f1 = H->at<T>(P.off_lvl[0][3]);
     double* q = H->grid(G_Q);
     for (int k = 0; k < n; ++k) {
         if (k == 0 && from_zero) {
-            vcycle<T>(H, alpha, rhs, nullptr, cinv);
+            launch_enter<T>(H->st, base, f0, f1, z0, d.nx, d.ny, d.nz, inv_diag, nullptr);
+            if (M) launch_spread_enter<T>(H->st, spread_lists(H), *M, base, scale, f0, f1, z0, d.nx, d.ny, inv_diag);
+            H->alg_bytes += (double)P.ncell * (8 + 1.5 * P.esz);
+            vcycle<T>(H, alpha, nullptr, nullptr, cinv, true);
             launch_split_to_nat<T>(H->st, z0, z1, x, d.nx, d.ny, d.nz, 0.0);
             H->alg_bytes += (double)P.ncell * (P.esz + 8);
         } else {
-            launch_applyA_plain(H->st, x, q, alpha, s, d.nx, d.ny, d.nz);
-            launch_axpby(H->st, q, rhs, P.ncell, -1.0, 1.0);
+            fg_resid(H, alpha, base, M, scale, x, q);
             vcycle<T>(H, alpha, q, nullptr, cinv);
             launch_split_to_nat<T>(H->st, z0, z1, x, d.nx, d.ny, d.nz, 1.0);
-            H->alg_bytes += (double)P.ncell * (16 + 24 + P.esz + 16);
+            H->alg_bytes += (double)P.ncell * (P.esz + 16);
         }
     }
 }
@@ -2706,7 +2730,9 @@ void fg_apply_K(blob_rd* H, double alpha, const double* xg, const double* xl, do
 // source, the blob-space mean projected out of h~, of each inner product and of
 // lam~ (a constant offset of an approximate concentration only shifts J c by a
 // constant, which that projection removes), and the mean concentration from the
-// constraint. Grid scratch: G_T1 (source minus the mean sink), G_T2, G_Q, G_U.
+// constraint. The right-hand sides vg - lbar S 1 and vg - S (lam~ + lbar) are
+// never formed on the grid: vg enters densely and the spread terms at the
+// touched cells. Grid scratch: G_Q, G_U.
 template <typename T>
 void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, const double* vf, double* zg,
                 double* zl) {
@@ -2716,24 +2742,28 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
     const double h3 = H->prm.h * H->prm.h * H->prm.h;
     const double* cinv = select_cinv(H, alpha);
     const bool sing = alpha == 0.0;
+    const LevelDims& d = P.lev[0];
+    const SpreadLists L = spread_lists(H);
+    T* z0 = H->at<T>(P.off_lvl[0][0]);
+    T* z1 = H->at<T>(P.off_lvl[0][1]);
     double* ds = H->dsc() + 48;  // [0] sum of vg, [8..10] sums of vf - J c
-    // 1. source with the mean sink removed, and the concentration estimate c*
-    const double* g_t = vg;
+    double* ml = H->nv(3);       // -lbar on every blob (alpha = 0)
+    // 1. concentration estimate c* from vg - lbar S 1
     if (sing) {
         unsigned np = 0;
         launch_norm_partials(st, vg, P.ncell, H->part(), &np);
         launch_reduce_parts(st, H->part(), np, 1, ds);
         H->alg_bytes += (double)P.ncell * 8;
-        double* ml = H->nv(3);
         launch_nvec_copy_scale(st, nullptr, ml, N, 0.0, 0.0);
-        launch_add_shift(st, ml, N, ds, -h3 / N);  // -lbar on every blob
-        fg_spread(H, ml, vg, H->grid(G_T1), H->inv_h3(), 0);
-        g_t = H->grid(G_T1);
+        launch_add_shift(st, ml, N, ds, -h3 / N);
     }
-    fg_cycles<T>(H, alpha, g_t, zg, true, o.n, cinv);
+    const SpreadMult m1{nullptr, ml, 1.0, 0.0};
+    fg_cycles<T>(H, alpha, vg, sing ? &m1 : nullptr, H->inv_h3(), zg, true, o.n, cinv);
     // 2. Schur-complement system for the (fluctuating) multipliers, right side J c* - vf
+    double* jv = H->nv(6);
     double* hv = H->nv(4);
-    fg_interp(H, zg, hv);
+    fg_interp(H, zg, jv);
+    launch_nvec_copy_scale(st, jv, hv, N, 1.0, 0.0);
     launch_axpby(st, hv, vf, N, 1.0, -1.0);
     if (sing) launch_nvec_project(st, hv, N);
     // the learned W approximates the inverse of J (-D L)^+ S on mean-zero multipliers:
@@ -2751,11 +2781,8 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
         double* Hm = H->at<double>(P.off_H);
         double* gv = H->at<double>(P.off_gv);
         launch_gmres_start(st, hv, nullptr, 0, V, gv, N, H->gs());
-        T* z0 = H->at<T>(P.off_lvl[0][0]);
-        T* z1 = H->at<T>(P.off_lvl[0][1]);
         T* f0 = H->at<T>(P.off_lvl[0][2]);
         T* f1 = H->at<T>(P.off_lvl[0][3]);
-        const LevelDims& d = P.lev[0];
         const size_t nh = P.ncell / 2;
         const double inv_diag = 1.0 / (alpha + 6.0 * H->prm.D / (d.h * d.h));
         for (int k = 0; k < o.m; ++k) {
@@ -2771,8 +2798,7 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
                 launch_zero<T>(st, f0, nh);
                 launch_zero<T>(st, f1, nh);
             }
-            launch_spread_enter<T>(st, vk, H->ntouched, H->at<int>(P.off_tcell), H->at<int>(P.off_tptr),
-                                   H->at<int>(P.off_tblob), H->at<double>(P.off_tw), H->inv_h3(), f0, f1, z0, d.nx,
+            launch_spread_enter<T>(st, L, SpreadMult{vk, nullptr, 0.0, 0.0}, nullptr, H->inv_h3(), f0, f1, z0, d.nx,
                                    d.ny, inv_diag);
             H->alg_bytes += (double)nh * P.esz * (k == 0 ? 3 : 1);
             vcycle<T>(H, alpha, nullptr, nullptr, cinv, true);
@@ -2788,19 +2814,35 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
         H->inner_iters += o.m;
     }
     if (sing) launch_nvec_project(st, zl, N);
-    // 3. corrected concentration from g~ - S lam~, started at c*
-    fg_spread(H, zl, g_t, H->grid(G_T2), -H->inv_h3(), 0);
-    fg_cycles<T>(H, alpha, H->grid(G_T2), zg, false, o.n, cinv);
-    if (sing) {
-        // 4. mean concentration: mean over blobs of vf - J c ; 5. lam = lam~ + lbar
-        double* jv = H->nv(6);
-        fg_interp(H, zg, jv);
-        launch_axpby(st, jv, vf, N, -1.0, 1.0);
-        launch_nvec_sums(st, jv, nullptr, N, ds + 8);
-        launch_add_shift(st, zg, P.ncell, ds + 8, 1.0 / N);
-        launch_add_shift(st, zl, N, ds, h3 / N);
-        H->alg_bytes += (double)P.ncell * 16;
+    // 3. corrected concentration: cycles on A c = vg - S (lam~ + lbar), started at c*
+    const SpreadMult m2{zl, sing ? ml : nullptr, -1.0, 0.0};
+    if (sing && o.n == 1) {
+        // one cycle; 4. the mean concentration from J c* + J z before z is added,
+        // so the shift rides on the pass that adds z
+        double* q = H->grid(G_Q);
+        fg_resid(H, alpha, vg, &m2, -H->inv_h3(), zg, q);
+        vcycle<T>(H, alpha, q, nullptr, cinv);
+        double* jz = H->nv(5);
+        launch_interp_split<T>(st, z0, z1, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
+                               H->at<int>(P.off_perm), jz);
+        launch_axpby(st, jz, vf, N, -1.0, 1.0);  // vf - J z
+        launch_axpby(st, jz, jv, N, 1.0, -1.0);  // vf - J z - J c*
+        launch_nvec_sums(st, jz, nullptr, N, ds + 8);
+        launch_split_to_nat<T>(st, z0, z1, zg, d.nx, d.ny, d.nz, 1.0, ds + 8, 1.0 / N);
+        H->alg_bytes += (double)P.ncell * (P.esz + 16);
+    } else {
+        fg_cycles<T>(H, alpha, vg, &m2, -H->inv_h3(), zg, false, o.n, cinv);
+        if (sing) {
+            // 4. mean concentration: mean over blobs of vf - J c
+            fg_interp(H, zg, jv);
+            launch_axpby(st, jv, vf, N, -1.0, 1.0);
+            launch_nvec_sums(st, jv, nullptr, N, ds + 8);
+            launch_add_shift(st, zg, P.ncell, ds + 8, 1.0 / N);
+            H->alg_bytes += (double)P.ncell * 16;
+        }
     }
+    // 5. lam = lam~ + lbar
+    if (sing) launch_add_shift(st, zl, N, ds, h3 / N);
 }
 
 // Flexible GMRES (right preconditioned, restarted, modified Gram-Schmidt) on
@@ -2922,8 +2964,8 @@ int blob_rd_schur_apply_cycles(blob_rd_t H, double alpha, const double* x, doubl
         if (alpha == 0.0) launch_nvec_project(H->st, xt, P.N);
         spread_to(H, xt, 0.0, nullptr, H->grid(G_T2), H->inv_h3(), nullptr);
         const double* cinv = select_cinv(H, alpha);
-        if (P.esz == 4) fg_cycles<float>(H, alpha, H->grid(G_T2), H->grid(G_U), true, cycles, cinv);
-        else fg_cycles<double>(H, alpha, H->grid(G_T2), H->grid(G_U), true, cycles, cinv);
+        if (P.esz == 4) fg_cycles<float>(H, alpha, H->grid(G_T2), nullptr, 0.0, H->grid(G_U), true, cycles, cinv);
+        else fg_cycles<double>(H, alpha, H->grid(G_T2), nullptr, 0.0, H->grid(G_U), true, cycles, cinv);
         fg_interp(H, H->grid(G_U), y);
         if (alpha == 0.0) launch_nvec_project(H->st, y, P.N);
         HIPCHK(hipGetLastError());

@@ -230,14 +230,23 @@ __global__ void __launch_bounds__(kBlock) kb_interp(const InstDev* inst, const i
     }
 }
 
-// out[c] = base(c) + scale * sum_e tw[e] (lam[tblob[e]] + lam_shift) for touched cell k
-__device__ __forceinline__ void spread_sparse_cell(int k, const double* __restrict__ lam, double lam_shift,
-                                                   const int* __restrict__ tcell, const int* __restrict__ tptr,
-                                                   const int* __restrict__ tblob, const double* __restrict__ tw,
-                                                   const double* base_in, double* out, double scale) {
+// sum_e w[e] m(blob[e]) over the entries of touched cell k
+__device__ __forceinline__ double spread_acc(int k, const SpreadLists& L, const SpreadMult& M) {
     double acc = 0.0;
-    for (int e = tptr[k]; e < tptr[k + 1]; ++e) acc += tw[e] * ((lam ? lam[tblob[e]] : 0.0) + lam_shift);
-    const int c = tcell[k];
+    for (int e = L.ptr[k]; e < L.ptr[k + 1]; ++e) {
+        const int b = L.blob[e];
+        double v = M.lam ? M.lam[b] : 0.0;
+        if (M.lam2) v += M.c2 * M.lam2[b];
+        acc += L.w[e] * (v + M.shift);
+    }
+    return acc;
+}
+
+// out[c] = base(c) + scale * sum_e w[e] m(blob[e]) for touched cell k
+__device__ __forceinline__ void spread_sparse_cell(int k, const SpreadLists& L, const SpreadMult& M,
+                                                   const double* base_in, double* out, double scale) {
+    const double acc = spread_acc(k, L, M);
+    const int c = L.cell[k];
     const double b = base_in ? base_in[c] : 0.0;
     out[c] = b + scale * acc;
 }
@@ -251,7 +260,8 @@ __global__ void __launch_bounds__(kBlock) kb_spread(const InstDev* inst, const i
         if (!I || !I->blobs) continue;
         const int k = (int)(blk.b * blockDim.x + threadIdx.x);
         if (k < I->ntouched)
-            spread_sparse_cell(k, I->mu, 0.0, I->tcell, I->tptr, I->tblob, I->tw, I->q, I->q, I->inv_h3);
+            spread_sparse_cell(k, SpreadLists{I->ntouched, I->tcell, I->tptr, I->tblob, I->tw},
+                               SpreadMult{I->mu, nullptr, 0.0, 0.0}, I->q, I->q, I->inv_h3);
     }
 }
 
@@ -430,46 +440,38 @@ void launch_spread_plan(hipStream_t st, int mode, BlobGeom g, const int* base, c
                        tcell, tptr, tblob, tw);
 }
 
-// out[c] = base(c) + scale * sum_e tw[e] (lam[tblob[e]] + lam_shift) over the
-// touched cells c (base(c) = base_in[c], 0 without base_in); other cells are
-// not touched (the caller's dense pass set them, or base_in aliases out).
-__global__ void __launch_bounds__(kBlock) k_spread_sparse(const double* __restrict__ lam, double lam_shift,
-                                                          int ntouched, const int* __restrict__ tcell,
-                                                          const int* __restrict__ tptr, const int* __restrict__ tblob,
-                                                          const double* __restrict__ tw, const double* base_in,
+// out[c] = base(c) + scale * sum_e w[e] m(blob[e]) over the touched cells c
+// (base(c) = base_in[c], 0 without base_in); other cells are not touched (the
+// caller's dense pass set them, or base_in aliases out).
+__global__ void __launch_bounds__(kBlock) k_spread_sparse(SpreadLists L, SpreadMult M, const double* base_in,
                                                           double* out, double scale, const Scalars* sc) {
     if (sc && sc->done) return;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= ntouched) return;
-    spread_sparse_cell(k, lam, lam_shift, tcell, tptr, tblob, tw, base_in, out, scale);
+    if (k >= L.n) return;
+    spread_sparse_cell(k, L, M, base_in, out, scale);
 }
 
-void launch_spread_sparse(hipStream_t st, const double* lam, double lam_shift, int ntouched, const int* tcell,
-                          const int* tptr, const int* tblob, const double* tw, const double* base_in, double* out,
-                          double scale, const Scalars* sc) {
-    if (ntouched <= 0) return;
-    hipLaunchKernelGGL(k_spread_sparse, dim3(nblocks(ntouched)), dim3(kBlock), 0, st, lam, lam_shift, ntouched, tcell,
-                       tptr, tblob, tw, base_in, out, scale, sc);
+void launch_spread_sparse(hipStream_t st, const SpreadLists& L, const SpreadMult& M, const double* base_in,
+                          double* out, double scale, const Scalars* sc) {
+    if (L.n <= 0) return;
+    hipLaunchKernelGGL(k_spread_sparse, dim3(nblocks(L.n)), dim3(kBlock), 0, st, L, M, base_in, out, scale, sc);
 }
 
-// V-cycle entry straight from the contribution lists: the right-hand side
-// r = h^-3 scale S lam is nonzero only on touched cells, so its split level-0
-// copy f and the first red half-sweep from zero (u_red = f_red / diag) are
-// written there only; the caller has zeroed u0 (and f0, f1 unless they hold
-// zeros outside the touched cells from a previous entry of the same lists).
-// Bitwise the spread into a zeroed grid followed by k_enter.
+// V-cycle entry at the touched cells: r = base(c) + scale S m, the split
+// level-0 copy f and the first red half-sweep from zero (u_red = f_red / diag)
+// are written there only. Without base_in the caller has zeroed u0 (and f0, f1
+// unless they hold zeros outside the touched cells from a previous entry of the
+// same lists); with base_in, k_enter of base_in has set every other cell.
+// Bitwise the spread into a grid followed by k_enter.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_spread_enter(const double* __restrict__ lam, int ntouched,
-                                                         const int* __restrict__ tcell, const int* __restrict__ tptr,
-                                                         const int* __restrict__ tblob, const double* __restrict__ tw,
+__global__ void __launch_bounds__(kBlock) k_spread_enter(SpreadLists L, SpreadMult M, const double* __restrict__ base_in,
                                                          double scale, T* __restrict__ f0, T* __restrict__ f1,
                                                          T* __restrict__ u0, int nx, int ny, double inv_diag) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= ntouched) return;
-    double acc = 0.0;
-    for (int e = tptr[k]; e < tptr[k + 1]; ++e) acc += tw[e] * (lam[tblob[e]] + 0.0);
-    const double r = 0.0 + scale * acc;
-    const int c = tcell[k];
+    if (k >= L.n) return;
+    const double acc = spread_acc(k, L, M);
+    const int c = L.cell[k];
+    const double r = (base_in ? base_in[c] : 0.0) + scale * acc;
     const int X = c % nx;
     const int t = c / nx;
     const int Y = t % ny, Z = t / ny;
@@ -483,17 +485,16 @@ __global__ void __launch_bounds__(kBlock) k_spread_enter(const double* __restric
 }
 
 template <typename T>
-void launch_spread_enter(hipStream_t st, const double* lam, int ntouched, const int* tcell, const int* tptr,
-                         const int* tblob, const double* tw, double scale, T* f0, T* f1, T* u0, int nx, int ny,
-                         double inv_diag) {
-    if (ntouched <= 0) return;
-    hipLaunchKernelGGL(k_spread_enter<T>, dim3(nblocks(ntouched)), dim3(kBlock), 0, st, lam, ntouched, tcell, tptr,
-                       tblob, tw, scale, f0, f1, u0, nx, ny, inv_diag);
+void launch_spread_enter(hipStream_t st, const SpreadLists& L, const SpreadMult& M, const double* base_in,
+                         double scale, T* f0, T* f1, T* u0, int nx, int ny, double inv_diag) {
+    if (L.n <= 0) return;
+    hipLaunchKernelGGL(k_spread_enter<T>, dim3(nblocks(L.n)), dim3(kBlock), 0, st, L, M, base_in, scale, f0, f1, u0,
+                       nx, ny, inv_diag);
 }
-template void launch_spread_enter<float>(hipStream_t, const double*, int, const int*, const int*, const int*,
-                                         const double*, double, float*, float*, float*, int, int, double);
-template void launch_spread_enter<double>(hipStream_t, const double*, int, const int*, const int*, const int*,
-                                          const double*, double, double*, double*, double*, int, int, double);
+template void launch_spread_enter<float>(hipStream_t, const SpreadLists&, const SpreadMult&, const double*, double,
+                                         float*, float*, float*, int, int, double);
+template void launch_spread_enter<double>(hipStream_t, const SpreadLists&, const SpreadMult&, const double*, double,
+                                          double*, double*, double*, int, int, double);
 
 template <typename T>
 __global__ void k_zero(T* __restrict__ p, size_t n) {
@@ -511,17 +512,6 @@ template void launch_zero<double>(hipStream_t, double*, size_t);
 
 // ---------------------------------------------------------------------------
 // N-vector kernels: one work-group of kFinBlock threads, fixed reduction order.
-__device__ __forceinline__ double wg_sum(double s) {
-    __shared__ double sh[kFinBlock / 64];
-    s = wave_sum(s);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
-    __syncthreads();
-    return t;
-}
 
 __global__ void __launch_bounds__(kFinBlock) k_nvec_project(double* v, int N) {
     double s = 0.0;

@@ -356,27 +356,33 @@ void launch_residual_from_q(hipStream_t st, const double* g, const double* q0, d
 
 // Split-layout value at natural (X, Y, Z) of level 0.
 
-// out = scale * out + z   (z split -> natural)
+// out = scale * out + z (+ shift_scale * *shift_dev)   (z split -> natural)
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_split_to_nat(const T* __restrict__ z0, const T* __restrict__ z1,
                                                          double* __restrict__ out, int nx, int ny, unsigned ncell,
-                                                         double scale) {
+                                                         double scale, const double* __restrict__ shift_dev,
+                                                         double shift_scale) {
     const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= ncell) return;
     const int X = idx % nx;
     const unsigned t = idx / nx;
     const double zv = split_at(z0, z1, X, (int)(t % ny), (int)(t / ny), nx >> 1, ny);
-    out[idx] = scale == 0.0 ? zv : scale * out[idx] + zv;
+    double v = scale == 0.0 ? zv : scale * out[idx] + zv;
+    if (shift_dev) v += shift_scale * shift_dev[0];
+    out[idx] = v;
 }
 
 template <typename T>
 void launch_split_to_nat(hipStream_t st, const T* z0, const T* z1, double* out, int nx, int ny, int nz,
-                         double scale) {
+                         double scale, const double* shift_dev, double shift_scale) {
     const unsigned n = (unsigned)nx * ny * nz;
-    hipLaunchKernelGGL(k_split_to_nat<T>, dim3(nblocks(n)), dim3(kBlock), 0, st, z0, z1, out, nx, ny, n, scale);
+    hipLaunchKernelGGL(k_split_to_nat<T>, dim3(nblocks(n)), dim3(kBlock), 0, st, z0, z1, out, nx, ny, n, scale,
+                       shift_dev, shift_scale);
 }
-template void launch_split_to_nat<float>(hipStream_t, const float*, const float*, double*, int, int, int, double);
-template void launch_split_to_nat<double>(hipStream_t, const double*, const double*, double*, int, int, int, double);
+template void launch_split_to_nat<float>(hipStream_t, const float*, const float*, double*, int, int, int, double,
+                                         const double*, double);
+template void launch_split_to_nat<double>(hipStream_t, const double*, const double*, double*, int, int, int, double,
+                                          const double*, double);
 
 __global__ void __launch_bounds__(kBlock) k_norm_partials(const double* __restrict__ v, unsigned n, double* part) {
     unsigned lo, hi;

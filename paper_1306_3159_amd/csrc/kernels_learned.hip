@@ -335,6 +335,34 @@ void launch_spmv(hipStream_t st, const int* rowptr, const int* col, const double
     hipLaunchKernelGGL(k_spmv, dim3(nblocks(N)), dim3(kBlock), 0, st, rowptr, col, val, x, y, N);
 }
 
+// y = W (x - mean(x)): each block sums x itself (the same order in every block,
+// so every block subtracts the same mean), then one thread per row.
+__global__ void __launch_bounds__(kBlock) k_spmv_centered(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                          const double* __restrict__ val,
+                                                          const double* __restrict__ x, double* __restrict__ y,
+                                                          int N) {
+    __shared__ double sh[kBlock / 64];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) s += x[i];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double tot = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += sh[w];
+    const double m = tot / (double)N;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double acc = 0.0;
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) acc += val[k] * (x[col[k]] - m);
+    y[i] = acc;
+}
+
+void launch_spmv_centered(hipStream_t st, const int* rowptr, const int* col, const double* val, const double* x,
+                          double* y, int N) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_spmv_centered, dim3(nblocks(N)), dim3(kBlock), 0, st, rowptr, col, val, x, y, N);
+}
+
 // Non-finite entries of W (watchdog)
 __global__ void __launch_bounds__(kFinBlock) k_count_bad(const double* v, long long n, int* out) {
     int bad = 0;

@@ -34,10 +34,10 @@ void launch_update2_enter(hipStream_t st, double* x, double* r, const double* p,
 template <typename T>
 void launch_zdots2(hipStream_t st, const T* z0, const T* z1, const double* r, const double* q, int nx, int ny, int nz,
                    double* part, const Scalars* sc, unsigned* nparts_out);
-// x += shift + z (final correction of a preconditioner application, z split)
+// out = scale * out + z (+ shift_scale * *shift_dev): z split -> natural FP64
 template <typename T>
 void launch_split_to_nat(hipStream_t st, const T* z0, const T* z1, double* out, int nx, int ny, int nz,
-                         double scale_in_place);
+                         double scale_in_place, const double* shift_dev = nullptr, double shift_scale = 0.0);
 // sums (sum v, v.v) of a natural vector
 void launch_norm_partials(hipStream_t st, const double* v, size_t n, double* part, unsigned* nparts_out);
 void launch_fill(hipStream_t st, double* v, size_t n, double value);
@@ -152,18 +152,14 @@ void launch_interp_split(hipStream_t st, const T* z0, const T* z1, int N, BlobGe
 void launch_spread_plan(hipStream_t st, int mode, BlobGeom g, const int* base, const double* wts, const int* offsets,
                         const int* perm, int* cnt, const int* offE, const int* offC, int* tcell, int* tptr,
                         int* tblob, double* tw);
-// out[c] = base(c) + scale * sum (lam + lam_shift) w over the touched cells only
-void launch_spread_sparse(hipStream_t st, const double* lam, double lam_shift, int ntouched, const int* tcell,
-                          const int* tptr, const int* tblob, const double* tw, const double* base_in, double* out,
-                          double scale, const Scalars* sc);
-
-// V-cycle entry of r = scale S lam from the contribution lists (split f at the
-// touched cells, u_red = f_red / diag there); u0, and f0/f1 outside the touched
-// cells, must already be zero
+// out[c] = base(c) + scale * sum_e w m(blob) over the touched cells only
+void launch_spread_sparse(hipStream_t st, const SpreadLists& L, const SpreadMult& M, const double* base_in,
+                          double* out, double scale, const Scalars* sc);
+// V-cycle entry of r = base + scale S m at the touched cells (split f, u_red = f_red / diag);
+// u0, and f0/f1 elsewhere, must already hold zeros (no base) or k_enter's values of base_in
 template <typename T>
-void launch_spread_enter(hipStream_t st, const double* lam, int ntouched, const int* tcell, const int* tptr,
-                         const int* tblob, const double* tw, double scale, T* f0, T* f1, T* u0, int nx, int ny,
-                         double inv_diag);
+void launch_spread_enter(hipStream_t st, const SpreadLists& L, const SpreadMult& M, const double* base_in,
+                         double scale, T* f0, T* f1, T* u0, int nx, int ny, double inv_diag);
 template <typename T>
 void launch_zero(hipStream_t st, T* p, size_t n);
 
@@ -190,6 +186,9 @@ void launch_net_assemble(hipStream_t st, const double* q, PairGeom pg, NetDev ne
                          long long nnz, double Dh, double diag, double* val);
 void launch_spmv(hipStream_t st, const int* rowptr, const int* col, const double* val, const double* x, double* y,
                  int N);
+// y = W (x - mean(x))
+void launch_spmv_centered(hipStream_t st, const int* rowptr, const int* col, const double* val, const double* x,
+                          double* y, int N);
 void launch_count_bad(hipStream_t st, const double* v, long long n, int* out);
 void launch_entry_grad(hipStream_t st, const int* rowidx, const int* col, long long nnz, const double* RP,
                        const double* YP, const double* coef, int S, int N, double half_Dh, float* dg);
