@@ -100,15 +100,22 @@ LOCKSTEP_MAX_CELLS = 64 ** 3
 
 def bench_batch(args, dev, rtol):
     """64 uneven suspensions (grids 32..128, up to 2000 blobs, reactive/absorbing 50/50); a step
-    is the whole batch. value: the lock-step executor (every instance's CG iterations in shared
-    batched launches, one captured graph replayed in rounds); beside it the per-instance-stream
-    executor and one-by-one solves."""
+    is the whole batch. value: the lock-step executor (the reactive instances' CG iterations in
+    shared batched launches, one captured graph replayed in rounds) with the absorbing instances
+    solved by the block FGMRES on their own streams meanwhile; beside it the per-instance-stream
+    executor, one-by-one solves, and the lock-step executor with Schur-GMRES absorbing solves
+    (their inner CG iterations in the lock-step launches too)."""
     import torch
     import workloads as W
-    from paper_1306_3159_amd import BlobRD, MIXED, solve_batch, solve_batched
+    from paper_1306_3159_amd import BlobRD, MIXED, SOLVER_BLOCK, SOLVER_SCHUR, solve_batch, solve_batched
     insts = W.batch_instances()
-    Hs = [BlobRD(i.n, torch.tensor(i.q, device=dev), torch.tensor(i.kappa, device=dev), precision=MIXED, rtol=rtol,
-                 stream=torch.cuda.Stream(dev)) for i in insts]
+
+    def handles(solver):
+        return [BlobRD(i.n, torch.tensor(i.q, device=dev), torch.tensor(i.kappa, device=dev), precision=MIXED,
+                       rtol=rtol, stream=torch.cuda.Stream(dev),
+                       saddle_solver=solver if i.kind == "absorbing" else SOLVER_SCHUR) for i in insts]
+
+    Hs = handles(SOLVER_BLOCK)
     fs = [torch.tensor(i.f, device=dev) for i in insts]
     kinds = [1 if i.kind == "absorbing" else 0 for i in insts]
     cs = [torch.zeros_like(f) for f in fs]
@@ -145,6 +152,13 @@ def bench_batch(args, dev, rtol):
         else:
             H.solve_reactive(f, c=c)
     serial = time.perf_counter() - t1
+    for H in Hs:
+        H.close()
+    Hs = handles(SOLVER_SCHUR)
+    if args.autotune:
+        for H in Hs:
+            H.autotune(reps=5, cache=cache)
+    qdt, (qrc, _) = timed(step_lockstep, max(2, args.steps // 2), 1)
     cells = sum(i.n ** 3 for i in insts)
     out = {"metric": METRIC, "value": len(insts) * args.steps / dt, "unit": "instances/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
@@ -152,12 +166,15 @@ def bench_batch(args, dev, rtol):
            "dtype": "f64 Krylov/residuals + f32 V-cycles", "data": "synthetic",
            "config": {"workload": "batch64", "instances": len(insts), "total_cells": cells,
                       "total_blobs": sum(i.N for i in insts), "rtol": rtol,
-                      "executor": "lock-step batched launches for grids <= 64^3, own streams for larger grids",
-                      "lockstep_instances": sum(1 for i in insts if i.n ** 3 <= LOCKSTEP_MAX_CELLS),
+                      "executor": "lock-step batched launches for reactive grids <= 64^3, own streams for larger "
+                                  "grids and for the absorbing instances (block FGMRES)",
+                      "lockstep_instances": sum(1 for i in insts if i.n ** 3 <= LOCKSTEP_MAX_CELLS
+                                                and i.kind != "absorbing"),
                       "stream_threads": args.threads, "autotuned_levels": tuned},
            "rc": rc, "max_rel_resid": max(s["rel_resid"] for s in stats),
            "streams_executor": {"instances_per_s": len(insts) * ns / sdt, "threads": args.threads, "rc": src},
-           "serial_instances_per_s": len(insts) / serial}
+           "serial_instances_per_s": len(insts) / serial,
+           "lockstep_schur_gmres": {"instances_per_s": len(insts) * ns / qdt, "rc": qrc}}
     for H in Hs:
         H.close()
     print(json.dumps(out))

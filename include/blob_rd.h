@@ -55,6 +55,13 @@ extern "C" {
 #define BLOB_RD_PRECOND_DIAGONAL 1 /* scalar gamma^-1 of eq. Schur_diagonal */
 #define BLOB_RD_PRECOND_LEARNED 2  /* sparse pairwise network preconditioner */
 
+/* Absorbing solves of a handle (blob_rd_params.saddle_solver). The block
+ * solvers reserve the flexible-GMRES basis (restart = gmres_restart) in the
+ * handle's workspace, see blob_rd_solve_absorbing_fgmres. */
+#define BLOB_RD_SOLVER_SCHUR 0         /* Schur-complement GMRES with inner multigrid-CG solves */
+#define BLOB_RD_SOLVER_BLOCK 1         /* block FGMRES, approximate-Schur preconditioner (m = 5, n = 1) */
+#define BLOB_RD_SOLVER_BLOCK_LEARNED 2 /* the same with the learned inner preconditioning */
+
 typedef struct blob_rd* blob_rd_t;
 
 typedef struct {
@@ -74,6 +81,7 @@ typedef struct {
     void* workspace;         /* device memory owned by the caller */
     size_t workspace_bytes;
     void* stream;            /* hipStream_t, NULL = default stream */
+    int32_t saddle_solver;   /* BLOB_RD_SOLVER_*: how blob_rd_solve_absorbing solves (default Schur GMRES) */
 } blob_rd_params;
 
 typedef struct {
@@ -118,7 +126,10 @@ int blob_rd_solve_reactive(blob_rd_t h, double alpha, const double* f, double* c
  * r_schur) with inner multigrid-preconditioned CG solves; for alpha = 0
  * the periodic null space is handled as in Appendix A (sum(lambda) =
  * h^3 sum(f), mean-zero fluctuation, mean concentration recovered from the
- * constraint). c (grid) and lambda (N) are outputs. EINVAL if N = 0. */
+ * constraint). c (grid) and lambda (N) are outputs. EINVAL if N = 0.
+ * With saddle_solver = BLOB_RD_SOLVER_BLOCK(_LEARNED) the handle solves the
+ * same system by the paper's block FGMRES instead (as
+ * blob_rd_solve_absorbing_fgmres, with its basis in the handle's workspace). */
 int blob_rd_solve_absorbing(blob_rd_t h, double alpha, const double* f, double* c,
                             double* lambda, blob_rd_stats* stats);
 

@@ -7,7 +7,9 @@ library's kernels. There is no CPU fallback: if the library is missing the
 import of :mod:`paper_1306_3159_amd.native` fails loudly.
 """
 from .native import (BlobRD, Net, NET_PARAMS, solve_batch, solve_batched, BlobRDError, NotConverged, Stats,
-                     load_library, FP64, MIXED, PRECOND_NONE, PRECOND_DIAGONAL, PRECOND_LEARNED)
+                     load_library, FP64, MIXED, PRECOND_NONE, PRECOND_DIAGONAL, PRECOND_LEARNED, SOLVER_SCHUR,
+                     SOLVER_BLOCK, SOLVER_BLOCK_LEARNED)
 
 __all__ = ["BlobRD", "Net", "NET_PARAMS", "solve_batch", "solve_batched", "BlobRDError", "NotConverged", "Stats",
-           "load_library", "FP64", "MIXED", "PRECOND_NONE", "PRECOND_DIAGONAL", "PRECOND_LEARNED"]
+           "load_library", "FP64", "MIXED", "PRECOND_NONE", "PRECOND_DIAGONAL", "PRECOND_LEARNED", "SOLVER_SCHUR",
+           "SOLVER_BLOCK", "SOLVER_BLOCK_LEARNED"]

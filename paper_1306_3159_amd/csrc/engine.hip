@@ -99,10 +99,20 @@ struct Plan {
            off_cursor = 0, off_perm = 0;
     // spread contribution lists: per-tile counts and offsets, touched cells, entries
     size_t off_sp_cnt = 0, off_sp_off = 0, off_tcell = 0, off_tptr = 0, off_tblob = 0, off_tw = 0;
+    // flexible-GMRES basis of the block solvers (handles that use them)
+    size_t off_fg = 0, fg_size = 0;
     size_t off_nv[12]{};
     size_t off_V = 0, off_H = 0, off_cs = 0, off_sn = 0, off_gv = 0, off_yv = 0;
     size_t total = 0;
 };
+
+// doubles between consecutive long vectors (grid part, blob part, padding)
+size_t fg_stride(const Plan& P) { return (P.ncell + (size_t)P.N + 31) & ~(size_t)31; }
+
+size_t fg_bytes(const Plan& P, int restart) {
+    const size_t ld = (size_t)restart + 1;
+    return (2 * (size_t)restart + 1) * fg_stride(P) * 8 + (ld * restart + 4 * ld + 8) * 8 + 256;
+}
 
 int make_plan(const blob_rd_params* p, Plan* P, std::string* why) {
     if (!p) {
@@ -209,6 +219,14 @@ int make_plan(const blob_rd_params* p, Plan* P, std::string* why) {
     P->off_sn = take(m * 8);
     P->off_gv = take((m + 1) * 8);
     P->off_yv = take(m * 8);
+    if (p->saddle_solver != BLOB_RD_SOLVER_SCHUR) {
+        if (p->saddle_solver != BLOB_RD_SOLVER_BLOCK && p->saddle_solver != BLOB_RD_SOLVER_BLOCK_LEARNED) {
+            *why = "unknown saddle_solver";
+            return BLOB_RD_EINVAL;
+        }
+        P->fg_size = fg_bytes(*P, P->restart);
+        P->off_fg = take(P->fg_size);
+    }
     P->total = o + 256;
     return 0;
 }
@@ -1333,6 +1351,14 @@ int blob_rd_solve_absorbing(blob_rd_t H, double alpha, const double* f, double* 
     if (!H || !f || !c || !lambda) return g_last_error = "null argument", BLOB_RD_EINVAL;
     if (H->P.N <= 0) return g_last_error = "absorbing solve needs at least one blob", BLOB_RD_EINVAL;
     if (!(alpha >= 0.0) || !std::isfinite(alpha)) return g_last_error = "alpha must be >= 0", BLOB_RD_EINVAL;
+    if (H->prm.saddle_solver != BLOB_RD_SOLVER_SCHUR) {
+        blob_rd_saddle_opts o{};
+        o.precond = H->prm.saddle_solver == BLOB_RD_SOLVER_BLOCK_LEARNED ? BLOB_RD_SADDLE_LEARNED
+                                                                          : BLOB_RD_SADDLE_APPROX_SCHUR;
+        o.restart = H->P.restart;
+        o.maxit = H->prm.max_iter;
+        return blob_rd_solve_absorbing_fgmres(H, alpha, &o, f, c, lambda, H->ws + H->P.off_fg, H->P.fg_size, stt);
+    }
     return guarded(H, stt, [&]() {
         int rc = H->P.esz == 4 ? absorbing_solve<float>(H, alpha, f, c, lambda, stt)
                                : absorbing_solve<double>(H, alpha, f, c, lambda, stt);
@@ -2517,6 +2543,7 @@ int blob_rd_solve_batched(blob_rd_t* hs, int32_t n, const int32_t* kind, double 
     for (int i = 0; i < n; ++i) {
         const blob_rd* H = hs[i];
         if (lockstep_max_cells > 0 && (int64_t)H->P.ncell > lockstep_max_cells) continue;
+        if (kind[i] == 1 && H->prm.saddle_solver != BLOB_RD_SOLVER_SCHUR) continue;  // block FGMRES: own stream
         if (!batch_unfit(H, esz ? esz : (int)H->P.esz).empty()) continue;
         esz = (int)H->P.esz;
         member.push_back(i);
@@ -2644,13 +2671,6 @@ FgOpts fg_opts(const blob_rd* H, const blob_rd_saddle_opts* o) {
     return r;
 }
 
-// doubles between consecutive long vectors (grid part, blob part, padding)
-size_t fg_stride(const Plan& P) { return (P.ncell + (size_t)P.N + 31) & ~(size_t)31; }
-
-size_t fg_bytes(const Plan& P, int restart) {
-    const size_t ld = (size_t)restart + 1;
-    return (2 * (size_t)restart + 1) * fg_stride(P) * 8 + (ld * restart + 4 * ld + 8) * 8 + 256;
-}
 
 SpreadLists spread_lists(const blob_rd* H) {
     const Plan& P = H->P;

@@ -20,6 +20,9 @@ MIXED = 1
 PRECOND_NONE = 0
 PRECOND_DIAGONAL = 1
 PRECOND_LEARNED = 2
+SOLVER_SCHUR = 0
+SOLVER_BLOCK = 1
+SOLVER_BLOCK_LEARNED = 2
 
 OK = 0
 ENOTCONV = 1
@@ -34,7 +37,7 @@ class Params(ctypes.Structure):
         ("precision", ctypes.c_int32), ("schur_precond", ctypes.c_int32),
         ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
         ("inner_max_iter", ctypes.c_int32), ("workspace", ctypes.c_void_p),
-        ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p), ("saddle_solver", ctypes.c_int32),
     ]
 
 
@@ -246,7 +249,8 @@ class BlobRD:
     def __init__(self, shape: Union[int, Sequence[int]], q: torch.Tensor, kappa: Optional[torch.Tensor] = None,
                  h: float = 1.0, D: float = 1.0, kernel_w: int = 4, precision: int = FP64,
                  schur_precond: int = PRECOND_NONE, rtol: float = 1e-8, max_iter: int = 0,
-                 gmres_restart: int = 0, inner_max_iter: int = 0, stream: Optional[torch.cuda.Stream] = None):
+                 gmres_restart: int = 0, inner_max_iter: int = 0, stream: Optional[torch.cuda.Stream] = None,
+                 saddle_solver: int = 0):
         L = load_library()
         if isinstance(shape, int):
             shape = (shape, shape, shape)
@@ -264,7 +268,7 @@ class BlobRD:
         p = Params(nx, ny, nz, float(h), float(D), int(kernel_w), N, q.data_ptr() if N > 0 else None,
                    None if kappa is None else kappa.data_ptr(), int(precision), int(schur_precond),
                    float(rtol), int(max_iter), int(gmres_restart), int(inner_max_iter), None, 0,
-                   ctypes.c_void_p(self.stream.cuda_stream))
+                   ctypes.c_void_p(self.stream.cuda_stream), int(saddle_solver))
         nbytes = L.blob_rd_workspace_bytes(ctypes.byref(p))
         if nbytes == 0:
             raise BlobRDError(-1, L.blob_rd_last_error(None).decode())

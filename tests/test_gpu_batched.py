@@ -117,3 +117,49 @@ def test_batched_serves_unfit_instances_on_streams(dev):
         assert np.array_equal(c.cpu().numpy(), r)
     for S in Hs:
         S.close()
+
+
+def test_batched_with_block_solver_instances(dev):
+    """Absorbing instances whose handles solve by the block FGMRES run on their own streams while
+    the reactive ones share the lock-step launches; every result is bitwise the solo solve, and
+    the block handles' absorbing solves are those of blob_rd_solve_absorbing_fgmres."""
+    _say("batched with block-solver instances")
+    from paper_1306_3159_amd import BlobRD, solve_batched, solve_batch, SOLVER_BLOCK
+    specs = [(32, 60, 0), (48, 200, 1), (64, 300, 0), (32, 20, 1), (64, 150, 1), (48, 90, 0)]
+    inst = _instances(specs, 4300)
+
+    def handles():
+        return [BlobRD(n, torch.tensor(q, device=dev), torch.tensor(kap, device=dev), precision=1,
+                       stream=torch.cuda.Stream(dev), saddle_solver=SOLVER_BLOCK if kind else 0)
+                for n, q, kap, kind, f in inst]
+
+    Hs = handles()
+    solo = []
+    for S, (n, q, kap, kind, f) in zip(Hs, inst):
+        ft = torch.tensor(f, device=dev)
+        if kind:
+            c, lam, st = S.solve_absorbing(ft)
+            c2, lam2, st2 = S.solve_absorbing_fgmres(ft, precond="schur")
+            assert np.array_equal(c.cpu().numpy(), c2.cpu().numpy())
+            assert st["outer_iters"] == st2["outer_iters"]
+            solo.append((c.cpu().numpy(), lam.cpu().numpy()))
+        else:
+            c, st = S.solve_reactive(ft)
+            solo.append((c.cpu().numpy(), None))
+        assert st["rc"] == 0 and st["rel_resid"] <= 1e-8
+    for runner in ("batched", "streams"):
+        fs = [torch.tensor(f, device=dev) for *_, f in inst]
+        cs = [torch.zeros_like(f) for f in fs]
+        ls = [torch.zeros(q.shape[0], dtype=torch.float64, device=dev) if kind else None for _, q, _, kind, _ in inst]
+        kinds = [kind for _, _, _, kind, _ in inst]
+        if runner == "batched":
+            rc, stats = solve_batched(Hs, kinds, fs, cs, ls)
+        else:
+            rc, stats = solve_batch(Hs, kinds, fs, cs, ls, threads=3)
+        assert rc == 0, stats
+        for (c0, l0), c, l in zip(solo, cs, ls):
+            assert np.array_equal(c.cpu().numpy(), c0)
+            if l0 is not None:
+                assert np.array_equal(l.cpu().numpy(), l0)
+    for S in Hs:
+        S.close()
