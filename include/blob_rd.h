@@ -230,7 +230,8 @@ size_t blob_rd_fgmres_workspace_bytes(blob_rd_t h, int restart);
  * vcycles = multigrid cycles (the paper's cost measure), refinements = restarts,
  * rel_resid = the true FP64 relative residual. Errors: EINVAL (null pointer,
  * N = 0, alpha < 0, bad options, misaligned workspace), ENOMEM (workspace too
- * small), ENOTCONV (maxit reached), ENUMERIC, EDEVICE. */
+ * small), ENOTCONV (maxit reached, or two restarts in a row that cut the true
+ * residual by less than 1 %: rtol below its rounding floor), ENUMERIC, EDEVICE. */
 int blob_rd_solve_absorbing_fgmres(blob_rd_t h, double alpha, const blob_rd_saddle_opts* opts, const double* f,
                                    double* c, double* lambda, void* workspace, size_t workspace_bytes,
                                    blob_rd_stats* stats);

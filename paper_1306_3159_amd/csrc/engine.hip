@@ -2885,8 +2885,8 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
     double* sd = yv + ld;  // [0] beta, [2..3] Givens outputs
     launch_fill(st, c, ncell, 0.0);
     launch_fill(st, lam, P.N, 0.0);
-    int its = 0, cycles = 0;
-    double bnorm = -1.0, rel = 0.0;
+    int its = 0, cycles = 0, stalled = 0;
+    double bnorm = -1.0, rel = 0.0, prev_rel = 0.0;
     bool sub = false;
     for (;;) {
         if (sub) fg_apply_K(H, alpha, c, lam, V, V + ncell);
@@ -2900,6 +2900,11 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
         if (bnorm < 0.0) bnorm = beta > 0.0 ? beta : 1.0;
         rel = beta / bnorm;
         if (rel <= o.rtol || its >= o.maxit) break;
+        // A restarted cycle cannot raise the true residual; two cycles in a row that cut it
+        // by less than 1 % mean the rounding floor of the residual is above rtol.
+        stalled = (cycles > 0 && rel > 0.99 * prev_rel) ? stalled + 1 : 0;
+        if (stalled >= 2) break;
+        prev_rel = rel;
         ++cycles;
         launch_fg_scale(st, V, sd, n);
         launch_fg_gstart(st, gv, ld, sd);

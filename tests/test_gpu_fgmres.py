@@ -252,3 +252,17 @@ def test_schur_apply_cycles_parity(dev, prec):
         ref -= ref.mean()
         assert rel(y, ref) < (1e-10 if prec == 0 else 1e-5)
     S.close()
+
+
+def test_fgmres_stops_at_rounding_floor(dev):
+    """A tolerance below the FP64 rounding floor of the residual ends after two restarts that
+    do not reduce it, reported as not converged with the floor as the residual."""
+    _say("fgmres rounding floor")
+    n = 16
+    q = np.array([[8.0, 8.0, 8.0]])
+    f = torch.full((n, n, n), 1.0 / n ** 3, dtype=torch.float64, device=dev)
+    S = make(dev, n, q, rtol=1e-17)
+    c, lam, st = S.solve_absorbing_fgmres(f, precond="schur", restart=10)
+    assert st["rc"] == 1 and st["outer_iters"] < 200, st
+    assert st["rel_resid"] < 1e-12
+    S.close()
