@@ -213,7 +213,8 @@ typedef struct {
     int32_t restart; /* FGMRES restart length; 0 = 30; <= 1024 */
     int32_t maxit;   /* total FGMRES iterations; 0 = 1000 */
     double rtol;     /* relative residual target; 0 = the handle's rtol */
-    double diag;     /* D/gamma of the diagonal variant; 0 = 4 pi a0 D with a0 = 1.255 h (Sec. IV.A) */
+    double diag;     /* D/gamma of the diagonal variant; 0 = 4 pi a0 D with a0 = 1.255 h for the
+                        four-point kernel, 0.885 h for the three-point one (Sec. IV.A) */
 } blob_rd_saddle_opts;
 
 /* Device bytes of the caller's FGMRES workspace for this handle and restart

@@ -37,9 +37,10 @@ import numpy as np
 
 from . import exact as ex
 
-# Averaged reactive radius of a four-point blob in units of h (Sec. IV.A); the
-# diagonal preconditioner takes gamma = 1/(4 pi a0).
-A0_OVER_H = 1.255
+# Reactive radius of a blob in units of h (Sec. IV.A): the position-averaged value of
+# the four-point kernel and the three-point kernel's value at a node; the diagonal
+# preconditioner takes gamma = 1/(4 pi a0).
+A0_OVER_H = {4: 1.255, 3: 0.885}
 
 
 class SaddleOps:
@@ -114,7 +115,8 @@ def precondition(ops: SaddleOps, vg, vf, kind: str, ainv_n, ainv_1=None, m: int 
     """One application of the paper's saddle-point preconditioner to [vg; vf] (appendix on
     preconditioning the saddle-point solver, steps 1-5; Sec. III.E for the two variants).
 
-    kind 'diagonal': multipliers lam~ = diag * h~ with diag = D/gamma = 4 pi a0 D by default.
+    kind 'diagonal': multipliers lam~ = diag * h~ with diag = D/gamma = 4 pi a0 D by default
+    (a0 from A0_OVER_H for the kernel).
     kind 'schur': m GMRES iterations on (J A1^{-1} S) lam~ = h~, A1^{-1} one cycle (ainv_1).
     kind 'learned': the same iterations right-preconditioned by an approximate inverse Schur
     complement w_apply (the learned P W P): (J A1^{-1} S W) y = h~, lam~ = W y.
@@ -132,7 +134,7 @@ def precondition(ops: SaddleOps, vg, vf, kind: str, ainv_n, ainv_1=None, m: int 
     # 2. the Schur-complement system for the fluctuating multipliers
     h_t = proj(ops.J(c_star) - vf)
     if kind == "diagonal":
-        lam_t = (4.0 * math.pi * A0_OVER_H * ops.h * ops.D if diag is None else diag) * h_t
+        lam_t = (4.0 * math.pi * A0_OVER_H[ops.w] * ops.h * ops.D if diag is None else diag) * h_t
     elif kind == "schur":
         lam_t = gmres_fixed(lambda v: proj(ops.J(ainv_1(ops.S(v)))), h_t, m)
     elif kind == "learned":

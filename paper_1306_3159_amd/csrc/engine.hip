@@ -2642,8 +2642,10 @@ struct FgOpts {
     double rtol = 1e-8, diag = 0.0;
 };
 
-// averaged reactive radius of a four-point blob in units of h (Sec. IV.A)
+// reactive radius of a blob in units of h (Sec. IV.A): the position average of the
+// four-point kernel, and the three-point kernel's value at a node
 constexpr double kA0OverH = 1.255;
+constexpr double kA0OverH3 = 0.885;
 
 FgOpts fg_opts(const blob_rd* H, const blob_rd_saddle_opts* o) {
     FgOpts r;
@@ -2667,7 +2669,7 @@ FgOpts fg_opts(const blob_rd* H, const blob_rd_saddle_opts* o) {
         throw Err(BLOB_RD_EINVAL, "inner Krylov iterations exceed the handle's GMRES restart length");
     if (r.n > 64) throw Err(BLOB_RD_EINVAL, "at most 64 multigrid cycles per approximate solve");
     if (r.restart > kFgMaxRestart) throw Err(BLOB_RD_EINVAL, "FGMRES restart length above 1024");
-    if (r.diag == 0.0) r.diag = 4.0 * M_PI * kA0OverH * H->prm.h * H->prm.D;
+    if (r.diag == 0.0) r.diag = 4.0 * M_PI * (H->prm.kernel_w == 3 ? kA0OverH3 : kA0OverH) * H->prm.h * H->prm.D;
     return r;
 }
 

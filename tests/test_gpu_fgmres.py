@@ -266,3 +266,27 @@ def test_fgmres_stops_at_rounding_floor(dev):
     assert st["rc"] == 1 and st["outer_iters"] < 200, st
     assert st["rel_resid"] < 1e-12
     S.close()
+
+
+@pytest.mark.parametrize("kind", ["diagonal", "schur"])
+def test_fgmres_three_point_kernel(dev, kind):
+    """The three-point kernel (27-cell support): preconditioner parity with the oracle and the
+    exact saddle solution."""
+    _say("fgmres w=3", kind)
+    rng = np.random.default_rng(78)
+    n, N = 32, 30
+    q = W.rsa_positions(rng, n, N, 3.0)
+    vg = rng.standard_normal((n, n, n))
+    vf = rng.standard_normal(N)
+    f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
+    S = make(dev, n, q, precision=0, kernel_w=3, rtol=1e-10)
+    zg, zl = S.saddle_precond(T(vg, dev), T(vf, dev), alpha=0.0, precond=kind)
+    ops = fg.SaddleOps(q, (n, n, n), 0.0, w=3)
+    inv = fg.cycles_inverse(ops, lambda r: it.vcycle(r, 0.0), 1)
+    cg, cl = fg.precondition(ops, vg, vf, kind, inv, inv, m=5)
+    assert rel(H(zg), cg) < 1e-9 and rel(H(zl), cl) < 1e-9
+    c, lam, st = S.solve_absorbing_fgmres(T(f, dev), precond=kind)
+    assert st["rc"] == 0, st
+    ce, le = ex.solve_absorbing(f, q, 0.0, w=3)
+    assert rel(H(c), ce) < 1e-8 and rel(H(lam), le) < 1e-8
+    S.close()
