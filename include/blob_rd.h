@@ -147,7 +147,9 @@ int blob_rd_step(blob_rd_t h, double dt, const double* f, double* c, blob_rd_sta
  * J A^{-1} S, eqs. c_exact and r_schur). c: c^n on entry, c^{n+1} on exit.
  * lambda: N sink strengths, written on exit; with warm != 0 its entry values
  * (say the previous step's multipliers) are GMRES's initial guess, with
- * warm = 0 they are ignored and GMRES starts from zero. stats->rel_resid is
+ * warm = 0 they are ignored and GMRES starts from zero. On a handle with
+ * saddle_solver = BLOB_RD_SOLVER_BLOCK(_LEARNED) the step is solved by the
+ * block FGMRES started from (c^n, lambda or zero). stats->rel_resid is
  * measured against g = c^n/dt + f. Errors: EINVAL (null pointer, dt not
  * positive and finite, N = 0), ENOTCONV, ENUMERIC, EDEVICE. */
 int blob_rd_step_absorbing(blob_rd_t h, double dt, const double* f, double* c, double* lambda, int warm,

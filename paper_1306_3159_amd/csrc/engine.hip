@@ -1142,6 +1142,347 @@ int guarded(blob_rd* H, blob_rd_stats* stt, F&& fn) {
 }  // namespace
 
 // ===========================================================================
+namespace {
+
+struct FgOpts {
+    int kind = BLOB_RD_SADDLE_APPROX_SCHUR;
+    int m = 5, n = 1, restart = 30, maxit = 1000;
+    double rtol = 1e-8, diag = 0.0;
+};
+
+// reactive radius of a blob in units of h (Sec. IV.A): the position average of the
+// four-point kernel, and the three-point kernel's value at a node
+constexpr double kA0OverH = 1.255;
+constexpr double kA0OverH3 = 0.885;
+
+FgOpts fg_opts(const blob_rd* H, const blob_rd_saddle_opts* o) {
+    FgOpts r;
+    r.rtol = H->prm.rtol > 0.0 ? H->prm.rtol : 1e-8;
+    if (o) {
+        r.kind = o->precond;
+        if (o->m > 0) r.m = o->m;
+        if (o->n > 0) r.n = o->n;
+        if (o->restart > 0) r.restart = o->restart;
+        if (o->maxit > 0) r.maxit = o->maxit;
+        if (o->rtol > 0.0) r.rtol = o->rtol;
+        r.diag = o->diag;
+        if (o->m < 0 || o->n < 0 || o->restart < 0 || o->maxit < 0 || !(o->rtol >= 0.0) || !(o->diag >= 0.0) ||
+            !std::isfinite(o->diag) || !std::isfinite(o->rtol))
+            throw Err(BLOB_RD_EINVAL, "saddle solver options must be non-negative and finite");
+    }
+    if (r.kind != BLOB_RD_SADDLE_DIAGONAL && r.kind != BLOB_RD_SADDLE_APPROX_SCHUR &&
+        r.kind != BLOB_RD_SADDLE_LEARNED)
+        throw Err(BLOB_RD_EINVAL, "unknown saddle preconditioner");
+    if (r.m > H->P.restart)
+        throw Err(BLOB_RD_EINVAL, "inner Krylov iterations exceed the handle's GMRES restart length");
+    if (r.n > 64) throw Err(BLOB_RD_EINVAL, "at most 64 multigrid cycles per approximate solve");
+    if (r.restart > kFgMaxRestart) throw Err(BLOB_RD_EINVAL, "FGMRES restart length above 1024");
+    if (r.diag == 0.0) r.diag = 4.0 * M_PI * (H->prm.kernel_w == 3 ? kA0OverH3 : kA0OverH) * H->prm.h * H->prm.D;
+    return r;
+}
+
+
+SpreadLists spread_lists(const blob_rd* H) {
+    const Plan& P = H->P;
+    return SpreadLists{H->ntouched, H->at<int>(P.off_tcell), H->at<int>(P.off_tptr), H->at<int>(P.off_tblob),
+                       H->at<double>(P.off_tw)};
+}
+
+// q = base - A x + scale S m: the dense residual of base, then the spread term
+// added at the touched cells only (M null: no spread term).
+void fg_resid(blob_rd* H, double alpha, const double* base, const SpreadMult* M, double scale, const double* x,
+              double* q) {
+    const Plan& P = H->P;
+    const LevelDims& d = P.lev[0];
+    launch_applyA_plain(H->st, x, q, alpha, H->prm.D / (d.h * d.h), d.nx, d.ny, d.nz);
+    launch_axpby(H->st, q, base, P.ncell, -1.0, 1.0);
+    if (M) launch_spread_sparse(H->st, spread_lists(H), *M, q, q, scale, nullptr);
+    H->alg_bytes += (double)P.ncell * (16 + 24);
+}
+
+// n multigrid cycles for A x = r, r = base + scale S m (M null: r = base), as a
+// stationary iteration: from a zero guess the first cycle is x = V r (base
+// enters the V-cycle densely and the spread term at the touched cells, so r is
+// never formed), every further cycle (all of them when x holds a guess) adds
+// V (r - A x).
+template <typename T>
+void fg_cycles(blob_rd* H, double alpha, const double* base, const SpreadMult* M, double scale, double* x,
+               bool from_zero, int n, const double* cinv) {
+    const Plan& P = H->P;
+    const LevelDims& d = P.lev[0];
+    const double inv_diag = 1.0 / (alpha + 6.0 * H->prm.D / (d.h * d.h));
+    T* z0 = H->at<T>(P.off_lvl[0][0]);
+    T* z1 = H->at<T>(P.off_lvl[0][1]);
+    T* f0 = H->at<T>(P.off_lvl[0][2]);
+    T* f1 = H->at<T>(P.off_lvl[0][3]);
+    double* q = H->grid(G_Q);
+    for (int k = 0; k < n; ++k) {
+        if (k == 0 && from_zero) {
+            launch_enter<T>(H->st, base, f0, f1, z0, d.nx, d.ny, d.nz, inv_diag, nullptr);
+            if (M) launch_spread_enter<T>(H->st, spread_lists(H), *M, base, scale, f0, f1, z0, d.nx, d.ny, inv_diag);
+            H->alg_bytes += (double)P.ncell * (8 + 1.5 * P.esz);
+            vcycle<T>(H, alpha, nullptr, nullptr, cinv, true);
+            launch_split_to_nat<T>(H->st, z0, z1, x, d.nx, d.ny, d.nz, 0.0);
+            H->alg_bytes += (double)P.ncell * (P.esz + 8);
+        } else {
+            fg_resid(H, alpha, base, M, scale, x, q);
+            vcycle<T>(H, alpha, q, nullptr, cinv);
+            launch_split_to_nat<T>(H->st, z0, z1, x, d.nx, d.ny, d.nz, 1.0);
+            H->alg_bytes += (double)P.ncell * (P.esz + 16);
+        }
+    }
+}
+
+void fg_spread(blob_rd* H, const double* lam, const double* base_in, double* out, double scale, int add_only) {
+    const Plan& P = H->P;
+    spread_to(H, lam, 0.0, base_in, out, scale, nullptr);
+    H->alg_bytes += (double)P.ncell * (base_in && !add_only ? 16 : 8);
+}
+
+void fg_interp(blob_rd* H, const double* c, double* out) {
+    const Plan& P = H->P;
+    launch_interp(H->st, c, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts), H->at<int>(P.off_perm),
+                  nullptr, nullptr, out, nullptr);
+}
+
+// [yg; yl] = [A, S; J, 0] [xg; xl]
+void fg_apply_K(blob_rd* H, double alpha, const double* xg, const double* xl, double* yg, double* yl) {
+    const Plan& P = H->P;
+    const LevelDims& d = P.lev[0];
+    launch_applyA_plain(H->st, xg, yg, alpha, H->prm.D / (d.h * d.h), d.nx, d.ny, d.nz);
+    H->alg_bytes += (double)P.ncell * 16;
+    fg_spread(H, xl, yg, yg, H->inv_h3(), 1);
+    fg_interp(H, xg, yl);
+}
+
+// One application of the preconditioner to [vg; vf] -> [zg; zl] (steps 1-5 of
+// the appendix). For A = -D L (alpha = 0): the mean multiplier from the total
+// source, the blob-space mean projected out of h~, of each inner product and of
+// lam~ (a constant offset of an approximate concentration only shifts J c by a
+// constant, which that projection removes), and the mean concentration from the
+// constraint. The right-hand sides vg - lbar S 1 and vg - S (lam~ + lbar) are
+// never formed on the grid: vg enters densely and the spread terms at the
+// touched cells. Grid scratch: G_Q, G_U.
+template <typename T>
+void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, const double* vf, double* zg,
+                double* zl) {
+    const Plan& P = H->P;
+    hipStream_t st = H->st;
+    const int N = P.N;
+    const double h3 = H->prm.h * H->prm.h * H->prm.h;
+    const double* cinv = select_cinv(H, alpha);
+    const bool sing = alpha == 0.0;
+    const LevelDims& d = P.lev[0];
+    const SpreadLists L = spread_lists(H);
+    T* z0 = H->at<T>(P.off_lvl[0][0]);
+    T* z1 = H->at<T>(P.off_lvl[0][1]);
+    double* ds = H->dsc() + 48;  // [0] sum of vg, [8..10] sums of vf - J c
+    double* ml = H->nv(3);       // -lbar on every blob (alpha = 0)
+    // 1. concentration estimate c* from vg - lbar S 1
+    if (sing) {
+        unsigned np = 0;
+        launch_norm_partials(st, vg, P.ncell, H->part(), &np);
+        launch_reduce_parts(st, H->part(), np, 1, ds);
+        H->alg_bytes += (double)P.ncell * 8;
+        launch_nvec_copy_scale(st, nullptr, ml, N, 0.0, 0.0);
+        launch_add_shift(st, ml, N, ds, -h3 / N);
+    }
+    const SpreadMult m1{nullptr, ml, 1.0, 0.0};
+    fg_cycles<T>(H, alpha, vg, sing ? &m1 : nullptr, H->inv_h3(), zg, true, o.n, cinv);
+    // 2. Schur-complement system for the (fluctuating) multipliers, right side J c* - vf
+    double* jv = H->nv(6);
+    double* hv = H->nv(4);
+    fg_interp(H, zg, jv);
+    launch_nvec_copy_scale(st, jv, hv, N, 1.0, 0.0);
+    launch_axpby(st, hv, vf, N, 1.0, -1.0);
+    if (sing) launch_nvec_project(st, hv, N);
+    // the learned W approximates the inverse of J (-D L)^+ S on mean-zero multipliers:
+    // it right-preconditions the inner GMRES (plain inner GMRES without it)
+    bool learned = false;
+    if (o.kind == BLOB_RD_SADDLE_LEARNED) {
+        learned = sing && H->lrn.ready && !H->lrn.bad;
+        if (!learned) H->fallback = 1;
+    }
+    if (o.kind == BLOB_RD_SADDLE_DIAGONAL) {
+        launch_nvec_copy_scale(st, hv, zl, N, o.diag, 0.0);
+    } else {
+        // m GMRES iterations on (J A1^{-1} S [W]) y = h~ with one cycle per product, lam~ = [W] y
+        double* V = H->at<double>(P.off_V);
+        double* Hm = H->at<double>(P.off_H);
+        double* gv = H->at<double>(P.off_gv);
+        launch_gmres_start(st, hv, nullptr, 0, V, gv, N, H->gs());
+        T* f0 = H->at<T>(P.off_lvl[0][2]);
+        T* f1 = H->at<T>(P.off_lvl[0][3]);
+        const size_t nh = P.ncell / 2;
+        const double inv_diag = 1.0 / (alpha + 6.0 * H->prm.D / (d.h * d.h));
+        for (int k = 0; k < o.m; ++k) {
+            const double* vk = V + (size_t)k * N;
+            if (learned) {
+                precond_apply(H, vk, H->nv(9));
+                vk = H->nv(9);
+            }
+            // S v enters the V-cycle from the contribution lists: level-0 f is zero
+            // outside the touched cells after the first product of the loop
+            launch_zero<T>(st, z0, nh);
+            if (k == 0) {
+                launch_zero<T>(st, f0, nh);
+                launch_zero<T>(st, f1, nh);
+            }
+            launch_spread_enter<T>(st, L, SpreadMult{vk, nullptr, 0.0, 0.0}, nullptr, H->inv_h3(), f0, f1, z0, d.nx,
+                                   d.ny, inv_diag);
+            H->alg_bytes += (double)nh * P.esz * (k == 0 ? 3 : 1);
+            vcycle<T>(H, alpha, nullptr, nullptr, cinv, true);
+            launch_interp_split<T>(st, z0, z1, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
+                                   H->at<int>(P.off_perm), V + (size_t)(k + 1) * N);
+            launch_gmres_arnoldi(st, V, Hm, H->at<double>(P.off_cs), H->at<double>(P.off_sn), gv, N, k, o.m,
+                                 H->gs(), sing ? 1 : 0);
+        }
+        double* y = learned ? H->nv(10) : zl;
+        launch_nvec_copy_scale(st, nullptr, y, N, 0.0, 0.0);
+        launch_gmres_update(st, V, Hm, gv, H->at<double>(P.off_yv), y, N, o.m, o.m);
+        if (learned) precond_apply(H, y, zl);
+        H->inner_iters += o.m;
+    }
+    if (sing) launch_nvec_project(st, zl, N);
+    // 3. corrected concentration: cycles on A c = vg - S (lam~ + lbar), started at c*
+    const SpreadMult m2{zl, sing ? ml : nullptr, -1.0, 0.0};
+    if (sing && o.n == 1) {
+        // one cycle; 4. the mean concentration from J c* + J z before z is added,
+        // so the shift rides on the pass that adds z
+        double* q = H->grid(G_Q);
+        fg_resid(H, alpha, vg, &m2, -H->inv_h3(), zg, q);
+        vcycle<T>(H, alpha, q, nullptr, cinv);
+        double* jz = H->nv(5);
+        launch_interp_split<T>(st, z0, z1, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
+                               H->at<int>(P.off_perm), jz);
+        launch_axpby(st, jz, vf, N, -1.0, 1.0);  // vf - J z
+        launch_axpby(st, jz, jv, N, 1.0, -1.0);  // vf - J z - J c*
+        launch_nvec_sums(st, jz, nullptr, N, ds + 8);
+        launch_split_to_nat<T>(st, z0, z1, zg, d.nx, d.ny, d.nz, 1.0, ds + 8, 1.0 / N);
+        H->alg_bytes += (double)P.ncell * (P.esz + 16);
+    } else {
+        fg_cycles<T>(H, alpha, vg, &m2, -H->inv_h3(), zg, false, o.n, cinv);
+        if (sing) {
+            // 4. mean concentration: mean over blobs of vf - J c
+            fg_interp(H, zg, jv);
+            launch_axpby(st, jv, vf, N, -1.0, 1.0);
+            launch_nvec_sums(st, jv, nullptr, N, ds + 8);
+            launch_add_shift(st, zg, P.ncell, ds + 8, 1.0 / N);
+            H->alg_bytes += (double)P.ncell * 16;
+        }
+    }
+    // 5. lam = lam~ + lbar
+    if (sing) launch_add_shift(st, zl, N, ds, h3 / N);
+}
+
+// Flexible GMRES (right preconditioned, restarted, modified Gram-Schmidt) on
+// [A, S; J, 0][c; lam] = [f; 0] from a zero guess. Every cycle starts from the
+// true FP64 residual b - K x, which also decides convergence at the end.
+template <typename T>
+int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double* c, double* lam, char* ws,
+             blob_rd_stats* stt, bool warm = false) {
+    const Plan& P = H->P;
+    hipStream_t st = H->st;
+    const size_t ncell = P.ncell, n = ncell + (size_t)P.N, stride = fg_stride(P);
+    const int m = o.restart, ld = m + 1;
+    double* V = reinterpret_cast<double*>(ws);
+    double* Z = V + (size_t)(m + 1) * stride;
+    double* Hd = Z + (size_t)m * stride;
+    double* cs = Hd + (size_t)ld * m;
+    double* sn = cs + ld;
+    double* gv = sn + ld;
+    double* yv = gv + ld;
+    double* sd = yv + ld;  // [0] beta, [2..3] Givens outputs
+    double bnorm = -1.0, rel = 0.0, prev_rel = 0.0;
+    if (warm) {
+        // (c, lam) hold the initial guess; the scale of the residual is |b| = |f|
+        unsigned np = 0;
+        launch_norm_partials(st, f, ncell, H->part(), &np);
+        launch_reduce_parts(st, H->part(), np, 2, sd + 4);
+        sync_read(H, H->hbuf, sd + 4, 16);
+        bnorm = H->hbuf[1] > 0.0 ? std::sqrt(H->hbuf[1]) : 1.0;
+        H->alg_bytes += (double)ncell * 8;
+    } else {
+        launch_fill(st, c, ncell, 0.0);
+        launch_fill(st, lam, P.N, 0.0);
+    }
+    int its = 0, cycles = 0, stalled = 0;
+    bool sub = warm;
+    for (;;) {
+        if (sub) fg_apply_K(H, alpha, c, lam, V, V + ncell);
+        unsigned np = 0;
+        launch_fg_resid(st, V, f, ncell, n, sub ? 1 : 0, H->part(), &np);
+        launch_fg_fin(st, H->part(), np, sd, 1);
+        H->alg_bytes += (double)n * (sub ? 24 : 16);
+        sync_read(H, H->hbuf, sd, 8);
+        const double beta = H->hbuf[0];
+        if (!std::isfinite(beta)) throw Err(BLOB_RD_ENUMERIC, "non-finite FGMRES residual");
+        if (bnorm < 0.0) bnorm = beta > 0.0 ? beta : 1.0;  // zero start: the first residual is b
+        rel = beta / bnorm;
+        if (rel <= o.rtol || its >= o.maxit) break;
+        // A restarted cycle cannot raise the true residual; two cycles in a row that cut it
+        // by less than 1 % mean the rounding floor of the residual is above rtol.
+        stalled = (cycles > 0 && rel > 0.99 * prev_rel) ? stalled + 1 : 0;
+        if (stalled >= 2) break;
+        prev_rel = rel;
+        ++cycles;
+        launch_fg_scale(st, V, sd, n);
+        launch_fg_gstart(st, gv, ld, sd);
+        H->alg_bytes += (double)n * 16;
+        int k = 0;
+        for (int j = 0; j < m && its < o.maxit; ++j) {
+            double* vj = V + (size_t)j * stride;
+            double* zj = Z + (size_t)j * stride;
+            double* w = V + (size_t)(j + 1) * stride;
+            fg_precond<T>(H, alpha, o, vj, vj + ncell, zj, zj + ncell);
+            fg_apply_K(H, alpha, zj, zj + ncell, w, w + ncell);
+            double* col = Hd + (size_t)j * ld;
+            for (int i = 0; i <= j + 1; ++i) {
+                const double* vprev = i > 0 ? V + (size_t)(i - 1) * stride : nullptr;
+                const double* vnext = i <= j ? V + (size_t)i * stride : nullptr;
+                launch_fg_mgs(st, w, vprev, i > 0 ? col + (i - 1) : nullptr, vnext, n, H->part(), &np);
+                launch_fg_fin(st, H->part(), np, col + i, i == j + 1);
+                H->alg_bytes += (double)n * 8 * ((vprev ? 3 : 1) + (vnext ? 1 : 0));
+            }
+            launch_fg_scale(st, w, col + j + 1, n);
+            H->alg_bytes += (double)n * 16;
+            launch_fg_givens(st, Hd, ld, cs, sn, gv, j, sd + 2);
+            sync_read(H, H->hbuf, sd + 2, 16);
+            ++its;
+            k = j + 1;
+            const double res = H->hbuf[0], sub_diag = H->hbuf[1];
+            if (!std::isfinite(res) || !std::isfinite(sub_diag)) throw Err(BLOB_RD_ENUMERIC, "FGMRES breakdown");
+            if (res <= o.rtol * bnorm || sub_diag == 0.0) break;
+        }
+        launch_fg_backsolve(st, Hd, ld, gv, yv, k);
+        launch_fg_update(st, c, Z, stride, 0, ncell, k, yv);
+        launch_fg_update(st, lam, Z, stride, ncell, P.N, k, yv);
+        H->alg_bytes += (double)n * 8 * (k + 2);
+        sub = true;
+    }
+    if (stt) {
+        stt->outer_iters = its;
+        stt->rel_resid = rel;
+        stt->refinements = cycles > 0 ? cycles - 1 : 0;
+    }
+    return rel <= o.rtol ? BLOB_RD_OK : BLOB_RD_ENOTCONV;
+}
+
+
+// Block solver options of a handle created with saddle_solver != BLOB_RD_SOLVER_SCHUR
+// (the learned inner preconditioning only where W applies, alpha = 0).
+FgOpts handle_fg_opts(const blob_rd* H, double alpha) {
+    blob_rd_saddle_opts o{};
+    o.precond = (H->prm.saddle_solver == BLOB_RD_SOLVER_BLOCK_LEARNED && alpha == 0.0) ? BLOB_RD_SADDLE_LEARNED
+                                                                                        : BLOB_RD_SADDLE_APPROX_SCHUR;
+    o.restart = H->P.restart;
+    o.maxit = H->prm.max_iter;
+    return fg_opts(H, &o);
+}
+
+}  // namespace
+
+// ===========================================================================
 // C ABI
 // ===========================================================================
 extern "C" {
@@ -1338,9 +1679,19 @@ int blob_rd_step_absorbing(blob_rd_t H, double dt, const double* f, double* c, d
         hipLaunchKernelGGL(k_step_rhs, dim3(nblocks(H->P.ncell)), dim3(kBlock), 0, H->st, f, c, g,
                            (unsigned)H->P.ncell, 1.0 / dt);
         H->alg_bytes += (double)H->P.ncell * 24;
-        const double* lam0 = warm ? lambda : nullptr;
-        int rc = H->P.esz == 4 ? absorbing_solve<float>(H, 1.0 / dt, g, c, lambda, stt, lam0)
+        int rc;
+        if (H->prm.saddle_solver != BLOB_RD_SOLVER_SCHUR) {
+            // block FGMRES started from (c^n, previous multipliers or zero)
+            if (!warm) launch_fill(H->st, lambda, H->P.N, 0.0);
+            const FgOpts o = handle_fg_opts(H, 1.0 / dt);
+            char* ws = H->ws + H->P.off_fg;
+            rc = H->P.esz == 4 ? fg_solve<float>(H, 1.0 / dt, o, g, c, lambda, ws, stt, true)
+                               : fg_solve<double>(H, 1.0 / dt, o, g, c, lambda, ws, stt, true);
+        } else {
+            const double* lam0 = warm ? lambda : nullptr;
+            rc = H->P.esz == 4 ? absorbing_solve<float>(H, 1.0 / dt, g, c, lambda, stt, lam0)
                                : absorbing_solve<double>(H, 1.0 / dt, g, c, lambda, stt, lam0);
+        }
         HIPCHK(hipGetLastError());
         return rc;
     });
@@ -1353,8 +1704,9 @@ int blob_rd_solve_absorbing(blob_rd_t H, double alpha, const double* f, double* 
     if (!(alpha >= 0.0) || !std::isfinite(alpha)) return g_last_error = "alpha must be >= 0", BLOB_RD_EINVAL;
     if (H->prm.saddle_solver != BLOB_RD_SOLVER_SCHUR) {
         blob_rd_saddle_opts o{};
-        o.precond = H->prm.saddle_solver == BLOB_RD_SOLVER_BLOCK_LEARNED ? BLOB_RD_SADDLE_LEARNED
-                                                                          : BLOB_RD_SADDLE_APPROX_SCHUR;
+        o.precond = (H->prm.saddle_solver == BLOB_RD_SOLVER_BLOCK_LEARNED && alpha == 0.0)
+                        ? BLOB_RD_SADDLE_LEARNED
+                        : BLOB_RD_SADDLE_APPROX_SCHUR;
         o.restart = H->P.restart;
         o.maxit = H->prm.max_iter;
         return blob_rd_solve_absorbing_fgmres(H, alpha, &o, f, c, lambda, H->ws + H->P.off_fg, H->P.fg_size, stt);
@@ -2633,325 +2985,6 @@ int blob_rd_solve_batched(blob_rd_t* hs, int32_t n, const int32_t* kind, double 
 // diffusion-limited case; appendix on preconditioning the saddle-point
 // solver): flexible GMRES on the whole block system [A, S; J, 0] with the
 // diagonal or the approximate-Schur-complement preconditioner.
-// ===========================================================================
-namespace {
-
-struct FgOpts {
-    int kind = BLOB_RD_SADDLE_APPROX_SCHUR;
-    int m = 5, n = 1, restart = 30, maxit = 1000;
-    double rtol = 1e-8, diag = 0.0;
-};
-
-// reactive radius of a blob in units of h (Sec. IV.A): the position average of the
-// four-point kernel, and the three-point kernel's value at a node
-constexpr double kA0OverH = 1.255;
-constexpr double kA0OverH3 = 0.885;
-
-FgOpts fg_opts(const blob_rd* H, const blob_rd_saddle_opts* o) {
-    FgOpts r;
-    r.rtol = H->prm.rtol > 0.0 ? H->prm.rtol : 1e-8;
-    if (o) {
-        r.kind = o->precond;
-        if (o->m > 0) r.m = o->m;
-        if (o->n > 0) r.n = o->n;
-        if (o->restart > 0) r.restart = o->restart;
-        if (o->maxit > 0) r.maxit = o->maxit;
-        if (o->rtol > 0.0) r.rtol = o->rtol;
-        r.diag = o->diag;
-        if (o->m < 0 || o->n < 0 || o->restart < 0 || o->maxit < 0 || !(o->rtol >= 0.0) || !(o->diag >= 0.0) ||
-            !std::isfinite(o->diag) || !std::isfinite(o->rtol))
-            throw Err(BLOB_RD_EINVAL, "saddle solver options must be non-negative and finite");
-    }
-    if (r.kind != BLOB_RD_SADDLE_DIAGONAL && r.kind != BLOB_RD_SADDLE_APPROX_SCHUR &&
-        r.kind != BLOB_RD_SADDLE_LEARNED)
-        throw Err(BLOB_RD_EINVAL, "unknown saddle preconditioner");
-    if (r.m > H->P.restart)
-        throw Err(BLOB_RD_EINVAL, "inner Krylov iterations exceed the handle's GMRES restart length");
-    if (r.n > 64) throw Err(BLOB_RD_EINVAL, "at most 64 multigrid cycles per approximate solve");
-    if (r.restart > kFgMaxRestart) throw Err(BLOB_RD_EINVAL, "FGMRES restart length above 1024");
-    if (r.diag == 0.0) r.diag = 4.0 * M_PI * (H->prm.kernel_w == 3 ? kA0OverH3 : kA0OverH) * H->prm.h * H->prm.D;
-    return r;
-}
-
-
-SpreadLists spread_lists(const blob_rd* H) {
-    const Plan& P = H->P;
-    return SpreadLists{H->ntouched, H->at<int>(P.off_tcell), H->at<int>(P.off_tptr), H->at<int>(P.off_tblob),
-                       H->at<double>(P.off_tw)};
-}
-
-// q = base - A x + scale S m: the dense residual of base, then the spread term
-// added at the touched cells only (M null: no spread term).
-void fg_resid(blob_rd* H, double alpha, const double* base, const SpreadMult* M, double scale, const double* x,
-              double* q) {
-    const Plan& P = H->P;
-    const LevelDims& d = P.lev[0];
-    launch_applyA_plain(H->st, x, q, alpha, H->prm.D / (d.h * d.h), d.nx, d.ny, d.nz);
-    launch_axpby(H->st, q, base, P.ncell, -1.0, 1.0);
-    if (M) launch_spread_sparse(H->st, spread_lists(H), *M, q, q, scale, nullptr);
-    H->alg_bytes += (double)P.ncell * (16 + 24);
-}
-
-// n multigrid cycles for A x = r, r = base + scale S m (M null: r = base), as a
-// stationary iteration: from a zero guess the first cycle is x = V r (base
-// enters the V-cycle densely and the spread term at the touched cells, so r is
-// never formed), every further cycle (all of them when x holds a guess) adds
-// V (r - A x).
-template <typename T>
-void fg_cycles(blob_rd* H, double alpha, const double* base, const SpreadMult* M, double scale, double* x,
-               bool from_zero, int n, const double* cinv) {
-    const Plan& P = H->P;
-    const LevelDims& d = P.lev[0];
-    const double inv_diag = 1.0 / (alpha + 6.0 * H->prm.D / (d.h * d.h));
-    T* z0 = H->at<T>(P.off_lvl[0][0]);
-    T* z1 = H->at<T>(P.off_lvl[0][1]);
-    T* f0 = H->at<T>(P.off_lvl[0][2]);
-    T* f1 = H->at<T>(P.off_lvl[0][3]);
-    double* q = H->grid(G_Q);
-    for (int k = 0; k < n; ++k) {
-        if (k == 0 && from_zero) {
-            launch_enter<T>(H->st, base, f0, f1, z0, d.nx, d.ny, d.nz, inv_diag, nullptr);
-            if (M) launch_spread_enter<T>(H->st, spread_lists(H), *M, base, scale, f0, f1, z0, d.nx, d.ny, inv_diag);
-            H->alg_bytes += (double)P.ncell * (8 + 1.5 * P.esz);
-            vcycle<T>(H, alpha, nullptr, nullptr, cinv, true);
-            launch_split_to_nat<T>(H->st, z0, z1, x, d.nx, d.ny, d.nz, 0.0);
-            H->alg_bytes += (double)P.ncell * (P.esz + 8);
-        } else {
-            fg_resid(H, alpha, base, M, scale, x, q);
-            vcycle<T>(H, alpha, q, nullptr, cinv);
-            launch_split_to_nat<T>(H->st, z0, z1, x, d.nx, d.ny, d.nz, 1.0);
-            H->alg_bytes += (double)P.ncell * (P.esz + 16);
-        }
-    }
-}
-
-void fg_spread(blob_rd* H, const double* lam, const double* base_in, double* out, double scale, int add_only) {
-    const Plan& P = H->P;
-    spread_to(H, lam, 0.0, base_in, out, scale, nullptr);
-    H->alg_bytes += (double)P.ncell * (base_in && !add_only ? 16 : 8);
-}
-
-void fg_interp(blob_rd* H, const double* c, double* out) {
-    const Plan& P = H->P;
-    launch_interp(H->st, c, P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts), H->at<int>(P.off_perm),
-                  nullptr, nullptr, out, nullptr);
-}
-
-// [yg; yl] = [A, S; J, 0] [xg; xl]
-void fg_apply_K(blob_rd* H, double alpha, const double* xg, const double* xl, double* yg, double* yl) {
-    const Plan& P = H->P;
-    const LevelDims& d = P.lev[0];
-    launch_applyA_plain(H->st, xg, yg, alpha, H->prm.D / (d.h * d.h), d.nx, d.ny, d.nz);
-    H->alg_bytes += (double)P.ncell * 16;
-    fg_spread(H, xl, yg, yg, H->inv_h3(), 1);
-    fg_interp(H, xg, yl);
-}
-
-// One application of the preconditioner to [vg; vf] -> [zg; zl] (steps 1-5 of
-// the appendix). For A = -D L (alpha = 0): the mean multiplier from the total
-// source, the blob-space mean projected out of h~, of each inner product and of
-// lam~ (a constant offset of an approximate concentration only shifts J c by a
-// constant, which that projection removes), and the mean concentration from the
-// constraint. The right-hand sides vg - lbar S 1 and vg - S (lam~ + lbar) are
-// never formed on the grid: vg enters densely and the spread terms at the
-// touched cells. Grid scratch: G_Q, G_U.
-template <typename T>
-void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, const double* vf, double* zg,
-                double* zl) {
-    const Plan& P = H->P;
-    hipStream_t st = H->st;
-    const int N = P.N;
-    const double h3 = H->prm.h * H->prm.h * H->prm.h;
-    const double* cinv = select_cinv(H, alpha);
-    const bool sing = alpha == 0.0;
-    const LevelDims& d = P.lev[0];
-    const SpreadLists L = spread_lists(H);
-    T* z0 = H->at<T>(P.off_lvl[0][0]);
-    T* z1 = H->at<T>(P.off_lvl[0][1]);
-    double* ds = H->dsc() + 48;  // [0] sum of vg, [8..10] sums of vf - J c
-    double* ml = H->nv(3);       // -lbar on every blob (alpha = 0)
-    // 1. concentration estimate c* from vg - lbar S 1
-    if (sing) {
-        unsigned np = 0;
-        launch_norm_partials(st, vg, P.ncell, H->part(), &np);
-        launch_reduce_parts(st, H->part(), np, 1, ds);
-        H->alg_bytes += (double)P.ncell * 8;
-        launch_nvec_copy_scale(st, nullptr, ml, N, 0.0, 0.0);
-        launch_add_shift(st, ml, N, ds, -h3 / N);
-    }
-    const SpreadMult m1{nullptr, ml, 1.0, 0.0};
-    fg_cycles<T>(H, alpha, vg, sing ? &m1 : nullptr, H->inv_h3(), zg, true, o.n, cinv);
-    // 2. Schur-complement system for the (fluctuating) multipliers, right side J c* - vf
-    double* jv = H->nv(6);
-    double* hv = H->nv(4);
-    fg_interp(H, zg, jv);
-    launch_nvec_copy_scale(st, jv, hv, N, 1.0, 0.0);
-    launch_axpby(st, hv, vf, N, 1.0, -1.0);
-    if (sing) launch_nvec_project(st, hv, N);
-    // the learned W approximates the inverse of J (-D L)^+ S on mean-zero multipliers:
-    // it right-preconditions the inner GMRES (plain inner GMRES without it)
-    bool learned = false;
-    if (o.kind == BLOB_RD_SADDLE_LEARNED) {
-        learned = sing && H->lrn.ready && !H->lrn.bad;
-        if (!learned) H->fallback = 1;
-    }
-    if (o.kind == BLOB_RD_SADDLE_DIAGONAL) {
-        launch_nvec_copy_scale(st, hv, zl, N, o.diag, 0.0);
-    } else {
-        // m GMRES iterations on (J A1^{-1} S [W]) y = h~ with one cycle per product, lam~ = [W] y
-        double* V = H->at<double>(P.off_V);
-        double* Hm = H->at<double>(P.off_H);
-        double* gv = H->at<double>(P.off_gv);
-        launch_gmres_start(st, hv, nullptr, 0, V, gv, N, H->gs());
-        T* f0 = H->at<T>(P.off_lvl[0][2]);
-        T* f1 = H->at<T>(P.off_lvl[0][3]);
-        const size_t nh = P.ncell / 2;
-        const double inv_diag = 1.0 / (alpha + 6.0 * H->prm.D / (d.h * d.h));
-        for (int k = 0; k < o.m; ++k) {
-            const double* vk = V + (size_t)k * N;
-            if (learned) {
-                precond_apply(H, vk, H->nv(9));
-                vk = H->nv(9);
-            }
-            // S v enters the V-cycle from the contribution lists: level-0 f is zero
-            // outside the touched cells after the first product of the loop
-            launch_zero<T>(st, z0, nh);
-            if (k == 0) {
-                launch_zero<T>(st, f0, nh);
-                launch_zero<T>(st, f1, nh);
-            }
-            launch_spread_enter<T>(st, L, SpreadMult{vk, nullptr, 0.0, 0.0}, nullptr, H->inv_h3(), f0, f1, z0, d.nx,
-                                   d.ny, inv_diag);
-            H->alg_bytes += (double)nh * P.esz * (k == 0 ? 3 : 1);
-            vcycle<T>(H, alpha, nullptr, nullptr, cinv, true);
-            launch_interp_split<T>(st, z0, z1, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
-                                   H->at<int>(P.off_perm), V + (size_t)(k + 1) * N);
-            launch_gmres_arnoldi(st, V, Hm, H->at<double>(P.off_cs), H->at<double>(P.off_sn), gv, N, k, o.m,
-                                 H->gs(), sing ? 1 : 0);
-        }
-        double* y = learned ? H->nv(10) : zl;
-        launch_nvec_copy_scale(st, nullptr, y, N, 0.0, 0.0);
-        launch_gmres_update(st, V, Hm, gv, H->at<double>(P.off_yv), y, N, o.m, o.m);
-        if (learned) precond_apply(H, y, zl);
-        H->inner_iters += o.m;
-    }
-    if (sing) launch_nvec_project(st, zl, N);
-    // 3. corrected concentration: cycles on A c = vg - S (lam~ + lbar), started at c*
-    const SpreadMult m2{zl, sing ? ml : nullptr, -1.0, 0.0};
-    if (sing && o.n == 1) {
-        // one cycle; 4. the mean concentration from J c* + J z before z is added,
-        // so the shift rides on the pass that adds z
-        double* q = H->grid(G_Q);
-        fg_resid(H, alpha, vg, &m2, -H->inv_h3(), zg, q);
-        vcycle<T>(H, alpha, q, nullptr, cinv);
-        double* jz = H->nv(5);
-        launch_interp_split<T>(st, z0, z1, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
-                               H->at<int>(P.off_perm), jz);
-        launch_axpby(st, jz, vf, N, -1.0, 1.0);  // vf - J z
-        launch_axpby(st, jz, jv, N, 1.0, -1.0);  // vf - J z - J c*
-        launch_nvec_sums(st, jz, nullptr, N, ds + 8);
-        launch_split_to_nat<T>(st, z0, z1, zg, d.nx, d.ny, d.nz, 1.0, ds + 8, 1.0 / N);
-        H->alg_bytes += (double)P.ncell * (P.esz + 16);
-    } else {
-        fg_cycles<T>(H, alpha, vg, &m2, -H->inv_h3(), zg, false, o.n, cinv);
-        if (sing) {
-            // 4. mean concentration: mean over blobs of vf - J c
-            fg_interp(H, zg, jv);
-            launch_axpby(st, jv, vf, N, -1.0, 1.0);
-            launch_nvec_sums(st, jv, nullptr, N, ds + 8);
-            launch_add_shift(st, zg, P.ncell, ds + 8, 1.0 / N);
-            H->alg_bytes += (double)P.ncell * 16;
-        }
-    }
-    // 5. lam = lam~ + lbar
-    if (sing) launch_add_shift(st, zl, N, ds, h3 / N);
-}
-
-// Flexible GMRES (right preconditioned, restarted, modified Gram-Schmidt) on
-// [A, S; J, 0][c; lam] = [f; 0] from a zero guess. Every cycle starts from the
-// true FP64 residual b - K x, which also decides convergence at the end.
-template <typename T>
-int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double* c, double* lam, char* ws,
-             blob_rd_stats* stt) {
-    const Plan& P = H->P;
-    hipStream_t st = H->st;
-    const size_t ncell = P.ncell, n = ncell + (size_t)P.N, stride = fg_stride(P);
-    const int m = o.restart, ld = m + 1;
-    double* V = reinterpret_cast<double*>(ws);
-    double* Z = V + (size_t)(m + 1) * stride;
-    double* Hd = Z + (size_t)m * stride;
-    double* cs = Hd + (size_t)ld * m;
-    double* sn = cs + ld;
-    double* gv = sn + ld;
-    double* yv = gv + ld;
-    double* sd = yv + ld;  // [0] beta, [2..3] Givens outputs
-    launch_fill(st, c, ncell, 0.0);
-    launch_fill(st, lam, P.N, 0.0);
-    int its = 0, cycles = 0, stalled = 0;
-    double bnorm = -1.0, rel = 0.0, prev_rel = 0.0;
-    bool sub = false;
-    for (;;) {
-        if (sub) fg_apply_K(H, alpha, c, lam, V, V + ncell);
-        unsigned np = 0;
-        launch_fg_resid(st, V, f, ncell, n, sub ? 1 : 0, H->part(), &np);
-        launch_fg_fin(st, H->part(), np, sd, 1);
-        H->alg_bytes += (double)n * (sub ? 24 : 16);
-        sync_read(H, H->hbuf, sd, 8);
-        const double beta = H->hbuf[0];
-        if (!std::isfinite(beta)) throw Err(BLOB_RD_ENUMERIC, "non-finite FGMRES residual");
-        if (bnorm < 0.0) bnorm = beta > 0.0 ? beta : 1.0;
-        rel = beta / bnorm;
-        if (rel <= o.rtol || its >= o.maxit) break;
-        // A restarted cycle cannot raise the true residual; two cycles in a row that cut it
-        // by less than 1 % mean the rounding floor of the residual is above rtol.
-        stalled = (cycles > 0 && rel > 0.99 * prev_rel) ? stalled + 1 : 0;
-        if (stalled >= 2) break;
-        prev_rel = rel;
-        ++cycles;
-        launch_fg_scale(st, V, sd, n);
-        launch_fg_gstart(st, gv, ld, sd);
-        H->alg_bytes += (double)n * 16;
-        int k = 0;
-        for (int j = 0; j < m && its < o.maxit; ++j) {
-            double* vj = V + (size_t)j * stride;
-            double* zj = Z + (size_t)j * stride;
-            double* w = V + (size_t)(j + 1) * stride;
-            fg_precond<T>(H, alpha, o, vj, vj + ncell, zj, zj + ncell);
-            fg_apply_K(H, alpha, zj, zj + ncell, w, w + ncell);
-            double* col = Hd + (size_t)j * ld;
-            for (int i = 0; i <= j + 1; ++i) {
-                const double* vprev = i > 0 ? V + (size_t)(i - 1) * stride : nullptr;
-                const double* vnext = i <= j ? V + (size_t)i * stride : nullptr;
-                launch_fg_mgs(st, w, vprev, i > 0 ? col + (i - 1) : nullptr, vnext, n, H->part(), &np);
-                launch_fg_fin(st, H->part(), np, col + i, i == j + 1);
-                H->alg_bytes += (double)n * 8 * ((vprev ? 3 : 1) + (vnext ? 1 : 0));
-            }
-            launch_fg_scale(st, w, col + j + 1, n);
-            H->alg_bytes += (double)n * 16;
-            launch_fg_givens(st, Hd, ld, cs, sn, gv, j, sd + 2);
-            sync_read(H, H->hbuf, sd + 2, 16);
-            ++its;
-            k = j + 1;
-            const double res = H->hbuf[0], sub_diag = H->hbuf[1];
-            if (!std::isfinite(res) || !std::isfinite(sub_diag)) throw Err(BLOB_RD_ENUMERIC, "FGMRES breakdown");
-            if (res <= o.rtol * bnorm || sub_diag == 0.0) break;
-        }
-        launch_fg_backsolve(st, Hd, ld, gv, yv, k);
-        launch_fg_update(st, c, Z, stride, 0, ncell, k, yv);
-        launch_fg_update(st, lam, Z, stride, ncell, P.N, k, yv);
-        H->alg_bytes += (double)n * 8 * (k + 2);
-        sub = true;
-    }
-    if (stt) {
-        stt->outer_iters = its;
-        stt->rel_resid = rel;
-        stt->refinements = cycles > 0 ? cycles - 1 : 0;
-    }
-    return rel <= o.rtol ? BLOB_RD_OK : BLOB_RD_ENOTCONV;
-}
-
-}  // namespace
-
 extern "C" {
 
 size_t blob_rd_fgmres_workspace_bytes(blob_rd_t H, int restart) {

@@ -244,18 +244,18 @@ def test_backward_euler_steps(dev):
     S.close()
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_absorbing_steps(dev, prec):
+@pytest.mark.parametrize("prec,solver", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_absorbing_steps(dev, prec, solver):
     """Backward-Euler steps of an absorbing suspension (A = I/dt - D L, J c = 0) against the
     oracle's exact steps, with GMRES warm-started from the previous step's multipliers; a cold
     start reaches the same answer within the tolerance."""
-    _say("absorbing steps", prec)
+    _say("absorbing steps", prec, solver)
     rng = np.random.default_rng(53)
     n, dt = 32, 0.5
     q = W.rsa_positions(rng, n, 30, 3.0)
     f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
     tol = 1e-10 if prec == 0 else 1e-8
-    S = make(dev, n, q, precision=prec, rtol=tol)
+    S = make(dev, n, q, precision=prec, rtol=tol, saddle_solver=solver)
     G = ex.schur_matrix(q, (n, n, n), 1.0 / dt)
     c = torch.zeros((n, n, n), dtype=torch.float64, device=dev)
     lam = torch.zeros(30, dtype=torch.float64, device=dev)
@@ -459,16 +459,18 @@ def test_rsa256_backward_euler(dev, rsa256):
     S.close()
 
 
-def test_rsa256_absorbing_steps(dev, rsa256):
+@pytest.mark.parametrize("solver", [0, 1])
+def test_rsa256_absorbing_steps(dev, rsa256, solver):
     """Absorbing suspension at full size (256^3, 2e4 RSA blobs), five backward-Euler steps
     dt = 0.5 from c = 0 with warm-started multipliers: every step meets 1e-8, the first is
     checked by the oracle's FP64 saddle residual, every step keeps the discrete mass balance
     h^3 sum(c1 - c0)/dt = h^3 sum(f) - sum(lam) up to its residual, and the warm starts need
-    fewer GMRES iterations than the cold first step."""
+    no more Krylov iterations than the cold first step (Schur GMRES, or the block FGMRES
+    started from c^n and the previous multipliers)."""
     inst = rsa256
-    _say("rsa256 absorbing steps")
+    _say("rsa256 absorbing steps", solver)
     n, dt = inst.n, 0.5
-    S = make(dev, n, inst.q, precision=1, rtol=1e-8)
+    S = make(dev, n, inst.q, precision=1, rtol=1e-8, saddle_solver=solver)
     c = torch.zeros((n,) * 3, dtype=torch.float64, device=dev)
     lam = torch.zeros(inst.q.shape[0], dtype=torch.float64, device=dev)
     f = T(inst.f, dev)
@@ -485,7 +487,7 @@ def test_rsa256_absorbing_steps(dev, rsa256):
         if k == 0:
             assert ex.absorbing_residual(H(c), H(lam), inst.f, inst.q, 1.0 / dt) <= 1e-8
     print("rsa256 absorbing steps, GMRES iterations", iters, flush=True)
-    assert max(iters[1:]) < iters[0]
+    assert max(iters[1:]) <= iters[0]
     S.close()
 
 
