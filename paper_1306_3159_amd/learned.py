@@ -116,14 +116,14 @@ def train(net: Net, samples: List[Sample], epochs: int, lr: float, batch: int, d
 
 
 def block_iterations(shape, q: np.ndarray, f: torch.Tensor, net: Optional[Net], device, rtol: float = 1e-8,
-                     precision: int = MIXED, m: int = 5):
+                     precision: int = MIXED, m: int = 5, kind: Optional[str] = None):
     """Block FGMRES iterations and wall time of one absorbing solve with the approximate-Schur
-    preconditioner, its inner GMRES preconditioned by W (net) or not."""
+    preconditioner, its inner GMRES preconditioned by W (net) or not (or kind = "diagonal")."""
     S = BlobRD(shape, torch.tensor(q, device=device), precision=precision, rtol=rtol,
                schur_precond=PRECOND_LEARNED if net is not None else PRECOND_NONE)
     if net is not None:
         S.precond_build(net)
-    kind = "learned" if net is not None else "schur"
+    kind = kind or ("learned" if net is not None else "schur")
     S.solve_absorbing_fgmres(f, precond=kind, m=m)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -40,6 +40,49 @@ def _positions(arg):
     return W.training_config(i, n, blobs).q
 
 
+def evaluate(net, spec_list: str, dev, W, LD, MIXED, FP64):
+    """Held-out absorbing solves (f = 1) with and without the network: Schur GMRES (plain FP64,
+    FP32 cycles, learned) and the block FGMRES (diagonal, approximate Schur, learned inner)."""
+    import torch
+    rows = []
+    for spec in spec_list.split(","):
+        if not spec:
+            continue
+        n, N, cnt = (int(v) for v in spec.split(":"))
+        for k in range(cnt):
+            inst = W.learned_eval(n, N, index=100 + k) if n == 256 else W.training_config(900_000 + k, n, N)
+            f = torch.ones((n, n, n), dtype=torch.float64, device=dev)
+            row = {"n": n, "N": N, "seed": inst.seed}
+            runs = (("plain_fp64", None, FP64, LD.gmres_iterations, {}),
+                    ("mixed", None, MIXED, LD.gmres_iterations, {}),
+                    ("learned_mixed", net, MIXED, LD.gmres_iterations, {}),
+                    ("block_diagonal_mixed", None, MIXED, LD.block_iterations, {"kind": "diagonal"}),
+                    ("block_mixed", None, MIXED, LD.block_iterations, {}),
+                    ("block_learned_mixed", net, MIXED, LD.block_iterations, {}))
+            for name, netx, prec, fn, kw in runs:
+                st, dt, c, lam = fn(n, inst.q, f, netx, dev, precision=prec, **kw)
+                row[name] = {"iters": st["outer_iters"], "inner_iters": st["inner_iters_total"],
+                             "vcycles": st["vcycles"], "seconds": dt, "rel_resid": st["rel_resid"], "rc": st["rc"],
+                             "fallback": st["fallback"]}
+                log(f"eval n={n} N={N} seed={inst.seed} {name}: iters={st['outer_iters']} "
+                    f"inner={st['inner_iters_total']} t={dt:.3f}s resid={st['rel_resid']:.2e}")
+            rows.append(row)
+    return rows
+
+
+def summarize(rows):
+    """Median iterations and seconds per method over the evaluated configurations."""
+    out = {}
+    if not rows:
+        return out
+    for name in [k for k in rows[0] if isinstance(rows[0][k], dict)]:
+        its = [r[name]["iters"] for r in rows]
+        sec = [r[name]["seconds"] for r in rows]
+        out[name] = {"median_iters": float(np.median(its)), "median_seconds": float(np.median(sec)),
+                     "max_rel_resid": max(r[name]["rel_resid"] for r in rows), "configs": len(rows)}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--configs", type=int, default=500)
@@ -56,6 +99,8 @@ def main(argv=None):
     ap.add_argument("--lr-final", type=float, default=None,
                     help="cosine-decay the learning rate to this value over the epochs (default: constant)")
     ap.add_argument("--workers", type=int, default=1, help="host processes generating the configurations")
+    ap.add_argument("--eval-only", default=None, metavar="WEIGHTS",
+                    help="skip training: evaluate these saved weights on the --eval sets and print the report")
     ap.add_argument("--cycles", type=int, default=0,
                     help="train against the approximate-Schur operator with this many multigrid cycles per product "
                          "(the block preconditioner's inner operator); 0: Schur products with inner solves")
@@ -68,6 +113,13 @@ def main(argv=None):
 
     dev = torch.device("cuda:0")
     t0 = time.time()
+    if args.eval_only:
+        net = Net(dev)
+        net.set_params(torch.tensor(np.load(args.eval_only), device=dev))
+        report = {"weights": args.eval_only, "eval": evaluate(net, args.eval, dev, W, LD, MIXED, FP64)}
+        report["summary"] = summarize(report["eval"])
+        log("REPORT " + json.dumps(report))
+        return
     samples = []
     pool = None
     if args.workers > 1:
@@ -95,26 +147,8 @@ def main(argv=None):
               "epochs": args.epochs, "lr": args.lr, "lr_final": args.lr_final, "batch": args.batch,
               "smooth": args.smooth, "seed": args.seed, "cycles": args.cycles, "loss": hist,
               "train_seconds": time.time() - t0, "eval": []}
-    for spec in args.eval.split(","):
-        if not spec:
-            continue
-        n, N, cnt = (int(v) for v in spec.split(":"))
-        for k in range(cnt):
-            inst = W.learned_eval(n, N, index=100 + k) if n == 256 else W.training_config(900_000 + k, n, N)
-            f = torch.ones((n, n, n), dtype=torch.float64, device=dev)
-            row = {"n": n, "N": N, "seed": inst.seed}
-            runs = (("plain_fp64", None, FP64, LD.gmres_iterations), ("mixed", None, MIXED, LD.gmres_iterations),
-                    ("learned_mixed", net, MIXED, LD.gmres_iterations),
-                    ("block_mixed", None, MIXED, LD.block_iterations),
-                    ("block_learned_mixed", net, MIXED, LD.block_iterations))
-            for name, netx, prec, fn in runs:
-                st, dt, c, lam = fn(n, inst.q, f, netx, dev, precision=prec)
-                row[name] = {"gmres_iters": st["outer_iters"], "inner_iters": st["inner_iters_total"],
-                             "seconds": dt, "rel_resid": st["rel_resid"], "rc": st["rc"],
-                             "fallback": st["fallback"]}
-                log(f"eval n={n} N={N} {name}: iters={st['outer_iters']} inner={st['inner_iters_total']} "
-                    f"t={dt:.3f}s resid={st['rel_resid']:.2e}")
-            report["eval"].append(row)
+    report["eval"] = evaluate(net, args.eval, dev, W, LD, MIXED, FP64)
+    report["summary"] = summarize(report["eval"])
     log("REPORT " + json.dumps(report))
 
 
