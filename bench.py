@@ -71,16 +71,25 @@ def measured_traffic(n):
     return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
 
 
+STEP_TIMES = {}
+
+
 def timed(fn, steps, warmup):
+    """Total wall time of `steps` calls after `warmup` untimed ones (each call returns once its
+    solve is complete); the per-call times are kept in STEP_TIMES[fn] for the median."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = None
+    per = []
     for _ in range(steps):
+        t1 = time.perf_counter()
         st = fn()
+        per.append(time.perf_counter() - t1)
     torch.cuda.synchronize()
+    STEP_TIMES[fn] = per
     return time.perf_counter() - t0, st
 
 
@@ -221,6 +230,7 @@ def main():
     else:
         dt, st = timed(lambda: S.solve_absorbing(f)[2], args.steps, args.warmup)
     value = args.steps / dt
+    med = float(np.median(next(iter(STEP_TIMES.values())))) if len(STEP_TIMES) == 1 else None
     out = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
@@ -232,6 +242,7 @@ def main():
                    if learned else "Schur GMRES + inner MG-CG + fp32",
                    "source": "f=1" if learned else "f=1+0.5N(0,1)", "seed": inst.seed},
         "solve": summary(st, block=learned),
+        "median_ms_per_step": None if med is None else 1e3 * med,
         "tuning": tuning,
     }
     out["solve"]["alg_GBs"] = st["alg_bytes"] / (dt / args.steps) / 1e9
@@ -312,10 +323,17 @@ def main():
         per_solve = st["outer_iters"] if args.workload != "rsa256_learned" else out.get("plain_fp64", {}).get(
             "gmres_iters", st["outer_iters"])
         n_poisson = per_solve + 2
+        cpu = "unknown CPU"
+        try:
+            with open("/proc/cpuinfo") as fh:
+                cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
         out["cpu_baseline"] = {
             "value": 1.0 / (tp * n_poisson), "unit": "solves/s", "cores": it.num_threads(), "kind": "oracle",
             "sample": f"{k} oracle MG-CG Poisson solves on the same grid (rtol 5e-10, {tp:.2f} s each), scaled by "
-                      f"{n_poisson} Poisson solves per absorbing solve ({per_solve} Schur GMRES products + 2)"}
+                      f"{n_poisson} Poisson solves per absorbing solve ({per_solve} Schur GMRES products + 2); "
+                      f"{it.num_threads()} OpenMP threads of {os.cpu_count()} logical CPUs, {cpu}"}
     if args.copy_probe:
         src = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
