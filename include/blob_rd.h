@@ -62,6 +62,27 @@ extern "C" {
 #define BLOB_RD_SOLVER_BLOCK 1         /* block FGMRES, approximate-Schur preconditioner (m = 5, n = 1) */
 #define BLOB_RD_SOLVER_BLOCK_LEARNED 2 /* the same with the learned inner preconditioning */
 
+/* Domain of a handle (blob_rd_params.boundary).
+ * PERIODIC: the periodic cell of Sec. III (every operation of this header).
+ * DIRICHLET: a box whose faces hold c = boundary_value (the single-blob tests of
+ * Sec. IV.C, eq. c_r_approx). On the cell-centred grid the face value is the
+ * mean of a boundary cell and its ghost, so the 7-point Laplacian takes the
+ * ghost 2 c_b - c. Solves work on u = c - c_b: the operator becomes
+ * alpha I - D L_0 (ghost -u, invertible for every alpha >= 0, no null space),
+ * the reactive right side f - alpha c_b - c_b S kappa and the absorbing
+ * constraint J u = -c_b; c is returned with c_b added back. Every blob must lie
+ * at least 3h inside each face (its kernel support then stays off the boundary
+ * cells and J 1 = 1), else blob_rd_create returns EINVAL. Supported: the
+ * reactive solve and step, the absorbing solve and step with saddle_solver
+ * BLOCK or BLOCK_LEARNED (the learned part is never used in a box: its network
+ * models the periodic cell), blob_rd_solve_absorbing_fgmres and the operator
+ * calls (blob_rd_apply applies the homogeneous operator alpha I - D L_0 [+ S kappa J],
+ * blob_rd_vcycle its V-cycle). EINVAL: absorbing solves with saddle_solver
+ * SCHUR, blob_rd_precond_build, blob_rd_time_kernel, blob_rd_autotune; batched
+ * calls run box handles on their own streams, never in the lock-step launches. */
+#define BLOB_RD_BOUNDARY_PERIODIC 0
+#define BLOB_RD_BOUNDARY_DIRICHLET 1
+
 typedef struct blob_rd* blob_rd_t;
 
 typedef struct {
@@ -82,6 +103,8 @@ typedef struct {
     size_t workspace_bytes;
     void* stream;            /* hipStream_t, NULL = default stream */
     int32_t saddle_solver;   /* BLOB_RD_SOLVER_*: how blob_rd_solve_absorbing solves (default Schur GMRES) */
+    int32_t boundary;        /* BLOB_RD_BOUNDARY_*: periodic cell (default) or a box with fixed faces */
+    double boundary_value;   /* c on the faces of a Dirichlet box (c_inf); ignored when periodic */
 } blob_rd_params;
 
 typedef struct {

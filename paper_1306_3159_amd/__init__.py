@@ -8,8 +8,8 @@ import of :mod:`paper_1306_3159_amd.native` fails loudly.
 """
 from .native import (BlobRD, Net, NET_PARAMS, solve_batch, solve_batched, BlobRDError, NotConverged, Stats,
                      load_library, FP64, MIXED, PRECOND_NONE, PRECOND_DIAGONAL, PRECOND_LEARNED, SOLVER_SCHUR,
-                     SOLVER_BLOCK, SOLVER_BLOCK_LEARNED)
+                     SOLVER_BLOCK, SOLVER_BLOCK_LEARNED, BOUNDARY_PERIODIC, BOUNDARY_DIRICHLET)
 
 __all__ = ["BlobRD", "Net", "NET_PARAMS", "solve_batch", "solve_batched", "BlobRDError", "NotConverged", "Stats",
            "load_library", "FP64", "MIXED", "PRECOND_NONE", "PRECOND_DIAGONAL", "PRECOND_LEARNED", "SOLVER_SCHUR",
-           "SOLVER_BLOCK", "SOLVER_BLOCK_LEARNED"]
+           "SOLVER_BLOCK", "SOLVER_BLOCK_LEARNED", "BOUNDARY_PERIODIC", "BOUNDARY_DIRICHLET"]

@@ -12,7 +12,8 @@ ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libblob_rd.so")
 
-SOURCES = ["kernels_grid.hip", "kernels_mg.hip", "kernels_blob.hip", "kernels_learned.hip", "engine.hip"]
+SOURCES = ["kernels_grid.hip", "kernels_mg.hip", "kernels_box.hip", "kernels_blob.hip", "kernels_learned.hip",
+           "engine.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -121,6 +121,14 @@ struct SpreadMult {
     double shift;
 };
 
+// A box held at a fixed face value (Dirichlet): the homogeneous operator takes the
+// ghost beyond a face as minus the boundary cell, so a cell touching f faces has
+// the diagonal alpha + s (6 + f) and no neighbour term across them. v[f] holds
+// the per-cell coefficient (diagonal or its inverse) for f = 0..3.
+struct BoxCoef {
+    double v[4];
+};
+
 // Logical block of a launch: partial-sum slot b of nb. Solo kernels pass
 // (blockIdx.x, gridDim.x); batched kernels pass an instance's local slot, so
 // every instance's partition of work and of partial sums is the solo one.
@@ -174,6 +182,11 @@ struct LevelDims {
 
 // ---- helpers -------------------------------------------------------------
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// number of box faces cell (x, y, z) touches (at most one per axis for edges >= 2)
+__device__ __forceinline__ int box_faces(int x, int y, int z, int nx, int ny, int nz) {
+    return (x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1) + (z == 0) + (z == nz - 1);
+}
 
 // Value of cell (X, Y, Z) of a red/black split level (colour (X + Y + Z) mod 2,
 // index X/2 of row (Y, Z) of its colour array, hx = nx/2) as a double.

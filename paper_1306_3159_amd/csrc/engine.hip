@@ -143,6 +143,14 @@ int make_plan(const blob_rd_params* p, Plan* P, std::string* why) {
         *why = "precision must be FP64 (0) or MIXED (1)";
         return BLOB_RD_EINVAL;
     }
+    if (p->boundary != BLOB_RD_BOUNDARY_PERIODIC && p->boundary != BLOB_RD_BOUNDARY_DIRICHLET) {
+        *why = "boundary must be PERIODIC (0) or DIRICHLET (1)";
+        return BLOB_RD_EINVAL;
+    }
+    if (!std::isfinite(p->boundary_value)) {
+        *why = "boundary_value must be finite";
+        return BLOB_RD_EINVAL;
+    }
     const size_t ncell = (size_t)p->nx * p->ny * p->nz;
     if (ncell > (size_t)1 << 30) {
         *why = "grid too large";
@@ -232,13 +240,16 @@ int make_plan(const blob_rd_params* p, Plan* P, std::string* why) {
 }
 
 // Dense (pseudo-)inverse of the coarsest operator alpha I - D L_H (row-major m x m).
-// For alpha = 0 it returns (A + e e^T/m)^{-1} - e e^T/m, the pseudo-inverse on
-// mean-zero vectors. LU with partial pivoting, then column-wise solves.
-std::vector<double> coarse_inverse(const LevelDims& C, double D, double alpha) {
+// Periodic with alpha = 0 it returns (A + e e^T/m)^{-1} - e e^T/m, the pseudo-inverse
+// on mean-zero vectors. In a box with fixed faces (box) a neighbour beyond a face is
+// the ghost -u, which adds s to the diagonal; the operator is then invertible for
+// every alpha >= 0. LU with partial pivoting, then column-wise solves.
+std::vector<double> coarse_inverse(const LevelDims& C, double D, double alpha, bool box) {
     const int nx = C.nx, ny = C.ny, nz = C.nz, m = nx * ny * nz;
     const double s = D / (C.h * C.h);
     std::vector<double> A((size_t)m * m, 0.0);
     auto id = [&](int x, int y, int z) {
+        if (box && (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz)) return -1;
         x = (x + nx) % nx;
         y = (y + ny) % ny;
         z = (z + nz) % nz;
@@ -251,10 +262,14 @@ std::vector<double> coarse_inverse(const LevelDims& C, double D, double alpha) {
                 A[(size_t)r * m + r] += alpha + 6.0 * s;
                 const int nb[6] = {id(x - 1, y, z), id(x + 1, y, z), id(x, y - 1, z),
                                    id(x, y + 1, z), id(x, y, z - 1), id(x, y, z + 1)};
-                for (int k = 0; k < 6; ++k) A[(size_t)r * m + nb[k]] -= s;
+                for (int k = 0; k < 6; ++k) {
+                    if (nb[k] < 0) A[(size_t)r * m + r] += s;  // ghost -u beyond a face
+                    else A[(size_t)r * m + nb[k]] -= s;
+                }
             }
+    const bool sing = alpha == 0.0 && !box;
     const double e = 1.0 / m;
-    if (alpha == 0.0)
+    if (sing)
         for (auto& v : A) v += e;
     std::vector<int> piv(m);
     for (int k = 0; k < m; ++k) {
@@ -285,7 +300,7 @@ std::vector<double> coarse_inverse(const LevelDims& C, double D, double alpha) {
             for (int j = i + 1; j < m; ++j) col[i] -= A[(size_t)i * m + j] * col[j];
             col[i] /= A[(size_t)i * m + i];
         }
-        for (int r = 0; r < m; ++r) inv[(size_t)r * m + c] = col[r] - (alpha == 0.0 ? e : 0.0);
+        for (int r = 0; r < m; ++r) inv[(size_t)r * m + c] = col[r] - (sing ? e : 0.0);
     }
     return inv;
 }
@@ -346,6 +361,9 @@ struct blob_rd {
     } lrn;
     int fallback = 0;
     int ntouched = 0;  // cells with a nonzero spread weight (length of the contribution lists)
+    // box with the concentration held at cb on its faces (solves work on u = c - cb)
+    bool box = false;
+    double cb = 0.0;
     // lock-step batch executor this handle currently belongs to (null: solo)
     BatchServer* batch = nullptr;
     int batch_slot = -1;
@@ -418,7 +436,7 @@ const double* select_cinv(blob_rd* H, double alpha) {
         }
     }
     H->cinv_alpha[slot] = alpha;
-    std::vector<double> inv = coarse_inverse(H->P.lev[H->P.nlev - 1], H->prm.D, alpha);
+    std::vector<double> inv = coarse_inverse(H->P.lev[H->P.nlev - 1], H->prm.D, alpha, H->box);
     double* dst = H->at<double>(H->P.off_cinv[slot]);
     HIPCHK(hipMemcpyAsync(dst, inv.data(), inv.size() * 8, hipMemcpyHostToDevice, H->st));
     HIPCHK(hipStreamSynchronize(H->st));
@@ -487,6 +505,67 @@ constexpr double kProlongPostBytes = 1.125 + 4 * 1.5;
 constexpr double kBlockedDownBytes = 0.5 + 1.0 + 0.5 + 0.1875;
 constexpr double kBlockedUpBytes = 0.125 + 0.5 + 1.0 + 1.0;
 
+// alpha I - D L has a null space (the constant) only on the periodic grid with alpha = 0
+bool singular(const blob_rd* H, double alpha) { return alpha == 0.0 && !H->box; }
+
+// Diagonal and inverse diagonal of level l of a box with fixed faces, per number of
+// faces a cell touches.
+void box_coefs(const blob_rd* H, int l, double alpha, BoxCoef* diag, BoxCoef* inv) {
+    const LevelDims& d = H->P.lev[l];
+    const double s = H->prm.D / (d.h * d.h);
+    for (int f = 0; f < 4; ++f) {
+        const double v = alpha + s * (6.0 + f);
+        if (diag) diag->v[f] = v;
+        if (inv) inv->v[f] = 1.0 / v;
+    }
+}
+
+// The V-cycle of vcycle() below for the box operator alpha I - D L_0: the same
+// steps and order with the box kernels on every level, no temporally blocked
+// levels and no LDS tail, the coarsest level by the dense box inverse.
+template <typename T>
+void vcycle_box(blob_rd* H, double alpha, const double* r, const Scalars* sc, const double* cinv, bool entered) {
+    const Plan& P = H->P;
+    const int L = P.nlev - 1;
+    hipStream_t st = H->st;
+    auto lv = [&](int l, int k) { return H->at<T>(P.off_lvl[l][k]); };  // 0 u0, 1 u1, 2 f0, 3 f1, 4 r0 (red)
+    BoxCoef dg[kMaxLevels], inv[kMaxLevels];
+    for (int l = 0; l <= L; ++l) box_coefs(H, l, alpha, &dg[l], &inv[l]);
+    if (!entered) {
+        const LevelDims& d = P.lev[0];
+        launch_enter_box<T>(st, r, lv(0, 2), lv(0, 3), lv(0, 0), d.nx, d.ny, d.nz, inv[0], sc);
+        H->alg_bytes += (double)P.ncell * (8 + P.esz * 1.5);
+    }
+    for (int l = 0; l < L; ++l) {
+        const LevelDims& d = P.lev[l];
+        const double s = H->prm.D / (d.h * d.h);
+        launch_gs_box<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.nx, d.ny, d.nz, 1, s, inv[l], sc);
+        launch_gs_box<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.nx, d.ny, d.nz, 0, s, inv[l], sc);
+        launch_gs_box<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.nx, d.ny, d.nz, 1, s, inv[l], sc);
+        launch_resid_red_box<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), lv(l, 4), d.nx, d.ny, d.nz, s, dg[l], sc);
+        if (l + 1 == L)
+            launch_restrict_box<T>(st, lv(l, 4), d.nx, d.ny, d.nz, lv(L, 2), nullptr, nullptr, 1, inv[L], sc);
+        else
+            launch_restrict_box<T>(st, lv(l, 4), d.nx, d.ny, d.nz, lv(l + 1, 2), lv(l + 1, 3), lv(l + 1, 0), 0,
+                                   inv[l + 1], sc);
+        H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * kPreRestrictBytes;
+    }
+    launch_coarse<T>(st, lv(L, 2), lv(L, 0), cinv, P.m, sc);
+    for (int l = L - 1; l >= 0; --l) {
+        const LevelDims& d = P.lev[l];
+        const double s = H->prm.D / (d.h * d.h);
+        const int cnat = (l + 1 == L);
+        launch_prolong_red_box<T>(st, lv(l + 1, 0), cnat ? nullptr : lv(l + 1, 1), cnat, lv(l, 0), d.nx, d.ny, d.nz,
+                                  sc);
+        launch_gs_box<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.nx, d.ny, d.nz, 1, s, inv[l], sc);
+        launch_gs_box<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.nx, d.ny, d.nz, 0, s, inv[l], sc);
+        launch_gs_box<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.nx, d.ny, d.nz, 1, s, inv[l], sc);
+        launch_gs_box<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.nx, d.ny, d.nz, 0, s, inv[l], sc);
+        H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * kProlongPostBytes;
+    }
+    H->vcycles += 1;
+}
+
 // entered: level 0's f and first red sweep were already written (fused CG
 // update). dot_q (with a non-null sc): fuse the CG dots (sum z, z.r, z.q) into
 // the closing red half-sweep of level 0 when that level has its own launches;
@@ -494,6 +573,10 @@ constexpr double kBlockedUpBytes = 0.125 + 0.5 + 1.0 + 1.0;
 template <typename T>
 unsigned vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const double* cinv,
                 bool entered = false, const double* dot_q = nullptr) {
+    if (H->box) {
+        vcycle_box<T>(H, alpha, r, sc, cinv, entered);
+        return 0;
+    }
     const Plan& P = H->P;
     const int L = P.nlev - 1;
     hipStream_t st = H->st;
@@ -679,8 +762,10 @@ PcgResult pcg(blob_rd* H, bool with_blobs, double alpha, const double* g, double
     double* q = H->grid(G_Q);
     const LevelDims& d = P.lev[0];
     const double s = H->prm.D / (d.h * d.h);
-    const int project = alpha == 0.0 ? 1 : 0;
+    const int project = singular(H, alpha) ? 1 : 0;
     const bool blobs = with_blobs && P.N > 0 && H->has_kappa;
+    BoxCoef binv;
+    box_coefs(H, 0, alpha, nullptr, &binv);
     const double eBe = alpha * (double)P.ncell + H->sum_kappa * H->inv_h3();
     const double eBe_inv = (with_blobs && project && eBe > 0.0) ? 1.0 / eBe : 0.0;
     const double* cinv = select_cinv(H, alpha);
@@ -697,7 +782,7 @@ PcgResult pcg(blob_rd* H, bool with_blobs, double alpha, const double* g, double
             H->alg_bytes += (double)P.ncell * 16;
         }
     } else {
-        launch_applyA_plain(st, x, q, alpha, s, d.nx, d.ny, d.nz);
+        launch_applyA_plain(st, x, q, alpha, s, d.nx, d.ny, d.nz, H->box);
         if (blobs) blob_term(H, x, q, nullptr);
         launch_residual_from_q(st, g, q, r, P.ncell, H->part(), &np);
         H->alg_bytes += (double)P.ncell * 40;
@@ -716,7 +801,7 @@ PcgResult pcg(blob_rd* H, bool with_blobs, double alpha, const double* g, double
         double* p = pbuf[0];
         (void)parity;
         launch_dir2<T>(s_, H->at<T>(P.off_lvl[0][0]), H->at<T>(P.off_lvl[0][1]), p, d.nx, d.ny, d.nz, H->sc());
-        launch_applyA2(s_, p, q, alpha, s, d.nx, d.ny, d.nz, H->part(), H->sc(), &np);
+        launch_applyA2(s_, p, q, alpha, s, d.nx, d.ny, d.nz, H->part(), H->sc(), &np, H->box);
         if (blobs) {
             blob_term(H, p, q, H->sc());
             launch_fin(s_, FIN_ALPHA, H->part(), np, H->sc(), H->nv(0), H->nv(1), P.N, H->inv_h3());
@@ -725,7 +810,7 @@ PcgResult pcg(blob_rd* H, bool with_blobs, double alpha, const double* g, double
         }
         launch_update2_enter<T>(s_, x, r, p, q, H->at<T>(P.off_lvl[0][2]), H->at<T>(P.off_lvl[0][3]),
                                 H->at<T>(P.off_lvl[0][0]), d.nx, d.ny, d.nz, 1.0 / (alpha + 6.0 * s), H->part(),
-                                H->sc(), &np);
+                                H->sc(), &np, H->box ? &binv : nullptr);
         launch_fin(s_, FIN_UPDATE, H->part(), np, H->sc(), nullptr, nullptr, 0, 0.0);
         precond_zdots<T>(H, alpha, r, q, cinv, true);
         // direction (z, p r/w), stencil (p, q), update (x, r r/w, p, q) with the V-cycle entry (f, red u)
@@ -814,7 +899,7 @@ void true_residual(blob_rd* H, bool with_blobs, double alpha, const double* g, c
     const LevelDims& d = P.lev[0];
     const double s = H->prm.D / (d.h * d.h);
     double* q = H->grid(G_Q);
-    launch_applyA_plain(H->st, x, q, alpha, s, d.nx, d.ny, d.nz);
+    launch_applyA_plain(H->st, x, q, alpha, s, d.nx, d.ny, d.nz, H->box);
     if (with_blobs && P.N > 0 && H->has_kappa) blob_term(H, x, q, nullptr);
     unsigned np = 0;
     launch_residual_from_q(H->st, g, q, t, P.ncell, H->part(), &np);
@@ -874,7 +959,7 @@ void schur_apply(blob_rd* H, double alpha, const double* x, double* y, double in
     hipStream_t st = H->st;
     double* xt = H->nv(2);
     launch_nvec_copy_scale(st, x, xt, P.N, 1.0, 0.0);
-    if (alpha == 0.0) launch_nvec_project(st, xt, P.N);
+    if (singular(H, alpha)) launch_nvec_project(st, xt, P.N);
     // S x straight into the CG residual (zero start: r = g)
     spread_to(H, xt, 0.0, nullptr, H->grid(G_R), H->inv_h3(), nullptr);
     H->alg_bytes += (double)P.ncell * 8;
@@ -883,7 +968,7 @@ void schur_apply(blob_rd* H, double alpha, const double* x, double* y, double in
     H->inner_iters += pr.iters;
     launch_interp(st, H->grid(G_U), P.N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
                   H->at<int>(P.off_perm), nullptr, nullptr, y, nullptr);
-    if (alpha == 0.0) launch_nvec_project(st, y, P.N);
+    if (singular(H, alpha)) launch_nvec_project(st, y, P.N);
 }
 
 struct SaddleInfo {
@@ -1038,7 +1123,7 @@ void saddle_residual(blob_rd* H, double alpha, const double* g, const double* ph
     const LevelDims& d = P.lev[0];
     const double s = H->prm.D / (d.h * d.h);
     double* q = H->grid(G_Q);
-    launch_applyA_plain(H->st, c, q, alpha, s, d.nx, d.ny, d.nz);
+    launch_applyA_plain(H->st, c, q, alpha, s, d.nx, d.ny, d.nz, H->box);
     spread_to(H, lam, 0.0, q, q, H->inv_h3(), nullptr);
     unsigned np = 0;
     launch_residual_from_q(H->st, g, q, t, P.ncell, H->part(), &np);
@@ -1194,7 +1279,7 @@ void fg_resid(blob_rd* H, double alpha, const double* base, const SpreadMult* M,
               double* q) {
     const Plan& P = H->P;
     const LevelDims& d = P.lev[0];
-    launch_applyA_plain(H->st, x, q, alpha, H->prm.D / (d.h * d.h), d.nx, d.ny, d.nz);
+    launch_applyA_plain(H->st, x, q, alpha, H->prm.D / (d.h * d.h), d.nx, d.ny, d.nz, H->box);
     launch_axpby(H->st, q, base, P.ncell, -1.0, 1.0);
     if (M) launch_spread_sparse(H->st, spread_lists(H), *M, q, q, scale, nullptr);
     H->alg_bytes += (double)P.ncell * (16 + 24);
@@ -1218,7 +1303,13 @@ void fg_cycles(blob_rd* H, double alpha, const double* base, const SpreadMult* M
     double* q = H->grid(G_Q);
     for (int k = 0; k < n; ++k) {
         if (k == 0 && from_zero) {
-            launch_enter<T>(H->st, base, f0, f1, z0, d.nx, d.ny, d.nz, inv_diag, nullptr);
+            if (H->box) {
+                BoxCoef binv;
+                box_coefs(H, 0, alpha, nullptr, &binv);
+                launch_enter_box<T>(H->st, base, f0, f1, z0, d.nx, d.ny, d.nz, binv, nullptr);
+            } else {
+                launch_enter<T>(H->st, base, f0, f1, z0, d.nx, d.ny, d.nz, inv_diag, nullptr);
+            }
             if (M) launch_spread_enter<T>(H->st, spread_lists(H), *M, base, scale, f0, f1, z0, d.nx, d.ny, inv_diag);
             H->alg_bytes += (double)P.ncell * (8 + 1.5 * P.esz);
             vcycle<T>(H, alpha, nullptr, nullptr, cinv, true);
@@ -1249,7 +1340,7 @@ void fg_interp(blob_rd* H, const double* c, double* out) {
 void fg_apply_K(blob_rd* H, double alpha, const double* xg, const double* xl, double* yg, double* yl) {
     const Plan& P = H->P;
     const LevelDims& d = P.lev[0];
-    launch_applyA_plain(H->st, xg, yg, alpha, H->prm.D / (d.h * d.h), d.nx, d.ny, d.nz);
+    launch_applyA_plain(H->st, xg, yg, alpha, H->prm.D / (d.h * d.h), d.nx, d.ny, d.nz, H->box);
     H->alg_bytes += (double)P.ncell * 16;
     fg_spread(H, xl, yg, yg, H->inv_h3(), 1);
     fg_interp(H, xg, yl);
@@ -1271,7 +1362,7 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
     const int N = P.N;
     const double h3 = H->prm.h * H->prm.h * H->prm.h;
     const double* cinv = select_cinv(H, alpha);
-    const bool sing = alpha == 0.0;
+    const bool sing = singular(H, alpha);
     const LevelDims& d = P.lev[0];
     const SpreadLists L = spread_lists(H);
     T* z0 = H->at<T>(P.off_lvl[0][0]);
@@ -1376,8 +1467,10 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
 }
 
 // Flexible GMRES (right preconditioned, restarted, modified Gram-Schmidt) on
-// [A, S; J, 0][c; lam] = [f; 0] from a zero guess. Every cycle starts from the
-// true FP64 residual b - K x, which also decides convergence at the end.
+// [A, S; J, 0][c; lam] = [f; phi] from a zero guess (warm: from (c, lam)), with
+// phi = -cb on every blob in a box held at cb (the lifted system) and 0 otherwise.
+// Every cycle starts from the true FP64 residual b - K x, which also decides
+// convergence at the end.
 template <typename T>
 int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double* c, double* lam, char* ws,
              blob_rd_stats* stt, bool warm = false) {
@@ -1394,13 +1487,15 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
     double* yv = gv + ld;
     double* sd = yv + ld;  // [0] beta, [2..3] Givens outputs
     double bnorm = -1.0, rel = 0.0, prev_rel = 0.0;
+    const double phi = H->box ? -H->cb : 0.0;
     if (warm) {
-        // (c, lam) hold the initial guess; the scale of the residual is |b| = |f|
+        // (c, lam) hold the initial guess; the scale of the residual is |b| = |[f; phi]|
         unsigned np = 0;
         launch_norm_partials(st, f, ncell, H->part(), &np);
         launch_reduce_parts(st, H->part(), np, 2, sd + 4);
         sync_read(H, H->hbuf, sd + 4, 16);
-        bnorm = H->hbuf[1] > 0.0 ? std::sqrt(H->hbuf[1]) : 1.0;
+        const double bb = H->hbuf[1] + (double)P.N * phi * phi;
+        bnorm = bb > 0.0 ? std::sqrt(bb) : 1.0;
         H->alg_bytes += (double)ncell * 8;
     } else {
         launch_fill(st, c, ncell, 0.0);
@@ -1411,7 +1506,7 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
     for (;;) {
         if (sub) fg_apply_K(H, alpha, c, lam, V, V + ncell);
         unsigned np = 0;
-        launch_fg_resid(st, V, f, ncell, n, sub ? 1 : 0, H->part(), &np);
+        launch_fg_resid(st, V, f, ncell, n, sub ? 1 : 0, H->part(), &np, phi);
         launch_fg_fin(st, H->part(), np, sd, 1);
         H->alg_bytes += (double)n * (sub ? 24 : 16);
         sync_read(H, H->hbuf, sd, 8);
@@ -1473,11 +1568,59 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
 // (the learned inner preconditioning only where W applies, alpha = 0).
 FgOpts handle_fg_opts(const blob_rd* H, double alpha) {
     blob_rd_saddle_opts o{};
-    o.precond = (H->prm.saddle_solver == BLOB_RD_SOLVER_BLOCK_LEARNED && alpha == 0.0) ? BLOB_RD_SADDLE_LEARNED
-                                                                                        : BLOB_RD_SADDLE_APPROX_SCHUR;
+    o.precond = (H->prm.saddle_solver == BLOB_RD_SOLVER_BLOCK_LEARNED && singular(H, alpha))
+                    ? BLOB_RD_SADDLE_LEARNED
+                    : BLOB_RD_SADDLE_APPROX_SCHUR;
     o.restart = H->P.restart;
     o.maxit = H->prm.max_iter;
     return fg_opts(H, &o);
+}
+
+// A box held at cb on its faces: the solves work on u = c - cb (the ghost 2 cb - c
+// becomes -u), and a blob whose kernel support lies inside the box has J 1 = 1, so
+// (alpha I - D L_cb + S kappa J) c = f becomes (alpha I - D L_0 + S kappa J) u =
+// f - alpha cb - cb S kappa, and the saddle point's constraint J c = 0 becomes J u = -cb.
+// box_lift writes out = f - alpha cb [- cb S kappa] (out may alias f).
+void box_lift(blob_rd* H, double alpha, const double* f, double* out, bool kappa_term) {
+    const Plan& P = H->P;
+    launch_nvec_copy_scale(H->st, f, out, (int)P.ncell, 1.0, -alpha * H->cb);
+    if (kappa_term && P.N > 0 && H->has_kappa)
+        spread_to(H, H->at<double>(P.off_kappa), 0.0, out, out, -H->cb * H->inv_h3(), nullptr);
+    H->alg_bytes += (double)P.ncell * 16;
+}
+
+// v += a on a grid vector
+void grid_shift(blob_rd* H, double* v, double a) {
+    launch_nvec_copy_scale(H->st, v, v, (int)H->P.ncell, 1.0, a);
+    H->alg_bytes += (double)H->P.ncell * 16;
+}
+
+// block FGMRES of the handle's options on the saddle point with right side f
+// (lifted in a box); c and lam hold the guess when warm.
+template <typename T>
+int fg_entry(blob_rd* H, double alpha, const FgOpts& o, const double* f, double* c, double* lam, char* ws,
+             blob_rd_stats* stt, bool warm) {
+    if (!H->box) return fg_solve<T>(H, alpha, o, f, c, lam, ws, stt, warm);
+    double* g = H->grid(G_G);
+    box_lift(H, alpha, f, g, false);
+    if (warm) grid_shift(H, c, -H->cb);
+    const int rc = fg_solve<T>(H, alpha, o, g, c, lam, ws, stt, warm);
+    grid_shift(H, c, H->cb);
+    HIPCHK(hipStreamSynchronize(H->st));
+    return rc;
+}
+
+// multigrid CG on the reactive system with right side f (lifted in a box); c holds the guess
+template <typename T>
+int reactive_entry(blob_rd* H, double alpha, const double* f, double* c, blob_rd_stats* stt) {
+    if (!H->box) return reactive_solve<T>(H, alpha, f, c, stt);
+    double* g = H->grid(G_G);
+    box_lift(H, alpha, f, g, true);
+    grid_shift(H, c, -H->cb);
+    const int rc = reactive_solve<T>(H, alpha, g, c, stt);
+    grid_shift(H, c, H->cb);
+    HIPCHK(hipStreamSynchronize(H->st));
+    return rc;
 }
 
 }  // namespace
@@ -1518,6 +1661,8 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
     }
     H->prm = *p;
     H->st = (hipStream_t)p->stream;
+    H->box = p->boundary == BLOB_RD_BOUNDARY_DIRICHLET;
+    H->cb = H->box ? p->boundary_value : 0.0;
     if (const char* g = std::getenv("BLOB_RD_GRAPHS")) H->use_graphs = std::atoi(g) != 0;
     for (auto& row : H->bs)
         for (int& v : row) v = kBlock;
@@ -1549,6 +1694,16 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
             HIPCHK(hipStreamSynchronize(st));
             for (double v : hq)
                 if (!std::isfinite(v) || std::fabs(v) > 1e12) throw Err(BLOB_RD_EINVAL, "q contains non-finite or huge values");
+            if (H->box) {
+                // the kernel support of every blob stays off the boundary cells
+                const double edge[3] = {p->nx * p->h, p->ny * p->h, p->nz * p->h};
+                for (int i = 0; i < N; ++i)
+                    for (int a = 0; a < 3; ++a) {
+                        const double v = hq[(size_t)i * 3 + a];
+                        if (v < 3.0 * p->h || v > edge[a] - 3.0 * p->h)
+                            throw Err(BLOB_RD_EINVAL, "in a Dirichlet box every blob must lie at least 3h inside each face");
+                    }
+            }
             for (double v : hk)
                 if (!std::isfinite(v) || v < 0.0) throw Err(BLOB_RD_EINVAL, "kappa must be finite and >= 0");
             HIPCHK(hipMemcpyAsync(H->at<double>(P.off_q), p->q, (size_t)N * 24, hipMemcpyDeviceToDevice, st));
@@ -1643,10 +1798,10 @@ const char* blob_rd_last_error(blob_rd_t H) {
 int blob_rd_solve_reactive(blob_rd_t H, double alpha, const double* f, double* c, blob_rd_stats* stt) {
     if (!H || !f || !c) return g_last_error = "null argument", BLOB_RD_EINVAL;
     if (!(alpha >= 0.0) || !std::isfinite(alpha)) return g_last_error = "alpha must be >= 0", BLOB_RD_EINVAL;
-    if (alpha == 0.0 && !(H->sum_kappa > 0.0))
+    if (alpha == 0.0 && !(H->sum_kappa > 0.0) && !H->box)
         return g_last_error = "steady reactive system with zero total rate is singular", BLOB_RD_ESINGULAR;
     return guarded(H, stt, [&]() {
-        int rc = H->P.esz == 4 ? reactive_solve<float>(H, alpha, f, c, stt) : reactive_solve<double>(H, alpha, f, c, stt);
+        int rc = H->P.esz == 4 ? reactive_entry<float>(H, alpha, f, c, stt) : reactive_entry<double>(H, alpha, f, c, stt);
         HIPCHK(hipGetLastError());
         return rc;
     });
@@ -1660,8 +1815,8 @@ int blob_rd_step(blob_rd_t H, double dt, const double* f, double* c, blob_rd_sta
         hipLaunchKernelGGL(k_step_rhs, dim3(nblocks(H->P.ncell)), dim3(kBlock), 0, H->st, f, c, g,
                            (unsigned)H->P.ncell, 1.0 / dt);
         H->alg_bytes += (double)H->P.ncell * 24;
-        int rc = H->P.esz == 4 ? reactive_solve<float>(H, 1.0 / dt, g, c, stt)
-                               : reactive_solve<double>(H, 1.0 / dt, g, c, stt);
+        int rc = H->P.esz == 4 ? reactive_entry<float>(H, 1.0 / dt, g, c, stt)
+                               : reactive_entry<double>(H, 1.0 / dt, g, c, stt);
         HIPCHK(hipGetLastError());
         return rc;
     });
@@ -1672,6 +1827,8 @@ int blob_rd_step_absorbing(blob_rd_t H, double dt, const double* f, double* c, d
     if (!H || !f || !c || !lambda) return g_last_error = "null argument", BLOB_RD_EINVAL;
     if (H->P.N <= 0) return g_last_error = "absorbing step needs at least one blob", BLOB_RD_EINVAL;
     if (!(dt > 0.0) || !std::isfinite(dt)) return g_last_error = "dt must be positive", BLOB_RD_EINVAL;
+    if (H->box && H->prm.saddle_solver == BLOB_RD_SOLVER_SCHUR)
+        return g_last_error = "absorbing solves in a Dirichlet box need saddle_solver BLOCK", BLOB_RD_EINVAL;
     return guarded(H, stt, [&]() {
         // g = c^n/dt + f in its own buffer: c is overwritten by c^{n+1}, and the
         // saddle residual and refinement read g after that
@@ -1685,8 +1842,8 @@ int blob_rd_step_absorbing(blob_rd_t H, double dt, const double* f, double* c, d
             if (!warm) launch_fill(H->st, lambda, H->P.N, 0.0);
             const FgOpts o = handle_fg_opts(H, 1.0 / dt);
             char* ws = H->ws + H->P.off_fg;
-            rc = H->P.esz == 4 ? fg_solve<float>(H, 1.0 / dt, o, g, c, lambda, ws, stt, true)
-                               : fg_solve<double>(H, 1.0 / dt, o, g, c, lambda, ws, stt, true);
+            rc = H->P.esz == 4 ? fg_entry<float>(H, 1.0 / dt, o, g, c, lambda, ws, stt, true)
+                               : fg_entry<double>(H, 1.0 / dt, o, g, c, lambda, ws, stt, true);
         } else {
             const double* lam0 = warm ? lambda : nullptr;
             rc = H->P.esz == 4 ? absorbing_solve<float>(H, 1.0 / dt, g, c, lambda, stt, lam0)
@@ -1702,9 +1859,11 @@ int blob_rd_solve_absorbing(blob_rd_t H, double alpha, const double* f, double* 
     if (!H || !f || !c || !lambda) return g_last_error = "null argument", BLOB_RD_EINVAL;
     if (H->P.N <= 0) return g_last_error = "absorbing solve needs at least one blob", BLOB_RD_EINVAL;
     if (!(alpha >= 0.0) || !std::isfinite(alpha)) return g_last_error = "alpha must be >= 0", BLOB_RD_EINVAL;
+    if (H->box && H->prm.saddle_solver == BLOB_RD_SOLVER_SCHUR)
+        return g_last_error = "absorbing solves in a Dirichlet box need saddle_solver BLOCK", BLOB_RD_EINVAL;
     if (H->prm.saddle_solver != BLOB_RD_SOLVER_SCHUR) {
         blob_rd_saddle_opts o{};
-        o.precond = (H->prm.saddle_solver == BLOB_RD_SOLVER_BLOCK_LEARNED && alpha == 0.0)
+        o.precond = (H->prm.saddle_solver == BLOB_RD_SOLVER_BLOCK_LEARNED && singular(H, alpha))
                         ? BLOB_RD_SADDLE_LEARNED
                         : BLOB_RD_SADDLE_APPROX_SCHUR;
         o.restart = H->P.restart;
@@ -1748,7 +1907,7 @@ int blob_rd_apply(blob_rd_t H, double alpha, int with_blobs, const double* x, do
     return guarded(H, nullptr, [&]() {
         const Plan& P = H->P;
         const LevelDims& d = P.lev[0];
-        launch_applyA_plain(H->st, x, y, alpha, H->prm.D / (d.h * d.h), d.nx, d.ny, d.nz);
+        launch_applyA_plain(H->st, x, y, alpha, H->prm.D / (d.h * d.h), d.nx, d.ny, d.nz, H->box);
         if (with_blobs && P.N > 0 && H->has_kappa) blob_term(H, x, y, nullptr);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(H->st));
@@ -2453,6 +2612,7 @@ int blob_rd_net_adam_step(blob_rd_net_t N, float lr) {
 int blob_rd_precond_build(blob_rd_t H, blob_rd_net_t Nt, void* buf, size_t bytes, size_t* needed) {
     if (!H || !Nt) return g_last_error = "null argument", BLOB_RD_EINVAL;
     if (H->P.N <= 0) return g_last_error = "no blobs", BLOB_RD_EINVAL;
+    if (H->box) return g_last_error = "the learned preconditioner is for the periodic cell", BLOB_RD_EINVAL;
     return guarded(H, nullptr, [&]() {
         const int N = H->P.N;
         const PairGeom pg = pair_geom(H);
@@ -2628,6 +2788,7 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
     const bool cold = (kernel & BLOB_RD_KERNEL_COLD) != 0;
     kernel &= ~BLOB_RD_KERNEL_COLD;
     if (kernel < 0 || kernel > 4) return g_last_error = "unknown kernel id", BLOB_RD_EINVAL;
+    if (H->box) return g_last_error = "kernel timing covers the periodic multigrid kernels", BLOB_RD_EINVAL;
     return guarded(H, nullptr, [&]() {
         const Plan& P = H->P;
         const LevelDims& d = P.lev[0];
@@ -2803,6 +2964,7 @@ int blob_rd_set_tuning(blob_rd_t H, const int32_t* table, int32_t n_entries) {
 
 int blob_rd_autotune(blob_rd_t H, int32_t reps, const char* cache_path, int32_t* timed) {
     if (!H || reps <= 0) return g_last_error = "bad argument", BLOB_RD_EINVAL;
+    if (H->box) return g_last_error = "launch tuning covers the periodic multigrid kernels", BLOB_RD_EINVAL;
     if (!cache_path) cache_path = std::getenv("BLOB_RD_TUNE_CACHE");
     return guarded(H, nullptr, [&]() {
         const Plan& P = H->P;
@@ -2896,6 +3058,7 @@ int blob_rd_solve_batched(blob_rd_t* hs, int32_t n, const int32_t* kind, double 
         const blob_rd* H = hs[i];
         if (lockstep_max_cells > 0 && (int64_t)H->P.ncell > lockstep_max_cells) continue;
         if (kind[i] == 1 && H->prm.saddle_solver != BLOB_RD_SOLVER_SCHUR) continue;  // block FGMRES: own stream
+        if (H->box) continue;  // the batched kernels are the periodic ones
         if (!batch_unfit(H, esz ? esz : (int)H->P.esz).empty()) continue;
         esz = (int)H->P.esz;
         member.push_back(i);
@@ -3006,8 +3169,8 @@ int blob_rd_solve_absorbing_fgmres(blob_rd_t H, double alpha, const blob_rd_sadd
         const FgOpts o = fg_opts(H, opts);
         if (workspace_bytes < fg_bytes(H->P, o.restart)) throw Err(BLOB_RD_ENOMEM, "FGMRES workspace too small");
         char* ws = static_cast<char*>(workspace);
-        int rc = H->P.esz == 4 ? fg_solve<float>(H, alpha, o, f, c, lambda, ws, stt)
-                               : fg_solve<double>(H, alpha, o, f, c, lambda, ws, stt);
+        int rc = H->P.esz == 4 ? fg_entry<float>(H, alpha, o, f, c, lambda, ws, stt, false)
+                               : fg_entry<double>(H, alpha, o, f, c, lambda, ws, stt, false);
         HIPCHK(hipGetLastError());
         return rc;
     });
@@ -3021,13 +3184,13 @@ int blob_rd_schur_apply_cycles(blob_rd_t H, double alpha, const double* x, doubl
         const Plan& P = H->P;
         double* xt = H->nv(2);
         launch_nvec_copy_scale(H->st, x, xt, P.N, 1.0, 0.0);
-        if (alpha == 0.0) launch_nvec_project(H->st, xt, P.N);
+        if (singular(H, alpha)) launch_nvec_project(H->st, xt, P.N);
         spread_to(H, xt, 0.0, nullptr, H->grid(G_T2), H->inv_h3(), nullptr);
         const double* cinv = select_cinv(H, alpha);
         if (P.esz == 4) fg_cycles<float>(H, alpha, H->grid(G_T2), nullptr, 0.0, H->grid(G_U), true, cycles, cinv);
         else fg_cycles<double>(H, alpha, H->grid(G_T2), nullptr, 0.0, H->grid(G_U), true, cycles, cinv);
         fg_interp(H, H->grid(G_U), y);
-        if (alpha == 0.0) launch_nvec_project(H->st, y, P.N);
+        if (singular(H, alpha)) launch_nvec_project(H->st, y, P.N);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(H->st));
         return BLOB_RD_OK;

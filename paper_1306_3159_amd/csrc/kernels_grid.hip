@@ -9,22 +9,35 @@
 
 namespace brd {
 
-// y = alpha x - s (sum of 6 neighbours - 6 x), s = D / h^2
+// y = alpha x - s (sum of 6 neighbours - 6 x), s = D / h^2. BOX: a box with
+// homogeneous faces, where the neighbour beyond a face is the ghost -x.
+template <bool BOX>
 __device__ __forceinline__ double stencil_A(const double* __restrict__ x, int X, int Y, int Z, int nx, int ny, int nz,
                                             double alpha, double s, size_t idx, double* center) {
     const long long sxy = (long long)nx * ny;
     const long long i = (long long)idx;
     const double c = x[i];
-    const double xm = x[i - X + wrapi(X - 1, nx)];
-    const double xp = x[i - X + wrapi(X + 1, nx)];
-    const double ym = x[i + (long long)(wrapi(Y - 1, ny) - Y) * nx];
-    const double yp = x[i + (long long)(wrapi(Y + 1, ny) - Y) * nx];
-    const double zm = x[i + (long long)(wrapi(Z - 1, nz) - Z) * sxy];
-    const double zp = x[i + (long long)(wrapi(Z + 1, nz) - Z) * sxy];
+    double xm, xp, ym, yp, zm, zp;
+    if (BOX) {
+        xm = X > 0 ? x[i - 1] : -c;
+        xp = X + 1 < nx ? x[i + 1] : -c;
+        ym = Y > 0 ? x[i - nx] : -c;
+        yp = Y + 1 < ny ? x[i + nx] : -c;
+        zm = Z > 0 ? x[i - sxy] : -c;
+        zp = Z + 1 < nz ? x[i + sxy] : -c;
+    } else {
+        xm = x[i - X + wrapi(X - 1, nx)];
+        xp = x[i - X + wrapi(X + 1, nx)];
+        ym = x[i + (long long)(wrapi(Y - 1, ny) - Y) * nx];
+        yp = x[i + (long long)(wrapi(Y + 1, ny) - Y) * nx];
+        zm = x[i + (long long)(wrapi(Z - 1, nz) - Z) * sxy];
+        zp = x[i + (long long)(wrapi(Z + 1, nz) - Z) * sxy];
+    }
     *center = c;
     return alpha * c - s * ((xm + xp) + (ym + yp) + (zm + zp) - 6.0 * c);
 }
 
+template <bool BOX>
 __global__ void __launch_bounds__(kBlock) k_applyA(const double* __restrict__ p, double* __restrict__ q,
                                                    double alpha, double s, int nx, int ny, int nz, unsigned ncell,
                                                    double* part, const Scalars* sc) {
@@ -37,7 +50,7 @@ __global__ void __launch_bounds__(kBlock) k_applyA(const double* __restrict__ p,
         const unsigned t = idx / nx;
         const int Y = t % ny, Z = t / ny;
         double c;
-        const double y = stencil_A(p, X, Y, Z, nx, ny, nz, alpha, s, idx, &c);
+        const double y = stencil_A<BOX>(p, X, Y, Z, nx, ny, nz, alpha, s, idx, &c);
         q[idx] = y;
         v[0] += c * y;
         v[1] += y;
@@ -49,7 +62,7 @@ void launch_applyA(hipStream_t st, const double* p, double* q, double alpha, dou
                    double* part, const Scalars* sc, unsigned* np) {
     const unsigned n = (unsigned)nx * ny * nz;
     const unsigned nb = part ? red_blocks(n) : nblocks(n);
-    hipLaunchKernelGGL(k_applyA, dim3(nb), dim3(kBlock), 0, st, p, q, alpha, s, nx, ny, nz, n, part, sc);
+    hipLaunchKernelGGL(k_applyA<false>, dim3(nb), dim3(kBlock), 0, st, p, q, alpha, s, nx, ny, nz, n, part, sc);
     if (np) *np = nb;
 }
 
@@ -57,6 +70,7 @@ typedef double double2_t __attribute__((ext_vector_type(2)));
 
 // Two cells per thread (x even, x + 1) with 16-byte loads: q = alpha p - D L p,
 // partials (p.q, sum q). Same arithmetic and summation order as stencil_A.
+template <bool BOX>
 __device__ __forceinline__ void applyA2_body(const double* __restrict__ p, double* __restrict__ q, double alpha,
                                              double s, int nx, int ny, int nz, unsigned npair, double* part, Blk blk) {
     unsigned lo, hi;
@@ -70,12 +84,23 @@ __device__ __forceinline__ void applyA2_body(const double* __restrict__ p, doubl
         const int Y = t % ny, Z = t / ny;
         const long long i = ((long long)Z * ny + Y) * nx + X;
         const double2_t c = *reinterpret_cast<const double2_t*>(p + i);
-        const double xl = p[i - X + (X == 0 ? nx - 1 : X - 1)];
-        const double xr = p[i - X + (X + 2 == nx ? 0 : X + 2)];
-        const double2_t ym = *reinterpret_cast<const double2_t*>(p + i + (long long)(wrapi(Y - 1, ny) - Y) * nx);
-        const double2_t yp = *reinterpret_cast<const double2_t*>(p + i + (long long)(wrapi(Y + 1, ny) - Y) * nx);
-        const double2_t zm = *reinterpret_cast<const double2_t*>(p + i + (long long)(wrapi(Z - 1, nz) - Z) * sxy);
-        const double2_t zp = *reinterpret_cast<const double2_t*>(p + i + (long long)(wrapi(Z + 1, nz) - Z) * sxy);
+        double xl, xr;
+        double2_t ym, yp, zm, zp;
+        if (BOX) {
+            xl = X > 0 ? p[i - 1] : -c[0];
+            xr = X + 2 < nx ? p[i + 2] : -c[1];
+            ym = Y > 0 ? *reinterpret_cast<const double2_t*>(p + i - nx) : -c;
+            yp = Y + 1 < ny ? *reinterpret_cast<const double2_t*>(p + i + nx) : -c;
+            zm = Z > 0 ? *reinterpret_cast<const double2_t*>(p + i - sxy) : -c;
+            zp = Z + 1 < nz ? *reinterpret_cast<const double2_t*>(p + i + sxy) : -c;
+        } else {
+            xl = p[i - X + (X == 0 ? nx - 1 : X - 1)];
+            xr = p[i - X + (X + 2 == nx ? 0 : X + 2)];
+            ym = *reinterpret_cast<const double2_t*>(p + i + (long long)(wrapi(Y - 1, ny) - Y) * nx);
+            yp = *reinterpret_cast<const double2_t*>(p + i + (long long)(wrapi(Y + 1, ny) - Y) * nx);
+            zm = *reinterpret_cast<const double2_t*>(p + i + (long long)(wrapi(Z - 1, nz) - Z) * sxy);
+            zp = *reinterpret_cast<const double2_t*>(p + i + (long long)(wrapi(Z + 1, nz) - Z) * sxy);
+        }
         double2_t y;
         y[0] = alpha * c[0] - s * ((xl + c[1]) + (ym[0] + yp[0]) + (zm[0] + zp[0]) - 6.0 * c[0]);
         y[1] = alpha * c[1] - s * ((c[0] + xr) + (ym[1] + yp[1]) + (zm[1] + zp[1]) - 6.0 * c[1]);
@@ -86,11 +111,12 @@ __device__ __forceinline__ void applyA2_body(const double* __restrict__ p, doubl
     if (part) block_partials<2>(v, part, blk.nb, blk.b);
 }
 
+template <bool BOX>
 __global__ void __launch_bounds__(kBlock) k_applyA2(const double* __restrict__ p, double* __restrict__ q,
                                                     double alpha, double s, int nx, int ny, int nz, unsigned npair,
                                                     double* part, const Scalars* sc) {
     if (sc && sc->done) return;
-    applyA2_body(p, q, alpha, s, nx, ny, nz, npair, part, Blk{blockIdx.x, gridDim.x});
+    applyA2_body<BOX>(p, q, alpha, s, nx, ny, nz, npair, part, Blk{blockIdx.x, gridDim.x});
 }
 
 __global__ void __launch_bounds__(kBlock) kb_applyA2(const InstDev* inst, const int* gate, const BatchTab* tab) {
@@ -99,17 +125,18 @@ __global__ void __launch_bounds__(kBlock) kb_applyA2(const InstDev* inst, const 
         Blk blk;
         const InstDev* I = batch_slot(inst, gate, ent, tab->n, g, blk);
         if (!I) continue;
-        applyA2_body(I->p, I->q, I->alpha, I->ls[0], I->nx, I->ny, I->nz, (unsigned)(I->nx / 2) * I->ny * I->nz,
+        applyA2_body<false>(I->p, I->q, I->alpha, I->ls[0], I->nx, I->ny, I->nz, (unsigned)(I->nx / 2) * I->ny * I->nz,
                      I->part, blk);
         __syncthreads();  // partial-sum scratch is reused by the next virtual block
     }
 }
 
 void launch_applyA2(hipStream_t st, const double* p, double* q, double alpha, double s, int nx, int ny, int nz,
-                    double* part, const Scalars* sc, unsigned* np) {
+                    double* part, const Scalars* sc, unsigned* np, bool box) {
     const unsigned npair = (unsigned)(nx / 2) * ny * nz;
     const unsigned nb = red_blocks(npair);
-    hipLaunchKernelGGL(k_applyA2, dim3(nb), dim3(kBlock), 0, st, p, q, alpha, s, nx, ny, nz, npair, part, sc);
+    hipLaunchKernelGGL(box ? k_applyA2<true> : k_applyA2<false>, dim3(nb), dim3(kBlock), 0, st, p, q, alpha, s, nx,
+                       ny, nz, npair, part, sc);
     *np = nb;
 }
 
@@ -170,12 +197,14 @@ template void launch_dir2<double>(hipStream_t, const double*, const double*, dou
 // entry for the new r in the same pass: f = r - mean (the mean predicted from
 // sum r and sum q) into the split level-0 arrays, and the first red
 // half-sweep from a zero guess, u_red = f_red / diag (as k_enter computes it).
-template <typename T>
+// BOX: the diagonal of a box with fixed faces, per red cell from its face count.
+template <typename T, bool BOX = false>
 __device__ __forceinline__ void update2_enter_body(double* __restrict__ x, double* __restrict__ r,
                                                    const double* __restrict__ p, const double* __restrict__ q,
                                                    T* __restrict__ f0, T* __restrict__ f1, T* __restrict__ u0, int nx,
                                                    int ny, unsigned npair, double inv_diag, double a, double m,
-                                                   bool fresh, double* part, Blk blk) {
+                                                   bool fresh, double* part, Blk blk, int nz = 0,
+                                                   BoxCoef binv = BoxCoef{}) {
     unsigned lo, hi;
     chunk_of(xcd_block(blk.b, blk.nb), blk.nb, npair, &lo, &hi);
     double v[2] = {0.0, 0.0};
@@ -200,7 +229,12 @@ __device__ __forceinline__ void update2_enter_body(double* __restrict__ x, doubl
         const double fr = par ? fb : fa, fk = par ? fa : fb;
         f0[k] = (T)fr;
         f1[k] = (T)fk;
-        u0[k] = (T)((T)fr * (T)inv_diag);
+        if (BOX) {
+            const int xr = 2 * (int)(k % hx) + par;  // the red cell of the pair
+            u0[k] = (T)((T)fr * (T)binv.v[box_faces(xr, (int)(t % ny), (int)(t / ny), nx, ny, nz)]);
+        } else {
+            u0[k] = (T)((T)fr * (T)inv_diag);
+        }
     }
     block_partials<2>(v, part, blk.nb, blk.b);
 }
@@ -214,6 +248,18 @@ __global__ void __launch_bounds__(kBlock) k_update2_enter(double* __restrict__ x
     if (sc->done) return;
     update2_enter_body<T>(x, r, p, q, f0, f1, u0, nx, ny, npair, inv_diag, sc->alpha, sc->mean_next,
                           sc->xzero && sc->iters == 0, part, Blk{blockIdx.x, gridDim.x});
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_update2_enter_box(double* __restrict__ x, double* __restrict__ r,
+                                                              const double* __restrict__ p,
+                                                              const double* __restrict__ q, T* __restrict__ f0,
+                                                              T* __restrict__ f1, T* __restrict__ u0, int nx, int ny,
+                                                              int nz, unsigned npair, BoxCoef binv, double* part,
+                                                              const Scalars* sc) {
+    if (sc->done) return;
+    update2_enter_body<T, true>(x, r, p, q, f0, f1, u0, nx, ny, npair, 0.0, sc->alpha, sc->mean_next,
+                                sc->xzero && sc->iters == 0, part, Blk{blockIdx.x, gridDim.x}, nz, binv);
 }
 
 template <typename T>
@@ -233,18 +279,24 @@ __global__ void __launch_bounds__(kBlock) kb_update2_enter(const InstDev* inst, 
 
 template <typename T>
 void launch_update2_enter(hipStream_t st, double* x, double* r, const double* p, const double* q, T* f0, T* f1, T* u0,
-                          int nx, int ny, int nz, double inv_diag, double* part, const Scalars* sc, unsigned* np) {
+                          int nx, int ny, int nz, double inv_diag, double* part, const Scalars* sc, unsigned* np,
+                          const BoxCoef* box_inv) {
     const unsigned npair = (unsigned)(nx / 2) * ny * nz;
     const unsigned nb = red_blocks(npair);
-    hipLaunchKernelGGL(k_update2_enter<T>, dim3(nb), dim3(kBlock), 0, st, x, r, p, q, f0, f1, u0, nx, ny, npair,
-                       inv_diag, part, sc);
+    if (box_inv)
+        hipLaunchKernelGGL(k_update2_enter_box<T>, dim3(nb), dim3(kBlock), 0, st, x, r, p, q, f0, f1, u0, nx, ny, nz,
+                           npair, *box_inv, part, sc);
+    else
+        hipLaunchKernelGGL(k_update2_enter<T>, dim3(nb), dim3(kBlock), 0, st, x, r, p, q, f0, f1, u0, nx, ny, npair,
+                           inv_diag, part, sc);
     *np = nb;
 }
 template void launch_update2_enter<float>(hipStream_t, double*, double*, const double*, const double*, float*, float*,
-                                          float*, int, int, int, double, double*, const Scalars*, unsigned*);
+                                          float*, int, int, int, double, double*, const Scalars*, unsigned*,
+                                          const BoxCoef*);
 template void launch_update2_enter<double>(hipStream_t, double*, double*, const double*, const double*, double*,
                                            double*, double*, int, int, int, double, double*, const Scalars*,
-                                           unsigned*);
+                                           unsigned*, const BoxCoef*);
 
 // partials (sum z, z.r, z.q), two cells per thread
 template <typename T>
@@ -284,16 +336,16 @@ template void launch_zdots2<double>(hipStream_t, const double*, const double*, c
                                     int, int, double*, const Scalars*, unsigned*);
 
 void launch_applyA_plain(hipStream_t st, const double* x, double* y, double alpha, double s, int nx, int ny,
-                         int nz) {
+                         int nz, bool box) {
     const unsigned n = (unsigned)nx * ny * nz;
     if (nx % 2 == 0) {  // two cells per thread, the same arithmetic
         const unsigned npair = n / 2;
-        hipLaunchKernelGGL(k_applyA2, dim3(nblocks(npair)), dim3(kBlock), 0, st, x, y, alpha, s, nx, ny, nz, npair,
-                           (double*)nullptr, (const Scalars*)nullptr);
+        hipLaunchKernelGGL(box ? k_applyA2<true> : k_applyA2<false>, dim3(nblocks(npair)), dim3(kBlock), 0, st, x, y,
+                           alpha, s, nx, ny, nz, npair, (double*)nullptr, (const Scalars*)nullptr);
         return;
     }
-    hipLaunchKernelGGL(k_applyA, dim3(nblocks(n)), dim3(kBlock), 0, st, x, y, alpha, s, nx, ny, nz, n,
-                       (double*)nullptr, (const Scalars*)nullptr);
+    hipLaunchKernelGGL(box ? k_applyA<true> : k_applyA<false>, dim3(nblocks(n)), dim3(kBlock), 0, st, x, y, alpha,
+                       s, nx, ny, nz, n, (double*)nullptr, (const Scalars*)nullptr);
 }
 
 // r = g - (alpha x - D L x) or, with x == nullptr, r = g - q0 (q0 may be null: r = g).
@@ -310,7 +362,7 @@ __global__ void __launch_bounds__(kBlock) k_residual64(const double* __restrict_
             const int X = idx % nx;
             const unsigned t = idx / nx;
             double c;
-            ax = stencil_A(x, X, (int)(t % ny), (int)(t / ny), nx, ny, nz, alpha, s, idx, &c);
+            ax = stencil_A<false>(x, X, (int)(t % ny), (int)(t / ny), nx, ny, nz, alpha, s, idx, &c);
         } else if (q0) {
             ax = q0[idx];
         }
@@ -681,12 +733,12 @@ void launch_fg_scale(hipStream_t st, double* w, const double* h, size_t n) {
 
 // r = b - r (sub) or r = b, with b = [bg; 0]; partials of r.r
 __global__ void __launch_bounds__(kBlock) k_fg_resid(double* __restrict__ r, const double* __restrict__ bg,
-                                                     unsigned ncell, unsigned n, int sub, double* part) {
+                                                     unsigned ncell, unsigned n, int sub, double* part, double phi) {
     unsigned lo, hi;
     chunk_of(blockIdx.x, gridDim.x, n, &lo, &hi);
     double a[1] = {0.0};
     for (unsigned i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const double b = i < ncell ? bg[i] : 0.0;
+        const double b = i < ncell ? bg[i] : phi;
         const double v = sub ? b - r[i] : b;
         r[i] = v;
         a[0] += v * v;
@@ -695,9 +747,10 @@ __global__ void __launch_bounds__(kBlock) k_fg_resid(double* __restrict__ r, con
 }
 
 void launch_fg_resid(hipStream_t st, double* r, const double* bg, size_t ncell, size_t n, int sub, double* part,
-                     unsigned* np) {
+                     unsigned* np, double phi) {
     const unsigned nb = red_blocks(n);
-    hipLaunchKernelGGL(k_fg_resid, dim3(nb), dim3(kBlock), 0, st, r, bg, (unsigned)ncell, (unsigned)n, sub, part);
+    hipLaunchKernelGGL(k_fg_resid, dim3(nb), dim3(kBlock), 0, st, r, bg, (unsigned)ncell, (unsigned)n, sub, part,
+                       phi);
     *np = nb;
 }
 

@@ -9,9 +9,9 @@ namespace brd {
 // q = alpha p - D L p ; partials (p.q, sum q) into part[0..1][nb]
 void launch_applyA(hipStream_t st, const double* p, double* q, double alpha, double s, int nx, int ny,
                    int nz, double* part, const Scalars* sc, unsigned* nparts_out);
-// y = alpha x - D L x (no partials, no guard)
+// y = alpha x - D L x (no partials, no guard); box: L with homogeneous box faces
 void launch_applyA_plain(hipStream_t st, const double* x, double* y, double alpha, double s, int nx, int ny,
-                         int nz);
+                         int nz, bool box = false);
 // partials (g.g, sum g, g.g) of a residual that already holds g
 void launch_self_partials(hipStream_t st, const double* g, size_t n, double* part, unsigned* nparts_out);
 // r = g - q0 (q0 may be null: r = g); partials (r.r, sum r, g.g)
@@ -20,16 +20,17 @@ void launch_residual_from_q(hipStream_t st, const double* g, const double* q0, d
 // Two-cells-per-thread forms (nx even): stencil with partials, direction update,
 // CG update, z dots.
 void launch_applyA2(hipStream_t st, const double* p, double* q, double alpha, double s, int nx, int ny, int nz,
-                    double* part, const Scalars* sc, unsigned* nparts_out);
+                    double* part, const Scalars* sc, unsigned* nparts_out, bool box = false);
 // p = z + shift + beta p (z split, level-0 layout of type T)
 template <typename T>
 void launch_dir2(hipStream_t st, const T* z0, const T* z1, double* p, int nx, int ny, int nz, const Scalars* sc);
 // x += alpha p ; r -= alpha q with partials (r.r, sum r), and the V-cycle entry of
-// the new r (f split, first red sweep u0)
+// the new r (f split, first red sweep u0); box_inv: per-face-count inverse
+// diagonals of a box with fixed faces (inv_diag unused)
 template <typename T>
 void launch_update2_enter(hipStream_t st, double* x, double* r, const double* p, const double* q, T* f0, T* f1, T* u0,
                           int nx, int ny, int nz, double inv_diag, double* part, const Scalars* sc,
-                          unsigned* nparts_out);
+                          unsigned* nparts_out, const BoxCoef* box_inv = nullptr);
 // partials (sum z, z.r, z.q) with z split of type T
 template <typename T>
 void launch_zdots2(hipStream_t st, const T* z0, const T* z1, const double* r, const double* q, int nx, int ny, int nz,
@@ -52,9 +53,9 @@ void launch_fg_mgs(hipStream_t st, double* w, const double* vprev, const double*
 void launch_fg_fin(hipStream_t st, const double* part, unsigned np, double* out, int take_sqrt);
 // w /= *h (0 if *h == 0)
 void launch_fg_scale(hipStream_t st, double* w, const double* h, size_t n);
-// r = [bg; 0] - r (sub) or [bg; 0]; partials of r.r
+// r = [bg; phi] - r (sub) or [bg; phi] (phi a constant on every blob); partials of r.r
 void launch_fg_resid(hipStream_t st, double* r, const double* bg, size_t ncell, size_t n, int sub, double* part,
-                     unsigned* np);
+                     unsigned* np, double phi = 0.0);
 // x[0..n) += sum_j y_j Z_j[off ..) (y on the device)
 void launch_fg_update(hipStream_t st, double* x, const double* Z, size_t stride, size_t off, size_t n, int k,
                       const double* y);
@@ -97,6 +98,26 @@ void launch_prolong(hipStream_t st, const T* cu0, const T* cu1, int coarse_natur
                     int nz, const Scalars* sc, int bs = kBlock);
 template <typename T>
 void launch_coarse(hipStream_t st, const T* f, T* u, const double* cinv, int m, const Scalars* sc);
+
+// ---- multigrid of a box with homogeneous faces (split layout, one cell per thread) ----
+// The same V-cycle steps as above with the box operator: per-cell diagonals from
+// the face count (BoxCoef, index = faces touched), no neighbours across faces,
+// restriction and prolongation with the ghost -u beyond a face.
+template <typename T>
+void launch_enter_box(hipStream_t st, const double* r, T* f0, T* f1, T* u0, int nx, int ny, int nz,
+                      const BoxCoef& inv, const Scalars* sc);
+template <typename T>
+void launch_gs_box(hipStream_t st, T* uc, const T* uo, const T* fc, int nx, int ny, int nz, int color, double s,
+                   const BoxCoef& inv, const Scalars* sc);
+template <typename T>
+void launch_resid_red_box(hipStream_t st, const T* u0, const T* u1, const T* f0, T* r0, int nx, int ny, int nz,
+                          double s, const BoxCoef& diag, const Scalars* sc);
+template <typename T>
+void launch_restrict_box(hipStream_t st, const T* r0, int nx, int ny, int nz, T* cf0, T* cf1, T* cu0,
+                         int coarse_natural, const BoxCoef& inv_c, const Scalars* sc);
+template <typename T>
+void launch_prolong_red_box(hipStream_t st, const T* cu0, const T* cu1, int coarse_natural, T* u0, int nx, int ny,
+                            int nz, const Scalars* sc);
 
 template <typename T>
 void launch_tail(hipStream_t st, const T* f0, const T* f1, T* u0, T* u1, const TailDesc& d, const double* cinv,

@@ -23,6 +23,8 @@ PRECOND_LEARNED = 2
 SOLVER_SCHUR = 0
 SOLVER_BLOCK = 1
 SOLVER_BLOCK_LEARNED = 2
+BOUNDARY_PERIODIC = 0
+BOUNDARY_DIRICHLET = 1
 
 OK = 0
 ENOTCONV = 1
@@ -38,6 +40,7 @@ class Params(ctypes.Structure):
         ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
         ("inner_max_iter", ctypes.c_int32), ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p), ("saddle_solver", ctypes.c_int32),
+        ("boundary", ctypes.c_int32), ("boundary_value", ctypes.c_double),
     ]
 
 
@@ -240,7 +243,8 @@ class Net:
 
 
 class BlobRD:
-    """A blob configuration on a periodic grid (wraps a blob_rd handle).
+    """A blob configuration on a periodic grid, or in a box whose faces hold c = boundary_value
+    (boundary=BOUNDARY_DIRICHLET), wrapping a blob_rd handle.
 
     Grid tensors are float64 CUDA tensors of shape (nz, ny, nx); q is (N, 3)
     float64 (x, y, z) and kappa (N,) float64 on the same device.
@@ -250,7 +254,7 @@ class BlobRD:
                  h: float = 1.0, D: float = 1.0, kernel_w: int = 4, precision: int = FP64,
                  schur_precond: int = PRECOND_NONE, rtol: float = 1e-8, max_iter: int = 0,
                  gmres_restart: int = 0, inner_max_iter: int = 0, stream: Optional[torch.cuda.Stream] = None,
-                 saddle_solver: int = 0):
+                 saddle_solver: int = 0, boundary: int = 0, boundary_value: float = 0.0):
         L = load_library()
         if isinstance(shape, int):
             shape = (shape, shape, shape)
@@ -268,7 +272,8 @@ class BlobRD:
         p = Params(nx, ny, nz, float(h), float(D), int(kernel_w), N, q.data_ptr() if N > 0 else None,
                    None if kappa is None else kappa.data_ptr(), int(precision), int(schur_precond),
                    float(rtol), int(max_iter), int(gmres_restart), int(inner_max_iter), None, 0,
-                   ctypes.c_void_p(self.stream.cuda_stream), int(saddle_solver))
+                   ctypes.c_void_p(self.stream.cuda_stream), int(saddle_solver), int(boundary),
+                   float(boundary_value))
         nbytes = L.blob_rd_workspace_bytes(ctypes.byref(p))
         if nbytes == 0:
             raise BlobRDError(-1, L.blob_rd_last_error(None).decode())
