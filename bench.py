@@ -41,7 +41,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rsa256_learned", choices=["rsa256_learned", "lattice128_randf", "batch64"])
+    ap.add_argument("--workload", default="rsa256_learned",
+                    choices=["rsa256_learned", "lattice128_randf", "batch64", "box256"])
     ap.add_argument("--threads", type=int, default=8, help="host workers of the batch executor")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run one device copy of this many MiB (calibrates memory counters)")
@@ -197,14 +198,17 @@ def main():
         sys.exit(2)
     import torch
     import workloads as W
-    from paper_1306_3159_amd import BlobRD, Net, MIXED, FP64, PRECOND_LEARNED, PRECOND_NONE
+    from paper_1306_3159_amd import BlobRD, Net, MIXED, FP64, PRECOND_LEARNED, PRECOND_NONE, BOUNDARY_DIRICHLET
 
     dev = torch.device("cuda:0")
     rtol = 1e-8
     if args.workload == "batch64":
         return bench_batch(args, dev, rtol)
+    box = args.workload == "box256"
     if args.workload == "rsa256_learned":
         inst = W.learned_eval(256, 10000, index=0)
+    elif box:
+        inst = W.box_suspension(256, 10000)
     else:
         inst = W.cubic_lattice(random_f=True)
     q = torch.tensor(inst.q, device=dev)
@@ -216,16 +220,21 @@ def main():
         net.set_params(torch.tensor(np.load(WEIGHTS), device=dev))
         S = BlobRD(inst.n, q, precision=MIXED, schur_precond=PRECOND_LEARNED, rtol=rtol)
         S.precond_build(net)
+    elif box:
+        S = BlobRD(inst.n, q, precision=MIXED, rtol=rtol, boundary=BOUNDARY_DIRICHLET, boundary_value=1.0)
     else:
         S = BlobRD(inst.n, q, precision=MIXED, rtol=rtol)
     tuning = None
-    if args.autotune:
+    if args.autotune and not box:
         S.autotune(reps=10)
         tuning = S.get_tuning().tolist()
     learned = args.workload == "rsa256_learned"
     if learned:
         # block FGMRES, approximate-Schur preconditioner with the learned inner preconditioning
         dt, st = timed(lambda: S.solve_absorbing_fgmres(f, precond="learned", m=5, n=1, restart=30)[2], args.steps,
+                       args.warmup)
+    elif box:
+        dt, st = timed(lambda: S.solve_absorbing_fgmres(f, precond="schur", m=5, n=1, restart=30)[2], args.steps,
                        args.warmup)
     else:
         dt, st = timed(lambda: S.solve_absorbing(f)[2], args.steps, args.warmup)
@@ -239,15 +248,16 @@ def main():
         "config": {"workload": args.workload, "n": inst.n, "N": inst.N, "kind": "absorbing", "rtol": rtol,
                    "kernel_w": 4, "restart": 30,
                    "path": "block FGMRES + approximate Schur (m=5, n=1) with learned inner preconditioning + fp32"
-                   if learned else "Schur GMRES + inner MG-CG + fp32",
-                   "source": "f=1" if learned else "f=1+0.5N(0,1)", "seed": inst.seed},
-        "solve": summary(st, block=learned),
+                   if learned else ("Dirichlet box c_inf=1: block FGMRES + approximate Schur (m=5, n=1) + fp32"
+                                    if box else "Schur GMRES + inner MG-CG + fp32"),
+                   "source": "f=1" if (learned or box) else "f=1+0.5N(0,1)", "seed": inst.seed},
+        "solve": summary(st, block=learned or box),
         "median_ms_per_step": None if med is None else 1e3 * med,
         "tuning": tuning,
     }
     out["solve"]["alg_GBs"] = st["alg_bytes"] / (dt / args.steps) / 1e9
 
-    if not args.no_extra:
+    if not args.no_extra and not box:
         n = max(2, args.steps // 2)
         P = BlobRD(inst.n, q, precision=FP64, rtol=rtol)
         if args.autotune:
@@ -288,6 +298,18 @@ def main():
                                        "block_fgmres": summary(lbst, True)}
             L.close()
             L2.close()
+            # the same suspension size in a box held at c_inf = 1 (Sec. IV.C): block FGMRES on the
+            # lifted system, box multigrid kernels in FP32
+            bx = W.box_suspension(inst.n, inst.N)
+            Bx = BlobRD(bx.n, torch.tensor(bx.q, device=dev), precision=MIXED, rtol=rtol,
+                        boundary=BOUNDARY_DIRICHLET, boundary_value=1.0)
+            bf = torch.tensor(bx.f, device=dev)
+            xdt, xst = timed(lambda: Bx.solve_absorbing_fgmres(bf, precond="schur")[2], n, 1)
+            gms, gby = Bx.time_kernel("gs", args.kernel_reps, cold=True)
+            out["dirichlet_box256_block_fgmres_fp32"] = {
+                "value": n / xdt, "ms_per_step": 1e3 * xdt / n, "N": bx.N, "seed": bx.seed, **summary(xst, True),
+                "gs_box_cold_us": gms * 1e3, "gs_box_cold_GBs": gby / (gms * 1e-3) / 1e9}
+            Bx.close()
 
     # Roofline of the dominant kernel: the finest-level Gauss-Seidel half-sweep
     # (FP32), timed with HIP events on the handle's stream. Cold: back-to-back
@@ -296,9 +318,10 @@ def main():
     ms, by = S.time_kernel("gs", args.kernel_reps, cold=True)
     wms, _ = S.time_kernel("gs", args.kernel_reps)
     ach = by / (ms * 1e-3) / 1e9
-    out["roofline"] = {"kernel": "k_gs_vec<float> finest level", "bound": "hbm", "achieved": ach,
-                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                       "traffic": measured_traffic(inst.n), "avg_us": ms * 1e3, "bytes_per_launch": by,
+    out["roofline"] = {"kernel": "k_gs_box<float> finest level" if box else "k_gs_vec<float> finest level",
+                       "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": ach / HBM_PEAK_GBS,
+                       "traffic": None if box else measured_traffic(inst.n), "avg_us": ms * 1e3, "bytes_per_launch": by,
                        "warm_avg_us": wms * 1e3, "warm_GBs": by / (wms * 1e-3) / 1e9}
     kern = {}
     for k in ("stencil", "restrict", "prolong", "vcycle"):
@@ -309,7 +332,7 @@ def main():
     if net is not None:
         net.close()
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not box:
         from oracle import iterative as it
         it.build(force=False)
         # the method's first Poisson right-hand side: f minus the mean sink strength spread

@@ -77,9 +77,10 @@ extern "C" {
  * BLOCK or BLOCK_LEARNED (the learned part is never used in a box: its network
  * models the periodic cell), blob_rd_solve_absorbing_fgmres and the operator
  * calls (blob_rd_apply applies the homogeneous operator alpha I - D L_0 [+ S kappa J],
- * blob_rd_vcycle its V-cycle). EINVAL: absorbing solves with saddle_solver
- * SCHUR, blob_rd_precond_build, blob_rd_time_kernel, blob_rd_autotune; batched
- * calls run box handles on their own streams, never in the lock-step launches. */
+ * blob_rd_vcycle its V-cycle, blob_rd_time_kernel the box forms of its kernels).
+ * EINVAL: absorbing solves with saddle_solver SCHUR, blob_rd_precond_build,
+ * blob_rd_autotune; batched calls run box handles on their own streams, never in
+ * the lock-step launches. */
 #define BLOB_RD_BOUNDARY_PERIODIC 0
 #define BLOB_RD_BOUNDARY_DIRICHLET 1
 
@@ -384,7 +385,8 @@ int blob_rd_solve_batched(blob_rd_t* h, int32_t n, const int32_t* kind, double a
  * evicted; the other kernels are each timed alone after >= 512 MB have been
  * streamed through the cache. avg_ms receives the mean time per launch and
  * bytes the algorithmic HBM bytes one launch must move (each input read once,
- * each output written once). */
+ * each output written once). On a Dirichlet-box handle the box forms of the
+ * kernels are timed (same byte counts). */
 int blob_rd_time_kernel(blob_rd_t h, int kernel, int reps, double* avg_ms, double* bytes);
 
 /* ---- Launch-shape autotuning ----

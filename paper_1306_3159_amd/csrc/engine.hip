@@ -25,6 +25,7 @@
 #include <mutex>
 #include <condition_variable>
 #include <chrono>
+#include <type_traits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -1701,7 +1702,8 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
                     for (int a = 0; a < 3; ++a) {
                         const double v = hq[(size_t)i * 3 + a];
                         if (v < 3.0 * p->h || v > edge[a] - 3.0 * p->h)
-                            throw Err(BLOB_RD_EINVAL, "in a Dirichlet box every blob must lie at least 3h inside each face");
+                            throw Err(BLOB_RD_EINVAL,
+                                      "in a Dirichlet box every blob must lie at least 3h inside each face");
                     }
             }
             for (double v : hk)
@@ -2788,12 +2790,21 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
     const bool cold = (kernel & BLOB_RD_KERNEL_COLD) != 0;
     kernel &= ~BLOB_RD_KERNEL_COLD;
     if (kernel < 0 || kernel > 4) return g_last_error = "unknown kernel id", BLOB_RD_EINVAL;
-    if (H->box) return g_last_error = "kernel timing covers the periodic multigrid kernels", BLOB_RD_EINVAL;
     return guarded(H, nullptr, [&]() {
         const Plan& P = H->P;
         const LevelDims& d = P.lev[0];
         const double alpha = 0.0, s = H->prm.D / (d.h * d.h), diag = alpha + 6.0 * s;
         const double* cinv = select_cinv(H, alpha);
+        // a box handle times its own kernels (the box forms of the same steps)
+        const bool box = H->box;
+        BoxCoef bdg0, binv0, binv1;
+        box_coefs(H, 0, alpha, &bdg0, &binv0);
+        box_coefs(H, 1, alpha, nullptr, &binv1);
+        auto gs_any = [&](auto* uc, const auto* uo, const auto* fc) {
+            typedef std::remove_const_t<std::remove_pointer_t<decltype(uo)>> TT;
+            if (box) launch_gs_box<TT>(H->st, uc, uo, fc, d.nx, d.ny, d.nz, 1, s, binv0, nullptr);
+            else launch_gs<TT>(H->st, uc, uo, fc, d.hx, d.ny, d.nz, 1, s, 1.0 / diag, nullptr);
+        };
         zero_levels(H);
         HIPCHK(hipMemsetAsync(H->grid(G_P), 0, P.ncell * 8, H->st));
         HIPCHK(hipMemsetAsync(H->grid(G_R), 0, P.ncell * 8, H->st));
@@ -2806,19 +2817,38 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
             const int cnat = P.nlev == 2;
             switch (kernel) {
                 case BLOB_RD_KERNEL_GS:
-                    if (f32) launch_gs<float>(H->st, H->at<float>(P.off_lvl[0][1]), H->at<float>(P.off_lvl[0][0]),
-                                              H->at<float>(P.off_lvl[0][3]), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, nullptr);
-                    else launch_gs<double>(H->st, H->at<double>(P.off_lvl[0][1]), H->at<double>(P.off_lvl[0][0]),
-                                           H->at<double>(P.off_lvl[0][3]), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, nullptr);
+                    if (f32) gs_any(H->at<float>(P.off_lvl[0][1]), H->at<float>(P.off_lvl[0][0]),
+                                    H->at<float>(P.off_lvl[0][3]));
+                    else gs_any(H->at<double>(P.off_lvl[0][1]), H->at<double>(P.off_lvl[0][0]),
+                                H->at<double>(P.off_lvl[0][3]));
                     break;
                 case BLOB_RD_KERNEL_STENCIL: {
                     unsigned npp = 0;
                     launch_applyA2(H->st, H->grid(G_P), H->grid(G_Q), alpha, s, d.nx, d.ny, d.nz, H->part(), nullptr,
-                                   &npp);
+                                   &npp, box);
                     break;
                 }
                 case BLOB_RD_KERNEL_RESTRICT:
-                    if (f32) {
+                    if (box && f32) {
+                        launch_resid_red_box<float>(H->st, H->at<float>(P.off_lvl[0][0]),
+                                                    H->at<float>(P.off_lvl[0][1]), H->at<float>(P.off_lvl[0][2]),
+                                                    H->at<float>(P.off_lvl[0][4]), d.nx, d.ny, d.nz, s, bdg0, nullptr);
+                        launch_restrict_box<float>(H->st, H->at<float>(P.off_lvl[0][4]), d.nx, d.ny, d.nz,
+                                                   H->at<float>(P.off_lvl[1][2]),
+                                                   cnat ? nullptr : H->at<float>(P.off_lvl[1][3]),
+                                                   cnat ? nullptr : H->at<float>(P.off_lvl[1][0]), cnat, binv1,
+                                                   nullptr);
+                    } else if (box) {
+                        launch_resid_red_box<double>(H->st, H->at<double>(P.off_lvl[0][0]),
+                                                     H->at<double>(P.off_lvl[0][1]), H->at<double>(P.off_lvl[0][2]),
+                                                     H->at<double>(P.off_lvl[0][4]), d.nx, d.ny, d.nz, s, bdg0,
+                                                     nullptr);
+                        launch_restrict_box<double>(H->st, H->at<double>(P.off_lvl[0][4]), d.nx, d.ny, d.nz,
+                                                    H->at<double>(P.off_lvl[1][2]),
+                                                    cnat ? nullptr : H->at<double>(P.off_lvl[1][3]),
+                                                    cnat ? nullptr : H->at<double>(P.off_lvl[1][0]), cnat, binv1,
+                                                    nullptr);
+                    } else if (f32) {
                         launch_resid_red<float>(H->st, H->at<float>(P.off_lvl[0][0]), H->at<float>(P.off_lvl[0][1]),
                                                 H->at<float>(P.off_lvl[0][2]), H->at<float>(P.off_lvl[0][4]), d.hx,
                                                 d.ny, d.nz, s, diag, nullptr);
@@ -2839,7 +2869,15 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
                     }
                     break;
                 case BLOB_RD_KERNEL_PROLONG:
-                    if (f32) launch_prolong<float>(H->st, H->at<float>(P.off_lvl[1][0]),
+                    if (box && f32) launch_prolong_red_box<float>(H->st, H->at<float>(P.off_lvl[1][0]),
+                                                                  cnat ? nullptr : H->at<float>(P.off_lvl[1][1]), cnat,
+                                                                  H->at<float>(P.off_lvl[0][0]), d.nx, d.ny, d.nz,
+                                                                  nullptr);
+                    else if (box) launch_prolong_red_box<double>(H->st, H->at<double>(P.off_lvl[1][0]),
+                                                                 cnat ? nullptr : H->at<double>(P.off_lvl[1][1]), cnat,
+                                                                 H->at<double>(P.off_lvl[0][0]), d.nx, d.ny, d.nz,
+                                                                 nullptr);
+                    else if (f32) launch_prolong<float>(H->st, H->at<float>(P.off_lvl[1][0]),
                                                    cnat ? nullptr : H->at<float>(P.off_lvl[1][1]), cnat,
                                                    H->at<float>(P.off_lvl[0][0]), H->at<float>(P.off_lvl[0][1]), d.nx,
                                                    d.ny, d.nz, nullptr);
@@ -2874,13 +2912,11 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
                 if (!gs) {
                     unsigned npp = 0;
                     launch_applyA2(H->st, (const double*)a[0], (double*)a[1], alpha, s, d.nx, d.ny, d.nz, H->part(),
-                                   nullptr, &npp);
+                                   nullptr, &npp, box);
                 } else if (P.esz == 4) {
-                    launch_gs<float>(H->st, (float*)a[0], (const float*)a[1], (const float*)a[2], d.hx, d.ny, d.nz, 1,
-                                     s, 1.0 / diag, nullptr);
+                    gs_any((float*)a[0], (const float*)a[1], (const float*)a[2]);
                 } else {
-                    launch_gs<double>(H->st, (double*)a[0], (const double*)a[1], (const double*)a[2], d.hx, d.ny,
-                                      d.nz, 1, s, 1.0 / diag, nullptr);
+                    gs_any((double*)a[0], (const double*)a[1], (const double*)a[2]);
                 }
             };
             for (int k = 0; k < nset; ++k) launch_set(k);  // first touch

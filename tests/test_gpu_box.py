@@ -237,6 +237,21 @@ def test_box_errors(dev):
     S = box(dev, 16, inner_blobs(rng, (16, 16, 16), 3), saddle_solver=SOLVER_SCHUR)
     with pytest.raises(BlobRDError, match="saddle_solver BLOCK"):
         S.solve_absorbing(torch.ones((16, 16, 16), dtype=torch.float64, device=dev))
-    with pytest.raises(BlobRDError):
-        S.time_kernel("gs", reps=2)
+    with pytest.raises(BlobRDError, match="periodic"):
+        S.autotune(reps=2)
+    S.close()
+
+
+def test_box_kernel_timing(dev):
+    """A box handle times the box forms of its kernels (positive times, the periodic byte counts)."""
+    from paper_1306_3159_amd import MIXED
+    rng = np.random.default_rng(1306_508)
+    S = box(dev, SHAPE, inner_blobs(rng, SHAPE, 3), precision=MIXED)
+    _say("box kernel timing")
+    n = SHAPE[0] * SHAPE[1] * SHAPE[2]
+    for k in ("gs", "stencil", "restrict", "prolong", "vcycle"):
+        ms, by = S.time_kernel(k, reps=3)
+        assert ms > 0.0 and by > 0.0
+    ms, by = S.time_kernel("gs", reps=3, cold=True)
+    assert ms > 0.0 and by == pytest.approx(n * 0.5 * 4 * 3)
     S.close()

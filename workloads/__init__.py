@@ -201,6 +201,18 @@ def learned_eval(n: int = 256, count: int = 10000, index: int = 0) -> Instance:
                     "absorbing", rtol=1e-8, seed=s)
 
 
+def box_suspension(n: int = 256, count: int = 10000, margin: float = 3.0, index: int = 0) -> Instance:
+    """RSA suspension in a box whose faces hold c = c_inf (the setting of Sec. IV.C): blobs at
+    least `margin` cells inside every face and 3 cells apart, absorbing, f = 1. The points are
+    drawn by periodic RSA in the inner cube [margin, n - margin)^3; its minimum-image test is
+    stricter than the plain distance, so the separation holds in the box as well."""
+    s = seed_for(5, index)
+    rng = np.random.default_rng(s)
+    q = margin + rsa_positions(rng, int(round(n - 2 * margin)), count)
+    return Instance(f"box{n}_N{count}_absorbing", n, q, np.zeros(count), uniform_source(n), "absorbing",
+                    rtol=1e-8, seed=s)
+
+
 def training_config(index: int, n: int = 128, count: int = 1250) -> Instance:
     """Training suspensions for the learned preconditioner (same density as 256^3/10^4)."""
     s = 1306_500_000 + index
