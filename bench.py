@@ -318,7 +318,7 @@ def main():
     ms, by = S.time_kernel("gs", args.kernel_reps, cold=True)
     wms, _ = S.time_kernel("gs", args.kernel_reps)
     ach = by / (ms * 1e-3) / 1e9
-    out["roofline"] = {"kernel": "k_gs_box<float> finest level" if box else "k_gs_vec<float> finest level",
+    out["roofline"] = {"kernel": "k_gs_box_vec<float> finest level" if box else "k_gs_vec<float> finest level",
                        "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": ach / HBM_PEAK_GBS,
                        "traffic": None if box else measured_traffic(inst.n), "avg_us": ms * 1e3, "bytes_per_launch": by,

@@ -522,12 +522,14 @@ void box_coefs(const blob_rd* H, int l, double alpha, BoxCoef* diag, BoxCoef* in
 }
 
 // The V-cycle of vcycle() below for the box operator alpha I - D L_0: the same
-// steps and order with the box kernels on every level, no temporally blocked
-// levels and no LDS tail, the coarsest level by the dense box inverse.
+// steps and order with the box kernels, per-level launches down to the first
+// level of the LDS tail (then the box tail kernel) or to the coarsest level (the
+// dense box inverse); no temporally blocked levels.
 template <typename T>
 void vcycle_box(blob_rd* H, double alpha, const double* r, const Scalars* sc, const double* cinv, bool entered) {
     const Plan& P = H->P;
     const int L = P.nlev - 1;
+    const int t = std::min(H->tail_level[sizeof(T) == 4 ? 0 : 1], L);
     hipStream_t st = H->st;
     auto lv = [&](int l, int k) { return H->at<T>(P.off_lvl[l][k]); };  // 0 u0, 1 u1, 2 f0, 3 f1, 4 r0 (red)
     BoxCoef dg[kMaxLevels], inv[kMaxLevels];
@@ -537,7 +539,7 @@ void vcycle_box(blob_rd* H, double alpha, const double* r, const Scalars* sc, co
         launch_enter_box<T>(st, r, lv(0, 2), lv(0, 3), lv(0, 0), d.nx, d.ny, d.nz, inv[0], sc);
         H->alg_bytes += (double)P.ncell * (8 + P.esz * 1.5);
     }
-    for (int l = 0; l < L; ++l) {
+    for (int l = 0; l < t; ++l) {
         const LevelDims& d = P.lev[l];
         const double s = H->prm.D / (d.h * d.h);
         launch_gs_box<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.nx, d.ny, d.nz, 1, s, inv[l], sc);
@@ -551,8 +553,9 @@ void vcycle_box(blob_rd* H, double alpha, const double* r, const Scalars* sc, co
                                    inv[l + 1], sc);
         H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * kPreRestrictBytes;
     }
-    launch_coarse<T>(st, lv(L, 2), lv(L, 0), cinv, P.m, sc);
-    for (int l = L - 1; l >= 0; --l) {
+    if (t < L) launch_tail_box<T>(st, lv(t, 2), lv(t, 3), lv(t, 0), lv(t, 1), make_tail<T>(H, t, alpha), cinv, sc);
+    else launch_coarse<T>(st, lv(L, 2), lv(L, 0), cinv, P.m, sc);
+    for (int l = t - 1; l >= 0; --l) {
         const LevelDims& d = P.lev[l];
         const double s = H->prm.D / (d.h * d.h);
         const int cnat = (l + 1 == L);
@@ -1761,11 +1764,11 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
         const int Lc = P.nlev - 1;
         if (H->tail_level[0] < Lc) {
             const size_t need = make_tail<float>(H, H->tail_level[0], 0.0).lds_bytes;
-            if (need > 48 * 1024) HIPCHK(tail_set_lds<float>(need));
+            if (need > 48 * 1024) HIPCHK(H->box ? tail_box_set_lds<float>(need) : tail_set_lds<float>(need));
         }
         if (H->tail_level[1] < Lc) {
             const size_t need = make_tail<double>(H, H->tail_level[1], 0.0).lds_bytes;
-            if (need > 48 * 1024) HIPCHK(tail_set_lds<double>(need));
+            if (need > 48 * 1024) HIPCHK(H->box ? tail_box_set_lds<double>(need) : tail_set_lds<double>(need));
         }
         if (H->blocked) {
             HIPCHK(blocked_set_lds<float>());

@@ -48,6 +48,57 @@ __device__ __forceinline__ T box_nb_sum(const T* __restrict__ uo, int i, int y, 
     return ((xm + xp) + (ym + yp)) + (zm + zp);
 }
 
+// 16-byte vectors of the split rows: 4 FP32 or 2 FP64 cells per thread.
+template <typename T>
+struct BoxVec;
+template <>
+struct BoxVec<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static constexpr int W = 4;
+};
+template <>
+struct BoxVec<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+    static constexpr int W = 2;
+};
+
+// Row vector i0 .. i0+VW-1 of colour c (x = 2i + so) and the in-box neighbour sums of
+// its cells from the other colour's array uo. An x-neighbour beyond a face exists only
+// for the first cell of a row (so = 0, x = 0) and the last one (so = 1, x = nx - 1);
+// y/z neighbour rows beyond a face contribute nothing.
+template <typename T>
+__device__ __forceinline__ typename BoxVec<T>::type box_nb_vec(const T* __restrict__ uo, int i0, int y, int z, int nx,
+                                                               int ny, int nz, int so) {
+    typedef typename BoxVec<T>::type V;
+    constexpr int VW = BoxVec<T>::W;
+    const int hx = nx >> 1;
+    const size_t row = ((size_t)z * ny + y) * hx;
+    const size_t plane = (size_t)ny * hx;
+    const T* orow = uo + row;
+    const V o = *reinterpret_cast<const V*>(orow + i0);
+    const T edge = so ? (i0 + VW < hx ? orow[i0 + VW] : (T)0) : (i0 > 0 ? orow[i0 - 1] : (T)0);
+    const V zero = (V)(T)0;
+    const V ym = y > 0 ? *reinterpret_cast<const V*>(orow - hx + i0) : zero;
+    const V yp = y + 1 < ny ? *reinterpret_cast<const V*>(orow + hx + i0) : zero;
+    const V zm = z > 0 ? *reinterpret_cast<const V*>(orow - plane + i0) : zero;
+    const V zp = z + 1 < nz ? *reinterpret_cast<const V*>(orow + plane + i0) : zero;
+    V nb;
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+        const T left = so ? o[k] : (k ? o[k - 1] : edge);
+        const T right = so ? (k + 1 < VW ? o[k + 1] : edge) : o[k];
+        nb[k] = ((left + right) + (ym[k] + yp[k])) + (zm[k] + zp[k]);
+    }
+    return nb;
+}
+
+// Face count of cell k of the row vector: the y/z faces of the row plus x = 0 (first
+// cell, so = 0) or x = nx - 1 (last cell, so = 1).
+template <int VW>
+__device__ __forceinline__ int box_faces_vec(int k, int i0, int hx, int so, int fyz) {
+    return fyz + ((so == 0 && i0 == 0 && k == 0) || (so == 1 && i0 + VW == hx && k == VW - 1) ? 1 : 0);
+}
+
 }  // namespace
 
 // Fine-level entry: f = r (FP64 natural -> T split) and the first red
@@ -96,9 +147,43 @@ __global__ void __launch_bounds__(kBlock) k_gs_box(T* __restrict__ uc, const T* 
     uc[idx] = (fc[idx] + s * nb) * (T)inv.v[box_faces(2 * i + so, y, z, nx, ny, nz)];
 }
 
+// Vector form: VW cells of a split row per thread (needs (nx/2) % VW == 0).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gs_box_vec(T* __restrict__ uc, const T* __restrict__ uo,
+                                                       const T* __restrict__ fc, int nx, int ny, int nz, int color,
+                                                       T s, BoxCoef inv, const Scalars* sc) {
+    if (sc && sc->done) return;
+    typedef typename BoxVec<T>::type V;
+    constexpr int VW = BoxVec<T>::W;
+    const int hx = nx >> 1, hv = hx / VW;
+    const unsigned nv = (unsigned)hv * ny * nz;
+    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= nv) return;
+    int iv, y, z;
+    split_pos(idx, hv, ny, iv, y, z);
+    const int i0 = iv * VW;
+    const int so = ((y + z) & 1) ^ color;
+    const V nb = box_nb_vec<T>(uo, i0, y, z, nx, ny, nz, so);
+    const size_t row = ((size_t)z * ny + y) * hx;
+    const V f = *reinterpret_cast<const V*>(fc + row + i0);
+    const int fyz = (y == 0) + (y + 1 == ny) + (z == 0) + (z + 1 == nz);
+    V out;
+#pragma unroll
+    for (int k = 0; k < VW; ++k)
+        out[k] = (f[k] + s * nb[k]) * (T)inv.v[box_faces_vec<VW>(k, i0, hx, so, fyz)];
+    *reinterpret_cast<V*>(uc + row + i0) = out;
+}
+
 template <typename T>
 void launch_gs_box(hipStream_t st, T* uc, const T* uo, const T* fc, int nx, int ny, int nz, int color, double s,
                    const BoxCoef& inv, const Scalars* sc) {
+    constexpr int VW = BoxVec<T>::W;
+    if ((nx / 2) % VW == 0) {
+        const unsigned nv = (unsigned)(nx / 2 / VW) * ny * nz;
+        hipLaunchKernelGGL(k_gs_box_vec<T>, dim3(nblocks(nv)), dim3(kBlock), 0, st, uc, uo, fc, nx, ny, nz, color,
+                           (T)s, inv, sc);
+        return;
+    }
     const unsigned nh = (unsigned)(nx / 2) * ny * nz;
     hipLaunchKernelGGL(k_gs_box<T>, dim3(nblocks(nh)), dim3(kBlock), 0, st, uc, uo, fc, nx, ny, nz, color, (T)s, inv,
                        sc);
@@ -123,8 +208,42 @@ __global__ void __launch_bounds__(kBlock) k_resid_box(const T* __restrict__ u0, 
 }
 
 template <typename T>
+__global__ void __launch_bounds__(kBlock) k_resid_box_vec(const T* __restrict__ u0, const T* __restrict__ u1,
+                                                          const T* __restrict__ f0, T* __restrict__ r0, int nx,
+                                                          int ny, int nz, T s, BoxCoef diag, const Scalars* sc) {
+    if (sc && sc->done) return;
+    typedef typename BoxVec<T>::type V;
+    constexpr int VW = BoxVec<T>::W;
+    const int hx = nx >> 1, hv = hx / VW;
+    const unsigned nv = (unsigned)hv * ny * nz;
+    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= nv) return;
+    int iv, y, z;
+    split_pos(idx, hv, ny, iv, y, z);
+    const int i0 = iv * VW;
+    const int so = (y + z) & 1;
+    const V nb = box_nb_vec<T>(u1, i0, y, z, nx, ny, nz, so);
+    const size_t row = ((size_t)z * ny + y) * hx;
+    const V u = *reinterpret_cast<const V*>(u0 + row + i0);
+    const V f = *reinterpret_cast<const V*>(f0 + row + i0);
+    const int fyz = (y == 0) + (y + 1 == ny) + (z == 0) + (z + 1 == nz);
+    V out;
+#pragma unroll
+    for (int k = 0; k < VW; ++k)
+        out[k] = f[k] - ((T)diag.v[box_faces_vec<VW>(k, i0, hx, so, fyz)] * u[k] - s * nb[k]);
+    *reinterpret_cast<V*>(r0 + row + i0) = out;
+}
+
+template <typename T>
 void launch_resid_red_box(hipStream_t st, const T* u0, const T* u1, const T* f0, T* r0, int nx, int ny, int nz,
                           double s, const BoxCoef& diag, const Scalars* sc) {
+    constexpr int VW = BoxVec<T>::W;
+    if ((nx / 2) % VW == 0) {
+        const unsigned nv = (unsigned)(nx / 2 / VW) * ny * nz;
+        hipLaunchKernelGGL(k_resid_box_vec<T>, dim3(nblocks(nv)), dim3(kBlock), 0, st, u0, u1, f0, r0, nx, ny, nz,
+                           (T)s, diag, sc);
+        return;
+    }
     const unsigned nh = (unsigned)(nx / 2) * ny * nz;
     hipLaunchKernelGGL(k_resid_box<T>, dim3(nblocks(nh)), dim3(kBlock), 0, st, u0, u1, f0, r0, nx, ny, nz, (T)s, diag,
                        sc);
@@ -198,9 +317,86 @@ __global__ void __launch_bounds__(kBlock) k_restrict_box(const T* __restrict__ r
     }
 }
 
+// Four consecutive coarse cells X0 .. X0+3 per thread (needs (nx/2) % 4 == 0): per fine
+// row one 4-wide load of the red residual plus one edge value. In a row of red parity s0
+// the red fine cells of coarse X are 2X-1 (1/8) and 2X+1 (3/8) when s0 = 1, 2X (3/8) and
+// 2X+2 (1/8) when s0 = 0; beyond a face the edge value is zero, and the boundary fine cell
+// of a boundary coarse cell weighs 2/8.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_restrict_box4(const T* __restrict__ r0, int nx, int ny, int nz,
+                                                          T* __restrict__ cf0, T* __restrict__ cf1,
+                                                          T* __restrict__ cu0, int coarse_natural, BoxCoef inv_c,
+                                                          const Scalars* sc) {
+    if (sc && sc->done) return;
+    typedef T V4 __attribute__((ext_vector_type(4)));
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    const int cx = nx >> 1, cy = ny >> 1, cz = nz >> 1, cv = cx >> 2;
+    const unsigned n4 = (unsigned)cv * cy * cz;
+    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= n4) return;
+    const int v = idx % cv;
+    const unsigned t = idx / cv;
+    const int Y = t % cy, Z = t / cy;
+    const int hx = nx >> 1, X0 = 4 * v;
+    const T w0 = (T)0.125, w1 = (T)0.375, wb = (T)0.25;
+    T acc[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const T wz = box_rweight<T>(c, Z, nz);
+        if (wz == (T)0) continue;
+        const int z = 2 * Z - 1 + c;
+        T accb[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const T wy = box_rweight<T>(b, Y, ny);
+            if (wy == (T)0) continue;
+            const int y = 2 * Y - 1 + b;
+            const T* row = r0 + ((size_t)z * ny + y) * hx;
+            const int s0 = (y + z) & 1;
+            const V4 m = *reinterpret_cast<const V4*>(row + X0);
+            const T e = s0 ? (X0 > 0 ? row[X0 - 1] : (T)0) : (X0 + 4 < hx ? row[X0 + 4] : (T)0);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                T val;
+                if (s0) {
+                    const T wm = (X0 + k == cx - 1) ? wb : w1;  // fine 2X+1 = nx-1 is the boundary cell
+                    val = w0 * (k ? m[k - 1] : e) + wm * m[k];
+                } else {
+                    const T wm = (X0 + k == 0) ? wb : w1;  // fine 2X = 0 is the boundary cell
+                    val = wm * m[k] + w0 * (k < 3 ? m[k + 1] : e);
+                }
+                accb[k] += wy * val;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += wz * accb[k];
+    }
+    if (coarse_natural) {
+        *reinterpret_cast<V4*>(cf0 + ((size_t)Z * cy + Y) * cx + X0) = V4{acc[0], acc[1], acc[2], acc[3]};
+    } else {
+        const int pc = (Y + Z) & 1;  // coarse X0 is red when pc == 0
+        const size_t j = ((size_t)Z * cy + Y) * (cx >> 1) + (X0 >> 1);
+        const V2 red = pc ? V2{acc[1], acc[3]} : V2{acc[0], acc[2]};
+        const V2 blk = pc ? V2{acc[0], acc[2]} : V2{acc[1], acc[3]};
+        *reinterpret_cast<V2*>(cf0 + j) = red;
+        *reinterpret_cast<V2*>(cf1 + j) = blk;
+        const int fyz = (Y == 0) + (Y + 1 == cy) + (Z == 0) + (Z + 1 == cz);
+        const int xa = X0 + pc, xb = X0 + pc + 2;  // the two red coarse cells
+        const T ia = (T)inv_c.v[fyz + (xa == 0) + (xa == cx - 1)];
+        const T ib = (T)inv_c.v[fyz + (xb == 0) + (xb == cx - 1)];
+        *reinterpret_cast<V2*>(cu0 + j) = V2{red[0] * ia, red[1] * ib};
+    }
+}
+
 template <typename T>
 void launch_restrict_box(hipStream_t st, const T* r0, int nx, int ny, int nz, T* cf0, T* cf1, T* cu0,
                          int coarse_natural, const BoxCoef& inv_c, const Scalars* sc) {
+    if ((nx / 2) % 4 == 0) {
+        const unsigned n4 = (unsigned)(nx / 8) * (ny / 2) * (nz / 2);
+        hipLaunchKernelGGL(k_restrict_box4<T>, dim3(nblocks(n4)), dim3(kBlock), 0, st, r0, nx, ny, nz, cf0, cf1, cu0,
+                           coarse_natural, inv_c, sc);
+        return;
+    }
     const unsigned nc = (unsigned)(nx / 2) * (ny / 2) * (nz / 2);
     hipLaunchKernelGGL(k_restrict_box<T>, dim3(nblocks(nc)), dim3(kBlock), 0, st, r0, nx, ny, nz, cf0, cf1, cu0,
                        coarse_natural, inv_c, sc);
@@ -262,12 +458,235 @@ __global__ void __launch_bounds__(kBlock) k_prolong_red_box(const T* __restrict_
     u0[idx] += c0 * (b0 * v00 + b1 * v10) + c1 * (b0 * v01 + b1 * v11);
 }
 
+// Vector form: VW red cells of a split row per thread, one 16-byte read-modify-write of u0.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong_red_box_vec(const T* __restrict__ cu0, const T* __restrict__ cu1,
+                                                                int nat, T* __restrict__ u0, int nx, int ny, int nz,
+                                                                const Scalars* sc) {
+    if (sc && sc->done) return;
+    typedef typename BoxVec<T>::type V;
+    constexpr int VW = BoxVec<T>::W;
+    const int hx = nx >> 1, hv = hx / VW;
+    const unsigned nv = (unsigned)hv * ny * nz;
+    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= nv) return;
+    int iv, y, z;
+    split_pos(idx, hv, ny, iv, y, z);
+    const int i0 = iv * VW;
+    const int cx = nx >> 1, cy = ny >> 1, cz = nz >> 1;
+    const int s0 = (y + z) & 1;  // red cell x = 2i + s0: coarse parent i
+    int J0, J1, K0, K1;
+    T b0, b1, c0, c1;
+    box_pweights<T>(y, cy, J0, J1, b0, b1);
+    box_pweights<T>(z, cz, K0, K1, c0, c1);
+    const size_t row = ((size_t)z * ny + y) * hx;
+    V u = *reinterpret_cast<const V*>(u0 + row + i0);
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+        int I0, I1;
+        T a0, a1;
+        box_pweights<T>(2 * (i0 + k) + s0, cx, I0, I1, a0, a1);
+        auto line = [&](int J, int K) {
+            return a0 * box_coarse_at(cu0, cu1, nat, I0, J, K, cx, cy) +
+                   a1 * box_coarse_at(cu0, cu1, nat, I1, J, K, cx, cy);
+        };
+        const T v00 = line(J0, K0), v10 = line(J1, K0), v01 = line(J0, K1), v11 = line(J1, K1);
+        u[k] += c0 * (b0 * v00 + b1 * v10) + c1 * (b0 * v01 + b1 * v11);
+    }
+    *reinterpret_cast<V*>(u0 + row + i0) = u;
+}
+
 template <typename T>
 void launch_prolong_red_box(hipStream_t st, const T* cu0, const T* cu1, int coarse_natural, T* u0, int nx, int ny,
                             int nz, const Scalars* sc) {
+    constexpr int VW = BoxVec<T>::W;
+    if ((nx / 2) % VW == 0) {
+        const unsigned nv = (unsigned)(nx / 2 / VW) * ny * nz;
+        hipLaunchKernelGGL(k_prolong_red_box_vec<T>, dim3(nblocks(nv)), dim3(kBlock), 0, st, cu0, cu1, coarse_natural,
+                           u0, nx, ny, nz, sc);
+        return;
+    }
     const unsigned nh = (unsigned)(nx / 2) * ny * nz;
     hipLaunchKernelGGL(k_prolong_red_box<T>, dim3(nblocks(nh)), dim3(kBlock), 0, st, cu0, cu1, coarse_natural, u0, nx,
                        ny, nz, sc);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse tail of the box V-cycle: every level from t down in LDS of one work-group
+// (natural layout), the steps of the per-level box kernels in their order: zero
+// guess, R B R B pre-smoothing, red residual, restriction, the coarsest dense
+// solve, correction, B R B R post-smoothing. The per-cell diagonal is
+// alpha + s (6 + faces) = d.diag[l] + faces * s.
+namespace {
+
+__device__ __forceinline__ void tail_pos(int j, int na, int nb, int& a, int& b, int& c) {
+    a = j % na;
+    const int t = j / na;
+    b = t % nb;
+    c = t / nb;
+}
+
+template <typename T>
+__device__ __forceinline__ T tail_nb_box(const T* u, int x, int y, int z, int nx, int ny, int nz) {
+    const int row = (z * ny + y) * nx + x;
+    const int plane = nx * ny;
+    const T xm = x > 0 ? u[row - 1] : (T)0;
+    const T xp = x + 1 < nx ? u[row + 1] : (T)0;
+    const T ym = y > 0 ? u[row - nx] : (T)0;
+    const T yp = y + 1 < ny ? u[row + nx] : (T)0;
+    const T zm = z > 0 ? u[row - plane] : (T)0;
+    const T zp = z + 1 < nz ? u[row + plane] : (T)0;
+    return ((xm + xp) + (ym + yp)) + (zm + zp);
+}
+
+template <typename T>
+__device__ __forceinline__ void tail_gs_box(T* u, const T* f, int nx, int ny, int nz, int color, T s, T dg0) {
+    const int hx = nx >> 1, nh = hx * ny * nz;
+    for (int j = threadIdx.x; j < nh; j += blockDim.x) {
+        int i, y, z;
+        tail_pos(j, hx, ny, i, y, z);
+        const int x = 2 * i + ((y + z + color) & 1);
+        const int k = (z * ny + y) * nx + x;
+        const T dg = dg0 + (T)box_faces(x, y, z, nx, ny, nz) * s;
+        u[k] = (f[k] + s * tail_nb_box(u, x, y, z, nx, ny, nz)) / dg;
+    }
+    __syncthreads();
+}
+
+}  // namespace
+
+template <typename T>
+__global__ void __launch_bounds__(kFinBlock) k_tail_box(const T* __restrict__ f0g, const T* __restrict__ f1g,
+                                                        T* __restrict__ u0g, T* __restrict__ u1g, TailDesc d,
+                                                        const double* __restrict__ cinv, const Scalars* sc) {
+    if (sc && sc->done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    auto U_ = [&](int l) { return reinterpret_cast<T*>(smem + d.off_u[l]); };
+    auto F_ = [&](int l) { return reinterpret_cast<T*>(smem + d.off_f[l]); };
+    auto R_ = [&](int l) { return reinterpret_cast<T*>(smem + d.off_r[l]); };
+    const int L = d.nlev - 1;  // coarsest, natural, m cells
+    {
+        // split (red, black) global arrays of the first tail level -> natural LDS
+        const int nx = d.nx[0], ny = d.ny[0], hx = nx >> 1, nh = hx * ny * d.nz[0];
+        T* F0 = F_(0);
+        for (int j = threadIdx.x; j < nh; j += blockDim.x) {
+            int i, y, z;
+            tail_pos(j, hx, ny, i, y, z);
+            const int row = (z * ny + y) * nx, par = (y + z) & 1;
+            F0[row + 2 * i + par] = f0g[j];
+            F0[row + 2 * i + (par ^ 1)] = f1g[j];
+        }
+    }
+    __syncthreads();
+    for (int l = 0; l < L; ++l) {
+        const int nx = d.nx[l], ny = d.ny[l], nz = d.nz[l], n = nx * ny * nz;
+        T* U = U_(l);
+        T* F = F_(l);
+        T* R = R_(l);
+        const T s = (T)d.s[l], dg0 = (T)d.diag[l];
+        for (int j = threadIdx.x; j < n; j += blockDim.x) U[j] = (T)0;
+        __syncthreads();
+        tail_gs_box(U, F, nx, ny, nz, 0, s, dg0);
+        tail_gs_box(U, F, nx, ny, nz, 1, s, dg0);
+        tail_gs_box(U, F, nx, ny, nz, 0, s, dg0);
+        tail_gs_box(U, F, nx, ny, nz, 1, s, dg0);
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            int x, y, z;
+            tail_pos(j, nx, ny, x, y, z);
+            const T dg = dg0 + (T)box_faces(x, y, z, nx, ny, nz) * s;
+            R[j] = ((x + y + z) & 1) ? (T)0 : F[j] - (dg * U[j] - s * tail_nb_box(U, x, y, z, nx, ny, nz));
+        }
+        __syncthreads();
+        const int cx = nx >> 1, cy = ny >> 1, nc = cx * cy * (nz >> 1);
+        T* Fc = F_(l + 1);
+        for (int j = threadIdx.x; j < nc; j += blockDim.x) {
+            int X, Y, Z;
+            tail_pos(j, cx, cy, X, Y, Z);
+            T acc = 0;
+            for (int c = 0; c < 4; ++c) {
+                const T wz = box_rweight<T>(c, Z, nz);
+                if (wz == (T)0) continue;
+                T accb = 0;
+                for (int b = 0; b < 4; ++b) {
+                    const T wy = box_rweight<T>(b, Y, ny);
+                    if (wy == (T)0) continue;
+                    const T* rr = R + ((2 * Z - 1 + c) * ny + (2 * Y - 1 + b)) * nx;
+                    T acca = 0;
+                    for (int a = 0; a < 4; ++a) {
+                        const T wx = box_rweight<T>(a, X, nx);
+                        if (wx != (T)0) acca += wx * rr[2 * X - 1 + a];
+                    }
+                    accb += wy * acca;
+                }
+                acc += wz * accb;
+            }
+            Fc[j] = acc;
+        }
+        __syncthreads();
+    }
+    {
+        // one wave per row of the dense inverse
+        const T* Fl = F_(L);
+        T* Ul = U_(L);
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        for (int i = wv; i < d.m; i += nw) {
+            const double* row = cinv + (size_t)i * d.m;
+            double acc = 0.0;
+            for (int j = lane; j < d.m; j += 64) acc += row[j] * (double)Fl[j];
+            acc = wave_sum(acc);
+            if (lane == 0) Ul[i] = (T)acc;
+        }
+    }
+    __syncthreads();
+    for (int l = L - 1; l >= 0; --l) {
+        const int nx = d.nx[l], ny = d.ny[l], nz = d.nz[l], n = nx * ny * nz;
+        const int cx = nx >> 1, cy = ny >> 1, cz = nz >> 1;
+        const T* C = U_(l + 1);
+        T* U = U_(l);
+        const T* F = F_(l);
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            int x, y, z;
+            tail_pos(j, nx, ny, x, y, z);
+            int I0, I1, J0, J1, K0, K1;
+            T a0, a1, b0, b1, c0, c1;
+            box_pweights<T>(x, cx, I0, I1, a0, a1);
+            box_pweights<T>(y, cy, J0, J1, b0, b1);
+            box_pweights<T>(z, cz, K0, K1, c0, c1);
+            auto line = [&](int J, int K) {
+                const T* cr = C + (K * cy + J) * cx;
+                return a0 * cr[I0] + a1 * cr[I1];
+            };
+            U[j] += c0 * (b0 * line(J0, K0) + b1 * line(J1, K0)) + c1 * (b0 * line(J0, K1) + b1 * line(J1, K1));
+        }
+        __syncthreads();
+        const T s = (T)d.s[l], dg0 = (T)d.diag[l];
+        tail_gs_box(U, F, nx, ny, nz, 1, s, dg0);
+        tail_gs_box(U, F, nx, ny, nz, 0, s, dg0);
+        tail_gs_box(U, F, nx, ny, nz, 1, s, dg0);
+        tail_gs_box(U, F, nx, ny, nz, 0, s, dg0);
+    }
+    {
+        const int nx = d.nx[0], ny = d.ny[0], hx = nx >> 1, nh = hx * ny * d.nz[0];
+        const T* U0 = U_(0);
+        for (int j = threadIdx.x; j < nh; j += blockDim.x) {
+            int i, y, z;
+            tail_pos(j, hx, ny, i, y, z);
+            const int row = (z * ny + y) * nx, par = (y + z) & 1;
+            u0g[j] = U0[row + 2 * i + par];
+            u1g[j] = U0[row + 2 * i + (par ^ 1)];
+        }
+    }
+}
+
+template <typename T>
+void launch_tail_box(hipStream_t st, const T* f0, const T* f1, T* u0, T* u1, const TailDesc& d, const double* cinv,
+                     const Scalars* sc) {
+    hipLaunchKernelGGL(k_tail_box<T>, dim3(1), dim3(kFinBlock), d.lds_bytes, st, f0, f1, u0, u1, d, cinv, sc);
+}
+
+template <typename T>
+hipError_t tail_box_set_lds(size_t bytes) {
+    return hipFuncSetAttribute((const void*)k_tail_box<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 #define BRD_BOX_INST(T)                                                                                              \
@@ -279,7 +698,10 @@ void launch_prolong_red_box(hipStream_t st, const T* cu0, const T* cu1, int coar
                                           const BoxCoef&, const Scalars*);                                           \
     template void launch_restrict_box<T>(hipStream_t, const T*, int, int, int, T*, T*, T*, int, const BoxCoef&,      \
                                          const Scalars*);                                                            \
-    template void launch_prolong_red_box<T>(hipStream_t, const T*, const T*, int, T*, int, int, int, const Scalars*);
+    template void launch_prolong_red_box<T>(hipStream_t, const T*, const T*, int, T*, int, int, int, const Scalars*); \
+    template void launch_tail_box<T>(hipStream_t, const T*, const T*, T*, T*, const TailDesc&, const double*,       \
+                                     const Scalars*);                                                                \
+    template hipError_t tail_box_set_lds<T>(size_t);
 BRD_BOX_INST(float)
 BRD_BOX_INST(double)
 #undef BRD_BOX_INST

@@ -118,6 +118,12 @@ void launch_restrict_box(hipStream_t st, const T* r0, int nx, int ny, int nz, T*
 template <typename T>
 void launch_prolong_red_box(hipStream_t st, const T* cu0, const T* cu1, int coarse_natural, T* u0, int nx, int ny,
                             int nz, const Scalars* sc);
+// the box V-cycle below level t in one work-group (levels in LDS), as launch_tail
+template <typename T>
+void launch_tail_box(hipStream_t st, const T* f0, const T* f1, T* u0, T* u1, const TailDesc& d, const double* cinv,
+                     const Scalars* sc);
+template <typename T>
+hipError_t tail_box_set_lds(size_t bytes);
 
 template <typename T>
 void launch_tail(hipStream_t st, const T* f0, const T* f1, T* u0, T* u1, const TailDesc& d, const double* cinv,

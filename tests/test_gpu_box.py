@@ -133,6 +133,31 @@ def test_box_reactive_parity(dev, precision, alpha):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_box_ragged_rows(dev, precision):
+    """Rows whose half-length is not a multiple of the vector width (nx = 20: 10 split cells)
+    take the one-cell-per-thread kernels; the answer is the same."""
+    from paper_1306_3159_amd import FP64, MIXED, SOLVER_BLOCK
+    rng = np.random.default_rng(1306_509)
+    shape = (16, 16, 20)  # (nz, ny, nx): levels 20x16x16 -> 10x8x8 -> 5x4x4 (coarsest)
+    N = 6
+    q = inner_blobs(rng, shape, N)
+    kappa = 10 ** rng.uniform(-1, 2, N)
+    f = 1.0 + 0.5 * rng.standard_normal(shape)
+    prec = FP64 if precision == "fp64" else MIXED
+    _say("box ragged", precision)
+    S = box(dev, shape, q, kappa, precision=prec, rtol=1e-10, saddle_solver=SOLVER_BLOCK)
+    c, st = S.solve_reactive(T(f, dev), alpha=0.2)
+    assert st["rc"] == 0, st
+    cr, _ = dr.solve_reactive_box(f, q, kappa, 0.2, CB)
+    assert rel(H(c), cr) < 1e-8
+    c, lam, st = S.solve_absorbing(T(f, dev))
+    assert st["rc"] == 0, st
+    cr, lr = dr.solve_absorbing_box(f, q, 0.0, CB)
+    assert rel(H(c), cr) < 1e-8 and rel(H(lam), lr) < 1e-8
+    S.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("alpha", [0.0, 0.4])
 def test_box_absorbing_parity(dev, precision, alpha):
     from paper_1306_3159_amd import FP64, MIXED, SOLVER_BLOCK
