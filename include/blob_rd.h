@@ -128,7 +128,8 @@ size_t blob_rd_workspace_bytes(const blob_rd_params* p);
  * the workspace, so the caller may free them afterwards. The workspace must
  * stay valid until blob_rd_destroy. Errors: EINVAL (dims < 8, a level that
  * cannot coarsen to <= 512 cells, kernel_w not 3/4, h or D not positive,
- * N < 0), ENOMEM (workspace too small), EDEVICE. */
+ * N < 0, an unknown boundary, a non-finite boundary_value, a blob closer than
+ * 3h to a face of a Dirichlet box), ENOMEM (workspace too small), EDEVICE. */
 int blob_rd_create(const blob_rd_params* p, blob_rd_t* out);
 
 /* Release the host handle (the caller frees the workspace). NULL is accepted. */

@@ -519,12 +519,28 @@ void launch_prolong_red_box(hipStream_t st, const T* cu0, const T* cu1, int coar
 // alpha + s (6 + faces) = d.diag[l] + faces * s.
 namespace {
 
-__device__ __forceinline__ void tail_pos(int j, int na, int nb, int& a, int& b, int& c) {
-    a = j % na;
-    const int t = j / na;
-    b = t % nb;
-    c = t / nb;
-}
+// j -> (a, b, c) for row-major dims (na, nb, *); shifts and masks when both are powers of two
+struct TailPos {
+    int na, nb, la, lab;
+    bool p2;
+    __device__ __forceinline__ TailPos(int a, int b) : na(a), nb(b) {
+        p2 = ((a & (a - 1)) == 0) && ((b & (b - 1)) == 0);
+        la = __ffs(a) - 1;
+        lab = la + __ffs(b) - 1;
+    }
+    __device__ __forceinline__ void operator()(int j, int& a, int& b, int& c) const {
+        if (p2) {
+            a = j & (na - 1);
+            b = (j >> la) & (nb - 1);
+            c = j >> lab;
+        } else {
+            a = j % na;
+            const int t = j / na;
+            b = t % nb;
+            c = t / nb;
+        }
+    }
+};
 
 template <typename T>
 __device__ __forceinline__ T tail_nb_box(const T* u, int x, int y, int z, int nx, int ny, int nz) {
@@ -539,16 +555,26 @@ __device__ __forceinline__ T tail_nb_box(const T* u, int x, int y, int z, int nx
     return ((xm + xp) + (ym + yp)) + (zm + zp);
 }
 
+// inverse diagonals of a level for 0..3 faces, selected without a runtime-indexed array
 template <typename T>
-__device__ __forceinline__ void tail_gs_box(T* u, const T* f, int nx, int ny, int nz, int color, T s, T dg0) {
+struct TailInv {
+    T i0, i1, i2, i3;
+    __device__ __forceinline__ TailInv(T dg0, T s)
+        : i0((T)1 / dg0), i1((T)1 / (dg0 + s)), i2((T)1 / (dg0 + 2 * s)), i3((T)1 / (dg0 + 3 * s)) {}
+    __device__ __forceinline__ T operator()(int f) const { return f == 0 ? i0 : (f == 1 ? i1 : (f == 2 ? i2 : i3)); }
+};
+
+template <typename T>
+__device__ __forceinline__ void tail_gs_box(T* u, const T* f, int nx, int ny, int nz, int color, T s,
+                                            const TailInv<T>& inv) {
     const int hx = nx >> 1, nh = hx * ny * nz;
+    const TailPos dec(hx, ny);
     for (int j = threadIdx.x; j < nh; j += blockDim.x) {
         int i, y, z;
-        tail_pos(j, hx, ny, i, y, z);
+        dec(j, i, y, z);
         const int x = 2 * i + ((y + z + color) & 1);
         const int k = (z * ny + y) * nx + x;
-        const T dg = dg0 + (T)box_faces(x, y, z, nx, ny, nz) * s;
-        u[k] = (f[k] + s * tail_nb_box(u, x, y, z, nx, ny, nz)) / dg;
+        u[k] = (f[k] + s * tail_nb_box(u, x, y, z, nx, ny, nz)) * inv(box_faces(x, y, z, nx, ny, nz));
     }
     __syncthreads();
 }
@@ -569,9 +595,10 @@ __global__ void __launch_bounds__(kFinBlock) k_tail_box(const T* __restrict__ f0
         // split (red, black) global arrays of the first tail level -> natural LDS
         const int nx = d.nx[0], ny = d.ny[0], hx = nx >> 1, nh = hx * ny * d.nz[0];
         T* F0 = F_(0);
+        const TailPos dec(hx, ny);
         for (int j = threadIdx.x; j < nh; j += blockDim.x) {
             int i, y, z;
-            tail_pos(j, hx, ny, i, y, z);
+            dec(j, i, y, z);
             const int row = (z * ny + y) * nx, par = (y + z) & 1;
             F0[row + 2 * i + par] = f0g[j];
             F0[row + 2 * i + (par ^ 1)] = f1g[j];
@@ -584,34 +611,40 @@ __global__ void __launch_bounds__(kFinBlock) k_tail_box(const T* __restrict__ f0
         T* F = F_(l);
         T* R = R_(l);
         const T s = (T)d.s[l], dg0 = (T)d.diag[l];
+        const TailInv<T> inv(dg0, s);
         for (int j = threadIdx.x; j < n; j += blockDim.x) U[j] = (T)0;
         __syncthreads();
-        tail_gs_box(U, F, nx, ny, nz, 0, s, dg0);
-        tail_gs_box(U, F, nx, ny, nz, 1, s, dg0);
-        tail_gs_box(U, F, nx, ny, nz, 0, s, dg0);
-        tail_gs_box(U, F, nx, ny, nz, 1, s, dg0);
+        tail_gs_box(U, F, nx, ny, nz, 0, s, inv);
+        tail_gs_box(U, F, nx, ny, nz, 1, s, inv);
+        tail_gs_box(U, F, nx, ny, nz, 0, s, inv);
+        tail_gs_box(U, F, nx, ny, nz, 1, s, inv);
+        const TailPos dec(nx, ny);
         for (int j = threadIdx.x; j < n; j += blockDim.x) {
             int x, y, z;
-            tail_pos(j, nx, ny, x, y, z);
+            dec(j, x, y, z);
             const T dg = dg0 + (T)box_faces(x, y, z, nx, ny, nz) * s;
             R[j] = ((x + y + z) & 1) ? (T)0 : F[j] - (dg * U[j] - s * tail_nb_box(U, x, y, z, nx, ny, nz));
         }
         __syncthreads();
         const int cx = nx >> 1, cy = ny >> 1, nc = cx * cy * (nz >> 1);
         T* Fc = F_(l + 1);
+        const TailPos cdec(cx, cy);
         for (int j = threadIdx.x; j < nc; j += blockDim.x) {
             int X, Y, Z;
-            tail_pos(j, cx, cy, X, Y, Z);
+            cdec(j, X, Y, Z);
             T acc = 0;
+#pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const T wz = box_rweight<T>(c, Z, nz);
                 if (wz == (T)0) continue;
                 T accb = 0;
+#pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const T wy = box_rweight<T>(b, Y, ny);
                     if (wy == (T)0) continue;
                     const T* rr = R + ((2 * Z - 1 + c) * ny + (2 * Y - 1 + b)) * nx;
                     T acca = 0;
+#pragma unroll
                     for (int a = 0; a < 4; ++a) {
                         const T wx = box_rweight<T>(a, X, nx);
                         if (wx != (T)0) acca += wx * rr[2 * X - 1 + a];
@@ -644,9 +677,10 @@ __global__ void __launch_bounds__(kFinBlock) k_tail_box(const T* __restrict__ f0
         const T* C = U_(l + 1);
         T* U = U_(l);
         const T* F = F_(l);
+        const TailPos dec(nx, ny);
         for (int j = threadIdx.x; j < n; j += blockDim.x) {
             int x, y, z;
-            tail_pos(j, nx, ny, x, y, z);
+            dec(j, x, y, z);
             int I0, I1, J0, J1, K0, K1;
             T a0, a1, b0, b1, c0, c1;
             box_pweights<T>(x, cx, I0, I1, a0, a1);
@@ -659,18 +693,20 @@ __global__ void __launch_bounds__(kFinBlock) k_tail_box(const T* __restrict__ f0
             U[j] += c0 * (b0 * line(J0, K0) + b1 * line(J1, K0)) + c1 * (b0 * line(J0, K1) + b1 * line(J1, K1));
         }
         __syncthreads();
-        const T s = (T)d.s[l], dg0 = (T)d.diag[l];
-        tail_gs_box(U, F, nx, ny, nz, 1, s, dg0);
-        tail_gs_box(U, F, nx, ny, nz, 0, s, dg0);
-        tail_gs_box(U, F, nx, ny, nz, 1, s, dg0);
-        tail_gs_box(U, F, nx, ny, nz, 0, s, dg0);
+        const T s = (T)d.s[l];
+        const TailInv<T> inv((T)d.diag[l], s);
+        tail_gs_box(U, F, nx, ny, nz, 1, s, inv);
+        tail_gs_box(U, F, nx, ny, nz, 0, s, inv);
+        tail_gs_box(U, F, nx, ny, nz, 1, s, inv);
+        tail_gs_box(U, F, nx, ny, nz, 0, s, inv);
     }
     {
         const int nx = d.nx[0], ny = d.ny[0], hx = nx >> 1, nh = hx * ny * d.nz[0];
         const T* U0 = U_(0);
+        const TailPos dec(hx, ny);
         for (int j = threadIdx.x; j < nh; j += blockDim.x) {
             int i, y, z;
-            tail_pos(j, hx, ny, i, y, z);
+            dec(j, i, y, z);
             const int row = (z * ny + y) * nx, par = (y + z) & 1;
             u0g[j] = U0[row + 2 * i + par];
             u1g[j] = U0[row + 2 * i + (par ^ 1)];
