@@ -12,9 +12,10 @@ of blobs with spacing L h) with the library and reduces the answer by the paper'
 
 Sweeps: the radius at a grid node against box size (Fig. ReactionRadius left), its variation
 as the blob moves off the node (right), beta_0 of cubic arrays against the fit eq.
-beta_cubic, Omega(P) and beta_P at finite P (Figs. finite_P_fit, finite_P_01), and the
+beta_cubic, Omega(P) and beta_P at finite P (Figs. finite_P_fit, finite_P_01), the
 iteration counts of the reactive steady solve of (L/4)^3 lattices against P~ (Fig.
-NonSaddleGMRES; the curves are not printed, so only the counts are reported).
+NonSaddleGMRES; the curves are not printed, so only the counts are reported), and the far
+field of one absorbing blob in a box held at c_inf (Fig. FarFieldDecay, eq. c_r_approx).
 
 Run: python -m paper_1306_3159_amd.sweeps --out results.json
 """
@@ -23,13 +24,15 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
+import sys
 import time
 from typing import Dict, List, Sequence
 
 import numpy as np
 import torch
 
-from .native import BlobRD, FP64, MIXED, SOLVER_BLOCK
+from .native import BlobRD, FP64, MIXED, SOLVER_BLOCK, BOUNDARY_DIRICHLET
 
 # Values the paper prints (Sec. IV.A, IV.B).
 PAPER = {"radius_node_w4": 1.27, "radius_node_w3": 0.885, "radius_average_w4": 1.255,
@@ -171,25 +174,145 @@ def sweep_reactive_convergence(dev, Ls: Sequence[int] = (32, 64, 128),
     return out
 
 
+def _lattice(L: int, spacing: float, offset: float) -> np.ndarray:
+    pts = np.arange(offset, L, spacing)
+    return np.stack(np.meshgrid(pts, pts, pts, indexing="ij"), -1).reshape(-1, 3)
+
+
+def _saddle_case(dev, L: int, q: np.ndarray, f: torch.Tensor, alpha: float, runs) -> dict:
+    """Solve one saddle point (eq. saddle_point) by each (name, kind, m, restart) of `runs` with the block
+    FGMRES (n = 1, FP64 cycles), and by the Schur-complement GMRES of the other layout."""
+    qt = torch.tensor(q, device=dev)
+    out = {"L": L, "blobs": int(q.shape[0]), "alpha": alpha}
+    S = BlobRD(L, qt, precision=FP64, rtol=1e-8, max_iter=4000, gmres_restart=30)
+    for name, kind, m, restart in runs:
+        t0 = time.perf_counter()
+        c, lam, st = S.solve_absorbing_fgmres(f, alpha=alpha, precond=kind, m=m, n=1, restart=restart, maxit=4000)
+        torch.cuda.synchronize()
+        out[name] = {"fgmres_iters": st["outer_iters"], "vcycles": st["vcycles"], "rel_resid": st["rel_resid"],
+                     "rc": st["rc"], "seconds": time.perf_counter() - t0}
+        print(f"[sweep]   L={L} N={q.shape[0]} alpha={alpha:g} {name}: {out[name]}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    c, lam, st = S.solve_absorbing(f, alpha=alpha)
+    torch.cuda.synchronize()
+    out["schur_gmres"] = {"gmres_iters": st["outer_iters"], "inner_cg_iters": st["inner_iters_total"],
+                          "vcycles": st["vcycles"], "rel_resid": st["rel_resid"], "rc": st["rc"],
+                          "seconds": time.perf_counter() - t0}
+    print(f"[sweep]   L={L} schur_gmres: {out['schur_gmres']}", file=sys.stderr, flush=True)
+    S.close()
+    return out
+
+
+def sweep_block_preconditioners(dev, Ls: Sequence[int] = (16, 32, 64, 128), m_L: int = 16,
+                                ms: Sequence[int] = (1, 2, 3, 5, 8, 12, 16),
+                                fixed_Ls: Sequence[int] = (16, 32, 64, 128, 256)) -> dict:
+    """Figs. DiagonalScaling, InexactSchur, FixedNScaling (E4-E6): the block FGMRES with the diagonal
+    preconditioner (n = 1, restart 200) and the approximate Schur complement (m = 5, n = 1, restart
+    30) on periodic cubic arrays of absorbing blobs 4 cells apart ((L/4)^3 blobs, four-point kernel)
+    with A = L^-2 I - L, beside the Schur-complement GMRES of the other layout; the approximate
+    Schur complement with A = -L (null space handled as in the appendix); the m study at 16^3; and
+    a fixed 64 = 4^3 blobs as L grows. The paper does not state the right-hand side: the source
+    is f = 1 + 0.5 N(0, 1) (seeded), since a uniform source on a symmetric lattice excites only
+    lattice-periodic modes. V-cycles count every multigrid cycle (m + 2n per outer iteration)."""
+    runs = [("diagonal", "diagonal", 0, 200), ("approx_schur", "schur", 5, 30)]
+    res = {"size": [], "singular": [], "m_study": None, "fixed_N": []}
+    for L in Ls:
+        rng = np.random.default_rng(1306_600 + L)
+        f = torch.tensor(1.0 + 0.5 * rng.standard_normal((L, L, L)), device=dev)
+        q = _lattice(L, 4.0, 2.0)
+        res["size"].append(_saddle_case(dev, L, q, f, 1.0 / L ** 2, runs))
+        res["singular"].append(_saddle_case(dev, L, q, f, 0.0, [("approx_schur", "schur", 5, 30)]))
+        print(f"[sweep] block preconditioners L={L}", file=sys.stderr, flush=True)
+    rng = np.random.default_rng(1306_600 + m_L)
+    f = torch.tensor(1.0 + 0.5 * rng.standard_normal((m_L, m_L, m_L)), device=dev)
+    res["m_study"] = _saddle_case(dev, m_L, _lattice(m_L, 4.0, 2.0), f, 1.0 / m_L ** 2,
+                                  [(f"m{m}", "schur", m, 30) for m in ms])
+    for L in fixed_Ls:
+        rng = np.random.default_rng(1306_700 + L)
+        f = torch.tensor(1.0 + 0.5 * rng.standard_normal((L, L, L)), device=dev)
+        res["fixed_N"].append(_saddle_case(dev, L, _lattice(L, L / 4.0, L / 8.0), f, 1.0 / L ** 2, runs))
+        print(f"[sweep] fixed N L={L}", file=sys.stderr, flush=True)
+    return res
+
+
+def far_field_law(r, L: float, a: float):
+    """eq. c_r_approx: c(r)/c_inf ~ L/(L - 2a) (1 - a/r), the spherical problem with c(a) = 0 and
+    c(L/2) = c_inf."""
+    return L / (L - 2.0 * a) * (1.0 - a / np.asarray(r, dtype=np.float64))
+
+
+def sweep_far_field(dev, n: int = 96, w: int = 4, rmax_frac: float = 0.25) -> dict:
+    """Fig. FarFieldDecay (E9): one absorbing blob at the centre node of an n^3 box held at
+    c_inf = 1, no source (the paper's box has 100 cells per edge; the multigrid here needs an
+    edge of the form 2^k times a small factor). Returns c along the +x axis and the (1,1,1)
+    diagonal from the blob, the law with the position-averaged radius 1.255 h, the largest
+    relative deviation from it for 3h <= r <= rmax_frac * n, and the radius a of a least-squares
+    fit of c = A (1 - a/r) over the same range."""
+    q = np.array([[n / 2.0] * 3])
+    S = BlobRD(n, torch.tensor(q, device=dev), kernel_w=w, precision=FP64, rtol=1e-10, saddle_solver=SOLVER_BLOCK,
+               boundary=BOUNDARY_DIRICHLET, boundary_value=1.0)
+    c, lam, st = S.solve_absorbing(torch.zeros((n, n, n), dtype=torch.float64, device=dev))
+    if st["rc"] < 0 or st["rel_resid"] > 1e-8:
+        raise RuntimeError(f"solve did not converge: {st}")
+    ch = c.cpu().numpy()
+    S.close()
+    k0 = n // 2  # cell centres k + 1/2: cell k0 sits half a cell from the blob along each axis
+    ks = np.arange(k0, n)
+    r_axis = np.sqrt((ks + 0.5 - n / 2.0) ** 2 + 2 * 0.25)
+    c_axis = ch[k0, k0, ks]
+    r_diag = np.sqrt(3.0) * (ks + 0.5 - n / 2.0)
+    c_diag = ch[ks, ks, ks]
+    a_paper = PAPER["radius_average_w4"] if w == 4 else PAPER["radius_node_w3"]
+    r = np.concatenate([r_axis, r_diag])
+    cv = np.concatenate([c_axis, c_diag])
+    sel = (r >= 3.0) & (r <= rmax_frac * n)
+    dev_rel = float(np.max(np.abs(cv[sel] / far_field_law(r[sel], n, a_paper) - 1.0)))
+    M = np.stack([np.ones(int(sel.sum())), -1.0 / r[sel]], 1)
+    (A, Aa), *_ = np.linalg.lstsq(M, cv[sel], rcond=None)
+    return {"n": n, "w": w, "lambda": float(lam[0]), "r_axis": r_axis.tolist(), "c_axis": c_axis.tolist(),
+            "r_diag": r_diag.tolist(), "c_diag": c_diag.tolist(), "a_paper": a_paper,
+            "max_rel_dev_from_law": dev_rel, "fit_A": float(A), "fit_a": float(Aa / A),
+            "fit_range": [3.0, rmax_frac * n]}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None)
     ap.add_argument("--quick", action="store_true", help="small sizes only")
+    ap.add_argument("--only", default=None,
+                    help="run one sweep (a result key) and replace that key in the --out file if it exists")
     args = ap.parse_args(argv)
     dev = torch.device("cuda:0")
     t0 = time.time()
     q = args.quick
-    res = {
-        "radius_node_w4": sweep_radius_node(dev, (16, 32) if q else (16, 32, 64, 128, 256), 4),
-        "radius_node_w3": sweep_radius_node(dev, (16, 32) if q else (16, 32, 64, 128, 256), 3),
-        "translation_w4": sweep_translation(dev, 32 if q else 128, 4),
-        "translation_w3": sweep_translation(dev, 32 if q else 128, 3),
-        "beta0_cubic": sweep_beta0_cubic(dev, (8, 16) if q else (8, 10, 12, 16, 24, 32, 64)),
-        "finite_P": sweep_finite_P(dev, 16 if q else 32),
-        "reactive_convergence": sweep_reactive_convergence(dev, (32,) if q else (32, 64, 128)),
-        "paper": PAPER,
+    sweeps = {
+        "radius_node_w4": lambda: sweep_radius_node(dev, (16, 32) if q else (16, 32, 64, 128, 256), 4),
+        "radius_node_w3": lambda: sweep_radius_node(dev, (16, 32) if q else (16, 32, 64, 128, 256), 3),
+        "translation_w4": lambda: sweep_translation(dev, 32 if q else 128, 4),
+        "translation_w3": lambda: sweep_translation(dev, 32 if q else 128, 3),
+        "beta0_cubic": lambda: sweep_beta0_cubic(dev, (8, 16) if q else (8, 10, 12, 16, 24, 32, 64)),
+        "finite_P": lambda: sweep_finite_P(dev, 16 if q else 32),
+        "reactive_convergence": lambda: sweep_reactive_convergence(dev, (32,) if q else (32, 64, 128)),
+        "far_field_w4": lambda: sweep_far_field(dev, 48 if q else 96, 4),
+        "block_preconditioners": lambda: sweep_block_preconditioners(
+            dev, (16, 32) if q else (16, 32, 64, 128), 16, (1, 3, 5, 8) if q else (1, 2, 3, 5, 8, 12, 16),
+            (16, 32) if q else (16, 32, 64, 128, 256)),
     }
-    res["seconds"] = time.time() - t0
+    if args.only is not None and args.only not in sweeps:
+        raise SystemExit(f"--only must be one of {sorted(sweeps)}")
+    res = {}
+    if args.only and args.out and os.path.exists(args.out):
+        with open(args.out) as fh:
+            res = json.load(fh)
+    for key, fn in sweeps.items():
+        if args.only and key != args.only:
+            continue
+        t1 = time.time()
+        res[key] = fn()
+        print(f"[sweep] {key} {time.time() - t1:.1f} s", file=sys.stderr, flush=True)
+    res["paper"] = PAPER
+    if not args.only:
+        res["seconds"] = time.time() - t0
     txt = json.dumps(res, indent=1)
     if args.out:
         with open(args.out, "w") as fh:

@@ -280,3 +280,44 @@ def test_box_kernel_timing(dev):
     ms, by = S.time_kernel("gs", reps=3, cold=True)
     assert ms > 0.0 and by == pytest.approx(n * 0.5 * 4 * 3)
     S.close()
+
+
+def test_box_in_batches(dev):
+    """Box handles in a lock-step batch run on their own streams (the batched kernels are the
+    periodic ones) and return what they return alone; the periodic member is unaffected."""
+    from paper_1306_3159_amd import BlobRD, MIXED, SOLVER_BLOCK, solve_batched
+    rng = np.random.default_rng(1306_510)
+    shape = (32, 32, 32)
+    qb = inner_blobs(rng, shape, 10)
+    kb = 10 ** rng.uniform(-1, 2, 10)
+    qp = rng.uniform(0, 32, (10, 3))
+    kp = 10 ** rng.uniform(-1, 2, 10)
+    f = 1.0 + 0.5 * rng.standard_normal(shape)
+    st = [torch.cuda.Stream(dev) for _ in range(3)]
+    mk = [lambda s: box(dev, 32, qb, kb, precision=MIXED, rtol=1e-10, stream=s),
+          lambda s: box(dev, 32, qb, precision=MIXED, rtol=1e-10, saddle_solver=SOLVER_BLOCK, stream=s),
+          lambda s: BlobRD(32, T(qp, dev), T(kp, dev), precision=MIXED, rtol=1e-10, stream=s)]
+    kinds = [0, 1, 0]
+    _say("box in batches")
+    solo = []
+    for i in range(3):
+        S = mk[i](None)  # alone, on the current stream
+        if kinds[i] == 0:
+            c, _ = S.solve_reactive(T(f, dev))
+            solo.append((H(c), None))
+        else:
+            c, lam, _ = S.solve_absorbing(T(f, dev))
+            solo.append((H(c), H(lam)))
+        S.close()
+    Ss = [mk[i](st[i]) for i in range(3)]
+    cs = [torch.zeros(shape, dtype=torch.float64, device=dev) for _ in range(3)]
+    lams = [None, torch.zeros(10, dtype=torch.float64, device=dev), None]
+    rc, stats = solve_batched(Ss, kinds, [T(f, dev)] * 3, cs, lams, lockstep_max_cells=64 ** 3)
+    assert rc == 0, stats
+    for i in range(3):
+        assert np.array_equal(H(cs[i]), solo[i][0]), i
+    assert np.array_equal(H(lams[1]), solo[1][1])
+    cr, _ = dr.solve_reactive_box(f, qb, kb, 0.0, CB)
+    assert rel(H(cs[0]), cr) < 1e-8
+    for S in Ss:
+        S.close()
