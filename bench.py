@@ -357,6 +357,23 @@ def main():
             "sample": f"{k} oracle MG-CG Poisson solves on the same grid (rtol 5e-10, {tp:.2f} s each), scaled by "
                       f"{n_poisson} Poisson solves per absorbing solve ({per_solve} Schur GMRES products + 2); "
                       f"{it.num_threads()} OpenMP threads of {os.cpu_count()} logical CPUs, {cpu}"}
+        # one core: the same right-hand side's oracle V-cycle timed on one thread and on all of
+        # them; the one-core rate is the all-thread rate scaled by their ratio
+        nt = it.num_threads()
+
+        def vtime():
+            t1 = time.perf_counter()
+            it.vcycle(g, 0.0)
+            return time.perf_counter() - t1
+
+        tv_all = min(vtime(), vtime())
+        it.set_num_threads(1)
+        tv_one = vtime()
+        it.set_num_threads(nt)
+        out["cpu_baseline"]["single_core"] = {
+            "value": out["cpu_baseline"]["value"] * tv_all / tv_one, "unit": "solves/s", "cores": 1,
+            "sample": f"one oracle V-cycle on the same grid on 1 thread ({tv_one:.2f} s) and on {nt} "
+                      f"({tv_all:.2f} s); the {nt}-thread rate scaled by that ratio"}
     if args.copy_probe:
         src = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

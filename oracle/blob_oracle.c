@@ -778,3 +778,13 @@ int ora_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Set the number of OpenMP threads of later calls (no effect without OpenMP). */
+void ora_set_num_threads(int n) {
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -73,6 +73,8 @@ def lib():
         L.ora_solve_absorbing.argtypes = [P, d, dp, dp, dp, d, d, i, i, ctypes.POINTER(Stats)]
         L.ora_solve_absorbing.restype = i
         L.ora_num_threads.restype = i
+        L.ora_set_num_threads.argtypes = [i]
+        L.ora_set_num_threads.restype = None
         L.ora_solve_poisson.argtypes = [P, d, dp, dp, d, i, ctypes.POINTER(Stats)]
         L.ora_solve_poisson.restype = i
         _lib = L
@@ -235,6 +237,11 @@ def step_absorbing(c, f, q, dt, D=1.0, h=1.0, w=4, rtol=1e-10, inner_rtol=1e-12,
 
 def num_threads() -> int:
     return int(lib().ora_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of later oracle calls (OpenMP; no effect in a build without it)."""
+    lib().ora_set_num_threads(int(n))
 
 
 def solve_poisson(g, alpha, D=1.0, h=1.0, rtol=1e-10, maxit=500):

@@ -321,3 +321,29 @@ def test_box_in_batches(dev):
     assert rel(H(cs[0]), cr) < 1e-8
     for S in Ss:
         S.close()
+
+
+@pytest.mark.parametrize("w", [3, 4])
+def test_box_scaled_units_and_kernels(dev, w):
+    """h, D != 1 and both kernels: the lifted solves scale like the oracle's (positions in
+    physical units, at least 3h inside each face); the learned handle option falls back to the
+    plain inner iteration in a box."""
+    from paper_1306_3159_amd import FP64, SOLVER_BLOCK_LEARNED
+    rng = np.random.default_rng(1306_511 + w)
+    h, D = 0.5, 2.5
+    N = 7
+    q = h * inner_blobs(rng, SHAPE, N)
+    kappa = 10 ** rng.uniform(-1, 2, N)
+    f = 1.0 + 0.5 * rng.standard_normal(SHAPE)
+    _say("box units", w)
+    S = box(dev, SHAPE, q, kappa, h=h, D=D, kernel_w=w, precision=FP64, rtol=1e-10,
+            saddle_solver=SOLVER_BLOCK_LEARNED)
+    c, st = S.solve_reactive(T(f, dev), alpha=0.3)
+    assert st["rc"] == 0, st
+    cr, _ = dr.solve_reactive_box(f, q, kappa, 0.3, CB, D=D, h=h, w=w)
+    assert rel(H(c), cr) < 1e-8
+    c, lam, st = S.solve_absorbing(T(f, dev))
+    assert st["rc"] == 0, st
+    cr, lr = dr.solve_absorbing_box(f, q, 0.0, CB, D=D, h=h, w=w)
+    assert rel(H(c), cr) < 1e-8 and rel(H(lam), lr) < 1e-8
+    S.close()
