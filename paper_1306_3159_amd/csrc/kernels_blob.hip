@@ -514,10 +514,31 @@ template void launch_zero<double>(hipStream_t, double*, size_t);
 // N-vector kernels: one work-group of kFinBlock threads, fixed reduction order.
 
 __global__ void __launch_bounds__(kFinBlock) k_nvec_project(double* v, int N) {
+    constexpr int R = 12;  // values held per thread when N <= R * blockDim.x
+    const int bd = (int)blockDim.x;
+    if (N <= R * bd) {
+        // every load issued before the first use: one memory latency, not N / blockDim.x
+        double r[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const int i = threadIdx.x + c * bd;
+            r[c] = i < N ? v[i] : 0.0;
+        }
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < R; ++c) s += r[c];
+        const double m = wg_sum(s) / (double)N;
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const int i = threadIdx.x + c * bd;
+            if (i < N) v[i] = r[c] - m;
+        }
+        return;
+    }
     double s = 0.0;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) s += v[i];
+    for (int i = threadIdx.x; i < N; i += bd) s += v[i];
     const double m = wg_sum(s) / (double)N;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) v[i] -= m;
+    for (int i = threadIdx.x; i < N; i += bd) v[i] -= m;
 }
 
 void launch_nvec_project(hipStream_t st, double* v, int N) {

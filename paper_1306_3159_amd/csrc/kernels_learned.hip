@@ -342,8 +342,16 @@ __global__ void __launch_bounds__(kBlock) k_spmv_centered(const int* __restrict_
                                                           const double* __restrict__ x, double* __restrict__ y,
                                                           int N) {
     __shared__ double sh[kBlock / 64];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) s += x[i];
+    // the block's copy of mean(x): eight independent partial sums keep eight loads in flight
+    double p[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int bd = (int)blockDim.x;
+    int i0 = threadIdx.x;
+    for (; i0 + 7 * bd < N; i0 += 8 * bd) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p[u] += x[i0 + u * bd];
+    }
+    for (; i0 < N; i0 += bd) p[0] += x[i0];
+    double s = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
     __syncthreads();
