@@ -1283,10 +1283,9 @@ void fg_resid(blob_rd* H, double alpha, const double* base, const SpreadMult* M,
               double* q) {
     const Plan& P = H->P;
     const LevelDims& d = P.lev[0];
-    launch_applyA_plain(H->st, x, q, alpha, H->prm.D / (d.h * d.h), d.nx, d.ny, d.nz, H->box);
-    launch_axpby(H->st, q, base, P.ncell, -1.0, 1.0);
+    launch_residA_plain(H->st, base, x, q, alpha, H->prm.D / (d.h * d.h), d.nx, d.ny, d.nz, H->box);
     if (M) launch_spread_sparse(H->st, spread_lists(H), *M, q, q, scale, nullptr);
-    H->alg_bytes += (double)P.ncell * (16 + 24);
+    H->alg_bytes += (double)P.ncell * 24;
 }
 
 // n multigrid cycles for A x = r, r = base + scale S m (M null: r = base), as a

@@ -72,7 +72,8 @@ typedef double double2_t __attribute__((ext_vector_type(2)));
 // partials (p.q, sum q). Same arithmetic and summation order as stencil_A.
 template <bool BOX>
 __device__ __forceinline__ void applyA2_body(const double* __restrict__ p, double* __restrict__ q, double alpha,
-                                             double s, int nx, int ny, int nz, unsigned npair, double* part, Blk blk) {
+                                             double s, int nx, int ny, int nz, unsigned npair, double* part, Blk blk,
+                                             const double* __restrict__ base = nullptr) {
     unsigned lo, hi;
     chunk_of(xcd_block(blk.b, blk.nb), blk.nb, npair, &lo, &hi);
     double v[2] = {0.0, 0.0};
@@ -104,6 +105,11 @@ __device__ __forceinline__ void applyA2_body(const double* __restrict__ p, doubl
         double2_t y;
         y[0] = alpha * c[0] - s * ((xl + c[1]) + (ym[0] + yp[0]) + (zm[0] + zp[0]) - 6.0 * c[0]);
         y[1] = alpha * c[1] - s * ((c[0] + xr) + (ym[1] + yp[1]) + (zm[1] + zp[1]) - 6.0 * c[1]);
+        if (base) {  // residual form q = base - A p
+            const double2_t b = *reinterpret_cast<const double2_t*>(base + i);
+            y[0] = b[0] - y[0];
+            y[1] = b[1] - y[1];
+        }
         *reinterpret_cast<double2_t*>(q + i) = y;
         v[0] += c[0] * y[0] + c[1] * y[1];
         v[1] += y[0] + y[1];
@@ -117,6 +123,14 @@ __global__ void __launch_bounds__(kBlock) k_applyA2(const double* __restrict__ p
                                                     double* part, const Scalars* sc) {
     if (sc && sc->done) return;
     applyA2_body<BOX>(p, q, alpha, s, nx, ny, nz, npair, part, Blk{blockIdx.x, gridDim.x});
+}
+
+// q = base - (alpha p - D L p), two cells per thread (no partials)
+template <bool BOX>
+__global__ void __launch_bounds__(kBlock) k_residA2(const double* __restrict__ base, const double* __restrict__ p,
+                                                    double* __restrict__ q, double alpha, double s, int nx, int ny,
+                                                    int nz, unsigned npair) {
+    applyA2_body<BOX>(p, q, alpha, s, nx, ny, nz, npair, nullptr, Blk{blockIdx.x, gridDim.x}, base);
 }
 
 __global__ void __launch_bounds__(kBlock) kb_applyA2(const InstDev* inst, const int* gate, const BatchTab* tab) {
@@ -346,6 +360,19 @@ void launch_applyA_plain(hipStream_t st, const double* x, double* y, double alph
     }
     hipLaunchKernelGGL(box ? k_applyA<true> : k_applyA<false>, dim3(nblocks(n)), dim3(kBlock), 0, st, x, y, alpha,
                        s, nx, ny, nz, n, (double*)nullptr, (const Scalars*)nullptr);
+}
+
+void launch_residA_plain(hipStream_t st, const double* base, const double* x, double* q, double alpha, double s,
+                         int nx, int ny, int nz, bool box) {
+    const unsigned n = (unsigned)nx * ny * nz;
+    if (nx % 2 == 0) {
+        const unsigned npair = n / 2;
+        hipLaunchKernelGGL(box ? k_residA2<true> : k_residA2<false>, dim3(nblocks(npair)), dim3(kBlock), 0, st, base,
+                           x, q, alpha, s, nx, ny, nz, npair);
+        return;
+    }
+    launch_applyA_plain(st, x, q, alpha, s, nx, ny, nz, box);
+    launch_axpby(st, q, base, n, -1.0, 1.0);
 }
 
 // r = g - (alpha x - D L x) or, with x == nullptr, r = g - q0 (q0 may be null: r = g).

@@ -12,6 +12,9 @@ void launch_applyA(hipStream_t st, const double* p, double* q, double alpha, dou
 // y = alpha x - D L x (no partials, no guard); box: L with homogeneous box faces
 void launch_applyA_plain(hipStream_t st, const double* x, double* y, double alpha, double s, int nx, int ny,
                          int nz, bool box = false);
+// q = base - (alpha x - D L x) in one pass (box: homogeneous box faces); q must not alias x
+void launch_residA_plain(hipStream_t st, const double* base, const double* x, double* q, double alpha, double s,
+                         int nx, int ny, int nz, bool box = false);
 // partials (g.g, sum g, g.g) of a residual that already holds g
 void launch_self_partials(hipStream_t st, const double* g, size_t n, double* part, unsigned* nparts_out);
 // r = g - q0 (q0 may be null: r = g); partials (r.r, sum r, g.g)
