@@ -576,7 +576,7 @@ void vcycle_box(blob_rd* H, double alpha, const double* r, const Scalars* sc, co
 // returns the number of partials written to H->part(), 0 when not fused.
 template <typename T>
 unsigned vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, const double* cinv,
-                bool entered = false, const double* dot_q = nullptr) {
+                bool entered = false, const double* dot_q = nullptr, bool from_f = false) {
     if (H->box) {
         vcycle_box<T>(H, alpha, r, sc, cinv, entered);
         return 0;
@@ -598,6 +598,16 @@ unsigned vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, co
                                       H->part(), sc, kBlock);
         if (!(l == 0 && ndots))
             launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
+    };
+    // opening black half-sweep of level l; with from_f, level 0's red u is not stored by the
+    // entry and the sweep takes it as f_red / diag (it keeps the default work-group size)
+    auto first_black = [&](int l, double s, double diag, const int* b) {
+        const LevelDims& d = P.lev[l];
+        if (l == 0 && from_f &&
+            launch_gs_from_f<T>(st, lv(0, 1), lv(0, 2), lv(0, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc))
+            return;
+        if (l == 0 && from_f) throw Err(BLOB_RD_EDEVICE, "V-cycle entry without a stored red sweep");
+        launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
     };
     if (!entered) {
         const LevelDims& d = P.lev[0];
@@ -625,7 +635,7 @@ unsigned vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, co
                 continue;
             }
             const int* b = H->bs[l];
-            launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
+            first_black(l, s, diag, b);
             launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
             launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
             launch_resid_red<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), lv(l, 4), d.hx, d.ny, d.nz, s, diag, sc, b[1]);
@@ -661,7 +671,7 @@ unsigned vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, co
         const LevelDims& d = P.lev[l];
         const double s = D / (d.h * d.h), diag = alpha + 6.0 * s;
         const int* b = H->bs[l];
-        launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
+        first_black(l, s, diag, b);
         launch_gs<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), d.hx, d.ny, d.nz, 0, s, 1.0 / diag, sc, b[0]);
         launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
         launch_resid_red<T>(st, lv(l, 0), lv(l, 1), lv(l, 2), lv(l, 4), d.hx, d.ny, d.nz, s, diag, sc, b[1]);
@@ -1409,6 +1419,10 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
         T* f1 = H->at<T>(P.off_lvl[0][3]);
         const size_t nh = P.ncell / 2;
         const double inv_diag = 1.0 / (alpha + 6.0 * H->prm.D / (d.h * d.h));
+        // the periodic V-cycle can open from f (level 0 in the LDS tail, or rows of the vector form)
+        const int t0 = std::min(H->tail_level[sizeof(T) == 4 ? 0 : 1], P.nlev - 1);
+        const int vw = 16 / (int)sizeof(T);
+        const bool from_f = !H->box && (t0 == 0 || (d.hx % vw == 0 && d.hx >= vw));
         for (int k = 0; k < o.m; ++k) {
             const double* vk = V + (size_t)k * N;
             if (learned) {
@@ -1416,16 +1430,18 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
                 vk = H->nv(9);
             }
             // S v enters the V-cycle from the contribution lists: level-0 f is zero
-            // outside the touched cells after the first product of the loop
-            launch_zero<T>(st, z0, nh);
+            // outside the touched cells after the first product of the loop. With from_f
+            // the opening black sweep takes the red zero-guess sweep as f_red / diag, so the
+            // stale red u of the previous product need not be cleared.
+            if (!from_f) launch_zero<T>(st, z0, nh);
             if (k == 0) {
                 launch_zero<T>(st, f0, nh);
                 launch_zero<T>(st, f1, nh);
             }
             launch_spread_enter<T>(st, L, SpreadMult{vk, nullptr, 0.0, 0.0}, nullptr, H->inv_h3(), f0, f1, z0, d.nx,
                                    d.ny, inv_diag);
-            H->alg_bytes += (double)nh * P.esz * (k == 0 ? 3 : 1);
-            vcycle<T>(H, alpha, nullptr, nullptr, cinv, true);
+            H->alg_bytes += (double)nh * P.esz * ((k == 0 ? 2 : 0) + (from_f ? 0 : 1));
+            vcycle<T>(H, alpha, nullptr, nullptr, cinv, true, nullptr, from_f);
             launch_interp_split<T>(st, z0, z1, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
                                    H->at<int>(P.off_perm), V + (size_t)(k + 1) * N);
             launch_gmres_arnoldi(st, V, Hm, H->at<double>(P.off_cs), H->at<double>(P.off_sn), gv, N, k, o.m,

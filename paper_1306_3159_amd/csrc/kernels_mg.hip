@@ -109,7 +109,10 @@ __device__ __forceinline__ void row_neighbours(const T* __restrict__ orow, int i
     }
 }
 
-template <typename T>
+// FROM_F: the first half-sweep after a V-cycle entry whose other colour still holds its
+// zero-guess sweep u = f / diag; uo is then that colour's f, scaled on the fly (the same
+// product the entry would have stored), so the entry need not store it.
+template <typename T, bool FROM_F = false>
 __device__ __forceinline__ void gs_vec_body(T* __restrict__ uc, const T* __restrict__ uo, const T* __restrict__ fc, int hx, int ny, int nz, int color, T s, T inv_diag, Blk blk) {
     typedef typename VecOf<T>::type V;
     constexpr int VW = VecOf<T>::W;
@@ -131,8 +134,27 @@ __device__ __forceinline__ void gs_vec_body(T* __restrict__ uc, const T* __restr
     const V zp = *reinterpret_cast<const V*>(uo + ((size_t)wrapi(z + 1, nz) * ny + y) * hx + i0);
     const V f = *reinterpret_cast<const V*>(fc + row + i0);
     V out;
+    if (FROM_F) {
 #pragma unroll
-    for (int k = 0; k < VW; ++k) out[k] = (f[k] + s * (((left[k] + right[k]) + (ym[k] + yp[k])) + (zm[k] + zp[k]))) * inv_diag;
+        for (int k = 0; k < VW; ++k) {
+            // each scaled value rounded on its own, as the entry's stored sweep is
+            T l, r, a, b, c, e;
+            {
+#pragma clang fp contract(off)
+                l = left[k] * inv_diag;
+                r = right[k] * inv_diag;
+                a = ym[k] * inv_diag;
+                b = yp[k] * inv_diag;
+                c = zm[k] * inv_diag;
+                e = zp[k] * inv_diag;
+            }
+            out[k] = (f[k] + s * (((l + r) + (a + b)) + (c + e))) * inv_diag;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < VW; ++k)
+            out[k] = (f[k] + s * (((left[k] + right[k]) + (ym[k] + yp[k])) + (zm[k] + zp[k]))) * inv_diag;
+    }
     *reinterpret_cast<V*>(uc + row + i0) = out;
 }
 
@@ -142,6 +164,14 @@ __global__ void __launch_bounds__(kMaxTuneBlock) k_gs_vec(T* __restrict__ uc, co
                                                    T inv_diag, const Scalars* sc) {
     if (sc && sc->done) return;
     gs_vec_body<T>(uc, uo, fc, hx, ny, nz, color, s, inv_diag, Blk{blockIdx.x, gridDim.x});
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMaxTuneBlock) k_gs_vec_from_f(T* __restrict__ uc, const T* __restrict__ fo,
+                                                          const T* __restrict__ fc, int hx, int ny, int nz,
+                                                          int color, T s, T inv_diag, const Scalars* sc) {
+    if (sc && sc->done) return;
+    gs_vec_body<T, true>(uc, fo, fc, hx, ny, nz, color, s, inv_diag, Blk{blockIdx.x, gridDim.x});
 }
 
 // The closing red half-sweep on the finest level fused with the CG dots of
@@ -214,6 +244,17 @@ unsigned launch_gs_dots(hipStream_t st, T* uc, const T* uo, const T* fc, int hx,
     hipLaunchKernelGGL(k_gs_vec_dots<T>, dim3(nb), dim3(bs), 0, st, uc, uo, fc, hx, ny, nz, (T)s, (T)inv_diag, r, q,
                        part, sc);
     return nb;
+}
+
+template <typename T>
+bool launch_gs_from_f(hipStream_t st, T* uc, const T* fo, const T* fc, int hx, int ny, int nz, int color, double s,
+                      double inv_diag, const Scalars* sc, int bs) {
+    constexpr int VW = VecOf<T>::W;
+    if (hx % VW != 0 || hx < VW) return false;
+    const unsigned nv = (unsigned)(hx / VW) * ny * nz;
+    hipLaunchKernelGGL(k_gs_vec_from_f<T>, dim3(nblocks(nv, bs)), dim3(bs), 0, st, uc, fo, fc, hx, ny, nz, color,
+                       (T)s, (T)inv_diag, sc);
+    return true;
 }
 
 template <typename T>
@@ -1103,6 +1144,8 @@ hipError_t tail_set_lds_batched(size_t bytes) {
     template void launch_enter<T>(hipStream_t, const double*, T*, T*, T*, int, int, int, double, const Scalars*);  \
     template void launch_gs<T>(hipStream_t, T*, const T*, const T*, int, int, int, int, double, double,            \
                                const Scalars*, int);                                                               \
+    template bool launch_gs_from_f<T>(hipStream_t, T*, const T*, const T*, int, int, int, int, double, double,     \
+                                      const Scalars*, int);                                                        \
     template void launch_resid_red<T>(hipStream_t, const T*, const T*, const T*, T*, int, int, int, double, double, \
                                       const Scalars*, int);                                                         \
     template void launch_restrict<T>(hipStream_t, const T*, int, int, int, T*, T*, T*, int, double, const Scalars*, \

@@ -82,6 +82,12 @@ void launch_enter(hipStream_t st, const double* r, T* f0, T* f1, T* u0, int nx, 
 template <typename T>
 void launch_gs(hipStream_t st, T* uc, const T* uo, const T* fc, int hx, int ny, int nz, int color, double s,
                double inv_diag, const Scalars* sc, int bs = kBlock);
+// the first half-sweep of colour `color` after a V-cycle entry, reading the other colour's f
+// fo and scaling it by inv_diag (the entry's zero-guess sweep) instead of its u; returns false
+// (nothing launched) when the rows do not take the vector form
+template <typename T>
+bool launch_gs_from_f(hipStream_t st, T* uc, const T* fo, const T* fc, int hx, int ny, int nz, int color, double s,
+                      double inv_diag, const Scalars* sc, int bs = kBlock);
 // closing red half-sweep of the finest level + partials (sum z, z.r, z.q); returns
 // the partial count, 0 if not applicable (nothing launched)
 template <typename T>
