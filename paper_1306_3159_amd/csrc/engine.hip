@@ -112,7 +112,7 @@ size_t fg_stride(const Plan& P) { return (P.ncell + (size_t)P.N + 31) & ~(size_t
 
 size_t fg_bytes(const Plan& P, int restart) {
     const size_t ld = (size_t)restart + 1;
-    return (2 * (size_t)restart + 1) * fg_stride(P) * 8 + (ld * restart + 4 * ld + 8) * 8 + 256;
+    return (2 * (size_t)restart + 1) * fg_stride(P) * 8 + (ld * restart + 5 * ld + 8) * 8 + 256;
 }
 
 int make_plan(const blob_rd_params* p, Plan* P, std::string* why) {
@@ -348,6 +348,7 @@ struct blob_rd {
     bool use_graphs = true;
     bool relax = true;  // relaxed inner tolerances in the Schur GMRES
     bool blocked = true;  // temporally blocked launches on the coarser per-level levels
+    bool reorth_always = false;  // the block FGMRES re-orthogonalises every new basis vector
     // learned Schur preconditioner (CSR of W in a caller-provided buffer)
     struct Learned {
         bool ready = false;
@@ -1504,7 +1505,16 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
     double* sn = cs + ld;
     double* gv = sn + ld;
     double* yv = gv + ld;
-    double* sd = yv + ld;  // [0] beta, [2..3] Givens outputs
+    double* sd = yv + ld;  // [0] beta, [2..3] Givens outputs, [4..5] norms of a warm start, [6] |w|^2, [7] redo flag
+    double* c2 = sd + 8;   // dots of the re-orthogonalisation pass
+    int* redo = reinterpret_cast<int*>(sd + 7);
+    // classical Gram-Schmidt in groups of up to 8 basis vectors per pass over w, as far as the
+    // partial-sum buffer allows (modified Gram-Schmidt otherwise)
+    const unsigned cgs_nb = fg_cgs_blocks(n);
+    const int group = (int)std::min<long long>(8, (long long)(3 * P.part_cap / cgs_nb) - 1);
+    // re-orthogonalise when the projection removed all but this fraction of |w| (always, with
+    // the handle's reorth_always)
+    const double kReorth = H->reorth_always ? 1e150 : 0.1;
     double bnorm = -1.0, rel = 0.0, prev_rel = 0.0;
     const double phi = H->box ? -H->cb : 0.0;
     if (warm) {
@@ -1551,12 +1561,26 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
             fg_precond<T>(H, alpha, o, vj, vj + ncell, zj, zj + ncell);
             fg_apply_K(H, alpha, zj, zj + ncell, w, w + ncell);
             double* col = Hd + (size_t)j * ld;
-            for (int i = 0; i <= j + 1; ++i) {
-                const double* vprev = i > 0 ? V + (size_t)(i - 1) * stride : nullptr;
-                const double* vnext = i <= j ? V + (size_t)i * stride : nullptr;
-                launch_fg_mgs(st, w, vprev, i > 0 ? col + (i - 1) : nullptr, vnext, n, H->part(), &np);
-                launch_fg_fin(st, H->part(), np, col + i, i == j + 1);
-                H->alg_bytes += (double)n * 8 * ((vprev ? 3 : 1) + (vnext ? 1 : 0));
+            if (group >= 1) {
+                // h = V^T w, w -= V h, |w|; once more (dots into c2, h += c2) when |w| fell below
+                // kReorth of its length before the projection
+                const int mv = j + 1;
+                launch_fg_cgs_dots(st, w, V, stride, n, mv, group, col, sd + 6, H->part(), nullptr);
+                launch_fg_cgs_update(st, w, V, stride, n, col, mv, H->part(), nullptr, col + j + 1, sd + 6,
+                                     kReorth * kReorth, redo, nullptr, nullptr);
+                launch_fg_cgs_dots(st, w, V, stride, n, mv, group, c2, nullptr, H->part(), redo);
+                launch_fg_cgs_update(st, w, V, stride, n, c2, mv, H->part(), redo, col + j + 1, nullptr, 0.0,
+                                     nullptr, col, c2);
+                const int passes = (mv + group - 1) / group;
+                H->alg_bytes += (double)n * 8 * ((double)mv + passes + (mv + 2));
+            } else {
+                for (int i = 0; i <= j + 1; ++i) {
+                    const double* vprev = i > 0 ? V + (size_t)(i - 1) * stride : nullptr;
+                    const double* vnext = i <= j ? V + (size_t)i * stride : nullptr;
+                    launch_fg_mgs(st, w, vprev, i > 0 ? col + (i - 1) : nullptr, vnext, n, H->part(), &np);
+                    launch_fg_fin(st, H->part(), np, col + i, i == j + 1);
+                    H->alg_bytes += (double)n * 8 * ((vprev ? 3 : 1) + (vnext ? 1 : 0));
+                }
             }
             launch_fg_scale(st, w, col + j + 1, n);
             H->alg_bytes += (double)n * 16;
@@ -1687,6 +1711,7 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
         for (int& v : row) v = kBlock;
     if (const char* g = std::getenv("BLOB_RD_RELAX")) H->relax = std::atoi(g) != 0;
     if (const char* g = std::getenv("BLOB_RD_BLOCKED")) H->blocked = std::atoi(g) != 0;
+    if (const char* g = std::getenv("BLOB_RD_FG_REORTH")) H->reorth_always = std::atoi(g) != 0;
     // Align the workspace base to 256 bytes.
     uintptr_t base = (uintptr_t)p->workspace;
     H->ws = (char*)((base + 255) & ~(uintptr_t)255);

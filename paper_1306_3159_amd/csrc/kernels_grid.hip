@@ -727,6 +727,143 @@ void launch_fg_mgs(hipStream_t st, double* w, const double* vprev, const double*
     *np = nb;
 }
 
+// ---- classical Gram-Schmidt passes of the flexible GMRES --------------------------------
+// Dots of w with the NV basis vectors V0 + v * stride (block partials, value v at part[v * nb]),
+// and w.w after them with WN. A set gate that reads 0 turns the launch into a no-op.
+template <int NV, bool WN>
+__global__ void __launch_bounds__(kBlock) k_fg_mdot(const double* __restrict__ w, const double* __restrict__ V0,
+                                                    size_t stride, unsigned n, double* part, const int* gate) {
+    if (gate && !*gate) return;
+    constexpr int K = NV + (WN ? 1 : 0);
+    const unsigned n2 = n >> 1;
+    unsigned lo, hi;
+    chunk_of(blockIdx.x, gridDim.x, n2, &lo, &hi);
+    double a[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) a[k] = 0.0;
+    const double2* w2 = reinterpret_cast<const double2*>(w);
+    for (unsigned p = lo + threadIdx.x; p < hi; p += blockDim.x) {
+        const double2 x = w2[p];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double2 y = reinterpret_cast<const double2*>(V0 + (size_t)v * stride)[p];
+            a[v] += x.x * y.x + x.y * y.y;
+        }
+        if (WN) a[K - 1] += x.x * x.x + x.y * x.y;
+    }
+    if ((n & 1u) && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        const double x = w[n - 1];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a[v] += x * V0[(size_t)v * stride + n - 1];
+        if (WN) a[K - 1] += x * x;
+    }
+    block_partials<K>(a, part, gridDim.x, blockIdx.x);
+}
+
+// out[v] (= or +=) the sum of value v's partials, v < nv; *wn = the last value's sum with wn.
+__global__ void __launch_bounds__(kFinBlock) k_fg_mfin(const double* __restrict__ part, unsigned np, int nv,
+                                                      double* out, double* wn, const int* gate) {
+    if (gate && !*gate) return;
+    for (int v = 0; v < nv; ++v) {
+        const double sv = fin_sum(part + (size_t)v * np, np);
+        if (threadIdx.x == 0) out[v] = sv;
+    }
+    if (wn) {
+        const double sw = fin_sum(part + (size_t)nv * np, np);
+        if (threadIdx.x == 0) *wn = sw;
+    }
+}
+
+// w -= sum_v h[v] v_v over the m basis vectors (in order), partials of the new w.w.
+__global__ void __launch_bounds__(kBlock) k_fg_mupdate(double* __restrict__ w, const double* __restrict__ V0,
+                                                       size_t stride, unsigned n, const double* __restrict__ h,
+                                                       int m, double* part, const int* gate) {
+    if (gate && !*gate) return;
+    __shared__ double hs[kFgMaxRestart];
+    for (int k = threadIdx.x; k < m; k += blockDim.x) hs[k] = h[k];
+    __syncthreads();
+    const unsigned n2 = n >> 1;
+    unsigned lo, hi;
+    chunk_of(blockIdx.x, gridDim.x, n2, &lo, &hi);
+    double a[1] = {0.0};
+    double2* w2 = reinterpret_cast<double2*>(w);
+    for (unsigned p = lo + threadIdx.x; p < hi; p += blockDim.x) {
+        double2 x = w2[p];
+        for (int v = 0; v < m; ++v) {
+            const double2 y = reinterpret_cast<const double2*>(V0 + (size_t)v * stride)[p];
+            x.x -= hs[v] * y.x;
+            x.y -= hs[v] * y.y;
+        }
+        w2[p] = x;
+        a[0] += x.x * x.x + x.y * x.y;
+    }
+    if ((n & 1u) && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        double x = w[n - 1];
+        for (int v = 0; v < m; ++v) x -= hs[v] * V0[(size_t)v * stride + n - 1];
+        w[n - 1] = x;
+        a[0] += x * x;
+    }
+    block_partials<1>(a, part, gridDim.x, blockIdx.x);
+}
+
+// *hout = |w| from the update's partials. First pass (add == null): *redo = 1 when |w|^2 fell
+// below eta2 * *pre2 (w lost most of its length to the projection, so the rounding left in
+// it is relatively large). Second pass (gated by redo): col[v] += add[v], v < m.
+__global__ void __launch_bounds__(kFinBlock) k_fg_norm(const double* __restrict__ part, unsigned np, double* hout,
+                                                      const double* pre2, double eta2, int* redo, double* col,
+                                                      const double* add, int m, const int* gate) {
+    if (gate && !*gate) return;
+    const double s = fin_sum(part, np);
+    if (threadIdx.x == 0) {
+        *hout = sqrt(s);
+        if (!add) *redo = s < eta2 * *pre2 ? 1 : 0;
+    }
+    if (add)
+        for (int v = threadIdx.x; v < m; v += blockDim.x) col[v] += add[v];
+}
+
+namespace {
+template <int NV>
+void mdot_launch(hipStream_t st, bool wn, unsigned nb, const double* w, const double* V0, size_t stride, unsigned n,
+                 double* part, const int* gate) {
+    if (wn) hipLaunchKernelGGL((k_fg_mdot<NV, true>), dim3(nb), dim3(kBlock), 0, st, w, V0, stride, n, part, gate);
+    else hipLaunchKernelGGL((k_fg_mdot<NV, false>), dim3(nb), dim3(kBlock), 0, st, w, V0, stride, n, part, gate);
+}
+}  // namespace
+
+unsigned fg_cgs_blocks(size_t n) { return red_blocks(n / 2 + 1); }
+
+void launch_fg_cgs_dots(hipStream_t st, const double* w, const double* V, size_t stride, size_t n, int m, int group,
+                        double* out, double* wn2, double* part, const int* gate) {
+    const unsigned nb = fg_cgs_blocks(n);
+    for (int g0 = 0; g0 < m; g0 += group) {
+        const int nv = m - g0 < group ? m - g0 : group;
+        const bool wn = g0 == 0 && wn2;
+        const double* V0 = V + (size_t)g0 * stride;
+        switch (nv) {
+            case 1: mdot_launch<1>(st, wn, nb, w, V0, stride, (unsigned)n, part, gate); break;
+            case 2: mdot_launch<2>(st, wn, nb, w, V0, stride, (unsigned)n, part, gate); break;
+            case 3: mdot_launch<3>(st, wn, nb, w, V0, stride, (unsigned)n, part, gate); break;
+            case 4: mdot_launch<4>(st, wn, nb, w, V0, stride, (unsigned)n, part, gate); break;
+            case 5: mdot_launch<5>(st, wn, nb, w, V0, stride, (unsigned)n, part, gate); break;
+            case 6: mdot_launch<6>(st, wn, nb, w, V0, stride, (unsigned)n, part, gate); break;
+            case 7: mdot_launch<7>(st, wn, nb, w, V0, stride, (unsigned)n, part, gate); break;
+            default: mdot_launch<8>(st, wn, nb, w, V0, stride, (unsigned)n, part, gate); break;
+        }
+        hipLaunchKernelGGL(k_fg_mfin, dim3(1), dim3(kFinBlock), 0, st, part, nb, nv, out + g0, wn ? wn2 : nullptr,
+                           gate);
+    }
+}
+
+void launch_fg_cgs_update(hipStream_t st, double* w, const double* V, size_t stride, size_t n, const double* h, int m,
+                          double* part, const int* gate, double* hout, const double* pre2, double eta2, int* redo,
+                          double* col, const double* add) {
+    const unsigned nb = fg_cgs_blocks(n);
+    hipLaunchKernelGGL(k_fg_mupdate, dim3(nb), dim3(kBlock), 0, st, w, V, stride, (unsigned)n, h, m, part, gate);
+    hipLaunchKernelGGL(k_fg_norm, dim3(1), dim3(kFinBlock), 0, st, part, nb, hout, pre2, eta2, redo, col, add, m,
+                       gate);
+}
+
 // out = sum of the partials (its square root with take_sqrt)
 __global__ void __launch_bounds__(kFinBlock) k_fg_fin(const double* __restrict__ part, unsigned np, double* out,
                                                       int take_sqrt) {

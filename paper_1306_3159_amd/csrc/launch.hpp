@@ -52,6 +52,17 @@ void launch_add_shift(hipStream_t st, double* v, size_t n, const double* shift_d
 // w -= (*hprev) vprev (if vprev), partials of w.vnext (w.w if vnext is null)
 void launch_fg_mgs(hipStream_t st, double* w, const double* vprev, const double* hprev, const double* vnext,
                    size_t n, double* part, unsigned* np);
+// Classical Gram-Schmidt for the flexible GMRES basis (v_k = V + k * stride, k < m):
+// out[k] = w . v_k (groups of `group` <= 8 vectors per pass over w; *wn2 = w.w when wn2 is set),
+// then w -= sum_k h[k] v_k with *hout = |w|; the first update (add null) sets *redo when
+// |w|^2 < eta2 * *pre2, a second one (gate = redo) adds `add` into col. A set gate reading 0
+// makes every launch a no-op. part needs (group + 1) * fg_cgs_blocks(n) doubles.
+unsigned fg_cgs_blocks(size_t n);
+void launch_fg_cgs_dots(hipStream_t st, const double* w, const double* V, size_t stride, size_t n, int m, int group,
+                        double* out, double* wn2, double* part, const int* gate);
+void launch_fg_cgs_update(hipStream_t st, double* w, const double* V, size_t stride, size_t n, const double* h, int m,
+                          double* part, const int* gate, double* hout, const double* pre2, double eta2, int* redo,
+                          double* col, const double* add);
 // *out = sum of partials (sqrt of it with take_sqrt)
 void launch_fg_fin(hipStream_t st, const double* part, unsigned np, double* out, int take_sqrt);
 // w /= *h (0 if *h == 0)

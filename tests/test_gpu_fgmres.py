@@ -113,6 +113,32 @@ def test_fgmres_solve_matches_oracle(dev, alpha, kind):
         S.close()
 
 
+@pytest.mark.parametrize("kind", ["diagonal", "schur"])
+def test_fgmres_second_gram_schmidt_pass(dev, kind, monkeypatch):
+    """The classical Gram-Schmidt of the block FGMRES re-orthogonalises a new basis vector when the
+    projection removed most of it; forcing that second pass on every vector (BLOB_RD_FG_REORTH=1)
+    gives the same iterations and the same solution to the tolerance, and still the oracle's
+    iteration count."""
+    _say("fgmres second pass", kind)
+    rng = np.random.default_rng(74)
+    n, N = 32, 30
+    q = W.rsa_positions(rng, n, N, 3.0)
+    f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
+    alpha = 1.0 / n ** 2
+    _, _, info = fg.solve(f, q, alpha, kind=kind, rtol=1e-10, cycle=lambda r: it.vcycle(r, alpha))
+    out = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("BLOB_RD_FG_REORTH", mode)
+        S = make(dev, n, q, precision=0, rtol=1e-10)
+        c, lam, st = S.solve_absorbing_fgmres(T(f, dev), alpha=alpha, precond=kind)
+        assert st["rc"] == 0 and st["rel_resid"] <= 1e-10, st
+        assert abs(st["outer_iters"] - info["iters"]) <= 1
+        out[mode] = (H(c), H(lam), st)
+        S.close()
+    assert out["0"][2]["outer_iters"] == out["1"][2]["outer_iters"]
+    assert rel(out["1"][0], out["0"][0]) < 1e-9 and rel(out["1"][1], out["0"][1]) < 1e-9
+
+
 def test_fgmres_fixed_blob_count_lattice(dev):
     """The paper's fixed-N test (64 = 4^3 blobs on a lattice, A = L^-2 I - L) at L = 64 with both
     preconditioners: converges, and the oracle's FP64 residual agrees at full size."""
