@@ -1938,7 +1938,6 @@ int blob_rd_interp(blob_rd_t H, const double* c, double* out) {
 int blob_rd_spread(blob_rd_t H, const double* lambda, double* out) {
     if (!H || !out || (!lambda && H->P.N > 0)) return g_last_error = "null argument", BLOB_RD_EINVAL;
     return guarded(H, nullptr, [&]() {
-        const Plan& P = H->P;
         spread_to(H, lambda, 0.0, nullptr, out, H->inv_h3(), nullptr);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(H->st));
@@ -2267,7 +2266,7 @@ std::string batch_unfit(const blob_rd* H, int esz) {
     const int L = P.nlev - 1;
     const int t = H->tail_level[P.esz == 4 ? 0 : 1];
     const int VW = 16 / P.esz;
-    if (P.esz != esz) return "mixed precisions";
+    if ((int)P.esz != esz) return "mixed precisions";
     if (t >= L || t < 1) return "no coarse tail below a per-level finest level";
     for (int l = 0; l < t; ++l) {
         const LevelDims& d = P.lev[l];

@@ -629,7 +629,7 @@ __global__ void __launch_bounds__(kFinBlock) k_gmres_arnoldi(double* V, double* 
             const double mean = wg_sum(s) / (double)N;
 #pragma unroll
             for (int c = 0; c < kArnoldiRegs; ++c)
-                if (threadIdx.x + c * blockDim.x < N) wr[c] -= mean;
+                if ((int)(threadIdx.x + c * blockDim.x) < N) wr[c] -= mean;
         }
         for (int j = 0; j <= k; ++j) {
             const double* vj = V + (size_t)j * N;
@@ -650,7 +650,7 @@ __global__ void __launch_bounds__(kFinBlock) k_gmres_arnoldi(double* V, double* 
         double s = 0.0;
 #pragma unroll
         for (int c = 0; c < kArnoldiRegs; ++c)
-            if (threadIdx.x + c * blockDim.x < N) s += wr[c] * wr[c];
+            if ((int)(threadIdx.x + c * blockDim.x) < N) s += wr[c] * wr[c];
         hk1 = sqrt(wg_sum(s));
         const double inv = hk1 > 0.0 ? 1.0 / hk1 : 0.0;
 #pragma unroll
