@@ -458,7 +458,35 @@ __global__ void __launch_bounds__(kBlock) k_prolong_red_box(const T* __restrict_
     u0[idx] += c0 * (b0 * v00 + b1 * v10) + c1 * (b0 * v01 + b1 * v11);
 }
 
-// Vector form: VW red cells of a split row per thread, one 16-byte read-modify-write of u0.
+// The coarse values c(i0 + d), d = 0 .. VW-1, of row (Y, Z) of a coarse box level, and
+// the next one on the fine cells' side, e = c(i0 + VW) (s = 1) or c(i0 - 1) (s = 0); past
+// a face e is the end cell's own value (its weight is then 0). In the split layout i0 is
+// even, so c(i0 + d) is element i0/2 + d/2 of c1 when d + Y + Z is odd and of c0
+// otherwise: one VW/2-wide load from each half gives the run.
+template <typename T>
+__device__ __forceinline__ void box_coarse_row(const T* __restrict__ c0, const T* __restrict__ c1, int nat, int Y,
+                                               int Z, int i0, int s, int cx, int cy, T (&m)[BoxVec<T>::W], T& e) {
+    constexpr int VW = BoxVec<T>::W, HW = VW / 2;
+    struct alignas(sizeof(T) * HW) Half { T v[HW]; };
+    if (nat) {
+        const T* r = c0 + ((size_t)Z * cy + Y) * cx;
+#pragma unroll
+        for (int d = 0; d < VW; ++d) m[d] = r[i0 + d];
+    } else {
+        const size_t rb = ((size_t)Z * cy + Y) * (cx >> 1);
+        const int p = (Y + Z) & 1;
+        const Half a = *reinterpret_cast<const Half*>(c0 + rb + (i0 >> 1));
+        const Half b = *reinterpret_cast<const Half*>(c1 + rb + (i0 >> 1));
+#pragma unroll
+        for (int d = 0; d < VW; ++d) m[d] = ((d + p) & 1) ? b.v[d >> 1] : a.v[d >> 1];
+    }
+    // clamped: past a face the end cell itself
+    const int X = s ? min(i0 + VW, cx - 1) : max(i0 - 1, 0);
+    e = box_coarse_at(c0, c1, nat, X, Y, Z, cx, cy);
+}
+
+// Vector form: VW red cells of a split row per thread, one 16-byte read-modify-write of
+// u0; the cells share their coarse rows, each read once (VW + 1 values).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_prolong_red_box_vec(const T* __restrict__ cu0, const T* __restrict__ cu1,
                                                                 int nat, T* __restrict__ u0, int nx, int ny, int nz,
@@ -479,6 +507,11 @@ __global__ void __launch_bounds__(kBlock) k_prolong_red_box_vec(const T* __restr
     T b0, b1, c0, c1;
     box_pweights<T>(y, cy, J0, J1, b0, b1);
     box_pweights<T>(z, cz, K0, K1, c0, c1);
+    T m00[VW], m10[VW], m01[VW], m11[VW], e00, e10, e01, e11;
+    box_coarse_row<T>(cu0, cu1, nat, J0, K0, i0, s0, cx, cy, m00, e00);
+    box_coarse_row<T>(cu0, cu1, nat, J1, K0, i0, s0, cx, cy, m10, e10);
+    box_coarse_row<T>(cu0, cu1, nat, J0, K1, i0, s0, cx, cy, m01, e01);
+    box_coarse_row<T>(cu0, cu1, nat, J1, K1, i0, s0, cx, cy, m11, e11);
     const size_t row = ((size_t)z * ny + y) * hx;
     V u = *reinterpret_cast<const V*>(u0 + row + i0);
 #pragma unroll
@@ -486,11 +519,13 @@ __global__ void __launch_bounds__(kBlock) k_prolong_red_box_vec(const T* __restr
         int I0, I1;
         T a0, a1;
         box_pweights<T>(2 * (i0 + k) + s0, cx, I0, I1, a0, a1);
-        auto line = [&](int J, int K) {
-            return a0 * box_coarse_at(cu0, cu1, nat, I0, J, K, cx, cy) +
-                   a1 * box_coarse_at(cu0, cu1, nat, I1, J, K, cx, cy);
-        };
-        const T v00 = line(J0, K0), v10 = line(J1, K0), v01 = line(J0, K1), v11 = line(J1, K1);
+        // the value at I1: the side neighbour, or past a face the cell itself (weight 0)
+        const T n00 = s0 ? (k + 1 < VW ? m00[k + 1] : e00) : (k > 0 ? m00[k - 1] : e00);
+        const T n10 = s0 ? (k + 1 < VW ? m10[k + 1] : e10) : (k > 0 ? m10[k - 1] : e10);
+        const T n01 = s0 ? (k + 1 < VW ? m01[k + 1] : e01) : (k > 0 ? m01[k - 1] : e01);
+        const T n11 = s0 ? (k + 1 < VW ? m11[k + 1] : e11) : (k > 0 ? m11[k - 1] : e11);
+        const T v00 = a0 * m00[k] + a1 * n00, v10 = a0 * m10[k] + a1 * n10;
+        const T v01 = a0 * m01[k] + a1 * n01, v11 = a0 * m11[k] + a1 * n11;
         u[k] += c0 * (b0 * v00 + b1 * v10) + c1 * (b0 * v01 + b1 * v11);
     }
     *reinterpret_cast<V*>(u0 + row + i0) = u;

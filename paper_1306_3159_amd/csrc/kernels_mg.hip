@@ -487,6 +487,23 @@ __device__ __forceinline__ T coarse_at(const T* __restrict__ c0, const T* __rest
     return ((X + Y + Z) & 1) ? c1[j] : c0[j];
 }
 
+// u plus the trilinear correction of one fine cell from its four coarse rows (J0, K0),
+// (J1, K0), (J0, K1), (J1, K1): m is a row's value at the cell's own coarse x, n the one at
+// the neighbour on the cell's side. Evaluated as written, with no contraction beyond the
+// explicit FMAs, so that every form of the correction (per level, blocked, LDS tail) rounds
+// alike.
+template <typename T>
+__device__ __forceinline__ T tri_add(T u, T m00, T n00, T m10, T n10, T m01, T n01, T m11, T n11) {
+#pragma clang fp contract(off)
+    const T a00 = fma((T)0.75, m00, (T)0.25 * n00);
+    const T a10 = fma((T)0.75, m10, (T)0.25 * n10);
+    const T a01 = fma((T)0.75, m01, (T)0.25 * n01);
+    const T a11 = fma((T)0.75, m11, (T)0.25 * n11);
+    const T b0 = fma((T)0.75, a00, (T)0.25 * a10);
+    const T b1 = fma((T)0.75, a01, (T)0.25 * a11);
+    return u + fma((T)0.75, b0, (T)0.25 * b1);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kMaxTuneBlock) k_prolong(const T* __restrict__ cu0, const T* __restrict__ cu1, int nat,
                                                     T* __restrict__ u0, T* __restrict__ u1, int nx, int ny, int nz,
@@ -507,24 +524,40 @@ __global__ void __launch_bounds__(kMaxTuneBlock) k_prolong(const T* __restrict__
     for (int c = 0; c < 2; ++c) {
         const int x = 2 * i + (s0 ^ c);
         const int I0 = x >> 1, I1 = wrapi((x & 1) ? I0 + 1 : I0 - 1, cx);
-        const T a00 = (T)0.75 * coarse_at(cu0, cu1, nat, I0, J0, K0, cx, cy) +
-                      (T)0.25 * coarse_at(cu0, cu1, nat, I1, J0, K0, cx, cy);
-        const T a10 = (T)0.75 * coarse_at(cu0, cu1, nat, I0, J1, K0, cx, cy) +
-                      (T)0.25 * coarse_at(cu0, cu1, nat, I1, J1, K0, cx, cy);
-        const T a01 = (T)0.75 * coarse_at(cu0, cu1, nat, I0, J0, K1, cx, cy) +
-                      (T)0.25 * coarse_at(cu0, cu1, nat, I1, J0, K1, cx, cy);
-        const T a11 = (T)0.75 * coarse_at(cu0, cu1, nat, I0, J1, K1, cx, cy) +
-                      (T)0.25 * coarse_at(cu0, cu1, nat, I1, J1, K1, cx, cy);
-        const T v = (T)0.75 * ((T)0.75 * a00 + (T)0.25 * a10) + (T)0.25 * ((T)0.75 * a01 + (T)0.25 * a11);
-        if (c == 0) u0[idx] += v;
-        else u1[idx] += v;
+        T* u = c == 0 ? u0 : u1;
+        u[idx] = tri_add(u[idx], coarse_at(cu0, cu1, nat, I0, J0, K0, cx, cy),
+                         coarse_at(cu0, cu1, nat, I1, J0, K0, cx, cy), coarse_at(cu0, cu1, nat, I0, J1, K0, cx, cy),
+                         coarse_at(cu0, cu1, nat, I1, J1, K0, cx, cy), coarse_at(cu0, cu1, nat, I0, J0, K1, cx, cy),
+                         coarse_at(cu0, cu1, nat, I1, J0, K1, cx, cy), coarse_at(cu0, cu1, nat, I0, J1, K1, cx, cy),
+                         coarse_at(cu0, cu1, nat, I1, J1, K1, cx, cy));
     }
+}
+
+// The coarse values c(i0 + d), d = 0 .. VW-1, of row (Y, Z) of a split coarse level, and
+// the next one on the fine cells' side, e = c(i0 + VW) (s = 1) or c(i0 - 1) (s = 0), wrapped.
+// i0 is a multiple of VW, hence even: c(i0 + d) is element i0/2 + d/2 of c1 when d + Y + Z
+// is odd and of c0 otherwise, so one VW/2-wide load from each half gives the run.
+template <typename T>
+__device__ __forceinline__ void coarse_row(const T* __restrict__ c0, const T* __restrict__ c1, int Y, int Z, int i0,
+                                           int s, int cx, int cy, T (&m)[VecOf<T>::W], T& e) {
+    constexpr int VW = VecOf<T>::W, HW = VW / 2;
+    struct alignas(sizeof(T) * HW) Half { T v[HW]; };
+    const size_t rb = ((size_t)Z * cy + Y) * (cx >> 1);
+    const int p = (Y + Z) & 1;
+    const Half a = *reinterpret_cast<const Half*>(c0 + rb + (i0 >> 1));
+    const Half b = *reinterpret_cast<const Half*>(c1 + rb + (i0 >> 1));
+#pragma unroll
+    for (int d = 0; d < VW; ++d) m[d] = ((d + p) & 1) ? b.v[d >> 1] : a.v[d >> 1];
+    const int X = s ? (i0 + VW == cx ? 0 : i0 + VW) : (i0 == 0 ? cx - 1 : i0 - 1);
+    e = (((X + p) & 1) ? c1 : c0)[rb + (X >> 1)];
 }
 
 // Red-only trilinear correction, VW red cells per thread. The V-cycle's
 // post-smoothing starts with a black half-sweep, which overwrites every black
 // value without reading it, so correcting black cells would be a dead store;
-// the result equals a correction of both colours followed by that sweep.
+// the result equals a correction of both colours followed by that sweep. The
+// VW cells of a thread share their coarse rows: each of the four rows is read
+// once (VW + 1 values).
 template <typename T>
 __device__ __forceinline__ void prolong_red_body(const T* __restrict__ cu0, const T* __restrict__ cu1, T* __restrict__ u0, int nx, int ny, int nz, Blk blk) {
     typedef typename VecOf<T>::type V;
@@ -540,21 +573,22 @@ __device__ __forceinline__ void prolong_red_body(const T* __restrict__ cu0, cons
     const int cx = nx >> 1, cy = ny >> 1, cz = nz >> 1;
     const int J0 = y >> 1, J1 = wrapi((y & 1) ? J0 + 1 : J0 - 1, cy);
     const int K0 = z >> 1, K1 = wrapi((z & 1) ? K0 + 1 : K0 - 1, cz);
-    const int s0 = (y + z) & 1;  // red cell x = 2 i + s0, coarse I0 = i, I1 = i +/- 1
+    const int s0 = (y + z) & 1;  // red cell x = 2 (i0 + k) + s0: coarse I0 = i0 + k, I1 = I0 +/- 1
     const size_t row = ((size_t)z * ny + y) * hx;
+    T m00[VW], m10[VW], m01[VW], m11[VW], e00, e10, e01, e11;
+    coarse_row<T>(cu0, cu1, J0, K0, i0, s0, cx, cy, m00, e00);
+    coarse_row<T>(cu0, cu1, J1, K0, i0, s0, cx, cy, m10, e10);
+    coarse_row<T>(cu0, cu1, J0, K1, i0, s0, cx, cy, m01, e01);
+    coarse_row<T>(cu0, cu1, J1, K1, i0, s0, cx, cy, m11, e11);
     V u = *reinterpret_cast<const V*>(u0 + row + i0);
 #pragma unroll
     for (int k = 0; k < VW; ++k) {
-        const int I0 = i0 + k, I1 = wrapi(s0 ? I0 + 1 : I0 - 1, cx);
-        const T a00 = (T)0.75 * coarse_at(cu0, cu1, 0, I0, J0, K0, cx, cy) +
-                      (T)0.25 * coarse_at(cu0, cu1, 0, I1, J0, K0, cx, cy);
-        const T a10 = (T)0.75 * coarse_at(cu0, cu1, 0, I0, J1, K0, cx, cy) +
-                      (T)0.25 * coarse_at(cu0, cu1, 0, I1, J1, K0, cx, cy);
-        const T a01 = (T)0.75 * coarse_at(cu0, cu1, 0, I0, J0, K1, cx, cy) +
-                      (T)0.25 * coarse_at(cu0, cu1, 0, I1, J0, K1, cx, cy);
-        const T a11 = (T)0.75 * coarse_at(cu0, cu1, 0, I0, J1, K1, cx, cy) +
-                      (T)0.25 * coarse_at(cu0, cu1, 0, I1, J1, K1, cx, cy);
-        u[k] += (T)0.75 * ((T)0.75 * a00 + (T)0.25 * a10) + (T)0.25 * ((T)0.75 * a01 + (T)0.25 * a11);
+        // the value at I1 = I0 + 1 (s0 = 1) or I0 - 1 (s0 = 0)
+        const T n00 = s0 ? (k + 1 < VW ? m00[k + 1] : e00) : (k > 0 ? m00[k - 1] : e00);
+        const T n10 = s0 ? (k + 1 < VW ? m10[k + 1] : e10) : (k > 0 ? m10[k - 1] : e10);
+        const T n01 = s0 ? (k + 1 < VW ? m01[k + 1] : e01) : (k > 0 ? m01[k - 1] : e01);
+        const T n11 = s0 ? (k + 1 < VW ? m11[k + 1] : e11) : (k > 0 ? m11[k - 1] : e11);
+        u[k] = tri_add(u[k], m00[k], n00, m10[k], n10, m01[k], n01, m11[k], n11);
     }
     *reinterpret_cast<V*>(u0 + row + i0) = u;
 }
@@ -745,13 +779,7 @@ __global__ void __launch_bounds__(kFinBlock) k_up(const T* __restrict__ cu0, con
             const T* c10 = C + (K0 * CW + J1) * CW;
             const T* c01 = C + (K1 * CW + J0) * CW;
             const T* c11 = C + (K1 * CW + J1) * CW;
-            const T a00 = (T)0.75 * c00[I0] + (T)0.25 * c00[I1];
-            const T a10 = (T)0.75 * c10[I0] + (T)0.25 * c10[I1];
-            const T a01 = (T)0.75 * c01[I0] + (T)0.25 * c01[I1];
-            const T a11 = (T)0.75 * c11[I0] + (T)0.25 * c11[I1];
-            T u = ured[k];
-            u += (T)0.75 * ((T)0.75 * a00 + (T)0.25 * a10) + (T)0.25 * ((T)0.75 * a01 + (T)0.25 * a11);
-            U[j] = u;
+            U[j] = tri_add(ured[k], c00[I0], c00[I1], c10[I0], c10[I1], c01[I0], c01[I1], c11[I0], c11[I1]);
         }
     }
     __syncthreads();
@@ -990,11 +1018,7 @@ __device__ __forceinline__ void tail_body(const T* __restrict__ f0g, const T* __
             const T* c10 = C + (K0 * cy + J1) * cx;
             const T* c01 = C + (K1 * cy + J0) * cx;
             const T* c11 = C + (K1 * cy + J1) * cx;
-            const T a00 = (T)0.75 * c00[I0] + (T)0.25 * c00[I1];
-            const T a10 = (T)0.75 * c10[I0] + (T)0.25 * c10[I1];
-            const T a01 = (T)0.75 * c01[I0] + (T)0.25 * c01[I1];
-            const T a11 = (T)0.75 * c11[I0] + (T)0.25 * c11[I1];
-            U[j] += (T)0.75 * ((T)0.75 * a00 + (T)0.25 * a10) + (T)0.25 * ((T)0.75 * a01 + (T)0.25 * a11);
+            U[j] = tri_add(U[j], c00[I0], c00[I1], c10[I0], c10[I1], c01[I0], c01[I1], c11[I0], c11[I1]);
         }
         __syncthreads();
         const T s = (T)d.s[l], idg = (T)d.inv_diag[l];
