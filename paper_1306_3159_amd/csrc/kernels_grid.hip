@@ -451,9 +451,47 @@ __global__ void __launch_bounds__(kBlock) k_split_to_nat(const T* __restrict__ z
     out[idx] = v;
 }
 
+// Pair form: the element j of each colour array per thread, i.e. the natural cells
+// x = 2i and 2i + 1 of a row (x = 2i has colour (y + z) & 1, x = 2i + 1 the other), which
+// sit at 2j and 2j + 1 of the natural vector; each computed as in the one-cell form.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_split_to_nat2(const T* __restrict__ z0, const T* __restrict__ z1,
+                                                          double* __restrict__ out, int hx, int ny, unsigned nh,
+                                                          double scale, const double* __restrict__ shift_dev,
+                                                          double shift_scale) {
+    typedef double D2 __attribute__((ext_vector_type(2)));
+    const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nh) return;
+    const unsigned t = idx / hx;  // row z * ny + y
+    const int p = ((int)(t % ny) + (int)(t / ny)) & 1;
+    const double a = (double)z0[idx], b = (double)z1[idx];
+    const double e0 = p ? b : a, e1 = p ? a : b;
+    D2* o = reinterpret_cast<D2*>(out) + idx;
+    double v0, v1;
+    if (scale == 0.0) {
+        v0 = e0;
+        v1 = e1;
+    } else {
+        const D2 prev = *o;
+        v0 = scale * prev[0] + e0;
+        v1 = scale * prev[1] + e1;
+    }
+    if (shift_dev) {
+        v0 += shift_scale * shift_dev[0];
+        v1 += shift_scale * shift_dev[0];
+    }
+    *o = D2{v0, v1};
+}
+
 template <typename T>
 void launch_split_to_nat(hipStream_t st, const T* z0, const T* z1, double* out, int nx, int ny, int nz,
                          double scale, const double* shift_dev, double shift_scale) {
+    if (nx % 2 == 0) {
+        const unsigned nh = (unsigned)(nx / 2) * ny * nz;
+        hipLaunchKernelGGL(k_split_to_nat2<T>, dim3(nblocks(nh)), dim3(kBlock), 0, st, z0, z1, out, nx / 2, ny, nh,
+                           scale, shift_dev, shift_scale);
+        return;
+    }
     const unsigned n = (unsigned)nx * ny * nz;
     hipLaunchKernelGGL(k_split_to_nat<T>, dim3(nblocks(n)), dim3(kBlock), 0, st, z0, z1, out, nx, ny, n, scale,
                        shift_dev, shift_scale);
