@@ -59,7 +59,7 @@ def parse():
 # rotating launches), scaled by what the same counters read for a 1 GiB device
 # copy (FETCH_SIZE reports half the bytes read, WRITE_SIZE all bytes written).
 # Valid only for the kernel source the counters were taken on.
-TRAFFIC = {"source_sha256": "cf3c9a576242636b85c45dff7f2bcefe858d134e8dafdd90503d255bc2caa0f6",
+TRAFFIC = {"source_sha256": "ed78cb548390e8ffb95315fa4ff6debaf589e2e212e9e6432ed11d9e661ab97c",
            "fetch_kib": 33813.0, "write_kib": 32768.0, "fetch_scale": 1.9999, "write_scale": 1.0}
 
 
