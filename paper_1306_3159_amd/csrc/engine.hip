@@ -1370,7 +1370,7 @@ void fg_apply_K(blob_rd* H, double alpha, const double* xg, const double* xl, do
 // touched cells. Grid scratch: G_Q, G_U.
 template <typename T>
 void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, const double* vf, double* zg,
-                double* zl) {
+                double* zl, bool sum_ready = false) {
     const Plan& P = H->P;
     hipStream_t st = H->st;
     const int N = P.N;
@@ -1381,14 +1381,16 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
     const SpreadLists L = spread_lists(H);
     T* z0 = H->at<T>(P.off_lvl[0][0]);
     T* z1 = H->at<T>(P.off_lvl[0][1]);
-    double* ds = H->dsc() + 48;  // [0] sum of vg, [8..10] sums of vf - J c
+    double* ds = H->dsc() + 48;  // [0] sum of vg (already there with sum_ready), [8..10] sums of vf - J c
     double* ml = H->nv(3);       // -lbar on every blob (alpha = 0)
     // 1. concentration estimate c* from vg - lbar S 1
     if (sing) {
-        unsigned np = 0;
-        launch_norm_partials(st, vg, P.ncell, H->part(), &np);
-        launch_reduce_parts(st, H->part(), np, 1, ds);
-        H->alg_bytes += (double)P.ncell * 8;
+        if (!sum_ready) {
+            unsigned np = 0;
+            launch_norm_partials(st, vg, P.ncell, H->part(), &np);
+            launch_reduce_parts(st, H->part(), np, 1, ds);
+            H->alg_bytes += (double)P.ncell * 8;
+        }
         launch_nvec_copy_scale(st, nullptr, ml, N, 0.0, 0.0);
         launch_add_shift(st, ml, N, ds, -h3 / N);
     }
@@ -1517,6 +1519,18 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
     const double kReorth = H->reorth_always ? 1e150 : 0.1;
     double bnorm = -1.0, rel = 0.0, prev_rel = 0.0;
     const double phi = H->box ? -H->cb : 0.0;
+    // normalising a basis vector also sums its grid part for the preconditioner's mean step
+    // (singular A) when the partial-sum buffer holds one partial per block
+    const bool fuse_sum = singular(H, alpha) && red_blocks(n) <= 3 * P.part_cap;
+    auto scale_basis = [&](double* v, const double* hv) {
+        if (fuse_sum) {
+            unsigned nps = 0;
+            launch_fg_scale_sum(st, v, hv, n, ncell, H->part(), &nps);
+            launch_reduce_parts(st, H->part(), nps, 1, H->dsc() + 48);
+        } else {
+            launch_fg_scale(st, v, hv, n);
+        }
+    };
     if (warm) {
         // (c, lam) hold the initial guess; the scale of the residual is |b| = |[f; phi]|
         unsigned np = 0;
@@ -1550,7 +1564,7 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
         if (stalled >= 2) break;
         prev_rel = rel;
         ++cycles;
-        launch_fg_scale(st, V, sd, n);
+        scale_basis(V, sd);
         launch_fg_gstart(st, gv, ld, sd);
         H->alg_bytes += (double)n * 16;
         int k = 0;
@@ -1558,7 +1572,7 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
             double* vj = V + (size_t)j * stride;
             double* zj = Z + (size_t)j * stride;
             double* w = V + (size_t)(j + 1) * stride;
-            fg_precond<T>(H, alpha, o, vj, vj + ncell, zj, zj + ncell);
+            fg_precond<T>(H, alpha, o, vj, vj + ncell, zj, zj + ncell, fuse_sum);
             fg_apply_K(H, alpha, zj, zj + ncell, w, w + ncell);
             double* col = Hd + (size_t)j * ld;
             if (group >= 1) {
@@ -1582,7 +1596,7 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
                     H->alg_bytes += (double)n * 8 * ((vprev ? 3 : 1) + (vnext ? 1 : 0));
                 }
             }
-            launch_fg_scale(st, w, col + j + 1, n);
+            scale_basis(w, col + j + 1);
             H->alg_bytes += (double)n * 16;
             launch_fg_givens(st, Hd, ld, cs, sn, gv, j, sd + 2);
             sync_read(H, H->hbuf, sd + 2, 16);

@@ -933,6 +933,31 @@ void launch_fg_scale(hipStream_t st, double* w, const double* h, size_t n) {
     hipLaunchKernelGGL(k_fg_scale, dim3(nblocks((n + 1) / 2)), dim3(kBlock), 0, st, w, h, (unsigned)n);
 }
 
+// w *= 1 / *h over the n entries, and block partial sums of the scaled grid part (the
+// first ncell entries) into part[block], as k_norm_partials' first component: the sum the
+// preconditioner's mean step reads next, without its own pass over w.
+__global__ void __launch_bounds__(kBlock) k_fg_scale_sum(double* __restrict__ w, const double* __restrict__ h,
+                                                         unsigned n, unsigned ncell, double* part) {
+    const double hv = *h;
+    const double inv = hv > 0.0 ? 1.0 / hv : 0.0;
+    unsigned lo, hi;
+    chunk_of(blockIdx.x, gridDim.x, n, &lo, &hi);
+    double a[1] = {0.0};
+    for (unsigned idx = lo + threadIdx.x; idx < hi; idx += blockDim.x) {
+        const double v = w[idx] * inv;
+        w[idx] = v;
+        if (idx < ncell) a[0] += v;
+    }
+    block_partials<1>(a, part, gridDim.x, blockIdx.x);
+}
+
+void launch_fg_scale_sum(hipStream_t st, double* w, const double* h, size_t n, size_t ncell, double* part,
+                         unsigned* np) {
+    const unsigned nb = red_blocks(n);
+    hipLaunchKernelGGL(k_fg_scale_sum, dim3(nb), dim3(kBlock), 0, st, w, h, (unsigned)n, (unsigned)ncell, part);
+    *np = nb;
+}
+
 // r = b - r (sub) or r = b, with b = [bg; 0]; partials of r.r
 __global__ void __launch_bounds__(kBlock) k_fg_resid(double* __restrict__ r, const double* __restrict__ bg,
                                                      unsigned ncell, unsigned n, int sub, double* part, double phi) {

@@ -67,6 +67,8 @@ void launch_fg_cgs_update(hipStream_t st, double* w, const double* V, size_t str
 void launch_fg_fin(hipStream_t st, const double* part, unsigned np, double* out, int take_sqrt);
 // w /= *h (0 if *h == 0)
 void launch_fg_scale(hipStream_t st, double* w, const double* h, size_t n);
+void launch_fg_scale_sum(hipStream_t st, double* w, const double* h, size_t n, size_t ncell, double* part,
+                         unsigned* np);
 // r = [bg; phi] - r (sub) or [bg; phi] (phi a constant on every blob); partials of r.r
 void launch_fg_resid(hipStream_t st, double* r, const double* bg, size_t ncell, size_t n, int sub, double* part,
                      unsigned* np, double phi = 0.0);
