@@ -1435,14 +1435,14 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
             // S v enters the V-cycle from the contribution lists: level-0 f is zero
             // outside the touched cells after the first product of the loop. With from_f
             // the opening black sweep takes the red zero-guess sweep as f_red / diag, so the
-            // stale red u of the previous product need not be cleared.
+            // stale red u of the previous product need not be cleared, nor the touched red u written.
             if (!from_f) launch_zero<T>(st, z0, nh);
             if (k == 0) {
                 launch_zero<T>(st, f0, nh);
                 launch_zero<T>(st, f1, nh);
             }
-            launch_spread_enter<T>(st, L, SpreadMult{vk, nullptr, 0.0, 0.0}, nullptr, H->inv_h3(), f0, f1, z0, d.nx,
-                                   d.ny, inv_diag);
+            launch_spread_enter<T>(st, L, SpreadMult{vk, nullptr, 0.0, 0.0}, nullptr, H->inv_h3(), f0, f1,
+                                   from_f ? nullptr : z0, d.nx, d.ny, inv_diag);
             H->alg_bytes += (double)nh * P.esz * ((k == 0 ? 2 : 0) + (from_f ? 0 : 1));
             vcycle<T>(H, alpha, nullptr, nullptr, cinv, true, nullptr, from_f);
             launch_interp_split<T>(st, z0, z1, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),

@@ -480,7 +480,7 @@ __global__ void __launch_bounds__(kBlock) k_spread_enter(SpreadLists L, SpreadMu
         f1[j] = (T)r;
     } else {
         f0[j] = (T)r;
-        u0[j] = (T)((T)r * (T)inv_diag);
+        if (u0) u0[j] = (T)((T)r * (T)inv_diag);  // null: the cycle opens from f
     }
 }
 

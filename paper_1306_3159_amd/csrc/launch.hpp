@@ -205,7 +205,8 @@ void launch_spread_plan(hipStream_t st, int mode, BlobGeom g, const int* base, c
 void launch_spread_sparse(hipStream_t st, const SpreadLists& L, const SpreadMult& M, const double* base_in,
                           double* out, double scale, const Scalars* sc);
 // V-cycle entry of r = base + scale S m at the touched cells (split f, u_red = f_red / diag);
-// u0, and f0/f1 elsewhere, must already hold zeros (no base) or k_enter's values of base_in
+// u0, and f0/f1 elsewhere, must already hold zeros (no base) or k_enter's values of base_in.
+// u0 null: u_red is not written (a cycle that opens from f)
 template <typename T>
 void launch_spread_enter(hipStream_t st, const SpreadLists& L, const SpreadMult& M, const double* base_in,
                          double scale, T* f0, T* f1, T* u0, int nx, int ny, double inv_diag);
