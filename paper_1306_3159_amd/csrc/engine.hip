@@ -1299,6 +1299,16 @@ void fg_resid(blob_rd* H, double alpha, const double* base, const SpreadMult* M,
     H->alg_bytes += (double)P.ncell * 24;
 }
 
+// The periodic V-cycle can open from f (the opening black sweep forms the red zero-guess
+// sweep as f_red / diag): level 0 in the LDS tail, or rows of the vector sweep.
+template <typename T>
+bool cycle_opens_from_f(const blob_rd* H) {
+    const Plan& P = H->P;
+    const int t0 = std::min(H->tail_level[sizeof(T) == 4 ? 0 : 1], P.nlev - 1);
+    const int vw = 16 / (int)sizeof(T);
+    return !H->box && (t0 == 0 || (P.lev[0].hx % vw == 0 && P.lev[0].hx >= vw));
+}
+
 // n multigrid cycles for A x = r, r = base + scale S m (M null: r = base), as a
 // stationary iteration: from a zero guess the first cycle is x = V r (base
 // enters the V-cycle densely and the spread term at the touched cells, so r is
@@ -1315,6 +1325,7 @@ void fg_cycles(blob_rd* H, double alpha, const double* base, const SpreadMult* M
     T* f0 = H->at<T>(P.off_lvl[0][2]);
     T* f1 = H->at<T>(P.off_lvl[0][3]);
     double* q = H->grid(G_Q);
+    const bool from_f = from_zero && cycle_opens_from_f<T>(H);
     for (int k = 0; k < n; ++k) {
         if (k == 0 && from_zero) {
             if (H->box) {
@@ -1322,11 +1333,13 @@ void fg_cycles(blob_rd* H, double alpha, const double* base, const SpreadMult* M
                 box_coefs(H, 0, alpha, nullptr, &binv);
                 launch_enter_box<T>(H->st, base, f0, f1, z0, d.nx, d.ny, d.nz, binv, nullptr);
             } else {
-                launch_enter<T>(H->st, base, f0, f1, z0, d.nx, d.ny, d.nz, inv_diag, nullptr);
+                launch_enter<T>(H->st, base, f0, f1, from_f ? nullptr : z0, d.nx, d.ny, d.nz, inv_diag, nullptr);
             }
-            if (M) launch_spread_enter<T>(H->st, spread_lists(H), *M, base, scale, f0, f1, z0, d.nx, d.ny, inv_diag);
-            H->alg_bytes += (double)P.ncell * (8 + 1.5 * P.esz);
-            vcycle<T>(H, alpha, nullptr, nullptr, cinv, true);
+            if (M)
+                launch_spread_enter<T>(H->st, spread_lists(H), *M, base, scale, f0, f1, from_f ? nullptr : z0, d.nx,
+                                       d.ny, inv_diag);
+            H->alg_bytes += (double)P.ncell * (8 + (from_f ? 1.0 : 1.5) * P.esz);
+            vcycle<T>(H, alpha, nullptr, nullptr, cinv, true, nullptr, from_f);
             launch_split_to_nat<T>(H->st, z0, z1, x, d.nx, d.ny, d.nz, 0.0);
             H->alg_bytes += (double)P.ncell * (P.esz + 8);
         } else {
@@ -1422,10 +1435,7 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
         T* f1 = H->at<T>(P.off_lvl[0][3]);
         const size_t nh = P.ncell / 2;
         const double inv_diag = 1.0 / (alpha + 6.0 * H->prm.D / (d.h * d.h));
-        // the periodic V-cycle can open from f (level 0 in the LDS tail, or rows of the vector form)
-        const int t0 = std::min(H->tail_level[sizeof(T) == 4 ? 0 : 1], P.nlev - 1);
-        const int vw = 16 / (int)sizeof(T);
-        const bool from_f = !H->box && (t0 == 0 || (d.hx % vw == 0 && d.hx >= vw));
+        const bool from_f = cycle_opens_from_f<T>(H);
         for (int k = 0; k < o.m; ++k) {
             const double* vk = V + (size_t)k * N;
             if (learned) {

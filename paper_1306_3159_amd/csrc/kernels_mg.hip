@@ -30,7 +30,8 @@ __device__ __forceinline__ T nb_sum(const T* __restrict__ uo, int i, int y, int 
 
 // ---------------------------------------------------------------------------
 // Fine-level entry: f = r - mean_r (FP64 natural -> T split) and the first red
-// half-sweep from a zero initial guess, u_red = f_red / diag.
+// half-sweep from a zero initial guess, u_red = f_red / diag (not stored when u0 is
+// null: the cycle's opening black sweep then forms it from f).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_enter(const double* __restrict__ r, T* __restrict__ f0,
                                                   T* __restrict__ f1, T* __restrict__ u0, int hx, int ny, int nz,
@@ -49,7 +50,7 @@ __global__ void __launch_bounds__(kBlock) k_enter(const double* __restrict__ r, 
     const double fb = r[rowN + 2 * i + (s0 ^ 1)] - m;
     f0[idx] = (T)fr;
     f1[idx] = (T)fb;
-    u0[idx] = (T)((T)fr * (T)inv_diag);
+    if (u0) u0[idx] = (T)((T)fr * (T)inv_diag);  // null: the cycle opens from f
 }
 
 template <typename T>
