@@ -59,7 +59,7 @@ def parse():
 # rotating launches), scaled by what the same counters read for a 1 GiB device
 # copy (FETCH_SIZE reports half the bytes read, WRITE_SIZE all bytes written).
 # Valid only for the kernel source the counters were taken on.
-TRAFFIC = {"source_sha256": "ed78cb548390e8ffb95315fa4ff6debaf589e2e212e9e6432ed11d9e661ab97c",
+TRAFFIC = {"source_sha256": "64f992908b027878b0cc1adce1ded5c37b01dd7bd1cd9e336be4a9e27e0f8321",
            "fetch_kib": 33813.0, "write_kib": 32768.0, "fetch_scale": 1.9999, "write_scale": 1.0}
 
 
