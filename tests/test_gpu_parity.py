@@ -97,9 +97,12 @@ def test_vcycle_parity_fp64(dev, shape, alpha):
 
 
 @pytest.mark.parametrize("alpha", [0.0, 2.0])
-def test_vcycle_parity_mixed(dev, alpha):
-    _say("vcycle mixed", alpha)
-    shape = (64, 64, 64)
+@pytest.mark.parametrize("shape", [(64, 64, 64), (48, 48, 48), (24, 40, 56)])
+def test_vcycle_parity_mixed(dev, alpha, shape):
+    """FP32 V-cycle against the FP64 oracle cycle. 64^3 and 48^3 run the vector forms of every
+    per-level kernel (the four-row-block restriction included); on 24 x 40 x 56 the second
+    level has 14-cell rows, so its correction and restriction take the one-cell forms."""
+    _say("vcycle mixed", alpha, shape)
     rng = np.random.default_rng(8)
     r = rng.standard_normal(shape)
     if alpha == 0.0:
