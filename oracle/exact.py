@@ -333,8 +333,9 @@ def absorbing_residual(c, lam, f, q, alpha, D=1.0, h=1.0, w=4, phi=None) -> floa
 
 
 def radius_from_mean(cbar: float, s: float, V: float, D: float = 1.0) -> float:
-    """a_L = [4 pi D cbar]^{-1} for total source s V = 1 (eq. beta0_low_phi)."""
-    return 1.0 / (4.0 * math.pi * D * cbar * s * V)
+    """a_L = s V / (4 pi D cbar) (eq. beta0_low_phi): the one sink absorbs the whole source
+    s V at the Smoluchowski rate 4 pi D a_L cbar, so a_L does not depend on the source."""
+    return s * V / (4.0 * math.pi * D * cbar)
 
 
 def radius_extrapolated(aL: float, L: float) -> float:

@@ -83,9 +83,11 @@ def _cell_mean(n: int, q, dev, w: int, kappa=None, precision=FP64, rtol=1e-10) -
 
 
 def radius(n: int, q, dev, w: int = 4) -> Dict[str, float]:
-    """a_L and the extrapolated a of one blob at q in an n^3 box (h = D = 1)."""
+    """a_L and the extrapolated a of one blob at q in an n^3 box (h = D = 1). The cell's
+    source is s = 1/V, so the sink absorbs s V = 1 and a_L = s V / (4 pi D cbar) = 1/(4 pi cbar)."""
     cbar = _cell_mean(n, q, dev, w)
-    aL = 1.0 / (4.0 * math.pi * cbar)
+    sV = 1.0
+    aL = sV / (4.0 * math.pi * cbar)
     return {"L": n, "a_L": aL, "a": radius_extrapolated(aL, n), "cbar": cbar}
 
 

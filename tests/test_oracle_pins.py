@@ -274,6 +274,25 @@ def test_negative_concentration_inside_absorbing_blob():
     assert abs(np.sum(Wt * sup)) < 1e-9 * np.abs(c).max()
 
 
+def test_reaction_radius_independent_of_source_and_D():
+    """Sec. IV.A, eq. beta0_low_phi: the single sink absorbs the total source s V at the rate
+    4 pi D a_L cbar, so a_L = s V / (4 pi D cbar) is a property of the blob and the box alone.
+    Tripling the source triples cbar and doubling D halves it; a_L must not move (1e-12)."""
+    n = 16
+    V = float(n ** 3)
+    q = np.array([[7.3, 8.1, 8.6]])
+    ref = None
+    for s, D in ((1.0 / V, 1.0), (3.0 / V, 1.0), (1.0 / V, 2.0), (3.0 / V, 0.5)):
+        c, lam = ex.solve_absorbing(np.full((n, n, n), s), q, 0.0, D=D)
+        assert lam[0] == pytest.approx(s * V, rel=1e-12)
+        a = ex.radius_from_mean(c.mean(), s, V, D)
+        if ref is None:
+            ref = a
+        assert a == pytest.approx(ref, rel=1e-12)
+    # at L = 16h the finite-box a_L is about 27 % above a; eq. a_phi brings it back near 1.27h
+    assert 1.22 < ex.radius_extrapolated(ref, n) < 1.32
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("w,key", [(4, "radius_phi4_node"), (3, "radius_phi3_node")])
 def test_reaction_radius_at_node(w, key):
