@@ -59,6 +59,18 @@ def _solo(dev, inst, prec):
     return res
 
 
+def _oracle_check(inst, cs, ls, rtol=1e-8):
+    """Every batched answer meets the tolerance by the oracle's own FP64 residual (so a fault
+    shared by the batched and the solo path, e.g. in the spread lists, cannot pass)."""
+    from oracle import exact as ex
+    for (n, q, kap, kind, f), c, l in zip(inst, cs, ls):
+        if kind == 0:
+            r = ex.reactive_residual(c.cpu().numpy(), f, q, kap, 0.0)
+        else:
+            r = ex.absorbing_residual(c.cpu().numpy(), l.cpu().numpy(), f, q, 0.0)
+        assert r <= rtol, (n, q.shape[0], kind, r)
+
+
 @pytest.mark.parametrize("prec,max_cells", [(1, 0), (0, 0), (1, 300000)])
 def test_batched_matches_solo(dev, prec, max_cells):
     """All instances in the lock-step launches (max_cells 0), or only grids up to 64^3 with the
@@ -83,6 +95,8 @@ def test_batched_matches_solo(dev, prec, max_cells):
             if l0 is not None:
                 assert np.array_equal(l.cpu().numpy(), l0)
             assert st["outer_iters"] == st0["outer_iters"]
+        if rep == 0:
+            _oracle_check(inst, cs, ls)
     # the handles still solve alone afterwards
     n, q, kap, kind, f = inst[0]
     c, st = Hs[0].solve_reactive(torch.tensor(f, device=dev))
@@ -161,5 +175,7 @@ def test_batched_with_block_solver_instances(dev):
             assert np.array_equal(c.cpu().numpy(), c0)
             if l0 is not None:
                 assert np.array_equal(l.cpu().numpy(), l0)
+        if runner == "batched":
+            _oracle_check(inst, cs, ls)
     for S in Hs:
         S.close()

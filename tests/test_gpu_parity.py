@@ -80,6 +80,43 @@ def test_interp_spread_apply_parity(dev, shape, N, h, w):
     S.close()
 
 
+# The densest batch suspensions (RSA capped at an excluded-volume fraction of 1/4: 579 blobs on
+# 32^3, 1955 on 48^3) put about 9 and 18 blobs in each 8^3 tile, so a tile's 27-tile neighbourhood
+# holds 250-500 candidates and the spread plan stages them in LDS over several passes.
+DENSE = [(32, 579, 4), (32, 579, 3), (48, 1955, 4), (48, 1955, 3)]
+
+
+@pytest.mark.parametrize("n,N,w", DENSE)
+def test_interp_spread_apply_parity_dense(dev, n, N, w):
+    _say("interp/spread/apply dense", n, N, w)
+    assert N == W.rsa_cap(n)
+    rng = np.random.default_rng(700 + N + w)
+    q = W.rsa_positions(rng, n, N, 3.0)
+    # candidates of the busiest 8^3 tile (blobs whose base cell lies in it or its 26 neighbours)
+    # exceed the 128 that one LDS staging pass holds
+    nt = n // 8
+    tiles = (np.floor(q - 0.5).astype(int) % n) // 8
+    cnt = np.zeros((nt,) * 3, int)
+    np.add.at(cnt, (tiles[:, 2], tiles[:, 1], tiles[:, 0]), 1)
+    cand = sum(np.roll(cnt, (a, b, c), (0, 1, 2)) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1))
+    assert cand.max() > 128
+    kappa = W.log_uniform(rng, 1e-2, 1e2, N)
+    shape = (n, n, n)
+    c = rng.standard_normal(shape)
+    lam = rng.standard_normal(N)
+    S = make(dev, shape, q, kappa, kernel_w=w)
+    jc = H(S.interp(T(c, dev)))
+    assert np.max(np.abs(jc - ex.interp(c, q, 1.0, w))) < 1e-13 * max(1, np.abs(jc).max())
+    sl = H(S.spread(T(lam, dev)))
+    ref = ex.spread(lam, q, shape, 1.0, w)
+    assert np.max(np.abs(sl - ref)) < 1e-13 * np.abs(ref).max()
+    for alpha in (0.0, 0.37):
+        y = H(S.apply(T(c, dev), alpha, True))
+        refy = ex.apply_B(c, q, kappa, alpha, 1.0, 1.0, w)
+        assert np.max(np.abs(y - refy)) < 1e-12 * np.abs(refy).max()
+    S.close()
+
+
 # ------------------------------------------------------------------ multigrid
 @pytest.mark.parametrize("shape", [(32, 32, 32), (48, 48, 48), (16, 32, 24), (64, 64, 64)])
 @pytest.mark.parametrize("alpha", [0.0, 2.0])
@@ -112,6 +149,9 @@ def test_vcycle_parity_mixed(dev, alpha, shape):
     z = H(S.vcycle(T(r, dev), alpha))
     zr = it.vcycle(r, alpha)
     assert rel(z, zr) < 2e-6
+    # element by element: a local slip in one of the ragged one-cell forms would pass the norm
+    # check; 1e-5 of the field's largest value is about 100 FP32 units in the last place
+    assert np.max(np.abs(z - zr)) < 1e-5 * np.abs(zr).max()
     S.close()
 
 
@@ -437,6 +477,32 @@ def test_rsa256_absorbing_full_size(dev, rsa256):
     assert ex.absorbing_residual(c, lam, inst.f, inst.q, 0.0) <= 1e-8
     assert lam.sum() == pytest.approx(inst.f.sum(), rel=1e-12)
     S.close()
+
+
+def test_rsa256_learned_block_fgmres_full_size(dev):
+    """The learned + FP32 headline solve at full size: 256^3, 10^4 RSA blobs, f = 1, the
+    committed network weights, block FGMRES(30) with the approximate-Schur preconditioner
+    (m = 5, n = 1) whose inner GMRES is right-preconditioned by W, FP32 V-cycles. The oracle's
+    FP64 saddle residual of the answer meets 1e-8, the multipliers carry the whole source
+    (sum(lam) = h^3 sum(f), Appendix A) and the network was used (no fallback)."""
+    import os
+    from paper_1306_3159_amd import BlobRD, Net, MIXED, PRECOND_LEARNED
+    inst = W.learned_eval(256, 10000, index=0)
+    _say("rsa256 learned block FGMRES", inst.seed)
+    wpath = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1306_3159_amd",
+                         "weights", "precond_rsa256.npy")
+    net = Net(dev)
+    net.set_params(torch.tensor(np.load(wpath), device=dev))
+    S = BlobRD(inst.n, T(inst.q, dev), precision=MIXED, schur_precond=PRECOND_LEARNED, rtol=1e-8)
+    S.precond_build(net)
+    c, lam, st = S.solve_absorbing_fgmres(T(inst.f, dev), precond="learned", m=5, n=1, restart=30)
+    print("rsa256 learned block FGMRES", st, flush=True)
+    assert st["rc"] == 0 and st["fallback"] == 0, st
+    c, lam = H(c), H(lam)
+    assert ex.absorbing_residual(c, lam, inst.f, inst.q, 0.0) <= 1e-8
+    assert lam.sum() == pytest.approx(inst.f.sum(), rel=1e-12)
+    S.close()
+    net.close()
 
 
 def test_rsa256_backward_euler(dev, rsa256):
