@@ -117,7 +117,7 @@ def bench_batch(args, dev, rtol):
     (their inner CG iterations in the lock-step launches too)."""
     import torch
     import workloads as W
-    from paper_1306_3159_amd import BlobRD, MIXED, SOLVER_BLOCK, SOLVER_SCHUR, solve_batch, solve_batched
+    from paper_1306_3159_amd import BlobRD, MIXED, SOLVER_BLOCK, SOLVER_SCHUR, solve_streams, solve_batched
     insts = W.batch_instances()
 
     def handles(solver):
@@ -148,7 +148,7 @@ def bench_batch(args, dev, rtol):
         for c in cs:
             c.zero_()
         torch.cuda.synchronize()
-        return solve_batch(Hs, kinds, fs, cs, ls, threads=args.threads)
+        return solve_streams(Hs, kinds, fs, cs, ls, threads=args.threads)
 
     dt, (rc, stats) = timed(step_lockstep, args.steps, args.warmup)
     sdt, (src, sstats) = timed(step_streams, max(2, args.steps // 2), 1)

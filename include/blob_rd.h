@@ -316,6 +316,53 @@ int blob_rd_net_adam_step(blob_rd_net_t net, float lr);
 int blob_rd_precond_build(blob_rd_t h, blob_rd_net_t net, void* buf, size_t bytes, size_t* needed);
 /* z = P W P r (N-vectors, device). */
 int blob_rd_precond_apply(blob_rd_t h, const double* r, double* z);
+/* ---- The handle's own network ----
+ *
+ * A periodic handle with at least one blob created with schur_precond =
+ * BLOB_RD_PRECOND_LEARNED or saddle_solver = BLOB_RD_SOLVER_BLOCK_LEARNED owns
+ * a network (its parameters, Adam moments and gradient) and room for W in its
+ * workspace (blob_rd_workspace_bytes counts both: about 20 MB for the network
+ * plus 20 B per pair for up to BLOB_RD_LEARNED_ROW_CAP pairs per blob on
+ * average). Its network starts untrained (zero parameters: W is the
+ * diagonal above), and blob_rd_create builds that W (ENOMEM there when the
+ * blobs have more pairs than the room). The three calls below act on that network and keep the
+ * handle's W built from it; other handles return EINVAL. blob_rd_precond_build
+ * with another network still replaces W (in the caller's buffer). */
+#define BLOB_RD_LEARNED_ROW_CAP 256
+
+/* The network's inference weights as one host byte blob, little endian:
+ * W1 bfloat16 [64][10] | b1 float32 [64] | W2 bfloat16 [64][64] | b2 float32 [64] |
+ * w3 bfloat16 [64] | b3 float32, packed without padding (10116 bytes). */
+#define BLOB_RD_PRECOND_BLOB_BYTES 10116
+
+/* Set the handle's network from a weight blob (host memory, bytes =
+ * BLOB_RD_PRECOND_BLOB_BYTES; the weights become the float32 masters exactly),
+ * reset its Adam state and build W (pair list of the handle's blobs, network
+ * evaluated on the GPU). Non-finite weights give a W that solves never use
+ * (stats.fallback = 1). Errors: EINVAL (null pointer, wrong size, a handle
+ * without its own network), ENOMEM (more pairs than the reserved room), EDEVICE. */
+int blob_rd_precond_set_weights(blob_rd_t h, const void* bf16_blob, size_t bytes);
+/* Copy the handle's network out as a weight blob (host memory), its float32
+ * masters rounded to bfloat16 (nearest, ties to even) where the blob holds bf16. */
+int blob_rd_precond_get_weights(blob_rd_t h, void* bf16_blob, size_t bytes);
+
+/* Sample pairs of one training step for one handle: rows x_s and y_s = P M P x_s
+ * (M the handle's Schur complement, say from blob_rd_schur_apply), device
+ * [n_samples][N] doubles, 1 <= n_samples <= 64 and 2 n_samples N + 64 <= cells. */
+typedef struct {
+    int32_t n_samples;
+    const double* x;
+    const double* y;
+} blob_rd_train_batch;
+
+/* One training step of the handle's network on the loss above: the loss and its
+ * gradient over the batch (W built from the current weights), one Adam step
+ * with learning rate lr (as blob_rd_net_adam_step), then W rebuilt from the new
+ * weights. batch_desc points to a blob_rd_train_batch; *loss (host, may be NULL)
+ * receives the loss before the step. Errors: EINVAL (null pointer, lr not
+ * positive, bad batch, a handle without its own network), ENOMEM, EDEVICE. */
+int blob_rd_precond_train_step(blob_rd_t h, const void* batch_desc, float lr, float* loss);
+
 /* Copy the CSR of W (rows ascending, columns ascending) to device buffers; any may be NULL. */
 int blob_rd_precond_csr(blob_rd_t h, int64_t* nnz, int32_t* rowptr, int32_t* col, double* val);
 /* Loss over S sample pairs (X, Y device [S][N], rows x_s and y_s) and its
@@ -343,8 +390,8 @@ int blob_rd_schur_apply_cycles(blob_rd_t h, double alpha, const double* x, doubl
  * results are bitwise those of solving each instance alone. Returns the
  * first hard error, else BLOB_RD_ENOTCONV if any instance missed its
  * tolerance, else 0; stats (may be NULL) receives one entry per instance. */
-int blob_rd_solve_batch(blob_rd_t* h, int32_t n, const int32_t* kind, double alpha, const double* const* f,
-                        double* const* c, double* const* lambda, int32_t threads, blob_rd_stats* stats);
+int blob_rd_solve_streams(blob_rd_t* h, int32_t n, const int32_t* kind, double alpha, const double* const* f,
+                          double* const* c, double* const* lambda, int32_t threads, blob_rd_stats* stats);
 
 /* Lock-step batched form of the same. The CG iterations of the member
  * instances run as one sequence of batched launches (one launch per step,
@@ -366,6 +413,33 @@ size_t blob_rd_batch_workspace_bytes(int32_t n);
 int blob_rd_solve_batched(blob_rd_t* h, int32_t n, const int32_t* kind, double alpha, const double* const* f,
                           double* const* c, double* const* lambda, int64_t lockstep_max_cells, int32_t threads,
                           void* workspace, size_t workspace_bytes, void* stream, blob_rd_stats* stats);
+
+/* A batch handle: n_inst instances, each created from p[i] exactly as by
+ * blob_rd_create (own workspace, stream, precision, solver), with the solve
+ * kind[i] (0 reactive, 1 absorbing) that blob_rd_solve_batch runs on it. The
+ * executor's descriptor tables live in member 0's workspace, which must hold
+ * blob_rd_workspace_bytes(&p[0]) + blob_rd_batch_workspace_bytes(n_inst)
+ * bytes (the tables take the tail). The executor runs on a stream of its own
+ * (created here, default priority). A separate handle type keeps batch and
+ * single-instance calls apart. Errors: EINVAL (bad kind, an absorbing
+ * instance without blobs, any member's create error), ENOMEM, EDEVICE. */
+typedef struct blob_rd_batch* blob_rd_batch_t;
+int blob_rd_create_batch(const blob_rd_params* p, int32_t n_inst, const int32_t* kind, blob_rd_batch_t* out);
+/* Destroys the members too. NULL is accepted. */
+int blob_rd_destroy_batch(blob_rd_batch_t b);
+/* Member i (owned by the batch: tune it, solve it alone, never destroy it), NULL if out of range. */
+blob_rd_t blob_rd_batch_member(blob_rd_batch_t b, int32_t i);
+/* Executor settings of blob_rd_solve_batch (lockstep_max_cells and threads as in
+ * blob_rd_solve_batched); defaults 64^3 cells and 8 threads. */
+int blob_rd_batch_set_executor(blob_rd_batch_t b, int64_t lockstep_max_cells, int32_t threads);
+/* Steady solves (alpha = 0) of every member by the lock-step executor of
+ * blob_rd_solve_batched: f[i], c[i] grid vectors of member i (c[i] the initial
+ * guess of a reactive member), lambda[i] the multipliers of an absorbing member
+ * (ignored for reactive ones; lambda may be NULL when no member is absorbing).
+ * stats (may be NULL) receives one entry per member. Returns the first hard
+ * error, else ENOTCONV if a member missed its tolerance, else 0. */
+int blob_rd_solve_batch(blob_rd_batch_t b, const double* const* f, double* const* c, double* const* lambda,
+                        blob_rd_stats* stats);
 
 /* ---- Measurement ---- */
 

@@ -28,6 +28,15 @@ method's own Schur operator,
     loss = (1/S) sum_s || P W y_s - x_s ||^2 / || x_s ||^2,
 
 with Adam (Kingma and Ba, 2015) on float32 master weights.
+
+Two arithmetic models of the same network. The default evaluates everything in
+float64 on the bf16-rounded weights. With mfma_operands=True the oracle also
+rounds to bfloat16 every operand that a bf16 matrix-unit product takes: the
+features (layer 1) and the first hidden activations (layer 2) in the forward
+pass, and the pre-activation gradients of layers 2 and 1 where they enter the
+products of the backward pass (d h1 = d a2 W2, the W2 and W1 gradients). The
+products and all sums stay float64; the rounding is treated as identity when
+differentiating (as the hardware path does).
 """
 from __future__ import annotations
 
@@ -142,34 +151,41 @@ def rounded(p: Dict[str, np.ndarray]) -> Dict[str, np.ndarray]:
     return out
 
 
-def forward(p: Dict[str, np.ndarray], X: np.ndarray):
+def _operand(a, mfma_operands):
+    """A matrix-product operand: bfloat16-rounded in the matrix-unit model, else as is."""
+    return bf16_round(a) if mfma_operands else a
+
+
+def forward(p: Dict[str, np.ndarray], X: np.ndarray, mfma_operands: bool = False):
     """g for each feature row of X (float64), with the cache needed by backward."""
-    a1 = X @ p["W1"].T + p["b1"]
-    h1 = silu(a1)
+    Xo = _operand(X, mfma_operands)
+    a1 = Xo @ p["W1"].T + p["b1"]
+    h1 = _operand(silu(a1), mfma_operands)
     a2 = h1 @ p["W2"].T + p["b2"]
     h2 = silu(a2)
     g = h2 @ p["w3"] + p["b3"][0]
-    return g, (X, a1, h1, a2, h2)
+    return g, (Xo, a1, h1, a2, h2, mfma_operands)
 
 
 def backward(p, cache, dg):
-    X, a1, h1, a2, h2 = cache
+    X, a1, h1, a2, h2, mfma_operands = cache
     grads = {"w3": h2.T @ dg, "b3": np.array([dg.sum()])}
     da2 = np.outer(dg, p["w3"]) * dsilu(a2)
-    grads["W2"] = da2.T @ h1
     grads["b2"] = da2.sum(0)
-    da1 = (da2 @ p["W2"]) * dsilu(a1)
-    grads["W1"] = da1.T @ X
+    da2o = _operand(da2, mfma_operands)
+    grads["W2"] = da2o.T @ h1
+    da1 = (da2o @ p["W2"]) * dsilu(a1)
     grads["b1"] = da1.sum(0)
+    grads["W1"] = _operand(da1, mfma_operands).T @ X
     return grads
 
 
-def assemble(p_rounded, q, n, h=1.0, D=1.0, rc=RC):
+def assemble(p_rounded, q, n, h=1.0, D=1.0, rc=RC, mfma_operands=False):
     """CSR of W: (ptr, col, val, cache) with val_ij = D h (diag + (g_ij + g_ji)/2)."""
     ptr, col = pair_list(q, n, h, rc)
     row = np.repeat(np.arange(q.shape[0]), np.diff(ptr))
     X = np.concatenate([features(q, n, row, col, h, rc), features(q, n, col, row, h, rc)])
-    g, cache = forward(p_rounded, X)
+    g, cache = forward(p_rounded, X, mfma_operands)
     m = row.size
     val = D * h * (0.5 * (g[:m] + g[m:]) + (row == col) * 4.0 * math.pi * A0)
     return ptr, col, val, (row, cache, m)
@@ -192,12 +208,13 @@ def apply(ptr, col, val, r):
 
 
 def loss_and_grad(params: Dict[str, np.ndarray], q, n, X_s: np.ndarray, Y_s: np.ndarray, h=1.0, D=1.0,
-                  rc=RC, want_grad=True, round_weights=True):
+                  rc=RC, want_grad=True, round_weights=True, mfma_operands=False):
     """loss = (1/S) sum_s |P W y_s - x_s|^2 / |x_s|^2 and its gradient w.r.t. the
     float32 master parameters (the rounding to bfloat16 is treated as identity;
-    round_weights=False evaluates everything with unrounded float64 weights)."""
+    round_weights=False evaluates everything with unrounded float64 weights;
+    mfma_operands selects the matrix-unit model of the module docstring)."""
     pr = rounded(params) if round_weights else {k: np.asarray(params[k], np.float64) for k in PARAM_ORDER}
-    ptr, col, val, (row, cache, m) = assemble(pr, q, n, h, D, rc)
+    ptr, col, val, (row, cache, m) = assemble(pr, q, n, h, D, rc, mfma_operands)
     S = X_s.shape[0]
     loss = 0.0
     GW = np.zeros(val.size)

@@ -102,6 +102,8 @@ struct Plan {
     size_t off_sp_cnt = 0, off_sp_off = 0, off_tcell = 0, off_tptr = 0, off_tblob = 0, off_tw = 0;
     // flexible-GMRES basis of the block solvers (handles that use them)
     size_t off_fg = 0, fg_size = 0;
+    // handle-owned learned preconditioner: network state and room for the CSR of W
+    size_t off_net = 0, off_lrn = 0, lrn_size = 0;
     size_t off_nv[12]{};
     size_t off_V = 0, off_H = 0, off_cs = 0, off_sn = 0, off_gv = 0, off_yv = 0;
     size_t total = 0;
@@ -114,6 +116,9 @@ size_t fg_bytes(const Plan& P, int restart) {
     const size_t ld = (size_t)restart + 1;
     return (2 * (size_t)restart + 1) * fg_stride(P) * 8 + (ld * restart + 5 * ld + 8) * 8 + 256;
 }
+
+size_t net_bytes();
+size_t learned_bytes(int N, long long nnz);
 
 int make_plan(const blob_rd_params* p, Plan* P, std::string* why) {
     if (!p) {
@@ -235,6 +240,12 @@ int make_plan(const blob_rd_params* p, Plan* P, std::string* why) {
         }
         P->fg_size = fg_bytes(*P, P->restart);
         P->off_fg = take(P->fg_size);
+    }
+    if ((p->schur_precond == BLOB_RD_PRECOND_LEARNED || p->saddle_solver == BLOB_RD_SOLVER_BLOCK_LEARNED) &&
+        p->boundary == BLOB_RD_BOUNDARY_PERIODIC && P->N > 0) {
+        P->off_net = take(net_bytes());
+        P->lrn_size = learned_bytes(P->N, (long long)P->N * BLOB_RD_LEARNED_ROW_CAP);
+        P->off_lrn = take(P->lrn_size);
     }
     P->total = o + 256;
     return 0;
@@ -362,6 +373,10 @@ struct blob_rd {
         PairGeom pg{};
     } lrn;
     int fallback = 0;
+    // network owned by the handle (handles created for the learned preconditioner): its state
+    // and W live in the handle's workspace; own_w says W was built from it
+    blob_rd_net* own_net = nullptr;
+    bool own_w = false;
     int ntouched = 0;  // cells with a nonzero spread weight (length of the contribution lists)
     // box with the concentration held at cb on its faces (solves work on u = c - cb)
     bool box = false;
@@ -1707,6 +1722,14 @@ size_t blob_rd_workspace_bytes(const blob_rd_params* p) {
     return P.total;
 }
 
+}  // extern "C"
+
+namespace {
+void own_build(blob_rd* H);
+}
+
+extern "C" {
+
 int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
     if (!out) {
         g_last_error = "null output handle";
@@ -1838,6 +1861,13 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
             HIPCHK(blocked_set_lds<float>());
             HIPCHK(blocked_set_lds<double>());
         }
+        if (P.off_net) {
+            // the handle's own network starts untrained: W is then the diagonal of eq. Schur_diagonal
+            if (blob_rd_net_create(H->ws + P.off_net, net_bytes(), (void*)st, &H->own_net) != BLOB_RD_OK)
+                throw Err(BLOB_RD_EDEVICE, "network set-up failed: " + g_last_error);
+            HIPCHK(hipStreamSynchronize(st));
+            own_build(H);
+        }
     } catch (const Err& e) {
         g_last_error = e.what();
         blob_rd_destroy(H);
@@ -1849,6 +1879,7 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
 
 int blob_rd_destroy(blob_rd_t H) {
     if (!H) return BLOB_RD_OK;
+    if (H->own_net) blob_rd_net_destroy(H->own_net);
     for (auto& g : H->graphs) (void)hipGraphExecDestroy(g.exec);
     H->graphs.clear();
     if (H->cap_stream) (void)hipStreamDestroy(H->cap_stream);
@@ -2677,52 +2708,65 @@ int blob_rd_net_adam_step(blob_rd_net_t N, float lr) {
     return hipGetLastError() == hipSuccess ? BLOB_RD_OK : BLOB_RD_EDEVICE;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Pair list of the handle's blobs and W from network Nt into buf (256-byte slack
+// included in learned_bytes); with buf null only *needed is set.
+int precond_build_into(blob_rd* H, blob_rd_net* Nt, void* buf, size_t bytes, size_t* needed) {
+    const int N = H->P.N;
+    const PairGeom pg = pair_geom(H);
+    int *rowptr_s, *cell, *offs, *prm;
+    const long long nnz = pair_count(H, pg, &rowptr_s, &cell, &offs, &prm);
+    const size_t need = learned_bytes(N, nnz);
+    if (needed) *needed = need;
+    if (!buf) return BLOB_RD_OK;
+    if (bytes < need) throw Err(BLOB_RD_ENOMEM, "precond buffer smaller than the size reported");
+    char* b = (char*)(((uintptr_t)buf + 255) & ~(uintptr_t)255);
+    if (b + need - 256 > (char*)buf + bytes) throw Err(BLOB_RD_ENOMEM, "precond buffer misaligned/too small");
+    auto& L = H->lrn;
+    L.rowptr = (int*)b;
+    b += align_up((size_t)(N + 1) * 4);
+    L.col = (int*)b;
+    b += align_up((size_t)nnz * 4);
+    L.rowidx = (int*)b;
+    b += align_up((size_t)nnz * 4);
+    L.val = (double*)b;
+    b += align_up((size_t)nnz * 8);
+    L.dg = (float*)b;
+    L.nnz = nnz;
+    L.pg = pg;
+    const double* q = H->at<double>(H->P.off_q);
+    HIPCHK(hipMemcpyAsync(L.rowptr, rowptr_s, (size_t)(N + 1) * 4, hipMemcpyDeviceToDevice, H->st));
+    launch_pair_fill(H->st, q, N, pg, cell, offs, prm, L.rowptr, L.col, L.rowidx);
+    launch_rowidx(H->st, L.rowptr, N, L.rowidx);
+    // the network's stream ordering: make sure its weights are current
+    HIPCHK(hipStreamSynchronize(Nt->st));
+    launch_net_assemble(H->st, q, pg, Nt->dev(), L.col, L.rowidx, nnz, H->prm.D * H->prm.h,
+                        4.0 * M_PI * 1.255, L.val);
+    int* bad = reinterpret_cast<int*>(H->dsc() + 40);
+    launch_count_bad(H->st, L.val, nnz, bad);
+    HIPCHK(hipMemcpyAsync(H->hbuf, bad, sizeof(int), hipMemcpyDeviceToHost, H->st));
+    HIPCHK(hipStreamSynchronize(H->st));
+    int nbad = 0;
+    std::memcpy(&nbad, H->hbuf, sizeof(int));
+    L.bad = nbad != 0;
+    L.ready = true;
+    H->own_w = Nt == H->own_net;
+    HIPCHK(hipGetLastError());
+    return BLOB_RD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int blob_rd_precond_build(blob_rd_t H, blob_rd_net_t Nt, void* buf, size_t bytes, size_t* needed) {
     if (!H || !Nt) return g_last_error = "null argument", BLOB_RD_EINVAL;
     if (H->P.N <= 0) return g_last_error = "no blobs", BLOB_RD_EINVAL;
     if (H->box) return g_last_error = "the learned preconditioner is for the periodic cell", BLOB_RD_EINVAL;
-    return guarded(H, nullptr, [&]() {
-        const int N = H->P.N;
-        const PairGeom pg = pair_geom(H);
-        int *rowptr_s, *cell, *offs, *prm;
-        const long long nnz = pair_count(H, pg, &rowptr_s, &cell, &offs, &prm);
-        const size_t need = learned_bytes(N, nnz);
-        if (needed) *needed = need;
-        if (!buf) return BLOB_RD_OK;
-        if (bytes < need) throw Err(BLOB_RD_ENOMEM, "precond buffer smaller than the size reported");
-        char* b = (char*)(((uintptr_t)buf + 255) & ~(uintptr_t)255);
-        if (b + need - 256 > (char*)buf + bytes) throw Err(BLOB_RD_ENOMEM, "precond buffer misaligned/too small");
-        auto& L = H->lrn;
-        L.rowptr = (int*)b;
-        b += align_up((size_t)(N + 1) * 4);
-        L.col = (int*)b;
-        b += align_up((size_t)nnz * 4);
-        L.rowidx = (int*)b;
-        b += align_up((size_t)nnz * 4);
-        L.val = (double*)b;
-        b += align_up((size_t)nnz * 8);
-        L.dg = (float*)b;
-        L.nnz = nnz;
-        L.pg = pg;
-        const double* q = H->at<double>(H->P.off_q);
-        HIPCHK(hipMemcpyAsync(L.rowptr, rowptr_s, (size_t)(N + 1) * 4, hipMemcpyDeviceToDevice, H->st));
-        launch_pair_fill(H->st, q, N, pg, cell, offs, prm, L.rowptr, L.col, L.rowidx);
-        launch_rowidx(H->st, L.rowptr, N, L.rowidx);
-        // the network's stream ordering: make sure its weights are current
-        HIPCHK(hipStreamSynchronize(Nt->st));
-        launch_net_assemble(H->st, q, pg, Nt->dev(), L.col, L.rowidx, nnz, H->prm.D * H->prm.h,
-                            4.0 * M_PI * 1.255, L.val);
-        int* bad = reinterpret_cast<int*>(H->dsc() + 40);
-        launch_count_bad(H->st, L.val, nnz, bad);
-        HIPCHK(hipMemcpyAsync(H->hbuf, bad, sizeof(int), hipMemcpyDeviceToHost, H->st));
-        HIPCHK(hipStreamSynchronize(H->st));
-        int nbad = 0;
-        std::memcpy(&nbad, H->hbuf, sizeof(int));
-        L.bad = nbad != 0;
-        L.ready = true;
-        HIPCHK(hipGetLastError());
-        return BLOB_RD_OK;
-    });
+    return guarded(H, nullptr, [&]() { return precond_build_into(H, Nt, buf, bytes, needed); });
 }
 
 int blob_rd_precond_apply(blob_rd_t H, const double* r, double* z) {
@@ -2796,6 +2840,148 @@ int blob_rd_precond_loss_grad(blob_rd_t H, blob_rd_net_t Nt, const double* X, co
     });
 }
 
+}  // extern "C"
+
+namespace {
+
+// The inference blob of the network: bfloat16 weights and float32 biases, in the
+// order of the float32 parameter vector.
+struct BlobPart {
+    int off_param, count;
+    bool bf16;
+};
+constexpr BlobPart kBlobParts[6] = {{kOffW1, 640, true}, {kOffB1, 64, false}, {kOffW2, 4096, true},
+                                    {kOffB2, 64, false}, {kOffW3, 64, true},  {kOffB3, 1, false}};
+
+float bf16_to_float(uint16_t b) {
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// round to nearest, ties to even (NaN stays a quiet NaN)
+uint16_t float_to_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+void blob_to_params(const unsigned char* blob, std::vector<float>& P) {
+    P.assign(kNetParams, 0.f);
+    size_t o = 0;
+    for (const BlobPart& part : kBlobParts) {
+        for (int k = 0; k < part.count; ++k) {
+            if (part.bf16) {
+                uint16_t b;
+                std::memcpy(&b, blob + o, 2);
+                P[part.off_param + k] = bf16_to_float(b);
+                o += 2;
+            } else {
+                std::memcpy(&P[part.off_param + k], blob + o, 4);
+                o += 4;
+            }
+        }
+    }
+}
+
+void params_to_blob(const std::vector<float>& P, unsigned char* blob) {
+    size_t o = 0;
+    for (const BlobPart& part : kBlobParts) {
+        for (int k = 0; k < part.count; ++k) {
+            if (part.bf16) {
+                const uint16_t b = float_to_bf16(P[part.off_param + k]);
+                std::memcpy(blob + o, &b, 2);
+                o += 2;
+            } else {
+                std::memcpy(blob + o, &P[part.off_param + k], 4);
+                o += 4;
+            }
+        }
+    }
+}
+
+// W of the handle's own network into the handle's learned region.
+void own_build(blob_rd* H) {
+    size_t need = 0;
+    precond_build_into(H, H->own_net, nullptr, 0, &need);
+    if (need > H->P.lrn_size)
+        throw Err(BLOB_RD_ENOMEM, "more blob pairs within 12h than the handle reserves (" +
+                                      std::to_string(BLOB_RD_LEARNED_ROW_CAP) + " per blob on average)");
+    precond_build_into(H, H->own_net, H->ws + H->P.off_lrn, H->P.lrn_size, &need);
+}
+
+int need_own_net(blob_rd* H) {
+    if (!H->own_net) {
+        g_last_error = "the handle holds no network: create it with schur_precond = LEARNED or saddle_solver = "
+                       "BLOCK_LEARNED, a periodic domain and at least one blob";
+        return BLOB_RD_EINVAL;
+    }
+    return BLOB_RD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int blob_rd_precond_set_weights(blob_rd_t H, const void* blob, size_t bytes) {
+    if (!H || !blob) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (bytes != BLOB_RD_PRECOND_BLOB_BYTES)
+        return g_last_error = "weight blob must be BLOB_RD_PRECOND_BLOB_BYTES bytes", BLOB_RD_EINVAL;
+    if (int rc = need_own_net(H)) return rc;
+    return guarded(H, nullptr, [&]() {
+        std::vector<float> P;
+        blob_to_params(static_cast<const unsigned char*>(blob), P);
+        blob_rd_net* Nt = H->own_net;
+        HIPCHK(hipMemcpyAsync(Nt->P, P.data(), (size_t)kNetParams * 4, hipMemcpyHostToDevice, Nt->st));
+        HIPCHK(hipMemsetAsync(Nt->m, 0, 3 * (size_t)kNetParams * 4, Nt->st));  // m, v, grad
+        Nt->t = 0;
+        launch_net_pack(Nt->st, Nt->P, Nt->W1b, Nt->W2b, Nt->w3b);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(Nt->st));
+        own_build(H);
+        return BLOB_RD_OK;
+    });
+}
+
+int blob_rd_precond_get_weights(blob_rd_t H, void* blob, size_t bytes) {
+    if (!H || !blob) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (bytes != BLOB_RD_PRECOND_BLOB_BYTES)
+        return g_last_error = "weight blob must be BLOB_RD_PRECOND_BLOB_BYTES bytes", BLOB_RD_EINVAL;
+    if (int rc = need_own_net(H)) return rc;
+    return guarded(H, nullptr, [&]() {
+        std::vector<float> P(kNetParams);
+        HIPCHK(hipMemcpyAsync(P.data(), H->own_net->P, (size_t)kNetParams * 4, hipMemcpyDeviceToHost,
+                              H->own_net->st));
+        HIPCHK(hipStreamSynchronize(H->own_net->st));
+        params_to_blob(P, static_cast<unsigned char*>(blob));
+        return BLOB_RD_OK;
+    });
+}
+
+int blob_rd_precond_train_step(blob_rd_t H, const void* batch_desc, float lr, float* loss) {
+    if (!H || !batch_desc) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (!(lr > 0.f) || !std::isfinite(lr)) return g_last_error = "learning rate must be positive", BLOB_RD_EINVAL;
+    if (int rc = need_own_net(H)) return rc;
+    const blob_rd_train_batch* b = static_cast<const blob_rd_train_batch*>(batch_desc);
+    if (!b->x || !b->y || b->n_samples <= 0 || b->n_samples > 64)
+        return g_last_error = "training batch needs 1..64 samples and device x, y", BLOB_RD_EINVAL;
+    return guarded(H, nullptr, [&]() {
+        blob_rd_net* Nt = H->own_net;
+        if (!H->lrn.ready || !H->own_w) own_build(H);
+        HIPCHK(hipMemsetAsync(Nt->grad, 0, (size_t)kNetParams * 4, Nt->st));
+        double l = 0.0;
+        int rc = blob_rd_precond_loss_grad(H, Nt, b->x, b->y, b->n_samples, &l);
+        if (rc != BLOB_RD_OK) throw Err(rc, g_last_error);
+        if (blob_rd_net_adam_step(Nt, lr) != BLOB_RD_OK) throw Err(BLOB_RD_EDEVICE, "Adam step failed");
+        own_build(H);  // the handle's W follows the updated weights
+        if (loss) *loss = (float)l;
+        return BLOB_RD_OK;
+    });
+}
+
 int blob_rd_schur_apply(blob_rd_t H, double alpha, const double* x, double* y, double inner_rtol) {
     if (!H || !x || !y || H->P.N <= 0) return g_last_error = "bad argument", BLOB_RD_EINVAL;
     if (!(alpha >= 0.0) || !(inner_rtol > 0.0)) return g_last_error = "bad alpha or tolerance", BLOB_RD_EINVAL;
@@ -2808,8 +2994,8 @@ int blob_rd_schur_apply(blob_rd_t H, double alpha, const double* x, double* y, d
     });
 }
 
-int blob_rd_solve_batch(blob_rd_t* hs, int32_t n, const int32_t* kind, double alpha, const double* const* f,
-                        double* const* c, double* const* lambda, int32_t threads, blob_rd_stats* stats) {
+int blob_rd_solve_streams(blob_rd_t* hs, int32_t n, const int32_t* kind, double alpha, const double* const* f,
+                          double* const* c, double* const* lambda, int32_t threads, blob_rd_stats* stats) {
     if (!hs || !kind || !f || !c || n < 0 || threads <= 0) return g_last_error = "bad argument", BLOB_RD_EINVAL;
     for (int i = 0; i < n; ++i) {
         if (!hs[i] || !f[i] || !c[i] || (kind[i] == 1 && (!lambda || !lambda[i])) || (kind[i] != 0 && kind[i] != 1))
@@ -3241,6 +3427,85 @@ int blob_rd_solve_batched(blob_rd_t* hs, int32_t n, const int32_t* kind, double 
     for (int i = 0; i < n; ++i)
         if (rcs[i] == BLOB_RD_ENOTCONV) return BLOB_RD_ENOTCONV;
     return BLOB_RD_OK;
+}
+
+// A batch handle: the member handles, their solve kinds, the executor's stream and
+// the descriptor tables (in the tail of member 0's workspace).
+struct blob_rd_batch {
+    std::vector<blob_rd*> hs;
+    std::vector<int32_t> kind;
+    hipStream_t st = nullptr;
+    char* tabs = nullptr;
+    size_t tab_bytes = 0;
+    int64_t lockstep_max_cells = (int64_t)64 * 64 * 64;
+    int32_t threads = 8;
+};
+
+int blob_rd_destroy_batch(blob_rd_batch_t b) {
+    if (!b) return BLOB_RD_OK;
+    for (blob_rd* H : b->hs) blob_rd_destroy(H);
+    if (b->st) (void)hipStreamDestroy(b->st);
+    delete b;
+    return BLOB_RD_OK;
+}
+
+int blob_rd_create_batch(const blob_rd_params* p, int32_t n_inst, const int32_t* kind, blob_rd_batch_t* out) {
+    if (!out) return g_last_error = "null output handle", BLOB_RD_EINVAL;
+    *out = nullptr;
+    if (!p || !kind || n_inst <= 0) return g_last_error = "bad argument", BLOB_RD_EINVAL;
+    for (int i = 0; i < n_inst; ++i)
+        if (kind[i] != 0 && kind[i] != 1) return g_last_error = "kind must be 0 or 1", BLOB_RD_EINVAL;
+    const size_t own0 = blob_rd_workspace_bytes(&p[0]);
+    if (own0 == 0) return BLOB_RD_EINVAL;
+    const size_t tabs = blob_rd_batch_workspace_bytes(n_inst);
+    if (!p[0].workspace || p[0].workspace_bytes < own0 + tabs)
+        return g_last_error = "member 0's workspace must hold blob_rd_workspace_bytes(&p[0]) + "
+                              "blob_rd_batch_workspace_bytes(n_inst) bytes",
+               BLOB_RD_ENOMEM;
+    blob_rd_batch* b = new blob_rd_batch();
+    for (int i = 0; i < n_inst; ++i) {
+        blob_rd* H = nullptr;
+        const int rc = blob_rd_create(&p[i], &H);
+        if (rc != BLOB_RD_OK) {
+            g_last_error = "instance " + std::to_string(i) + ": " + g_last_error;
+            blob_rd_destroy_batch(b);
+            return rc;
+        }
+        b->hs.push_back(H);
+        b->kind.push_back(kind[i]);
+        if (kind[i] == 1 && H->P.N <= 0) {
+            blob_rd_destroy_batch(b);
+            return g_last_error = "absorbing instance " + std::to_string(i) + " has no blobs", BLOB_RD_EINVAL;
+        }
+    }
+    b->tabs = static_cast<char*>(p[0].workspace) + own0;
+    b->tab_bytes = p[0].workspace_bytes - own0;
+    if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess) {
+        blob_rd_destroy_batch(b);
+        return g_last_error = "stream creation failed", BLOB_RD_EDEVICE;
+    }
+    *out = b;
+    return BLOB_RD_OK;
+}
+
+blob_rd_t blob_rd_batch_member(blob_rd_batch_t b, int32_t i) {
+    if (!b || i < 0 || i >= (int32_t)b->hs.size()) return nullptr;
+    return b->hs[i];
+}
+
+int blob_rd_batch_set_executor(blob_rd_batch_t b, int64_t lockstep_max_cells, int32_t threads) {
+    if (!b || threads < 0) return g_last_error = "bad argument", BLOB_RD_EINVAL;
+    b->lockstep_max_cells = lockstep_max_cells;
+    b->threads = threads;
+    return BLOB_RD_OK;
+}
+
+int blob_rd_solve_batch(blob_rd_batch_t b, const double* const* f, double* const* c, double* const* lambda,
+                        blob_rd_stats* stats) {
+    if (!b || !f || !c) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    const int n = (int)b->hs.size();
+    return blob_rd_solve_batched(b->hs.data(), n, b->kind.data(), 0.0, f, c, lambda, b->lockstep_max_cells,
+                                 b->threads, b->tabs, b->tab_bytes, b->st, stats);
 }
 
 }  // extern "C"

@@ -63,6 +63,10 @@ class SaddleOpts(ctypes.Structure):
                 ("diag", ctypes.c_double)]
 
 
+class TrainBatch(ctypes.Structure):
+    _fields_ = [("n_samples", ctypes.c_int32), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p)]
+
+
 SADDLE_PRECONDS = {"diagonal": 0, "schur": 1, "learned": 2}
 
 
@@ -152,9 +156,26 @@ def load_library(path: str = LIB_PATH):
     L.blob_rd_schur_apply.argtypes = [vp, d, vp, vp, d]
     L.blob_rd_schur_apply_cycles.argtypes = [vp, d, vp, vp, i32]
     L.blob_rd_schur_apply_cycles.restype = i32
-    L.blob_rd_solve_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), d,
-                                      ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int32, S]
+    L.blob_rd_solve_streams.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), d,
+                                        ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int32, S]
+    L.blob_rd_solve_streams.restype = i32
+    L.blob_rd_create_batch.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(vp)]
+    L.blob_rd_create_batch.restype = i32
+    L.blob_rd_destroy_batch.argtypes = [vp]
+    L.blob_rd_destroy_batch.restype = i32
+    L.blob_rd_batch_member.argtypes = [vp, ctypes.c_int32]
+    L.blob_rd_batch_member.restype = vp
+    L.blob_rd_batch_set_executor.argtypes = [vp, ctypes.c_int64, ctypes.c_int32]
+    L.blob_rd_batch_set_executor.restype = i32
+    L.blob_rd_solve_batch.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), S]
     L.blob_rd_solve_batch.restype = i32
+    L.blob_rd_precond_set_weights.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    L.blob_rd_precond_set_weights.restype = i32
+    L.blob_rd_precond_get_weights.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    L.blob_rd_precond_get_weights.restype = i32
+    L.blob_rd_precond_train_step.argtypes = [vp, ctypes.POINTER(TrainBatch), ctypes.c_float,
+                                             ctypes.POINTER(ctypes.c_float)]
+    L.blob_rd_precond_train_step.restype = i32
     L.blob_rd_batch_workspace_bytes.argtypes = [ctypes.c_int32]
     L.blob_rd_batch_workspace_bytes.restype = ctypes.c_size_t
     L.blob_rd_solve_batched.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), d,
@@ -186,6 +207,37 @@ def _ptr(t: Optional[torch.Tensor]):
 
 
 NET_PARAMS = 4929
+PRECOND_BLOB_BYTES = 10116
+# the weight blob: (parameter offset, count, stored as bfloat16) in the order of the float32 vector
+_BLOB_PARTS = ((0, 640, True), (640, 64, False), (704, 4096, True), (4800, 64, False), (4864, 64, True),
+               (4928, 1, False))
+
+
+def weights_blob(params) -> bytes:
+    """The weight blob of blob_rd_precond_set_weights from a float32 parameter vector (weights
+    stored as bfloat16, the form the network uses them in; biases as float32)."""
+    v = torch.as_tensor(np.asarray(params, dtype=np.float32).ravel())
+    assert v.numel() == NET_PARAMS
+    out = b""
+    for off, n, bf in _BLOB_PARTS:
+        part = v[off:off + n]
+        out += (part.to(torch.bfloat16).view(torch.int16).numpy().tobytes() if bf else part.numpy().tobytes())
+    assert len(out) == PRECOND_BLOB_BYTES
+    return out
+
+
+def blob_params(blob: bytes) -> np.ndarray:
+    """The float32 parameter vector held in a weight blob."""
+    assert len(blob) == PRECOND_BLOB_BYTES
+    out, o = np.zeros(NET_PARAMS, np.float32), 0
+    for off, n, bf in _BLOB_PARTS:
+        if bf:
+            out[off:off + n] = torch.frombuffer(bytearray(blob[o:o + 2 * n]), dtype=torch.bfloat16).float().numpy()
+            o += 2 * n
+        else:
+            out[off:off + n] = np.frombuffer(blob[o:o + 4 * n], dtype=np.float32)
+            o += 4 * n
+    return out
 
 
 class Net:
@@ -460,6 +512,27 @@ class BlobRD:
         self._check(self._lib.blob_rd_precond_csr(self._h, ctypes.byref(nnz), None, None, None))
         return int(nnz.value)
 
+    def precond_set_weights(self, blob: bytes) -> None:
+        """Set this handle's own network from a weight blob and build W (handles created with
+        schur_precond=PRECOND_LEARNED or saddle_solver=SOLVER_BLOCK_LEARNED)."""
+        self._check(self._lib.blob_rd_precond_set_weights(self._h, bytes(blob), len(blob)))
+
+    def precond_get_weights(self) -> bytes:
+        buf = ctypes.create_string_buffer(PRECOND_BLOB_BYTES)
+        self._check(self._lib.blob_rd_precond_get_weights(self._h, buf, PRECOND_BLOB_BYTES))
+        return buf.raw
+
+    def precond_train_step(self, X: torch.Tensor, Y: torch.Tensor, lr: float) -> float:
+        """One loss/gradient/Adam step of this handle's own network on sample pairs (rows of X,
+        Y); W follows the new weights. Returns the loss before the step."""
+        X = _dev_f64(X.contiguous(), (X.shape[0], self.N), "X")
+        Y = _dev_f64(Y.contiguous(), (X.shape[0], self.N), "Y")
+        b = TrainBatch(int(X.shape[0]), X.data_ptr(), Y.data_ptr())
+        loss = ctypes.c_float()
+        self._check(self._lib.blob_rd_precond_train_step(self._h, ctypes.byref(b), ctypes.c_float(lr),
+                                                         ctypes.byref(loss)))
+        return float(loss.value)
+
     def precond_csr(self):
         nnz = ctypes.c_int64()
         self._check(self._lib.blob_rd_precond_csr(self._h, ctypes.byref(nnz), None, None, None))
@@ -496,8 +569,8 @@ class BlobRD:
         return y
 
 
-def solve_batch(solvers: Sequence["BlobRD"], kinds: Sequence[int], fs, cs, lams, alpha: float = 0.0,
-                threads: int = 8):
+def solve_streams(solvers: Sequence["BlobRD"], kinds: Sequence[int], fs, cs, lams, alpha: float = 0.0,
+                  threads: int = 8):
     """Solve independent instances concurrently (each solver should own its own stream).
     kinds: 0 reactive, 1 absorbing. Returns (rc, list of stats dicts)."""
     L = load_library()
@@ -508,7 +581,7 @@ def solve_batch(solvers: Sequence["BlobRD"], kinds: Sequence[int], fs, cs, lams,
     C = (ctypes.c_void_p * n)(*[c.data_ptr() for c in cs])
     Lm = (ctypes.c_void_p * n)(*[(l.data_ptr() if l is not None else None) for l in lams])
     st = (Stats * n)()
-    rc = L.blob_rd_solve_batch(H, n, K, float(alpha), F, C, Lm, int(threads), st)
+    rc = L.blob_rd_solve_streams(H, n, K, float(alpha), F, C, Lm, int(threads), st)
     if rc < 0:
         raise BlobRDError(rc, L.blob_rd_last_error(None).decode())
     return rc, [st[i].as_dict(rc) for i in range(n)]
@@ -538,3 +611,105 @@ def solve_batched(solvers: Sequence["BlobRD"], kinds: Sequence[int], fs, cs, lam
     if rc < 0:
         raise BlobRDError(rc, L.blob_rd_last_error(None).decode())
     return rc, [st[i].as_dict(rc) for i in range(n)]
+
+
+class _Member(BlobRD):
+    """A member handle of a Batch (owned by the batch: closing it does nothing)."""
+
+    def __init__(self, lib, h, shape, N, device, stream):
+        self._lib, self._h, self.shape, self.N, self.device, self.stream = lib, h, shape, N, device, stream
+
+    def close(self):
+        self._h = None
+
+
+class Batch:
+    """A blob_rd batch handle (blob_rd_create_batch): instances with their own grids, blobs,
+    precisions, solvers and streams, solved together by blob_rd_solve_batch.
+
+    specs: one dict per instance with the BlobRD keyword arguments (shape, q, kappa, precision,
+    saddle_solver, ...) and `kind` (0 reactive, 1 absorbing); each instance gets its own stream."""
+
+    def __init__(self, specs: Sequence[dict], lockstep_max_cells: Optional[int] = None, threads: Optional[int] = None):
+        L = load_library()
+        self._lib = L
+        n = len(specs)
+        params = (Params * n)()
+        self._keep, self.members, self.kinds = [], [], []
+        for i, sp in enumerate(specs):
+            sp = dict(sp)
+            kind = int(sp.pop("kind"))
+            shape = sp.pop("shape")
+            shape = (shape,) * 3 if isinstance(shape, int) else tuple(int(v) for v in shape)
+            q = sp.pop("q")
+            kappa = sp.pop("kappa", None)
+            N = int(q.shape[0])
+            if N > 0:
+                _dev_f64(q, (N, 3), "q")
+            if kappa is not None:
+                _dev_f64(kappa, (N,), "kappa")
+            stream = sp.pop("stream", None) or torch.cuda.Stream(q.device)
+            a = dict(h=1.0, D=1.0, kernel_w=4, precision=FP64, schur_precond=PRECOND_NONE, rtol=1e-8, max_iter=0,
+                     gmres_restart=0, inner_max_iter=0, saddle_solver=0, boundary=0, boundary_value=0.0)
+            unknown = set(sp) - set(a)
+            if unknown:
+                raise ValueError(f"unknown instance options {sorted(unknown)}")
+            a.update(sp)
+            nz, ny, nx = shape
+            p = Params(nx, ny, nz, float(a["h"]), float(a["D"]), int(a["kernel_w"]), N,
+                       q.data_ptr() if N > 0 else None, None if kappa is None else kappa.data_ptr(),
+                       int(a["precision"]), int(a["schur_precond"]), float(a["rtol"]), int(a["max_iter"]),
+                       int(a["gmres_restart"]), int(a["inner_max_iter"]), None, 0,
+                       ctypes.c_void_p(stream.cuda_stream), int(a["saddle_solver"]), int(a["boundary"]),
+                       float(a["boundary_value"]))
+            nbytes = int(L.blob_rd_workspace_bytes(ctypes.byref(p)))
+            if nbytes == 0:
+                raise BlobRDError(-1, L.blob_rd_last_error(None).decode())
+            if i == 0:
+                nbytes += int(L.blob_rd_batch_workspace_bytes(n))
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=q.device)
+            p.workspace, p.workspace_bytes = ws.data_ptr(), nbytes
+            params[i] = p
+            self._keep += [ws, q, kappa, stream]
+            self.members.append((shape, N, q.device, stream))
+            self.kinds.append(kind)
+        K = (ctypes.c_int32 * n)(*self.kinds)
+        h = ctypes.c_void_p()
+        rc = L.blob_rd_create_batch(params, n, K, ctypes.byref(h))
+        if rc != OK:
+            raise BlobRDError(rc, L.blob_rd_last_error(None).decode())
+        self._h = h
+        self.members = [_Member(L, L.blob_rd_batch_member(h, i), shape, N, dev, st)
+                        for i, (shape, N, dev, st) in enumerate(self.members)]
+        if lockstep_max_cells is not None or threads is not None:
+            rc = L.blob_rd_batch_set_executor(h, int(64 ** 3 if lockstep_max_cells is None else lockstep_max_cells),
+                                              int(8 if threads is None else threads))
+            if rc != OK:
+                raise BlobRDError(rc, L.blob_rd_last_error(None).decode())
+
+    def solve(self, fs, cs, lams):
+        """blob_rd_solve_batch: fs, cs grid tensors per member (cs: initial guess of reactive members,
+        solution out), lams multiplier tensors of absorbing members (None for reactive ones)."""
+        n = len(self.members)
+        F = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+        C = (ctypes.c_void_p * n)(*[c.data_ptr() for c in cs])
+        Lm = (ctypes.c_void_p * n)(*[(l.data_ptr() if l is not None else None) for l in lams])
+        st = (Stats * n)()
+        torch.cuda.synchronize()
+        rc = self._lib.blob_rd_solve_batch(self._h, F, C, Lm, st)
+        if rc < 0:
+            raise BlobRDError(rc, self._lib.blob_rd_last_error(None).decode())
+        return rc, [st[i].as_dict(rc) for i in range(n)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for m in self.members:
+                m.close()
+            self._lib.blob_rd_destroy_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

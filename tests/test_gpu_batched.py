@@ -138,7 +138,7 @@ def test_batched_with_block_solver_instances(dev):
     the reactive ones share the lock-step launches; every result is bitwise the solo solve, and
     the block handles' absorbing solves are those of blob_rd_solve_absorbing_fgmres."""
     _say("batched with block-solver instances")
-    from paper_1306_3159_amd import BlobRD, solve_batched, solve_batch, SOLVER_BLOCK
+    from paper_1306_3159_amd import BlobRD, solve_batched, solve_streams, SOLVER_BLOCK
     specs = [(32, 60, 0), (48, 200, 1), (64, 300, 0), (32, 20, 1), (64, 150, 1), (48, 90, 0)]
     inst = _instances(specs, 4300)
 
@@ -169,7 +169,7 @@ def test_batched_with_block_solver_instances(dev):
         if runner == "batched":
             rc, stats = solve_batched(Hs, kinds, fs, cs, ls)
         else:
-            rc, stats = solve_batch(Hs, kinds, fs, cs, ls, threads=3)
+            rc, stats = solve_streams(Hs, kinds, fs, cs, ls, threads=3)
         assert rc == 0, stats
         for (c0, l0), c, l in zip(solo, cs, ls):
             assert np.array_equal(c.cpu().numpy(), c0)

@@ -201,8 +201,10 @@ def _net(dev, p):
 def test_precond_parity_learned(dev, trained):
     """Learned variant (inner GMRES right-preconditioned by P W P). Untrained network: W is
     exactly the diagonal of eq. Schur_diagonal on both sides, so the FP64 handle matches the
-    oracle to 1e-9. Random weights: W itself differs by the BF16 activation rounding of the
-    network (about 1 %), which bounds the agreement."""
+    oracle to 1e-9. Random weights: the oracle's W is its matrix-unit model of the network
+    (bf16 operands in every product), which the GPU's W matches to float32 accumulation
+    except for rare bf16 rounding flips (one bf16 step of one hidden unit in a few entries);
+    the preconditioner output then agrees to 1e-3."""
     _say("saddle precond learned", trained)
     from oracle import learned as LN
     from paper_1306_3159_amd import PRECOND_LEARNED
@@ -219,11 +221,11 @@ def test_precond_parity_learned(dev, trained):
     S = make(dev, n, q, precision=0, schur_precond=PRECOND_LEARNED)
     S.precond_build(net)
     zg, zl = S.saddle_precond(T(vg, dev), T(vf, dev), alpha=0.0, precond="learned", m=4)
-    ptr, col, val, _ = LN.assemble(LN.rounded(p), q, n)
+    ptr, col, val, _ = LN.assemble(LN.rounded(p), q, n, mfma_operands=True)
     ops = fg.SaddleOps(q, (n, n, n), 0.0)
     inv = fg.cycles_inverse(ops, lambda r: it.vcycle(r, 0.0), 1)
     cg, cl = fg.precondition(ops, vg, vf, "learned", inv, inv, m=4, w_apply=lambda v: LN.apply(ptr, col, val, v))
-    tol = 5e-2 if trained else 1e-9
+    tol = 1e-3 if trained else 1e-9
     assert rel(H(zg), cg) < tol and rel(H(zl), cl) < tol
     S.close()
     net.close()

@@ -49,10 +49,24 @@ def net_with(dev, p):
     return net
 
 
+def w_matches_model(val, mval, diag):
+    """W from the GPU against the oracle's matrix-unit model, relative to the largest learned
+    entry. The two sides form the layer-1 pre-activations in float32 (MFMA) and float64: where
+    an activation lies within that difference of a bfloat16 rounding midpoint the two round it
+    to neighbouring bf16 values, and the entries built from that evaluation move by up to one
+    bf16 step of one hidden unit. So: at least 99 % of the entries agree to 1e-5 (float32
+    accumulation only), and every entry to 1e-2."""
+    err = np.abs(val - mval) / np.max(np.abs(mval - diag))
+    assert np.mean(err > 1e-5) <= 0.01, np.mean(err > 1e-5)
+    assert err.max() <= 1e-2, err.max()
+
+
 @pytest.mark.parametrize("n,N", [(32, 40), (48, 120), (64, 300)])
 def test_pair_list_and_assembly(dev, n, N):
-    """CSR pattern identical to the oracle's (integers: bitwise); values within the bf16
-    activation rounding of the MFMA path (oracle: float64 on the same bf16 weights)."""
+    """CSR pattern identical to the oracle's (integers: bitwise). Values against the oracle's
+    matrix-unit model (bf16 operands in every network product, float64 sums), element by
+    element: see w_matches_model. Against the plain float64 network on the same bf16 weights:
+    within 1e-2 in norm."""
     _say("pairs", n, N)
     from paper_1306_3159_amd import BlobRD
     rng = np.random.default_rng(n + N)
@@ -63,11 +77,13 @@ def test_pair_list_and_assembly(dev, n, N):
     nnz = S.precond_build(net)
     ptr, col, val = (t.cpu().numpy() for t in S.precond_csr())
     optr, ocol, oval, _ = LN.assemble(LN.rounded(p), q, (n, n, n))
+    _, _, mval, _ = LN.assemble(LN.rounded(p), q, (n, n, n), mfma_operands=True)
     assert nnz == ocol.size
     assert np.array_equal(ptr, optr) and np.array_equal(col, ocol)
     diag = (np.repeat(np.arange(N), np.diff(optr)) == ocol) * 4 * math.pi * LN.A0
     learned_o, learned_g = oval - diag, val - diag
-    assert np.linalg.norm(learned_g - learned_o) <= 2e-2 * np.linalg.norm(learned_o)
+    w_matches_model(val, mval, diag)
+    assert np.linalg.norm(learned_g - learned_o) <= 1e-2 * np.linalg.norm(learned_o)
     # symmetric
     Wd = np.zeros((N, N))
     for i in range(N):
@@ -97,8 +113,9 @@ def test_untrained_net_is_diagonal(dev):
 
 
 def test_gradient_matches_oracle(dev):
-    """GPU forward/backward (bf16 MFMA, fp32 accumulation) vs the oracle's float64 gradient
-    on the same bf16-rounded weights: relative error per tensor <= 1e-2... 3e-2."""
+    """GPU forward/backward (bf16 MFMA, fp32 accumulation) on the same bf16-rounded weights:
+    relative error per tensor <= 1e-2 against the oracle's float64 network, and <= 1e-4
+    against its matrix-unit model (bf16 operands in every product, float64 sums)."""
     _say("grad")
     from paper_1306_3159_amd import BlobRD
     rng = np.random.default_rng(11)
@@ -109,16 +126,19 @@ def test_gradient_matches_oracle(dev):
     X -= X.mean(1, keepdims=True)
     Y = 0.05 * rng.standard_normal((Sm, N))
     loss_o, g_o = LN.loss_and_grad(p, q, (n, n, n), X, Y)
+    loss_m, g_m = LN.loss_and_grad(p, q, (n, n, n), X, Y, mfma_operands=True)
     net = net_with(dev, p)
     net.zero_grad()
     S = BlobRD(n, T(q, dev))
     S.precond_build(net)
     loss_g = S.precond_loss_grad(net, T(X, dev), T(Y, dev))
     g = LN.unflatten(net.get_grad().cpu().numpy())
-    assert loss_g == pytest.approx(loss_o, rel=1e-2)
+    assert loss_g == pytest.approx(loss_o, rel=1e-3)
+    assert loss_g == pytest.approx(loss_m, rel=1e-6)
     for k in LN.PARAM_ORDER:
-        a, b = np.asarray(g[k], np.float64), np.asarray(g_o[k], np.float64)
-        assert np.linalg.norm(a - b) <= 3e-2 * np.linalg.norm(b) + 1e-12, (k, np.linalg.norm(a - b) / np.linalg.norm(b))
+        a, b, m = np.asarray(g[k], np.float64), np.asarray(g_o[k], np.float64), g_m[k]
+        assert np.linalg.norm(a - b) <= 1e-2 * np.linalg.norm(b), (k, np.linalg.norm(a - b) / np.linalg.norm(b))
+        assert np.linalg.norm(a - m) <= 1e-4 * np.linalg.norm(m), (k, np.linalg.norm(a - m) / np.linalg.norm(m))
     S.close()
     net.close()
 

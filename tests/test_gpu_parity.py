@@ -406,7 +406,7 @@ def test_batch_matches_solo(dev):
     """Uneven instances (grids 32/48/64, reactive and absorbing) solved concurrently on
     their own streams give bitwise the results of solving each alone."""
     _say("batch")
-    from paper_1306_3159_amd import BlobRD, solve_batch
+    from paper_1306_3159_amd import BlobRD, solve_streams
     specs = [(32, 60, 0), (48, 200, 1), (64, 300, 0), (32, 20, 1), (48, 90, 0), (64, 150, 1)]
     inst = []
     for k, (n, N, kind) in enumerate(specs):
@@ -438,7 +438,7 @@ def test_batch_matches_solo(dev):
     cs = [torch.zeros((n, n, n), dtype=torch.float64, device=dev) for n, _, _, _ in inst]
     ls = [torch.zeros(q.shape[0], dtype=torch.float64, device=dev) if kind else None for _, q, _, kind in inst]
     torch.cuda.synchronize()
-    rc, stats = solve_batch(Hs, [k for *_, k in inst], fs, cs, ls, threads=4)
+    rc, stats = solve_streams(Hs, [k for *_, k in inst], fs, cs, ls, threads=4)
     assert rc == 0, stats
     for (c0, l0), c, l in zip(solo, cs, ls):
         assert np.array_equal(H(c), c0)

@@ -113,3 +113,35 @@ def test_adam_first_step_moves_by_lr_times_sign():
     for k in LN.PARAM_ORDER:
         assert np.allclose(out[k].astype(np.float64), p[k].astype(np.float64) - 1e-3 * np.sign(g[k]), atol=1e-6)
     assert st["t"] == 1
+
+
+def test_matrix_unit_model_within_bf16_of_fp64():
+    """The matrix-unit model (bf16 operands in every network product) stays within the bf16
+    rounding bound of the float64 network, which is pinned by finite differences above: W and
+    every gradient tensor agree to 1e-2 (bf16 keeps 8 significand bits, 2^-9 relative), W stays
+    exactly symmetric, and the model does differ from float64 (its roundings take effect)."""
+    rng = np.random.default_rng(10)
+    n, N = 32, 90
+    q = W.rsa_positions(rng, n, N, 3.0)
+    p = LN.init_params(11)
+    p["b1"] = (0.1 * rng.standard_normal(64)).astype(np.float32)
+    p["w3"] = (0.3 * rng.standard_normal(64)).astype(np.float32)
+    p["b3"] = np.array([0.2], np.float32)
+    Xs = rng.standard_normal((3, N))
+    Xs -= Xs.mean(1, keepdims=True)
+    Ys = 0.05 * rng.standard_normal((3, N))
+    l64, g64 = LN.loss_and_grad(p, q, (n, n, n), Xs, Ys)
+    lmu, gmu = LN.loss_and_grad(p, q, (n, n, n), Xs, Ys, mfma_operands=True)
+    assert lmu == pytest.approx(l64, rel=1e-2)
+    for k in LN.PARAM_ORDER:
+        d = np.linalg.norm(gmu[k] - g64[k]) / np.linalg.norm(g64[k])
+        assert d <= 1e-2, (k, d)
+    assert any(not np.array_equal(gmu[k], g64[k]) for k in ("W1", "W2"))
+    ptr, col, v64, _ = LN.assemble(LN.rounded(p), q, (n, n, n))
+    _, _, vmu, _ = LN.assemble(LN.rounded(p), q, (n, n, n), mfma_operands=True)
+    diag = (np.repeat(np.arange(N), np.diff(ptr)) == col) * 4 * math.pi * LN.A0
+    assert 0 < np.linalg.norm(vmu - v64) <= 1e-2 * np.linalg.norm(v64 - diag)
+    Wd = np.zeros((N, N))
+    for i in range(N):
+        Wd[i, col[ptr[i]:ptr[i + 1]]] = vmu[ptr[i]:ptr[i + 1]]
+    assert np.array_equal(Wd, Wd.T)
