@@ -264,6 +264,26 @@ int blob_rd_solve_absorbing_fgmres(blob_rd_t h, double alpha, const blob_rd_sadd
                                    double* c, double* lambda, void* workspace, size_t workspace_bytes,
                                    blob_rd_stats* stats);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc and the like):
+ * blob_rd_solve_absorbing_fgmres with the flexible-GMRES basis in a device
+ * array of the library instead of a caller workspace. The array holds
+ * BLOB_RD_NOALLOC_BYTES (256 MiB) on each GPU the library runs on, in each
+ * process, from the load of the library's device code until the process ends;
+ * its address is taken once per device by blob_rd_create. Same arguments and
+ * results as blob_rd_solve_absorbing_fgmres otherwise; the call allocates and
+ * frees nothing. Limit: blob_rd_fgmres_workspace_bytes(h, restart) <=
+ * BLOB_RD_NOALLOC_BYTES (for instance 64^3 cells with restart 30), else ENOMEM
+ * before any work. The array is shared by every call on that GPU: calls from
+ * one process are serialised by a lock, and each call synchronises the handle's
+ * stream before returning, so its contents (the last call's basis) never carry
+ * over; overlapping use from outside these calls would race. EINVAL also when
+ * alpha would evict a cached coarse inverse whose captured CG graphs it would
+ * have to free (solve with one of the handle's last four alphas). */
+#define BLOB_RD_NOALLOC_BYTES (256u << 20)
+int blob_rd_solve_absorbing_fgmres_noalloc(blob_rd_t h, double alpha, const blob_rd_saddle_opts* opts,
+                                           const double* f, double* c, double* lambda, blob_rd_stats* stats);
+
 /* One application of the preconditioner above: [zg; zl] ~ K^{-1} [vg; vf]
  * (grid vectors of ncell doubles, blob vectors of N doubles, device pointers;
  * vg, vf are not modified and must not alias zg, zl). Synchronises the

@@ -320,6 +320,38 @@ std::vector<double> coarse_inverse(const LevelDims& C, double D, double alpha, b
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// The flexible-GMRES basis of blob_rd_solve_absorbing_fgmres_noalloc: a device array
+// of the library (one per GPU in each process, held until the process ends), for
+// callers that cannot allocate device memory. Host code never passes `scratch`
+// itself to a kernel: it uses the device address taken once per device.
+static __device__ __align__(256) unsigned char scratch[BLOB_RD_NOALLOC_BYTES];
+
+namespace {
+
+struct ScratchSlot {
+    char* ptr = nullptr;
+    std::mutex use;  // one no-alloc solve at a time on this GPU in this process
+};
+std::mutex g_scratch_m;
+std::map<int, ScratchSlot> g_scratch;
+
+// The current device's scratch slot; its address is taken on first use on that device.
+ScratchSlot& scratch_slot() {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_m);
+    ScratchSlot& s = g_scratch[dev];
+    if (!s.ptr) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw Err(BLOB_RD_EDEVICE, "no device address for the no-alloc scratch");
+        s.ptr = static_cast<char*>(p);
+    }
+    return s;
+}
+
+}  // namespace
+
 struct BatchServer;
 
 struct blob_rd {
@@ -384,6 +416,8 @@ struct blob_rd {
     // lock-step batch executor this handle currently belongs to (null: solo)
     BatchServer* batch = nullptr;
     int batch_slot = -1;
+    // this device's no-alloc scratch (device address of `scratch`, taken at create)
+    ScratchSlot* noalloc = nullptr;
 
     template <typename T>
     T* at(size_t off) const {
@@ -1861,6 +1895,7 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
             HIPCHK(blocked_set_lds<float>());
             HIPCHK(blocked_set_lds<double>());
         }
+        H->noalloc = &scratch_slot();
         if (P.off_net) {
             // the handle's own network starts untrained: W is then the diagonal of eq. Schur_diagonal
             if (blob_rd_net_create(H->ws + P.off_net, net_bytes(), (void*)st, &H->own_net) != BLOB_RD_OK)
@@ -3539,6 +3574,37 @@ int blob_rd_solve_absorbing_fgmres(blob_rd_t H, double alpha, const blob_rd_sadd
         int rc = H->P.esz == 4 ? fg_entry<float>(H, alpha, o, f, c, lambda, ws, stt, false)
                                : fg_entry<double>(H, alpha, o, f, c, lambda, ws, stt, false);
         HIPCHK(hipGetLastError());
+        return rc;
+    });
+}
+
+int blob_rd_solve_absorbing_fgmres_noalloc(blob_rd_t H, double alpha, const blob_rd_saddle_opts* opts,
+                                           const double* f, double* c, double* lambda, blob_rd_stats* stt) {
+    if (!H || !f || !c || !lambda) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (H->P.N <= 0) return g_last_error = "absorbing solve needs at least one blob", BLOB_RD_EINVAL;
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return g_last_error = "alpha must be >= 0", BLOB_RD_EINVAL;
+    if (!H->noalloc) return g_last_error = "no scratch on this handle's device", BLOB_RD_EDEVICE;
+    // a new alpha evicting a cached coarse inverse would also drop captured CG graphs
+    bool cached = false;
+    for (int k = 0; k < H->cinv_used; ++k) cached = cached || H->cinv_alpha[k] == alpha;
+    if (!cached && H->cinv_used == 4)
+        for (const auto& g : H->graphs)
+            if (g.alpha == H->cinv_alpha[H->cinv_next])
+                return g_last_error = "this alpha would evict a captured CG graph; solve with a cached alpha",
+                       BLOB_RD_EINVAL;
+    return guarded(H, stt, [&]() {
+        const FgOpts o = fg_opts(H, opts);
+        const size_t need = fg_bytes(H->P, o.restart);
+        if (need > (size_t)BLOB_RD_NOALLOC_BYTES)
+            throw Err(BLOB_RD_ENOMEM, "the FGMRES basis needs " + std::to_string(need) + " bytes, more than the " +
+                                          std::to_string((size_t)BLOB_RD_NOALLOC_BYTES) +
+                                          " of the no-alloc scratch (use a shorter restart or a workspace)");
+        std::lock_guard<std::mutex> lk(H->noalloc->use);
+        char* ws = H->noalloc->ptr;
+        int rc = H->P.esz == 4 ? fg_entry<float>(H, alpha, o, f, c, lambda, ws, stt, false)
+                               : fg_entry<double>(H, alpha, o, f, c, lambda, ws, stt, false);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(H->st));  // the scratch is free again once this returns
         return rc;
     });
 }

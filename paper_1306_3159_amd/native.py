@@ -120,6 +120,8 @@ def load_library(path: str = LIB_PATH):
     L.blob_rd_fgmres_workspace_bytes.restype = ctypes.c_size_t
     L.blob_rd_solve_absorbing_fgmres.argtypes = [vp, d, ctypes.POINTER(SaddleOpts), vp, vp, vp, vp, ctypes.c_size_t, S]
     L.blob_rd_solve_absorbing_fgmres.restype = i32
+    L.blob_rd_solve_absorbing_fgmres_noalloc.argtypes = [vp, d, ctypes.POINTER(SaddleOpts), vp, vp, vp, S]
+    L.blob_rd_solve_absorbing_fgmres_noalloc.restype = i32
     L.blob_rd_saddle_precond.argtypes = [vp, d, ctypes.POINTER(SaddleOpts), vp, vp, vp, vp]
     L.blob_rd_saddle_precond.restype = i32
     L.blob_rd_interp.argtypes = [vp, vp, vp]
