@@ -190,6 +190,52 @@ def bench_batch(args, dev, rtol):
     print(json.dumps(out))
 
 
+def _say(msg):
+    """Progress on stderr (the one JSON line goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(inst):
+    """The oracle's own absorbing solve (Schur-complement GMRES(30) with inner MG-CG Poisson solves,
+    FP64 V(2,2) cycles, OpenMP over z-slabs) timed end to end on the same input and tolerance on
+    all host threads, once; and one full oracle Poisson solve of the same grid timed on one thread,
+    which with the solve's own count of Poisson solves gives the one-core rate."""
+    from oracle import iterative as it
+    it.build(force=False)
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    nt = it.num_threads()
+    _say(f"cpu baseline: oracle absorbing solve {inst.n}^3, {inst.N} blobs on {nt} threads")
+    t0 = time.perf_counter()
+    c, lam, ost = it.solve_absorbing(inst.f, inst.q, 0.0, rtol=inst.rtol, inner_rtol=1e-10)
+    ts = time.perf_counter() - t0
+    n_poisson = ost["iters"] + 2
+    _say(f"cpu baseline: {ts:.1f} s, {ost['iters']} GMRES iterations, {ost['inner_iters']} inner CG iterations, "
+         f"residual {ost['rel_resid']:.2e}; one-thread Poisson solve next")
+    lbar = float(np.sum(inst.f)) / inst.N
+    g = np.asarray(inst.f, dtype=np.float64) + it.spread(np.full(inst.N, -lbar), inst.q, inst.f.shape)
+    it.set_num_threads(1)
+    t1 = time.perf_counter()
+    _, pst = it.solve_poisson(g, 0.0, rtol=1e-10)
+    tp1 = time.perf_counter() - t1
+    it.set_num_threads(nt)
+    _say(f"cpu baseline: one-thread Poisson solve {tp1:.1f} s")
+    return {"value": 1.0 / ts, "unit": "solves/s", "cores": nt, "kind": "oracle",
+            "sample": f"one end-to-end oracle absorbing solve of this workload ({inst.n}^3, {inst.N} blobs, f=1, "
+                      f"rtol {inst.rtol:g}, inner Poisson rtol 1e-10): {ts:.1f} s, {ost['iters']} Schur GMRES "
+                      f"iterations, {ost['inner_iters']} inner CG iterations, {ost['vcycles']} V-cycles, oracle "
+                      f"residual {ost['rel_resid']:.2e}; {nt} OpenMP threads of {os.cpu_count()} logical CPUs, {cpu}",
+            "seconds": ts, "gmres_iters": ost["iters"], "rc": ost["rc"],
+            "single_core": {"value": 1.0 / (tp1 * n_poisson), "unit": "solves/s", "cores": 1,
+                            "sample": f"one full oracle Poisson solve of the same grid (its first right-hand side, "
+                                      f"rtol 1e-10, {pst['inner_iters']} CG iterations) on 1 thread: {tp1:.1f} s, "
+                                      f"times the {n_poisson} Poisson solves of the timed absorbing solve"}}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -333,47 +379,7 @@ def main():
         net.close()
 
     if not args.no_cpu_baseline and not box:
-        from oracle import iterative as it
-        it.build(force=False)
-        # the method's first Poisson right-hand side: f minus the mean sink strength spread
-        lbar = float(np.sum(inst.f)) / inst.N
-        g = np.asarray(inst.f, dtype=np.float64) + it.spread(np.full(inst.N, -lbar), inst.q, inst.f.shape)
-        k = 2
-        t0 = time.perf_counter()
-        for _ in range(k):
-            it.solve_poisson(g, 0.0, rtol=5e-10)
-        tp = (time.perf_counter() - t0) / k
-        per_solve = st["outer_iters"] if args.workload != "rsa256_learned" else out.get("plain_fp64", {}).get(
-            "gmres_iters", st["outer_iters"])
-        n_poisson = per_solve + 2
-        cpu = "unknown CPU"
-        try:
-            with open("/proc/cpuinfo") as fh:
-                cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
-        except (OSError, StopIteration):
-            pass
-        out["cpu_baseline"] = {
-            "value": 1.0 / (tp * n_poisson), "unit": "solves/s", "cores": it.num_threads(), "kind": "oracle",
-            "sample": f"{k} oracle MG-CG Poisson solves on the same grid (rtol 5e-10, {tp:.2f} s each), scaled by "
-                      f"{n_poisson} Poisson solves per absorbing solve ({per_solve} Schur GMRES products + 2); "
-                      f"{it.num_threads()} OpenMP threads of {os.cpu_count()} logical CPUs, {cpu}"}
-        # one core: the same right-hand side's oracle V-cycle timed on one thread and on all of
-        # them; the one-core rate is the all-thread rate scaled by their ratio
-        nt = it.num_threads()
-
-        def vtime():
-            t1 = time.perf_counter()
-            it.vcycle(g, 0.0)
-            return time.perf_counter() - t1
-
-        tv_all = min(vtime(), vtime())
-        it.set_num_threads(1)
-        tv_one = vtime()
-        it.set_num_threads(nt)
-        out["cpu_baseline"]["single_core"] = {
-            "value": out["cpu_baseline"]["value"] * tv_all / tv_one, "unit": "solves/s", "cores": 1,
-            "sample": f"one oracle V-cycle on the same grid on 1 thread ({tv_one:.2f} s) and on {nt} "
-                      f"({tv_all:.2f} s); the {nt}-thread rate scaled by that ratio"}
+        out["cpu_baseline"] = cpu_baseline(inst)
     if args.copy_probe:
         src = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
