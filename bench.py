@@ -104,17 +104,19 @@ def summary(st, block=False):
 
 
 # Grids up to 64^3 are launch-latency-bound and share the lock-step batched
-# launches; larger ones are bandwidth-bound and run on their own streams.
+# launches (reactive ones in the CG rounds, block-FGMRES absorbing ones in the
+# V-cycle rounds); larger ones are bandwidth-bound and run on their own streams.
 LOCKSTEP_MAX_CELLS = 64 ** 3
 
 
-def bench_batch(args, dev, rtol):
-    """64 uneven suspensions (grids 32..128, up to 2000 blobs, reactive/absorbing 50/50); a step
-    is the whole batch. value: the lock-step executor (the reactive instances' CG iterations in
-    shared batched launches, one captured graph replayed in rounds) with the absorbing instances
-    solved by the block FGMRES on their own streams meanwhile; beside it the per-instance-stream
-    executor, one-by-one solves, and the lock-step executor with Schur-GMRES absorbing solves
-    (their inner CG iterations in the lock-step launches too)."""
+def bench_batch(args, dev, rtol, steps, warmup):
+    """64 uneven suspensions (grids 32..128, up to 2000 blobs, reactive/absorbing 50/50, absorbing
+    ones by the block FGMRES); a step is the whole batch. value: the lock-step executor with grids
+    up to 64^3 in the batched launches (reactive CG iterations in the captured CG rounds, the
+    absorbing instances' V-cycles in the captured V-cycle rounds) and the larger grids on their own
+    streams meanwhile. Beside it: every instance in the batched launches, the per-instance-stream
+    executor, one-by-one solves, and the lock-step executor with Schur-GMRES absorbing solves (their
+    inner CG iterations in the CG rounds). Returns the line's fields."""
     import torch
     import workloads as W
     from paper_1306_3159_amd import BlobRD, MIXED, SOLVER_BLOCK, SOLVER_SCHUR, solve_streams, solve_batched
@@ -137,12 +139,13 @@ def bench_batch(args, dev, rtol):
         cache = os.path.join(tempfile.mkdtemp(), "tune.json")  # one timing per distinct level shape
         tuned = sum(H.autotune(reps=5, cache=cache) for H in Hs)
 
-    def step_lockstep():
-        for c in cs:
-            c.zero_()
-        torch.cuda.synchronize()
-        return solve_batched(Hs, kinds, fs, cs, ls, stream=bstream, lockstep_max_cells=LOCKSTEP_MAX_CELLS,
-                             threads=args.threads)
+    def step_lockstep(cap):
+        def fn():
+            for c in cs:
+                c.zero_()
+            torch.cuda.synchronize()
+            return solve_batched(Hs, kinds, fs, cs, ls, stream=bstream, lockstep_max_cells=cap, threads=args.threads)
+        return fn
 
     def step_streams():
         for c in cs:
@@ -150,9 +153,10 @@ def bench_batch(args, dev, rtol):
         torch.cuda.synchronize()
         return solve_streams(Hs, kinds, fs, cs, ls, threads=args.threads)
 
-    dt, (rc, stats) = timed(step_lockstep, args.steps, args.warmup)
-    sdt, (src, sstats) = timed(step_streams, max(2, args.steps // 2), 1)
-    ns = max(2, args.steps // 2)
+    ns = max(2, steps // 2)
+    dt, (rc, stats) = timed(step_lockstep(LOCKSTEP_MAX_CELLS), steps, warmup)
+    adt, (arc, _) = timed(step_lockstep(0), ns, 1)
+    sdt, (src, _) = timed(step_streams, ns, 1)
     t1 = time.perf_counter()
     for H, k, f, c, l in zip(Hs, kinds, fs, cs, ls):
         c.zero_()
@@ -168,26 +172,25 @@ def bench_batch(args, dev, rtol):
     if args.autotune:
         for H in Hs:
             H.autotune(reps=5, cache=cache)
-    qdt, (qrc, _) = timed(step_lockstep, max(2, args.steps // 2), 1)
-    cells = sum(i.n ** 3 for i in insts)
-    out = {"metric": METRIC, "value": len(insts) * args.steps / dt, "unit": "instances/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64 Krylov/residuals + f32 V-cycles", "data": "synthetic",
-           "config": {"workload": "batch64", "instances": len(insts), "total_cells": cells,
-                      "total_blobs": sum(i.N for i in insts), "rtol": rtol,
-                      "executor": "lock-step batched launches for reactive grids <= 64^3, own streams for larger "
-                                  "grids and for the absorbing instances (block FGMRES)",
-                      "lockstep_instances": sum(1 for i in insts if i.n ** 3 <= LOCKSTEP_MAX_CELLS
-                                                and i.kind != "absorbing"),
-                      "stream_threads": args.threads, "autotuned_levels": tuned},
-           "rc": rc, "max_rel_resid": max(s["rel_resid"] for s in stats),
-           "streams_executor": {"instances_per_s": len(insts) * ns / sdt, "threads": args.threads, "rc": src},
-           "serial_instances_per_s": len(insts) / serial,
-           "lockstep_schur_gmres": {"instances_per_s": len(insts) * ns / qdt, "rc": qrc}}
+    qdt, (qrc, _) = timed(step_lockstep(LOCKSTEP_MAX_CELLS), ns, 1)
     for H in Hs:
         H.close()
-    print(json.dumps(out))
+    cells = sum(i.n ** 3 for i in insts)
+    small = [i for i in insts if i.n ** 3 <= LOCKSTEP_MAX_CELLS]
+    return {"value": len(insts) * steps / dt, "unit": "instances/s", "steps": steps, "warmup": warmup,
+            "ms_per_step": 1e3 * dt / steps,
+            "config": {"workload": "batch64", "instances": len(insts), "total_cells": cells,
+                       "total_blobs": sum(i.N for i in insts), "rtol": rtol, "absorbing_solver": "block FGMRES",
+                       "executor": "lock-step batched launches (captured CG rounds, captured V-cycle rounds) for "
+                                   "grids <= 64^3, own streams for larger grids",
+                       "lockstep_cg_instances": sum(1 for i in small if i.kind != "absorbing"),
+                       "lockstep_vcycle_instances": sum(1 for i in small if i.kind == "absorbing"),
+                       "stream_threads": args.threads, "autotuned_levels": tuned},
+            "rc": rc, "max_rel_resid": max(s["rel_resid"] for s in stats),
+            "all_lockstep": {"instances_per_s": len(insts) * ns / adt, "rc": arc},
+            "streams_executor": {"instances_per_s": len(insts) * ns / sdt, "threads": args.threads, "rc": src},
+            "serial_instances_per_s": len(insts) / serial,
+            "lockstep_schur_gmres": {"instances_per_s": len(insts) * ns / qdt, "rc": qrc}}
 
 
 def _say(msg):
@@ -249,7 +252,11 @@ def main():
     dev = torch.device("cuda:0")
     rtol = 1e-8
     if args.workload == "batch64":
-        return bench_batch(args, dev, rtol)
+        b = bench_batch(args, dev, rtol, args.steps, args.warmup)
+        print(json.dumps({"metric": METRIC, "value": b.pop("value"), "unit": b.pop("unit"), "n_gpus": 1,
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f64 Krylov/residuals + f32 V-cycles", "data": "synthetic", **b}))
+        return
     box = args.workload == "box256"
     if args.workload == "rsa256_learned":
         inst = W.learned_eval(256, 10000, index=0)
@@ -356,6 +363,9 @@ def main():
                 "value": n / xdt, "ms_per_step": 1e3 * xdt / n, "N": bx.N, "seed": bx.seed, **summary(xst, True),
                 "gs_box_cold_us": gms * 1e3, "gs_box_cold_GBs": gby / (gms * 1e-3) / 1e9}
             Bx.close()
+            # the 64 uneven suspensions of the batched workload
+            _say("batch64")
+            out["batch64"] = bench_batch(args, dev, rtol, 4, 1)
 
     # Roofline of the dominant kernel: the finest-level Gauss-Seidel half-sweep
     # (FP32), timed with HIP events on the handle's stream. Cold: back-to-back

@@ -426,8 +426,14 @@ int blob_rd_solve_streams(blob_rd_t* h, int32_t n, const int32_t* kind, double a
  * launched per level and vectorizable (x edge divisible by 16 for FP32, 8 for
  * FP64) above a coarse tail, in the first member's precision; the other
  * instances run their whole solves on their own streams meanwhile, at most
- * `threads` at a time (0: all). The results are bitwise those of solving
- * each instance alone. workspace: caller-owned device memory of
+ * `threads` at a time (0: all). Absorbing members whose handles solve by the
+ * block FGMRES (saddle_solver BLOCK or BLOCK_LEARNED) hand the executor their
+ * multigrid V-cycles instead: a second captured graph runs one V-cycle of every
+ * member waiting for one (level-0 right side and first red sweep written by the
+ * member on its own stream, ordered by an event), in rounds that start when
+ * every such member still solving is waiting or 300 us after the first request
+ * (environment BLOB_RD_VROUND_WAIT_US). The results are bitwise those of
+ * solving each instance alone. workspace: caller-owned device memory of
  * blob_rd_batch_workspace_bytes(n) bytes (descriptors and work lists). */
 size_t blob_rd_batch_workspace_bytes(int32_t n);
 int blob_rd_solve_batched(blob_rd_t* h, int32_t n, const int32_t* kind, double alpha, const double* const* f,

@@ -413,9 +413,13 @@ struct blob_rd {
     // box with the concentration held at cb on its faces (solves work on u = c - cb)
     bool box = false;
     double cb = 0.0;
-    // lock-step batch executor this handle currently belongs to (null: solo)
+    // lock-step batch executor this handle currently belongs to (null: solo); batch_v: its
+    // block-FGMRES V-cycles run in the executor's batched V-cycle rounds (batch_ev orders them
+    // after the handle's own work)
     BatchServer* batch = nullptr;
     int batch_slot = -1;
+    bool batch_v = false;
+    hipEvent_t batch_ev = nullptr;
     // this device's no-alloc scratch (device address of `scratch`, taken at create)
     ScratchSlot* noalloc = nullptr;
 
@@ -1349,13 +1353,40 @@ void fg_resid(blob_rd* H, double alpha, const double* base, const SpreadMult* M,
 }
 
 // The periodic V-cycle can open from f (the opening black sweep forms the red zero-guess
-// sweep as f_red / diag): level 0 in the LDS tail, or rows of the vector sweep.
+// sweep as f_red / diag): level 0 in the LDS tail, or rows of the vector sweep. Not in a
+// batch's V-cycle rounds, whose cycles start from a stored red sweep.
 template <typename T>
 bool cycle_opens_from_f(const blob_rd* H) {
     const Plan& P = H->P;
     const int t0 = std::min(H->tail_level[sizeof(T) == 4 ? 0 : 1], P.nlev - 1);
     const int vw = 16 / (int)sizeof(T);
-    return !H->box && (t0 == 0 || (P.lev[0].hx % vw == 0 && P.lev[0].hx >= vw));
+    return !H->box && !(H->batch && H->batch_v) && (t0 == 0 || (P.lev[0].hx % vw == 0 && P.lev[0].hx >= vw));
+}
+
+void batch_run_vcycle(blob_rd* H);
+
+// One V-cycle of the block solver: entered (r null: level-0 f and, unless from_f, the
+// first red sweep already written) or from the FP64 right side r. In a batch whose
+// V-cycle rounds take this handle, the executor runs the levels with the other
+// members' cycles (the same kernel bodies and order, so the same results).
+template <typename T>
+void fg_vcycle(blob_rd* H, double alpha, const double* r, const double* cinv, bool from_f) {
+    if (!(H->batch && H->batch_v)) {
+        vcycle<T>(H, alpha, r, nullptr, cinv, r == nullptr, nullptr, from_f);
+        return;
+    }
+    const Plan& P = H->P;
+    if (r) {
+        const LevelDims& d = P.lev[0];
+        launch_enter<T>(H->st, r, H->at<T>(P.off_lvl[0][2]), H->at<T>(P.off_lvl[0][3]), H->at<T>(P.off_lvl[0][0]),
+                        d.nx, d.ny, d.nz, 1.0 / (alpha + 6.0 * H->prm.D / (d.h * d.h)), nullptr);
+        H->alg_bytes += (double)P.ncell * (8 + P.esz * 1.5);
+    }
+    batch_run_vcycle(H);
+    const int t = std::min(H->tail_level[P.esz == 4 ? 0 : 1], P.nlev - 1);
+    for (int l = 0; l < t; ++l)
+        H->alg_bytes += (double)P.ncell / (1 << (3 * l)) * P.esz * (kPreRestrictBytes + kProlongPostBytes);
+    H->vcycles += 1;
 }
 
 // n multigrid cycles for A x = r, r = base + scale S m (M null: r = base), as a
@@ -1388,12 +1419,12 @@ void fg_cycles(blob_rd* H, double alpha, const double* base, const SpreadMult* M
                 launch_spread_enter<T>(H->st, spread_lists(H), *M, base, scale, f0, f1, from_f ? nullptr : z0, d.nx,
                                        d.ny, inv_diag);
             H->alg_bytes += (double)P.ncell * (8 + (from_f ? 1.0 : 1.5) * P.esz);
-            vcycle<T>(H, alpha, nullptr, nullptr, cinv, true, nullptr, from_f);
+            fg_vcycle<T>(H, alpha, nullptr, cinv, from_f);
             launch_split_to_nat<T>(H->st, z0, z1, x, d.nx, d.ny, d.nz, 0.0);
             H->alg_bytes += (double)P.ncell * (P.esz + 8);
         } else {
             fg_resid(H, alpha, base, M, scale, x, q);
-            vcycle<T>(H, alpha, q, nullptr, cinv);
+            fg_vcycle<T>(H, alpha, q, cinv, false);
             launch_split_to_nat<T>(H->st, z0, z1, x, d.nx, d.ny, d.nz, 1.0);
             H->alg_bytes += (double)P.ncell * (P.esz + 16);
         }
@@ -1503,7 +1534,7 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
             launch_spread_enter<T>(st, L, SpreadMult{vk, nullptr, 0.0, 0.0}, nullptr, H->inv_h3(), f0, f1,
                                    from_f ? nullptr : z0, d.nx, d.ny, inv_diag);
             H->alg_bytes += (double)nh * P.esz * ((k == 0 ? 2 : 0) + (from_f ? 0 : 1));
-            vcycle<T>(H, alpha, nullptr, nullptr, cinv, true, nullptr, from_f);
+            fg_vcycle<T>(H, alpha, nullptr, cinv, from_f);
             launch_interp_split<T>(st, z0, z1, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
                                    H->at<int>(P.off_perm), V + (size_t)(k + 1) * N);
             launch_gmres_arnoldi(st, V, Hm, H->at<double>(P.off_cs), H->at<double>(P.off_sn), gv, N, k, o.m,
@@ -1523,7 +1554,7 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
         // so the shift rides on the pass that adds z
         double* q = H->grid(G_Q);
         fg_resid(H, alpha, vg, &m2, -H->inv_h3(), zg, q);
-        vcycle<T>(H, alpha, q, nullptr, cinv);
+        fg_vcycle<T>(H, alpha, q, cinv, false);
         double* jz = H->nv(5);
         launch_interp_split<T>(st, z0, z1, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
                                H->at<int>(P.off_perm), jz);
@@ -1914,6 +1945,7 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
 
 int blob_rd_destroy(blob_rd_t H) {
     if (!H) return BLOB_RD_OK;
+    if (H->batch_ev) (void)hipEventDestroy(H->batch_ev);
     if (H->own_net) blob_rd_net_destroy(H->own_net);
     for (auto& g : H->graphs) (void)hipGraphExecDestroy(g.exec);
     H->graphs.clear();
@@ -2283,9 +2315,18 @@ namespace {
 // instance's solver logic (GMRES, set-up, final solves) runs on its own host
 // thread and stream; whenever it needs CG iterations it hands them to the
 // executor and waits. An instance takes part in a round only when it is gated
-// in, and its kernels become no-ops once its done flag is set.
+// in, and its kernels become no-ops once its done flag is set. Instances that
+// solve by the block FGMRES hand the executor their multigrid V-cycles instead:
+// a second captured graph runs one V-cycle (entered: level-0 f and the first red
+// sweep already written by the instance) for every instance gated into it.
 // ===========================================================================
 constexpr int kBatchRoundIters = 2;  // CG iterations per graph replay
+// a V-cycle round starts when every V-cycle member still solving is waiting, or
+// when the first waiter has waited this long (BLOB_RD_VROUND_WAIT_US overrides)
+double vround_wait_s() {
+    const char* e = std::getenv("BLOB_RD_VROUND_WAIT_US");
+    return e ? std::atof(e) * 1e-6 : 300e-6;
+}
 
 }  // namespace
 
@@ -2318,10 +2359,27 @@ struct BatchServer {
     unsigned tail_lds = 0;
     hipGraphExec_t exec = nullptr;
     int rounds = 0;
+    // batched V-cycle rounds of the block-FGMRES members: their gate, work lists (the
+    // level tables again, compacted for the V-cycle gate), always-open scalars and graph
+    std::vector<char> vmem;
+    int nvmem = 0;
+    int* d_gate_v = nullptr;
+    int* h_gate_v = nullptr;
+    char* d_tabs_v = nullptr;
+    char* h_tabs_v = nullptr;
+    size_t tabs_v_bytes = 0;
+    std::vector<BatchTable> tabs_v;
+    Scalars* d_vsc = nullptr;
+    hipGraphExec_t exec_v = nullptr;
+    int vrounds = 0;
+    long long v_gated = 0;
     long long gated_rounds = 0;  // sum over rounds of gated instances
     double busy_s = 0.0, idle_s = 0.0;
     // coordination
     struct Slot {
+        bool vwaiting = false;  // asked for a V-cycle (block-FGMRES members)
+        bool vdone = false;     // that V-cycle has run
+        std::chrono::steady_clock::time_point vsince;
         bool waiting = false;   // asked for CG iterations
         bool gated = false;     // taking part in rounds
         bool released = false;  // its CG run has ended
@@ -2346,8 +2404,8 @@ constexpr unsigned kPersistBlocks = 2048;  // grid of a batched launch (8 work-g
 size_t batch_tab_bytes(int n) { return batch_align(sizeof(BatchTab) + (size_t)n * sizeof(BatchEntry)); }
 
 size_t batch_bytes(int n) {
-    return batch_align((size_t)n * sizeof(InstDev)) + 2 * batch_align((size_t)n * 2 * sizeof(int)) +
-           (TAB_LEVELS + 2 * kMaxLevels) * batch_tab_bytes(n);
+    return batch_align((size_t)n * sizeof(InstDev)) + 3 * batch_align((size_t)n * 2 * sizeof(int)) +
+           (TAB_LEVELS + 4 * kMaxLevels) * batch_tab_bytes(n) + batch_align((size_t)n * sizeof(Scalars));
 }
 
 // Why instance H cannot run its CG iterations in batched launches (empty: it can).
@@ -2412,16 +2470,43 @@ void batch_round(BatchServer& B, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_status, dim3((B.n + 63) / 64), dim3(64), 0, s, I, B.n, B.d_status);
 }
 
+// One entered V-cycle (level-0 f and the first red sweep written by the instance) of
+// every instance gated into the V-cycle rounds: the per-level launches of the CG
+// round's preconditioner, closing with a plain red sweep.
+template <typename T>
+void batch_round_v(BatchServer& B, hipStream_t s) {
+    const InstDev* I = B.d_inst;
+    const int* G = B.d_gate_v;
+    auto T_ = [&](int k) { return reinterpret_cast<const BatchTab*>(B.d_tabs_v + B.tabs_v[k].off); };
+    auto grid = [&](int k) { return B.tabs_v[k].grid; };
+    const int LV = 0, RS = B.Lmax;
+    for (int l = 0; l < B.Lmax; ++l) {
+        launchb_mg<T>(s, BMG_GS, I, G, T_(LV + l), grid(LV + l), l, 1, 0);
+        launchb_mg<T>(s, BMG_GS, I, G, T_(LV + l), grid(LV + l), l, 0, 0);
+        launchb_mg<T>(s, BMG_GS, I, G, T_(LV + l), grid(LV + l), l, 1, 0);
+        launchb_mg<T>(s, BMG_RESID, I, G, T_(LV + l), grid(LV + l), l, 0, 0);
+        launchb_mg<T>(s, BMG_RESTRICT, I, G, T_(RS + l), grid(RS + l), l, 0, 0);
+    }
+    launchb_mg<T>(s, BMG_TAIL, I, G, nullptr, B.n, 0, 0, B.tail_lds);
+    for (int l = B.Lmax - 1; l >= 0; --l) {
+        launchb_mg<T>(s, BMG_PROLONG, I, G, T_(LV + l), grid(LV + l), l, 0, 0);
+        launchb_mg<T>(s, BMG_GS, I, G, T_(LV + l), grid(LV + l), l, 1, 0);
+        launchb_mg<T>(s, BMG_GS, I, G, T_(LV + l), grid(LV + l), l, 0, 0);
+        launchb_mg<T>(s, BMG_GS, I, G, T_(LV + l), grid(LV + l), l, 1, 0);
+        launchb_mg<T>(s, BMG_GS, I, G, T_(LV + l), grid(LV + l), l, 0, 0);
+    }
+}
+
 // Work lists of the round: the gated instances' slices, each starting at a
 // multiple of 8 virtual blocks (a slot keeps the XCD of its solo launch).
-void batch_fill_tabs(BatchServer& B) {
-    for (const BatchTable& t : B.tabs) {
-        BatchTab* h = reinterpret_cast<BatchTab*>(B.h_tabs + t.off);
+void fill_tabs(const std::vector<BatchTable>& tabs, const int* gate, char* h_tabs, int n) {
+    for (const BatchTable& t : tabs) {
+        BatchTab* h = reinterpret_cast<BatchTab*>(h_tabs + t.off);
         BatchEntry* e = reinterpret_cast<BatchEntry*>(h + 1);
         unsigned g = 0;
         int k = 0;
-        for (int i = 0; i < B.n; ++i) {
-            if (!B.h_gate[i] || !t.nb[i]) continue;
+        for (int i = 0; i < n; ++i) {
+            if (!gate[i] || !t.nb[i]) continue;
             e[k++] = BatchEntry{g, t.nb[i], i, 0};
             g += (t.nb[i] + 7u) & ~7u;
         }
@@ -2429,6 +2514,7 @@ void batch_fill_tabs(BatchServer& B) {
         h->n = k;
     }
 }
+void batch_fill_tabs(BatchServer& B) { fill_tabs(B.tabs, B.h_gate, B.h_tabs, B.n); }
 
 // Descriptor of instance H for CG iterations with operator alpha (x set per CG run).
 void batch_describe(BatchServer& B, int i, blob_rd* H, bool blobs) {
@@ -2437,7 +2523,7 @@ void batch_describe(BatchServer& B, int i, blob_rd* H, bool blobs) {
     std::memset(&D, 0, sizeof(InstDev));
     const int L = P.nlev - 1;
     const int t = H->tail_level[P.esz == 4 ? 0 : 1];
-    D.sc = H->sc();
+    D.sc = B.vmem[i] ? B.d_vsc + i : H->sc();  // V-cycle members: a done flag that stays 0
     D.part = H->part();
     D.x = H->grid(G_U);
     D.r = H->grid(G_R);
@@ -2489,11 +2575,19 @@ void batch_setup(BatchServer& B, char* ws, size_t ws_bytes, const int32_t* kind)
     o += batch_align((size_t)n * 2 * sizeof(int));
     B.d_status = reinterpret_cast<int*>(o);
     o += batch_align((size_t)n * 2 * sizeof(int));
+    B.d_gate_v = reinterpret_cast<int*>(o);
+    o += batch_align((size_t)n * 2 * sizeof(int));
+    B.d_vsc = reinterpret_cast<Scalars*>(o);
+    o += batch_align((size_t)n * sizeof(Scalars));
     B.d_tabs = o;
+    B.d_tabs_v = o + (TAB_LEVELS + 2 * kMaxLevels) * batch_tab_bytes(n);
     (void)ws_bytes;
+    HIPCHK(hipMemsetAsync(B.d_vsc, 0, (size_t)n * sizeof(Scalars), B.st));
     HIPCHK(hipHostMalloc((void**)&B.h_inst, (size_t)n * sizeof(InstDev), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&B.h_gate, (size_t)n * 2 * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&B.h_status, (size_t)n * 2 * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&B.h_gate_v, (size_t)n * 2 * sizeof(int), hipHostMallocDefault));
+    std::memset(B.h_gate_v, 0, (size_t)n * 2 * sizeof(int));
     B.Lmax = 0;
     for (int i = 0; i < n; ++i) {
         blob_rd* H = B.hs[i];
@@ -2539,6 +2633,15 @@ void batch_setup(BatchServer& B, char* ws, size_t ws_bytes, const int32_t* kind)
     B.tabs_bytes = B.tabs.size() * tb;
     HIPCHK(hipHostMalloc((void**)&B.h_tabs, B.tabs_bytes, hipHostMallocDefault));
     std::memset(B.h_tabs, 0, B.tabs_bytes);
+    // the V-cycle rounds' copies of the level tables (sweep/residual/correction, restriction)
+    B.tabs_v.assign(2 * B.Lmax, BatchTable{});
+    for (int k = 0; k < 2 * B.Lmax; ++k) {
+        B.tabs_v[k] = B.tabs[TAB_LEVELS + k];
+        B.tabs_v[k].off = (size_t)k * tb;
+    }
+    B.tabs_v_bytes = std::max<size_t>(B.tabs_v.size() * tb, tb);
+    HIPCHK(hipHostMalloc((void**)&B.h_tabs_v, B.tabs_v_bytes, hipHostMallocDefault));
+    std::memset(B.h_tabs_v, 0, B.tabs_v_bytes);
     HIPCHK(hipMemcpyAsync(B.d_tabs, B.h_tabs, B.tabs_bytes, hipMemcpyHostToDevice, B.st));
     HIPCHK(hipMemcpyAsync(B.d_inst, B.h_inst, (size_t)n * sizeof(InstDev), hipMemcpyHostToDevice, B.st));
     HIPCHK(hipMemcpyAsync(B.d_gate, B.h_gate, (size_t)n * sizeof(int), hipMemcpyHostToDevice, B.st));
@@ -2554,11 +2657,25 @@ void batch_setup(BatchServer& B, char* ws, size_t ws_bytes, const int32_t* kind)
     HIPCHK(hipStreamEndCapture(cap, &graph));
     HIPCHK(hipGraphInstantiate(&B.exec, graph, nullptr, nullptr, 0));
     (void)hipGraphDestroy(graph);
+    if (B.nvmem) {
+        HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        if (B.esz == 4) batch_round_v<float>(B, cap);
+        else batch_round_v<double>(B, cap);
+        HIPCHK(hipStreamEndCapture(cap, &graph));
+        HIPCHK(hipGraphInstantiate(&B.exec_v, graph, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(graph);
+    }
     (void)hipStreamDestroy(cap);
 }
 
 void batch_teardown(BatchServer& B) {
     if (B.exec) (void)hipGraphExecDestroy(B.exec);
+    if (B.exec_v) (void)hipGraphExecDestroy(B.exec_v);
+    if (B.h_gate_v) (void)hipHostFree(B.h_gate_v);
+    if (B.h_tabs_v) (void)hipHostFree(B.h_tabs_v);
+    B.exec_v = nullptr;
+    B.h_gate_v = nullptr;
+    B.h_tabs_v = nullptr;
     if (B.h_inst) (void)hipHostFree(B.h_inst);
     if (B.h_gate) (void)hipHostFree(B.h_gate);
     if (B.h_status) (void)hipHostFree(B.h_status);
@@ -2592,24 +2709,60 @@ void batch_run_cg(blob_rd* H, double* x, int maxit, bool blobs, double alpha) {
     if (!B.fault.empty() && !S.released) throw Err(BLOB_RD_EDEVICE, "batch executor: " + B.fault);
 }
 
+// Instance side: one entered V-cycle of H's levels in the executor's next V-cycle round
+// (after H's own work so far, through its event); returns once that round has run.
+void batch_run_vcycle(blob_rd* H) {
+    BatchServer& B = *H->batch;
+    const int i = H->batch_slot;
+    HIPCHK(hipEventRecord(H->batch_ev, H->st));
+    std::unique_lock<std::mutex> lk(B.m);
+    if (!B.fault.empty()) throw Err(BLOB_RD_EDEVICE, "batch executor: " + B.fault);
+    BatchServer::Slot& S = B.slots[i];
+    S.vdone = false;
+    S.vwaiting = true;
+    S.vsince = std::chrono::steady_clock::now();
+    B.cv.notify_all();
+    S.cv.wait(lk, [&] { return S.vdone || !B.fault.empty(); });
+    if (!B.fault.empty() && !S.vdone) throw Err(BLOB_RD_EDEVICE, "batch executor: " + B.fault);
+}
+
 // Executor side: rounds of the captured graph for the gated instances until
 // every instance's solve has returned.
 void batch_serve(BatchServer& B) {
     using clk = std::chrono::steady_clock;
+    const auto vwait = std::chrono::duration_cast<clk::duration>(std::chrono::duration<double>(vround_wait_s()));
     for (;;) {
-        std::vector<int> upload;
+        std::vector<int> upload, vgated;
         const auto w0 = clk::now();
+        bool any = false;
         {
             std::unique_lock<std::mutex> lk(B.m);
-            B.cv.wait(lk, [&] {
-                bool any = false, all_done = true;
-                for (auto& S : B.slots) {
-                    any = any || S.waiting || S.gated;
+            // CG work starts a round at once; V-cycle requests wait for the other V-cycle
+            // members still solving (they ask at nearly the same points) or for a deadline
+            auto ready = [&](clk::time_point* deadline) {
+                bool cg = false, all_done = true, vany = false, vall = true;
+                clk::time_point first = clk::time_point::max();
+                for (int i = 0; i < B.n; ++i) {
+                    const BatchServer::Slot& S = B.slots[i];
+                    cg = cg || S.waiting || S.gated;
                     all_done = all_done && S.finished;
+                    if (!B.vmem[i] || S.finished) continue;
+                    if (S.vwaiting) {
+                        vany = true;
+                        first = std::min(first, S.vsince);
+                    } else {
+                        vall = false;
+                    }
                 }
-                return any || all_done;
-            });
-            bool any = false;
+                if (vany) *deadline = first + vwait;
+                return cg || all_done || (vany && (vall || clk::now() >= *deadline));
+            };
+            for (;;) {
+                clk::time_point deadline = clk::time_point::max();
+                if (ready(&deadline)) break;
+                if (deadline == clk::time_point::max()) B.cv.wait(lk);
+                else B.cv.wait_until(lk, deadline);
+            }
             for (int i = 0; i < B.n; ++i) {
                 BatchServer::Slot& S = B.slots[i];
                 if (S.waiting) {
@@ -2619,21 +2772,38 @@ void batch_serve(BatchServer& B) {
                     if (S.dirty) upload.push_back(i);
                     S.dirty = false;
                 }
+                B.h_gate_v[i] = 0;
+                if (S.vwaiting) {
+                    S.vwaiting = false;
+                    B.h_gate_v[i] = 1;
+                    vgated.push_back(i);
+                }
                 any = any || S.gated;
             }
-            if (!any) return;  // every solve has returned
-            batch_fill_tabs(B);
+            if (!any && vgated.empty()) return;  // every solve has returned
+            if (any) batch_fill_tabs(B);
+            if (!vgated.empty()) fill_tabs(B.tabs_v, B.h_gate_v, B.h_tabs_v, B.n);
         }
         const auto w1 = clk::now();
         B.idle_s += std::chrono::duration<double>(w1 - w0).count();
         for (int i = 0; i < B.n; ++i) B.gated_rounds += B.h_gate[i];
         try {
-            for (int i : upload)
-                HIPCHK(hipMemcpyAsync(B.d_inst + i, B.h_inst + i, sizeof(InstDev), hipMemcpyHostToDevice, B.st));
-            HIPCHK(hipMemcpyAsync(B.d_gate, B.h_gate, (size_t)B.n * sizeof(int), hipMemcpyHostToDevice, B.st));
-            HIPCHK(hipMemcpyAsync(B.d_tabs, B.h_tabs, B.tabs_bytes, hipMemcpyHostToDevice, B.st));
-            HIPCHK(hipGraphLaunch(B.exec, B.st));
-            HIPCHK(hipMemcpyAsync(B.h_status, B.d_status, (size_t)B.n * 2 * sizeof(int), hipMemcpyDeviceToHost, B.st));
+            if (!vgated.empty()) {
+                for (int i : vgated) HIPCHK(hipStreamWaitEvent(B.st, B.hs[i]->batch_ev, 0));
+                HIPCHK(hipMemcpyAsync(B.d_gate_v, B.h_gate_v, (size_t)B.n * sizeof(int), hipMemcpyHostToDevice,
+                                      B.st));
+                HIPCHK(hipMemcpyAsync(B.d_tabs_v, B.h_tabs_v, B.tabs_v_bytes, hipMemcpyHostToDevice, B.st));
+                HIPCHK(hipGraphLaunch(B.exec_v, B.st));
+            }
+            if (any) {
+                for (int i : upload)
+                    HIPCHK(hipMemcpyAsync(B.d_inst + i, B.h_inst + i, sizeof(InstDev), hipMemcpyHostToDevice, B.st));
+                HIPCHK(hipMemcpyAsync(B.d_gate, B.h_gate, (size_t)B.n * sizeof(int), hipMemcpyHostToDevice, B.st));
+                HIPCHK(hipMemcpyAsync(B.d_tabs, B.h_tabs, B.tabs_bytes, hipMemcpyHostToDevice, B.st));
+                HIPCHK(hipGraphLaunch(B.exec, B.st));
+                HIPCHK(hipMemcpyAsync(B.h_status, B.d_status, (size_t)B.n * 2 * sizeof(int),
+                                      hipMemcpyDeviceToHost, B.st));
+            }
             HIPCHK(hipStreamSynchronize(B.st));
         } catch (const Err& e) {
             std::lock_guard<std::mutex> lk(B.m);
@@ -2641,9 +2811,17 @@ void batch_serve(BatchServer& B) {
             for (auto& S : B.slots) S.cv.notify_all();
             return;
         }
-        ++B.rounds;
+        if (any) ++B.rounds;
+        if (!vgated.empty()) {
+            ++B.vrounds;
+            B.v_gated += (long long)vgated.size();
+        }
         B.busy_s += std::chrono::duration<double>(clk::now() - w1).count();
         std::lock_guard<std::mutex> lk(B.m);
+        for (int i : vgated) {
+            B.slots[i].vdone = true;
+            B.slots[i].cv.notify_all();
+        }
         for (int i = 0; i < B.n; ++i) {
             BatchServer::Slot& S = B.slots[i];
             if (!S.gated) continue;
@@ -3375,22 +3553,28 @@ int blob_rd_solve_batched(blob_rd_t* hs, int32_t n, const int32_t* kind, double 
     // Members of the lock-step launches: grids up to lockstep_max_cells whose
     // levels fit the batched kernels, in the first member's precision. The
     // others run their CG iterations on their own streams meanwhile.
+    // Block-FGMRES absorbing instances join as V-cycle members: their multigrid cycles
+    // run in the batched V-cycle rounds.
     std::vector<int> member, mkind;
+    std::vector<char> vmem;
     int esz = 0;
     for (int i = 0; i < n; ++i) {
         const blob_rd* H = hs[i];
+        const bool block = kind[i] == 1 && H->prm.saddle_solver != BLOB_RD_SOLVER_SCHUR;
         if (lockstep_max_cells > 0 && (int64_t)H->P.ncell > lockstep_max_cells) continue;
-        if (kind[i] == 1 && H->prm.saddle_solver != BLOB_RD_SOLVER_SCHUR) continue;  // block FGMRES: own stream
         if (H->box) continue;  // the batched kernels are the periodic ones
         if (!batch_unfit(H, esz ? esz : (int)H->P.esz).empty()) continue;
         esz = (int)H->P.esz;
         member.push_back(i);
         mkind.push_back(kind[i]);
+        vmem.push_back(block ? 1 : 0);
     }
     BatchServer B;
     B.n = (int)member.size();
     B.esz = esz ? esz : 4;
     B.alpha = alpha;
+    B.vmem = vmem;
+    for (char v : vmem) B.nvmem += v;
     for (int i : member) B.hs.push_back(hs[i]);
     B.st = (hipStream_t)stream;
     B.slots = std::vector<BatchServer::Slot>(B.n);
@@ -3405,8 +3589,18 @@ int blob_rd_solve_batched(blob_rd_t* hs, int32_t n, const int32_t* kind, double 
             return e.code;
         }
         for (int k = 0; k < B.n; ++k) {
+            blob_rd* H = hs[member[k]];
+            if (B.vmem[k] && !H->batch_ev &&
+                hipEventCreateWithFlags(&H->batch_ev, hipEventDisableTiming) != hipSuccess) {
+                batch_teardown(B);
+                g_last_error = "event creation failed";
+                return BLOB_RD_EDEVICE;
+            }
+        }
+        for (int k = 0; k < B.n; ++k) {
             hs[member[k]]->batch = &B;
             hs[member[k]]->batch_slot = k;
+            hs[member[k]]->batch_v = B.vmem[k] != 0;
         }
     }
     std::vector<int> rcs(n, 0), slot_of(n, -1);
@@ -3445,13 +3639,16 @@ int blob_rd_solve_batched(blob_rd_t* hs, int32_t n, const int32_t* kind, double 
     if (B.n) batch_serve(B);
     for (auto& t : th) t.join();
     if (std::getenv("BLOB_RD_LOG"))
-        std::fprintf(stderr, "[blob_rd] batched solve: %d instances (%d in lock-step launches), %.1f ms, %d rounds "
-                     "(%.1f ms running, %.1f ms waiting for instances), %.1f instances per round\n", n, B.n,
+        std::fprintf(stderr, "[blob_rd] batched solve: %d instances (%d in lock-step launches, %d of them by V-cycle "
+                     "rounds), %.1f ms, %d CG rounds, %d V-cycle rounds (%.1f ms running, %.1f ms waiting for "
+                     "instances), %.1f instances per CG round, %.1f per V-cycle round\n", n, B.n, B.nvmem,
                      1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(), B.rounds,
-                     1e3 * B.busy_s, 1e3 * B.idle_s, B.rounds ? (double)B.gated_rounds / B.rounds : 0.0);
+                     B.vrounds, 1e3 * B.busy_s, 1e3 * B.idle_s, B.rounds ? (double)B.gated_rounds / B.rounds : 0.0,
+                     B.vrounds ? (double)B.v_gated / B.vrounds : 0.0);
     for (int k = 0; k < B.n; ++k) {
         hs[member[k]]->batch = nullptr;
         hs[member[k]]->batch_slot = -1;
+        hs[member[k]]->batch_v = false;
     }
     batch_teardown(B);
     for (int i = 0; i < n; ++i)
