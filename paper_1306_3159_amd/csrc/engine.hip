@@ -387,6 +387,20 @@ struct blob_rd {
         double bytes_per_iter;
     };
     std::vector<GraphEntry> graphs;
+    // block-FGMRES iterations captured as HIP graphs, one per basis index j and
+    // configuration (basis workspace, alpha, preconditioner options), with the
+    // counters one replay adds
+    struct FgGraph {
+        const char* ws;
+        int j, esz, kind, m, n, restart, group;
+        double alpha;
+        bool fuse, learned;
+        hipGraphExec_t exec;
+        double bytes;
+        int vcycles, inner, fallback;
+    };
+    std::vector<FgGraph> fg_graphs;
+    bool fg_capture = true;  // off for calls that must not allocate
     hipStream_t cap_stream = nullptr;
     bool use_graphs = true;
     bool relax = true;  // relaxed inner tolerances in the Schur GMRES
@@ -485,6 +499,14 @@ const double* select_cinv(blob_rd* H, double alpha) {
             if (H->graphs[i].alpha == old) {
                 (void)hipGraphExecDestroy(H->graphs[i].exec);
                 H->graphs.erase(H->graphs.begin() + i);
+            } else {
+                ++i;
+            }
+        }
+        for (size_t i = 0; i < H->fg_graphs.size();) {
+            if (H->fg_graphs[i].alpha == old) {
+                (void)hipGraphExecDestroy(H->fg_graphs[i].exec);
+                H->fg_graphs.erase(H->fg_graphs.begin() + i);
             } else {
                 ++i;
             }
@@ -664,10 +686,12 @@ unsigned vcycle(blob_rd* H, double alpha, const double* r, const Scalars* sc, co
         launch_gs<T>(st, lv(l, 1), lv(l, 0), lv(l, 3), d.hx, d.ny, d.nz, 1, s, 1.0 / diag, sc, b[0]);
     };
     if (!entered) {
+        // with from_f the first red sweep is not stored: the opening black sweep forms it
         const LevelDims& d = P.lev[0];
         const double s = D / (d.h * d.h);
-        launch_enter<T>(st, r, lv(0, 2), lv(0, 3), lv(0, 0), d.nx, d.ny, d.nz, 1.0 / (alpha + 6.0 * s), sc);
-        H->alg_bytes += (double)P.ncell * (8 + P.esz * 1.5);
+        launch_enter<T>(st, r, lv(0, 2), lv(0, 3), from_f ? nullptr : lv(0, 0), d.nx, d.ny, d.nz,
+                        1.0 / (alpha + 6.0 * s), sc);
+        H->alg_bytes += (double)P.ncell * (8 + P.esz * (from_f ? 1.0 : 1.5));
     }
     // levels below the finest whose pre- and post-smoothing run temporally blocked:
     // those of at most 64^3 cells, where a launch costs more than the level's bytes
@@ -1372,7 +1396,8 @@ void batch_run_vcycle(blob_rd* H);
 template <typename T>
 void fg_vcycle(blob_rd* H, double alpha, const double* r, const double* cinv, bool from_f) {
     if (!(H->batch && H->batch_v)) {
-        vcycle<T>(H, alpha, r, nullptr, cinv, r == nullptr, nullptr, from_f);
+        // from a right side r the entry need not store the first red sweep either
+        vcycle<T>(H, alpha, r, nullptr, cinv, r == nullptr, nullptr, r ? cycle_opens_from_f<T>(H) : from_f);
         return;
     }
     const Plan& P = H->P;
@@ -1612,15 +1637,19 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
     // normalising a basis vector also sums its grid part for the preconditioner's mean step
     // (singular A) when the partial-sum buffer holds one partial per block
     const bool fuse_sum = singular(H, alpha) && red_blocks(n) <= 3 * P.part_cap;
-    auto scale_basis = [&](double* v, const double* hv) {
+    auto scale_basis = [&](hipStream_t s, double* v, const double* hv) {
         if (fuse_sum) {
             unsigned nps = 0;
-            launch_fg_scale_sum(st, v, hv, n, ncell, H->part(), &nps);
-            launch_reduce_parts(st, H->part(), nps, 1, H->dsc() + 48);
+            launch_fg_scale_sum(s, v, hv, n, ncell, H->part(), &nps);
+            launch_reduce_parts(s, H->part(), nps, 1, H->dsc() + 48);
         } else {
-            launch_fg_scale(st, v, hv, n);
+            launch_fg_scale(s, v, hv, n);
         }
     };
+    // the Arnoldi steps run as captured graphs (not in a batch's V-cycle rounds, which
+    // rendezvous with the executor on the host, nor where the call must not allocate)
+    const bool graphs = H->use_graphs && H->fg_capture && !H->batch;
+    (void)select_cinv(H, alpha);  // its upload, if any, happens outside any capture
     if (warm) {
         // (c, lam) hold the initial guess; the scale of the residual is |b| = |[f; phi]|
         unsigned np = 0;
@@ -1654,41 +1683,89 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
         if (stalled >= 2) break;
         prev_rel = rel;
         ++cycles;
-        scale_basis(V, sd);
+        scale_basis(st, V, sd);
         launch_fg_gstart(st, gv, ld, sd);
         H->alg_bytes += (double)n * 16;
         int k = 0;
         for (int j = 0; j < m && its < o.maxit; ++j) {
-            double* vj = V + (size_t)j * stride;
-            double* zj = Z + (size_t)j * stride;
-            double* w = V + (size_t)(j + 1) * stride;
-            fg_precond<T>(H, alpha, o, vj, vj + ncell, zj, zj + ncell, fuse_sum);
-            fg_apply_K(H, alpha, zj, zj + ncell, w, w + ncell);
-            double* col = Hd + (size_t)j * ld;
-            if (group >= 1) {
-                // h = V^T w, w -= V h, |w|; once more (dots into c2, h += c2) when |w| fell below
-                // kReorth of its length before the projection
-                const int mv = j + 1;
-                launch_fg_cgs_dots(st, w, V, stride, n, mv, group, col, sd + 6, H->part(), nullptr);
-                launch_fg_cgs_update(st, w, V, stride, n, col, mv, H->part(), nullptr, col + j + 1, sd + 6,
-                                     kReorth * kReorth, redo, nullptr, nullptr);
-                launch_fg_cgs_dots(st, w, V, stride, n, mv, group, c2, nullptr, H->part(), redo);
-                launch_fg_cgs_update(st, w, V, stride, n, c2, mv, H->part(), redo, col + j + 1, nullptr, 0.0,
-                                     nullptr, col, c2);
-                const int passes = (mv + group - 1) / group;
-                H->alg_bytes += (double)n * 8 * ((double)mv + passes + (mv + 2));
-            } else {
-                for (int i = 0; i <= j + 1; ++i) {
-                    const double* vprev = i > 0 ? V + (size_t)(i - 1) * stride : nullptr;
-                    const double* vnext = i <= j ? V + (size_t)i * stride : nullptr;
-                    launch_fg_mgs(st, w, vprev, i > 0 ? col + (i - 1) : nullptr, vnext, n, H->part(), &np);
-                    launch_fg_fin(st, H->part(), np, col + i, i == j + 1);
-                    H->alg_bytes += (double)n * 8 * ((vprev ? 3 : 1) + (vnext ? 1 : 0));
+            // one Arnoldi step: z_j = M^-1 v_j, w = K z_j orthogonalised against the basis and
+            // normalised, the Givens rotation of column j (all on the handle's current stream)
+            auto step = [&]() {
+                hipStream_t s = H->st;
+                double* vj = V + (size_t)j * stride;
+                double* zj = Z + (size_t)j * stride;
+                double* w = V + (size_t)(j + 1) * stride;
+                fg_precond<T>(H, alpha, o, vj, vj + ncell, zj, zj + ncell, fuse_sum);
+                fg_apply_K(H, alpha, zj, zj + ncell, w, w + ncell);
+                double* col = Hd + (size_t)j * ld;
+                if (group >= 1) {
+                    // h = V^T w, w -= V h, |w|; once more (dots into c2, h += c2) when |w| fell below
+                    // kReorth of its length before the projection
+                    const int mv = j + 1;
+                    launch_fg_cgs_dots(s, w, V, stride, n, mv, group, col, sd + 6, H->part(), nullptr);
+                    launch_fg_cgs_update(s, w, V, stride, n, col, mv, H->part(), nullptr, col + j + 1, sd + 6,
+                                         kReorth * kReorth, redo, nullptr, nullptr);
+                    launch_fg_cgs_dots(s, w, V, stride, n, mv, group, c2, nullptr, H->part(), redo);
+                    launch_fg_cgs_update(s, w, V, stride, n, c2, mv, H->part(), redo, col + j + 1, nullptr, 0.0,
+                                         nullptr, col, c2);
+                    const int passes = (mv + group - 1) / group;
+                    H->alg_bytes += (double)n * 8 * ((double)mv + passes + (mv + 2));
+                } else {
+                    unsigned np2 = 0;
+                    for (int i = 0; i <= j + 1; ++i) {
+                        const double* vprev = i > 0 ? V + (size_t)(i - 1) * stride : nullptr;
+                        const double* vnext = i <= j ? V + (size_t)i * stride : nullptr;
+                        launch_fg_mgs(s, w, vprev, i > 0 ? col + (i - 1) : nullptr, vnext, n, H->part(), &np2);
+                        launch_fg_fin(s, H->part(), np2, col + i, i == j + 1);
+                        H->alg_bytes += (double)n * 8 * ((vprev ? 3 : 1) + (vnext ? 1 : 0));
+                    }
                 }
+                scale_basis(s, w, col + j + 1);
+                H->alg_bytes += (double)n * 16;
+                launch_fg_givens(s, Hd, ld, cs, sn, gv, j, sd + 2);
+            };
+            if (graphs) {
+                // replay the captured step of this j (capture it on first use)
+                const bool learned = o.kind == BLOB_RD_SADDLE_LEARNED && singular(H, alpha) && H->lrn.ready &&
+                                     !H->lrn.bad;
+                blob_rd::FgGraph* ge = nullptr;
+                for (auto& g : H->fg_graphs)
+                    if (g.ws == ws && g.j == j && g.esz == (int)sizeof(T) && g.kind == o.kind && g.m == o.m &&
+                        g.n == o.n && g.restart == m && g.group == group && g.alpha == alpha && g.fuse == fuse_sum &&
+                        g.learned == learned)
+                        ge = &g;
+                if (!ge) {
+                    if (!H->cap_stream) HIPCHK(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
+                    const double b0 = H->alg_bytes;
+                    const int v0 = H->vcycles, i0 = H->inner_iters, f0 = H->fallback;
+                    hipStream_t keep = H->st;
+                    H->st = H->cap_stream;
+                    HIPCHK(hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeThreadLocal));
+                    step();
+                    hipGraph_t graph;
+                    H->st = keep;
+                    HIPCHK(hipStreamEndCapture(H->cap_stream, &graph));
+                    hipGraphExec_t exec;
+                    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(graph);
+                    HIPCHK(e);
+                    H->fg_graphs.push_back({ws, j, (int)sizeof(T), o.kind, o.m, o.n, m, group, alpha, fuse_sum,
+                                            learned, exec, H->alg_bytes - b0, H->vcycles - v0, H->inner_iters - i0,
+                                            H->fallback});
+                    ge = &H->fg_graphs.back();
+                    H->alg_bytes = b0;
+                    H->vcycles = v0;
+                    H->inner_iters = i0;
+                    H->fallback = f0;
+                }
+                HIPCHK(hipGraphLaunch(ge->exec, st));
+                H->alg_bytes += ge->bytes;
+                H->vcycles += ge->vcycles;
+                H->inner_iters += ge->inner;
+                H->fallback = std::max(H->fallback, ge->fallback);
+            } else {
+                step();
             }
-            scale_basis(w, col + j + 1);
-            H->alg_bytes += (double)n * 16;
-            launch_fg_givens(st, Hd, ld, cs, sn, gv, j, sd + 2);
             sync_read(H, H->hbuf, sd + 2, 16);
             ++its;
             k = j + 1;
@@ -1946,6 +2023,8 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
 int blob_rd_destroy(blob_rd_t H) {
     if (!H) return BLOB_RD_OK;
     if (H->batch_ev) (void)hipEventDestroy(H->batch_ev);
+    for (auto& g : H->fg_graphs) (void)hipGraphExecDestroy(g.exec);
+    H->fg_graphs.clear();
     if (H->own_net) blob_rd_net_destroy(H->own_net);
     for (auto& g : H->graphs) (void)hipGraphExecDestroy(g.exec);
     H->graphs.clear();
@@ -2301,6 +2380,8 @@ bool valid_block(int v) {
 void drop_graphs(blob_rd* H) {
     for (auto& g : H->graphs) (void)hipGraphExecDestroy(g.exec);
     H->graphs.clear();
+    for (auto& g : H->fg_graphs) (void)hipGraphExecDestroy(g.exec);
+    H->fg_graphs.clear();
 }
 
 }  // namespace
@@ -2938,6 +3019,10 @@ int precond_build_into(blob_rd* H, blob_rd_net* Nt, void* buf, size_t bytes, siz
     if (bytes < need) throw Err(BLOB_RD_ENOMEM, "precond buffer smaller than the size reported");
     char* b = (char*)(((uintptr_t)buf + 255) & ~(uintptr_t)255);
     if (b + need - 256 > (char*)buf + bytes) throw Err(BLOB_RD_ENOMEM, "precond buffer misaligned/too small");
+    // captured block-FGMRES steps read the previous W's buffers
+    HIPCHK(hipStreamSynchronize(H->st));
+    for (auto& g : H->fg_graphs) (void)hipGraphExecDestroy(g.exec);
+    H->fg_graphs.clear();
     auto& L = H->lrn;
     L.rowptr = (int*)b;
     b += align_up((size_t)(N + 1) * 4);
@@ -3784,11 +3869,15 @@ int blob_rd_solve_absorbing_fgmres_noalloc(blob_rd_t H, double alpha, const blob
     // a new alpha evicting a cached coarse inverse would also drop captured CG graphs
     bool cached = false;
     for (int k = 0; k < H->cinv_used; ++k) cached = cached || H->cinv_alpha[k] == alpha;
-    if (!cached && H->cinv_used == 4)
-        for (const auto& g : H->graphs)
-            if (g.alpha == H->cinv_alpha[H->cinv_next])
-                return g_last_error = "this alpha would evict a captured CG graph; solve with a cached alpha",
-                       BLOB_RD_EINVAL;
+    if (!cached && H->cinv_used == 4) {
+        const double old = H->cinv_alpha[H->cinv_next];
+        bool captured = false;
+        for (const auto& g : H->graphs) captured = captured || g.alpha == old;
+        for (const auto& g : H->fg_graphs) captured = captured || g.alpha == old;
+        if (captured)
+            return g_last_error = "this alpha would evict a captured graph; solve with a cached alpha",
+                   BLOB_RD_EINVAL;
+    }
     return guarded(H, stt, [&]() {
         const FgOpts o = fg_opts(H, opts);
         const size_t need = fg_bytes(H->P, o.restart);
@@ -3798,8 +3887,17 @@ int blob_rd_solve_absorbing_fgmres_noalloc(blob_rd_t H, double alpha, const blob
                                           " of the no-alloc scratch (use a shorter restart or a workspace)");
         std::lock_guard<std::mutex> lk(H->noalloc->use);
         char* ws = H->noalloc->ptr;
-        int rc = H->P.esz == 4 ? fg_entry<float>(H, alpha, o, f, c, lambda, ws, stt, false)
+        // no graph capture here (instantiating a graph allocates)
+        H->fg_capture = false;
+        int rc;
+        try {
+            rc = H->P.esz == 4 ? fg_entry<float>(H, alpha, o, f, c, lambda, ws, stt, false)
                                : fg_entry<double>(H, alpha, o, f, c, lambda, ws, stt, false);
+        } catch (...) {
+            H->fg_capture = true;
+            throw;
+        }
+        H->fg_capture = true;
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(H->st));  // the scratch is free again once this returns
         return rc;
