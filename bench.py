@@ -373,12 +373,18 @@ def main():
     # (HBM bandwidth); warm: back-to-back launches on the same data.
     ms, by = S.time_kernel("gs", args.kernel_reps, cold=True)
     wms, _ = S.time_kernel("gs", args.kernel_reps)
+    # the streaming ceiling of a launch this size: out = a + b over three arrays of the same size,
+    # in the sweep's launch shape, rotating cold the same way
+    pms, pby = S.time_kernel("stream", args.kernel_reps, cold=True)
     ach = by / (ms * 1e-3) / 1e9
     out["roofline"] = {"kernel": "k_gs_box_vec<float> finest level" if box else "k_gs_vec<float> finest level",
                        "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": ach / HBM_PEAK_GBS,
                        "traffic": None if box else measured_traffic(inst.n), "avg_us": ms * 1e3, "bytes_per_launch": by,
-                       "warm_avg_us": wms * 1e3, "warm_GBs": by / (wms * 1e-3) / 1e9}
+                       "warm_avg_us": wms * 1e3, "warm_GBs": by / (wms * 1e-3) / 1e9,
+                       "stream_probe": {"avg_us": pms * 1e3, "GBs": pby / (pms * 1e-3) / 1e9,
+                                        "frac": pby / (pms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                        "sweep_over_probe": (by / ms) / (pby / pms)}}
     kern = {}
     for k in ("stencil", "restrict", "prolong", "vcycle"):
         kms, kby = S.time_kernel(k, max(10, args.kernel_reps // 4))

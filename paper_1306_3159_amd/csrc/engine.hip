@@ -3339,7 +3339,7 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
     if (!H || !avg_ms || !bytes || reps <= 0) return g_last_error = "bad argument", BLOB_RD_EINVAL;
     const bool cold = (kernel & BLOB_RD_KERNEL_COLD) != 0;
     kernel &= ~BLOB_RD_KERNEL_COLD;
-    if (kernel < 0 || kernel > 4) return g_last_error = "unknown kernel id", BLOB_RD_EINVAL;
+    if (kernel < 0 || kernel > 5) return g_last_error = "unknown kernel id", BLOB_RD_EINVAL;
     return guarded(H, nullptr, [&]() {
         const Plan& P = H->P;
         const LevelDims& d = P.lev[0];
@@ -3365,7 +3365,12 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
             const bool f32 = P.esz == 4;
             const LevelDims& c = P.lev[1];
             const int cnat = P.nlev == 2;
+            const size_t half_bytes = (size_t)d.hx * d.ny * d.nz * P.esz;
             switch (kernel) {
+                case BLOB_RD_KERNEL_STREAM:
+                    launch_stream_add(H->st, H->at<char>(P.off_lvl[0][0]), H->at<char>(P.off_lvl[0][3]),
+                                      H->at<char>(P.off_lvl[0][1]), half_bytes);
+                    break;
                 case BLOB_RD_KERNEL_GS:
                     if (f32) gs_any(H->at<float>(P.off_lvl[0][1]), H->at<float>(P.off_lvl[0][0]),
                                     H->at<float>(P.off_lvl[0][3]));
@@ -3442,12 +3447,14 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
             }
         };
         float ms = 0.f;
-        if (cold && (kernel == BLOB_RD_KERNEL_GS || kernel == BLOB_RD_KERNEL_STENCIL)) {
+        if (cold && (kernel == BLOB_RD_KERNEL_GS || kernel == BLOB_RD_KERNEL_STENCIL ||
+                     kernel == BLOB_RD_KERNEL_STREAM)) {
             // Back-to-back launches rotating over independent buffer sets carved
             // from the eight FP64 grid vectors (> 256 MB in all), so no launch
             // finds its data in the last-level cache; event overhead is spread
             // over all the launches.
-            const bool gs = kernel == BLOB_RD_KERNEL_GS;
+            const bool gs = kernel != BLOB_RD_KERNEL_STENCIL;
+            const bool stream = kernel == BLOB_RD_KERNEL_STREAM;
             const size_t abytes = gs ? (size_t)d.hx * d.ny * d.nz * P.esz : P.ncell * 8;
             const size_t per_grid = (P.ncell * 8) / abytes;
             std::vector<char*> arr;
@@ -3459,7 +3466,9 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
             const int nset = (int)(arr.size() / per_set);
             auto launch_set = [&](int k) {
                 char** a = &arr[(size_t)k * per_set];
-                if (!gs) {
+                if (stream) {
+                    launch_stream_add(H->st, a[1], a[2], a[0], abytes);
+                } else if (!gs) {
                     unsigned npp = 0;
                     launch_applyA2(H->st, (const double*)a[0], (double*)a[1], alpha, s, d.nx, d.ny, d.nz, H->part(),
                                    nullptr, &npp, box);
@@ -3505,6 +3514,7 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
         const double n = (double)P.ncell, e = (double)P.esz;
         switch (kernel) {
             case BLOB_RD_KERNEL_GS: *bytes = n * 0.5 * e * 3; break;              // other colour, f, own colour
+            case BLOB_RD_KERNEL_STREAM: *bytes = n * 0.5 * e * 3; break;          // a, b in, out
             case BLOB_RD_KERNEL_STENCIL: *bytes = n * 16; break;                 // read x, write y (FP64)
             case BLOB_RD_KERNEL_RESTRICT: *bytes = n * e * 2.5 + n / 8 * e * 1.5; break;  // red u, black u, red f; red r write+read; coarse f, u
             case BLOB_RD_KERNEL_PROLONG: *bytes = n * e + n / 8 * e; break;  // red u read+write, coarse read

@@ -518,6 +518,22 @@ void launch_norm_partials(hipStream_t st, const double* v, size_t n, double* par
     *np = nb;
 }
 
+// Measurement probe: out = a + b over n16 16-byte vectors, the launch shape of the vector
+// half-sweep (one vector per thread, XCD-mapped blocks): the bandwidth a plain streaming
+// launch of the sweep's size reaches, the ceiling its roofline fraction is read against.
+__global__ void __launch_bounds__(kBlock) k_stream_add(const float4* __restrict__ a, const float4* __restrict__ b,
+                                                       float4* __restrict__ out, unsigned n16) {
+    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= n16) return;
+    const float4 x = a[idx], y = b[idx];
+    out[idx] = make_float4(x.x + y.x, x.y + y.y, x.z + y.z, x.w + y.w);
+}
+void launch_stream_add(hipStream_t st, const void* a, const void* b, void* out, size_t bytes) {
+    const unsigned n16 = (unsigned)(bytes / 16);
+    hipLaunchKernelGGL(k_stream_add, dim3(nblocks(n16)), dim3(kBlock), 0, st, (const float4*)a, (const float4*)b,
+                       (float4*)out, n16);
+}
+
 __global__ void k_fill(double* v, unsigned n, double value) {
     const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < n) v[idx] = value;

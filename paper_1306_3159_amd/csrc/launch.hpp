@@ -177,6 +177,8 @@ void launchb_mg(hipStream_t st, int what, const InstDev* inst, const int* gate, 
                 int l, int color, unsigned lds);
 template <typename T>
 hipError_t tail_set_lds_batched(size_t bytes);
+// measurement probe: out = a + b over `bytes` bytes of 16-byte vectors
+void launch_stream_add(hipStream_t st, const void* a, const void* b, void* out, size_t bytes);
 // blob term: interp (spread = 0) or spread (1)
 void launchb_blob(hipStream_t st, int spread, const InstDev* inst, const int* gate, const BatchTab* tab,
                   unsigned grid);

@@ -167,3 +167,29 @@ def test_fgmres_exact_preconditioner_converges_in_one_iteration():
     assert info["iters"] == 1
     ce, le = ex.solve_absorbing(f, q, 0.2)
     assert np.linalg.norm(c - ce) / np.linalg.norm(ce) < 1e-10
+
+
+def test_outer_iterations_set_by_the_concentration_cycles():
+    """The approximate-Schur preconditioner (appendix on preconditioning; eq. approx_Schur) with
+    one V-cycle per approximate Poisson solve: at the 256^3 / 10^4 blob density (20 blobs in
+    32^3), m = 5 inner GMRES iterations already solve the one-cycle Schur system as well as m = N
+    does, and right-preconditioning them by the exact inverse Schur complement (the best any
+    learned W can be) leaves the outer FGMRES count unchanged; only more concentration cycles
+    (n = 2) lower it. This bounds what a better W can gain in the block solver."""
+    rng = np.random.default_rng(100)
+    n, N = 32, 20
+    q = W.rsa_positions(rng, n, N, 3.0)
+    f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
+    cyc = lambda r: it.vcycle(r, 0.0)
+    G = ex.schur_matrix(q, (n, n, n), 0.0)
+    P = np.eye(N) - 1.0 / N
+    Minv = np.linalg.pinv(P @ G @ P)
+    its = {}
+    for name, kw in (("m5", dict(kind="schur", m=5)), ("mN", dict(kind="schur", m=N)),
+                     ("exactW", dict(kind="learned", m=5, w_apply=lambda v: P @ (Minv @ (P @ v)))),
+                     ("n2", dict(kind="schur", m=5, n=2))):
+        c, lam, info = fg.solve(f, q, 0.0, cycle=cyc, **kw)
+        assert ex.absorbing_residual(c, lam, f, q, 0.0) <= 1e-8
+        its[name] = info["iters"]
+    assert its["m5"] == its["mN"] == its["exactW"], its
+    assert its["n2"] < its["m5"], its
