@@ -389,6 +389,11 @@ def main():
     for k in ("stencil", "restrict", "prolong", "vcycle"):
         kms, kby = S.time_kernel(k, max(10, args.kernel_reps // 4))
         kern[k] = {"avg_us": kms * 1e3, "alg_GBs": kby / (kms * 1e-3) / 1e9, "bytes": kby}
+    # the FP64 stencil of the Krylov vectors, cold (rotating buffer sets larger than the
+    # Infinity Cache): its HBM bandwidth as a fraction of the peak
+    kms, kby = S.time_kernel("stencil", args.kernel_reps, cold=True)
+    kern["stencil"].update({"cold_avg_us": kms * 1e3, "cold_GBs": kby / (kms * 1e-3) / 1e9,
+                            "cold_frac": kby / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS})
     out["kernels"] = kern
     S.close()
     if net is not None:
