@@ -394,6 +394,12 @@ def main():
     kms, kby = S.time_kernel("stencil", args.kernel_reps, cold=True)
     kern["stencil"].update({"cold_avg_us": kms * 1e3, "cold_GBs": kby / (kms * 1e-3) / 1e9,
                             "cold_frac": kby / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS})
+    # the same stencil without the CG dots, the form the block solver applies
+    wms, wby = S.time_kernel("stencil_plain", max(10, args.kernel_reps // 4))
+    kms, kby = S.time_kernel("stencil_plain", args.kernel_reps, cold=True)
+    kern["stencil_plain"] = {"avg_us": wms * 1e3, "alg_GBs": wby / (wms * 1e-3) / 1e9, "bytes": wby,
+                             "cold_avg_us": kms * 1e3, "cold_GBs": kby / (kms * 1e-3) / 1e9,
+                             "cold_frac": kby / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     out["kernels"] = kern
     S.close()
     if net is not None:

@@ -474,6 +474,7 @@ int blob_rd_solve_batch(blob_rd_batch_t b, const double* const* f, double* const
 #define BLOB_RD_KERNEL_RESTRICT 2  /* finest residual + full-weighting restriction */
 #define BLOB_RD_KERNEL_PROLONG 3   /* trilinear prolongation + correction onto the finest level */
 #define BLOB_RD_KERNEL_VCYCLE 4    /* one whole V-cycle (all levels) */
+#define BLOB_RD_KERNEL_STENCIL_PLAIN 6 /* FP64 operator apply without the CG dots, the block solver's form */
 #define BLOB_RD_KERNEL_STREAM 5    /* probe: out = a + b over three arrays of the finest half-level's size in the
                                       V-cycle precision, in the half-sweep's launch shape: the streaming ceiling of
                                       a launch that moves the half-sweep's bytes */

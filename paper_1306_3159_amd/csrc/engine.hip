@@ -3339,7 +3339,7 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
     if (!H || !avg_ms || !bytes || reps <= 0) return g_last_error = "bad argument", BLOB_RD_EINVAL;
     const bool cold = (kernel & BLOB_RD_KERNEL_COLD) != 0;
     kernel &= ~BLOB_RD_KERNEL_COLD;
-    if (kernel < 0 || kernel > 5) return g_last_error = "unknown kernel id", BLOB_RD_EINVAL;
+    if (kernel < 0 || kernel > 6) return g_last_error = "unknown kernel id", BLOB_RD_EINVAL;
     return guarded(H, nullptr, [&]() {
         const Plan& P = H->P;
         const LevelDims& d = P.lev[0];
@@ -3383,6 +3383,9 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
                                    &npp, box);
                     break;
                 }
+                case BLOB_RD_KERNEL_STENCIL_PLAIN:
+                    launch_applyA_plain(H->st, H->grid(G_P), H->grid(G_Q), alpha, s, d.nx, d.ny, d.nz, box);
+                    break;
                 case BLOB_RD_KERNEL_RESTRICT:
                     if (box && f32) {
                         launch_resid_red_box<float>(H->st, H->at<float>(P.off_lvl[0][0]),
@@ -3448,12 +3451,13 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
         };
         float ms = 0.f;
         if (cold && (kernel == BLOB_RD_KERNEL_GS || kernel == BLOB_RD_KERNEL_STENCIL ||
-                     kernel == BLOB_RD_KERNEL_STREAM)) {
+                     kernel == BLOB_RD_KERNEL_STREAM || kernel == BLOB_RD_KERNEL_STENCIL_PLAIN)) {
             // Back-to-back launches rotating over independent buffer sets carved
             // from the eight FP64 grid vectors (> 256 MB in all), so no launch
             // finds its data in the last-level cache; event overhead is spread
             // over all the launches.
-            const bool gs = kernel != BLOB_RD_KERNEL_STENCIL;
+            const bool gs = kernel != BLOB_RD_KERNEL_STENCIL && kernel != BLOB_RD_KERNEL_STENCIL_PLAIN;
+            const bool plain = kernel == BLOB_RD_KERNEL_STENCIL_PLAIN;
             const bool stream = kernel == BLOB_RD_KERNEL_STREAM;
             const size_t abytes = gs ? (size_t)d.hx * d.ny * d.nz * P.esz : P.ncell * 8;
             const size_t per_grid = (P.ncell * 8) / abytes;
@@ -3468,6 +3472,8 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
                 char** a = &arr[(size_t)k * per_set];
                 if (stream) {
                     launch_stream_add(H->st, a[1], a[2], a[0], abytes);
+                } else if (plain) {
+                    launch_applyA_plain(H->st, (const double*)a[0], (double*)a[1], alpha, s, d.nx, d.ny, d.nz, box);
                 } else if (!gs) {
                     unsigned npp = 0;
                     launch_applyA2(H->st, (const double*)a[0], (double*)a[1], alpha, s, d.nx, d.ny, d.nz, H->part(),
@@ -3516,6 +3522,7 @@ int blob_rd_time_kernel(blob_rd_t H, int kernel, int reps, double* avg_ms, doubl
             case BLOB_RD_KERNEL_GS: *bytes = n * 0.5 * e * 3; break;              // other colour, f, own colour
             case BLOB_RD_KERNEL_STREAM: *bytes = n * 0.5 * e * 3; break;          // a, b in, out
             case BLOB_RD_KERNEL_STENCIL: *bytes = n * 16; break;                 // read x, write y (FP64)
+            case BLOB_RD_KERNEL_STENCIL_PLAIN: *bytes = n * 16; break;
             case BLOB_RD_KERNEL_RESTRICT: *bytes = n * e * 2.5 + n / 8 * e * 1.5; break;  // red u, black u, red f; red r write+read; coarse f, u
             case BLOB_RD_KERNEL_PROLONG: *bytes = n * e + n / 8 * e; break;  // red u read+write, coarse read
             default: {

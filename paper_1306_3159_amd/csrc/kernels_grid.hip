@@ -6,6 +6,7 @@
 #include "launch.hpp"
 
 #include <cmath>
+#include <cstdlib>
 
 namespace brd {
 
@@ -79,40 +80,58 @@ __device__ __forceinline__ void applyA2_body(const double* __restrict__ p, doubl
     double v[2] = {0.0, 0.0};
     const int hx = nx >> 1;
     const long long sxy = (long long)nx * ny;
-    for (unsigned k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-        const int X = 2 * (int)(k % hx);
-        const unsigned t = k / hx;
-        const int Y = t % ny, Z = t / ny;
-        const long long i = ((long long)Z * ny + Y) * nx + X;
-        const double2_t c = *reinterpret_cast<const double2_t*>(p + i);
-        double xl, xr;
-        double2_t ym, yp, zm, zp;
-        if (BOX) {
-            xl = X > 0 ? p[i - 1] : -c[0];
-            xr = X + 2 < nx ? p[i + 2] : -c[1];
-            ym = Y > 0 ? *reinterpret_cast<const double2_t*>(p + i - nx) : -c;
-            yp = Y + 1 < ny ? *reinterpret_cast<const double2_t*>(p + i + nx) : -c;
-            zm = Z > 0 ? *reinterpret_cast<const double2_t*>(p + i - sxy) : -c;
-            zp = Z + 1 < nz ? *reinterpret_cast<const double2_t*>(p + i + sxy) : -c;
-        } else {
-            xl = p[i - X + (X == 0 ? nx - 1 : X - 1)];
-            xr = p[i - X + (X + 2 == nx ? 0 : X + 2)];
-            ym = *reinterpret_cast<const double2_t*>(p + i + (long long)(wrapi(Y - 1, ny) - Y) * nx);
-            yp = *reinterpret_cast<const double2_t*>(p + i + (long long)(wrapi(Y + 1, ny) - Y) * nx);
-            zm = *reinterpret_cast<const double2_t*>(p + i + (long long)(wrapi(Z - 1, nz) - Z) * sxy);
-            zp = *reinterpret_cast<const double2_t*>(p + i + (long long)(wrapi(Z + 1, nz) - Z) * sxy);
+    // kU pairs per pass: every load of the pass is issued before any of its pairs is
+    // computed (a chunk of several pairs per thread then keeps kU x 7 loads in flight);
+    // pairs are computed and summed in the chunk's order, as one at a time would be
+    constexpr int kU = 4;
+    const unsigned bd = blockDim.x;
+    for (unsigned k0 = lo + threadIdx.x; k0 < hi; k0 += kU * bd) {
+        long long i[kU];
+        int X[kU];
+        double2_t c[kU], ym[kU], yp[kU], zm[kU], zp[kU], b[kU];
+        double xl[kU], xr[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const unsigned k = k0 + u * bd;
+            if (k >= hi) continue;
+            X[u] = 2 * (int)(k % hx);
+            const unsigned t = k / hx;
+            const int Y = t % ny, Z = t / ny;
+            i[u] = ((long long)Z * ny + Y) * nx + X[u];
+            c[u] = *reinterpret_cast<const double2_t*>(p + i[u]);
+            if (BOX) {
+                xl[u] = X[u] > 0 ? p[i[u] - 1] : -c[u][0];
+                xr[u] = X[u] + 2 < nx ? p[i[u] + 2] : -c[u][1];
+                ym[u] = Y > 0 ? *reinterpret_cast<const double2_t*>(p + i[u] - nx) : -c[u];
+                yp[u] = Y + 1 < ny ? *reinterpret_cast<const double2_t*>(p + i[u] + nx) : -c[u];
+                zm[u] = Z > 0 ? *reinterpret_cast<const double2_t*>(p + i[u] - sxy) : -c[u];
+                zp[u] = Z + 1 < nz ? *reinterpret_cast<const double2_t*>(p + i[u] + sxy) : -c[u];
+            } else {
+                xl[u] = p[i[u] - X[u] + (X[u] == 0 ? nx - 1 : X[u] - 1)];
+                xr[u] = p[i[u] - X[u] + (X[u] + 2 == nx ? 0 : X[u] + 2)];
+                ym[u] = *reinterpret_cast<const double2_t*>(p + i[u] + (long long)(wrapi(Y - 1, ny) - Y) * nx);
+                yp[u] = *reinterpret_cast<const double2_t*>(p + i[u] + (long long)(wrapi(Y + 1, ny) - Y) * nx);
+                zm[u] = *reinterpret_cast<const double2_t*>(p + i[u] + (long long)(wrapi(Z - 1, nz) - Z) * sxy);
+                zp[u] = *reinterpret_cast<const double2_t*>(p + i[u] + (long long)(wrapi(Z + 1, nz) - Z) * sxy);
+            }
+            if (base) b[u] = *reinterpret_cast<const double2_t*>(base + i[u]);
         }
-        double2_t y;
-        y[0] = alpha * c[0] - s * ((xl + c[1]) + (ym[0] + yp[0]) + (zm[0] + zp[0]) - 6.0 * c[0]);
-        y[1] = alpha * c[1] - s * ((c[0] + xr) + (ym[1] + yp[1]) + (zm[1] + zp[1]) - 6.0 * c[1]);
-        if (base) {  // residual form q = base - A p
-            const double2_t b = *reinterpret_cast<const double2_t*>(base + i);
-            y[0] = b[0] - y[0];
-            y[1] = b[1] - y[1];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (k0 + u * bd >= hi) continue;
+            double2_t y;
+            y[0] = alpha * c[u][0] - s * ((xl[u] + c[u][1]) + (ym[u][0] + yp[u][0]) + (zm[u][0] + zp[u][0]) -
+                                          6.0 * c[u][0]);
+            y[1] = alpha * c[u][1] - s * ((c[u][0] + xr[u]) + (ym[u][1] + yp[u][1]) + (zm[u][1] + zp[u][1]) -
+                                          6.0 * c[u][1]);
+            if (base) {  // residual form q = base - A p
+                y[0] = b[u][0] - y[0];
+                y[1] = b[u][1] - y[1];
+            }
+            *reinterpret_cast<double2_t*>(q + i[u]) = y;
+            v[0] += c[u][0] * y[0] + c[u][1] * y[1];
+            v[1] += y[0] + y[1];
         }
-        *reinterpret_cast<double2_t*>(q + i) = y;
-        v[0] += c[0] * y[0] + c[1] * y[1];
-        v[1] += y[0] + y[1];
     }
     if (part) block_partials<2>(v, part, blk.nb, blk.b);
 }
@@ -349,13 +368,25 @@ template void launch_zdots2<float>(hipStream_t, const float*, const float*, cons
 template void launch_zdots2<double>(hipStream_t, const double*, const double*, const double*, const double*, int,
                                     int, int, double*, const Scalars*, unsigned*);
 
+// pairs of cells per thread of the plain stencil launches (BLOB_RD_STENCIL_PAIRS, default 2:
+// at 256^3 38 us warm and 71 us cold against 50 and 77 with one pair per thread)
+unsigned stencil_pairs() {
+    static const unsigned v = [] {
+        const char* e = std::getenv("BLOB_RD_STENCIL_PAIRS");
+        const int k = e ? std::atoi(e) : 2;
+        return (unsigned)(k >= 1 && k <= 16 ? k : 2);
+    }();
+    return v;
+}
+
 void launch_applyA_plain(hipStream_t st, const double* x, double* y, double alpha, double s, int nx, int ny,
                          int nz, bool box) {
     const unsigned n = (unsigned)nx * ny * nz;
     if (nx % 2 == 0) {  // two cells per thread, the same arithmetic
         const unsigned npair = n / 2;
-        hipLaunchKernelGGL(box ? k_applyA2<true> : k_applyA2<false>, dim3(nblocks(npair)), dim3(kBlock), 0, st, x, y,
-                           alpha, s, nx, ny, nz, npair, (double*)nullptr, (const Scalars*)nullptr);
+        hipLaunchKernelGGL(box ? k_applyA2<true> : k_applyA2<false>, dim3(nblocks(npair, kBlock * stencil_pairs())),
+                           dim3(kBlock), 0, st, x, y, alpha, s, nx, ny, nz, npair, (double*)nullptr,
+                           (const Scalars*)nullptr);
         return;
     }
     hipLaunchKernelGGL(box ? k_applyA<true> : k_applyA<false>, dim3(nblocks(n)), dim3(kBlock), 0, st, x, y, alpha,
@@ -367,8 +398,8 @@ void launch_residA_plain(hipStream_t st, const double* base, const double* x, do
     const unsigned n = (unsigned)nx * ny * nz;
     if (nx % 2 == 0) {
         const unsigned npair = n / 2;
-        hipLaunchKernelGGL(box ? k_residA2<true> : k_residA2<false>, dim3(nblocks(npair)), dim3(kBlock), 0, st, base,
-                           x, q, alpha, s, nx, ny, nz, npair);
+        hipLaunchKernelGGL(box ? k_residA2<true> : k_residA2<false>, dim3(nblocks(npair, kBlock * stencil_pairs())),
+                           dim3(kBlock), 0, st, base, x, q, alpha, s, nx, ny, nz, npair);
         return;
     }
     launch_applyA_plain(st, x, q, alpha, s, nx, ny, nz, box);

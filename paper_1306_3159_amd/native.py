@@ -469,7 +469,7 @@ class BlobRD:
         return z
 
     # -- measurement ------------------------------------------------------------
-    KERNELS = {"gs": 0, "stencil": 1, "restrict": 2, "prolong": 3, "vcycle": 4, "stream": 5}
+    KERNELS = {"gs": 0, "stencil": 1, "restrict": 2, "prolong": 3, "vcycle": 4, "stream": 5, "stencil_plain": 6}
 
     def time_kernel(self, kernel: str, reps: int = 50, cold: bool = False) -> Tuple[float, float]:
         """Mean ms per launch (HIP events on this handle's stream) and algorithmic bytes per launch.
