@@ -383,6 +383,48 @@ typedef struct {
  * positive, bad batch, a handle without its own network), ENOMEM, EDEVICE. */
 int blob_rd_precond_train_step(blob_rd_t h, const void* batch_desc, float lr, float* loss);
 
+/* ---- Fourier coarse level of the Schur preconditioner ----
+ *
+ * The diagonal of eq. Schur_diagonal (Sec. III.E) and the learned W are local;
+ * the long-wave modes of M = J (alpha I - D L)^+ S, whose eigenvalues grow
+ * like (N/V)/(alpha + D |k|^2), are left to GMRES. The coarse level adds the
+ * span of the lowest Fourier modes of the blob set,
+ *   Z = [cos(k.q_i) - mean, sin(k.q_i) - mean],  k = 2 pi (m_x/L_x, m_y/L_y, m_z/L_z),
+ * over the integer wave vectors 0 < |m|^2 <= m2max (one of each +-m pair;
+ * m2max = 1, 2, 3, 6, 12 give K = 6, 18, 26, 80, 178 columns), and the Schur
+ * GMRES of blob_rd_solve_absorbing and blob_rd_step_absorbing then applies
+ * the balancing two-level preconditioner (Mandel 1993)
+ *   B = Q + (I - Q M) W (I - M Q),   Q = Z E^{-1} Z^T,  E = Z^T M Z,
+ * with W = P W_learned P when the handle uses the learned preconditioner at
+ * alpha = 0 and otherwise the diagonal 4 pi a0 D I of eq. Schur_diagonal (a0 as
+ * in blob_rd_saddle_opts.diag; P (4 pi a0 D) P at alpha = 0). B solves the coarse
+ * modes exactly and keeps residuals orthogonal to them. This extends the
+ * paper's Schur preconditioner; the paper has no coarse level.
+ *
+ * Building costs K Schur products (inner multigrid-CG solves to inner_rtol)
+ * and holds for the alpha given: solves at another alpha ignore it. The
+ * block solver (blob_rd_solve_absorbing_fgmres) never uses it. */
+#define BLOB_RD_COARSE_MAX_COLS 256
+
+/* Device bytes blob_rd_coarse_build needs for m2max (about 16 K N bytes); 0 on
+ * a bad argument (null handle, no blobs, m2max < 1). */
+size_t blob_rd_coarse_bytes(blob_rd_t h, int32_t m2max);
+/* Build the coarse level for alpha into caller-owned device memory buf (at
+ * least blob_rd_coarse_bytes; it must stay valid until blob_rd_coarse_clear,
+ * a rebuild or blob_rd_destroy). inner_rtol = 0 means 1e-6. *ncols (host, may
+ * be NULL) receives K. Synchronises the handle's stream. Errors: EINVAL (null
+ * pointer, no blobs, a box handle, a handle in a batch, alpha < 0, inner_rtol
+ * outside (0, 1), m2max < 1, K > BLOB_RD_COARSE_MAX_COLS, K above N - 1 at
+ * alpha = 0 or N otherwise), ENOMEM (buffer too small), ENUMERIC (E not
+ * positive definite: the level stays unbuilt), EDEVICE. */
+int blob_rd_coarse_build(blob_rd_t h, double alpha, int32_t m2max, double inner_rtol, void* buf, size_t bytes,
+                         int32_t* ncols);
+/* Drop the coarse level (the buffer is the caller's again). */
+int blob_rd_coarse_clear(blob_rd_t h);
+/* z = B r with the built coarse level (N-vectors, device, r != z), W as the solve
+ * at the level's alpha would use it. EINVAL if nothing is built. */
+int blob_rd_coarse_apply(blob_rd_t h, const double* r, double* z);
+
 /* Copy the CSR of W (rows ascending, columns ascending) to device buffers; any may be NULL. */
 int blob_rd_precond_csr(blob_rd_t h, int64_t* nnz, int32_t* rowptr, int32_t* col, double* val);
 /* Loss over S sample pairs (X, Y device [S][N], rows x_s and y_s) and its

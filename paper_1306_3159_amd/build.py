@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libblob_rd.so")
 
 SOURCES = ["kernels_grid.hip", "kernels_mg.hip", "kernels_box.hip", "kernels_blob.hip", "kernels_learned.hip",
-           "engine.hip"]
+           "kernels_coarse.hip", "engine.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

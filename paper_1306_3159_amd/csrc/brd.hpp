@@ -25,6 +25,7 @@ constexpr int kMaxTuneBlock = 512;  // largest work-group the autotuner may pick
 constexpr int kFinBlock = 1024;
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarse = 512;
+constexpr int kMaxCoarseCols = 256;  // columns of the Schur preconditioner's Fourier coarse level
 constexpr int kStageBlobs = 128;   // candidate blobs staged in LDS per pass of the spread planner
 
 // Device-resident scalars of one CG solve. Every kernel of an iteration reads

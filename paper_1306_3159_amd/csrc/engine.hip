@@ -419,6 +419,24 @@ struct blob_rd {
         PairGeom pg{};
     } lrn;
     int fallback = 0;
+    // Fourier coarse level of the Schur preconditioner (in a caller-owned buffer): the basis Z,
+    // M Z and E^{-1} = (Z^T M Z)^{-1} for the alpha it was built for, plus apply scratch
+    struct Coarse {
+        bool ready = false;
+        double alpha = 0.0;
+        int K = 0;
+        int* modes = nullptr;
+        double* Z = nullptr;
+        double* MZ = nullptr;
+        double* Einv = nullptr;
+        double* E = nullptr;
+        double* r2 = nullptr;
+        double* w = nullptr;
+        double* d = nullptr;
+        double* coef = nullptr;
+        double* a = nullptr;
+        double w0 = 0.0;  // scale of W without the learned part: 4 pi a0 D (eq. Schur_diagonal)
+    } crs;
     // network owned by the handle (handles created for the learned preconditioner): its state
     // and W live in the handle's workspace; own_w says W was built from it
     blob_rd_net* own_net = nullptr;
@@ -1063,6 +1081,160 @@ void schur_apply(blob_rd* H, double alpha, const double* x, double* y, double in
     if (singular(H, alpha)) launch_nvec_project(st, y, P.N);
 }
 
+// Reactive radius a0 / h of one blob, averaged over its position in the cell (Sec. IV.A),
+// for the four- and three-point kernels: the diagonal 4 pi a0 D of eq. Schur_diagonal.
+constexpr double kA0OverH = 1.255;
+constexpr double kA0OverH3 = 0.885;
+
+// ---- Fourier coarse level of the Schur preconditioner ----
+// Integer wave vectors m with 0 < |m|^2 <= m2max, one of each pair +-m (the one whose
+// first nonzero component is positive), 3 ints per vector.
+std::vector<int> coarse_modes(int m2max) {
+    std::vector<int> mv;
+    int r = 0;
+    while ((r + 1) * (r + 1) <= m2max) ++r;
+    for (int mx = -r; mx <= r; ++mx)
+        for (int my = -r; my <= r; ++my)
+            for (int mz = -r; mz <= r; ++mz) {
+                const int m2 = mx * mx + my * my + mz * mz;
+                if (m2 == 0 || m2 > m2max) continue;
+                const int first = mx != 0 ? mx : (my != 0 ? my : mz);
+                if (first > 0) {
+                    mv.push_back(mx);
+                    mv.push_back(my);
+                    mv.push_back(mz);
+                }
+            }
+    return mv;
+}
+
+// Buffer layout: modes | Z (K x N) | M Z (K x N) | E^{-1} (K x K) | E (K x K) | r2, w (N) |
+// d, coef, a (K). With buf == null only the size is computed.
+size_t coarse_layout(int N, int K, char* buf, blob_rd::Coarse* C) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = align_up(o + bytes);
+        return buf ? buf + r : nullptr;
+    };
+    char* modes = take((size_t)K / 2 * 3 * 4);
+    char* Z = take((size_t)K * N * 8);
+    char* MZ = take((size_t)K * N * 8);
+    char* Einv = take((size_t)K * K * 8);
+    char* E = take((size_t)K * K * 8);
+    char* r2 = take((size_t)N * 8);
+    char* w = take((size_t)N * 8);
+    char* d = take((size_t)K * 8);
+    char* coef = take((size_t)K * 8);
+    char* a = take((size_t)K * 8);
+    if (C) {
+        C->modes = reinterpret_cast<int*>(modes);
+        C->Z = reinterpret_cast<double*>(Z);
+        C->MZ = reinterpret_cast<double*>(MZ);
+        C->Einv = reinterpret_cast<double*>(Einv);
+        C->E = reinterpret_cast<double*>(E);
+        C->r2 = reinterpret_cast<double*>(r2);
+        C->w = reinterpret_cast<double*>(w);
+        C->d = reinterpret_cast<double*>(d);
+        C->coef = reinterpret_cast<double*>(coef);
+        C->a = reinterpret_cast<double*>(a);
+    }
+    return o;
+}
+
+// Inverse of a symmetric positive definite K x K matrix (row-major) by Cholesky;
+// false if a pivot is not positive and finite.
+bool spd_inverse(std::vector<double>& A, int K) {
+    std::vector<double> L((size_t)K * K, 0.0);
+    for (int j = 0; j < K; ++j) {
+        double dj = A[(size_t)j * K + j];
+        for (int k = 0; k < j; ++k) dj -= L[(size_t)j * K + k] * L[(size_t)j * K + k];
+        if (!(dj > 0.0) || !std::isfinite(dj)) return false;
+        const double ljj = std::sqrt(dj);
+        L[(size_t)j * K + j] = ljj;
+        for (int i = j + 1; i < K; ++i) {
+            double v = A[(size_t)i * K + j];
+            for (int k = 0; k < j; ++k) v -= L[(size_t)i * K + k] * L[(size_t)j * K + k];
+            L[(size_t)i * K + j] = v / ljj;
+        }
+    }
+    // columns of A^{-1}: L y = e_c, then L^T x = y
+    std::vector<double> y(K);
+    for (int c = 0; c < K; ++c) {
+        for (int i = 0; i < K; ++i) {
+            double v = i == c ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) v -= L[(size_t)i * K + k] * y[k];
+            y[i] = v / L[(size_t)i * K + i];
+        }
+        for (int i = K - 1; i >= 0; --i) {
+            double v = y[i];
+            for (int k = i + 1; k < K; ++k) v -= L[(size_t)k * K + i] * A[(size_t)k * K + c];
+            A[(size_t)i * K + c] = v / L[(size_t)i * K + i];
+        }
+    }
+    return true;
+}
+
+// Z (cos/sin of the wave vectors at the blobs, column means removed), M Z by K Schur
+// products with inner solves to inner_rtol, E = sym(Z^T M Z) and its inverse.
+template <typename T>
+void coarse_build(blob_rd* H, double alpha, const std::vector<int>& mv, double inner_rtol, char* buf) {
+    blob_rd::Coarse& C = H->crs;
+    C.ready = false;
+    const int N = H->P.N;
+    const int nm = (int)mv.size() / 3;
+    const int K = 2 * nm;
+    coarse_layout(N, K, buf, &C);
+    hipStream_t st = H->st;
+    HIPCHK(hipMemcpyAsync(C.modes, mv.data(), mv.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    const double two_pi = 6.283185307179586476925286766559;
+    const double h = H->prm.h;
+    launch_coarse_basis(st, H->at<double>(H->P.off_q), N, C.modes, nm, two_pi / (H->prm.nx * h),
+                        two_pi / (H->prm.ny * h), two_pi / (H->prm.nz * h), C.Z);
+    for (int j = 0; j < K; ++j) schur_apply<T>(H, alpha, C.Z + (size_t)j * N, C.MZ + (size_t)j * N, inner_rtol);
+    launch_coarse_gram(st, C.Z, C.MZ, N, K, C.E);
+    std::vector<double> E((size_t)K * K);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(E.data(), C.E, E.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < K; ++i)
+        for (int j = 0; j < i; ++j) {
+            const double v = 0.5 * (E[(size_t)i * K + j] + E[(size_t)j * K + i]);
+            E[(size_t)i * K + j] = v;
+            E[(size_t)j * K + i] = v;
+        }
+    if (!spd_inverse(E, K))
+        throw Err(BLOB_RD_ENUMERIC, "coarse matrix Z^T M Z is not positive definite (too many modes for the blobs?)");
+    HIPCHK(hipMemcpyAsync(C.Einv, E.data(), E.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    C.w0 = 4.0 * M_PI * (H->prm.kernel_w == 3 ? kA0OverH3 : kA0OverH) * h * H->prm.D;
+    C.alpha = alpha;
+    C.K = K;
+    C.ready = true;
+}
+
+// z = B r = Q r + (I - Q M) W (I - M Q) r with Q = Z E^{-1} Z^T (M symmetric, so
+// Z^T M w = (M Z)^T w). W is the learned P W P (use_w), else the paper's diagonal
+// 4 pi a0 D I (projected at alpha = 0): W must carry M^{-1}'s scale, as the coarse part
+// does. r and z must not alias.
+void coarse_apply(blob_rd* H, bool use_w, const double* r, double* z) {
+    blob_rd::Coarse& C = H->crs;
+    hipStream_t st = H->st;
+    const int N = H->P.N, K = C.K;
+    launch_coarse_dots(st, C.Z, N, K, r, C.d);                            // d = Z^T r
+    launch_coarse_coef(st, C.Einv, C.d, nullptr, K, -1.0, C.coef, C.a);   // a = E^{-1} d
+    launch_coarse_axpy(st, C.MZ, N, K, C.coef, r, C.r2);                  // r2 = r - M Z a
+    if (use_w) {
+        precond_apply(H, C.r2, C.w);
+    } else {
+        launch_nvec_copy_scale(st, C.r2, C.w, N, C.w0, 0.0);
+        if (singular(H, C.alpha)) launch_nvec_project(st, C.w, N);
+    }
+    launch_coarse_dots(st, C.MZ, N, K, C.w, C.d);                         // e = (M Z)^T w
+    launch_coarse_coef(st, C.Einv, C.d, C.a, K, -1.0, C.coef, nullptr);   // a - E^{-1} e
+    launch_coarse_axpy(st, C.Z, N, K, C.coef, C.w, z);                    // z = w + Z (a - E^{-1} e)
+}
+
 struct SaddleInfo {
     int gmres_iters = 0;
     double schur_res = 0.0;
@@ -1122,6 +1294,14 @@ SaddleInfo saddle_solve(blob_rd* H, double alpha, const double* g, const double*
         if (H->lrn.ready && !H->lrn.bad) use_w = true;
         else H->fallback = 1;
     }
+    // right preconditioner: the coarse level built for this alpha (around W or the
+    // diagonal), else W alone
+    const bool coarse_on = H->crs.ready && H->crs.alpha == alpha;
+    bool use_pre = use_w || coarse_on;
+    auto pre = [&](const double* r, double* z) {
+        if (coarse_on) coarse_apply(H, use_w, r, z);
+        else precond_apply(H, r, z);
+    };
     for (;;) {
         if (!first) schur_apply<T>(H, alpha, lt, w, inner_rtol);
         launch_gmres_start(st, b, w, first ? 0 : 1, V, H->at<double>(P.off_gv), N, H->gs());
@@ -1143,8 +1323,8 @@ SaddleInfo saddle_solve(blob_rd* H, double alpha, const double* g, const double*
             // and refinement of the caller guard the final answer.
             double tau = inner_rtol;
             if (H->relax && res_prev > 0.0) tau = std::min(1e-1, std::max(inner_rtol, atol_schur / res_prev));
-            if (use_w) {
-                precond_apply(H, V + (size_t)k * N, H->nv(9));
+            if (use_pre) {
+                pre(V + (size_t)k * N, H->nv(9));
                 schur_apply<T>(H, alpha, H->nv(9), V + (size_t)(k + 1) * N, tau);
             } else {
                 schur_apply<T>(H, alpha, V + (size_t)k * N, V + (size_t)(k + 1) * N, tau);
@@ -1160,15 +1340,15 @@ SaddleInfo saddle_solve(blob_rd* H, double alpha, const double* g, const double*
                 break;
             }
         }
-        if (use_w) {
-            // right preconditioning: lt += P W P (V y)
+        if (use_pre) {
+            // right preconditioning: lt += B (V y)
             launch_nvec_copy_scale(st, nullptr, H->nv(10), N, 0.0, 0.0);
             launch_gmres_update(st, V, Hm, H->at<double>(P.off_gv), H->at<double>(P.off_yv), H->nv(10), N, k, m);
-            precond_apply(H, H->nv(10), H->nv(9));
+            pre(H->nv(10), H->nv(9));
             launch_axpby(st, lt, H->nv(9), N, 1.0, 1.0);
-            // watchdog: a full cycle that did not cut the residual 10x drops the learned part
+            // watchdog: a full cycle that did not cut the residual 10x drops the preconditioner
             if (k == m && H->hgs->res > 0.1 * res_cycle0) {
-                use_w = false;
+                use_pre = false;
                 H->fallback = 1;
             }
         } else {
@@ -1329,8 +1509,6 @@ struct FgOpts {
 
 // reactive radius of a blob in units of h (Sec. IV.A): the position average of the
 // four-point kernel, and the three-point kernel's value at a node
-constexpr double kA0OverH = 1.255;
-constexpr double kA0OverH3 = 0.885;
 
 FgOpts fg_opts(const blob_rd* H, const blob_rd_saddle_opts* o) {
     FgOpts r;
@@ -3072,6 +3250,56 @@ int blob_rd_precond_apply(blob_rd_t H, const double* r, double* z) {
     if (!H->lrn.ready) return g_last_error = "learned preconditioner not built", BLOB_RD_EINVAL;
     return guarded(H, nullptr, [&]() {
         precond_apply(H, r, z);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(H->st));
+        return BLOB_RD_OK;
+    });
+}
+
+size_t blob_rd_coarse_bytes(blob_rd_t H, int32_t m2max) {
+    if (!H || H->P.N <= 0 || m2max < 1) return g_last_error = "bad argument", (size_t)0;
+    const int K = (int)coarse_modes(m2max).size() / 3 * 2;
+    return coarse_layout(H->P.N, K, nullptr, nullptr);
+}
+
+int blob_rd_coarse_build(blob_rd_t H, double alpha, int32_t m2max, double inner_rtol, void* buf, size_t bytes,
+                         int32_t* ncols) {
+    if (!H || !buf) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    if (H->P.N <= 0) return g_last_error = "no blobs", BLOB_RD_EINVAL;
+    if (H->box) return g_last_error = "the Fourier coarse level is for the periodic cell", BLOB_RD_EINVAL;
+    if (H->batch) return g_last_error = "the handle is in a batch", BLOB_RD_EINVAL;
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return g_last_error = "alpha must be finite and >= 0", BLOB_RD_EINVAL;
+    if (inner_rtol == 0.0) inner_rtol = 1e-6;
+    if (!(inner_rtol > 0.0 && inner_rtol < 1.0)) return g_last_error = "inner_rtol must be in (0, 1)", BLOB_RD_EINVAL;
+    if (m2max < 1) return g_last_error = "m2max must be >= 1", BLOB_RD_EINVAL;
+    const std::vector<int> mv = coarse_modes(m2max);
+    const int K = (int)mv.size() / 3 * 2;
+    if (K > kMaxCoarseCols)
+        return g_last_error = "more than " + std::to_string(kMaxCoarseCols) + " coarse columns", BLOB_RD_EINVAL;
+    if (K > H->P.N - (alpha == 0.0 ? 1 : 0))
+        return g_last_error = "more coarse columns than the blobs' mean-free dimension", BLOB_RD_EINVAL;
+    if (bytes < coarse_layout(H->P.N, K, nullptr, nullptr)) return g_last_error = "coarse buffer too small", BLOB_RD_ENOMEM;
+    return guarded(H, nullptr, [&]() {
+        if (H->P.esz == 4) coarse_build<float>(H, alpha, mv, inner_rtol, static_cast<char*>(buf));
+        else coarse_build<double>(H, alpha, mv, inner_rtol, static_cast<char*>(buf));
+        if (ncols) *ncols = K;
+        return BLOB_RD_OK;
+    });
+}
+
+int blob_rd_coarse_clear(blob_rd_t H) {
+    if (!H) return g_last_error = "null argument", BLOB_RD_EINVAL;
+    H->crs = blob_rd::Coarse{};
+    return BLOB_RD_OK;
+}
+
+int blob_rd_coarse_apply(blob_rd_t H, const double* r, double* z) {
+    if (!H || !r || !z || r == z) return g_last_error = "bad argument", BLOB_RD_EINVAL;
+    if (!H->crs.ready) return g_last_error = "coarse level not built", BLOB_RD_EINVAL;
+    const bool use_w = H->prm.schur_precond == BLOB_RD_PRECOND_LEARNED && H->crs.alpha == 0.0 && H->lrn.ready &&
+                       !H->lrn.bad;
+    return guarded(H, nullptr, [&]() {
+        coarse_apply(H, use_w, r, z);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(H->st));
         return BLOB_RD_OK;

@@ -184,6 +184,14 @@ def load_library(path: str = LIB_PATH):
                                         ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int64,
                                         ctypes.c_int32, vp, ctypes.c_size_t, vp, S]
     L.blob_rd_solve_batched.restype = i32
+    L.blob_rd_coarse_bytes.argtypes = [vp, ctypes.c_int32]
+    L.blob_rd_coarse_bytes.restype = ctypes.c_size_t
+    L.blob_rd_coarse_build.argtypes = [vp, d, ctypes.c_int32, d, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int32)]
+    L.blob_rd_coarse_build.restype = i32
+    L.blob_rd_coarse_clear.argtypes = [vp]
+    L.blob_rd_coarse_clear.restype = i32
+    L.blob_rd_coarse_apply.argtypes = [vp, vp, vp]
+    L.blob_rd_coarse_apply.restype = i32
     for name in ("blob_rd_net_create", "blob_rd_net_destroy", "blob_rd_net_set_params", "blob_rd_net_get_params",
                  "blob_rd_net_zero_grad", "blob_rd_net_get_grad", "blob_rd_net_adam_step", "blob_rd_precond_build",
                  "blob_rd_precond_apply", "blob_rd_precond_csr", "blob_rd_precond_loss_grad", "blob_rd_schur_apply"):
@@ -562,6 +570,30 @@ class BlobRD:
         self._check(self._lib.blob_rd_schur_apply(self._h, float(alpha), _ptr(x.contiguous()), _ptr(y),
                                                   float(inner_rtol)))
         return y
+
+    def coarse_build(self, alpha: float = 0.0, m2max: int = 3, inner_rtol: float = 1e-6) -> int:
+        """Build the Fourier coarse level of the Schur preconditioner for alpha (wave vectors
+        0 < |m|^2 <= m2max) in a buffer this object keeps; returns the number of columns K."""
+        nbytes = int(self._lib.blob_rd_coarse_bytes(self._h, int(m2max)))
+        if nbytes == 0:
+            raise BlobRDError(-1, self._lib.blob_rd_last_error(self._h).decode())
+        buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        k = ctypes.c_int32()
+        self._check(self._lib.blob_rd_coarse_build(self._h, float(alpha), int(m2max), float(inner_rtol), _ptr(buf),
+                                                   nbytes, ctypes.byref(k)))
+        self._coarse_buf = buf
+        return int(k.value)
+
+    def coarse_clear(self) -> None:
+        self._check(self._lib.blob_rd_coarse_clear(self._h))
+        self._coarse_buf = None
+
+    def coarse_apply(self, r: torch.Tensor) -> torch.Tensor:
+        """z = B r, the two-level Schur preconditioner of the built coarse level."""
+        self._nvec(r, "r")
+        z = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        self._check(self._lib.blob_rd_coarse_apply(self._h, _ptr(r), _ptr(z)))
+        return z
 
     def schur_apply_cycles(self, x: torch.Tensor, alpha: float = 0.0, cycles: int = 1) -> torch.Tensor:
         """y = P J A_n^{-1} S P x with n multigrid cycles (the approximate-Schur operator)."""

@@ -1,0 +1,231 @@
+"""GPU parity of the Schur preconditioner's Fourier coarse level against oracle/coarse.py."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import coarse as CO
+from oracle import exact as ex
+from oracle import learned as LN
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1306_3159_amd",
+                       "weights", "precond_rsa256.npy")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1306_3159_amd import native
+    native.load_library()
+    return torch.device("cuda:0")
+
+
+def T(a, dev, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=dev)
+
+
+def H(t):
+    return t.detach().cpu().numpy()
+
+
+def _rsa(shape, N, h, seed):
+    """RSA blobs in a (possibly non-cubic) periodic box: positions drawn in the cube of the
+    longest edge and kept if inside, 3 h apart (minimum image in the box)."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    L = np.array([nx, ny, nz], dtype=np.float64) * h
+    q = []
+    while len(q) < N:
+        p = rng.uniform(0.0, 1.0, 3) * L
+        if all(np.linalg.norm((p - o + 0.5 * L) % L - 0.5 * L) >= 3.0 * h for o in q):
+            q.append(p)
+    return np.array(q)
+
+
+@pytest.mark.parametrize("shape,h,N,alpha,m2max,precision", [
+    ((32, 32, 32), 1.0, 80, 0.0, 3, 0),
+    ((32, 32, 32), 1.0, 80, 0.37, 2, 0),
+    ((24, 32, 40), 0.7, 60, 0.0, 3, 0),          # ragged box, h != 1: k_x, k_y, k_z differ
+    ((32, 32, 32), 1.0, 120, 0.0, 6, 1),         # 80 columns, FP32 cycles inside the inner solves
+])
+def test_coarse_apply_matches_the_oracle(dev, shape, h, N, alpha, m2max, precision):
+    """B r with the diagonal W = 4 pi a0 D I of eq. Schur_diagonal (the handle has no
+    learned part; a0 = 1.255 h) against the oracle's dense balancing form on the exact Schur
+    matrix (FFT solves), element-wise."""
+    from paper_1306_3159_amd import BlobRD
+    _say("coarse apply", shape, h, N, alpha, m2max, precision)
+    q = _rsa(shape, N, h, seed=31 + N)
+    G = ex.schur_matrix(q, shape, alpha, h=h)
+    w0 = 4.0 * np.pi * 1.255 * h
+    if alpha == 0.0:
+        P = CO.projector(N)
+        M, Wm = P @ G @ P, w0 * P
+    else:
+        M, Wm = G, w0 * np.eye(N)
+    Z = CO.basis(q, shape, h, m2max)
+    B = CO.two_level(M, Z, Wm)
+    S = BlobRD(shape, T(q, dev), h=h, precision=precision)
+    K = S.coarse_build(alpha, m2max, inner_rtol=1e-12)
+    assert K == Z.shape[1]
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        r = rng.standard_normal(N)
+        if alpha == 0.0:
+            r -= r.mean()
+        z = H(S.coarse_apply(T(r, dev)))
+        ref = B @ r
+        assert np.abs(z - ref).max() <= 1e-8 * np.abs(ref).max(), np.abs(z - ref).max() / np.abs(ref).max()
+    S.close()
+
+
+def _learned_handle(dev, n, q, precision=1):
+    from paper_1306_3159_amd import BlobRD, Net, PRECOND_LEARNED
+    net = Net(dev)
+    net.set_params(torch.tensor(np.load(WEIGHTS), device=dev))
+    S = BlobRD(n, T(q, dev), precision=precision, schur_precond=PRECOND_LEARNED, rtol=1e-8)
+    S.precond_build(net)
+    return S, net
+
+
+def test_coarse_with_the_learned_w(dev):
+    """64^3 with 156 RSA blobs (the 256^3 / 10^4 density), the committed network: B solves the
+    coarse modes exactly (B M Z = Z) and leaves Z^T (M B r - r) = 0, with the GPU's own Schur
+    products; and B r agrees with the oracle's balancing form around the oracle's matrix-unit
+    model of W (whose entries match the GPU's to 1e-5 but for rare bf16 rounding flips)."""
+    _say("coarse with learned W")
+    n, N = 64, 156
+    q = W.rsa_positions(np.random.default_rng(41), n, N, 3.0)
+    S, net = _learned_handle(dev, n, q)
+    K = S.coarse_build(0.0, 3, inner_rtol=1e-12)
+    Z = CO.basis(q, (n, n, n), 1.0, 3)
+    assert K == Z.shape[1] == 26
+    for j in (0, 7, 25):
+        mz = S.schur_apply(T(Z[:, j], dev), 0.0, 1e-12)
+        bz = H(S.coarse_apply(mz))
+        assert np.abs(bz - Z[:, j]).max() <= 1e-7 * np.abs(Z[:, j]).max()
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(N)
+    r -= r.mean()
+    br = S.coarse_apply(T(r, dev))
+    mbr = H(S.schur_apply(br, 0.0, 1e-12))
+    assert np.abs(Z.T @ (mbr - r)).max() <= 1e-7 * np.linalg.norm(r) * np.sqrt(N)
+    # against the oracle (dense exact M, the matrix-unit model of the same bf16 weights)
+    G = ex.schur_matrix(q, (n, n, n), 0.0)
+    P = CO.projector(N)
+    p = LN.rounded(LN.unflatten(np.load(WEIGHTS)))
+    ptr, col, val, _ = LN.assemble(p, q, (n, n, n), mfma_operands=True)
+    Wd = np.zeros((N, N))
+    for i in range(N):
+        Wd[i, col[ptr[i]:ptr[i + 1]]] = val[ptr[i]:ptr[i + 1]]
+    B = CO.two_level(P @ G @ P, Z, P @ Wd @ P)
+    ref = B @ r
+    assert np.linalg.norm(H(br) - ref) <= 1e-3 * np.linalg.norm(ref)
+    S.close()
+    net.close()
+
+
+def test_schur_gmres_with_the_coarse_level(dev):
+    """Absorbing solves at 64^3 (156 blobs) through the Schur GMRES: with the learned W and
+    the coarse level (alpha = 0), and with the coarse level alone in a backward-Euler step
+    (alpha = 1/dt). Each answer meets the oracle's saddle residual and matches its exact solve. At this size the long waves
+    of M are not yet separated from the rest (N/V / |k_min|^2 = 0.06, about the local part of
+    M's diagonal), so the level may not save iterations here; it must not cost any. A level
+    built for another alpha is not used (the iterations equal those without it)."""
+    from paper_1306_3159_amd import BlobRD
+    _say("schur gmres + coarse")
+    n, N = 64, 156
+    rng = np.random.default_rng(43)
+    q = W.rsa_positions(rng, n, N, 3.0)
+    f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
+    ce, le = ex.solve_absorbing(f, q, 0.0)
+    S, net = _learned_handle(dev, n, q)
+    _, _, st0 = S.solve_absorbing(T(f, dev))
+    S.coarse_build(0.0, 3)
+    c, lam, st1 = S.solve_absorbing(T(f, dev))
+    print("alpha 0: W", st0["outer_iters"], "W + coarse", st1["outer_iters"], flush=True)
+    assert st1["rc"] == 0 and st1["fallback"] == 0, st1
+    assert ex.absorbing_residual(H(c), H(lam), f, q, 0.0) <= 1e-8
+    assert np.linalg.norm(H(lam) - le) <= 1e-6 * np.linalg.norm(le)
+    assert st1["outer_iters"] <= st0["outer_iters"]
+    S.close()
+    net.close()
+    dt = 2.0
+    c0 = np.abs(rng.standard_normal((n, n, n)))
+    ce1, le1 = ex.step_absorbing(c0, f, q, dt)
+    S = BlobRD(n, T(q, dev), precision=1, rtol=1e-8)
+    its = []
+    for build in (None, 1.0 / dt, 0.25):
+        if build is not None:
+            S.coarse_build(build, 3)
+        c = T(c0, dev)
+        lam = torch.zeros(N, dtype=torch.float64, device=dev)
+        st = S.step_absorbing(T(f, dev), c, lam, dt, warm=False)
+        assert st["rc"] == 0, st
+        assert ex.absorbing_residual(H(c), H(lam), f + c0 / dt, q, 1.0 / dt) <= 1e-8
+        assert np.abs(H(c) - ce1).max() <= 1e-6 * np.abs(ce1).max()
+        its.append(st["outer_iters"])
+    print("step alpha 1/dt: plain, coarse, coarse at another alpha", its, flush=True)
+    assert its[1] <= its[0] and its[2] == its[0]
+    S.close()
+
+
+def test_coarse_level_full_size(dev):
+    """256^3 with 10^4 RSA blobs, f = 1, the committed network, FP32 cycles: the Schur GMRES
+    with W and the 26-column coarse level meets the oracle's FP64 saddle residual 1e-8 with
+    sum(lam) = h^3 sum(f), and needs at most 0.8 x the iterations of W alone."""
+    _say("coarse full size")
+    inst = W.learned_eval(256, 10000, index=0)
+    S, net = _learned_handle(dev, inst.n, inst.q)
+    f = T(inst.f, dev)
+    _, _, st0 = S.solve_absorbing(f)
+    S.coarse_build(0.0, 3)
+    c, lam, st1 = S.solve_absorbing(f)
+    print("rsa256: W", st0, "W + coarse", st1, flush=True)
+    assert st1["rc"] == 0 and st1["fallback"] == 0, st1
+    c, lam = H(c), H(lam)
+    assert ex.absorbing_residual(c, lam, inst.f, inst.q, 0.0) <= 1e-8
+    assert lam.sum() == pytest.approx(inst.f.sum(), rel=1e-12)
+    assert st1["outer_iters"] <= 0.8 * st0["outer_iters"]
+    S.close()
+    net.close()
+
+
+def test_coarse_level_errors(dev):
+    """Argument checks: too many columns for the blobs, a box handle, a small buffer, apply
+    before a build or after a clear."""
+    from paper_1306_3159_amd import BlobRD, BlobRDError, BOUNDARY_DIRICHLET
+    from paper_1306_3159_amd.native import load_library, _ptr
+    _say("coarse errors")
+    L = load_library()
+    q = W.rsa_positions(np.random.default_rng(2), 32, 20, 3.0)
+    S = BlobRD(32, T(q, dev))
+    with pytest.raises(BlobRDError):
+        S.coarse_apply(T(np.zeros(20), dev))
+    with pytest.raises(BlobRDError):
+        S.coarse_build(0.0, 3)                # 26 columns > 19
+    assert S.coarse_build(0.0, 2) == 18       # 18 <= 19
+    nb = int(L.blob_rd_coarse_bytes(S._h, 2))
+    buf = torch.empty(nb - 8, dtype=torch.uint8, device=dev)
+    assert L.blob_rd_coarse_build(S._h, 0.0, 2, 0.0, _ptr(buf), nb - 8, None) == -2     # ENOMEM
+    assert int(L.blob_rd_coarse_bytes(S._h, 0)) == 0
+    S.coarse_clear()
+    with pytest.raises(BlobRDError):
+        S.coarse_apply(T(np.zeros(20), dev))
+    S.close()
+    qb = W.rsa_positions(np.random.default_rng(2), 26, 20, 3.0) + 3.0
+    B = BlobRD(32, T(qb, dev), boundary=BOUNDARY_DIRICHLET)
+    with pytest.raises(BlobRDError):
+        B.coarse_build(0.0, 1)
+    B.close()
