@@ -135,12 +135,21 @@ def block_iterations(shape, q: np.ndarray, f: torch.Tensor, net: Optional[Net], 
 
 
 def gmres_iterations(shape, q: np.ndarray, f: torch.Tensor, net: Optional[Net], device, rtol: float = 1e-8,
-                     precision: int = MIXED):
-    """Schur GMRES iterations and wall time of one absorbing solve, with or without W."""
+                     precision: int = MIXED, coarse_m2: int = 0, coarse_rtol: float = 1e-4):
+    """Schur GMRES iterations and wall time of one absorbing solve, with or without W, and with
+    the Fourier coarse level over 0 < |m|^2 <= coarse_m2 (0: none; its build time is returned
+    in the stats as coarse_build_seconds, outside the solve's time)."""
     S = BlobRD(shape, torch.tensor(q, device=device), precision=precision, rtol=rtol,
                schur_precond=PRECOND_LEARNED if net is not None else PRECOND_NONE)
     if net is not None:
         S.precond_build(net)
+    tb = 0.0
+    if coarse_m2 > 0:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.coarse_build(0.0, coarse_m2, coarse_rtol)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
     c, lam, st = S.solve_absorbing(f)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -148,4 +157,5 @@ def gmres_iterations(shape, q: np.ndarray, f: torch.Tensor, net: Optional[Net], 
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     S.close()
+    st["coarse_build_seconds"] = tb
     return st, dt, c, lam

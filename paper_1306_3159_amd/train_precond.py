@@ -42,7 +42,8 @@ def _positions(arg):
 
 def evaluate(net, spec_list: str, dev, W, LD, MIXED, FP64):
     """Held-out absorbing solves (f = 1) with and without the network: Schur GMRES (plain FP64,
-    FP32 cycles, learned) and the block FGMRES (diagonal, approximate Schur, learned inner)."""
+    FP32 cycles, learned, and both with the 80-column Fourier coarse level, |m|^2 <= 6) and the
+    block FGMRES (diagonal, approximate Schur, learned inner)."""
     import torch
     rows = []
     for spec in spec_list.split(","):
@@ -56,6 +57,8 @@ def evaluate(net, spec_list: str, dev, W, LD, MIXED, FP64):
             runs = (("plain_fp64", None, FP64, LD.gmres_iterations, {}),
                     ("mixed", None, MIXED, LD.gmres_iterations, {}),
                     ("learned_mixed", net, MIXED, LD.gmres_iterations, {}),
+                    ("coarse_mixed", None, MIXED, LD.gmres_iterations, {"coarse_m2": 6}),
+                    ("learned_coarse_mixed", net, MIXED, LD.gmres_iterations, {"coarse_m2": 6}),
                     ("block_diagonal_mixed", None, MIXED, LD.block_iterations, {"kind": "diagonal"}),
                     ("block_mixed", None, MIXED, LD.block_iterations, {}),
                     ("block_learned_mixed", net, MIXED, LD.block_iterations, {}))
@@ -64,6 +67,8 @@ def evaluate(net, spec_list: str, dev, W, LD, MIXED, FP64):
                 row[name] = {"iters": st["outer_iters"], "inner_iters": st["inner_iters_total"],
                              "vcycles": st["vcycles"], "seconds": dt, "rel_resid": st["rel_resid"], "rc": st["rc"],
                              "fallback": st["fallback"]}
+                if "coarse_m2" in kw:
+                    row[name]["coarse_build_seconds"] = st["coarse_build_seconds"]
                 log(f"eval n={n} N={N} seed={inst.seed} {name}: iters={st['outer_iters']} "
                     f"inner={st['inner_iters_total']} t={dt:.3f}s resid={st['rel_resid']:.2e}")
             rows.append(row)
@@ -80,6 +85,9 @@ def summarize(rows):
         sec = [r[name]["seconds"] for r in rows]
         out[name] = {"median_iters": float(np.median(its)), "median_seconds": float(np.median(sec)),
                      "max_rel_resid": max(r[name]["rel_resid"] for r in rows), "configs": len(rows)}
+        if "coarse_build_seconds" in rows[0][name]:
+            out[name]["median_coarse_build_seconds"] = float(np.median([r[name]["coarse_build_seconds"]
+                                                                        for r in rows]))
     return out
 
 
