@@ -391,7 +391,7 @@ int blob_rd_precond_train_step(blob_rd_t h, const void* batch_desc, float lr, fl
  * span of the lowest Fourier modes of the blob set,
  *   Z = [cos(k.q_i) - mean, sin(k.q_i) - mean],  k = 2 pi (m_x/L_x, m_y/L_y, m_z/L_z),
  * over the integer wave vectors 0 < |m|^2 <= m2max (one of each +-m pair;
- * m2max = 1, 2, 3, 6, 12 give K = 6, 18, 26, 80, 178 columns), and the Schur
+ * m2max = 1, 2, 3, 6, 12, 16 give K = 6, 18, 26, 80, 178, 256 columns), and the Schur
  * GMRES of blob_rd_solve_absorbing and blob_rd_step_absorbing then applies
  * the balancing two-level preconditioner (Mandel 1993)
  *   B = Q + (I - Q M) W (I - M Q),   Q = Z E^{-1} Z^T,  E = Z^T M Z,
@@ -407,14 +407,14 @@ int blob_rd_precond_train_step(blob_rd_t h, const void* batch_desc, float lr, fl
 #define BLOB_RD_COARSE_MAX_COLS 256
 
 /* Device bytes blob_rd_coarse_build needs for m2max (about 16 K N bytes); 0 on
- * a bad argument (null handle, no blobs, m2max < 1). */
+ * a bad argument (null handle, no blobs, m2max outside [1, 16]). */
 size_t blob_rd_coarse_bytes(blob_rd_t h, int32_t m2max);
 /* Build the coarse level for alpha into caller-owned device memory buf (at
  * least blob_rd_coarse_bytes; it must stay valid until blob_rd_coarse_clear,
  * a rebuild or blob_rd_destroy). inner_rtol = 0 means 1e-6. *ncols (host, may
  * be NULL) receives K. Synchronises the handle's stream. Errors: EINVAL (null
  * pointer, no blobs, a box handle, a handle in a batch, alpha < 0, inner_rtol
- * outside (0, 1), m2max < 1, K > BLOB_RD_COARSE_MAX_COLS, K above N - 1 at
+ * outside (0, 1), m2max outside [1, 16], K above N - 1 at
  * alpha = 0 or N otherwise), ENOMEM (buffer too small), ENUMERIC (E not
  * positive definite: the level stays unbuilt), EDEVICE. */
 int blob_rd_coarse_build(blob_rd_t h, double alpha, int32_t m2max, double inner_rtol, void* buf, size_t bytes,

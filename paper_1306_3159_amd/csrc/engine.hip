@@ -3257,7 +3257,9 @@ int blob_rd_precond_apply(blob_rd_t H, const double* r, double* z) {
 }
 
 size_t blob_rd_coarse_bytes(blob_rd_t H, int32_t m2max) {
-    if (!H || H->P.N <= 0 || m2max < 1) return g_last_error = "bad argument", (size_t)0;
+    // |m|^2 <= 16 gives 256 columns, the most the level takes; larger m2max are refused
+    // before the wave vectors are enumerated
+    if (!H || H->P.N <= 0 || m2max < 1 || m2max > 16) return g_last_error = "bad argument", (size_t)0;
     const int K = (int)coarse_modes(m2max).size() / 3 * 2;
     return coarse_layout(H->P.N, K, nullptr, nullptr);
 }
@@ -3271,7 +3273,7 @@ int blob_rd_coarse_build(blob_rd_t H, double alpha, int32_t m2max, double inner_
     if (!(alpha >= 0.0) || !std::isfinite(alpha)) return g_last_error = "alpha must be finite and >= 0", BLOB_RD_EINVAL;
     if (inner_rtol == 0.0) inner_rtol = 1e-6;
     if (!(inner_rtol > 0.0 && inner_rtol < 1.0)) return g_last_error = "inner_rtol must be in (0, 1)", BLOB_RD_EINVAL;
-    if (m2max < 1) return g_last_error = "m2max must be >= 1", BLOB_RD_EINVAL;
+    if (m2max < 1 || m2max > 16) return g_last_error = "m2max must be in [1, 16]", BLOB_RD_EINVAL;
     const std::vector<int> mv = coarse_modes(m2max);
     const int K = (int)mv.size() / 3 * 2;
     if (K > kMaxCoarseCols)

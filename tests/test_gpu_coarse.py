@@ -220,6 +220,8 @@ def test_coarse_level_errors(dev):
     buf = torch.empty(nb - 8, dtype=torch.uint8, device=dev)
     assert L.blob_rd_coarse_build(S._h, 0.0, 2, 0.0, _ptr(buf), nb - 8, None) == -2     # ENOMEM
     assert int(L.blob_rd_coarse_bytes(S._h, 0)) == 0
+    assert int(L.blob_rd_coarse_bytes(S._h, 17)) == 0     # more than 256 columns
+    assert int(L.blob_rd_coarse_bytes(S._h, 1 << 30)) == 0
     S.coarse_clear()
     with pytest.raises(BlobRDError):
         S.coarse_apply(T(np.zeros(20), dev))
