@@ -300,17 +300,18 @@ int blob_rd_saddle_precond(blob_rd_t h, double alpha, const blob_rd_saddle_opts*
  * 1.255 h, the averaged reactive radius of Sec. IV.A) and adds a symmetric
  * pairwise correction for blob pairs closer than r_c = 12 h:
  *   W_ij = D h [delta_ij 4 pi a0/h + (g(i,j) + g(j,i))/2],
- * g a 10 -> 64 -> 64 -> 1 SiLU network of pair features
- *   [d/r_c (3), |d|/r_c, frac(q_i/h - 1/2) (3), frac(q_j/h - 1/2) (3)]
- * (d the minimum-image separation), bfloat16 weights with float32
+ * g a 12 -> 64 -> 64 -> 1 SiLU network of pair features
+ *   [d/r_c (3), |d|/r_c, frac(q_i/h - 1/2) (3), frac(q_j/h - 1/2) (3), nu_i/4, nu_j/4]
+ * (d the minimum-image separation, nu_i the number of other blobs within
+ * r_c/2 of blob i: the pair's surroundings), bfloat16 weights with float32
  * accumulation. GMRES applies z = P W P r as a right preconditioner on
  * steady (alpha = 0) absorbing solves when schur_precond = LEARNED.
  * Training minimises (1/S) sum_s |P W y_s - x_s|^2/|x_s|^2 over sample pairs
  * (x_s, y_s = P M P x_s) from blob_rd_schur_apply, with Adam.
  *
  * Parameters are one float32 vector of BLOB_RD_NET_PARAMS values:
- * [W1 (64 x 10, row = output unit) | b1 (64) | W2 (64 x 64) | b2 (64) | w3 (64) | b3]. */
-#define BLOB_RD_NET_PARAMS 4929
+ * [W1 (64 x 12, row = output unit) | b1 (64) | W2 (64 x 64) | b2 (64) | w3 (64) | b3]. */
+#define BLOB_RD_NET_PARAMS 5057
 
 typedef struct blob_rd_net* blob_rd_net_t;
 
@@ -351,9 +352,9 @@ int blob_rd_precond_apply(blob_rd_t h, const double* r, double* z);
 #define BLOB_RD_LEARNED_ROW_CAP 256
 
 /* The network's inference weights as one host byte blob, little endian:
- * W1 bfloat16 [64][10] | b1 float32 [64] | W2 bfloat16 [64][64] | b2 float32 [64] |
- * w3 bfloat16 [64] | b3 float32, packed without padding (10116 bytes). */
-#define BLOB_RD_PRECOND_BLOB_BYTES 10116
+ * W1 bfloat16 [64][12] | b1 float32 [64] | W2 bfloat16 [64][64] | b2 float32 [64] |
+ * w3 bfloat16 [64] | b3 float32, packed without padding (10372 bytes). */
+#define BLOB_RD_PRECOND_BLOB_BYTES 10372
 
 /* Set the handle's network from a weight blob (host memory, bytes =
  * BLOB_RD_PRECOND_BLOB_BYTES; the weights become the float32 masters exactly),

@@ -14,8 +14,12 @@ network, symmetric by construction:
 with a0 = 1.255 h (the position-averaged reactive radius of Sec. IV.A),
 r_c = 12 h, minimum-image separations, and
 
-    x(i, j) = [d / r_c (3), |d| / r_c, frac(q_i/h - 1/2) (3), frac(q_j/h - 1/2) (3)]
-    g = w3 . silu(W2 silu(W1 x + b1) + b2) + b3,   widths 10 -> 64 -> 64 -> 1.
+    x(i, j) = [d / r_c (3), |d| / r_c, frac(q_i/h - 1/2) (3), frac(q_j/h - 1/2) (3),
+               nu_i / 4, nu_j / 4]
+    g = w3 . silu(W2 silu(W1 x + b1) + b2) + b3,   widths 12 -> 64 -> 64 -> 1,
+
+where nu_i counts the other blobs within r_c / 2 of blob i (minimum image): the
+pair's surroundings, which set how strongly its neighbours shield it.
 
 The weights W1, W2, w3 are used rounded to bfloat16 (round to nearest even);
 biases and all arithmetic here are float64. The preconditioner applied to a
@@ -47,7 +51,8 @@ import numpy as np
 
 RC = 12.0
 WIDTH = 64
-NFEAT = 10
+NFEAT = 12
+NU_SCALE = 0.25  # the neighbour counts enter as nu / 4
 A0 = 1.255   # reactive radius of a four-point blob, in units of h
 
 
@@ -120,7 +125,22 @@ def pair_list(q: np.ndarray, n, h: float = 1.0, rc: float = RC) -> Tuple[np.ndar
     return ptr, np.concatenate(rows) if rows else np.zeros(0, np.int64)
 
 
-def features(q: np.ndarray, n, i: np.ndarray, j: np.ndarray, h: float = 1.0, rc: float = RC) -> np.ndarray:
+def neighbour_counts(q: np.ndarray, n, h: float = 1.0, rc: float = RC) -> np.ndarray:
+    """nu_i: the number of blobs j != i with minimum-image |q_j - q_i| < rc / 2."""
+    box = np.asarray(n, dtype=np.float64) * h
+    qw = wrap_positions(q, n, h)
+    N = q.shape[0]
+    nu = np.zeros(N)
+    for i in range(N):
+        d = qw - qw[i]
+        d -= box * np.round(d / box)
+        r = np.sqrt(np.einsum("ij,ij->i", d, d))
+        nu[i] = np.count_nonzero(r < 0.5 * rc) - 1
+    return nu
+
+
+def features(q: np.ndarray, n, i: np.ndarray, j: np.ndarray, nu: np.ndarray, h: float = 1.0,
+             rc: float = RC) -> np.ndarray:
     box = np.asarray(n, dtype=np.float64) * h
     qw = wrap_positions(q, n, h)
     d = qw[j] - qw[i]
@@ -130,7 +150,8 @@ def features(q: np.ndarray, n, i: np.ndarray, j: np.ndarray, h: float = 1.0, rc:
     sj = qw[j] / h - 0.5
     fi = si - np.floor(si)
     fj = sj - np.floor(sj)
-    return np.concatenate([d / rc, (r / rc)[:, None], fi, fj], axis=1)
+    return np.concatenate([d / rc, (r / rc)[:, None], fi, fj, NU_SCALE * nu[i][:, None], NU_SCALE * nu[j][:, None]],
+                          axis=1)
 
 
 # ---------------------------------------------------------------- network
@@ -184,7 +205,8 @@ def assemble(p_rounded, q, n, h=1.0, D=1.0, rc=RC, mfma_operands=False):
     """CSR of W: (ptr, col, val, cache) with val_ij = D h (diag + (g_ij + g_ji)/2)."""
     ptr, col = pair_list(q, n, h, rc)
     row = np.repeat(np.arange(q.shape[0]), np.diff(ptr))
-    X = np.concatenate([features(q, n, row, col, h, rc), features(q, n, col, row, h, rc)])
+    nu = neighbour_counts(q, n, h, rc)
+    X = np.concatenate([features(q, n, row, col, nu, h, rc), features(q, n, col, row, nu, h, rc)])
     g, cache = forward(p_rounded, X, mfma_operands)
     m = row.size
     val = D * h * (0.5 * (g[:m] + g[m:]) + (row == col) * 4.0 * math.pi * A0)

@@ -78,10 +78,11 @@ struct TailDesc {
 };
 
 // Learned preconditioner network: flat float32 parameter vector
-// [W1 (64 x 10, row = output) | b1 | W2 (64 x 64) | b2 | w3 | b3].
-constexpr int kNetFeat = 10;
-constexpr int kOffW1 = 0, kOffB1 = 640, kOffW2 = 704, kOffB2 = 4800, kOffW3 = 4864, kOffB3 = 4928;
-constexpr int kNetParams = 4929;
+// [W1 (64 x 12, row = output) | b1 | W2 (64 x 64) | b2 | w3 | b3].
+constexpr int kNetFeat = 12;
+constexpr int kOffW1 = 0, kOffB1 = 768, kOffW2 = 832, kOffB2 = 4928, kOffW3 = 4992, kOffB3 = 5056;
+constexpr int kNetParams = 5057;
+constexpr float kNuScale = 0.25f;  // neighbour counts enter the network as nu / 4
 
 struct NetDev {
     const float* P;     // float32 masters
@@ -95,6 +96,7 @@ struct PairGeom {
     double h;
     double rc;      // pair cutoff
     int ncx, ncy, ncz;  // pair-search cells per axis
+    const float* nu;    // per blob: other blobs within rc / 2 (network input; null while the list is built)
 };
 
 struct BlobGeom {

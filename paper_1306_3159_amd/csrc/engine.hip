@@ -416,6 +416,7 @@ struct blob_rd {
         int* rowidx = nullptr;
         double* val = nullptr;
         float* dg = nullptr;
+        float* nu = nullptr;  // per blob: other blobs within rc / 2 (a network input)
         PairGeom pg{};
     } lrn;
     int fallback = 0;
@@ -2452,7 +2453,7 @@ long long pair_count(blob_rd* H, const PairGeom& pg, int** rowptr_out, int** cel
 
 size_t learned_bytes(int N, long long nnz) {
     return align_up((size_t)(N + 1) * 4) + 2 * align_up((size_t)nnz * 4) + align_up((size_t)nnz * 8) +
-           align_up((size_t)nnz * 4) + 256;
+           align_up((size_t)nnz * 4) + align_up((size_t)N * 4) + 256;
 }
 }  // namespace
 
@@ -3211,15 +3212,19 @@ int precond_build_into(blob_rd* H, blob_rd_net* Nt, void* buf, size_t bytes, siz
     L.val = (double*)b;
     b += align_up((size_t)nnz * 8);
     L.dg = (float*)b;
+    b += align_up((size_t)nnz * 4);
+    L.nu = (float*)b;
     L.nnz = nnz;
     L.pg = pg;
+    L.pg.nu = L.nu;
     const double* q = H->at<double>(H->P.off_q);
     HIPCHK(hipMemcpyAsync(L.rowptr, rowptr_s, (size_t)(N + 1) * 4, hipMemcpyDeviceToDevice, H->st));
     launch_pair_fill(H->st, q, N, pg, cell, offs, prm, L.rowptr, L.col, L.rowidx);
     launch_rowidx(H->st, L.rowptr, N, L.rowidx);
+    launch_pair_nu(H->st, q, L.pg, L.rowptr, L.col, N, L.nu);
     // the network's stream ordering: make sure its weights are current
     HIPCHK(hipStreamSynchronize(Nt->st));
-    launch_net_assemble(H->st, q, pg, Nt->dev(), L.col, L.rowidx, nnz, H->prm.D * H->prm.h,
+    launch_net_assemble(H->st, q, L.pg, Nt->dev(), L.col, L.rowidx, nnz, H->prm.D * H->prm.h,
                         4.0 * M_PI * 1.255, L.val);
     int* bad = reinterpret_cast<int*>(H->dsc() + 40);
     launch_count_bad(H->st, L.val, nnz, bad);
@@ -3378,7 +3383,7 @@ struct BlobPart {
     int off_param, count;
     bool bf16;
 };
-constexpr BlobPart kBlobParts[6] = {{kOffW1, 640, true}, {kOffB1, 64, false}, {kOffW2, 4096, true},
+constexpr BlobPart kBlobParts[6] = {{kOffW1, 64 * kNetFeat, true}, {kOffB1, 64, false}, {kOffW2, 4096, true},
                                     {kOffB2, 64, false}, {kOffW3, 64, true},  {kOffB3, 1, false}};
 
 float bf16_to_float(uint16_t b) {

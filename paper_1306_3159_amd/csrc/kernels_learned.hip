@@ -169,6 +169,40 @@ __device__ __forceinline__ void pair_features(const double* __restrict__ q, Pair
     x[1] = (float)(d[1] / pg.rc);
     x[2] = (float)(d[2] / pg.rc);
     x[3] = (float)(r / pg.rc);
+    x[10] = kNuScale * pg.nu[a];
+    x[11] = kNuScale * pg.nu[b];
+}
+
+// nu_i: the other blobs of row i of the pair list closer than rc / 2 (minimum image, the
+// separation formed as in pair_features).
+__global__ void k_pair_nu(const double* __restrict__ q, PairGeom pg, const int* __restrict__ rowptr,
+                          const int* __restrict__ col, int N, float* __restrict__ nu) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double qi[3];
+    for (int k = 0; k < 3; ++k) {
+        const double L = pg.box[k];
+        qi[k] = q[3 * i + k] - L * floor(q[3 * i + k] / L);
+    }
+    int count = 0;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        const int j = col[e];
+        if (j == i) continue;
+        double r2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double L = pg.box[k];
+            const double qj = q[3 * j + k] - L * floor(q[3 * j + k] / L);
+            const double dk = min_image(qj - qi[k], L);
+            r2 += dk * dk;
+        }
+        if (sqrt(r2) < 0.5 * pg.rc) ++count;
+    }
+    nu[i] = (float)count;
+}
+
+void launch_pair_nu(hipStream_t st, const double* q, PairGeom pg, const int* rowptr, const int* col, int N, float* nu) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_pair_nu, dim3(nblocks(N)), dim3(kBlock), 0, st, q, pg, rowptr, col, N, nu);
 }
 
 // Weight operands in registers (per lane), loaded once per kernel.
@@ -258,7 +292,7 @@ __device__ __forceinline__ bf16x8 feature_operand(const double* q, PairGeom pg, 
 #pragma unroll
     for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.0f;
     if (g < 2) {
-        float x[10];
+        float x[kNetFeat];
         if (ev < nev) {
             const long long e = ev >> 1;
             const int a = rowidx[e], b = col[e];
@@ -266,12 +300,12 @@ __device__ __forceinline__ bf16x8 feature_operand(const double* q, PairGeom pg, 
             else pair_features(q, pg, a, b, x);
         } else {
 #pragma unroll
-            for (int k = 0; k < 10; ++k) x[k] = 0.f;
+            for (int k = 0; k < kNetFeat; ++k) x[k] = 0.f;
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int k = 8 * g + j;
-            v[j] = (__bf16)(k < 10 ? x[k] : 0.f);
+            v[j] = (__bf16)(k < kNetFeat ? x[k] : 0.f);
         }
     }
     return v;

@@ -243,6 +243,7 @@ void launch_pair_count(hipStream_t st, const double* q, int N, PairGeom pg, cons
 void launch_pair_fill(hipStream_t st, const double* q, int N, PairGeom pg, const int* cell_of, const int* offsets,
                       const int* perm, const int* rowptr, int* col, int* rowidx);
 void launch_rowidx(hipStream_t st, const int* rowptr, int N, int* rowidx);
+void launch_pair_nu(hipStream_t st, const double* q, PairGeom pg, const int* rowptr, const int* col, int N, float* nu);
 void launch_net_assemble(hipStream_t st, const double* q, PairGeom pg, NetDev net, const int* col, const int* rowidx,
                          long long nnz, double Dh, double diag, double* val);
 void launch_spmv(hipStream_t st, const int* rowptr, const int* col, const double* val, const double* x, double* y,

@@ -22,10 +22,10 @@ from .native import BlobRD, Net, MIXED, PRECOND_LEARNED, PRECOND_NONE, NET_PARAM
 
 def initial_params(seed: int = 0) -> np.ndarray:
     """Seeded starting weights as one float32 vector in the library's parameter layout
-    [W1 (64x10) | b1 | W2 (64x64) | b2 | w3 | b3]: He-scaled normal hidden layers and a
+    [W1 (64x12) | b1 | W2 (64x64) | b2 | w3 | b3]: He-scaled normal hidden layers and a
     zero output layer, so the untrained network reproduces the diagonal preconditioner."""
     rng = np.random.default_rng(seed)
-    w1 = rng.standard_normal((64, 10)) * np.sqrt(2.0 / 10)
+    w1 = rng.standard_normal((64, 12)) * np.sqrt(2.0 / 12)
     w2 = rng.standard_normal((64, 64)) * np.sqrt(2.0 / 64)
     v = np.concatenate([w1.ravel(), np.zeros(64), w2.ravel(), np.zeros(64), np.zeros(64), np.zeros(1)])
     assert v.size == NET_PARAMS

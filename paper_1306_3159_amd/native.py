@@ -216,11 +216,11 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-NET_PARAMS = 4929
-PRECOND_BLOB_BYTES = 10116
+NET_PARAMS = 5057
+PRECOND_BLOB_BYTES = 10372
 # the weight blob: (parameter offset, count, stored as bfloat16) in the order of the float32 vector
-_BLOB_PARTS = ((0, 640, True), (640, 64, False), (704, 4096, True), (4800, 64, False), (4864, 64, True),
-               (4928, 1, False))
+_BLOB_PARTS = ((0, 768, True), (768, 64, False), (832, 4096, True), (4928, 64, False), (4992, 64, True),
+               (5056, 1, False))
 
 
 def weights_blob(params) -> bytes:

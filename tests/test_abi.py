@@ -91,7 +91,7 @@ def test_weight_blob_round_trip():
     rng = np.random.default_rng(3)
     v = rng.standard_normal(LN.n_params()).astype(np.float32)
     b = weights_blob(v)
-    assert len(b) == PRECOND_BLOB_BYTES == 2 * (640 + 4096 + 64) + 4 * (64 + 64 + 1)
+    assert len(b) == PRECOND_BLOB_BYTES == 2 * (768 + 4096 + 64) + 4 * (64 + 64 + 1)
     back = LN.unflatten(blob_params(b))
     ref = LN.rounded(LN.unflatten(v))
     for k in LN.PARAM_ORDER:

@@ -41,13 +41,31 @@ def test_features_antisymmetric_and_bounded():
     q = rng.uniform(-5, n + 5, (50, 3))
     i = rng.integers(0, 50, 200)
     j = rng.integers(0, 50, 200)
-    a = LN.features(q, (n, n, n), i, j)
-    b = LN.features(q, (n, n, n), j, i)
+    nu = LN.neighbour_counts(q, (n, n, n))
+    a = LN.features(q, (n, n, n), i, j, nu)
+    b = LN.features(q, (n, n, n), j, i, nu)
+    assert a.shape[1] == LN.NFEAT == 12
     assert np.allclose(a[:, :3], -b[:, :3], atol=1e-15)
     assert np.allclose(a[:, 3], b[:, 3])
-    assert np.all((a[:, 4:] >= 0) & (a[:, 4:] < 1))
+    assert np.all((a[:, 4:10] >= 0) & (a[:, 4:10] < 1))
     assert np.allclose(a[:, 4:7], b[:, 7:10])
+    assert np.array_equal(a[:, 10], b[:, 11]) and np.array_equal(a[:, 10], 0.25 * nu[i])
     assert np.all(a[:, 3] <= math.sqrt(3) * n / 2 / LN.RC + 1e-12)
+
+
+def test_neighbour_counts_match_a_periodic_kdtree():
+    """nu_i = other blobs within r_c / 2 (minimum image): against scipy's periodic KD-tree, and
+    every pair counted from both ends."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(8)
+    n = 40
+    q = W.rsa_positions(rng, n, 400, 3.0)
+    nu = LN.neighbour_counts(q, (n, n, n))
+    tree = cKDTree(q % n, boxsize=n)
+    ref = np.array([len(x) - 1 for x in tree.query_ball_point(q % n, 0.5 * LN.RC - 1e-12)])
+    assert np.array_equal(nu, ref)
+    assert nu.sum() == 2 * len(tree.query_pairs(0.5 * LN.RC - 1e-12))
+    assert nu.max() > 0
 
 
 def test_untrained_network_is_the_diagonal_preconditioner():
