@@ -109,6 +109,8 @@ def main(argv=None):
     ap.add_argument("--workers", type=int, default=1, help="host processes generating the configurations")
     ap.add_argument("--eval-only", default=None, metavar="WEIGHTS",
                     help="skip training: evaluate these saved weights on the --eval sets and print the report")
+    ap.add_argument("--init", default=None, metavar="WEIGHTS",
+                    help="start from these saved weights instead of the seeded initial ones")
     ap.add_argument("--cycles", type=int, default=0,
                     help="train against the approximate-Schur operator with this many multigrid cycles per product "
                          "(the block preconditioner's inner operator); 0: Schur products with inner solves")
@@ -144,7 +146,8 @@ def main(argv=None):
     if pool is not None:
         pool.close()
     net = Net(dev)
-    net.set_params(torch.tensor(LD.initial_params(args.seed), device=dev))
+    init = np.load(args.init) if args.init else LD.initial_params(args.seed)
+    net.set_params(torch.tensor(init, device=dev))
     hist = LD.train(net, samples, args.epochs, args.lr, args.batch, dev, seed=args.seed, log=log,
                     lr_final=args.lr_final)
     params = net.get_params().cpu().numpy()
@@ -153,7 +156,7 @@ def main(argv=None):
     log(f"saved {args.out}")
     report = {"configs": args.configs, "n": args.n, "blobs": args.blobs, "samples": args.samples,
               "epochs": args.epochs, "lr": args.lr, "lr_final": args.lr_final, "batch": args.batch,
-              "smooth": args.smooth, "seed": args.seed, "cycles": args.cycles, "loss": hist,
+              "smooth": args.smooth, "seed": args.seed, "cycles": args.cycles, "init": args.init, "loss": hist,
               "train_seconds": time.time() - t0, "eval": []}
     report["eval"] = evaluate(net, args.eval, dev, W, LD, MIXED, FP64)
     report["summary"] = summarize(report["eval"])
