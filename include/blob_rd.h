@@ -231,7 +231,9 @@ int blob_rd_vcycle(blob_rd_t h, double alpha, const double* r, double* z);
 #define BLOB_RD_SADDLE_APPROX_SCHUR 1 /* m inner GMRES iterations, one cycle per product */
 #define BLOB_RD_SADDLE_LEARNED 2      /* approximate-Schur variant whose inner GMRES is right-
                                          preconditioned by the handle's learned W (alpha = 0; otherwise,
-                                         or without a built W, the plain variant, stats->fallback = 1) */
+                                         or without a built W, the plain variant, stats->fallback = 1),
+                                         or by the two-level B around W when a Fourier coarse level is
+                                         built for alpha (blob_rd_coarse_build) */
 
 typedef struct {
     int32_t precond; /* BLOB_RD_SADDLE_* */
@@ -402,9 +404,13 @@ int blob_rd_precond_train_step(blob_rd_t h, const void* batch_desc, float lr, fl
  * modes exactly and keeps residuals orthogonal to them. This extends the
  * paper's Schur preconditioner; the paper has no coarse level.
  *
+ * The block solver's learned variant (blob_rd_solve_absorbing_fgmres with
+ * BLOB_RD_SADDLE_LEARNED) right-preconditions its inner GMRES on the one-cycle
+ * Schur system with the same B (W = P W_learned P) instead of W alone; its
+ * other variants never use the level.
+ *
  * Building costs K Schur products (inner multigrid-CG solves to inner_rtol)
- * and holds for the alpha given: solves at another alpha ignore it. The
- * block solver (blob_rd_solve_absorbing_fgmres) never uses it. */
+ * and holds for the alpha given: solves at another alpha ignore it. */
 #define BLOB_RD_COARSE_MAX_COLS 256
 
 /* Device bytes blob_rd_coarse_build needs for m2max (about 16 K N bytes); 0 on

@@ -1178,9 +1178,17 @@ bool spd_inverse(std::vector<double>& A, int K) {
 
 // Z (cos/sin of the wave vectors at the blobs, column means removed), M Z by K Schur
 // products with inner solves to inner_rtol, E = sym(Z^T M Z) and its inverse.
+// Captured block-FGMRES steps read the coarse level's buffers: drop them when it changes.
+void drop_fg_graphs(blob_rd* H) {
+    HIPCHK(hipStreamSynchronize(H->st));
+    for (auto& g : H->fg_graphs) (void)hipGraphExecDestroy(g.exec);
+    H->fg_graphs.clear();
+}
+
 template <typename T>
 void coarse_build(blob_rd* H, double alpha, const std::vector<int>& mv, double inner_rtol, char* buf) {
     blob_rd::Coarse& C = H->crs;
+    drop_fg_graphs(H);
     C.ready = false;
     const int N = H->P.N;
     const int nm = (int)mv.size() / 3;
@@ -1720,10 +1728,15 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
         const size_t nh = P.ncell / 2;
         const double inv_diag = 1.0 / (alpha + 6.0 * H->prm.D / (d.h * d.h));
         const bool from_f = cycle_opens_from_f<T>(H);
+        // with a Fourier coarse level built for this alpha, the inner GMRES is right-preconditioned
+        // by the two-level B around W: the long waves of the multiplier system are solved by the
+        // level instead of left to the m inner iterations
+        const bool use_c = learned && H->crs.ready && H->crs.alpha == alpha;
         for (int k = 0; k < o.m; ++k) {
             const double* vk = V + (size_t)k * N;
             if (learned) {
-                precond_apply(H, vk, H->nv(9));
+                if (use_c) coarse_apply(H, true, vk, H->nv(9));
+                else precond_apply(H, vk, H->nv(9));
                 vk = H->nv(9);
             }
             // S v enters the V-cycle from the contribution lists: level-0 f is zero
@@ -1747,7 +1760,10 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
         double* y = learned ? H->nv(10) : zl;
         launch_nvec_copy_scale(st, nullptr, y, N, 0.0, 0.0);
         launch_gmres_update(st, V, Hm, gv, H->at<double>(P.off_yv), y, N, o.m, o.m);
-        if (learned) precond_apply(H, y, zl);
+        if (learned) {
+            if (use_c) coarse_apply(H, true, y, zl);
+            else precond_apply(H, y, zl);
+        }
         H->inner_iters += o.m;
     }
     if (sing) launch_nvec_project(st, zl, N);
@@ -3296,8 +3312,11 @@ int blob_rd_coarse_build(blob_rd_t H, double alpha, int32_t m2max, double inner_
 
 int blob_rd_coarse_clear(blob_rd_t H) {
     if (!H) return g_last_error = "null argument", BLOB_RD_EINVAL;
-    H->crs = blob_rd::Coarse{};
-    return BLOB_RD_OK;
+    return guarded(H, nullptr, [&]() {
+        drop_fg_graphs(H);
+        H->crs = blob_rd::Coarse{};
+        return BLOB_RD_OK;
+    });
 }
 
 int blob_rd_coarse_apply(blob_rd_t H, const double* r, double* z) {
