@@ -434,7 +434,6 @@ struct blob_rd {
         double* r2 = nullptr;
         double* w = nullptr;
         double* d = nullptr;
-        double* coef = nullptr;
         double* a = nullptr;
         double w0 = 0.0;  // scale of W without the learned part: 4 pi a0 D (eq. Schur_diagonal)
     } crs;
@@ -1110,7 +1109,7 @@ std::vector<int> coarse_modes(int m2max) {
 }
 
 // Buffer layout: modes | Z (K x N) | M Z (K x N) | E^{-1} (K x K) | E (K x K) | r2, w (N) |
-// d, coef, a (K). With buf == null only the size is computed.
+// d, a (K). With buf == null only the size is computed.
 size_t coarse_layout(int N, int K, char* buf, blob_rd::Coarse* C) {
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -1126,7 +1125,6 @@ size_t coarse_layout(int N, int K, char* buf, blob_rd::Coarse* C) {
     char* r2 = take((size_t)N * 8);
     char* w = take((size_t)N * 8);
     char* d = take((size_t)K * 8);
-    char* coef = take((size_t)K * 8);
     char* a = take((size_t)K * 8);
     if (C) {
         C->modes = reinterpret_cast<int*>(modes);
@@ -1137,7 +1135,6 @@ size_t coarse_layout(int N, int K, char* buf, blob_rd::Coarse* C) {
         C->r2 = reinterpret_cast<double*>(r2);
         C->w = reinterpret_cast<double*>(w);
         C->d = reinterpret_cast<double*>(d);
-        C->coef = reinterpret_cast<double*>(coef);
         C->a = reinterpret_cast<double*>(a);
     }
     return o;
@@ -1230,18 +1227,16 @@ void coarse_apply(blob_rd* H, bool use_w, const double* r, double* z) {
     blob_rd::Coarse& C = H->crs;
     hipStream_t st = H->st;
     const int N = H->P.N, K = C.K;
-    launch_coarse_dots(st, C.Z, N, K, r, C.d);                            // d = Z^T r
-    launch_coarse_coef(st, C.Einv, C.d, nullptr, K, -1.0, C.coef, C.a);   // a = E^{-1} d
-    launch_coarse_axpy(st, C.MZ, N, K, C.coef, r, C.r2);                  // r2 = r - M Z a
+    launch_coarse_dots(st, C.Z, N, K, r, C.d);                                    // d = Z^T r
+    launch_coarse_update(st, C.Einv, C.d, nullptr, K, -1.0, C.MZ, N, r, C.r2, C.a);  // a = E^{-1} d, r2 = r - M Z a
     if (use_w) {
         precond_apply(H, C.r2, C.w);
     } else {
         launch_nvec_copy_scale(st, C.r2, C.w, N, C.w0, 0.0);
         if (singular(H, C.alpha)) launch_nvec_project(st, C.w, N);
     }
-    launch_coarse_dots(st, C.MZ, N, K, C.w, C.d);                         // e = (M Z)^T w
-    launch_coarse_coef(st, C.Einv, C.d, C.a, K, -1.0, C.coef, nullptr);   // a - E^{-1} e
-    launch_coarse_axpy(st, C.Z, N, K, C.coef, C.w, z);                    // z = w + Z (a - E^{-1} e)
+    launch_coarse_dots(st, C.MZ, N, K, C.w, C.d);                                 // e = (M Z)^T w
+    launch_coarse_update(st, C.Einv, C.d, C.a, K, -1.0, C.Z, N, C.w, z, nullptr);   // z = w + Z (a - E^{-1} e)
 }
 
 struct SaddleInfo {

@@ -66,32 +66,29 @@ __global__ void __launch_bounds__(kBlock) k_coarse_gram(const double* __restrict
     if (threadIdx.x == 0) E[(size_t)blockIdx.y * K + blockIdx.x] = s;
 }
 
-// One work-group: a = Einv d (row-major K x K, K <= kBlock); coef = base + sgn a
-// (base may be null = 0); a_out (may be null) receives a.
-__global__ void __launch_bounds__(kBlock) k_coarse_coef(const double* __restrict__ Einv, const double* __restrict__ d,
-                                                        const double* __restrict__ base, int K, double sgn,
-                                                        double* __restrict__ coef, double* __restrict__ a_out) {
-    const int j = threadIdx.x;
-    if (j >= K) return;
-    const double* row = Einv + (size_t)j * K;
-    double s = 0.0;
-    for (int l = 0; l < K; ++l) s += row[l] * d[l];
-    coef[j] = (base ? base[j] : 0.0) + sgn * s;
-    if (a_out) a_out[j] = s;
-}
-
-// out = x + Y coef (Y an N x K block of columns, coef staged in LDS).
-__global__ void __launch_bounds__(kBlock) k_coarse_axpy(const double* __restrict__ Y, int N, int K,
-                                                        const double* __restrict__ coef, const double* __restrict__ x,
-                                                        double* __restrict__ out) {
+// out = x + Y c with c = base + sgn Einv d (Einv row-major K x K, base may be null = 0):
+// every work-group forms c in LDS from d (K^2 products, the same order in every block),
+// then one thread per entry sums its K column values. Block 0 writes Einv d to a_out
+// (may be null).
+__global__ void __launch_bounds__(kBlock) k_coarse_update(const double* __restrict__ Einv, const double* __restrict__ d,
+                                                          const double* __restrict__ base, int K, double sgn,
+                                                          const double* __restrict__ Y, int N,
+                                                          const double* __restrict__ x, double* __restrict__ out,
+                                                          double* __restrict__ a_out) {
     __shared__ double c[kMaxCoarseCols];
-    for (int j = threadIdx.x; j < K; j += kBlock) c[j] = coef[j];
+    for (int j = threadIdx.x; j < K; j += kBlock) {
+        const double* row = Einv + (size_t)j * K;
+        double s = 0.0;
+        for (int l = 0; l < K; ++l) s += row[l] * d[l];
+        c[j] = (base ? base[j] : 0.0) + sgn * s;
+        if (a_out && blockIdx.x == 0) a_out[j] = s;
+    }
     __syncthreads();
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= N) return;
-    double s = x[i];
-    for (int j = 0; j < K; ++j) s += Y[(size_t)j * N + i] * c[j];
-    out[i] = s;
+    double v = x[i];
+    for (int j = 0; j < K; ++j) v += Y[(size_t)j * N + i] * c[j];
+    out[i] = v;
 }
 
 void launch_coarse_basis(hipStream_t st, const double* q, int N, const int* mv, int nmodes, double kx, double ky,
@@ -109,15 +106,11 @@ void launch_coarse_dots(hipStream_t st, const double* A, int N, int K, const dou
     hipLaunchKernelGGL(k_coarse_dots, dim3(K), dim3(kBlock), 0, st, A, N, v, out);
 }
 
-void launch_coarse_coef(hipStream_t st, const double* Einv, const double* d, const double* base, int K, double sgn,
-                        double* coef, double* a_out) {
-    hipLaunchKernelGGL(k_coarse_coef, dim3(1), dim3(kBlock), 0, st, Einv, d, base, K, sgn, coef, a_out);
-}
-
-void launch_coarse_axpy(hipStream_t st, const double* Y, int N, int K, const double* coef, const double* x,
-                        double* out) {
+void launch_coarse_update(hipStream_t st, const double* Einv, const double* d, const double* base, int K, double sgn,
+                          const double* Y, int N, const double* x, double* out, double* a_out) {
     if (N <= 0) return;
-    hipLaunchKernelGGL(k_coarse_axpy, dim3(nblocks(N)), dim3(kBlock), 0, st, Y, N, K, coef, x, out);
+    hipLaunchKernelGGL(k_coarse_update, dim3(nblocks(N)), dim3(kBlock), 0, st, Einv, d, base, K, sgn, Y, N, x, out,
+                       a_out);
 }
 
 }  // namespace brd

@@ -222,10 +222,8 @@ void launch_coarse_basis(hipStream_t st, const double* q, int N, const int* mv, 
                          double kz, double* Z);
 void launch_coarse_gram(hipStream_t st, const double* Z, const double* Y, int N, int K, double* E);
 void launch_coarse_dots(hipStream_t st, const double* A, int N, int K, const double* v, double* out);
-void launch_coarse_coef(hipStream_t st, const double* Einv, const double* d, const double* base, int K, double sgn,
-                        double* coef, double* a_out);
-void launch_coarse_axpy(hipStream_t st, const double* Y, int N, int K, const double* coef, const double* x,
-                        double* out);
+void launch_coarse_update(hipStream_t st, const double* Einv, const double* d, const double* base, int K, double sgn,
+                          const double* Y, int N, const double* x, double* out, double* a_out);
 void launch_nvec_copy_scale(hipStream_t st, const double* x, double* y, int N, double a, double shift);
 void launch_gmres_start(hipStream_t st, const double* b, const double* w, int has_w, double* V, double* g, int N,
                         GmresScalars* gs);
