@@ -1211,6 +1211,13 @@ void coarse_build(blob_rd* H, double alpha, const std::vector<int>& mv, double i
         }
     if (!spd_inverse(E, K))
         throw Err(BLOB_RD_ENUMERIC, "coarse matrix Z^T M Z is not positive definite (too many modes for the blobs?)");
+    // exactly symmetric, so the apply may read its columns as rows
+    for (int i = 0; i < K; ++i)
+        for (int j = 0; j < i; ++j) {
+            const double v = 0.5 * (E[(size_t)i * K + j] + E[(size_t)j * K + i]);
+            E[(size_t)i * K + j] = v;
+            E[(size_t)j * K + i] = v;
+        }
     HIPCHK(hipMemcpyAsync(C.Einv, E.data(), E.size() * 8, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
     C.w0 = 4.0 * M_PI * (H->prm.kernel_w == 3 ? kA0OverH3 : kA0OverH) * h * H->prm.D;

@@ -66,29 +66,43 @@ __global__ void __launch_bounds__(kBlock) k_coarse_gram(const double* __restrict
     if (threadIdx.x == 0) E[(size_t)blockIdx.y * K + blockIdx.x] = s;
 }
 
-// out = x + Y c with c = base + sgn Einv d (Einv row-major K x K, base may be null = 0):
-// every work-group forms c in LDS from d (K^2 products, the same order in every block),
-// then one thread per entry sums its K column values. Block 0 writes Einv d to a_out
-// (may be null).
+// out = x + Y c with c = base + sgn Einv d (Einv K x K and symmetric, base may be null = 0):
+// every work-group forms c in LDS from d (thread j sums column j of Einv, which is row j, so
+// the threads' loads are contiguous; the same order in every block), then one thread per
+// entry sums its K column values. Block 0 writes Einv d to a_out (may be null).
 __global__ void __launch_bounds__(kBlock) k_coarse_update(const double* __restrict__ Einv, const double* __restrict__ d,
                                                           const double* __restrict__ base, int K, double sgn,
                                                           const double* __restrict__ Y, int N,
                                                           const double* __restrict__ x, double* __restrict__ out,
                                                           double* __restrict__ a_out) {
+    __shared__ double ds[kMaxCoarseCols];
     __shared__ double c[kMaxCoarseCols];
+    for (int j = threadIdx.x; j < K; j += kBlock) ds[j] = d[j];
+    __syncthreads();
+    // four independent partial sums keep four loads in flight per thread
     for (int j = threadIdx.x; j < K; j += kBlock) {
-        const double* row = Einv + (size_t)j * K;
-        double s = 0.0;
-        for (int l = 0; l < K; ++l) s += row[l] * d[l];
+        double p[4] = {0.0, 0.0, 0.0, 0.0};
+        int l = 0;
+        for (; l + 3 < K; l += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) p[u] += Einv[(size_t)(l + u) * K + j] * ds[l + u];
+        }
+        for (; l < K; ++l) p[0] += Einv[(size_t)l * K + j] * ds[l];
+        const double s = (p[0] + p[1]) + (p[2] + p[3]);
         c[j] = (base ? base[j] : 0.0) + sgn * s;
         if (a_out && blockIdx.x == 0) a_out[j] = s;
     }
     __syncthreads();
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= N) return;
-    double v = x[i];
-    for (int j = 0; j < K; ++j) v += Y[(size_t)j * N + i] * c[j];
-    out[i] = v;
+    double p[4] = {0.0, 0.0, 0.0, 0.0};
+    int j = 0;
+    for (; j + 3 < K; j += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) p[u] += Y[(size_t)(j + u) * N + i] * c[j + u];
+    }
+    for (; j < K; ++j) p[0] += Y[(size_t)j * N + i] * c[j];
+    out[i] = x[i] + ((p[0] + p[1]) + (p[2] + p[3]));
 }
 
 void launch_coarse_basis(hipStream_t st, const double* q, int N, const int* mv, int nmodes, double kx, double ky,
