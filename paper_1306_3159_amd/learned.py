@@ -116,13 +116,23 @@ def train(net: Net, samples: List[Sample], epochs: int, lr: float, batch: int, d
 
 
 def block_iterations(shape, q: np.ndarray, f: torch.Tensor, net: Optional[Net], device, rtol: float = 1e-8,
-                     precision: int = MIXED, m: int = 5, kind: Optional[str] = None):
+                     precision: int = MIXED, m: int = 5, kind: Optional[str] = None, coarse_m2: int = 0,
+                     coarse_rtol: float = 1e-4):
     """Block FGMRES iterations and wall time of one absorbing solve with the approximate-Schur
-    preconditioner, its inner GMRES preconditioned by W (net) or not (or kind = "diagonal")."""
+    preconditioner, its inner GMRES preconditioned by W (net) or not (or kind = "diagonal"); with
+    coarse_m2 > 0 (and a net) by the two-level B of the Fourier coarse level around W (its build
+    time is returned in the stats as coarse_build_seconds, outside the solve's time)."""
     S = BlobRD(shape, torch.tensor(q, device=device), precision=precision, rtol=rtol,
                schur_precond=PRECOND_LEARNED if net is not None else PRECOND_NONE)
     if net is not None:
         S.precond_build(net)
+    tb = 0.0
+    if coarse_m2 > 0:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.coarse_build(0.0, coarse_m2, coarse_rtol)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
     kind = kind or ("learned" if net is not None else "schur")
     S.solve_absorbing_fgmres(f, precond=kind, m=m)
     torch.cuda.synchronize()
@@ -131,6 +141,7 @@ def block_iterations(shape, q: np.ndarray, f: torch.Tensor, net: Optional[Net], 
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     S.close()
+    st["coarse_build_seconds"] = tb
     return st, dt, c, lam
 
 

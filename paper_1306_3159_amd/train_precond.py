@@ -43,7 +43,8 @@ def _positions(arg):
 def evaluate(net, spec_list: str, dev, W, LD, MIXED, FP64):
     """Held-out absorbing solves (f = 1) with and without the network: Schur GMRES (plain FP64,
     FP32 cycles, learned, and both with the 80-column Fourier coarse level, |m|^2 <= 6) and the
-    block FGMRES (diagonal, approximate Schur, learned inner)."""
+    block FGMRES (diagonal, approximate Schur, learned inner, learned inner with the coarse level
+    at m = 5 and m = 3)."""
     import torch
     rows = []
     for spec in spec_list.split(","):
@@ -61,7 +62,9 @@ def evaluate(net, spec_list: str, dev, W, LD, MIXED, FP64):
                     ("learned_coarse_mixed", net, MIXED, LD.gmres_iterations, {"coarse_m2": 6}),
                     ("block_diagonal_mixed", None, MIXED, LD.block_iterations, {"kind": "diagonal"}),
                     ("block_mixed", None, MIXED, LD.block_iterations, {}),
-                    ("block_learned_mixed", net, MIXED, LD.block_iterations, {}))
+                    ("block_learned_mixed", net, MIXED, LD.block_iterations, {}),
+                    ("block_learned_coarse_mixed", net, MIXED, LD.block_iterations, {"coarse_m2": 6}),
+                    ("block_learned_coarse_m3_mixed", net, MIXED, LD.block_iterations, {"coarse_m2": 6, "m": 3}))
             for name, netx, prec, fn, kw in runs:
                 st, dt, c, lam = fn(n, inst.q, f, netx, dev, precision=prec, **kw)
                 row[name] = {"iters": st["outer_iters"], "inner_iters": st["inner_iters_total"],
