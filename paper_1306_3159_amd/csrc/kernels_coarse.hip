@@ -10,6 +10,8 @@
 
 namespace brd {
 
+static_assert(kMaxCoarseCols <= kBlock, "the coarse-level kernels hold one column per thread");
+
 // Column 2t = cos(k_t . q_i), column 2t + 1 = sin(k_t . q_i), with
 // k_t = 2 pi (m_x / L_x, m_y / L_y, m_z / L_z) from the integer table mv (3 per mode).
 __global__ void k_coarse_basis(const double* __restrict__ q, int N, const int* __restrict__ mv, double kx, double ky,
@@ -77,18 +79,29 @@ __global__ void __launch_bounds__(kBlock) k_coarse_update(const double* __restri
                                                           double* __restrict__ a_out) {
     __shared__ double ds[kMaxCoarseCols];
     __shared__ double c[kMaxCoarseCols];
+    __shared__ double part[kBlock];
     for (int j = threadIdx.x; j < K; j += kBlock) ds[j] = d[j];
     __syncthreads();
-    // four independent partial sums keep four loads in flight per thread
-    for (int j = threadIdx.x; j < K; j += kBlock) {
+    // Einv d over all threads: row j split into `parts` chunks of its columns (threads of one
+    // chunk read contiguous entries), four independent partial sums per thread
+    const int parts = kBlock / K;  // >= 1 (K <= kMaxCoarseCols = kBlock); parts * K <= kBlock
+    const int chunk = (K + parts - 1) / parts;
+    const int t = threadIdx.x;
+    if (t < parts * K) {
+        const int j = t % K, l0 = (t / K) * chunk, l1 = l0 + chunk < K ? l0 + chunk : K;
         double p[4] = {0.0, 0.0, 0.0, 0.0};
-        int l = 0;
-        for (; l + 3 < K; l += 4) {
+        int l = l0;
+        for (; l + 3 < l1; l += 4) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) p[u] += Einv[(size_t)(l + u) * K + j] * ds[l + u];
         }
-        for (; l < K; ++l) p[0] += Einv[(size_t)l * K + j] * ds[l];
-        const double s = (p[0] + p[1]) + (p[2] + p[3]);
+        for (; l < l1; ++l) p[0] += Einv[(size_t)l * K + j] * ds[l];
+        part[t] = (p[0] + p[1]) + (p[2] + p[3]);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < K; j += kBlock) {
+        double s = 0.0;
+        for (int pi = 0; pi < parts; ++pi) s += part[pi * K + j];
         c[j] = (base ? base[j] : 0.0) + sgn * s;
         if (a_out && blockIdx.x == 0) a_out[j] = s;
     }
