@@ -413,7 +413,7 @@ int blob_rd_precond_train_step(blob_rd_t h, const void* batch_desc, float lr, fl
  * and holds for the alpha given: solves at another alpha ignore it. */
 #define BLOB_RD_COARSE_MAX_COLS 256
 
-/* Device bytes blob_rd_coarse_build needs for m2max (about 16 K N bytes); 0 on
+/* Device bytes blob_rd_coarse_build needs for m2max (about 32 K N bytes); 0 on
  * a bad argument (null handle, no blobs, m2max outside [1, 16]). */
 size_t blob_rd_coarse_bytes(blob_rd_t h, int32_t m2max);
 /* Build the coarse level for alpha into caller-owned device memory buf (at

@@ -26,6 +26,7 @@ constexpr int kFinBlock = 1024;
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarse = 512;
 constexpr int kMaxCoarseCols = 256;  // columns of the Schur preconditioner's Fourier coarse level
+constexpr int kCoarseChunk = 2048;   // rows per work-group in the coarse level's dot products
 constexpr int kStageBlobs = 128;   // candidate blobs staged in LDS per pass of the spread planner
 
 // Device-resident scalars of one CG solve. Every kernel of an iteration reads

@@ -421,7 +421,8 @@ struct blob_rd {
     } lrn;
     int fallback = 0;
     // Fourier coarse level of the Schur preconditioner (in a caller-owned buffer): the basis Z,
-    // M Z and E^{-1} = (Z^T M Z)^{-1} for the alpha it was built for, plus apply scratch
+    // M Z, E^{-1} = (Z^T M Z)^{-1} and the two folded into it (Z E^{-1}, M Z E^{-1}) for the
+    // alpha it was built for, plus apply scratch
     struct Coarse {
         bool ready = false;
         double alpha = 0.0;
@@ -429,11 +430,13 @@ struct blob_rd {
         int* modes = nullptr;
         double* Z = nullptr;
         double* MZ = nullptr;
+        double* ZE = nullptr;   // Z E^{-1}
+        double* MZE = nullptr;  // M Z E^{-1}
         double* Einv = nullptr;
         double* E = nullptr;
         double* r2 = nullptr;
         double* w = nullptr;
-        double* d = nullptr;
+        double* part = nullptr;  // K x (row chunks) partial dot products
         double* a = nullptr;
         double w0 = 0.0;  // scale of W without the learned part: 4 pi a0 D (eq. Schur_diagonal)
     } crs;
@@ -1108,8 +1111,9 @@ std::vector<int> coarse_modes(int m2max) {
     return mv;
 }
 
-// Buffer layout: modes | Z (K x N) | M Z (K x N) | E^{-1} (K x K) | E (K x K) | r2, w (N) |
-// d, a (K). With buf == null only the size is computed.
+// Buffer layout: modes | Z, M Z, Z E^{-1}, M Z E^{-1} (K x N each) | E^{-1}, E (K x K) |
+// r2, w (N) | partial dot products (K x row chunks) | a (K). With buf == null only the size
+// is computed.
 size_t coarse_layout(int N, int K, char* buf, blob_rd::Coarse* C) {
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -1120,21 +1124,25 @@ size_t coarse_layout(int N, int K, char* buf, blob_rd::Coarse* C) {
     char* modes = take((size_t)K / 2 * 3 * 4);
     char* Z = take((size_t)K * N * 8);
     char* MZ = take((size_t)K * N * 8);
+    char* ZE = take((size_t)K * N * 8);
+    char* MZE = take((size_t)K * N * 8);
     char* Einv = take((size_t)K * K * 8);
     char* E = take((size_t)K * K * 8);
     char* r2 = take((size_t)N * 8);
     char* w = take((size_t)N * 8);
-    char* d = take((size_t)K * 8);
+    char* part = take((size_t)K * coarse_chunks(N) * 8);
     char* a = take((size_t)K * 8);
     if (C) {
         C->modes = reinterpret_cast<int*>(modes);
         C->Z = reinterpret_cast<double*>(Z);
         C->MZ = reinterpret_cast<double*>(MZ);
+        C->ZE = reinterpret_cast<double*>(ZE);
+        C->MZE = reinterpret_cast<double*>(MZE);
         C->Einv = reinterpret_cast<double*>(Einv);
         C->E = reinterpret_cast<double*>(E);
         C->r2 = reinterpret_cast<double*>(r2);
         C->w = reinterpret_cast<double*>(w);
-        C->d = reinterpret_cast<double*>(d);
+        C->part = reinterpret_cast<double*>(part);
         C->a = reinterpret_cast<double*>(a);
     }
     return o;
@@ -1219,6 +1227,9 @@ void coarse_build(blob_rd* H, double alpha, const std::vector<int>& mv, double i
             E[(size_t)j * K + i] = v;
         }
     HIPCHK(hipMemcpyAsync(C.Einv, E.data(), E.size() * 8, hipMemcpyHostToDevice, st));
+    launch_coarse_rotate(st, C.Z, C.Einv, N, K, C.ZE);
+    launch_coarse_rotate(st, C.MZ, C.Einv, N, K, C.MZE);
+    HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     C.w0 = 4.0 * M_PI * (H->prm.kernel_w == 3 ? kA0OverH3 : kA0OverH) * h * H->prm.D;
     C.alpha = alpha;
@@ -1226,24 +1237,24 @@ void coarse_build(blob_rd* H, double alpha, const std::vector<int>& mv, double i
     C.ready = true;
 }
 
-// z = B r = Q r + (I - Q M) W (I - M Q) r with Q = Z E^{-1} Z^T (M symmetric, so
-// Z^T M w = (M Z)^T w). W is the learned P W P (use_w), else the paper's diagonal
-// 4 pi a0 D I (projected at alpha = 0): W must carry M^{-1}'s scale, as the coarse part
-// does. r and z must not alias.
+// z = B r = Q r + (I - Q M) W (I - M Q) r with Q = Z E^{-1} Z^T (M and E^{-1} symmetric, so
+// E^{-1} Z^T r = (Z E^{-1})^T r and E^{-1} Z^T M w = (M Z E^{-1})^T w). W is the learned
+// P W P (use_w), else the paper's diagonal 4 pi a0 D I (projected at alpha = 0): W must
+// carry M^{-1}'s scale, as the coarse part does. r and z must not alias.
 void coarse_apply(blob_rd* H, bool use_w, const double* r, double* z) {
     blob_rd::Coarse& C = H->crs;
     hipStream_t st = H->st;
     const int N = H->P.N, K = C.K;
-    launch_coarse_dots(st, C.Z, N, K, r, C.d);                                    // d = Z^T r
-    launch_coarse_update(st, C.Einv, C.d, nullptr, K, -1.0, C.MZ, N, r, C.r2, C.a);  // a = E^{-1} d, r2 = r - M Z a
+    launch_coarse_dots(st, C.ZE, N, K, r, C.part);                                // a = E^{-1} Z^T r
+    launch_coarse_update(st, C.part, nullptr, K, -1.0, C.MZ, N, r, C.r2, C.a);    // r2 = r - M Z a
     if (use_w) {
         precond_apply(H, C.r2, C.w);
     } else {
         launch_nvec_copy_scale(st, C.r2, C.w, N, C.w0, 0.0);
         if (singular(H, C.alpha)) launch_nvec_project(st, C.w, N);
     }
-    launch_coarse_dots(st, C.MZ, N, K, C.w, C.d);                                 // e = (M Z)^T w
-    launch_coarse_update(st, C.Einv, C.d, C.a, K, -1.0, C.Z, N, C.w, z, nullptr);   // z = w + Z (a - E^{-1} e)
+    launch_coarse_dots(st, C.MZE, N, K, C.w, C.part);                             // e = E^{-1} (M Z)^T w
+    launch_coarse_update(st, C.part, C.a, K, -1.0, C.Z, N, C.w, z, nullptr);      // z = w + Z (a - e)
 }
 
 struct SaddleInfo {

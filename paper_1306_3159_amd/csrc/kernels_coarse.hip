@@ -10,8 +10,6 @@
 
 namespace brd {
 
-static_assert(kMaxCoarseCols <= kBlock, "the coarse-level kernels hold one column per thread");
-
 // Column 2t = cos(k_t . q_i), column 2t + 1 = sin(k_t . q_i), with
 // k_t = 2 pi (m_x / L_x, m_y / L_y, m_z / L_z) from the integer table mv (3 per mode).
 __global__ void k_coarse_basis(const double* __restrict__ q, int N, const int* __restrict__ mv, double kx, double ky,
@@ -36,20 +34,23 @@ __global__ void __launch_bounds__(kBlock) k_coarse_center(double* __restrict__ Z
     for (int i = threadIdx.x; i < N; i += kBlock) z[i] -= m;
 }
 
-// out[j] = sum_i A[j][i] v[i] for the K columns of A: one work-group per column, four
-// independent partial sums per thread to keep loads in flight.
+// part[j][s] = sum_{i in chunk s} A[j][i] v[i] for the K columns of A and the row chunks
+// [s kCoarseChunk, (s + 1) kCoarseChunk): one work-group per (chunk, column) so the grid fills
+// the chip, four independent partial sums per thread to keep loads in flight.
 __global__ void __launch_bounds__(kBlock) k_coarse_dots(const double* __restrict__ A, int N,
-                                                        const double* __restrict__ v, double* __restrict__ out) {
-    const double* a = A + (size_t)blockIdx.x * N;
+                                                        const double* __restrict__ v, double* __restrict__ part) {
+    const int s = blockIdx.x, j = blockIdx.y;
+    const double* a = A + (size_t)j * N;
+    const int i1 = min(N, (s + 1) * kCoarseChunk);
     double p[4] = {0.0, 0.0, 0.0, 0.0};
-    int i = threadIdx.x;
-    for (; i + 3 * kBlock < N; i += 4 * kBlock) {
+    int i = s * kCoarseChunk + threadIdx.x;
+    for (; i + 3 * kBlock < i1; i += 4 * kBlock) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) p[u] += a[i + u * kBlock] * v[i + u * kBlock];
     }
-    for (; i < N; i += kBlock) p[0] += a[i] * v[i];
-    const double s = wg_sum((p[0] + p[1]) + (p[2] + p[3]));
-    if (threadIdx.x == 0) out[blockIdx.x] = s;
+    for (; i < i1; i += kBlock) p[0] += a[i] * v[i];
+    const double t = wg_sum((p[0] + p[1]) + (p[2] + p[3]));
+    if (threadIdx.x == 0) part[(size_t)j * gridDim.x + s] = t;
 }
 
 // E[a][b] = sum_i Z[a][i] Y[b][i]: one work-group per entry (grid K x K).
@@ -68,54 +69,59 @@ __global__ void __launch_bounds__(kBlock) k_coarse_gram(const double* __restrict
     if (threadIdx.x == 0) E[(size_t)blockIdx.y * K + blockIdx.x] = s;
 }
 
-// out = x + Y c with c = base + sgn Einv d (Einv K x K and symmetric, base may be null = 0):
-// every work-group forms c in LDS from d (thread j sums column j of Einv, which is row j, so
-// the threads' loads are contiguous; the same order in every block), then one thread per
-// entry sums its K column values. Block 0 writes Einv d to a_out (may be null).
-__global__ void __launch_bounds__(kBlock) k_coarse_update(const double* __restrict__ Einv, const double* __restrict__ d,
+// out = x + Y c with c = base + sgn d, d[j] = sum_s part[j][s] over the S chunk sums of
+// k_coarse_dots (base may be null = 0). A work-group takes 64 rows: every block forms c in LDS
+// (the same order in every block), then wave w sums the rows' values of its quarter of the
+// columns and the four quarters are added in a fixed order. Block 0 writes d to a_out (may be
+// null).
+__global__ void __launch_bounds__(kBlock) k_coarse_update(const double* __restrict__ part, int S,
                                                           const double* __restrict__ base, int K, double sgn,
                                                           const double* __restrict__ Y, int N,
                                                           const double* __restrict__ x, double* __restrict__ out,
                                                           double* __restrict__ a_out) {
-    __shared__ double ds[kMaxCoarseCols];
     __shared__ double c[kMaxCoarseCols];
-    __shared__ double part[kBlock];
-    for (int j = threadIdx.x; j < K; j += kBlock) ds[j] = d[j];
-    __syncthreads();
-    // Einv d over all threads: row j split into `parts` chunks of its columns (threads of one
-    // chunk read contiguous entries), four independent partial sums per thread
-    const int parts = kBlock / K;  // >= 1 (K <= kMaxCoarseCols = kBlock); parts * K <= kBlock
-    const int chunk = (K + parts - 1) / parts;
-    const int t = threadIdx.x;
-    if (t < parts * K) {
-        const int j = t % K, l0 = (t / K) * chunk, l1 = l0 + chunk < K ? l0 + chunk : K;
-        double p[4] = {0.0, 0.0, 0.0, 0.0};
-        int l = l0;
-        for (; l + 3 < l1; l += 4) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) p[u] += Einv[(size_t)(l + u) * K + j] * ds[l + u];
-        }
-        for (; l < l1; ++l) p[0] += Einv[(size_t)l * K + j] * ds[l];
-        part[t] = (p[0] + p[1]) + (p[2] + p[3]);
-    }
-    __syncthreads();
+    __shared__ double q[kBlock];
     for (int j = threadIdx.x; j < K; j += kBlock) {
-        double s = 0.0;
-        for (int pi = 0; pi < parts; ++pi) s += part[pi * K + j];
-        c[j] = (base ? base[j] : 0.0) + sgn * s;
-        if (a_out && blockIdx.x == 0) a_out[j] = s;
+        const double* pj = part + (size_t)j * S;
+        double t = 0.0;
+        for (int s = 0; s < S; ++s) t += pj[s];
+        c[j] = (base ? base[j] : 0.0) + sgn * t;
+        if (a_out && blockIdx.x == 0) a_out[j] = t;
     }
     __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
+    const int kq = (K + 3) >> 2;
+    const int j0 = w * kq, j1 = min(K, j0 + kq);
+    double p[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < N) {
+        int j = j0;
+        for (; j + 3 < j1; j += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) p[u] += Y[(size_t)(j + u) * N + i] * c[j + u];
+        }
+        for (; j < j1; ++j) p[0] += Y[(size_t)j * N + i] * c[j];
+    }
+    q[threadIdx.x] = (p[0] + p[1]) + (p[2] + p[3]);
+    __syncthreads();
+    if (w == 0 && i < N) out[i] = x[i] + ((q[lane] + q[64 + lane]) + (q[128 + lane] + q[192 + lane]));
+}
+
+// out column j = sum_l Y column l * Einv[l][j]: the basis with E^{-1} folded in, so that the
+// apply's coefficients E^{-1} Z^T r are plain dot products (Einv symmetric).
+__global__ void __launch_bounds__(kBlock) k_coarse_rotate(const double* __restrict__ Y, const double* __restrict__ Einv,
+                                                          int N, int K, double* __restrict__ out) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int j = blockIdx.y;
     if (i >= N) return;
     double p[4] = {0.0, 0.0, 0.0, 0.0};
-    int j = 0;
-    for (; j + 3 < K; j += 4) {
+    int l = 0;
+    for (; l + 3 < K; l += 4) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) p[u] += Y[(size_t)(j + u) * N + i] * c[j + u];
+        for (int u = 0; u < 4; ++u) p[u] += Y[(size_t)(l + u) * N + i] * Einv[(size_t)(l + u) * K + j];
     }
-    for (; j < K; ++j) p[0] += Y[(size_t)j * N + i] * c[j];
-    out[i] = x[i] + ((p[0] + p[1]) + (p[2] + p[3]));
+    for (; l < K; ++l) p[0] += Y[(size_t)l * N + i] * Einv[(size_t)l * K + j];
+    out[(size_t)j * N + i] = (p[0] + p[1]) + (p[2] + p[3]);
 }
 
 void launch_coarse_basis(hipStream_t st, const double* q, int N, const int* mv, int nmodes, double kx, double ky,
@@ -129,15 +135,23 @@ void launch_coarse_gram(hipStream_t st, const double* Z, const double* Y, int N,
     hipLaunchKernelGGL(k_coarse_gram, dim3(K, K), dim3(kBlock), 0, st, Z, Y, N, K, E);
 }
 
-void launch_coarse_dots(hipStream_t st, const double* A, int N, int K, const double* v, double* out) {
-    hipLaunchKernelGGL(k_coarse_dots, dim3(K), dim3(kBlock), 0, st, A, N, v, out);
+int coarse_chunks(int N) { return N > 0 ? (N + kCoarseChunk - 1) / kCoarseChunk : 0; }
+
+void launch_coarse_dots(hipStream_t st, const double* A, int N, int K, const double* v, double* part) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_coarse_dots, dim3(coarse_chunks(N), K), dim3(kBlock), 0, st, A, N, v, part);
 }
 
-void launch_coarse_update(hipStream_t st, const double* Einv, const double* d, const double* base, int K, double sgn,
-                          const double* Y, int N, const double* x, double* out, double* a_out) {
+void launch_coarse_update(hipStream_t st, const double* part, const double* base, int K, double sgn, const double* Y,
+                          int N, const double* x, double* out, double* a_out) {
     if (N <= 0) return;
-    hipLaunchKernelGGL(k_coarse_update, dim3(nblocks(N)), dim3(kBlock), 0, st, Einv, d, base, K, sgn, Y, N, x, out,
-                       a_out);
+    hipLaunchKernelGGL(k_coarse_update, dim3((N + 63) / 64), dim3(kBlock), 0, st, part, coarse_chunks(N), base, K, sgn,
+                       Y, N, x, out, a_out);
+}
+
+void launch_coarse_rotate(hipStream_t st, const double* Y, const double* Einv, int N, int K, double* out) {
+    if (N <= 0) return;
+    hipLaunchKernelGGL(k_coarse_rotate, dim3(nblocks(N), K), dim3(kBlock), 0, st, Y, Einv, N, K, out);
 }
 
 }  // namespace brd

@@ -221,9 +221,11 @@ void launch_nvec_project(hipStream_t st, double* v, int N);  // v -= mean(v)
 void launch_coarse_basis(hipStream_t st, const double* q, int N, const int* mv, int nmodes, double kx, double ky,
                          double kz, double* Z);
 void launch_coarse_gram(hipStream_t st, const double* Z, const double* Y, int N, int K, double* E);
-void launch_coarse_dots(hipStream_t st, const double* A, int N, int K, const double* v, double* out);
-void launch_coarse_update(hipStream_t st, const double* Einv, const double* d, const double* base, int K, double sgn,
-                          const double* Y, int N, const double* x, double* out, double* a_out);
+int coarse_chunks(int N);  // row chunks of the coarse-level dot products
+void launch_coarse_dots(hipStream_t st, const double* A, int N, int K, const double* v, double* part);
+void launch_coarse_update(hipStream_t st, const double* part, const double* base, int K, double sgn, const double* Y,
+                          int N, const double* x, double* out, double* a_out);
+void launch_coarse_rotate(hipStream_t st, const double* Y, const double* Einv, int N, int K, double* out);
 void launch_nvec_copy_scale(hipStream_t st, const double* x, double* y, int N, double a, double shift);
 void launch_gmres_start(hipStream_t st, const double* b, const double* w, int has_w, double* V, double* g, int N,
                         GmresScalars* gs);
