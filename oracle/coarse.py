@@ -78,6 +78,23 @@ def two_level(M: np.ndarray, Z: np.ndarray, W: Union[np.ndarray, Callable[[np.nd
     return Q + (I - Q @ M) @ Wr
 
 
+def two_level_operator(apply_M: Callable[[np.ndarray], np.ndarray], Z: np.ndarray,
+                       apply_W: Callable[[np.ndarray], np.ndarray]) -> Callable[[np.ndarray], np.ndarray]:
+    """The same balancing form without forming M: M enters through its products with the
+    K columns of Z (taken once) and with one more vector per application. Returns r -> B r,
+    evaluated in the order of the definition: a = E^{-1} Z^T r, w = W (r - M Z a),
+    z = w + Z (a - E^{-1} Z^T M w) (M symmetric, so Z^T M w = (M Z)^T w is not used)."""
+    MZ = np.column_stack([apply_M(Z[:, k]) for k in range(Z.shape[1])])
+    E = Z.T @ MZ
+    E = 0.5 * (E + E.T)
+
+    def apply(r: np.ndarray) -> np.ndarray:
+        a = np.linalg.solve(E, Z.T @ r)
+        w = apply_W(r - MZ @ a)
+        return w + Z @ (a - np.linalg.solve(E, Z.T @ apply_M(w)))
+    return apply
+
+
 def projector(N: int) -> np.ndarray:
     """P = I - 1 1^T / N (Appendix A's null-space projection)."""
     return np.eye(N) - np.full((N, N), 1.0 / N)

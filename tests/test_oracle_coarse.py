@@ -103,6 +103,23 @@ def test_full_coarse_space_is_the_exact_inverse():
         assert np.allclose(CO.two_level(M, Z, Wm), np.linalg.pinv(M, rcond=1e-12), atol=1e-9)
 
 
+@pytest.mark.parametrize("alpha", [0.0, 0.5])
+def test_matrix_free_form_is_the_dense_form(alpha):
+    """two_level_operator (M only through products) against two_level on the dense matrix;
+    a W that is not symmetric, so swapped roles of the two projections would show."""
+    n = 16
+    q, M, P = _config(alpha)
+    N = q.shape[0]
+    Z = CO.basis(q, (n, n, n), 1.0, 3)
+    rng = np.random.default_rng(13)
+    Wm = P @ rng.standard_normal((N, N)) @ P
+    B = CO.two_level(M, Z, Wm)
+    op = CO.two_level_operator(lambda v: M @ v, Z, lambda v: Wm @ v)
+    for _ in range(3):
+        r = rng.standard_normal(N)
+        assert np.allclose(op(r), B @ r, atol=1e-10 * np.abs(B).max() * np.abs(r).max())
+
+
 def test_plausible_mistakes_break_a_pin():
     """Swapping the two projections, or keeping the column means, fails the pins above."""
     n = 16
