@@ -90,6 +90,37 @@ def test_coarse_apply_matches_the_oracle(dev, shape, h, N, alpha, m2max, precisi
     S.close()
 
 
+def test_coarse_apply_many_blobs_matches_the_oracle(dev):
+    """2100 blobs on 48^3 (alpha = 0, 26 columns, FP64): the apply's dot products split the
+    rows into two chunks (2048 and a ragged 52) and its update blocks take 64 rows (the last
+    52) with the columns in four groups (7, 7, 7, 5). Element-wise against the oracle's
+    matrix-free balancing form with exact (FFT) Schur products."""
+    from paper_1306_3159_amd import BlobRD
+    _say("coarse apply, 2100 blobs")
+    n, N, h = 48, 2100, 1.0
+    shape = (n, n, n)
+    q = W.rsa_positions(np.random.default_rng(2100), n, N, 3.0)
+
+    def apply_M(v):
+        v = v - v.mean()
+        u = ex.interp(ex.solve_A(ex.spread(v, q, shape, h, 4), 0.0, 1.0, h), q, h, 4)
+        return u - u.mean()
+
+    w0 = 4.0 * np.pi * 1.255 * h
+    Z = CO.basis(q, shape, h, 3)
+    B = CO.two_level_operator(apply_M, Z, lambda v: w0 * (v - v.mean()))
+    S = BlobRD(shape, T(q, dev), h=h, precision=0)
+    assert S.coarse_build(0.0, 3, inner_rtol=1e-12) == 26
+    rng = np.random.default_rng(4)
+    for _ in range(2):
+        r = rng.standard_normal(N)
+        r -= r.mean()
+        z = H(S.coarse_apply(T(r, dev)))
+        ref = B(r)
+        assert np.abs(z - ref).max() <= 1e-8 * np.abs(ref).max(), np.abs(z - ref).max() / np.abs(ref).max()
+    S.close()
+
+
 def _learned_handle(dev, n, q, precision=1):
     from paper_1306_3159_amd import BlobRD, Net, PRECOND_LEARNED
     net = Net(dev)
