@@ -201,6 +201,25 @@ __device__ __forceinline__ double split_at(const T* __restrict__ z0, const T* __
     return ((X + Y + Z) & 1) ? (double)z1[j] : (double)z0[j];
 }
 
+// g - (alpha c - D L c) at natural cell (X, Y, Z) of the periodic level 0 (nx even, s = D / h^2)
+// with c in the split layout, in FP64 on c's values: the stencil association of the natural
+// two-cell form (x pair, y pair, z pair, then the centre).
+template <typename T>
+__device__ __forceinline__ double split_resid(const double* __restrict__ g, const T* __restrict__ c0,
+                                              const T* __restrict__ c1, int X, int Y, int Z, int nx, int ny, int nz,
+                                              double alpha, double s) {
+    const int hx = nx >> 1;
+    const double c = split_at(c0, c1, X, Y, Z, hx, ny);
+    const double xl = split_at(c0, c1, wrapi(X - 1, nx), Y, Z, hx, ny);
+    const double xr = split_at(c0, c1, wrapi(X + 1, nx), Y, Z, hx, ny);
+    const double ym = split_at(c0, c1, X, wrapi(Y - 1, ny), Z, hx, ny);
+    const double yp = split_at(c0, c1, X, wrapi(Y + 1, ny), Z, hx, ny);
+    const double zm = split_at(c0, c1, X, Y, wrapi(Z - 1, nz), hx, ny);
+    const double zp = split_at(c0, c1, X, Y, wrapi(Z + 1, nz), hx, ny);
+    const double a = alpha * c - s * ((xl + xr) + (ym + yp) + (zm + zp) - 6.0 * c);
+    return g[((size_t)Z * ny + Y) * nx + X] - a;
+}
+
 // Blocks are dispatched to the 8 XCDs round-robin; this remaps the hardware
 // block id so each XCD works on one contiguous eighth of the index space,
 // keeping neighbouring rows and planes in the same XCD's L2.

@@ -1713,11 +1713,34 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
         launch_add_shift(st, ml, N, ds, -h3 / N);
     }
     const SpreadMult m1{nullptr, ml, 1.0, 0.0};
-    fg_cycles<T>(H, alpha, vg, sing ? &m1 : nullptr, H->inv_h3(), zg, true, o.n, cinv);
+    // With one cycle per approximate solve (singular A), c* stays in the cycle's split layout
+    // and precision (its FP64 natural copy holds the same values): J c*, step 3's residual and
+    // the final sum read it there, so it is never widened and narrowed again. Kept in G_Q.
+    const bool split_cstar = sing && o.n == 1 && d.nx % 2 == 0;
+    T* cs0 = reinterpret_cast<T*>(H->grid(G_Q));
+    T* cs1 = cs0 + P.ncell / 2;
+    const double inv_diag0 = 1.0 / (alpha + 6.0 * H->prm.D / (d.h * d.h));
+    if (split_cstar) {
+        const bool from_f = cycle_opens_from_f<T>(H);
+        T* f0 = H->at<T>(P.off_lvl[0][2]);
+        T* f1 = H->at<T>(P.off_lvl[0][3]);
+        launch_enter<T>(st, vg, f0, f1, from_f ? nullptr : z0, d.nx, d.ny, d.nz, inv_diag0, nullptr);
+        launch_spread_enter<T>(st, L, m1, vg, H->inv_h3(), f0, f1, from_f ? nullptr : z0, d.nx, d.ny, inv_diag0);
+        H->alg_bytes += (double)P.ncell * (8 + (from_f ? 1.0 : 1.5) * P.esz);
+        fg_vcycle<T>(H, alpha, nullptr, cinv, from_f);
+        launch_copy2<T>(st, z0, z1, cs0, cs1, P.ncell / 2);
+        H->alg_bytes += (double)P.ncell * 2 * P.esz;
+    } else {
+        fg_cycles<T>(H, alpha, vg, sing ? &m1 : nullptr, H->inv_h3(), zg, true, o.n, cinv);
+    }
     // 2. Schur-complement system for the (fluctuating) multipliers, right side J c* - vf
     double* jv = H->nv(6);
     double* hv = H->nv(4);
-    fg_interp(H, zg, jv);
+    if (split_cstar)
+        launch_interp_split<T>(st, cs0, cs1, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
+                               H->at<int>(P.off_perm), jv);
+    else
+        fg_interp(H, zg, jv);
     launch_nvec_copy_scale(st, jv, hv, N, 1.0, 0.0);
     launch_axpby(st, hv, vf, N, 1.0, -1.0);
     if (sing) launch_nvec_project(st, hv, N);
@@ -1785,17 +1808,36 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
     if (sing && o.n == 1) {
         // one cycle; 4. the mean concentration from J c* + J z before z is added,
         // so the shift rides on the pass that adds z
-        double* q = H->grid(G_Q);
-        fg_resid(H, alpha, vg, &m2, -H->inv_h3(), zg, q);
-        fg_vcycle<T>(H, alpha, q, cinv, false);
+        if (split_cstar) {
+            // the entry of vg - A c* - S (lam~ + lbar) straight from the split c*
+            const bool from_f = cycle_opens_from_f<T>(H);
+            T* f0 = H->at<T>(P.off_lvl[0][2]);
+            T* f1 = H->at<T>(P.off_lvl[0][3]);
+            const double s0 = H->prm.D / (d.h * d.h);
+            launch_resid_enter<T>(st, vg, cs0, cs1, f0, f1, from_f ? nullptr : z0, d.nx, d.ny, d.nz, alpha, s0,
+                                  inv_diag0);
+            launch_resid_spread_enter<T>(st, L, m2, vg, cs0, cs1, -H->inv_h3(), f0, f1, from_f ? nullptr : z0, d.nx,
+                                         d.ny, d.nz, alpha, s0, inv_diag0);
+            H->alg_bytes += (double)P.ncell * (8 + P.esz * (from_f ? 2.0 : 2.5));
+            fg_vcycle<T>(H, alpha, nullptr, cinv, from_f);
+        } else {
+            double* q = H->grid(G_Q);
+            fg_resid(H, alpha, vg, &m2, -H->inv_h3(), zg, q);
+            fg_vcycle<T>(H, alpha, q, cinv, false);
+        }
         double* jz = H->nv(5);
         launch_interp_split<T>(st, z0, z1, N, P.geom, H->at<int>(P.off_base), H->at<double>(P.off_wts),
                                H->at<int>(P.off_perm), jz);
         launch_axpby(st, jz, vf, N, -1.0, 1.0);  // vf - J z
         launch_axpby(st, jz, jv, N, 1.0, -1.0);  // vf - J z - J c*
         launch_nvec_sums(st, jz, nullptr, N, ds + 8);
-        launch_split_to_nat<T>(st, z0, z1, zg, d.nx, d.ny, d.nz, 1.0, ds + 8, 1.0 / N);
-        H->alg_bytes += (double)P.ncell * (P.esz + 16);
+        if (split_cstar) {
+            launch_split_add_to_nat<T>(st, cs0, cs1, z0, z1, zg, d.nx, d.ny, d.nz, ds + 8, 1.0 / N);
+            H->alg_bytes += (double)P.ncell * (2 * P.esz + 8);
+        } else {
+            launch_split_to_nat<T>(st, z0, z1, zg, d.nx, d.ny, d.nz, 1.0, ds + 8, 1.0 / N);
+            H->alg_bytes += (double)P.ncell * (P.esz + 16);
+        }
     } else {
         fg_cycles<T>(H, alpha, vg, &m2, -H->inv_h3(), zg, false, o.n, cinv);
         if (sing) {

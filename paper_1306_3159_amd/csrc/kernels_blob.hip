@@ -496,6 +496,48 @@ template void launch_spread_enter<float>(hipStream_t, const SpreadLists&, const 
 template void launch_spread_enter<double>(hipStream_t, const SpreadLists&, const SpreadMult&, const double*, double,
                                           double*, double*, double*, int, int, double);
 
+// The entry from the residual of a split-layout guess c at the touched cells of a spread term:
+// r = (g - (alpha c - D L c)) + scale S m, f and (u0 set) the red zero-guess sweep written
+// there only, after k_resid_enter has written every cell.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_resid_spread_enter(SpreadLists L, SpreadMult M,
+                                                               const double* __restrict__ g, const T* __restrict__ c0,
+                                                               const T* __restrict__ c1, double scale,
+                                                               T* __restrict__ f0, T* __restrict__ f1,
+                                                               T* __restrict__ u0, int nx, int ny, int nz, double alpha,
+                                                               double s, double inv_diag) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= L.n) return;
+    const double acc = spread_acc(k, L, M);
+    const int c = L.cell[k];
+    const int X = c % nx;
+    const int t = c / nx;
+    const int Y = t % ny, Z = t / ny;
+    const double r = split_resid(g, c0, c1, X, Y, Z, nx, ny, nz, alpha, s) + scale * acc;
+    const size_t j = ((size_t)Z * ny + Y) * (nx >> 1) + (X >> 1);
+    if ((X + Y + Z) & 1) {
+        f1[j] = (T)r;
+    } else {
+        f0[j] = (T)r;
+        if (u0) u0[j] = (T)((T)r * (T)inv_diag);
+    }
+}
+
+template <typename T>
+void launch_resid_spread_enter(hipStream_t st, const SpreadLists& L, const SpreadMult& M, const double* g,
+                               const T* c0, const T* c1, double scale, T* f0, T* f1, T* u0, int nx, int ny, int nz,
+                               double alpha, double s, double inv_diag) {
+    if (L.n <= 0) return;
+    hipLaunchKernelGGL(k_resid_spread_enter<T>, dim3(nblocks(L.n)), dim3(kBlock), 0, st, L, M, g, c0, c1, scale, f0,
+                       f1, u0, nx, ny, nz, alpha, s, inv_diag);
+}
+template void launch_resid_spread_enter<float>(hipStream_t, const SpreadLists&, const SpreadMult&, const double*,
+                                               const float*, const float*, double, float*, float*, float*, int, int,
+                                               int, double, double, double);
+template void launch_resid_spread_enter<double>(hipStream_t, const SpreadLists&, const SpreadMult&, const double*,
+                                                const double*, const double*, double, double*, double*, double*, int,
+                                                int, int, double, double, double);
+
 template <typename T>
 __global__ void k_zero(T* __restrict__ p, size_t n) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -509,6 +551,24 @@ void launch_zero(hipStream_t st, T* p, size_t n) {
 }
 template void launch_zero<float>(hipStream_t, float*, size_t);
 template void launch_zero<double>(hipStream_t, double*, size_t);
+
+// b0 = a0, b1 = a1 (two arrays of n elements each)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_copy2(const T* __restrict__ a0, const T* __restrict__ a1,
+                                                  T* __restrict__ b0, T* __restrict__ b1, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    b0[i] = a0[i];
+    b1[i] = a1[i];
+}
+
+template <typename T>
+void launch_copy2(hipStream_t st, const T* a0, const T* a1, T* b0, T* b1, size_t n) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_copy2<T>, dim3(nblocks(n)), dim3(kBlock), 0, st, a0, a1, b0, b1, n);
+}
+template void launch_copy2<float>(hipStream_t, const float*, const float*, float*, float*, size_t);
+template void launch_copy2<double>(hipStream_t, const double*, const double*, double*, double*, size_t);
 
 // ---------------------------------------------------------------------------
 // N-vector kernels: one work-group of kFinBlock threads, fixed reduction order.

@@ -531,6 +531,42 @@ template void launch_split_to_nat<float>(hipStream_t, const float*, const float*
 template void launch_split_to_nat<double>(hipStream_t, const double*, const double*, double*, int, int, int, double,
                                           const double*, double);
 
+// out = (b + z) + shift_scale * *shift_dev with b and z in the split layout (pair form, nx
+// even): what k_split_to_nat2 with scale 1 writes when out holds the natural copy of b.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_split_add_to_nat2(const T* __restrict__ b0, const T* __restrict__ b1,
+                                                              const T* __restrict__ z0, const T* __restrict__ z1,
+                                                              double* __restrict__ out, int hx, int ny, unsigned nh,
+                                                              const double* __restrict__ shift_dev,
+                                                              double shift_scale) {
+    typedef double D2 __attribute__((ext_vector_type(2)));
+    const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nh) return;
+    const unsigned t = idx / hx;  // row z * ny + y
+    const int p = ((int)(t % ny) + (int)(t / ny)) & 1;
+    const double a = (double)z0[idx], b = (double)z1[idx];
+    const double ba = (double)b0[idx], bb = (double)b1[idx];
+    double v0 = (p ? bb : ba) + (p ? b : a);
+    double v1 = (p ? ba : bb) + (p ? a : b);
+    if (shift_dev) {
+        v0 += shift_scale * shift_dev[0];
+        v1 += shift_scale * shift_dev[0];
+    }
+    reinterpret_cast<D2*>(out)[idx] = D2{v0, v1};
+}
+
+template <typename T>
+void launch_split_add_to_nat(hipStream_t st, const T* b0, const T* b1, const T* z0, const T* z1, double* out, int nx,
+                             int ny, int nz, const double* shift_dev, double shift_scale) {
+    const unsigned nh = (unsigned)(nx / 2) * ny * nz;
+    hipLaunchKernelGGL(k_split_add_to_nat2<T>, dim3(nblocks(nh)), dim3(kBlock), 0, st, b0, b1, z0, z1, out, nx / 2,
+                       ny, nh, shift_dev, shift_scale);
+}
+template void launch_split_add_to_nat<float>(hipStream_t, const float*, const float*, const float*, const float*,
+                                             double*, int, int, int, const double*, double);
+template void launch_split_add_to_nat<double>(hipStream_t, const double*, const double*, const double*,
+                                              const double*, double*, int, int, int, const double*, double);
+
 __global__ void __launch_bounds__(kBlock) k_norm_partials(const double* __restrict__ v, unsigned n, double* part) {
     unsigned lo, hi;
     chunk_of(blockIdx.x, gridDim.x, n, &lo, &hi);

@@ -61,6 +61,37 @@ void launch_enter(hipStream_t st, const double* r, T* f0, T* f1, T* u0, int nx, 
                        sc);
 }
 
+// Fine-level entry from the residual of a guess c held in the split layout: f = g - (alpha c
+// - D L c) at every cell (FP64 arithmetic on c's values, T split out) and, when u0 is set, the
+// first red half-sweep from zero, u_red = f_red / diag, as k_enter of that FP64 residual writes
+// them. A spread term's touched cells are rewritten afterwards (k_resid_spread_enter).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_resid_enter(const double* __restrict__ g, const T* __restrict__ c0,
+                                                        const T* __restrict__ c1, T* __restrict__ f0,
+                                                        T* __restrict__ f1, T* __restrict__ u0, int hx, int ny, int nz,
+                                                        double alpha, double s, double inv_diag) {
+    const unsigned nh = (unsigned)hx * ny * nz;
+    const unsigned idx = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (idx >= nh) return;
+    const int i = idx % hx;
+    const unsigned t = idx / hx;
+    const int y = t % ny, z = t / ny;
+    const int s0 = (y + z) & 1;  // x offset of the red cell in this row
+    const double fr = split_resid(g, c0, c1, 2 * i + s0, y, z, 2 * hx, ny, nz, alpha, s);
+    const double fb = split_resid(g, c0, c1, 2 * i + (s0 ^ 1), y, z, 2 * hx, ny, nz, alpha, s);
+    f0[idx] = (T)fr;
+    f1[idx] = (T)fb;
+    if (u0) u0[idx] = (T)((T)fr * (T)inv_diag);
+}
+
+template <typename T>
+void launch_resid_enter(hipStream_t st, const double* g, const T* c0, const T* c1, T* f0, T* f1, T* u0, int nx,
+                        int ny, int nz, double alpha, double s, double inv_diag) {
+    const unsigned nh = (unsigned)(nx / 2) * ny * nz;
+    hipLaunchKernelGGL(k_resid_enter<T>, dim3(nblocks(nh)), dim3(kBlock), 0, st, g, c0, c1, f0, f1, u0, nx / 2, ny,
+                       nz, alpha, s, inv_diag);
+}
+
 // ---------------------------------------------------------------------------
 // Gauss-Seidel half-sweep on colour `color`: u_c = (f_c + s * sum nbrs) / diag.
 template <typename T>
@@ -1259,6 +1290,8 @@ hipError_t tail_set_lds_batched(size_t bytes) {
 
 #define BRD_INST(T)                                                                                                \
     template void launch_enter<T>(hipStream_t, const double*, T*, T*, T*, int, int, int, double, const Scalars*);  \
+    template void launch_resid_enter<T>(hipStream_t, const double*, const T*, const T*, T*, T*, T*, int, int, int, \
+                                        double, double, double);                                                    \
     template void launch_gs<T>(hipStream_t, T*, const T*, const T*, int, int, int, int, double, double,            \
                                const Scalars*, int);                                                               \
     template bool launch_gs_from_f<T>(hipStream_t, T*, const T*, const T*, int, int, int, int, double, double,     \

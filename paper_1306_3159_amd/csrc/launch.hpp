@@ -42,6 +42,10 @@ void launch_zdots2(hipStream_t st, const T* z0, const T* z1, const double* r, co
 template <typename T>
 void launch_split_to_nat(hipStream_t st, const T* z0, const T* z1, double* out, int nx, int ny, int nz,
                          double scale_in_place, const double* shift_dev = nullptr, double shift_scale = 0.0);
+// out = (b + z) + shift_scale * *shift_dev (b, z split; nx even)
+template <typename T>
+void launch_split_add_to_nat(hipStream_t st, const T* b0, const T* b1, const T* z0, const T* z1, double* out, int nx,
+                             int ny, int nz, const double* shift_dev, double shift_scale);
 // sums (sum v, v.v) of a natural vector
 void launch_norm_partials(hipStream_t st, const double* v, size_t n, double* part, unsigned* nparts_out);
 void launch_fill(hipStream_t st, double* v, size_t n, double value);
@@ -92,6 +96,10 @@ void launch_reduce_parts(hipStream_t st, const double* part, unsigned nparts, in
 template <typename T>
 void launch_enter(hipStream_t st, const double* r, T* f0, T* f1, T* u0, int nx, int ny, int nz,
                   double inv_diag, const Scalars* sc);
+// entry from the residual g - A c of a split-layout guess c (periodic, nx even; u0 may be null)
+template <typename T>
+void launch_resid_enter(hipStream_t st, const double* g, const T* c0, const T* c1, T* f0, T* f1, T* u0, int nx,
+                        int ny, int nz, double alpha, double s, double inv_diag);
 template <typename T>
 void launch_gs(hipStream_t st, T* uc, const T* uo, const T* fc, int hx, int ny, int nz, int color, double s,
                double inv_diag, const Scalars* sc, int bs = kBlock);
@@ -212,8 +220,15 @@ void launch_spread_sparse(hipStream_t st, const SpreadLists& L, const SpreadMult
 template <typename T>
 void launch_spread_enter(hipStream_t st, const SpreadLists& L, const SpreadMult& M, const double* base_in,
                          double scale, T* f0, T* f1, T* u0, int nx, int ny, double inv_diag);
+// the same entry at a spread term's touched cells: (g - A c) + scale S m (after launch_resid_enter)
+template <typename T>
+void launch_resid_spread_enter(hipStream_t st, const SpreadLists& L, const SpreadMult& M, const double* g,
+                               const T* c0, const T* c1, double scale, T* f0, T* f1, T* u0, int nx, int ny, int nz,
+                               double alpha, double s, double inv_diag);
 template <typename T>
 void launch_zero(hipStream_t st, T* p, size_t n);
+template <typename T>
+void launch_copy2(hipStream_t st, const T* a0, const T* a1, T* b0, T* b1, size_t n);
 
 // ---- N-vector kernels (single work-group) ------------------------------------
 void launch_nvec_project(hipStream_t st, double* v, int N);  // v -= mean(v)
