@@ -1713,10 +1713,10 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
         launch_add_shift(st, ml, N, ds, -h3 / N);
     }
     const SpreadMult m1{nullptr, ml, 1.0, 0.0};
-    // With one cycle per approximate solve (singular A), c* stays in the cycle's split layout
+    // With one cycle per approximate solve (periodic), c* stays in the cycle's split layout
     // and precision (its FP64 natural copy holds the same values): J c*, step 3's residual and
     // the final sum read it there, so it is never widened and narrowed again. Kept in G_Q.
-    const bool split_cstar = sing && o.n == 1 && d.nx % 2 == 0;
+    const bool split_cstar = o.n == 1 && !H->box && d.nx % 2 == 0;
     T* cs0 = reinterpret_cast<T*>(H->grid(G_Q));
     T* cs1 = cs0 + P.ncell / 2;
     const double inv_diag0 = 1.0 / (alpha + 6.0 * H->prm.D / (d.h * d.h));
@@ -1725,7 +1725,9 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
         T* f0 = H->at<T>(P.off_lvl[0][2]);
         T* f1 = H->at<T>(P.off_lvl[0][3]);
         launch_enter<T>(st, vg, f0, f1, from_f ? nullptr : z0, d.nx, d.ny, d.nz, inv_diag0, nullptr);
-        launch_spread_enter<T>(st, L, m1, vg, H->inv_h3(), f0, f1, from_f ? nullptr : z0, d.nx, d.ny, inv_diag0);
+        if (sing)
+            launch_spread_enter<T>(st, L, m1, vg, H->inv_h3(), f0, f1, from_f ? nullptr : z0, d.nx, d.ny,
+                                   inv_diag0);
         H->alg_bytes += (double)P.ncell * (8 + (from_f ? 1.0 : 1.5) * P.esz);
         fg_vcycle<T>(H, alpha, nullptr, cinv, from_f);
         launch_copy2<T>(st, z0, z1, cs0, cs1, P.ncell / 2);
@@ -1838,6 +1840,18 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
             launch_split_to_nat<T>(st, z0, z1, zg, d.nx, d.ny, d.nz, 1.0, ds + 8, 1.0 / N);
             H->alg_bytes += (double)P.ncell * (P.esz + 16);
         }
+    } else if (split_cstar) {
+        // one cycle from c*: the entry of vg - A c* - S lam~ straight from the split c*
+        const bool from_f = cycle_opens_from_f<T>(H);
+        T* f0 = H->at<T>(P.off_lvl[0][2]);
+        T* f1 = H->at<T>(P.off_lvl[0][3]);
+        const double s0 = H->prm.D / (d.h * d.h);
+        launch_resid_enter<T>(st, vg, cs0, cs1, f0, f1, from_f ? nullptr : z0, d.nx, d.ny, d.nz, alpha, s0, inv_diag0);
+        launch_resid_spread_enter<T>(st, L, m2, vg, cs0, cs1, -H->inv_h3(), f0, f1, from_f ? nullptr : z0, d.nx, d.ny,
+                                     d.nz, alpha, s0, inv_diag0);
+        fg_vcycle<T>(H, alpha, nullptr, cinv, from_f);
+        launch_split_add_to_nat<T>(st, cs0, cs1, z0, z1, zg, d.nx, d.ny, d.nz, nullptr, 0.0);
+        H->alg_bytes += (double)P.ncell * (16 + P.esz * (from_f ? 4.0 : 4.5));
     } else {
         fg_cycles<T>(H, alpha, vg, &m2, -H->inv_h3(), zg, false, o.n, cinv);
         if (sing) {
