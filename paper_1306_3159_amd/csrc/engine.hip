@@ -455,6 +455,8 @@ struct blob_rd {
     int batch_slot = -1;
     bool batch_v = false;
     hipEvent_t batch_ev = nullptr;
+    // block FGMRES: the two steps in flight copy their residual estimates to hbuf[8..11]
+    hipEvent_t fg_ev[2] = {nullptr, nullptr};
     // this device's no-alloc scratch (device address of `scratch`, taken at create)
     ScratchSlot* noalloc = nullptr;
 
@@ -1913,6 +1915,10 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
     // the Arnoldi steps run as captured graphs (not in a batch's V-cycle rounds, which
     // rendezvous with the executor on the host, nor where the call must not allocate)
     const bool graphs = H->use_graphs && H->fg_capture && !H->batch;
+    const bool ahead = H->fg_capture && !H->batch;  // steps issued ahead of the host's reads
+    if (ahead)
+        for (auto& e : H->fg_ev)
+            if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     (void)select_cinv(H, alpha);  // its upload, if any, happens outside any capture
     if (warm) {
         // (c, lam) hold the initial guess; the scale of the residual is |b| = |[f; phi]|
@@ -1951,7 +1957,9 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
         launch_fg_gstart(st, gv, ld, sd);
         H->alg_bytes += (double)n * 16;
         int k = 0;
-        for (int j = 0; j < m && its < o.maxit; ++j) {
+        // issue Arnoldi step j: its kernels (or its captured graph), then the copy of its
+        // residual estimate and sub-diagonal to hbuf[8 + 2 (j & 1)], recorded by fg_ev[j & 1]
+        auto issue = [&](int j) {
             // one Arnoldi step: z_j = M^-1 v_j, w = K z_j orthogonalised against the basis and
             // normalised, the Givens rotation of column j (all on the handle's current stream)
             auto step = [&]() {
@@ -2030,12 +2038,58 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
             } else {
                 step();
             }
-            sync_read(H, H->hbuf, sd + 2, 16);
+            if (ahead) {
+                HIPCHK(hipMemcpyAsync(H->hbuf + 8 + 2 * (j & 1), sd + 2, 16, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipEventRecord(H->fg_ev[j & 1], st));
+            }
+        };
+        // Step j + 1 goes onto the stream before the host reads step j's estimate when the
+        // estimates so far (the last contraction, with a margin of 10) say step j will not reach
+        // the tolerance: the read and the next launch then overlap step j instead of leaving
+        // the GPU idle. A step writes only column j of H, Z_j, V_{j+1} and the Givens entries
+        // j, j + 1, so a step issued past convergence changes nothing the update below reads;
+        // it is not counted. (Not in a batch, whose V-cycle rounds meet the executor on the
+        // host, nor where the call must not allocate: there every step is read before the next.)
+        double e1 = beta, e2 = -1.0;  // estimates after the last two steps read (beta before the first)
+        for (int j = 0; j < m && its < o.maxit; ++j) {
+            if (j == 0 || !ahead) issue(j);
+            bool spec = false;
+            double b0 = 0.0;
+            int v0 = 0, i0 = 0;
+            if (ahead && j + 1 < m && its + 1 < o.maxit) {
+                const double q = e2 > 0.0 ? std::min(1.0, e1 / e2) : 1.0;
+                if (e1 * q > 10.0 * o.rtol * bnorm) {
+                    b0 = H->alg_bytes;
+                    v0 = H->vcycles;
+                    i0 = H->inner_iters;
+                    issue(j + 1);
+                    spec = true;
+                }
+            }
+            double res, sub_diag;
+            if (ahead) {
+                HIPCHK(hipEventSynchronize(H->fg_ev[j & 1]));
+                res = H->hbuf[8 + 2 * (j & 1)];
+                sub_diag = H->hbuf[9 + 2 * (j & 1)];
+            } else {
+                sync_read(H, H->hbuf, sd + 2, 16);
+                res = H->hbuf[0];
+                sub_diag = H->hbuf[1];
+            }
             ++its;
             k = j + 1;
-            const double res = H->hbuf[0], sub_diag = H->hbuf[1];
             if (!std::isfinite(res) || !std::isfinite(sub_diag)) throw Err(BLOB_RD_ENUMERIC, "FGMRES breakdown");
-            if (res <= o.rtol * bnorm || sub_diag == 0.0) break;
+            if (res <= o.rtol * bnorm || sub_diag == 0.0) {
+                if (spec) {
+                    H->alg_bytes = b0;
+                    H->vcycles = v0;
+                    H->inner_iters = i0;
+                }
+                break;
+            }
+            e2 = e1;
+            e1 = res;
+            if (ahead && !spec && j + 1 < m && its < o.maxit) issue(j + 1);
         }
         launch_fg_backsolve(st, Hd, ld, gv, yv, k);
         launch_fg_update(st, c, Z, stride, 0, ncell, k, yv);
@@ -2287,6 +2341,8 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
 int blob_rd_destroy(blob_rd_t H) {
     if (!H) return BLOB_RD_OK;
     if (H->batch_ev) (void)hipEventDestroy(H->batch_ev);
+    for (auto& e : H->fg_ev)
+        if (e) (void)hipEventDestroy(e);
     for (auto& g : H->fg_graphs) (void)hipGraphExecDestroy(g.exec);
     H->fg_graphs.clear();
     if (H->own_net) blob_rd_net_destroy(H->own_net);
