@@ -406,6 +406,9 @@ struct blob_rd {
     bool relax = true;  // relaxed inner tolerances in the Schur GMRES
     bool blocked = true;  // temporally blocked launches on the coarser per-level levels
     bool reorth_always = false;  // the block FGMRES re-orthogonalises every new basis vector
+    // block FGMRES steps issued ahead of the host's reads: 0 never, 1 when the contraction says
+    // the step in flight will not converge, 2 always (every converging step has one behind it)
+    int fg_ahead = 1;
     // learned Schur preconditioner (CSR of W in a caller-provided buffer)
     struct Learned {
         bool ready = false;
@@ -1915,7 +1918,7 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
     // the Arnoldi steps run as captured graphs (not in a batch's V-cycle rounds, which
     // rendezvous with the executor on the host, nor where the call must not allocate)
     const bool graphs = H->use_graphs && H->fg_capture && !H->batch;
-    const bool ahead = H->fg_capture && !H->batch;  // steps issued ahead of the host's reads
+    const bool ahead = H->fg_capture && !H->batch && H->fg_ahead > 0;  // steps issued ahead of the host's reads
     if (ahead)
         for (auto& e : H->fg_ev)
             if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -2058,7 +2061,7 @@ int fg_solve(blob_rd* H, double alpha, const FgOpts& o, const double* f, double*
             int v0 = 0, i0 = 0;
             if (ahead && j + 1 < m && its + 1 < o.maxit) {
                 const double q = e2 > 0.0 ? std::min(1.0, e1 / e2) : 1.0;
-                if (e1 * q > 10.0 * o.rtol * bnorm) {
+                if (H->fg_ahead == 2 || e1 * q > 10.0 * o.rtol * bnorm) {
                     b0 = H->alg_bytes;
                     v0 = H->vcycles;
                     i0 = H->inner_iters;
@@ -2219,6 +2222,7 @@ int blob_rd_create(const blob_rd_params* p, blob_rd_t* out) {
     if (const char* g = std::getenv("BLOB_RD_RELAX")) H->relax = std::atoi(g) != 0;
     if (const char* g = std::getenv("BLOB_RD_BLOCKED")) H->blocked = std::atoi(g) != 0;
     if (const char* g = std::getenv("BLOB_RD_FG_REORTH")) H->reorth_always = std::atoi(g) != 0;
+    if (const char* g = std::getenv("BLOB_RD_FG_AHEAD")) H->fg_ahead = std::min(2, std::max(0, std::atoi(g)));
     // Align the workspace base to 256 bytes.
     uintptr_t base = (uintptr_t)p->workspace;
     H->ws = (char*)((base + 255) & ~(uintptr_t)255);

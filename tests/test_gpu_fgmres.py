@@ -139,6 +139,38 @@ def test_fgmres_second_gram_schmidt_pass(dev, kind, monkeypatch):
     assert rel(out["1"][0], out["0"][0]) < 1e-9 and rel(out["1"][1], out["0"][1]) < 1e-9
 
 
+@pytest.mark.parametrize("alpha", [0.0, 1.0 / 32 ** 2])
+def test_fgmres_steps_issued_ahead(dev, alpha, monkeypatch):
+    """Arnoldi steps issued before the host has read the previous step's residual estimate:
+    never (BLOB_RD_FG_AHEAD=0), when the contraction predicts no convergence (1, the default) and
+    always (2, so the step that converges always has one more behind it, issued past
+    convergence). The extra step must change nothing the solution update reads: bitwise the
+    same solution, the same counts, and the exact solution to the tolerance."""
+    _say("fgmres steps ahead", alpha)
+    rng = np.random.default_rng(75)
+    n, N = 32, 30
+    q = W.rsa_positions(rng, n, N, 3.0)
+    f = 1.0 + 0.5 * rng.standard_normal((n, n, n))
+    ce, le = ex.solve_absorbing(f, q, alpha)
+    out = {}
+    for mode in ("0", "1", "2"):
+        monkeypatch.setenv("BLOB_RD_FG_AHEAD", mode)
+        for prec, tol in ((0, 1e-10), (1, 1e-8)):
+            S = make(dev, n, q, precision=prec, rtol=tol)
+            c, lam, st = S.solve_absorbing_fgmres(T(f, dev), alpha=alpha, precond="schur")
+            assert st["rc"] == 0 and st["rel_resid"] <= tol, st
+            c, lam = H(c), H(lam)
+            assert rel(c, ce) < 100 * tol and rel(lam, le) < 100 * tol
+            out[(mode, prec)] = (c, lam, st["outer_iters"], st["vcycles"], st["inner_iters_total"], st["alg_bytes"])
+            S.close()
+    for prec in (0, 1):
+        ref = out[("0", prec)]
+        for mode in ("1", "2"):
+            got = out[(mode, prec)]
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+            assert got[2:] == ref[2:]
+
+
 def test_fgmres_fixed_blob_count_lattice(dev):
     """The paper's fixed-N test (64 = 4^3 blobs on a lattice, A = L^-2 I - L) at L = 64 with both
     preconditioners: converges, and the oracle's FP64 residual agrees at full size."""
