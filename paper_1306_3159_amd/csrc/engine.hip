@@ -439,7 +439,7 @@ struct blob_rd {
         double* E = nullptr;
         double* r2 = nullptr;
         double* w = nullptr;
-        double* part = nullptr;  // K x (row chunks) partial dot products
+        double* part = nullptr;  // (K + 1) x (row chunks) partial dot products
         double* a = nullptr;
         double w0 = 0.0;  // scale of W without the learned part: 4 pi a0 D (eq. Schur_diagonal)
     } crs;
@@ -1117,8 +1117,8 @@ std::vector<int> coarse_modes(int m2max) {
 }
 
 // Buffer layout: modes | Z, M Z, Z E^{-1}, M Z E^{-1} (K x N each) | E^{-1}, E (K x K) |
-// r2, w (N) | partial dot products (K x row chunks) | a (K). With buf == null only the size
-// is computed.
+// r2, w (N) | partial dot products ((K + 1) x row chunks) | a (K). With buf == null only the
+// size is computed.
 size_t coarse_layout(int N, int K, char* buf, blob_rd::Coarse* C) {
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -1135,7 +1135,7 @@ size_t coarse_layout(int N, int K, char* buf, blob_rd::Coarse* C) {
     char* E = take((size_t)K * K * 8);
     char* r2 = take((size_t)N * 8);
     char* w = take((size_t)N * 8);
-    char* part = take((size_t)K * coarse_chunks(N) * 8);
+    char* part = take((size_t)(K + 1) * coarse_chunks(N) * 8);
     char* a = take((size_t)K * 8);
     if (C) {
         C->modes = reinterpret_cast<int*>(modes);
@@ -1250,16 +1250,15 @@ void coarse_apply(blob_rd* H, bool use_w, const double* r, double* z) {
     blob_rd::Coarse& C = H->crs;
     hipStream_t st = H->st;
     const int N = H->P.N, K = C.K;
+    const bool sing = singular(H, C.alpha);
     launch_coarse_dots(st, C.ZE, N, K, r, C.part);                                // a = E^{-1} Z^T r
     launch_coarse_update(st, C.part, nullptr, K, -1.0, C.MZ, N, r, C.r2, C.a);    // r2 = r - M Z a
-    if (use_w) {
-        precond_apply(H, C.r2, C.w);
-    } else {
-        launch_nvec_copy_scale(st, C.r2, C.w, N, C.w0, 0.0);
-        if (singular(H, C.alpha)) launch_nvec_project(st, C.w, N);
-    }
-    launch_coarse_dots(st, C.MZE, N, K, C.w, C.part);                             // e = E^{-1} (M Z)^T w
-    launch_coarse_update(st, C.part, C.a, K, -1.0, C.Z, N, C.w, z, nullptr);      // z = w + Z (a - e)
+    // w = W r2 (W P: the SpMV removes the input's mean), projected only in the last pass: at
+    // alpha = 0 the columns of M Z are mean-free, so w's mean changes no coefficient e
+    if (use_w) launch_spmv_centered(st, H->lrn.rowptr, H->lrn.col, H->lrn.val, C.r2, C.w, N);
+    else launch_nvec_copy_scale(st, C.r2, C.w, N, C.w0, 0.0);
+    launch_coarse_dots(st, C.MZE, N, K, C.w, C.part, sing);                       // e = E^{-1} (M Z)^T w
+    launch_coarse_update(st, C.part, C.a, K, -1.0, C.Z, N, C.w, z, nullptr, sing);  // z = P w + Z (a - e)
 }
 
 struct SaddleInfo {

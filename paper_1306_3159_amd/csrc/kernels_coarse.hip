@@ -36,10 +36,24 @@ __global__ void __launch_bounds__(kBlock) k_coarse_center(double* __restrict__ Z
 
 // part[j][s] = sum_{i in chunk s} A[j][i] v[i] for the K columns of A and the row chunks
 // [s kCoarseChunk, (s + 1) kCoarseChunk): one work-group per (chunk, column) so the grid fills
-// the chip, four independent partial sums per thread to keep loads in flight.
-__global__ void __launch_bounds__(kBlock) k_coarse_dots(const double* __restrict__ A, int N,
+// the chip, four independent partial sums per thread to keep loads in flight. A grid of K + 1
+// columns adds the chunk sums of v itself as column K.
+__global__ void __launch_bounds__(kBlock) k_coarse_dots(const double* __restrict__ A, int N, int K,
                                                         const double* __restrict__ v, double* __restrict__ part) {
     const int s = blockIdx.x, j = blockIdx.y;
+    if (j == K) {
+        const int i1 = min(N, (s + 1) * kCoarseChunk);
+        double p[4] = {0.0, 0.0, 0.0, 0.0};
+        int i = s * kCoarseChunk + threadIdx.x;
+        for (; i + 3 * kBlock < i1; i += 4 * kBlock) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) p[u] += v[i + u * kBlock];
+        }
+        for (; i < i1; i += kBlock) p[0] += v[i];
+        const double t = wg_sum((p[0] + p[1]) + (p[2] + p[3]));
+        if (threadIdx.x == 0) part[(size_t)j * gridDim.x + s] = t;
+        return;
+    }
     const double* a = A + (size_t)j * N;
     const int i1 = min(N, (s + 1) * kCoarseChunk);
     double p[4] = {0.0, 0.0, 0.0, 0.0};
@@ -69,26 +83,32 @@ __global__ void __launch_bounds__(kBlock) k_coarse_gram(const double* __restrict
     if (threadIdx.x == 0) E[(size_t)blockIdx.y * K + blockIdx.x] = s;
 }
 
-// out = x + Y c with c = base + sgn d, d[j] = sum_s part[j][s] over the S chunk sums of
-// k_coarse_dots (base may be null = 0). A work-group takes 64 rows: every block forms c in LDS
-// (the same order in every block), then wave w sums the rows' values of its quarter of the
-// columns and the four quarters are added in a fixed order. Block 0 writes d to a_out (may be
-// null).
+// out = (x - xm) + Y c with c = base + sgn d, d[j] = sum_s part[j][s] over the S chunk sums of
+// k_coarse_dots (base may be null = 0) and, with sub_mean, xm the mean of x from column K of
+// part (0 otherwise). A work-group takes 64 rows: every block forms c and xm in LDS (the same
+// order in every block), then wave w sums the rows' values of its quarter of the columns and
+// the four quarters are added in a fixed order. Block 0 writes d to a_out (may be null).
 __global__ void __launch_bounds__(kBlock) k_coarse_update(const double* __restrict__ part, int S,
                                                           const double* __restrict__ base, int K, double sgn,
                                                           const double* __restrict__ Y, int N,
                                                           const double* __restrict__ x, double* __restrict__ out,
-                                                          double* __restrict__ a_out) {
-    __shared__ double c[kMaxCoarseCols];
+                                                          double* __restrict__ a_out, int sub_mean) {
+    __shared__ double c[kMaxCoarseCols + 1];
     __shared__ double q[kBlock];
-    for (int j = threadIdx.x; j < K; j += kBlock) {
+    const int kc = K + (sub_mean ? 1 : 0);
+    for (int j = threadIdx.x; j < kc; j += kBlock) {
         const double* pj = part + (size_t)j * S;
         double t = 0.0;
         for (int s = 0; s < S; ++s) t += pj[s];
-        c[j] = (base ? base[j] : 0.0) + sgn * t;
-        if (a_out && blockIdx.x == 0) a_out[j] = t;
+        if (j == K) {
+            c[j] = t / (double)N;
+        } else {
+            c[j] = (base ? base[j] : 0.0) + sgn * t;
+            if (a_out && blockIdx.x == 0) a_out[j] = t;
+        }
     }
     __syncthreads();
+    const double xm = sub_mean ? c[K] : 0.0;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = blockIdx.x * 64 + lane;
     const int kq = (K + 3) >> 2;
@@ -104,7 +124,7 @@ __global__ void __launch_bounds__(kBlock) k_coarse_update(const double* __restri
     }
     q[threadIdx.x] = (p[0] + p[1]) + (p[2] + p[3]);
     __syncthreads();
-    if (w == 0 && i < N) out[i] = x[i] + ((q[lane] + q[64 + lane]) + (q[128 + lane] + q[192 + lane]));
+    if (w == 0 && i < N) out[i] = (x[i] - xm) + ((q[lane] + q[64 + lane]) + (q[128 + lane] + q[192 + lane]));
 }
 
 // out column j = sum_l Y column l * Einv[l][j]: the basis with E^{-1} folded in, so that the
@@ -137,16 +157,17 @@ void launch_coarse_gram(hipStream_t st, const double* Z, const double* Y, int N,
 
 int coarse_chunks(int N) { return N > 0 ? (N + kCoarseChunk - 1) / kCoarseChunk : 0; }
 
-void launch_coarse_dots(hipStream_t st, const double* A, int N, int K, const double* v, double* part) {
+void launch_coarse_dots(hipStream_t st, const double* A, int N, int K, const double* v, double* part, bool with_sum) {
     if (N <= 0) return;
-    hipLaunchKernelGGL(k_coarse_dots, dim3(coarse_chunks(N), K), dim3(kBlock), 0, st, A, N, v, part);
+    hipLaunchKernelGGL(k_coarse_dots, dim3(coarse_chunks(N), K + (with_sum ? 1 : 0)), dim3(kBlock), 0, st, A, N, K, v,
+                       part);
 }
 
 void launch_coarse_update(hipStream_t st, const double* part, const double* base, int K, double sgn, const double* Y,
-                          int N, const double* x, double* out, double* a_out) {
+                          int N, const double* x, double* out, double* a_out, bool sub_mean) {
     if (N <= 0) return;
     hipLaunchKernelGGL(k_coarse_update, dim3((N + 63) / 64), dim3(kBlock), 0, st, part, coarse_chunks(N), base, K, sgn,
-                       Y, N, x, out, a_out);
+                       Y, N, x, out, a_out, sub_mean ? 1 : 0);
 }
 
 void launch_coarse_rotate(hipStream_t st, const double* Y, const double* Einv, int N, int K, double* out) {

@@ -237,9 +237,12 @@ void launch_coarse_basis(hipStream_t st, const double* q, int N, const int* mv, 
                          double kz, double* Z);
 void launch_coarse_gram(hipStream_t st, const double* Z, const double* Y, int N, int K, double* E);
 int coarse_chunks(int N);  // row chunks of the coarse-level dot products
-void launch_coarse_dots(hipStream_t st, const double* A, int N, int K, const double* v, double* part);
+// with_sum: also the chunk sums of v (column K of part, which then needs K + 1 columns)
+void launch_coarse_dots(hipStream_t st, const double* A, int N, int K, const double* v, double* part,
+                        bool with_sum = false);
+// sub_mean: out = (x - mean x) + Y c, the mean from column K of part
 void launch_coarse_update(hipStream_t st, const double* part, const double* base, int K, double sgn, const double* Y,
-                          int N, const double* x, double* out, double* a_out);
+                          int N, const double* x, double* out, double* a_out, bool sub_mean = false);
 void launch_coarse_rotate(hipStream_t st, const double* Y, const double* Einv, int N, int K, double* out);
 void launch_nvec_copy_scale(hipStream_t st, const double* x, double* y, int N, double a, double shift);
 void launch_gmres_start(hipStream_t st, const double* b, const double* w, int has_w, double* V, double* g, int N,
