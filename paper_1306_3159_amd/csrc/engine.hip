@@ -1747,9 +1747,13 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
                                H->at<int>(P.off_perm), jv);
     else
         fg_interp(H, zg, jv);
-    launch_nvec_copy_scale(st, jv, hv, N, 1.0, 0.0);
-    launch_axpby(st, hv, vf, N, 1.0, -1.0);
-    if (sing) launch_nvec_project(st, hv, N);
+    // h~ = J c* - vf (mean removed at alpha = 0): formed on its own for the diagonal variant, by
+    // the inner GMRES's start otherwise
+    if (o.kind == BLOB_RD_SADDLE_DIAGONAL) {
+        launch_nvec_copy_scale(st, jv, hv, N, 1.0, 0.0);
+        launch_axpby(st, hv, vf, N, 1.0, -1.0);
+        if (sing) launch_nvec_project(st, hv, N);
+    }
     // the learned W approximates the inverse of J (-D L)^+ S on mean-zero multipliers:
     // it right-preconditions the inner GMRES (plain inner GMRES without it)
     bool learned = false;
@@ -1764,7 +1768,7 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
         double* V = H->at<double>(P.off_V);
         double* Hm = H->at<double>(P.off_H);
         double* gv = H->at<double>(P.off_gv);
-        launch_gmres_start(st, hv, nullptr, 0, V, gv, N, H->gs());
+        launch_gmres_start(st, jv, vf, 1, V, gv, N, H->gs(), sing ? 1 : 0);
         T* f0 = H->at<T>(P.off_lvl[0][2]);
         T* f1 = H->at<T>(P.off_lvl[0][3]);
         const size_t nh = P.ncell / 2;

@@ -636,13 +636,23 @@ void launch_nvec_sums(hipStream_t st, const double* a, const double* b, int N, d
 }
 
 // GMRES cycle start: r = b - w (or b), beta = |r|, V_0 = r / beta, g = beta e_1.
+// v_0 = r / |r| with r = b - w (has_w) or b, its mean removed first with project; g_0 = |r|.
 __global__ void __launch_bounds__(kFinBlock) k_gmres_start(const double* b, const double* w, int has_w, double* V,
-                                                           double* gvec, int N, GmresScalars* gs) {
+                                                           double* gvec, int N, GmresScalars* gs, int project) {
     double s = 0.0;
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const double r = has_w ? b[i] - w[i] : b[i];
         V[i] = r;
-        s += r * r;
+        s += project ? r : r * r;
+    }
+    if (project) {
+        const double mean = wg_sum(s) / (double)N;
+        s = 0.0;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            const double r = V[i] - mean;
+            V[i] = r;
+            s += r * r;
+        }
     }
     const double beta = sqrt(wg_sum(s));
     const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
@@ -657,8 +667,8 @@ __global__ void __launch_bounds__(kFinBlock) k_gmres_start(const double* b, cons
 }
 
 void launch_gmres_start(hipStream_t st, const double* b, const double* w, int has_w, double* V, double* g, int N,
-                        GmresScalars* gs) {
-    hipLaunchKernelGGL(k_gmres_start, dim3(1), dim3(kFinBlock), 0, st, b, w, has_w, V, g, N, gs);
+                        GmresScalars* gs, int project) {
+    hipLaunchKernelGGL(k_gmres_start, dim3(1), dim3(kFinBlock), 0, st, b, w, has_w, V, g, N, gs, project);
 }
 
 // Arnoldi step k with modified Gram-Schmidt: V_{k+1} holds G v_k on entry

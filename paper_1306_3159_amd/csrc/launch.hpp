@@ -245,8 +245,9 @@ void launch_coarse_update(hipStream_t st, const double* part, const double* base
                           int N, const double* x, double* out, double* a_out, bool sub_mean = false);
 void launch_coarse_rotate(hipStream_t st, const double* Y, const double* Einv, int N, int K, double* out);
 void launch_nvec_copy_scale(hipStream_t st, const double* x, double* y, int N, double a, double shift);
+// v_0 = r / |r|, r = b - w (has_w) or b with its mean removed when project is set; g_0 = |r|
 void launch_gmres_start(hipStream_t st, const double* b, const double* w, int has_w, double* V, double* g, int N,
-                        GmresScalars* gs);
+                        GmresScalars* gs, int project = 0);
 // Arnoldi step k (V_{k+1} holds the product; project: remove its mean first)
 void launch_gmres_arnoldi(hipStream_t st, double* V, double* H, double* cs, double* sn, double* g, int N, int k,
                           int m, GmresScalars* gs, int project = 0);
