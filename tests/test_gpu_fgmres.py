@@ -171,6 +171,38 @@ def test_fgmres_steps_issued_ahead(dev, alpha, monkeypatch):
             assert got[2:] == ref[2:]
 
 
+@pytest.mark.parametrize("alpha", [0.0, 0.05])
+def test_fgmres_non_cubic_grid_matches_oracle(dev, alpha):
+    """A 24 x 32 x 40 box (nz, ny, nx) with h = 0.7: half-rows of 20 cells, so the split-layout
+    steps of the block preconditioner (its FP32 concentration estimate, the residual entry, the
+    sum back to FP64) run their general forms on rows that are not powers of two. The exact
+    saddle solution (FFT Schur matrix) to 1e-10 in FP64 and 1e-8 mixed, with the oracle's
+    residual."""
+    _say("fgmres non-cubic", alpha)
+    shape, h = (24, 32, 40), 0.7
+    rng = np.random.default_rng(76)
+    N = 25
+    nz, ny, nx = shape
+    L = np.array([nx, ny, nz]) * h
+    q = []
+    while len(q) < N:
+        p = rng.uniform(0.0, 1.0, 3) * L
+        if all(np.linalg.norm((p - o + 0.5 * L) % L - 0.5 * L) >= 3.0 * h for o in q):
+            q.append(p)
+    q = np.array(q)
+    f = 1.0 + 0.5 * rng.standard_normal(shape)
+    ce, le = ex.solve_absorbing(f, q, alpha, h=h)
+    from paper_1306_3159_amd import BlobRD
+    for prec, tol in ((0, 1e-10), (1, 1e-8)):
+        S = BlobRD(shape, T(q, dev), h=h, precision=prec, rtol=tol)
+        c, lam, st = S.solve_absorbing_fgmres(T(f, dev), alpha=alpha, precond="schur")
+        assert st["rc"] == 0 and st["rel_resid"] <= tol, st
+        c, lam = H(c), H(lam)
+        assert ex.absorbing_residual(c, lam, f, q, alpha, h=h) <= 1.01 * tol
+        assert rel(c, ce) < 100 * tol and rel(lam, le) < 100 * tol
+        S.close()
+
+
 def test_fgmres_fixed_blob_count_lattice(dev):
     """The paper's fixed-N test (64 = 4^3 blobs on a lattice, A = L^-2 I - L) at L = 64 with both
     preconditioners: converges, and the oracle's FP64 residual agrees at full size."""
