@@ -228,7 +228,8 @@ int blob_rd_vcycle(blob_rd_t h, double alpha, const double* r, double* z);
  * stops when the true FP64 residual |b - K x| recomputed at a restart is
  * <= rtol |b|. */
 #define BLOB_RD_SADDLE_DIAGONAL 0     /* lam~ = (D/gamma)(J c* - vf) */
-#define BLOB_RD_SADDLE_APPROX_SCHUR 1 /* m inner GMRES iterations, one cycle per product */
+#define BLOB_RD_SADDLE_APPROX_SCHUR 1 /* m inner GMRES iterations, one cycle per product (right-
+                                         preconditioned by B of a coarse level built for alpha) */
 #define BLOB_RD_SADDLE_LEARNED 2      /* approximate-Schur variant whose inner GMRES is right-
                                          preconditioned by the handle's learned W (alpha = 0; otherwise,
                                          or without a built W, the plain variant, stats->fallback = 1),
@@ -407,7 +408,10 @@ int blob_rd_precond_train_step(blob_rd_t h, const void* batch_desc, float lr, fl
  * The block solver's learned variant (blob_rd_solve_absorbing_fgmres with
  * BLOB_RD_SADDLE_LEARNED) right-preconditions its inner GMRES on the one-cycle
  * Schur system with the same B (W = P W_learned P) instead of W alone; its
- * other variants never use the level.
+ * approximate-Schur variant (BLOB_RD_SADDLE_APPROX_SCHUR, and the block
+ * handles' time steps) with B around the diagonal W, where it has no inner
+ * preconditioner otherwise, when the level is built for the solve's alpha; the
+ * diagonal variant never uses the level.
  *
  * Building costs K Schur products (inner multigrid-CG solves to inner_rtol)
  * and holds for the alpha given: solves at another alpha ignore it. */

@@ -1775,14 +1775,18 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
         const double inv_diag = 1.0 / (alpha + 6.0 * H->prm.D / (d.h * d.h));
         const bool from_f = cycle_opens_from_f<T>(H);
         // with a Fourier coarse level built for this alpha, the inner GMRES is right-preconditioned
-        // by the two-level B around W: the long waves of the multiplier system are solved by the
+        // by the two-level B around W (the learned one, else the paper's diagonal for the
+        // approximate-Schur variant): the long waves of the multiplier system are solved by the
         // level instead of left to the m inner iterations
-        const bool use_c = learned && H->crs.ready && H->crs.alpha == alpha;
+        const bool use_c =
+            (learned || o.kind == BLOB_RD_SADDLE_APPROX_SCHUR) && H->crs.ready && H->crs.alpha == alpha;
         for (int k = 0; k < o.m; ++k) {
             const double* vk = V + (size_t)k * N;
-            if (learned) {
-                if (use_c) coarse_apply(H, true, vk, H->nv(9));
-                else precond_apply(H, vk, H->nv(9));
+            if (use_c) {
+                coarse_apply(H, learned, vk, H->nv(9));
+                vk = H->nv(9);
+            } else if (learned) {
+                precond_apply(H, vk, H->nv(9));
                 vk = H->nv(9);
             }
             // S v enters the V-cycle from the contribution lists: level-0 f is zero
@@ -1803,13 +1807,11 @@ void fg_precond(blob_rd* H, double alpha, const FgOpts& o, const double* vg, con
             launch_gmres_arnoldi(st, V, Hm, H->at<double>(P.off_cs), H->at<double>(P.off_sn), gv, N, k, o.m,
                                  H->gs(), sing ? 1 : 0);
         }
-        double* y = learned ? H->nv(10) : zl;
+        double* y = (learned || use_c) ? H->nv(10) : zl;
         launch_nvec_copy_scale(st, nullptr, y, N, 0.0, 0.0);
         launch_gmres_update(st, V, Hm, gv, H->at<double>(P.off_yv), y, N, o.m, o.m);
-        if (learned) {
-            if (use_c) coarse_apply(H, true, y, zl);
-            else precond_apply(H, y, zl);
-        }
+        if (use_c) coarse_apply(H, learned, y, zl);
+        else if (learned) precond_apply(H, y, zl);
         H->inner_iters += o.m;
     }
     if (sing) launch_nvec_project(st, zl, N);
